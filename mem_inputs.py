@@ -1,0 +1,187 @@
+"""Seeded synthetic workloads for the MEM hot path.
+
+This module is the only one read by both the FP64 oracle (``oracle/``) and the
+HIP library's users (tests, ``bench.py``).  It holds the random draws and the
+physical description of each workload -- Gaussian mixtures, shock states,
+initial profiles -- but none of the method's arithmetic: no partition function,
+no MaxEnt solve, no gauge transform, no flux.
+
+Target moments of Gaussian (mixture) states are the *definition* of the input
+and are written in closed form: for X ~ N(mu, s^2),
+E[He_n(X)] = h_n(mu; s^2 - 1) with h_n(b; c) = sum_j C(n, 2j) (2j-1)!! c^j b^(n-2j).
+Moments are returned in FP64 and in the orthonormal Hermite basis
+phi_(a,b,c)(u_bar) = He_a He_b He_c / sqrt(a! b! c!), a+b+c <= 4, ordered by total
+degree then lexicographically descending; gauge coordinates
+u_bar = ((u_x - w)/s_x, u_y/s_r, u_z/s_r).
+
+Workloads (seed = 1000*config + replica):
+
+1. ``config1_candidates``: 1D, 5 moments; per cell n ~ U(0.5, 2),
+   v ~ N(0, 1), T ~ U(0.5, 2), perturbation of the He_3/He_4 multipliers of
+   the standardised Maxwellian: c3 ~ N(0, 0.05), c4 = -|N(0, 0.05)|.  A pool
+   of candidates in a fixed order; the targets (64-node quadrature of the
+   perturbed density) are built by whoever evaluates the density.
+2. ``mott_smith_cells``: 3D, 35 moments; Mach ~ U(lo, hi), mixing weight
+   nu ~ U(0, 1), gamma = 5/3; f = (1-nu) f_M(upstream) + nu f_M(downstream)
+   with Rankine--Hugoniot downstream states; targets in the mixture's exact
+   Hermite gauge (its mean and standard deviations).
+3. ``shock_problem``: Mach-3 normal shock, tanh initial profile of the
+   upstream/downstream Maxwellian moments in a common gauge, Maxwellian
+   boundary states in their own gauges.
+5. ``ragged_batch``: many shock problems with log-uniform cell counts.
+"""
+
+import math
+
+import numpy as np
+
+GAMMA = 5.0 / 3.0
+MU_REF = math.sqrt(2.0 / math.pi)   # viscosity at T = 1 for Kn = 1 (non-dim units)
+
+
+def seed_for(config, replica=0):
+    return 1000 * config + replica
+
+
+def multi_indices(dim, degree=4):
+    out = []
+    for tot in range(degree + 1):
+        if dim == 1:
+            out.append((tot,))
+            continue
+        for a in range(tot, -1, -1):
+            for b in range(tot - a, -1, -1):
+                out.append((a, b, tot - a - b))
+    return out
+
+
+def _double_factorial_odd(k):
+    """(2j-1)!! for k = 2j-1 >= -1."""
+    r = 1
+    while k > 1:
+        r *= k
+        k -= 2
+    return r
+
+
+def hermite_gauss_moment(m, mean, var):
+    """E[He_m(X)] for X ~ N(mean, var), elementwise over arrays."""
+    mean = np.asarray(mean, dtype=np.float64)
+    c = np.asarray(var, dtype=np.float64) - 1.0
+    out = np.zeros(np.broadcast(mean, c).shape)
+    for j in range(m // 2 + 1):
+        coef = math.comb(m, 2 * j) * _double_factorial_odd(2 * j - 1)
+        out = out + coef * c ** j * mean ** (m - 2 * j)
+    return out
+
+
+def gaussian_moments(n, v, Txx, Trr, g):
+    """Moments in gauge g of n * N((v,0,0), diag(Txx, Trr, Trr)); arrays over cells."""
+    n, v, Txx, Trr = (np.asarray(a, dtype=np.float64) for a in (n, v, Txx, Trr))
+    g = np.asarray(g, dtype=np.float64)
+    mx = (v - g[:, 0]) / g[:, 1]
+    vx = Txx / g[:, 1] ** 2
+    vr = Trr / g[:, 2] ** 2
+    hx = [hermite_gauss_moment(k, mx, vx) for k in range(5)]
+    hr = [hermite_gauss_moment(k, 0.0 * mx, vr) for k in range(5)]
+    idx = multi_indices(3)
+    M = np.empty((n.shape[0], len(idx)))
+    for i, (a, b, c) in enumerate(idx):
+        norm = math.sqrt(math.factorial(a) * math.factorial(b) * math.factorial(c))
+        M[:, i] = n * hx[a] * hr[b] * hr[c] / norm
+    return M
+
+
+def rankine_hugoniot(mach, gamma=GAMMA):
+    """Upstream/downstream (n, v, T); non-dimensional m = 1, n_- = 1, T_- = 1."""
+    mach = np.asarray(mach, dtype=np.float64)
+    m2 = mach * mach
+    ratio = (gamma + 1) * m2 / ((gamma - 1) * m2 + 2)
+    tr = ((2 * gamma * m2 - (gamma - 1)) * ((gamma - 1) * m2 + 2)
+          / ((gamma + 1) ** 2 * m2))
+    v1 = math.sqrt(gamma) * mach
+    one = np.ones_like(mach)
+    return (one, v1, one), (ratio, v1 / ratio, tr)
+
+
+# --------------------------------------------------------------------------
+# workload 1: 1D perturbed Maxwellians (targets built by the density evaluator)
+# --------------------------------------------------------------------------
+def config1_candidates(n_pool=4096, replica=0):
+    rng = np.random.default_rng(seed_for(1, replica))
+    n = rng.uniform(0.5, 2.0, n_pool)
+    v = rng.normal(0.0, 1.0, n_pool)
+    T = rng.uniform(0.5, 2.0, n_pool)
+    c3 = rng.normal(0.0, 0.05, n_pool)
+    c4 = -np.abs(rng.normal(0.0, 0.05, n_pool))
+    return dict(n=n, v=v, T=T, c3=c3, c4=c4)
+
+
+# --------------------------------------------------------------------------
+# workload 2 / 4: Mott-Smith mixtures in their Hermite gauge
+# --------------------------------------------------------------------------
+def mott_smith_cells(n_cells, mach_lo=1.5, mach_hi=10.0, config=2, replica=0):
+    rng = np.random.default_rng(seed_for(config, replica))
+    mach = rng.uniform(mach_lo, mach_hi, n_cells)
+    nu = rng.uniform(0.0, 1.0, n_cells)
+    (n1, v1, T1), (n2, v2, T2) = rankine_hugoniot(mach)
+    a1, a2 = (1.0 - nu) * n1, nu * n2
+    N = a1 + a2
+    mean = (a1 * v1 + a2 * v2) / N
+    varx = (a1 * (T1 + v1 ** 2) + a2 * (T2 + v2 ** 2)) / N - mean ** 2
+    varr = (a1 * T1 + a2 * T2) / N
+    g = np.stack([mean, np.sqrt(varx), np.sqrt(varr)], axis=1)
+    M = ((1.0 - nu)[:, None] * gaussian_moments(n1, v1, T1, T1, g)
+         + nu[:, None] * gaussian_moments(n2, v2, T2, T2, g))
+    return dict(M=M, g=g, mach=mach, nu=nu)
+
+
+def maxwellian_beta(n_cells, K, n=None):
+    """Cold start: the Maxwellian in the cell's Hermite gauge (beta_0 = n)."""
+    beta = np.zeros((n_cells, K))
+    if n is not None:
+        beta[:, 0] = n
+    idx = multi_indices(3 if K == 35 else 1)
+    for i, e in enumerate(idx):
+        if sum(e) == 2 and max(e) == 2:
+            beta[:, i] = -1.0 / math.sqrt(2.0)
+    return beta
+
+
+# --------------------------------------------------------------------------
+# workload 3 / 5: normal shocks
+# --------------------------------------------------------------------------
+def shock_problem(mach=3.0, n_cells=1000, x_lo=-20.0, x_hi=20.0, thickness=5.44):
+    """Initial moments (common gauge), boundary Maxwellians and grid spacing."""
+    (n1, v1, T1), (n2, v2, T2) = (tuple(float(x) for x in s)
+                                  for s in rankine_hugoniot(np.array(mach)))
+    gm = np.array([[0.5 * (v1 + v2), 1.0, 1.0]])
+    Mm = gaussian_moments(np.array([n1]), np.array([v1]), np.array([T1]), np.array([T1]), gm)[0]
+    Mp = gaussian_moments(np.array([n2]), np.array([v2]), np.array([T2]), np.array([T2]), gm)[0]
+    dx = (x_hi - x_lo) / n_cells
+    x = x_lo + dx * (np.arange(n_cells) + 0.5)
+    th = thickness / 2.0
+    frac = ((np.tanh(x / th) - math.tanh(x_lo / th))
+            / (math.tanh(x_hi / th) - math.tanh(x_lo / th)) - 0.5)
+    M = (Mp - Mm)[None, :] * frac[:, None] + 0.5 * (Mp + Mm)[None, :]
+    g = np.repeat(gm, n_cells, axis=0)
+    gL = np.array([v1, math.sqrt(T1), math.sqrt(T1)])
+    gR = np.array([v2, math.sqrt(T2), math.sqrt(T2)])
+    ML = np.zeros(35); ML[0] = n1
+    MR = np.zeros(35); MR[0] = n2
+    return dict(M=M, g=g, dx=dx, x=x, M_left=ML, M_right=MR, g_left=gL, g_right=gR,
+                states=((n1, v1, T1), (n2, v2, T2)))
+
+
+def ragged_batch(n_problems=2048, lo=64, hi=4096, mach_lo=1.2, mach_hi=10.0,
+                 dx=1.0, thickness=10.0, replica=0):
+    """Independent shocks with log-uniform cell counts, concatenated."""
+    rng = np.random.default_rng(seed_for(5, replica))
+    counts = np.round(np.exp(rng.uniform(math.log(lo), math.log(hi), n_problems))).astype(np.int64)
+    mach = rng.uniform(mach_lo, mach_hi, n_problems)
+    offsets = np.concatenate([[0], np.cumsum(counts)])
+    probs = []
+    for p in range(n_problems):
+        half = 0.5 * counts[p] * dx
+        probs.append(shock_problem(mach[p], int(counts[p]), -half, half, thickness))
+    return dict(counts=counts, mach=mach, offsets=offsets, problems=probs, dx=dx)

@@ -1,0 +1,211 @@
+"""Collision, normal-shock set-up and the finite-volume time step (oracle).
+
+Test infrastructure only.  3D velocity space, 35-moment basis, 1D transport
+along x.  Paper passages followed:
+
+* macroscopic quantities n, v, T, pressure tensor and heat flux (Sec. 2.1 and
+  App. A, eq. "Pressure, Stress, and Heat flux"), obtained from moments by
+  expanding each velocity monomial in the basis (coefficients by projection);
+* ES-BGK target (App. A, eq. "The ES BGK model"): Gaussian with
+  Sigma = (1/Pr) T I + (1 - 1/Pr) P/n, restricted -- as the paper's statistics
+  {1, u_x, u_x^2, u_r^2} for the target are (App. B) -- to the axisymmetric
+  form (v_x, Sigma_xx, Sigma_rr = (Sigma_yy + Sigma_zz)/2);  its moments are
+  integrated with Gauss--Hermite in the Gaussian's own coordinates (exact for
+  polynomials);  relaxation time from mu/Pr = n T tau with Maxwell-molecule
+  viscosity mu = mu_ref T (eqs. "Maxwell viscosity coef", "The ES BGK
+  viscosity");
+* operator-split relaxation M <- (1 - h/tau) M + (h/tau) M~ (eq. "source
+  update");
+* Rankine--Hugoniot states (eq. "RH condition") with the non-dimensionalisation
+  m = 1, rho_- = 1, v_- = sqrt(gamma) Ma, T_- = 1 (eq. "Non-dim");
+* tanh initial profile between M_- and M_+ (eq. "Mx ini");
+* local Lax--Friedrichs flux and conservative update in each cell's own gauge,
+  neighbours moved into it by T (eqs. "The lax F", "The ME equation fvm 2",
+  "The lax F convert");
+* Alg. 2 Step: Collision(dt/2), Transport(dt), Collision(dt/2), then the
+  Hermite-gauge update.
+
+Reading for the step size (paper gives only a CFL relation): the step taken at
+step k is CFL*dx/max rho from the characteristic speeds of the transport of
+step k-1 (ghost cells included); the first step uses a solve of the initial
+state.
+"""
+
+import math
+
+import numpy as np
+
+from . import basis as _basis
+from . import flux as _flux
+from . import gauge as _gauge
+from . import maxent as _maxent
+from . import quadrature as _quad
+
+DIM = 3
+
+
+def macroscopic(M, g):
+    """n, v_x, T, P_xx, P_yy, P_zz, q_x from moments M in gauge g (3D)."""
+    M = np.asarray(M, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    n = M[:, 0]
+
+    def E(expo):
+        return (M @ _gauge.monomial_coefficients(expo, DIM)) / n
+
+    ex, exx, eyy, ezz = E((1, 0, 0)), E((2, 0, 0)), E((0, 2, 0)), E((0, 0, 2))
+    exxx, exyy, exzz = E((3, 0, 0)), E((1, 2, 0)), E((1, 0, 2))
+    w, sx, sr = g[:, 0], g[:, 1], g[:, 2]
+    v = w + sx * ex
+    Pxx = n * sx ** 2 * (exx - ex ** 2)
+    Pyy = n * sr ** 2 * eyy
+    Pzz = n * sr ** 2 * ezz
+    T = (Pxx + Pyy + Pzz) / (3.0 * n)
+    # q_x = 1/2 n E[c_x |c|^2], c = (sx (ux - ex), sr uy, sr uz)
+    cxxx = exxx - 3 * ex * exx + 2 * ex ** 3
+    cxrr = (exyy + exzz) - ex * (eyy + ezz)
+    qx = 0.5 * n * (sx ** 3 * cxxx + sx * sr ** 2 * cxrr)
+    return dict(n=n, v=v, T=T, Pxx=Pxx, Pyy=Pyy, Pzz=Pzz, qx=qx)
+
+
+def gaussian_moments(n, v, Sxx, Srr, g, nq=8):
+    """Moments in gauge g of n * N((v, 0, 0), diag(Sxx, Srr, Srr)) by quadrature."""
+    n, v, Sxx, Srr = (np.atleast_1d(np.asarray(a, dtype=np.float64))
+                      for a in (n, v, Sxx, Srr))
+    g = np.atleast_2d(np.asarray(g, dtype=np.float64))
+    z, w = _quad.tensor_rule(nq, DIM)
+    out = np.empty((n.shape[0], len(_basis.multi_indices(DIM))))
+    for c in range(n.shape[0]):
+        u = np.empty_like(z)
+        u[:, 0] = v[c] + math.sqrt(Sxx[c]) * z[:, 0]
+        u[:, 1] = math.sqrt(Srr[c]) * z[:, 1]
+        u[:, 2] = math.sqrt(Srr[c]) * z[:, 2]
+        ub = np.empty_like(u)
+        ub[:, 0] = (u[:, 0] - g[c, 0]) / g[c, 1]
+        ub[:, 1] = u[:, 1] / g[c, 2]
+        ub[:, 2] = u[:, 2] / g[c, 2]
+        out[c] = n[c] * (w @ _basis.evaluate(ub, DIM))
+    return out
+
+
+def es_bgk_target(M, g, prandtl):
+    mac = macroscopic(M, g)
+    n, T = mac["n"], mac["T"]
+    Sxx = T / prandtl + (1.0 - 1.0 / prandtl) * mac["Pxx"] / n
+    Srr = T / prandtl + (1.0 - 1.0 / prandtl) * 0.5 * (mac["Pyy"] + mac["Pzz"]) / n
+    return gaussian_moments(n, mac["v"], Sxx, Srr, g), n
+
+
+def collision(M, g, h, prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi)):
+    """M <- (1 - h/tau) M + (h/tau) M~, tau = mu_ref/(Pr n) (Maxwell molecules)."""
+    Mt, n = es_bgk_target(M, g, prandtl)
+    tau = mu_ref / (prandtl * n)
+    r = (h / tau)[:, None]
+    return (1.0 - r) * M + r * Mt
+
+
+def rankine_hugoniot(mach, gamma=5.0 / 3.0):
+    """(n, v, T) upstream and downstream, non-dimensional (m=1, n_-=1, T_-=1)."""
+    m2 = mach * mach
+    ratio = (gamma + 1) * m2 / ((gamma - 1) * m2 + 2)
+    tr = ((2 * gamma * m2 - (gamma - 1)) * ((gamma - 1) * m2 + 2)
+          / ((gamma + 1) ** 2 * m2))
+    v1 = math.sqrt(gamma) * mach
+    return (1.0, v1, 1.0), (ratio, v1 / ratio, tr)
+
+
+def maxwellian_state(n, v, T):
+    """Moments, beta and Hermite gauge of a Maxwellian (moments by quadrature)."""
+    g = np.array([[v, math.sqrt(T), math.sqrt(T)]])
+    M = gaussian_moments(n, v, T, T, g)
+    return M, g
+
+
+def shock_initial(mach, n_cells, x_lo, x_hi, thickness, gamma=5.0 / 3.0):
+    """Cell-centred tanh profile of eq. "Mx ini" (moments interpolated in a common gauge)."""
+    (n1, v1, T1), (n2, v2, T2) = rankine_hugoniot(mach, gamma)
+    gm = np.array([[0.5 * (v1 + v2), 1.0, 1.0]])
+    Mm = gaussian_moments(n1, v1, T1, T1, gm)[0]
+    Mp = gaussian_moments(n2, v2, T2, T2, gm)[0]
+    dx = (x_hi - x_lo) / n_cells
+    x = x_lo + dx * (np.arange(n_cells) + 0.5)
+    th = thickness / 2.0
+    frac = ((np.tanh(x / th) - math.tanh(x_lo / th))
+            / (math.tanh(x_hi / th) - math.tanh(x_lo / th)) - 0.5)
+    M = (Mp - Mm)[None, :] * frac[:, None] + 0.5 * (Mp + Mm)[None, :]
+    g = np.repeat(gm, n_cells, axis=0)
+    return M, g, dx
+
+
+class ShockSolver:
+    """Oracle time stepper for one 1D shock problem (Alg. 2 with LLF)."""
+
+    def __init__(self, mach, n_cells, x_lo, x_hi, thickness, nodes_1d=12,
+                 cfl=0.5, prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi),
+                 gamma=5.0 / 3.0, newton=None):
+        self.nodes, w = _quad.tensor_rule(nodes_1d, DIM)
+        self.logw = _quad.lebesgue_log_weights(self.nodes, w)
+        self.Phi = _basis.evaluate(self.nodes, DIM)
+        self.cfl, self.prandtl, self.mu_ref = cfl, prandtl, mu_ref
+        self.newton = dict(tol_grad=1e-11, max_iter=100)
+        if newton:
+            self.newton.update(newton)
+        (n1, v1, T1), (n2, v2, T2) = rankine_hugoniot(mach, gamma)
+        self.rh = ((n1, v1, T1), (n2, v2, T2))
+        M0, g0, self.dx = shock_initial(mach, n_cells, x_lo, x_hi, thickness, gamma)
+        self.M, _, self.g = _gauge.to_hermite_gauge(M0, None, g0, DIM)
+        self.beta = _maxent.maxwellian_beta(self.M, DIM)
+        # ghost cells: upstream / downstream Maxwellians in their own gauge
+        gh = []
+        for (n, v, T) in self.rh:
+            Mg, gg = maxwellian_state(n, v, T)
+            bg = self._solve(Mg, _maxent.maxwellian_beta(Mg, DIM))
+            Fg = _flux.fluxes(bg, gg, self.nodes, self.Phi, self.logw)
+            rg = _flux.spectral_radius(bg, gg, self.nodes, self.Phi, self.logw)
+            gh.append((Mg[0], Fg[0], rg[0], gg[0]))
+        self.ghost_left, self.ghost_right = gh
+        self.t = 0.0
+        self.beta = self._solve(self.M, self.beta)
+        rho = _flux.spectral_radius(self.beta, self.g, self.nodes, self.Phi, self.logw)
+        self.dt = self._dt(rho)
+
+    def _solve(self, M, beta):
+        out = _maxent.newton_solve(M, beta, self.Phi, self.logw, **self.newton)
+        return out["beta"]
+
+    def _dt(self, rho):
+        rmax = max(np.max(rho), self.ghost_left[2], self.ghost_right[2])
+        return self.cfl * self.dx / rmax
+
+    def _fv(self, M, F, rho, dt):
+        N = M.shape[0]
+        g = self.g
+        MLg, FLg, rL, gL = self.ghost_left
+        MRg, FRg, rR, gR = self.ghost_right
+        # neighbour data (left and right), each in its own gauge
+        Ml = np.vstack([MLg[None], M[:-1]]); Fl = np.vstack([FLg[None], F[:-1]])
+        gl = np.vstack([gL[None], g[:-1]]); rl = np.concatenate([[rL], rho[:-1]])
+        Mr = np.vstack([M[1:], MRg[None]]); Fr = np.vstack([F[1:], FRg[None]])
+        gr = np.vstack([g[1:], gR[None]]); rr = np.concatenate([rho[1:], [rR]])
+        Tl = _gauge.change_matrix(g, gl, DIM)
+        Tr = _gauge.change_matrix(g, gr, DIM)
+        Ml = np.einsum("cij,cj->ci", Tl, Ml); Fl = np.einsum("cij,cj->ci", Tl, Fl)
+        Mr = np.einsum("cij,cj->ci", Tr, Mr); Fr = np.einsum("cij,cj->ci", Tr, Fr)
+        lm = np.maximum(rl, rho)[:, None]
+        lp = np.maximum(rho, rr)[:, None]
+        f_minus = 0.5 * (Fl + F) + 0.5 * lm * (Ml - M)
+        f_plus = 0.5 * (F + Fr) + 0.5 * lp * (M - Mr)
+        return M + dt / self.dx * (f_minus - f_plus)
+
+    def step(self):
+        dt = self.dt
+        M = collision(self.M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
+        beta = self._solve(M, self.beta)
+        F = _flux.fluxes(beta, self.g, self.nodes, self.Phi, self.logw)
+        rho = _flux.spectral_radius(beta, self.g, self.nodes, self.Phi, self.logw)
+        M = self._fv(M, F, rho, dt)
+        M = collision(M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
+        self.M, self.beta, self.g = _gauge.to_hermite_gauge(M, beta, self.g, DIM)
+        self.t += dt
+        self.dt = self._dt(rho)
+        return dt
