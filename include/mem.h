@@ -1,0 +1,251 @@
+/*
+ * mem.h -- C ABI of the MI355X (gfx950) maximal-entropy moment method library.
+ *
+ * The library implements, as HIP kernels, the per-cell maximal-entropy dual
+ * problem of the canonical-form exponential family and the finite-volume step
+ * around it, following "Stabilizing the Maximal Entropy Moment Method for
+ * Rarefied Gas Dynamics at Single-Precision" (Zheng, Wang, Chen):
+ *
+ *   canonical form f = n exp(beta_i phi_i(u_bar) - log Z(beta)),  i >= 1
+ *       (Sec. 2.2, eq. "exp family"; beta_0 = n is the number density);
+ *   log Z by log-sum-exp over fixed quadrature nodes (Sec. 3.1);
+ *   dual objective, gradient and Hessian (App. C);
+ *   modified Newton with lambda*I shift and Armijo backtracking (Alg. 1);
+ *   gauge u_bar = ((u_x - w_x)/s_x, u_y/s_r, u_z/s_r), Hermite gauge and the
+ *       change of gauge T(g', g) (Sec. 3.3);
+ *   moment fluxes, local Lax--Friedrichs in local gauges, ES-BGK source
+ *       splitting and the time step of Alg. 2 (Sec. 3.4, App. A).
+ *
+ * Discretisation: tensor Gauss--Hermite nodes fixed in gauge coordinates
+ * (n_nodes_1d per axis), basis = orthonormal Hermite products of total degree
+ * <= 4: phi_(a,b,c) = He_a(x) He_b(y) He_c(z) / sqrt(a! b! c!), K = 35 in 3D
+ * (K = 5 in 1D, phi_k = He_k/sqrt(k!)).  Basis order: by total degree, then
+ * lexicographically descending in (a,b,c); index 0 = 1, 1..3 = x, y, z.
+ *
+ * Conventions for every entry point
+ *   - Arrays named M, beta, F, g, lam, iters, resid, status, t, dt are DEVICE
+ *     pointers owned by the caller (for example PyTorch tensors), row-major:
+ *     M[n][K], beta[n][K], F[n][K], g[n][G] with G = 2 (1D: w, s) or
+ *     G = 3 (3D: w_x, s_x, s_r).  Struct arguments (mem_config_t,
+ *     mem_solve_opts_t, mem_batch_t) are HOST memory; the pointers inside
+ *     mem_batch_t are device pointers.
+ *   - Every call is asynchronous on `stream` (NULL = default stream) except
+ *     where stated.  A context is used by one stream at a time.
+ *   - Return codes report API misuse and HIP failures only.  Numerical
+ *     failure of a cell never returns an error: it sets that cell's status
+ *     bits (MEM_ST_*) and leaves the rest of the batch untouched.
+ *   - Only mem_create and mem_reserve allocate device memory.  Entry points
+ *     that need workspace grow it through mem_reserve when it is too small;
+ *     reserve first to keep allocation out of timed or captured regions.
+ */
+#ifndef MEM_H
+#define MEM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MEM_API __attribute__((visibility("default")))
+
+typedef struct mem_ctx_s* mem_ctx_t;
+
+typedef enum {
+  MEM_OK = 0,
+  MEM_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad option      */
+  MEM_ERR_HIP = 2,           /* a HIP runtime call or kernel launch failed   */
+  MEM_ERR_NOMEM = 3,         /* device allocation failed                     */
+  MEM_ERR_UNSUPPORTED = 4    /* configuration this build does not implement  */
+} mem_err_t;
+
+/* Arithmetic of the moment/Hessian assembly GEMM. */
+typedef enum {
+  MEM_PREC_FP32 = 0,         /* FP32 MFMA (v_mfma_f32_16x16x4_f32)           */
+  MEM_PREC_BF16X3 = 1,       /* hi+lo BF16 split, 3 products, FP32 accumulate */
+  MEM_PREC_FP16X3 = 2        /* hi+lo FP16 split, 3 products, FP32 accumulate */
+} mem_prec_t;
+
+/* Per-cell status bits (written by mem_maxent_solve and mem_step). */
+#define MEM_ST_CONVERGED     0x01u  /* max_i |G_i| <= tol_grad, or decrement <= tol_dec with max|G| <= tol_grad_loose */
+#define MEM_ST_MAXITER       0x02u  /* iteration budget exhausted                                  */
+#define MEM_ST_STAGNATED     0x04u  /* line-search step alpha <= alpha_min (Alg. 1 exit test)      */
+#define MEM_ST_SHIFTED       0x08u  /* Cholesky needed H + lambda I at least once (Alg. 1)         */
+#define MEM_ST_FP64          0x10u  /* FP32 pivot ratio below threshold: direction solved in FP64  */
+#define MEM_ST_NONFINITE     0x20u  /* non-finite input or iterate                                 */
+#define MEM_ST_NONREALIZABLE 0x40u  /* n <= 0, or the dual value fell below min_p log w~_p, which
+                                       certifies that no minimiser exists on the node set, or
+                                       |beta| exceeded beta_max                                */
+#define MEM_ST_LAMBDA_FAIL   0x80u  /* characteristic speeds could not be computed                 */
+
+typedef struct {
+  int32_t dim;          /* 1 or 3                                                      */
+  int32_t n_nodes_1d;   /* Gauss--Hermite nodes per velocity axis (2..64)              */
+  int32_t prec;         /* mem_prec_t used by the Newton Hessian assembly              */
+  int32_t reserved;     /* must be 0                                                   */
+} mem_config_t;
+
+/* Options of Alg. 1.  Defaults (mem_solve_opts_default) are the paper's
+ * constants where it gives them: tol 1e-8 on the Newton decrement, maxI 400,
+ * maxT 25 (26 trials alpha = 1 .. 2^-25), Armijo c = 5e-4, atol = 5e-6,
+ * rtol = 5e-5, lambda = 1e-3 growing x10, exit when alpha <= 1e-6. */
+typedef struct {
+  float   tol_grad;         /* stop when max_{i>=1} |E[phi_i] - M_i/n| <= tol_grad (2e-6)  */
+  float   tol_dec;          /* or when 1/2 G^T (H+lambda I)^-1 G <= tol_dec (1e-8) ...      */
+  float   tol_grad_loose;   /* ... and max|G| <= tol_grad_loose (1e-5)                       */
+  int32_t max_iter;         /* Newton iterations per solve (400)                             */
+  int32_t max_ls;           /* line-search halvings (25)                                     */
+  float   armijo_c;         /* 5e-4                                                          */
+  float   atol;             /* 5e-6                                                          */
+  float   rtol;             /* 5e-5                                                          */
+  float   lambda0;          /* first Hessian shift (1e-3)                                    */
+  float   lambda_mul;       /* shift growth factor (10)                                      */
+  float   alpha_min;        /* alpha <= alpha_min ends the solve as stagnated (1e-6)         */
+  float   fp64_pivot_ratio; /* min/max Cholesky pivot below this -> FP64 direction (1e-6);
+                               0 disables the FP64 path (pure FP32 Alg. 1)                   */
+  int32_t check_every;      /* mem_maxent_solve polls the live-cell count every this many
+                               iterations (2); 0 = never poll (runs max_iter iterations)     */
+  int32_t refine;           /* residual refinement passes (3): cells that converge, or
+                               whose FP32 residual (<= 1e-3) stops halving for 6
+                               iterations, get their residual re-evaluated with a
+                               compensated FP32 exponent and moment sum (double-float
+                               arithmetic) and, while above tol_grad, a Newton correction
+                               with their FP32 Hessian; the reported resid is this
+                               compensated residual and a cell is CONVERGED only if it is
+                               <= tol_grad_loose (else STAGNATED).  0 = off.               */
+  float   beta_max;         /* |beta_i|, i >= 1, above this ends the cell as NONREALIZABLE
+                               (100; 0 = off).  In the Hermite gauge solvable targets have
+                               |beta| of order 1-10; iterates that run away along a ray
+                               of the dual (targets outside the nodes' moment set) are
+                               stopped here before the dual-value certificate fires.      */
+} mem_solve_opts_t;
+
+/* A ragged batch of independent 1D normal-shock problems (dim must be 3).
+ * Cells of problem p are cell_offsets[p] .. cell_offsets[p+1]-1 of the flat
+ * M/beta/g arrays, ordered left to right.  Boundary (ghost) states are
+ * Maxwellian moments M_left/M_right in their own gauges g_left/g_right. */
+typedef struct {
+  int64_t        n_cells;        /* host copy of cell_offsets[n_problems]                   */
+  int32_t        n_problems;
+  int32_t        collision;      /* 0 = BGK (Pr forced to 1), 1 = ES-BGK                   */
+  const int64_t* cell_offsets;   /* device [n_problems + 1]                                 */
+  const float*   dx;             /* device [n_problems]                                     */
+  const float*   M_left;         /* device [n_problems][K]                                  */
+  const float*   M_right;        /* device [n_problems][K]                                  */
+  const float*   g_left;         /* device [n_problems][3]                                  */
+  const float*   g_right;        /* device [n_problems][3]                                  */
+  float          cfl;            /* dt = cfl * dx / max spectral radius (0.5)               */
+  float          prandtl;        /* 2/3 for monatomic gas (App. A)                          */
+  float          mu_ref;         /* viscosity at T = 1; tau = mu_ref / (Pr n)  (sqrt(2/pi)) */
+  int32_t        newton_per_step;/* Newton iteration budget per time step (8)               */
+} mem_batch_t;
+
+/* ---- context -------------------------------------------------------------- */
+
+/* Build the quadrature and basis tables in FP64 on the host, convert them to
+ * the device layouts and upload them to the current device.  Allocates. */
+MEM_API mem_err_t mem_create(const mem_config_t* cfg, mem_ctx_t* out);
+MEM_API mem_err_t mem_destroy(mem_ctx_t ctx);
+/* Pre-size the per-cell workspace for up to max_cells cells and max_problems
+ * problems (graph- and timing-safe calls afterwards).  Allocates. */
+MEM_API mem_err_t mem_reserve(mem_ctx_t ctx, int64_t max_cells, int32_t max_problems);
+MEM_API const char* mem_strerror(mem_err_t err);
+/* Detail of the last error on this context (host string, valid until the next call). */
+MEM_API const char* mem_last_error(mem_ctx_t ctx);
+MEM_API void mem_solve_opts_default(mem_solve_opts_t* opts);
+MEM_API int32_t mem_n_basis(mem_ctx_t ctx);   /* K */
+MEM_API int32_t mem_n_nodes(mem_ctx_t ctx);   /* Q = n_nodes_1d^dim */
+/* Copy a host-side FP64 table built by mem_create (for checking).  which:
+ * 0 = nodes [Q][dim], 1 = weights [Q] (sum 1), 2 = Phi [Q][K].  Writes at most
+ * n_values doubles to host_out; returns the table size through n_total. */
+MEM_API mem_err_t mem_copy_table(mem_ctx_t ctx, int32_t which, double* host_out,
+                                 int64_t n_values, int64_t* n_total);
+
+/* Host-only variant of mem_copy_table that needs no device: builds the FP64
+ * tables of (dim, n_nodes_1d) on the host and copies table `which` (as above,
+ * plus 3 = Lebesgue log weights [Q]). */
+MEM_API mem_err_t mem_host_table(int32_t dim, int32_t n_nodes_1d, int32_t which,
+                                 double* host_out, int64_t n_values, int64_t* n_total);
+
+/* ---- hot path --------------------------------------------------------------- */
+
+/* Hermite gauge (Sec. 3.3, eqs. "Hermite parameters", "Change gauge M F";
+ * Alg. 2 ComputeGaugeParameters + GaugeTransformation).  In place for n_cells
+ * cells: reads M and g, computes the Hermite gauge g_H from the moments,
+ * writes M <- T(g_H, g) M, beta_{i>=1} <- (T(g, g_H)^T alpha)_{i>=1} (beta may
+ * be NULL; beta_0 is left as n) and g <- g_H.  Cells with n <= 0 or a
+ * non-positive variance are left unchanged. */
+MEM_API mem_err_t mem_gauge(mem_ctx_t ctx, int64_t n_cells, float* M, float* beta,
+                            float* g, hipStream_t stream);
+
+/* Alg. 1 for every cell: find beta minimising the dual objective for target
+ * moments M (in each cell's gauge, M[:,0] = n > 0).  beta: in = initial guess
+ * (beta[:,0] ignored), out = solution with beta[:,0] = n.  iters, resid
+ * (max_{i>=1}|G_i| at the returned beta, FP32) and status are per-cell
+ * outputs, each may be NULL.  Synchronises `stream` every check_every
+ * iterations to poll the number of live cells. */
+MEM_API mem_err_t mem_maxent_solve(mem_ctx_t ctx, int64_t n_cells, const float* M,
+                                   float* beta, const mem_solve_opts_t* opts,
+                                   int32_t* iters, float* resid, uint32_t* status,
+                                   hipStream_t stream);
+
+/* Dual evaluation at given beta (Sec. 3.1 and App. C), for checking the
+ * kernels: logZ[n] (log partition function with Lebesgue weights), E[n][K] =
+ * E_sigma[phi], H[n][K-1][K-1] = covariance block of the Hessian (i,j >= 1).
+ * Any output may be NULL.  dim must be 3. */
+MEM_API mem_err_t mem_dual(mem_ctx_t ctx, int64_t n_cells, const float* beta,
+                           float* logZ, float* E, float* H, hipStream_t stream);
+
+/* Moment fluxes (eq. "The ME equation", flux line; Alg. 2 ComputeFluxes):
+ * F[n][K] = int u_x phi_i(u_bar) f du in each cell's gauge, from beta
+ * (beta[:,0] = n) and g.  lam[n][2] (may be NULL) = (min, max) eigenvalue of
+ * dF/dM in physical units (local Lax--Friedrichs speeds, Sec. 3.4). */
+MEM_API mem_err_t mem_flux(mem_ctx_t ctx, int64_t n_cells, const float* beta,
+                           const float* g, float* F, float* lam, hipStream_t stream);
+
+/* ES-BGK source term by operator splitting (eq. "source update", App. A):
+ * M <- (1 - h/tau) M + (h/tau) M~(g), tau = mu_ref/(Pr n), in place.  The
+ * target M~ is the axisymmetric Gaussian with Sigma = T/Pr I + (1-1/Pr) P/n.
+ * dim must be 3. */
+MEM_API mem_err_t mem_collide(mem_ctx_t ctx, int64_t n_cells, float* M, const float* g,
+                              float h, float prandtl, float mu_ref, hipStream_t stream);
+
+/* Alg. 2 Step, n_steps times, for a ragged batch: Collision(dt/2),
+ * Transport(dt) = MaxEnt solve (warm start from beta, at most
+ * newton_per_step iterations) + fluxes + characteristic speeds + local
+ * Lax--Friedrichs update with neighbours moved into each cell's gauge,
+ * Collision(dt/2), Hermite-gauge update.  M, beta, g: device [n_cells][K|3],
+ * in/out.  t: device [n_problems], advanced.  dt: device [n_problems], in =
+ * step for the first step (a value <= 0 requests one from a solve of the
+ * current state), out = step for the next call (CFL rule from the last
+ * transport's speeds).  status (may be NULL): device [n_cells], OR of the
+ * cells' solve status over the steps.  No host synchronisation. */
+MEM_API mem_err_t mem_step(mem_ctx_t ctx, const mem_batch_t* batch, float* M, float* beta,
+                           float* g, float* t, float* dt, int32_t n_steps,
+                           const mem_solve_opts_t* opts, uint32_t* status,
+                           hipStream_t stream);
+
+/* Conserved totals per problem in FP64 (check of mem_step):
+ * out[p][3] = dx * sum over the problem's cells of (n, n v_x, n (v^2/2 + 3T/2))
+ * computed in double precision from M and g.  out is a device double array. */
+MEM_API mem_err_t mem_conserved(mem_ctx_t ctx, const mem_batch_t* batch, const float* M,
+                                const float* g, double* out, hipStream_t stream);
+
+/* ---- measurement -------------------------------------------------------------- */
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * launch of the selected kernels while enabled (enable != 0 clears the
+ * totals).  kernel: 0 = assembly GEMM (k_assemble3), 1 = Newton direction
+ * (k_direction3), 2 = log-sum-exp / line search (k_lse3).  mem_profile_read
+ * synchronises on the recorded events and returns the summed duration in ms
+ * and the number of launches timed. */
+MEM_API mem_err_t mem_profile_enable(mem_ctx_t ctx, int32_t enable);
+MEM_API mem_err_t mem_profile_read(mem_ctx_t ctx, int32_t kernel, double* total_ms,
+                                   int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEM_H */

@@ -25,6 +25,14 @@ oracle stops on max_{i>=1} |G_i| <= tol_grad so that it reaches the FP64 floor.
 
 Moments and the Hessian are direct weighted sums over nodes (Phi^T diag(sigma)
 Phi), never a table of basis products.
+
+Realizability on the node set (Sec. 2.3 discusses when beta exists): at a
+minimiser sigma* matches the targets, so
+    logZ(beta*) - beta*.M/n = sum_p sigma*_p log w~_p - sum_p sigma*_p log sigma*_p
+                            >= min_p log w~_p.
+An iterate whose value logZ - beta.M/n falls below min_p log w~_p therefore
+certifies that the discrete dual has no minimiser (the targets lie outside the
+moment set of distributions on the nodes); such cells stop as non-realizable.
 """
 
 import numpy as np
@@ -74,6 +82,11 @@ def objective(beta, M, Phi, logw):
     logZ = log_partition(beta, Phi, logw)
     return (logZ - np.sum(beta[:, 1:] * M[:, 1:], axis=1) / n
             - n ** 2 * (np.log(b0) - b0 / n))
+
+
+def dual_value(beta, M, Phi, logw):
+    """logZ(beta) - sum_{i>=1} beta_i M_i/n (L without its constant beta_0 term)."""
+    return log_partition(beta, Phi, logw) - np.sum(beta[:, 1:] * M[:, 1:], axis=1) / M[:, 0]
 
 
 def gradient(beta, M, Phi, logw):
@@ -137,8 +150,10 @@ def newton_solve(M, beta_init, Phi, logw, tol_grad=1e-12, tol_dec=0.0,
     """Alg. 1 for a batch of independent cells (FP64).
 
     Returns dict with beta (C, K), iters, resid (max_{i>=1}|G_i| at the
-    returned beta), converged, stagnated, shifted (lambda used at least once),
-    cond (condition number of the last unshifted covariance block).
+    returned beta), converged, stagnated, nonrealizable (certified by the
+    lower bound min_p log w~_p on the dual value at a minimiser), shifted
+    (lambda used at least once), cond (condition number of the last
+    unshifted covariance block).
     """
     M = np.asarray(M, dtype=np.float64)
     C, K = M.shape
@@ -152,8 +167,10 @@ def newton_solve(M, beta_init, Phi, logw, tol_grad=1e-12, tol_dec=0.0,
     converged = np.zeros(C, dtype=bool)
     stagnated = np.zeros(C, dtype=bool)
     shifted = np.zeros(C, dtype=bool)
+    nonreal = np.zeros(C, dtype=bool)
     cond = np.zeros(C)
     active = np.ones(C, dtype=bool)
+    lmin = np.min(logw)
 
     for _ in range(max_iter + 1):
         act = np.nonzero(active)[0]
@@ -205,14 +222,17 @@ def newton_solve(M, beta_init, Phi, logw, tol_grad=1e-12, tol_dec=0.0,
         done_grad = r <= tol_grad
         done_dec = res <= tol_dec
         stag = a <= alpha_min
-        fin = done_grad | done_dec | stag | ~np.isfinite(res)
+        below = dual_value(b, m, Phi, logw) < lmin
+        fin = done_grad | done_dec | stag | below | ~np.isfinite(res)
         converged[act] = done_grad | done_dec
-        stagnated[act] = stag & ~(done_grad | done_dec)
+        nonreal[act] = below & ~(done_grad | done_dec)
+        stagnated[act] = stag & ~(done_grad | done_dec) & ~below
         active[act[fin]] = False
         over = iters > max_iter
         active &= ~over
     return dict(beta=beta, iters=iters, resid=resid, converged=converged,
-                stagnated=stagnated, shifted=shifted, cond=cond, alpha=alpha)
+                stagnated=stagnated, nonrealizable=nonreal, shifted=shifted, cond=cond,
+                alpha=alpha)
 
 
 def moment_residual(beta, M, Phi, logw):

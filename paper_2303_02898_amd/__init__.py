@@ -1,0 +1,310 @@
+"""MI355X (gfx950) maximal-entropy moment method -- Python binding.
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels
+of ``libmem_mi355x.so`` (built in-tree by ``python -m paper_2303_02898_amd.build``).
+PyTorch supplies device memory and the current HIP stream.  If the library is
+missing, creating a :class:`Context` raises -- there is no fallback path.
+
+Entry points mirror ``include/mem.h``: ``gauge``, ``solve`` (mem_maxent_solve),
+``dual``, ``flux``, ``collide``, ``step`` and ``conserved``.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmem_mi355x.so")
+
+ST_CONVERGED = 0x01
+ST_MAXITER = 0x02
+ST_STAGNATED = 0x04
+ST_SHIFTED = 0x08
+ST_FP64 = 0x10
+ST_NONFINITE = 0x20
+ST_NONREALIZABLE = 0x40
+ST_LAMBDA_FAIL = 0x80
+
+PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
+
+_c_i32, _c_i64, _c_f32, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
+
+
+class MemConfig(ctypes.Structure):
+    _fields_ = [("dim", _c_i32), ("n_nodes_1d", _c_i32), ("prec", _c_i32), ("reserved", _c_i32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol_grad", _c_f32), ("tol_dec", _c_f32), ("tol_grad_loose", _c_f32),
+                ("max_iter", _c_i32), ("max_ls", _c_i32), ("armijo_c", _c_f32),
+                ("atol", _c_f32), ("rtol", _c_f32), ("lambda0", _c_f32),
+                ("lambda_mul", _c_f32), ("alpha_min", _c_f32),
+                ("fp64_pivot_ratio", _c_f32), ("check_every", _c_i32), ("refine", _c_i32),
+                ("beta_max", _c_f32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_cells", _c_i64), ("n_problems", _c_i32), ("collision", _c_i32),
+                ("cell_offsets", _vp), ("dx", _vp), ("M_left", _vp), ("M_right", _vp),
+                ("g_left", _vp), ("g_right", _vp), ("cfl", _c_f32), ("prandtl", _c_f32),
+                ("mu_ref", _c_f32), ("newton_per_step", _c_i32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmem_mi355x.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {LIB_PATH}; build it with "
+                           "`python -m paper_2303_02898_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, E = _vp, ctypes.c_int
+    sig = {
+        "mem_create": ([ctypes.POINTER(MemConfig), ctypes.POINTER(_vp)], E),
+        "mem_destroy": ([P], E),
+        "mem_reserve": ([P, _c_i64, _c_i32], E),
+        "mem_strerror": ([E], ctypes.c_char_p),
+        "mem_last_error": ([P], ctypes.c_char_p),
+        "mem_solve_opts_default": ([ctypes.POINTER(SolveOpts)], None),
+        "mem_n_basis": ([P], _c_i32),
+        "mem_n_nodes": ([P], _c_i32),
+        "mem_copy_table": ([P, _c_i32, P, _c_i64, ctypes.POINTER(_c_i64)], E),
+        "mem_host_table": ([_c_i32, _c_i32, _c_i32, P, _c_i64, ctypes.POINTER(_c_i64)], E),
+        "mem_gauge": ([P, _c_i64, P, P, P, P], E),
+        "mem_maxent_solve": ([P, _c_i64, P, P, ctypes.POINTER(SolveOpts), P, P, P, P], E),
+        "mem_dual": ([P, _c_i64, P, P, P, P, P], E),
+        "mem_flux": ([P, _c_i64, P, P, P, P, P], E),
+        "mem_collide": ([P, _c_i64, P, P, _c_f32, _c_f32, _c_f32, P], E),
+        "mem_step": ([P, ctypes.POINTER(Batch), P, P, P, P, P, _c_i32,
+                      ctypes.POINTER(SolveOpts), P, P], E),
+        "mem_conserved": ([P, ctypes.POINTER(Batch), P, P, P, P], E),
+        "mem_profile_enable": ([P, _c_i32], E),
+        "mem_profile_read": ([P, _c_i32, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(_c_i64)], E),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def host_table(dim, n_nodes_1d, which):
+    """FP64 table built by the library's host code (no device needed)."""
+    import numpy as np
+    lib = load_library()
+    wid = {"nodes": 0, "weights": 1, "phi": 2, "logw": 3}[which]
+    tot = _c_i64()
+    err = lib.mem_host_table(dim, n_nodes_1d, wid, None, 0, ctypes.byref(tot))
+    if err != 0:
+        raise MemError(f"mem_host_table: {lib.mem_strerror(err).decode()}")
+    out = np.empty(tot.value, dtype=np.float64)
+    lib.mem_host_table(dim, n_nodes_1d, wid, out.ctypes.data, tot.value, None)
+    K = 35 if dim == 3 else 5
+    if which == "nodes":
+        return out.reshape(-1, dim)
+    if which == "phi":
+        return out.reshape(-1, K)
+    return out
+
+
+def default_opts(**kw):
+    lib = load_library()
+    o = SolveOpts()
+    lib.mem_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t, dtype=None, shape_tail=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (n, {shape_tail})")
+    del torch
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class MemError(RuntimeError):
+    pass
+
+
+class Context:
+    """A library context: quadrature/basis tables on the current device plus workspace."""
+
+    def __init__(self, dim=3, n_nodes_1d=12, prec="fp32"):
+        self._lib = load_library()
+        cfg = MemConfig(dim, n_nodes_1d, PREC[prec] if isinstance(prec, str) else int(prec), 0)
+        h = _vp()
+        err = self._lib.mem_create(ctypes.byref(cfg), ctypes.byref(h))
+        if err != 0:
+            raise MemError(f"mem_create: {self._lib.mem_strerror(err).decode()}")
+        self._h = h
+        self.dim = dim
+        self.n_nodes_1d = n_nodes_1d
+        self.K = self._lib.mem_n_basis(h)
+        self.Q = self._lib.mem_n_nodes(h)
+        self.G = 2 if dim == 1 else 3
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, err, what):
+        if err != 0:
+            detail = self._lib.mem_last_error(self._h).decode()
+            raise MemError(f"{what}: {self._lib.mem_strerror(err).decode()} ({detail})")
+
+    def reserve(self, max_cells, max_problems=0):
+        self._check(self._lib.mem_reserve(self._h, int(max_cells), int(max_problems)), "mem_reserve")
+
+    def table(self, which):
+        """Host FP64 table: 'nodes' (Q, dim), 'weights' (Q,), 'phi' (Q, K)."""
+        import numpy as np
+        wid = {"nodes": 0, "weights": 1, "phi": 2}[which]
+        tot = _c_i64()
+        self._check(self._lib.mem_copy_table(self._h, wid, None, 0, ctypes.byref(tot)), "mem_copy_table")
+        out = np.empty(tot.value, dtype=np.float64)
+        self._check(self._lib.mem_copy_table(self._h, wid, out.ctypes.data, tot.value, None),
+                    "mem_copy_table")
+        if which == "nodes":
+            return out.reshape(-1, self.dim)
+        if which == "phi":
+            return out.reshape(-1, self.K)
+        return out
+
+    def profile(self, enable=True):
+        """Enable (and clear) or disable HIP-event timing of the solver kernels."""
+        self._check(self._lib.mem_profile_enable(self._h, 1 if enable else 0), "mem_profile_enable")
+
+    def profile_read(self, kernel):
+        """(total ms, launches) for kernel 'assemble', 'direction' or 'lse'."""
+        kid = {"assemble": 0, "direction": 1, "lse": 2}[kernel]
+        ms, cnt = ctypes.c_double(), _c_i64()
+        self._check(self._lib.mem_profile_read(self._h, kid, ctypes.byref(ms), ctypes.byref(cnt)),
+                    "mem_profile_read")
+        return ms.value, cnt.value
+
+    # ---- hot path -------------------------------------------------------------------
+    def gauge(self, M, beta, g, stream=None):
+        import torch
+        n = M.shape[0]
+        self._check(self._lib.mem_gauge(
+            self._h, n, _ptr(M, torch.float32, (self.K,), "M"),
+            _ptr(beta, torch.float32, (self.K,), "beta"), _ptr(g, torch.float32, (self.G,), "g"),
+            _stream(stream)), "mem_gauge")
+
+    def solve(self, M, beta, opts=None, iters=None, resid=None, status=None, stream=None):
+        import torch
+        n = M.shape[0]
+        dev = M.device
+        if iters is None:
+            iters = torch.zeros(n, dtype=torch.int32, device=dev)
+        if resid is None:
+            resid = torch.zeros(n, dtype=torch.float32, device=dev)
+        if status is None:
+            status = torch.zeros(n, dtype=torch.int32, device=dev)
+        o = ctypes.byref(opts) if opts is not None else None
+        self._check(self._lib.mem_maxent_solve(
+            self._h, n, _ptr(M, torch.float32, (self.K,), "M"),
+            _ptr(beta, torch.float32, (self.K,), "beta"), o, _ptr(iters, torch.int32),
+            _ptr(resid, torch.float32), _ptr(status, torch.int32), _stream(stream)),
+            "mem_maxent_solve")
+        return iters, resid, status
+
+    def dual(self, beta, stream=None):
+        import torch
+        n = beta.shape[0]
+        dev = beta.device
+        logZ = torch.empty(n, dtype=torch.float32, device=dev)
+        E = torch.empty(n, self.K, dtype=torch.float32, device=dev)
+        H = torch.empty(n, self.K - 1, self.K - 1, dtype=torch.float32, device=dev)
+        self._check(self._lib.mem_dual(self._h, n, _ptr(beta, torch.float32, (self.K,), "beta"),
+                                       logZ.data_ptr(), E.data_ptr(), H.data_ptr(),
+                                       _stream(stream)), "mem_dual")
+        return logZ, E, H
+
+    def flux(self, beta, g, want_lam=True, stream=None):
+        import torch
+        n = beta.shape[0]
+        F = torch.empty(n, self.K, dtype=torch.float32, device=beta.device)
+        lam = torch.empty(n, 2, dtype=torch.float32, device=beta.device) if want_lam else None
+        self._check(self._lib.mem_flux(self._h, n, _ptr(beta, torch.float32, (self.K,), "beta"),
+                                       _ptr(g, torch.float32, (3,), "g"), F.data_ptr(),
+                                       lam.data_ptr() if lam is not None else None,
+                                       _stream(stream)), "mem_flux")
+        return F, lam
+
+    def collide(self, M, g, h, prandtl=2.0 / 3.0, mu_ref=0.7978845608028654, stream=None):
+        import torch
+        self._check(self._lib.mem_collide(self._h, M.shape[0], _ptr(M, torch.float32, (self.K,), "M"),
+                                          _ptr(g, torch.float32, (3,), "g"), float(h),
+                                          float(prandtl), float(mu_ref), _stream(stream)),
+                    "mem_collide")
+
+    def step(self, batch, M, beta, g, t, dt, n_steps, opts=None, status=None, stream=None):
+        import torch
+        o = ctypes.byref(opts) if opts is not None else None
+        self._check(self._lib.mem_step(
+            self._h, ctypes.byref(batch.struct), _ptr(M, torch.float32, (self.K,), "M"),
+            _ptr(beta, torch.float32, (self.K,), "beta"), _ptr(g, torch.float32, (3,), "g"),
+            _ptr(t, torch.float32), _ptr(dt, torch.float32), int(n_steps), o,
+            _ptr(status, torch.int32) if status is not None else None, _stream(stream)), "mem_step")
+
+    def conserved(self, batch, M, g, stream=None):
+        import torch
+        out = torch.zeros(batch.n_problems, 3, dtype=torch.float64, device=M.device)
+        self._check(self._lib.mem_conserved(self._h, ctypes.byref(batch.struct),
+                                            _ptr(M, torch.float32, (self.K,), "M"),
+                                            _ptr(g, torch.float32, (3,), "g"), out.data_ptr(),
+                                            _stream(stream)), "mem_conserved")
+        return out
+
+
+class ShockBatch:
+    """Device-side description of a ragged batch of 1D shock problems (mem_batch_t)."""
+
+    def __init__(self, offsets, dx, M_left, M_right, g_left, g_right, device="cuda",
+                 cfl=0.5, prandtl=2.0 / 3.0, mu_ref=0.7978845608028654, collision=1,
+                 newton_per_step=8):
+        import torch
+        f32 = dict(dtype=torch.float32, device=device)
+        self.offsets = torch.as_tensor(offsets, dtype=torch.int64, device=device).contiguous()
+        self.n_problems = int(self.offsets.numel() - 1)
+        self.n_cells = int(self.offsets[-1].item())
+        self.dx = torch.as_tensor(dx, **f32).reshape(self.n_problems).contiguous()
+        self.M_left = torch.as_tensor(M_left, **f32).reshape(self.n_problems, 35).contiguous()
+        self.M_right = torch.as_tensor(M_right, **f32).reshape(self.n_problems, 35).contiguous()
+        self.g_left = torch.as_tensor(g_left, **f32).reshape(self.n_problems, 3).contiguous()
+        self.g_right = torch.as_tensor(g_right, **f32).reshape(self.n_problems, 3).contiguous()
+        self.struct = Batch(self.n_cells, self.n_problems, int(collision), self.offsets.data_ptr(),
+                            self.dx.data_ptr(), self.M_left.data_ptr(), self.M_right.data_ptr(),
+                            self.g_left.data_ptr(), self.g_right.data_ptr(), float(cfl),
+                            float(prandtl), float(mu_ref), int(newton_per_step))

@@ -1,0 +1,503 @@
+// C ABI of the MEM library: context, argument checks, workspace and the launch
+// sequences of the entry points declared in include/mem.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "mem_internal.h"
+
+using namespace memk;
+
+namespace {
+
+mem_err_t fail(mem_ctx_t c, mem_err_t e, const std::string& msg) {
+  if (c) c->err = msg;
+  return e;
+}
+
+#define MEM_HIP(c, x)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      return fail((c), MEM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+template <typename T>
+bool dalloc(T*& p, size_t count) {
+  dfree(p);
+  return hipMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T)) == hipSuccess;
+}
+
+void free_workspace(mem_ctx_t c) {
+  dfree(c->w_S); dfree(c->w_Sx); dfree(c->w_dbeta); dfree(c->w_logZ); dfree(c->w_L);
+  dfree(c->w_alpha); dfree(c->w_gdot); dfree(c->w_resid); dfree(c->w_iters);
+  dfree(c->w_status);
+  for (auto& l : c->w_list) dfree(l);
+  dfree(c->w_Eacc); dfree(c->w_racc); dfree(c->w_rbest); dfree(c->w_itbest);
+  dfree(c->w_Mnew); dfree(c->w_F); dfree(c->w_rho); dfree(c->w_prob);
+  c->cap_cells = 0;
+}
+
+void free_problems(mem_ctx_t c) {
+  dfree(c->w_gM); dfree(c->w_gB); dfree(c->w_gG); dfree(c->w_gF); dfree(c->w_gR);
+  dfree(c->w_rmax);
+  c->cap_problems = 0;
+}
+
+SolveParams params_from(const mem_solve_opts_t* o) {
+  mem_solve_opts_t d;
+  mem_solve_opts_default(&d);
+  if (!o) o = &d;
+  SolveParams p;
+  p.tol_grad = o->tol_grad; p.tol_dec = o->tol_dec; p.tol_loose = o->tol_grad_loose;
+  p.max_iter = o->max_iter; p.max_ls = o->max_ls;
+  p.c = o->armijo_c; p.atol = o->atol; p.rtol = o->rtol;
+  p.lambda0 = o->lambda0; p.lambda_mul = o->lambda_mul; p.alpha_min = o->alpha_min;
+  p.fp64_ratio = o->fp64_pivot_ratio;
+  p.beta_max = o->beta_max;
+  p.lmin = -3.0e38f;
+  p.refine = 0;
+  return p;
+}
+
+// Lower bound of the dual value at any minimiser: min_p log w~_p (small margin
+// for FP32 evaluation of the value).
+float dual_floor(mem_ctx_t c) {
+  double m = 1e300;
+  for (double v : c->h_logw) m = std::min(m, v);
+  return (float)(m - 1e-3 * (1.0 + std::fabs(m)));
+}
+
+bool opts_ok(const mem_solve_opts_t* o) {
+  if (!o) return true;
+  return o->max_iter >= 1 && o->max_iter <= 100000 && o->max_ls >= 0 && o->max_ls <= 60 &&
+         o->lambda0 > 0.f && o->lambda_mul > 1.f && o->check_every >= 0 &&
+         o->fp64_pivot_ratio >= 0.f && o->fp64_pivot_ratio < 1.f && std::isfinite(o->tol_grad) &&
+         o->refine >= 0 && o->refine <= 8 && o->beta_max >= 0.f;
+}
+
+mem_err_t ensure_cells(mem_ctx_t c, int64_t n) {
+  if (n <= c->cap_cells) return MEM_OK;
+  return mem_reserve(c, n, c->cap_problems);
+}
+
+// Optional event pair around a launch (kernel timing for measurement).
+struct ProfScope {
+  mem_ctx_t c; int k; hipStream_t s; hipEvent_t b = nullptr, e = nullptr;
+  ProfScope(mem_ctx_t c_, int k_, hipStream_t s_) : c(c_), k(k_), s(s_) {
+    if (c->prof && c->prof_used + 2 <= c->prof_pool.size()) {
+      b = c->prof_pool[c->prof_used++];
+      e = c->prof_pool[c->prof_used++];
+      (void)hipEventRecord(b, s);
+    }
+  }
+  ~ProfScope() {
+    if (b) {
+      (void)hipEventRecord(e, s);
+      c->prof_marks.push_back({k, {b, e}});
+    }
+  }
+};
+
+// Newton iterations of Alg. 1 over the live work-list.  With poll > 0 the
+// stream is synchronised every `poll` iterations to stop once no cell is live.
+// Counters: 0/1 live lists (alternating), 2 FP64 list, 3 converged list,
+// 4/5 refinement lists.
+mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const SolveParams& p,
+                  int max_iter, int poll, int refine, int32_t* iters, float* resid,
+                  uint32_t* status, hipStream_t s) {
+  int32_t* ctr = c->w_ctr;
+  int32_t* done = refine > 0 ? c->w_list[3] : nullptr;
+  MEM_HIP(c, launch_set_ctr(ctr, 8, s));
+  MEM_HIP(c, launch_init3(c, n, M, beta, c->w_list[0], &ctr[0], iters, resid, status, s));
+  {
+    ProfScope ps(c, 2, s);
+    MEM_HIP(c, launch_lse3(c, n, c->w_list[0], &ctr[0], n, M, beta, false, p, nullptr, nullptr, s));
+  }
+  int cur = 0;
+  int64_t grid = n;  // live cells never increase: the last polled count bounds the grids
+  for (int it = 0; it <= max_iter; ++it) {
+    const int nxt = 1 - cur;
+    {
+      ProfScope ps(c, 0, s);
+      MEM_HIP(c, launch_assemble3(c, grid, c->w_list[cur], &ctr[cur], n, beta, c->d_psi, c->w_S, s));
+    }
+    {
+      ProfScope ps(c, 1, s);
+      MEM_HIP(c, launch_direction3(c, grid, c->w_list[cur], &ctr[cur], M, beta, p, c->w_list[nxt],
+                                   &ctr[nxt], c->w_list[2], &ctr[2], iters, resid, status, done,
+                                   &ctr[3], s));
+    }
+    MEM_HIP(c, launch_fallback3(c, grid, c->w_list[2], &ctr[2], M, beta, p, c->w_list[nxt], &ctr[nxt],
+                                iters, resid, status, done, &ctr[3], s));
+    {
+      ProfScope ps(c, 2, s);
+      MEM_HIP(c, launch_lse3(c, grid, c->w_list[nxt], &ctr[nxt], n, M, beta, true, p, &ctr[cur],
+                             &ctr[2], s));
+    }
+    cur = nxt;
+    if (poll > 0 && (it + 1) % poll == 0) {
+      MEM_HIP(c, hipMemcpyAsync(c->h_ctr, &ctr[cur], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      MEM_HIP(c, hipStreamSynchronize(s));
+      if (*c->h_ctr == 0) break;
+      grid = *c->h_ctr;
+    }
+  }
+  if (refine > 0) {
+    // compensated residual of the converged cells; those above tol_grad get a
+    // Newton correction and are evaluated again
+    int32_t* la = c->w_list[0];
+    int32_t* lb = c->w_list[1];
+    MEM_HIP(c, launch_set_ctr(&ctr[4], 1, s));
+    MEM_HIP(c, launch_accurate3(c, n, c->w_list[3], &ctr[3], M, beta, p.tol_grad, la, &ctr[4], s));
+    int ca = 4, cb = 5;
+    for (int pass = 0; pass < refine; ++pass) {
+      MEM_HIP(c, launch_refine3(c, n, la, &ctr[ca], M, beta, s));
+      MEM_HIP(c, launch_set_ctr(&ctr[cb], 1, s));
+      MEM_HIP(c, launch_accurate3(c, n, la, &ctr[ca], M, beta, p.tol_grad, lb, &ctr[cb], s));
+      std::swap(la, lb);
+      std::swap(ca, cb);
+    }
+    MEM_HIP(c, launch_refine_final(c, n, c->w_list[3], &ctr[3], p.tol_loose, resid, status, s));
+  }
+  return MEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mem_strerror(mem_err_t e) {
+  switch (e) {
+    case MEM_OK: return "ok";
+    case MEM_ERR_INVALID_ARG: return "invalid argument";
+    case MEM_ERR_HIP: return "HIP runtime error";
+    case MEM_ERR_NOMEM: return "device allocation failed";
+    case MEM_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown error";
+}
+
+const char* mem_last_error(mem_ctx_t c) { return c ? c->err.c_str() : "null context"; }
+
+void mem_solve_opts_default(mem_solve_opts_t* o) {
+  if (!o) return;
+  o->tol_grad = 2e-6f;
+  o->tol_dec = 1e-8f;        // Alg. 1: tol
+  o->tol_grad_loose = 1e-5f;
+  o->max_iter = 400;         // Alg. 1: maxI
+  o->max_ls = 25;            // Alg. 1: maxT
+  o->armijo_c = 5e-4f;       // Alg. 1: ArmijoCondition
+  o->atol = 5e-6f;
+  o->rtol = 5e-5f;
+  o->lambda0 = 1e-3f;        // Alg. 1: lambda
+  o->lambda_mul = 10.f;
+  o->alpha_min = 1e-6f;      // Alg. 1: convergence on the step size
+  o->fp64_pivot_ratio = 1e-6f;
+  o->check_every = 2;
+  o->refine = 3;
+  o->beta_max = 100.f;
+}
+
+mem_err_t mem_create(const mem_config_t* cfg, mem_ctx_t* out) {
+  if (!cfg || !out) return MEM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (cfg->reserved != 0) return MEM_ERR_INVALID_ARG;
+  if (cfg->dim != 1 && cfg->dim != 3) return MEM_ERR_UNSUPPORTED;
+  if (cfg->n_nodes_1d < 2 || cfg->n_nodes_1d > (cfg->dim == 1 ? Q1MAX : 32)) return MEM_ERR_UNSUPPORTED;
+  if (cfg->prec < MEM_PREC_FP32 || cfg->prec > MEM_PREC_FP16X3) return MEM_ERR_UNSUPPORTED;
+  if (cfg->dim == 1 && cfg->prec != MEM_PREC_FP32) return MEM_ERR_UNSUPPORTED;
+  mem_ctx_t c = new (std::nothrow) mem_ctx_s;
+  if (!c) return MEM_ERR_NOMEM;
+  c->dim = cfg->dim;
+  c->n1d = cfg->n_nodes_1d;
+  c->prec = cfg->prec;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return MEM_ERR_HIP; }
+  try {
+    memt::build_tables(c);
+  } catch (...) {
+    mem_destroy(c);
+    return MEM_ERR_NOMEM;
+  }
+  if (hipMalloc((void**)&c->w_ctr, 8 * sizeof(int32_t)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_ctr, sizeof(int32_t)) != hipSuccess) {
+    mem_destroy(c);
+    return MEM_ERR_NOMEM;
+  }
+  *out = c;
+  return MEM_OK;
+}
+
+mem_err_t mem_destroy(mem_ctx_t c) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  (void)hipDeviceSynchronize();
+  free_workspace(c);
+  free_problems(c);
+  dfree(c->d_phiA); dfree(c->d_psi); dfree(c->d_psix); dfree(c->d_tab1);
+  dfree(c->d_accHi); dfree(c->d_accLo);
+  dfree(c->d_psi_hi); dfree(c->d_psi_lo); dfree(c->d_colscale);
+  dfree(c->w_ctr);
+  if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+  for (auto& ev : c->prof_pool) (void)hipEventDestroy(ev);
+  delete c;
+  return MEM_OK;
+}
+
+mem_err_t mem_reserve(mem_ctx_t c, int64_t max_cells, int32_t max_problems) {
+  if (!c || max_cells < 0 || max_problems < 0) return MEM_ERR_INVALID_ARG;
+  if (max_cells > (int64_t)INT32_MAX - 64) return fail(c, MEM_ERR_INVALID_ARG, "too many cells");
+  if (c->dim == 1) return MEM_OK;
+  (void)hipDeviceSynchronize();
+  if (max_cells > c->cap_cells) {
+    const size_t n = (size_t)max_cells;
+    free_workspace(c);
+    bool ok = dalloc(c->w_S, n * NCOL) && dalloc(c->w_Sx, n * NCOL) && dalloc(c->w_dbeta, n * 36) &&
+              dalloc(c->w_logZ, n) && dalloc(c->w_L, n) && dalloc(c->w_alpha, n) &&
+              dalloc(c->w_gdot, n) && dalloc(c->w_resid, n) && dalloc(c->w_iters, n) &&
+              dalloc(c->w_status, n) && dalloc(c->w_list[0], n) && dalloc(c->w_list[1], n) &&
+              dalloc(c->w_list[2], n) && dalloc(c->w_list[3], n) && dalloc(c->w_Eacc, n * 36) &&
+              dalloc(c->w_racc, n) && dalloc(c->w_rbest, n) && dalloc(c->w_itbest, n) &&
+              dalloc(c->w_Mnew, n * K3) && dalloc(c->w_F, n * K3) &&
+              dalloc(c->w_rho, n) && dalloc(c->w_prob, n);
+    if (!ok) { free_workspace(c); return fail(c, MEM_ERR_NOMEM, "workspace allocation"); }
+    c->cap_cells = max_cells;
+  }
+  if (max_problems > c->cap_problems) {
+    const size_t P = (size_t)max_problems;
+    free_problems(c);
+    bool ok = dalloc(c->w_gM, 2 * P * K3) && dalloc(c->w_gB, 2 * P * K3) && dalloc(c->w_gG, 2 * P * 3) &&
+              dalloc(c->w_gF, 2 * P * K3) && dalloc(c->w_gR, 2 * P) && dalloc(c->w_rmax, P);
+    if (!ok) { free_problems(c); return fail(c, MEM_ERR_NOMEM, "problem workspace allocation"); }
+    c->cap_problems = max_problems;
+  }
+  return MEM_OK;
+}
+
+int32_t mem_n_basis(mem_ctx_t c) { return c ? c->K : -1; }
+int32_t mem_n_nodes(mem_ctx_t c) { return c ? c->Q : -1; }
+
+mem_err_t mem_copy_table(mem_ctx_t c, int32_t which, double* host_out, int64_t n_values,
+                         int64_t* n_total) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  const std::vector<double>* v = which == 0 ? &c->h_nodes : which == 1 ? &c->h_w
+                               : which == 2 ? &c->h_phi : nullptr;
+  if (!v) return fail(c, MEM_ERR_INVALID_ARG, "table id");
+  if (n_total) *n_total = (int64_t)v->size();
+  if (host_out && n_values > 0)
+    std::memcpy(host_out, v->data(), sizeof(double) * (size_t)std::min<int64_t>(n_values, v->size()));
+  return MEM_OK;
+}
+
+mem_err_t mem_host_table(int32_t dim, int32_t n1d, int32_t which, double* host_out,
+                         int64_t n_values, int64_t* n_total) {
+  if ((dim != 1 && dim != 3) || n1d < 2 || n1d > (dim == 1 ? Q1MAX : 32) || which < 0 || which > 3)
+    return MEM_ERR_INVALID_ARG;
+  std::vector<double> nodes, w, logw, phi;
+  int K = 0, Q = 0;
+  memt::build_host(dim, n1d, nodes, w, logw, phi, K, Q);
+  const std::vector<double>& v = which == 0 ? nodes : which == 1 ? w : which == 2 ? phi : logw;
+  if (n_total) *n_total = (int64_t)v.size();
+  if (host_out && n_values > 0)
+    std::memcpy(host_out, v.data(), sizeof(double) * (size_t)std::min<int64_t>(n_values, v.size()));
+  return MEM_OK;
+}
+
+mem_err_t mem_gauge(mem_ctx_t c, int64_t n, float* M, float* beta, float* g, hipStream_t s) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!M || !g))) return fail(c, MEM_ERR_INVALID_ARG, "mem_gauge: arguments");
+  if (n == 0) return MEM_OK;
+  MEM_HIP(c, c->dim == 1 ? launch_gauge1(c, n, M, beta, g, s) : launch_gauge3(c, n, M, beta, g, s));
+  return MEM_OK;
+}
+
+mem_err_t mem_maxent_solve(mem_ctx_t c, int64_t n, const float* M, float* beta,
+                           const mem_solve_opts_t* opts, int32_t* iters, float* resid,
+                           uint32_t* status, hipStream_t s) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!M || !beta))) return fail(c, MEM_ERR_INVALID_ARG, "mem_maxent_solve: arguments");
+  if (!opts_ok(opts)) return fail(c, MEM_ERR_INVALID_ARG, "mem_maxent_solve: options");
+  if (n == 0) return MEM_OK;
+  SolveParams p = params_from(opts);
+  p.lmin = dual_floor(c);
+  if (c->dim == 1) {
+    p.refine = 0;
+    MEM_HIP(c, launch_solve1(c, n, M, beta, p, iters, resid, status, s));
+    return MEM_OK;
+  }
+  if (c->prec != MEM_PREC_FP32) return fail(c, MEM_ERR_UNSUPPORTED, "mixed precision not built");
+  mem_err_t e = ensure_cells(c, n);
+  if (e != MEM_OK) return e;
+  mem_solve_opts_t d;
+  mem_solve_opts_default(&d);
+  const int poll = opts ? opts->check_every : d.check_every;
+  const int refine = opts ? opts->refine : d.refine;
+  p.refine = refine;
+  return newton3(c, n, M, beta, p, p.max_iter, poll, refine, iters, resid, status, s);
+}
+
+mem_err_t mem_dual(mem_ctx_t c, int64_t n, const float* beta, float* logZ, float* E, float* H,
+                   hipStream_t s) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  if (c->dim != 3) return fail(c, MEM_ERR_UNSUPPORTED, "mem_dual: dim 3 only");
+  if (n < 0 || (n > 0 && !beta)) return fail(c, MEM_ERR_INVALID_ARG, "mem_dual: arguments");
+  if (n == 0) return MEM_OK;
+  mem_err_t e = ensure_cells(c, n);
+  if (e != MEM_OK) return e;
+  SolveParams p = params_from(nullptr);
+  float* b = const_cast<float*>(beta);
+  MEM_HIP(c, launch_lse3(c, n, nullptr, nullptr, n, nullptr, b, false, p, nullptr, nullptr, s));
+  MEM_HIP(c, launch_assemble3(c, n, nullptr, nullptr, n, beta, c->d_psi, c->w_S, s));
+  if (logZ) MEM_HIP(c, launch_copy(n, c->w_logZ, logZ, s));
+  if (E || H) MEM_HIP(c, launch_unpack3(c, n, E, H, s));
+  return MEM_OK;
+}
+
+mem_err_t mem_flux(mem_ctx_t c, int64_t n, const float* beta, const float* g, float* F, float* lam,
+                   hipStream_t s) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  if (c->dim != 3) return fail(c, MEM_ERR_UNSUPPORTED, "mem_flux: dim 3 only");
+  if (n < 0 || (n > 0 && (!beta || !g || (!F && !lam))))
+    return fail(c, MEM_ERR_INVALID_ARG, "mem_flux: arguments");
+  if (n == 0) return MEM_OK;
+  mem_err_t e = ensure_cells(c, n);
+  if (e != MEM_OK) return e;
+  MEM_HIP(c, launch_flux3(c, n, beta, g, F, lam, lam != nullptr, false, nullptr, s));
+  return MEM_OK;
+}
+
+mem_err_t mem_collide(mem_ctx_t c, int64_t n, float* M, const float* g, float h, float prandtl,
+                      float mu_ref, hipStream_t s) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  if (c->dim != 3) return fail(c, MEM_ERR_UNSUPPORTED, "mem_collide: dim 3 only");
+  if (n < 0 || (n > 0 && (!M || !g)) || !(prandtl > 0.5f) || !(mu_ref > 0.f) || !(h >= 0.f))
+    return fail(c, MEM_ERR_INVALID_ARG, "mem_collide: arguments");
+  if (n == 0) return MEM_OK;
+  MEM_HIP(c, launch_collide3(c, n, M, g, h, nullptr, nullptr, prandtl, mu_ref, s));
+  return MEM_OK;
+}
+
+// Validates the host fields and the device cell offsets (copied to the host:
+// every kernel indexes neighbours and problems through them).
+static mem_err_t check_batch(mem_ctx_t c, const mem_batch_t* b) {
+  if (!b || b->n_problems <= 0 || b->n_cells < b->n_problems || !b->cell_offsets || !b->dx ||
+      !b->M_left || !b->M_right || !b->g_left || !b->g_right || !(b->cfl > 0.f) ||
+      !(b->prandtl > 0.5f) || !(b->mu_ref > 0.f) || b->newton_per_step < 1 ||
+      b->newton_per_step > 1000 || (b->collision != 0 && b->collision != 1))
+    return fail(c, MEM_ERR_INVALID_ARG, "mem_batch_t");
+  std::vector<int64_t> off((size_t)b->n_problems + 1);
+  MEM_HIP(c, hipMemcpy(off.data(), b->cell_offsets, off.size() * sizeof(int64_t),
+                       hipMemcpyDeviceToHost));
+  if (off[0] != 0 || off.back() != b->n_cells)
+    return fail(c, MEM_ERR_INVALID_ARG, "cell_offsets must start at 0 and end at n_cells");
+  for (size_t p = 0; p + 1 < off.size(); ++p)
+    if (off[p + 1] <= off[p]) return fail(c, MEM_ERR_INVALID_ARG, "every problem needs >= 1 cell");
+  return MEM_OK;
+}
+
+mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, float* g, float* t,
+                   float* dt, int32_t n_steps, const mem_solve_opts_t* opts, uint32_t* status,
+                   hipStream_t s) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  if (c->dim != 3) return fail(c, MEM_ERR_UNSUPPORTED, "mem_step: dim 3 only");
+  mem_err_t e = check_batch(c, b);
+  if (e != MEM_OK) return e;
+  if (!M || !beta || !g || !t || !dt || n_steps < 0 || !opts_ok(opts))
+    return fail(c, MEM_ERR_INVALID_ARG, "mem_step: arguments");
+  const int64_t n = b->n_cells;
+  const int P = b->n_problems;
+  if (std::max<int64_t>(n, 2 * (int64_t)P) > c->cap_cells || P > c->cap_problems) {
+    e = mem_reserve(c, std::max<int64_t>(std::max<int64_t>(n, 2 * (int64_t)P), c->cap_cells),
+                    std::max(P, c->cap_problems));
+    if (e != MEM_OK) return e;
+  }
+  SolveParams p = params_from(opts);
+  p.lmin = dual_floor(c);
+  const int budget = b->newton_per_step;
+  p.max_iter = budget;
+  const float Pr = b->collision == 1 ? b->prandtl : 1.f;
+  // batch set-up: cell -> problem map, ghost states (solved once), running max
+  MEM_HIP(c, launch_prob_map(c, b->cell_offsets, P, c->w_prob, s));
+  MEM_HIP(c, launch_ghost_pack(c, b, s));
+  mem_solve_opts_t dflt;
+  mem_solve_opts_default(&dflt);
+  const int refine = opts ? opts->refine : dflt.refine;
+  p.refine = refine;
+  e = newton3(c, 2 * (int64_t)P, c->w_gM, c->w_gB, p, budget, 0, refine, nullptr, nullptr, nullptr, s);
+  if (e != MEM_OK) return e;
+  MEM_HIP(c, launch_flux3(c, 2 * (int64_t)P, c->w_gB, c->w_gG, c->w_gF, c->w_gR, true, true, nullptr, s));
+  MEM_HIP(c, launch_rmax_init(c, P, s));
+  // solve the current state; set dt where the caller asked for one
+  e = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, s);
+  if (e != MEM_OK) return e;
+  MEM_HIP(c, launch_flux3(c, n, beta, g, nullptr, c->w_rho, true, true, status, s));
+  MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, s));
+  MEM_HIP(c, launch_dt_update(c, P, b->dx, b->cfl, t, dt, false, s));
+  for (int step = 0; step < n_steps; ++step) {
+    MEM_HIP(c, launch_collide3(c, n, M, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, s));
+    e = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, s);
+    if (e != MEM_OK) return e;
+    if (status) MEM_HIP(c, launch_status_or(n, c->w_status, status, s));
+    MEM_HIP(c, launch_flux3(c, n, beta, g, c->w_F, c->w_rho, true, true, status, s));
+    MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, s));
+    MEM_HIP(c, launch_fv3(c, n, M, c->w_F, c->w_rho, g, c->w_prob, b->cell_offsets, b->dx, dt,
+                          c->w_Mnew, P, s));
+    MEM_HIP(c, launch_collide3(c, n, c->w_Mnew, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, s));
+    MEM_HIP(c, launch_gauge3(c, n, c->w_Mnew, beta, g, s));
+    MEM_HIP(c, launch_copy(n * K3, c->w_Mnew, M, s));
+    MEM_HIP(c, launch_dt_update(c, P, b->dx, b->cfl, t, dt, true, s));
+  }
+  return MEM_OK;
+}
+
+mem_err_t mem_conserved(mem_ctx_t c, const mem_batch_t* b, const float* M, const float* g,
+                        double* out, hipStream_t s) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  if (c->dim != 3) return fail(c, MEM_ERR_UNSUPPORTED, "mem_conserved: dim 3 only");
+  mem_err_t e = check_batch(c, b);
+  if (e != MEM_OK) return e;
+  if (!M || !g || !out) return fail(c, MEM_ERR_INVALID_ARG, "mem_conserved: arguments");
+  MEM_HIP(c, launch_conserved(c, b, M, g, out, s));
+  return MEM_OK;
+}
+
+mem_err_t mem_profile_enable(mem_ctx_t c, int32_t enable) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  c->prof = enable != 0;
+  if (c->prof) {
+    if (c->prof_pool.empty()) {
+      c->prof_pool.resize(8192);
+      for (auto& ev : c->prof_pool)
+        if (hipEventCreate(&ev) != hipSuccess) return fail(c, MEM_ERR_HIP, "hipEventCreate");
+    }
+    MEM_HIP(c, hipDeviceSynchronize());
+    c->prof_used = 0;
+    c->prof_marks.clear();
+  }
+  return MEM_OK;
+}
+
+mem_err_t mem_profile_read(mem_ctx_t c, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  double ms = 0.0;
+  int64_t cnt = 0;
+  for (auto& m : c->prof_marks) {
+    if (m.first != kernel) continue;
+    MEM_HIP(c, hipEventSynchronize(m.second.second));
+    float x = 0.f;
+    MEM_HIP(c, hipEventElapsedTime(&x, m.second.first, m.second.second));
+    ms += x;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = cnt;
+  return MEM_OK;
+}
+
+}  // extern "C"

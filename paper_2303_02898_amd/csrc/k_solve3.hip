@@ -1,0 +1,830 @@
+// 3D (35-moment) maximal-entropy dual solve on gfx950.
+//
+// One Newton iteration of Alg. 1 is four launches over a work-list of live
+// cells (cells that have not met a stopping test):
+//   k_assemble3  : sigma_p = exp(beta.phi_p + log w~_p - log Z) for 16-node
+//                  groups, the exponent itself an MFMA product of the node
+//                  table with beta, then S = sigma . Psi on FP32 MFMA, where
+//                  Psi[p][(i,j)] = phi_i phi_j(u_p) (630 pair columns + 10 pad).
+//                  Row (0, j) of S gives E[phi_j]; the rest gives E[phi_i phi_j].
+//   k_direction3 : Hessian H_ij = E[phi_i phi_j] - E_i E_j (App. C) and gradient
+//                  G_i = E_i - M_i/n, Cholesky with the lambda*I shift, Newton
+//                  direction, decrement, stopping tests; cells whose FP32 pivot
+//                  ratio is below the threshold go to the FP64 kernel.
+//   k_fallback3  : the same direction in FP64 (rare path).
+//   k_lse3       : backtracking line search with the Armijo test of Alg. 1; each
+//                  trial is one log-sum-exp pass (Sec. 3.1) over the nodes.
+// beta_0 is held at n, which zeroes G_0 and decouples H_00 = n^2/beta_0^2, so
+// the Newton system is the 34 x 34 covariance block.
+#include <cfloat>
+#include <cmath>
+
+#include "mem_internal.h"
+
+namespace memk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Wave-aggregated append of `cell` to a work list.  Every lane of the wave
+// must call it (it uses a ballot).
+__device__ __forceinline__ void wave_append(bool pred, int cell, int32_t* list, int32_t* ctr) {
+  unsigned long long mask = __ballot(pred);
+  if (mask == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(ctr, __popcll(mask));
+  base = __shfl(base, leader);
+  if (pred) {
+    unsigned long long below = lane ? (mask & ((1ull << lane) - 1ull)) : 0ull;
+    list[base + __popcll(below)] = cell;
+  }
+}
+
+// Row-major packed upper triangle of the 34 x 34 block: (i <= j).
+__device__ __forceinline__ int hidx(int i, int j) { return 34 * i - (i * (i + 1)) / 2 + j; }
+
+// --------------------------------------------------------------------------
+// init: validate, beta_0 = n, seed the live list
+// --------------------------------------------------------------------------
+__global__ void k_init3(int64_t n, const float* __restrict__ M, float* __restrict__ beta,
+                        float* alpha, int32_t* iters_w, uint32_t* status_w, float* resid_w,
+                        float* rbest_w, int32_t* itbest_w,
+                        int32_t* list, int32_t* ctr, int32_t* iters_out, float* resid_out,
+                        uint32_t* status_out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool ok = false;
+  if (c < n) {
+    const float* m = M + c * K3;
+    float* b = beta + c * K3;
+    bool fin = true;
+    for (int k = 0; k < K3; ++k) fin = fin && isfinite(m[k]) && (k == 0 || isfinite(b[k]));
+    uint32_t st = 0;
+    if (!fin) st = MEM_ST_NONFINITE;
+    else if (!(m[0] > 0.f)) st = MEM_ST_NONREALIZABLE;
+    ok = st == 0;
+    if (ok) b[0] = m[0];
+    alpha[c] = 1.f;
+    iters_w[c] = 0;
+    status_w[c] = st;
+    resid_w[c] = INFINITY;
+    rbest_w[c] = INFINITY;
+    itbest_w[c] = 0;
+    if (!ok) {
+      if (iters_out) iters_out[c] = 0;
+      if (resid_out) resid_out[c] = INFINITY;
+      if (status_out) status_out[c] = st;
+    }
+  }
+  wave_append(ok, (int)c, list, ctr);
+}
+
+__global__ void k_set_ctr(int32_t* ctr, int n) {
+  if (threadIdx.x < (unsigned)n) ctr[threadIdx.x] = 0;
+}
+
+// --------------------------------------------------------------------------
+// log-sum-exp pass and the Armijo backtracking line search of Alg. 1
+// --------------------------------------------------------------------------
+constexpr int LSE_CH = 8;  // node groups staged in LDS per barrier
+
+template <bool LS>
+__global__ __launch_bounds__(256) void k_lse3(
+    const float* __restrict__ phiA, int ngroups, const int32_t* __restrict__ list,
+    const int32_t* __restrict__ ctr, int64_t n, const float* __restrict__ M,
+    float* __restrict__ beta, const float* __restrict__ dbeta, float* __restrict__ logZ,
+    float* __restrict__ Lval, float* __restrict__ alpha_w, const float* __restrict__ gdot,
+    SolveParams p, int32_t* reset_a, int32_t* reset_b) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (reset_a) *reset_a = 0;
+    if (reset_b) *reset_b = 0;
+  }
+  const int64_t count = ctr ? (int64_t)(*ctr) : n;
+  const int64_t tile = (int64_t)blockIdx.x * TILE;
+  if (tile >= count) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int kq = lane >> 4;
+  const int64_t slot = tile + wave * 16 + (lane & 15);
+  const bool valid = slot < count;
+  const int64_t cell = valid ? (list ? (int64_t)list[slot] : slot) : 0;
+
+  // lane holds coefficients k = 4j + kq of its cell (k = 0 multiplies log w~)
+  float b[NJ], d[NJ], m[NJ];
+  // M may be null (log Z only): the linear term of L is then dropped
+  const float nn = (valid && M) ? M[cell * K3] : 1.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int k = 4 * j + kq;
+    const bool in = valid && k >= 1 && k < K3;
+    b[j] = k == 0 ? 1.f : (in ? beta[cell * K3 + k] : 0.f);
+    d[j] = (LS && in) ? dbeta[cell * 36 + k] : 0.f;
+    m[j] = (in && M) ? M[cell * K3 + k] / nn : 0.f;
+  }
+  float L0 = 0.f, gd = 0.f;
+  if (LS && valid) { L0 = Lval[cell]; gd = gdot[cell]; }
+  float alpha = 1.f;
+  bool active = valid;
+
+  __shared__ float sA[LSE_CH * NJ * 64];
+  for (int s = 0;; ++s) {
+    float bt[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) bt[j] = (4 * j + kq == 0) ? 1.f : b[j] + alpha * d[j];
+    float mx = -FLT_MAX, sm = 0.f;
+    for (int g0 = 0; g0 < ngroups; g0 += LSE_CH) {
+      const int nch = min(LSE_CH, ngroups - g0);
+      __syncthreads();
+      const f4* src = reinterpret_cast<const f4*>(phiA + (size_t)g0 * NJ * 64);
+      for (int i = threadIdx.x; i < nch * NJ * 16; i += 256) reinterpret_cast<f4*>(sA)[i] = src[i];
+      __syncthreads();
+      for (int g = 0; g < nch; ++g) {
+        f4 e = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) e = mfma4(sA[(g * NJ + j) * 64 + lane], bt[j], e);
+        const float gm = fmaxf(fmaxf(e[0], e[1]), fmaxf(e[2], e[3]));
+        if (gm > mx) { sm *= __expf(mx - gm); mx = gm; }
+        sm += __expf(e[0] - mx) + __expf(e[1] - mx) + __expf(e[2] - mx) + __expf(e[3] - mx);
+      }
+    }
+    // combine the four lanes that hold the same cell (lanes l, l^16, l^32, l^48)
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
+      const float om = __shfl_xor(mx, off), os = __shfl_xor(sm, off);
+      const float nm = fmaxf(mx, om);
+      sm = sm * __expf(mx - nm) + os * __expf(om - nm);
+      mx = nm;
+    }
+    const float lz = mx + __logf(sm);
+    float dot = 0.f;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) dot += bt[j] * m[j];
+    dot += __shfl_xor(dot, 16);
+    dot += __shfl_xor(dot, 32);
+    const float Lt = lz - dot;  // dual objective up to the constant beta_0 term
+
+    if (!LS) {
+      if (valid && kq == 0) { logZ[cell] = lz; Lval[cell] = Lt; }
+      break;
+    }
+    // Armijo test with the floating-point tolerance (Alg. 1, ArmijoCondition)
+    const float LD = L0 - Lt;
+    const float gradD = -p.c * alpha * gd;
+    const bool sat = (LD - gradD) >= -(p.atol + p.rtol * fabsf(LD));
+    const bool finish = active && (sat || s >= p.max_ls);  // last trial is kept (Alg. 1)
+    if (finish) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int k = 4 * j + kq;
+        if (k >= 1 && k < K3) beta[cell * K3 + k] = bt[j];
+      }
+      if (kq == 0) { logZ[cell] = lz; Lval[cell] = Lt; alpha_w[cell] = alpha; }
+      active = false;
+    } else if (active) {
+      alpha *= 0.5f;
+    }
+    if (!__syncthreads_or(active ? 1 : 0)) break;
+  }
+}
+
+// --------------------------------------------------------------------------
+// assembly: S[cell][col] = sum_p sigma_p Psi[p][col] on FP32 MFMA
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256, 2) void k_assemble3(
+    const float* __restrict__ phiA, const float* __restrict__ psi, int ngroups,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ ctr, int64_t n,
+    const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ S) {
+  const int64_t count = ctr ? (int64_t)(*ctr) : n;
+  const int64_t tile = (int64_t)blockIdx.x * TILE;
+  if (tile >= count) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int kq = lane >> 4;
+  const int64_t slot = tile + wave * 16 + (lane & 15);
+  const bool valid = slot < count;
+  const int64_t cell = valid ? (list ? (int64_t)list[slot] : slot) : 0;
+
+  float bt[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int k = 4 * j + kq;
+    bt[j] = k == 0 ? 1.f : ((valid && k < K3) ? beta[cell * K3 + k] : 0.f);
+  }
+  const float lz = valid ? logZ[cell] : 0.f;
+
+  f4 acc[NBLK];
+#pragma unroll
+  for (int b = 0; b < NBLK; ++b) acc[b] = (f4){0.f, 0.f, 0.f, 0.f};
+
+  __shared__ f4 sB[4 * 10 * 64];   // 40 KB: Psi operand of one node group
+  __shared__ float sA[NJ * 64];    // exponent operand of one node group
+  for (int g = 0; g < ngroups; ++g) {
+    __syncthreads();
+    {
+      const f4* src = reinterpret_cast<const f4*>(psi) + (size_t)g * (4 * 10 * 64);
+#pragma unroll
+      for (int i = 0; i < 10; ++i) sB[threadIdx.x + 256 * i] = src[threadIdx.x + 256 * i];
+      const f4* srcA = reinterpret_cast<const f4*>(phiA + (size_t)g * NJ * 64);
+      if (threadIdx.x < NJ * 16) reinterpret_cast<f4*>(sA)[threadIdx.x] = srcA[threadIdx.x];
+    }
+    __syncthreads();
+    f4 e = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) e = mfma4(sA[j * 64 + lane], bt[j], e);
+    float sg[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sg[r] = valid ? __expf(e[r] - lz) : 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int b4 = 0; b4 < 10; ++b4) {
+        const f4 bv = sB[(r * 10 + b4) * 64 + lane];
+        acc[4 * b4 + 0] = mfma4(sg[r], bv[0], acc[4 * b4 + 0]);
+        acc[4 * b4 + 1] = mfma4(sg[r], bv[1], acc[4 * b4 + 1]);
+        acc[4 * b4 + 2] = mfma4(sg[r], bv[2], acc[4 * b4 + 2]);
+        acc[4 * b4 + 3] = mfma4(sg[r], bv[3], acc[4 * b4 + 3]);
+      }
+    }
+  }
+  // D layout: lane l, register q -> row 4(l/16) + q of the wave's 16 cells, column l%16
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t sl = tile + wave * 16 + 4 * kq + q;
+    if (sl < count) {
+      const int64_t cw = list ? (int64_t)list[sl] : sl;
+      float* dst = S + cw * NCOL + (lane & 15);
+#pragma unroll
+      for (int b = 0; b < NBLK; ++b) dst[16 * b] = acc[b][q];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Newton direction (FP32) with the lambda*I shift of Alg. 1
+// --------------------------------------------------------------------------
+// One thread per cell; the 34 x 34 packed matrix of each cell lives in LDS,
+// element e of cell c at e*64 + (c ^ (e & 31)) (conflict-free both for the
+// cooperative transposed load and for per-thread access).  A 34-vector per
+// cell holds E[phi] and is overwritten by the forward-substitution result.
+__device__ __forceinline__ int sw(int e, int c) { return e * 64 + (c ^ (e & 31)); }
+
+struct DirOut {
+  int32_t* next_list; int32_t* next_ctr;
+  int32_t* iters_out; float* resid_out; uint32_t* status_out;
+  int32_t* done_list; int32_t* done_ctr;  // converged cells (for refinement), may be null
+};
+
+// Stopping tests of Alg. 1 (residual sign read as 1/2 G^T (H + lambda I)^-1 G)
+// and book-keeping shared by the FP32 and FP64 direction kernels.  Returns
+// true when the cell stays live; then the caller stores the direction.
+// Stopping tests of Alg. 1 (residual sign read as 1/2 G^T (H + lambda I)^-1 G),
+// plus two exits for FP32 arithmetic:
+//  * a dual value below min_p log w~_p certifies that no minimiser exists (the
+//    targets lie outside the moment set of distributions on the nodes);
+//  * stall: the FP32 residual has not halved for STALL_WINDOW iterations (its
+//    rounding floor); with refinement on, such a cell -- like a converged one
+//    -- is handed to the compensated refinement, which decides the status.
+// Returns 1 when the cell stays live, 2 when it goes to refinement, 0 otherwise.
+constexpr int STALL_WINDOW = 6;
+constexpr float STALL_GATE = 1e-3f;
+
+__device__ __forceinline__ int finish_cell(bool valid, int64_t cell, float r, float res,
+                                           bool dir_ok, uint32_t extra, const SolveParams& p,
+                                           float* gdot, float* alpha_w, int32_t* iters_w,
+                                           uint32_t* status_w, float* resid_w,
+                                           const float* Lval, float* rbest_w, int32_t* itbest_w,
+                                           const float* beta, const DirOut& o) {
+  if (!valid) return 0;
+  float bmax = 0.f;
+  for (int k = 1; k < K3; ++k) bmax = fmaxf(bmax, fabsf(beta[cell * K3 + k]));
+  const int it = iters_w[cell] + 1;
+  iters_w[cell] = it;
+  uint32_t st = status_w[cell] | extra;
+  resid_w[cell] = r;
+  if (r < 0.5f * rbest_w[cell]) { rbest_w[cell] = r; itbest_w[cell] = it; }
+  const bool conv = (r <= p.tol_grad) || (res <= p.tol_dec && r <= p.tol_loose);
+  const bool near = r <= STALL_GATE && p.refine > 0;
+  const bool stall = near && (it - itbest_w[cell] >= STALL_WINDOW || alpha_w[cell] <= p.alpha_min ||
+                              it >= p.max_iter);
+  bool done = true, cand = false;
+  if (conv || stall) { st |= MEM_ST_CONVERGED; cand = p.refine > 0; }
+  else if (Lval[cell] < p.lmin || (p.beta_max > 0.f && bmax > p.beta_max))
+    st |= MEM_ST_NONREALIZABLE;
+  else if (!isfinite(r) || !dir_ok) st |= MEM_ST_NONFINITE;
+  else if (alpha_w[cell] <= p.alpha_min) st |= MEM_ST_STAGNATED;
+  else if (it >= p.max_iter) st |= MEM_ST_MAXITER;
+  else done = false;
+  status_w[cell] = st;
+  if (done) {
+    if (o.iters_out) o.iters_out[cell] = it;
+    if (o.resid_out) o.resid_out[cell] = r;
+    if (o.status_out) o.status_out[cell] = st;
+    return cand ? 2 : 0;
+  }
+  gdot[cell] = -2.f * res;  // G . dbeta = -G^T (H + lambda I)^-1 G
+  return 1;
+}
+
+__device__ bool chol_upper_lds(float* sh, int t, float& dmin, float& dmax) {
+  dmin = FLT_MAX; dmax = 0.f;
+  for (int k = 0; k < NH; ++k) {
+    const float dk = sh[sw(hidx(k, k), t)];
+    if (!(dk > 0.f) || !isfinite(dk)) return false;
+    dmin = fminf(dmin, dk); dmax = fmaxf(dmax, dk);
+    const float ukk = sqrtf(dk), inv = 1.f / ukk;
+    sh[sw(hidx(k, k), t)] = ukk;
+    for (int j = k + 1; j < NH; ++j) sh[sw(hidx(k, j), t)] *= inv;
+    for (int i = k + 1; i < NH; ++i) {
+      const float uki = sh[sw(hidx(k, i), t)];
+      for (int j = i; j < NH; ++j) sh[sw(hidx(i, j), t)] -= uki * sh[sw(hidx(k, j), t)];
+    }
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(64) void k_direction3(
+    const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
+    const float* __restrict__ S, const float* __restrict__ M, float* __restrict__ dbeta,
+    float* __restrict__ gdot, float* __restrict__ alpha_w, int32_t* __restrict__ iters_w,
+    uint32_t* __restrict__ status_w, float* __restrict__ resid_w,
+    const float* __restrict__ Lval, float* __restrict__ rbest_w, int32_t* __restrict__ itbest_w,
+    const float* __restrict__ beta, SolveParams p, int32_t* fb_list, int32_t* fb_ctr, DirOut o) {
+  const int64_t count = *ctr;
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  if (base >= count) return;
+  const int t = threadIdx.x;
+  const int64_t slot = base + t;
+  const bool valid = slot < count;
+  const int64_t cell = valid ? (int64_t)list[slot] : 0;
+
+  __shared__ float sh[HPACK * 64];
+  __shared__ float sv[NH * 64];
+  // coalesced transposed load of the pair columns (i, j >= 1) of the tile's cells
+  for (int c = 0; c < 64; ++c) {
+    if (base + c >= count) break;
+    const float* src = S + (int64_t)list[base + c] * NCOL + K3;
+    for (int e = t; e < HPACK; e += 64) sh[sw(e, c)] = src[e];
+  }
+  __syncthreads();
+
+  const float* Sc = S + cell * NCOL;
+  const float s00 = valid ? Sc[0] : 1.f;
+  const float inv0 = 1.f / s00;
+  for (int a = 0; a < NH; ++a) sv[sw(a, t)] = valid ? Sc[a + 1] * inv0 : 0.f;
+  // H = S/s00 - E E^T, and r = max |G|
+  for (int i = 0; i < NH; ++i) {
+    const float ei = sv[sw(i, t)];
+    for (int j = i; j < NH; ++j) {
+      float* h = &sh[sw(hidx(i, j), t)];
+      *h = valid ? (*h * inv0 - ei * sv[sw(j, t)]) : (i == j ? 1.f : 0.f);
+    }
+  }
+  const float* Mc = M + cell * K3;
+  const float nn = valid ? Mc[0] : 1.f;
+  float r = 0.f;
+  for (int a = 0; a < NH; ++a)
+    r = fmaxf(r, fabsf(valid ? sv[sw(a, t)] - Mc[a + 1] / nn : 0.f));
+  if (!isfinite(s00) || !(s00 > 0.f)) r = NAN;
+
+  float dmin, dmax;
+  bool ok = chol_upper_lds(sh, t, dmin, dmax);
+  bool to_fp64 = false;
+  uint32_t extra = 0;
+  if (p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
+    to_fp64 = valid && isfinite(r);
+  } else if (!ok && valid && isfinite(r)) {
+    // Alg. 1: Cholesky of H + lambda I, lambda = lambda0 * mul^m
+    float lam = p.lambda0;
+    extra |= MEM_ST_SHIFTED;
+    for (int tries = 0; tries < 40 && !ok; ++tries, lam *= p.lambda_mul) {
+      for (int i = 0; i < NH; ++i)
+        for (int j = i; j < NH; ++j) {
+          const float v = Sc[pair_col(i + 1, j + 1)] * inv0 - sv[sw(i, t)] * sv[sw(j, t)];
+          sh[sw(hidx(i, j), t)] = v + (i == j ? lam : 0.f);
+        }
+      ok = chol_upper_lds(sh, t, dmin, dmax);
+    }
+  }
+  float res = 0.f;
+  bool fin = ok;
+  const bool solve = valid && ok && !to_fp64;
+  if (solve) {
+    // forward U^T w = -G (w overwrites E in sv), backward U d = w in place
+    for (int i = 0; i < NH; ++i) {
+      float acc = -(sv[sw(i, t)] - Mc[i + 1] / nn);
+      for (int k = 0; k < i; ++k) acc -= sh[sw(hidx(k, i), t)] * sv[sw(k, t)];
+      const float wi = acc / sh[sw(hidx(i, i), t)];
+      sv[sw(i, t)] = wi;
+      res += wi * wi;
+    }
+    res *= 0.5f;
+    for (int i = NH - 1; i >= 0; --i) {
+      float acc = sv[sw(i, t)];
+      for (int j = i + 1; j < NH; ++j) acc -= sh[sw(hidx(i, j), t)] * sv[sw(j, t)];
+      const float di = acc / sh[sw(hidx(i, i), t)];
+      sv[sw(i, t)] = di;
+      fin = fin && isfinite(di);
+    }
+  }
+  wave_append(to_fp64, (int)cell, fb_list, fb_ctr);
+  const int code = to_fp64 ? 0 : finish_cell(valid, cell, r, res, fin, extra, p, gdot, alpha_w,
+                                              iters_w, status_w, resid_w, Lval, rbest_w, itbest_w,
+                                              beta, o);
+  const bool live = code == 1;
+  if (o.done_list) wave_append(code == 2, (int)cell, o.done_list, o.done_ctr);
+  if (live) {
+    float* db = dbeta + cell * 36;
+    db[0] = 0.f;
+    for (int a = 0; a < NH; ++a) db[1 + a] = sv[sw(a, t)];
+  }
+  wave_append(live, (int)cell, o.next_list, o.next_ctr);
+}
+
+// --------------------------------------------------------------------------
+// Newton direction in FP64 for cells with a small FP32 pivot ratio
+// --------------------------------------------------------------------------
+// 32 cells per workgroup (threads 32..63 idle); element e of cell c at
+// e*32 + (c ^ (e & 15)) in doubles.
+__device__ __forceinline__ int swd(int e, int c) { return e * 32 + (c ^ (e & 15)); }
+
+__device__ bool chol_upper_lds_d(double* sh, int t) {
+  for (int k = 0; k < NH; ++k) {
+    const double dk = sh[swd(hidx(k, k), t)];
+    if (!(dk > 0.0) || !isfinite(dk)) return false;
+    const double ukk = sqrt(dk), inv = 1.0 / ukk;
+    sh[swd(hidx(k, k), t)] = ukk;
+    for (int j = k + 1; j < NH; ++j) sh[swd(hidx(k, j), t)] *= inv;
+    for (int i = k + 1; i < NH; ++i) {
+      const double uki = sh[swd(hidx(k, i), t)];
+      for (int j = i; j < NH; ++j) sh[swd(hidx(i, j), t)] -= uki * sh[swd(hidx(k, j), t)];
+    }
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(64) void k_fallback3(
+    const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
+    const float* __restrict__ S, const float* __restrict__ M, float* __restrict__ dbeta,
+    float* __restrict__ gdot, float* __restrict__ alpha_w, int32_t* __restrict__ iters_w,
+    uint32_t* __restrict__ status_w, float* __restrict__ resid_w,
+    const float* __restrict__ Lval, float* __restrict__ rbest_w, int32_t* __restrict__ itbest_w,
+    const float* __restrict__ beta, SolveParams p, DirOut o) {
+  const int64_t count = *ctr;
+  const int64_t base = (int64_t)blockIdx.x * 32;
+  if (base >= count) return;
+  const int t = threadIdx.x;
+  const int64_t slot = base + t;
+  const bool valid = t < 32 && slot < count;
+  const int64_t cell = valid ? (int64_t)list[slot] : 0;
+  const int tt = t & 31;
+  __shared__ double sh[HPACK * 32];
+  __shared__ double sv[NH * 32];
+
+  const float* Sc = S + cell * NCOL;
+  const float* Mc = M + cell * K3;
+  const double inv0 = valid ? 1.0 / (double)Sc[0] : 1.0;
+  const double nn = valid ? (double)Mc[0] : 1.0;
+  bool ok = false, fin = false;
+  float r = 0.f, res = 0.f;
+  uint32_t extra = MEM_ST_FP64;
+  if (t < 32) {
+    for (int a = 0; a < NH; ++a) sv[swd(a, tt)] = valid ? (double)Sc[a + 1] * inv0 : 0.0;
+    for (int a = 0; a < NH; ++a)
+      r = fmaxf(r, fabsf(valid ? (float)(sv[swd(a, tt)] - (double)Mc[a + 1] / nn) : 0.f));
+    double lam = 0.0;
+    for (int tries = 0; tries < 41; ++tries) {
+      for (int i = 0; i < NH; ++i)
+        for (int j = i; j < NH; ++j) {
+          const double v = valid ? ((double)Sc[pair_col(i + 1, j + 1)] * inv0 - sv[swd(i, tt)] * sv[swd(j, tt)])
+                                 : (i == j ? 1.0 : 0.0);
+          sh[swd(hidx(i, j), tt)] = v + (i == j ? lam : 0.0);
+        }
+      ok = chol_upper_lds_d(sh, tt);
+      if (ok) break;
+      lam = (tries == 0) ? (double)p.lambda0 : lam * (double)p.lambda_mul;
+      extra |= MEM_ST_SHIFTED;
+    }
+    fin = ok;
+    if (ok && valid) {
+      double rs = 0.0;
+      for (int i = 0; i < NH; ++i) {
+        double acc = -(sv[swd(i, tt)] - (double)Mc[i + 1] / nn);
+        for (int k = 0; k < i; ++k) acc -= sh[swd(hidx(k, i), tt)] * sv[swd(k, tt)];
+        const double wi = acc / sh[swd(hidx(i, i), tt)];
+        sv[swd(i, tt)] = wi;
+        rs += wi * wi;
+      }
+      res = (float)(0.5 * rs);
+      for (int i = NH - 1; i >= 0; --i) {
+        double acc = sv[swd(i, tt)];
+        for (int j = i + 1; j < NH; ++j) acc -= sh[swd(hidx(i, j), tt)] * sv[swd(j, tt)];
+        const double di = acc / sh[swd(hidx(i, i), tt)];
+        sv[swd(i, tt)] = di;
+        fin = fin && isfinite(di);
+      }
+    }
+  }
+  const int code = finish_cell(valid, cell, r, res, fin, extra, p, gdot, alpha_w, iters_w,
+                               status_w, resid_w, Lval, rbest_w, itbest_w, beta, o);
+  const bool live = code == 1;
+  if (o.done_list) wave_append(code == 2, (int)cell, o.done_list, o.done_ctr);
+  if (live) {
+    float* db = dbeta + cell * 36;
+    db[0] = 0.f;
+    for (int a = 0; a < NH; ++a) db[1 + a] = (float)sv[swd(a, tt)];
+  }
+  wave_append(live, (int)cell, o.next_list, o.next_ctr);
+}
+
+// --------------------------------------------------------------------------
+// Residual refinement in compensated FP32 arithmetic
+// --------------------------------------------------------------------------
+// FP32 rounding of the exponent e_p = log w~_p + sum_k beta_k phi_k(p) (terms of
+// magnitude up to ~10 that cancel) limits the moment residual the FP32 Newton
+// iteration can certify to ~1e-5.  For converged cells the residual is
+// re-evaluated with the exponent as an error-free double-float dot product
+// (TwoProduct by FMA, TwoSum, tables split into hi + lo parts), then one Newton
+// correction uses the FP32 Hessian already assembled for the cell: classical
+// iterative refinement, all in FP32 operations.
+constexpr int ACC_CH = 64;  // nodes per LDS chunk
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float z = s - a;
+  e = (a - (s - z)) + (b - z);
+}
+
+__global__ __launch_bounds__(64) void k_accurate3(
+    const float* __restrict__ tabHi, const float* __restrict__ tabLo, int Q,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
+    const float* __restrict__ M, const float* __restrict__ beta, const float* __restrict__ logZ,
+    float* __restrict__ Eacc, float* __restrict__ racc, float tol, int32_t* out_list,
+    int32_t* out_ctr) {
+  const int64_t count = *ctr;
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  if (base >= count) return;
+  const int t = threadIdx.x;
+  const int64_t slot = base + t;
+  const bool valid = slot < count;
+  const int64_t cell = valid ? (int64_t)list[slot] : 0;
+  float b[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) b[k] = k == 0 ? 1.f : ((valid && k < K3) ? beta[cell * K3 + k] : 0.f);
+  const float lz = valid ? logZ[cell] : 0.f;
+  // moment sums with exact-product Kahan compensation
+  float S[K3], Cc[K3];
+#pragma unroll
+  for (int i = 0; i < K3; ++i) { S[i] = 0.f; Cc[i] = 0.f; }
+  __shared__ float sH[ACC_CH * 36], sL[ACC_CH * 36];
+  for (int p0 = 0; p0 < Q; p0 += ACC_CH) {
+    const int np = min(ACC_CH, Q - p0);
+    __syncthreads();
+    for (int i = t; i < np * 36; i += 64) {
+      sH[i] = tabHi[(size_t)p0 * 36 + i];
+      sL[i] = tabLo[(size_t)p0 * 36 + i];
+    }
+    __syncthreads();
+    for (int q = 0; q < np; ++q) {
+      const float* h = sH + q * 36;
+      const float* l = sL + q * 36;
+      // e - log Z as an unevaluated sum s + c (error-free products and sums)
+      float s = -lz, c = 0.f;
+#pragma unroll
+      for (int k = 0; k < 36; ++k) {
+        const float pr = b[k] * h[k];
+        const float pe = fmaf(b[k], h[k], -pr);
+        float ns, se;
+        two_sum(s, pr, ns, se);
+        s = ns;
+        c += pe + se + b[k] * l[k];
+      }
+      if (s + c < -60.f) continue;  // weight below 1e-26: no measurable moment
+      const float ex = expf(s);     // accurate to ~1 ulp for any |s|
+      const float w = fmaf(ex, c, ex);
+      {  // phi_0 = 1 (column 0 of the table holds log w~, the exponent's constant)
+        const float y = w - Cc[0];
+        const float tt = S[0] + y;
+        Cc[0] = (tt - S[0]) - y;
+        S[0] = tt;
+      }
+#pragma unroll
+      for (int i = 1; i < K3; ++i) {
+        const float pr = w * h[i];
+        const float y = (pr - Cc[i]) + fmaf(w, h[i], -pr);
+        const float tt = S[i] + y;
+        Cc[i] = (tt - S[i]) - y;
+        S[i] = tt;
+      }
+    }
+  }
+  float r = 0.f;
+  const float inv0 = 1.f / (S[0] - Cc[0]);
+  const float nn = valid ? M[cell * K3] : 1.f;
+  if (valid) {
+    Eacc[cell * 36] = 1.f;
+#pragma unroll
+    for (int i = 1; i < K3; ++i) {
+      const float e = (S[i] - Cc[i]) * inv0;
+      Eacc[cell * 36 + i] = e;
+      r = fmaxf(r, fabsf(e - M[cell * K3 + i] / nn));
+    }
+    racc[cell] = r;
+  }
+  wave_append(valid && !(r <= tol), (int)cell, out_list, out_ctr);
+}
+
+// One Newton correction with the accurate gradient and the FP32 Hessian of
+// the cell's last assembly (same LDS layout as k_direction3).
+__global__ __launch_bounds__(64) void k_refine3(
+    const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
+    const float* __restrict__ S, const float* __restrict__ M, const float* __restrict__ Eacc,
+    float* __restrict__ beta) {
+  const int64_t count = *ctr;
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  if (base >= count) return;
+  const int t = threadIdx.x;
+  const int64_t slot = base + t;
+  const bool valid = slot < count;
+  const int64_t cell = valid ? (int64_t)list[slot] : 0;
+  __shared__ float sh[HPACK * 64];
+  __shared__ float sv[NH * 64];
+  for (int c = 0; c < 64; ++c) {
+    if (base + c >= count) break;
+    const float* src = S + (int64_t)list[base + c] * NCOL + K3;
+    for (int e = t; e < HPACK; e += 64) sh[sw(e, c)] = src[e];
+  }
+  __syncthreads();
+  const float* Sc = S + cell * NCOL;
+  const float inv0 = valid ? 1.f / Sc[0] : 1.f;
+  for (int a = 0; a < NH; ++a) sv[sw(a, t)] = valid ? Sc[a + 1] * inv0 : 0.f;
+  for (int i = 0; i < NH; ++i) {
+    const float ei = sv[sw(i, t)];
+    for (int j = i; j < NH; ++j) {
+      float* h = &sh[sw(hidx(i, j), t)];
+      *h = valid ? (*h * inv0 - ei * sv[sw(j, t)]) : (i == j ? 1.f : 0.f);
+    }
+  }
+  float dmin, dmax;
+  const bool ok = chol_upper_lds(sh, t, dmin, dmax);
+  if (!(valid && ok)) return;
+  const float* Mc = M + cell * K3;
+  const float nn = Mc[0];
+  const float* Ea = Eacc + cell * 36;
+  for (int i = 0; i < NH; ++i) {
+    float acc = -(Ea[i + 1] - Mc[i + 1] / nn);
+    for (int k = 0; k < i; ++k) acc -= sh[sw(hidx(k, i), t)] * sv[sw(k, t)];
+    sv[sw(i, t)] = acc / sh[sw(hidx(i, i), t)];
+  }
+  for (int i = NH - 1; i >= 0; --i) {
+    float acc = sv[sw(i, t)];
+    for (int j = i + 1; j < NH; ++j) acc -= sh[sw(hidx(i, j), t)] * sv[sw(j, t)];
+    sv[sw(i, t)] = acc / sh[sw(hidx(i, i), t)];
+  }
+  bool fin = true;
+  for (int a = 0; a < NH; ++a) fin = fin && isfinite(sv[sw(a, t)]);
+  if (fin)
+    for (int a = 0; a < NH; ++a) beta[cell * K3 + 1 + a] += sv[sw(a, t)];
+}
+
+// Final status and residual of refined cells.
+__global__ void k_refine_final(const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
+                               const float* __restrict__ racc, float tol_loose,
+                               uint32_t* __restrict__ status_w, float* resid_out,
+                               uint32_t* status_out) {
+  const int64_t count = *ctr;
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= count) return;
+  const int64_t cell = list[slot];
+  const float r = racc[cell];
+  uint32_t st = status_w[cell];
+  if (!(r <= tol_loose)) st = (st & ~MEM_ST_CONVERGED) | MEM_ST_STAGNATED;
+  status_w[cell] = st;
+  if (resid_out) resid_out[cell] = r;
+  if (status_out) status_out[cell] = st;
+}
+
+// --------------------------------------------------------------------------
+// E and the covariance block from S (checking entry point)
+// --------------------------------------------------------------------------
+__global__ void k_unpack3(int64_t n, const float* __restrict__ S, float* E, float* H) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const float* Sc = S + c * NCOL;
+  const float inv0 = 1.f / Sc[0];
+  if (E)
+    for (int k = 0; k < K3; ++k) E[c * K3 + k] = k == 0 ? Sc[0] * inv0 : Sc[k] * inv0;
+  if (H)
+    for (int i = 0; i < NH; ++i)
+      for (int j = 0; j < NH; ++j) {
+        const int a = min(i, j), b = max(i, j);
+        H[(c * NH + i) * NH + j] = Sc[pair_col(a + 1, b + 1)] * inv0 - Sc[i + 1] * inv0 * Sc[j + 1] * inv0;
+      }
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+static inline unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_set_ctr(int32_t* ctr, int n, hipStream_t s) {
+  k_set_ctr<<<1, 64, 0, s>>>(ctr, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init3(mem_ctx_t c, int64_t n, const float* M, float* beta, int32_t* out_list,
+                        int32_t* out_ctr, int32_t* iters, float* resid, uint32_t* status,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_init3<<<nblocks(n, 256), 256, 0, s>>>(n, M, beta, c->w_alpha, c->w_iters, c->w_status,
+                                           c->w_resid, c->w_rbest, c->w_itbest, out_list, out_ctr,
+                                           iters, resid, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_lse3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
+                       int64_t n, const float* M, float* beta, bool line_search,
+                       const SolveParams& p, int32_t* reset_a, int32_t* reset_b, hipStream_t s) {
+  const unsigned nb = nblocks(grid_cells > 0 ? grid_cells : 1, TILE);
+  if (line_search)
+    k_lse3<true><<<nb, 256, 0, s>>>(c->d_phiA, c->ngroups, list, ctr, n, M, beta, c->w_dbeta,
+                                    c->w_logZ, c->w_L, c->w_alpha, c->w_gdot, p, reset_a, reset_b);
+  else
+    k_lse3<false><<<nb, 256, 0, s>>>(c->d_phiA, c->ngroups, list, ctr, n, M, beta, c->w_dbeta,
+                                     c->w_logZ, c->w_L, c->w_alpha, c->w_gdot, p, reset_a, reset_b);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                            const int32_t* ctr, int64_t n, const float* beta, const float* table,
+                            float* S, hipStream_t s) {
+  if (grid_cells <= 0) return hipSuccess;
+  k_assemble3<<<nblocks(grid_cells, TILE), 256, 0, s>>>(c->d_phiA, table, c->ngroups, list, ctr, n,
+                                                        beta, c->w_logZ, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                             const int32_t* ctr, const float* M, const float* beta,
+                             const SolveParams& p,
+                             int32_t* next_list, int32_t* next_ctr, int32_t* fb_list,
+                             int32_t* fb_ctr, int32_t* iters, float* resid, uint32_t* status,
+                             int32_t* done_list, int32_t* done_ctr, hipStream_t s) {
+  if (grid_cells <= 0) return hipSuccess;
+  DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
+  k_direction3<<<nblocks(grid_cells, 64), 64, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
+                                                      c->w_alpha, c->w_iters, c->w_status,
+                                                      c->w_resid, c->w_L, c->w_rbest, c->w_itbest,
+                                                      beta, p, fb_list, fb_ctr, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_fallback3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                            const int32_t* ctr, const float* M, const float* beta,
+                            const SolveParams& p,
+                            int32_t* next_list, int32_t* next_ctr, int32_t* iters, float* resid,
+                            uint32_t* status, int32_t* done_list, int32_t* done_ctr,
+                            hipStream_t s) {
+  if (grid_cells <= 0) return hipSuccess;
+  DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
+  k_fallback3<<<nblocks(grid_cells, 32), 64, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
+                                                     c->w_alpha, c->w_iters, c->w_status,
+                                                     c->w_resid, c->w_L, c->w_rbest, c->w_itbest,
+                                                     beta, p, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
+                           const float* M, const float* beta, float tol, int32_t* out_list,
+                           int32_t* out_ctr, hipStream_t s) {
+  if (grid_cells <= 0) return hipSuccess;
+  k_accurate3<<<nblocks(grid_cells, 64), 64, 0, s>>>(c->d_accHi, c->d_accLo, c->Q, list, ctr, M,
+                                                     beta, c->w_logZ, c->w_Eacc, c->w_racc, tol,
+                                                     out_list, out_ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
+                          const float* M, float* beta, hipStream_t s) {
+  if (grid_cells <= 0) return hipSuccess;
+  k_refine3<<<nblocks(grid_cells, 64), 64, 0, s>>>(list, ctr, c->w_S, M, c->w_Eacc, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_final(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                               const int32_t* ctr, float tol_loose, float* resid,
+                               uint32_t* status, hipStream_t s) {
+  if (grid_cells <= 0) return hipSuccess;
+  k_refine_final<<<nblocks(grid_cells, 256), 256, 0, s>>>(list, ctr, c->w_racc, tol_loose,
+                                                          c->w_status, resid, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack3(mem_ctx_t c, int64_t n, float* E, float* H, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_unpack3<<<nblocks(n, 128), 128, 0, s>>>(n, c->w_S, E, H);
+  return hipGetLastError();
+}
+
+}  // namespace memk

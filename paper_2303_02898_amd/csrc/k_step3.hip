@@ -1,0 +1,617 @@
+// Gauge, flux, characteristic speeds, collision and finite-volume kernels for
+// the 3D 35-moment system with transport along x (Sec. 3.3-3.4, App. A, Alg. 2).
+//
+// Change of gauge (eq. "Change gauge M F"): per axis u_bar' = a u_bar + b with
+// a = s/s', b = (w - w')/s' (b = 0 on the transverse axes).  For the
+// orthonormal Hermite basis the 1D connection is
+//   phi_n(a x + b) = sum_{k<=n} C(n,k) a^k h_{n-k}(b; a^2-1) sqrt(k!/n!) phi_k(x),
+// with h_m(b; c) = E[He_m(X)], X ~ N(b, 1 + c); the 3D matrix is the
+// Kronecker product of the three axis matrices, applied axis by axis on the
+// total-degree-<=4 index set (which the lower-triangular factors preserve).
+#include <cfloat>
+#include <cmath>
+
+#include "mem_internal.h"
+
+namespace memk {
+
+// basis index of (a, b, c): degree offset + position within the degree
+__host__ __device__ constexpr int bidx(int a, int b, int c) {
+  return (a + b + c) * (a + b + c + 1) * (a + b + c + 2) / 6 +
+         (b + c) * (b + c + 1) / 2 + c;
+}
+
+__device__ __forceinline__ void hpoly3(float b, float c, float (&h)[5]) {
+  h[0] = 1.f;
+  h[1] = b;
+  h[2] = b * b + c;
+  h[3] = b * b * b + 3.f * b * c;
+  h[4] = b * b * b * b + 6.f * b * b * c + 3.f * c * c;
+}
+
+__device__ __forceinline__ void conn(float a, float b, float (&t)[5][5]) {
+  const float binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0},
+                             {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+  const float sfact[5] = {1.f, 1.f, 1.41421356237f, 2.44948974278f, 4.89897948557f};
+  float h[5];
+  hpoly3(b, a * a - 1.f, h);
+  const float ak[5] = {1.f, a, a * a, a * a * a, a * a * a * a};
+#pragma unroll
+  for (int n = 0; n < 5; ++n)
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      t[n][k] = k <= n ? binom[n][k] * ak[k] * h[n - k] * sfact[k] / sfact[n] : 0.f;
+}
+
+// v <- (t along axis AX) v, or its transpose
+template <int AX, bool TR>
+__device__ __forceinline__ void axis_apply(const float (&t)[5][5], float (&v)[K3]) {
+  float o[K3];
+#pragma unroll
+  for (int a = 0; a <= 4; ++a)
+#pragma unroll
+    for (int b = 0; b <= 4 - a; ++b)
+#pragma unroll
+      for (int c = 0; c <= 4 - a - b; ++c) {
+        const int x = AX == 0 ? a : (AX == 1 ? b : c);
+        const int rest = a + b + c - x;
+        float acc = 0.f;
+        if (!TR) {
+#pragma unroll
+          for (int x2 = 0; x2 <= x; ++x2) {
+            const int i = AX == 0 ? bidx(x2, b, c) : (AX == 1 ? bidx(a, x2, c) : bidx(a, b, x2));
+            acc += t[x][x2] * v[i];
+          }
+        } else {
+#pragma unroll
+          for (int x2 = x; x2 <= 4 - rest; ++x2) {
+            const int i = AX == 0 ? bidx(x2, b, c) : (AX == 1 ? bidx(a, x2, c) : bidx(a, b, x2));
+            acc += t[x2][x] * v[i];
+          }
+        }
+        o[bidx(a, b, c)] = acc;
+      }
+#pragma unroll
+  for (int i = 0; i < K3; ++i) v[i] = o[i];
+}
+
+// v <- T(g_to, g_from) v
+__device__ __forceinline__ void change_gauge(float (&v)[K3], const float* gto, const float* gfrom) {
+  float tx[5][5], tr[5][5];
+  conn(gfrom[1] / gto[1], (gfrom[0] - gto[0]) / gto[1], tx);
+  conn(gfrom[2] / gto[2], 0.f, tr);
+  axis_apply<0, false>(tx, v);
+  axis_apply<1, false>(tr, v);
+  axis_apply<2, false>(tr, v);
+}
+
+// ---- Hermite gauge ------------------------------------------------------------
+__device__ __forceinline__ bool hermite_params(const float (&m)[K3], const float* g, float* gH) {
+  const float n = m[0];
+  if (!(n > 0.f)) return false;
+  const float s2 = 1.41421356237f;
+  const float m1 = m[bidx(1, 0, 0)] / n;
+  const float exx = (s2 * m[bidx(2, 0, 0)] + n) / n;
+  const float err = (s2 * (m[bidx(0, 2, 0)] + m[bidx(0, 0, 2)]) + 2.f * n) / n;
+  const float vx = exx - m1 * m1;
+  if (!(vx > 0.f) || !(err > 0.f) || !isfinite(vx) || !isfinite(err)) return false;
+  gH[0] = g[0] + g[1] * m1;
+  gH[1] = g[1] * sqrtf(vx);
+  gH[2] = g[2] * sqrtf(0.5f * err);
+  return true;
+}
+
+__global__ __launch_bounds__(128) void k_gauge3(int64_t n, float* __restrict__ M, float* __restrict__ beta,
+                         float* __restrict__ g) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  float m[K3];
+#pragma unroll
+  for (int k = 0; k < K3; ++k) m[k] = M[c * K3 + k];
+  const float gg[3] = {g[c * 3], g[c * 3 + 1], g[c * 3 + 2]};
+  if (!(gg[1] > 0.f) || !(gg[2] > 0.f)) return;
+  float gH[3];
+  if (!hermite_params(m, gg, gH)) return;
+  change_gauge(m, gH, gg);
+#pragma unroll
+  for (int k = 0; k < K3; ++k) M[c * K3 + k] = m[k];
+  if (beta) {
+    // alpha(g_H) = T(g, g_H)^T alpha(g); beta_i = alpha_i for i >= 1
+    float b[K3];
+#pragma unroll
+    for (int k = 0; k < K3; ++k) b[k] = k == 0 ? 0.f : beta[c * K3 + k];
+    float tx[5][5], tr[5][5];
+    conn(gH[1] / gg[1], (gH[0] - gg[0]) / gg[1], tx);
+    conn(gH[2] / gg[2], 0.f, tr);
+    axis_apply<0, true>(tx, b);
+    axis_apply<1, true>(tr, b);
+    axis_apply<2, true>(tr, b);
+#pragma unroll
+    for (int k = 1; k < K3; ++k) beta[c * K3 + k] = b[k];
+  }
+  g[c * 3] = gH[0];
+  g[c * 3 + 1] = gH[1];
+  g[c * 3 + 2] = gH[2];
+}
+
+// ---- fluxes from the assembled moments --------------------------------------------
+// F_i = n (w E[phi_i] + s_x E[u_bar_x phi_i]); phi_1 = u_bar_x so E[u_bar_x phi_i]
+// is the (1, i) pair column of S.
+__global__ void k_flux3(int64_t n, const float* __restrict__ S, const float* __restrict__ beta,
+                        const float* __restrict__ g, float* __restrict__ F) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const float* Sc = S + c * NCOL;
+  const float inv0 = 1.f / Sc[0];
+  const float nn = beta[c * K3];
+  const float w = g[c * 3], sx = g[c * 3 + 1];
+  for (int i = 0; i < K3; ++i) {
+    const float e = Sc[i] * inv0;
+    const float x = (i == 0 ? Sc[1] : Sc[pair_col(i < 1 ? i : 1, i < 1 ? 1 : i)]) * inv0;
+    F[c * K3 + i] = nn * (w * e + sx * x);
+  }
+}
+
+// ---- characteristic speeds -------------------------------------------------------
+// Eigenvalues of dF/dM solve C v = mu B v with B = E[phi phi^T], C = E[u_bar_x
+// phi phi^T] (35 x 35, phi_0 included); lambda = w + s_x mu.  Per cell:
+// Cholesky B = L L^T, A = L^-1 C L^-T, Householder tridiagonalisation of A,
+// Sturm bisection for the extreme eigenvalues.  One thread per cell, matrices
+// in LDS (cell-interleaved).
+constexpr int EIG_CPW = 20;  // cells per workgroup (LDS bound)
+constexpr int EIG_L = 630, EIG_A = K3 * K3;
+constexpr int EIG_PER = EIG_L + EIG_A + 4 * K3;
+
+__device__ __forceinline__ int lidx(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
+
+__global__ __launch_bounds__(64) void k_eig3(int64_t n, const float* __restrict__ S,
+                                             const float* __restrict__ Sx,
+                                             const float* __restrict__ g, float umax,
+                                             float* __restrict__ out, int radius_only,
+                                             uint32_t* status) {
+  __shared__ float sh[EIG_PER * EIG_CPW];
+  const int t = threadIdx.x;
+  const int64_t c = (int64_t)blockIdx.x * EIG_CPW + t;
+  if (t >= EIG_CPW || c >= n) return;
+#define LL(i, j) sh[(lidx(i, j)) * EIG_CPW + t]
+#define AA(i, j) sh[(EIG_L + (i) * K3 + (j)) * EIG_CPW + t]
+#define VV(i) sh[(EIG_L + EIG_A + (i)) * EIG_CPW + t]
+#define PP(i) sh[(EIG_L + EIG_A + K3 + (i)) * EIG_CPW + t]
+#define DD(i) sh[(EIG_L + EIG_A + 2 * K3 + (i)) * EIG_CPW + t]
+#define EE(i) sh[(EIG_L + EIG_A + 3 * K3 + (i)) * EIG_CPW + t]
+  const float* Sc = S + c * NCOL;
+  const float* Xc = Sx + c * NCOL;
+  const float inv0 = 1.f / Sc[0];
+  bool ok = isfinite(inv0) && inv0 > 0.f;
+  for (int i = 0; i < K3; ++i)
+    for (int j = 0; j <= i; ++j) {
+      LL(i, j) = Sc[pair_col(j, i)] * inv0;
+      const float cv = Xc[pair_col(j, i)] * inv0;
+      AA(i, j) = cv;
+      AA(j, i) = cv;
+    }
+  // Cholesky of B (lower)
+  for (int k = 0; k < K3 && ok; ++k) {
+    float d = LL(k, k);
+    for (int j = 0; j < k; ++j) d -= LL(k, j) * LL(k, j);
+    if (!(d > 0.f) || !isfinite(d)) { ok = false; break; }
+    const float lkk = sqrtf(d);
+    LL(k, k) = lkk;
+    for (int i = k + 1; i < K3; ++i) {
+      float s = LL(i, k);
+      for (int j = 0; j < k; ++j) s -= LL(i, j) * LL(k, j);
+      LL(i, k) = s / lkk;
+    }
+  }
+  float mu_lo = 0.f, mu_hi = 0.f;
+  if (ok) {
+    // Y = L^-1 C (columns), then A = L^-1 Y^T (rows, in place)
+    for (int j = 0; j < K3; ++j)
+      for (int i = 0; i < K3; ++i) {
+        float s = AA(i, j);
+        for (int k = 0; k < i; ++k) s -= LL(i, k) * AA(k, j);
+        AA(i, j) = s / LL(i, i);
+      }
+    for (int j = 0; j < K3; ++j)
+      for (int i = 0; i < K3; ++i) {
+        float s = AA(j, i);
+        for (int k = 0; k < i; ++k) s -= LL(i, k) * AA(j, k);
+        AA(j, i) = s / LL(i, i);
+      }
+    // symmetrise against rounding
+    for (int i = 0; i < K3; ++i)
+      for (int j = 0; j < i; ++j) {
+        const float v = 0.5f * (AA(i, j) + AA(j, i));
+        AA(i, j) = v; AA(j, i) = v;
+      }
+    // Householder tridiagonalisation
+    for (int k = 0; k < K3 - 2; ++k) {
+      float sig = 0.f;
+      for (int i = k + 1; i < K3; ++i) sig += AA(i, k) * AA(i, k);
+      const float nx = sqrtf(sig);
+      if (nx == 0.f) { DD(k) = AA(k, k); EE(k) = 0.f; continue; }
+      const float x0 = AA(k + 1, k);
+      const float al = x0 > 0.f ? -nx : nx;
+      for (int i = k + 1; i < K3; ++i) VV(i) = AA(i, k);
+      VV(k + 1) = x0 - al;
+      float vn = 0.f;
+      for (int i = k + 1; i < K3; ++i) vn += VV(i) * VV(i);
+      DD(k) = AA(k, k);
+      EE(k) = al;
+      if (vn == 0.f) continue;
+      const float bet = 2.f / vn;
+      float vp = 0.f;
+      for (int i = k + 1; i < K3; ++i) {
+        float s = 0.f;
+        for (int j = k + 1; j < K3; ++j) s += AA(i, j) * VV(j);
+        PP(i) = bet * s;
+        vp += VV(i) * PP(i);
+      }
+      const float Kc = 0.5f * bet * vp;
+      for (int i = k + 1; i < K3; ++i) PP(i) -= Kc * VV(i);
+      for (int i = k + 1; i < K3; ++i)
+        for (int j = k + 1; j < K3; ++j) AA(i, j) -= VV(i) * PP(j) + PP(i) * VV(j);
+    }
+    DD(K3 - 2) = AA(K3 - 2, K3 - 2);
+    DD(K3 - 1) = AA(K3 - 1, K3 - 1);
+    EE(K3 - 2) = AA(K3 - 1, K3 - 2);
+    // Gershgorin bracket, then Sturm bisection for the smallest and largest
+    float lo = FLT_MAX, hi = -FLT_MAX;
+    for (int i = 0; i < K3; ++i) {
+      const float r = (i > 0 ? fabsf(EE(i - 1)) : 0.f) + (i < K3 - 1 ? fabsf(EE(i)) : 0.f);
+      lo = fminf(lo, DD(i) - r);
+      hi = fmaxf(hi, DD(i) + r);
+    }
+    auto count_below = [&](float x) {
+      int cnt = 0;
+      float q = DD(0) - x;
+      if (q == 0.f) q = -1e-30f;
+      if (q < 0.f) ++cnt;
+      for (int i = 1; i < K3; ++i) {
+        q = DD(i) - x - EE(i - 1) * EE(i - 1) / q;
+        if (q == 0.f) q = -1e-30f;
+        if (q < 0.f) ++cnt;
+      }
+      return cnt;
+    };
+    float a = lo, b = hi;
+    for (int it = 0; it < 48; ++it) {
+      const float mid = 0.5f * (a + b);
+      if (count_below(mid) >= 1) b = mid; else a = mid;
+    }
+    mu_lo = 0.5f * (a + b);
+    a = lo; b = hi;
+    for (int it = 0; it < 48; ++it) {
+      const float mid = 0.5f * (a + b);
+      if (count_below(mid) >= K3) b = mid; else a = mid;
+    }
+    mu_hi = 0.5f * (a + b);
+    ok = isfinite(mu_lo) && isfinite(mu_hi);
+  }
+  if (!ok) {  // bound |mu| <= max_p |u_bar_x,p|
+    mu_lo = -umax; mu_hi = umax;
+    if (status) status[c] |= MEM_ST_LAMBDA_FAIL;
+  }
+  const float w = g[c * 3], sx = g[c * 3 + 1];
+  const float l0 = w + sx * mu_lo, l1 = w + sx * mu_hi;
+  if (radius_only) out[c] = fmaxf(fabsf(l0), fabsf(l1));
+  else { out[c * 2] = l0; out[c * 2 + 1] = l1; }
+#undef LL
+#undef AA
+#undef VV
+#undef PP
+#undef DD
+#undef EE
+}
+
+// ---- ES-BGK collision -----------------------------------------------------------
+__global__ __launch_bounds__(128) void k_collide3(int64_t n, float* __restrict__ M, const float* __restrict__ g,
+                           float h_scalar, const float* __restrict__ dt_prob,
+                           const int32_t* __restrict__ prob, float prandtl, float mu_ref) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  float m[K3];
+#pragma unroll
+  for (int k = 0; k < K3; ++k) m[k] = M[c * K3 + k];
+  const float nn = m[0];
+  if (!(nn > 0.f)) return;
+  const float w = g[c * 3], sx = g[c * 3 + 1], sr = g[c * 3 + 2];
+  const float s2 = 1.41421356237f;
+  const float m1 = m[bidx(1, 0, 0)] / nn;
+  const float exx = (s2 * m[bidx(2, 0, 0)] + nn) / nn;
+  const float eyy = (s2 * m[bidx(0, 2, 0)] + nn) / nn;
+  const float ezz = (s2 * m[bidx(0, 0, 2)] + nn) / nn;
+  const float v = w + sx * m1;
+  const float pxx = sx * sx * (exx - m1 * m1);       // P_xx / n
+  const float prr = 0.5f * sr * sr * (eyy + ezz);    // (P_yy + P_zz) / (2n)
+  const float T = (pxx + 2.f * prr) / 3.f;
+  const float ip = 1.f / prandtl;
+  const float Sxx = T * ip + (1.f - ip) * pxx;
+  const float Srr = T * ip + (1.f - ip) * prr;
+  float hx[5], hr[5];
+  hpoly3((v - w) / sx, Sxx / (sx * sx) - 1.f, hx);
+  hpoly3(0.f, Srr / (sr * sr) - 1.f, hr);
+  const float sfact[5] = {1.f, 1.f, 1.41421356237f, 2.44948974278f, 4.89897948557f};
+  const float h = dt_prob ? 0.5f * dt_prob[prob[c]] : h_scalar;
+  const float tau = mu_ref / (prandtl * nn);
+  const float rr = h / tau;
+#pragma unroll
+  for (int a = 0; a <= 4; ++a)
+#pragma unroll
+    for (int b = 0; b <= 4 - a; ++b)
+#pragma unroll
+      for (int cc = 0; cc <= 4 - a - b; ++cc) {
+        const int i = bidx(a, b, cc);
+        const float mt = nn * hx[a] * hr[b] * hr[cc] / (sfact[a] * sfact[b] * sfact[cc]);
+        M[c * K3 + i] = (1.f - rr) * m[i] + rr * mt;
+      }
+}
+
+// ---- local Lax--Friedrichs update in each cell's gauge ----------------------------------
+__global__ __launch_bounds__(64) void k_fv3(int64_t n, const float* __restrict__ M, const float* __restrict__ F,
+                      const float* __restrict__ rho, const float* __restrict__ g,
+                      const int32_t* __restrict__ prob, const int64_t* __restrict__ off,
+                      const float* __restrict__ dx, const float* __restrict__ dt,
+                      const float* __restrict__ gM, const float* __restrict__ gF,
+                      const float* __restrict__ gR, const float* __restrict__ gG,
+                      float* __restrict__ Mnew) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int p = prob[c];
+  const bool first = c == off[p], last = c == off[p + 1] - 1;
+  const float* gc = g + c * 3;
+  const float* gl = first ? gG + (2 * p) * 3 : g + (c - 1) * 3;
+  const float* gr = last ? gG + (2 * p + 1) * 3 : g + (c + 1) * 3;
+  const float* Ml = first ? gM + (int64_t)(2 * p) * K3 : M + (c - 1) * K3;
+  const float* Fl = first ? gF + (int64_t)(2 * p) * K3 : F + (c - 1) * K3;
+  const float* Mr = last ? gM + (int64_t)(2 * p + 1) * K3 : M + (c + 1) * K3;
+  const float* Fr = last ? gF + (int64_t)(2 * p + 1) * K3 : F + (c + 1) * K3;
+  const float rl = first ? gR[2 * p] : rho[c - 1];
+  const float rr = last ? gR[2 * p + 1] : rho[c + 1];
+  const float rc = rho[c];
+  const float lm = fmaxf(rl, rc), lp = fmaxf(rc, rr);
+  const float k = dt[p] / dx[p];
+  float acc[K3];
+#pragma unroll
+  for (int i = 0; i < K3; ++i) acc[i] = M[c * K3 + i];
+  // F_{n-1/2} = (F_l + F_c)/2 + lm/2 (M_l - M_c); F_{n+1/2} = (F_c + F_r)/2 + lp/2 (M_c - M_r)
+  // contribution to M_c: k (F_{n-1/2} - F_{n+1/2})
+  //   = k/2 [F_l - F_r] + k/2 [lm M_l + lp M_r] - k/2 (lm + lp) M_c
+#pragma unroll
+  for (int i = 0; i < K3; ++i) acc[i] -= 0.5f * k * (lm + lp) * M[c * K3 + i];
+#pragma unroll 1
+  for (int side = 0; side < 2; ++side) {
+    const float* gn = side ? gr : gl;
+    const float* Mn = side ? Mr : Ml;
+    const float* Fn = side ? Fr : Fl;
+    const float lam = side ? lp : lm;
+    const float sgn = side ? -1.f : 1.f;
+    float tx[5][5], tr[5][5];
+    conn(gn[1] / gc[1], (gn[0] - gc[0]) / gc[1], tx);
+    conn(gn[2] / gc[2], 0.f, tr);
+    float v[K3];
+#pragma unroll
+    for (int i = 0; i < K3; ++i) v[i] = lam * Mn[i] + sgn * Fn[i];
+    axis_apply<0, false>(tx, v);
+    axis_apply<1, false>(tr, v);
+    axis_apply<2, false>(tr, v);
+#pragma unroll
+    for (int i = 0; i < K3; ++i) acc[i] += 0.5f * k * v[i];
+  }
+#pragma unroll
+  for (int i = 0; i < K3; ++i) Mnew[c * K3 + i] = acc[i];
+}
+
+// ---- batch book-keeping ---------------------------------------------------------------
+__global__ void k_prob_map(const int64_t* __restrict__ off, int P, int32_t* __restrict__ prob) {
+  const int p = blockIdx.x;
+  if (p >= P) return;
+  for (int64_t c = off[p] + threadIdx.x; c < off[p + 1]; c += blockDim.x) prob[c] = p;
+}
+
+__global__ void k_ghost_pack(int P, const float* __restrict__ ML, const float* __restrict__ MR,
+                             const float* __restrict__ gL, const float* __restrict__ gR,
+                             float* gM, float* gB, float* gG) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  for (int side = 0; side < 2; ++side) {
+    const float* m = side ? MR + (int64_t)p * K3 : ML + (int64_t)p * K3;
+    const float* gg = side ? gR + p * 3 : gL + p * 3;
+    const int64_t o = 2 * (int64_t)p + side;
+    for (int k = 0; k < K3; ++k) {
+      gM[o * K3 + k] = m[k];
+      const bool sq = (k == bidx(2, 0, 0) || k == bidx(0, 2, 0) || k == bidx(0, 0, 2));
+      gB[o * K3 + k] = k == 0 ? m[0] : (sq ? -0.70710678118f : 0.f);
+    }
+    for (int k = 0; k < 3; ++k) gG[o * 3 + k] = gg[k];
+  }
+}
+
+__global__ void k_rmax_init(int P, const float* __restrict__ gR, uint32_t* rmax) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  rmax[p] = __float_as_uint(fmaxf(gR[2 * p], gR[2 * p + 1]));
+}
+
+__global__ void k_rho_max(int64_t n, const float* __restrict__ rho, const int32_t* __restrict__ prob,
+                          uint32_t* rmax) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const float r = rho[c];
+  if (isfinite(r) && r >= 0.f) atomicMax(&rmax[prob[c]], __float_as_uint(r));
+}
+
+// mode 0: set dt where dt <= 0; mode 1: t += dt, dt = CFL dx / max radius.
+// Either way the running maximum is reset to the ghost radii afterwards.
+__global__ void k_dt3(int P, const float* __restrict__ dx, float cfl, float* t, float* dt,
+                      uint32_t* rmax, const float* __restrict__ gR, int mode) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const float r = __uint_as_float(rmax[p]);
+  const float ndt = cfl * dx[p] / r;
+  if (mode == 0) {
+    if (!(dt[p] > 0.f)) dt[p] = ndt;
+  } else {
+    t[p] += dt[p];
+    dt[p] = ndt;
+  }
+  rmax[p] = __float_as_uint(fmaxf(gR[2 * p], gR[2 * p + 1]));
+}
+
+__global__ void k_status_or(int64_t n, const uint32_t* __restrict__ src, uint32_t* dst) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) dst[c] |= src[c];
+}
+
+__global__ void k_copy(int64_t n, const float* __restrict__ src, float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// ---- conserved totals in FP64 ---------------------------------------------------------
+__global__ void k_conserved(const int64_t* __restrict__ off, const float* __restrict__ dx,
+                            const float* __restrict__ M, const float* __restrict__ g,
+                            double* out) {
+  const int p = blockIdx.x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t c = off[p] + threadIdx.x; c < off[p + 1]; c += blockDim.x) {
+    const float* m = M + c * K3;
+    const double nn = m[0];
+    const double w = g[c * 3], sx = g[c * 3 + 1], sr = g[c * 3 + 2];
+    const double r2 = 1.4142135623730951;
+    const double m1 = m[bidx(1, 0, 0)] / nn;
+    const double exx = (r2 * m[bidx(2, 0, 0)] + nn) / nn;
+    const double err = (r2 * (m[bidx(0, 2, 0)] + m[bidx(0, 0, 2)]) + 2.0 * nn) / nn;
+    const double v = w + sx * m1;
+    const double trP = nn * (sx * sx * (exx - m1 * m1) + sr * sr * err);
+    s0 += nn;
+    s1 += nn * v;
+    s2 += 0.5 * nn * v * v + 0.5 * trP;
+  }
+  __shared__ double red[3][256];
+  red[0][threadIdx.x] = s0; red[1][threadIdx.x] = s1; red[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double h = dx[p];
+    out[p * 3] = h * red[0][0];
+    out[p * 3 + 1] = h * red[1][0];
+    out[p * 3 + 2] = h * red[2][0];
+  }
+}
+
+// ---- launchers ---------------------------------------------------------------------------
+static inline unsigned nb(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_gauge3(mem_ctx_t c, int64_t n, float* M, float* beta, float* g, hipStream_t s) {
+  (void)c;
+  if (n <= 0) return hipSuccess;
+  k_gauge3<<<nb(n, 128), 128, 0, s>>>(n, M, beta, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux3(mem_ctx_t c, int64_t n, const float* beta, const float* g, float* F,
+                        float* out, bool want_lam, bool radius_only, uint32_t* status,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  // log Z at beta, then S = sigma . Psi (and Sx = sigma . Psi_x for the speeds)
+  SolveParams dummy{};
+  hipError_t e = launch_lse3(c, n, nullptr, nullptr, n, nullptr, const_cast<float*>(beta), false,
+                             dummy, nullptr, nullptr, s);
+  if (e != hipSuccess) return e;
+  e = launch_assemble3(c, n, nullptr, nullptr, n, beta, c->d_psi, c->w_S, s);
+  if (e != hipSuccess) return e;
+  if (F) {
+    k_flux3<<<nb(n, 128), 128, 0, s>>>(n, c->w_S, beta, g, F);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (want_lam) {
+    e = launch_assemble3(c, n, nullptr, nullptr, n, beta, c->d_psix, c->w_Sx, s);
+    if (e != hipSuccess) return e;
+    double um = 0.0;
+    for (int p = 0; p < c->Q; ++p) um = fmax(um, fabs(c->h_nodes[(size_t)p * 3]));
+    k_eig3<<<nb(n, EIG_CPW), 64, 0, s>>>(n, c->w_S, c->w_Sx, g, (float)um, out, radius_only ? 1 : 0,
+                                         status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_collide3(mem_ctx_t c, int64_t n, float* M, const float* g, float h_scalar,
+                           const float* dt_prob, const int32_t* prob, float prandtl, float mu_ref,
+                           hipStream_t s) {
+  (void)c;
+  if (n <= 0) return hipSuccess;
+  k_collide3<<<nb(n, 128), 128, 0, s>>>(n, M, g, h_scalar, dt_prob, prob, prandtl, mu_ref);
+  return hipGetLastError();
+}
+
+hipError_t launch_fv3(mem_ctx_t c, int64_t n, const float* M, const float* F, const float* rho,
+                      const float* g, const int32_t* prob, const int64_t* offsets, const float* dx,
+                      const float* dt, float* Mnew, int P, hipStream_t s) {
+  (void)P;
+  if (n <= 0) return hipSuccess;
+  k_fv3<<<nb(n, 64), 64, 0, s>>>(n, M, F, rho, g, prob, offsets, dx, dt, c->w_gM, c->w_gF, c->w_gR,
+                                 c->w_gG, Mnew);
+  return hipGetLastError();
+}
+
+hipError_t launch_prob_map(mem_ctx_t c, const int64_t* offsets, int P, int32_t* prob,
+                           hipStream_t s) {
+  (void)c;
+  if (P <= 0) return hipSuccess;
+  k_prob_map<<<P, 256, 0, s>>>(offsets, P, prob);
+  return hipGetLastError();
+}
+
+hipError_t launch_ghost_pack(mem_ctx_t c, const mem_batch_t* b, hipStream_t s) {
+  const int P = b->n_problems;
+  k_ghost_pack<<<nb(P, 128), 128, 0, s>>>(P, b->M_left, b->M_right, b->g_left, b->g_right, c->w_gM,
+                                          c->w_gB, c->w_gG);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho_max(mem_ctx_t c, int64_t n, const float* rho, const int32_t* prob, int P,
+                          hipStream_t s) {
+  (void)P;
+  if (n <= 0) return hipSuccess;
+  k_rho_max<<<nb(n, 256), 256, 0, s>>>(n, rho, prob, c->w_rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt_update(mem_ctx_t c, int P, const float* dx, float cfl, float* t, float* dt,
+                            bool advance_t, hipStream_t s) {
+  k_dt3<<<nb(P, 128), 128, 0, s>>>(P, dx, cfl, t, dt, c->w_rmax, c->w_gR, advance_t ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_rmax_init(mem_ctx_t c, int P, hipStream_t s) {
+  k_rmax_init<<<nb(P, 128), 128, 0, s>>>(P, c->w_gR, c->w_rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_or(int64_t n, const uint32_t* src, uint32_t* dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_status_or<<<nb(n, 256), 256, 0, s>>>(n, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(int64_t n, const float* src, float* dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_copy<<<nb(n, 256), 256, 0, s>>>(n, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_conserved(mem_ctx_t c, const mem_batch_t* b, const float* M, const float* g,
+                            double* out, hipStream_t s) {
+  (void)c;
+  if (b->n_problems <= 0) return hipSuccess;
+  k_conserved<<<b->n_problems, 256, 0, s>>>(b->cell_offsets, b->dx, M, g, out);
+  return hipGetLastError();
+}
+
+}  // namespace memk

@@ -1,0 +1,184 @@
+// Internal declarations shared by the host API and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mem.h"
+
+namespace memk {
+
+// ---- 3D, 35-moment layout constants -----------------------------------------
+constexpr int K3 = 35;        // basis size (total degree <= 4 in 3 variables)
+constexpr int NH = 34;        // Newton unknowns beta_1..beta_34
+constexpr int NPAIR = 630;    // pairs (i <= j) of basis functions
+constexpr int NCOL = 640;     // pair columns padded to 40 MFMA blocks of 16
+constexpr int NBLK = 40;      // 16-column blocks of the assembly GEMM
+constexpr int GRP = 16;       // quadrature nodes per MFMA node group
+constexpr int NJ = 9;         // 4-wide k-chunks of the exponent GEMM (36 = 9*4)
+constexpr int HPACK = 595;    // packed upper triangle of the 34x34 Hessian
+constexpr int TILE = 64;      // cells per assembly / line-search workgroup
+constexpr float NEG_BIG = -1.0e30f;  // log weight of padding nodes (exp -> 0)
+
+// Column of the pair (i, j), i <= j, in the row-major upper-triangle order.
+__host__ __device__ constexpr int pair_col(int i, int j) {
+  return i * K3 - (i * (i - 1)) / 2 + (j - i);
+}
+
+// ---- 1D, 5-moment layout ---------------------------------------------------
+constexpr int K1 = 5;
+constexpr int Q1MAX = 64;
+
+// Per-call options as seen by kernels (plain floats, no host structs).
+struct SolveParams {
+  float tol_grad, tol_dec, tol_loose;
+  int max_iter, max_ls;
+  float c, atol, rtol;
+  float lambda0, lambda_mul, alpha_min;
+  float fp64_ratio;
+  float lmin;  // min_p log w~_p: a dual value below it certifies non-realizability
+  int refine;  // > 0: converged and stalled cells go on to compensated refinement
+  float beta_max;  // |beta|_inf beyond this ends a cell as non-realizable (0 = off)
+};
+
+}  // namespace memk
+
+// ---- context -----------------------------------------------------------------
+struct mem_ctx_s {
+  int dim = 3, n1d = 12, K = 35, Q = 0, Qpad = 0, ngroups = 0, prec = 0;
+  int device = 0;
+  // host FP64 tables (checked against the oracle by the tests)
+  std::vector<double> h_nodes, h_w, h_phi, h_logw;
+  // device tables, 3D
+  float* d_phiA = nullptr;   // exponent A operand  [ngroups][NJ][64]
+  float* d_psi = nullptr;    // assembly B operand  [ngroups][4][10][64][4]
+  float* d_psix = nullptr;   // flux-Jacobian B operand, same layout
+  void* d_psi_hi = nullptr;  // mixed precision B operands (16-bit), see kernels
+  void* d_psi_lo = nullptr;
+  float* d_colscale = nullptr;  // per-column power-of-two scale for FP16 tables
+  float* d_accHi = nullptr;  // [Qpad][36] (log w~, phi_1..phi_34, 0), FP32 high part
+  float* d_accLo = nullptr;  // [Qpad][36] FP32 low part (table - high part)
+  // device tables, 1D
+  float* d_tab1 = nullptr;   // [Q][8]: phi_0..phi_4, log w~, 0, 0
+  // workspace (per cell unless stated)
+  int64_t cap_cells = 0;
+  int32_t cap_problems = 0;
+  float* w_S = nullptr;       // [cap][NCOL]
+  float* w_Sx = nullptr;      // [cap][NCOL]
+  float* w_dbeta = nullptr;   // [cap][36]
+  float* w_logZ = nullptr;    // [cap]
+  float* w_L = nullptr;
+  float* w_alpha = nullptr;
+  float* w_gdot = nullptr;
+  float* w_resid = nullptr;
+  int32_t* w_iters = nullptr;
+  uint32_t* w_status = nullptr;
+  int32_t* w_list[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t* w_ctr = nullptr;   // [8] list counters
+  float* w_Eacc = nullptr;    // [cap][36] compensated moments
+  float* w_racc = nullptr;    // [cap] compensated residual
+  float* w_rbest = nullptr;   // [cap] best FP32 residual so far (stall test)
+  int32_t* w_itbest = nullptr;// [cap] iteration of the last halving of the residual
+  int32_t* h_ctr = nullptr;   // pinned host mirror for polling
+  // time stepping
+  float* w_Mnew = nullptr;    // [cap][K]
+  float* w_F = nullptr;       // [cap][K]
+  float* w_rho = nullptr;     // [cap]
+  int32_t* w_prob = nullptr;  // [cap] problem of each cell
+  float* w_gM = nullptr;      // ghost moments   [2*P][K]
+  float* w_gB = nullptr;      // ghost beta      [2*P][K]
+  float* w_gG = nullptr;      // ghost gauge     [2*P][3]
+  float* w_gF = nullptr;      // ghost fluxes    [2*P][K]
+  float* w_gR = nullptr;      // ghost radius    [2*P]
+  uint32_t* w_rmax = nullptr; // per-problem max radius (float bits) [P]
+  // kernel timing (mem_profile_enable / mem_profile_read)
+  bool prof = false;
+  std::vector<hipEvent_t> prof_pool;
+  size_t prof_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_marks;
+  std::string err;
+};
+
+// ---- kernel launchers (defined in the .hip files) ------------------------------
+namespace memk {
+
+hipError_t launch_solve1(mem_ctx_t c, int64_t n, const float* M, float* beta,
+                         const SolveParams& p, int32_t* iters, float* resid,
+                         uint32_t* status, hipStream_t s);
+hipError_t launch_gauge1(mem_ctx_t c, int64_t n, float* M, float* beta, float* g,
+                         hipStream_t s);
+hipError_t launch_gauge3(mem_ctx_t c, int64_t n, float* M, float* beta, float* g,
+                         hipStream_t s);
+
+// 3D Newton pieces.  Lists are arrays of cell ids with a device counter; a
+// null list means "cells 0..n-1".
+hipError_t launch_init3(mem_ctx_t c, int64_t n, const float* M, float* beta,
+                        int32_t* out_list, int32_t* out_ctr, int32_t* iters, float* resid,
+                        uint32_t* status, hipStream_t s);
+hipError_t launch_lse3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                       const int32_t* ctr, int64_t n, const float* M, float* beta,
+                       bool line_search, const SolveParams& p, int32_t* reset_a,
+                       int32_t* reset_b, hipStream_t s);
+hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                            const int32_t* ctr, int64_t n, const float* beta,
+                            const float* table, float* S, hipStream_t s);
+hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                             const int32_t* ctr, const float* M, const float* beta,
+                             const SolveParams& p,
+                             int32_t* next_list, int32_t* next_ctr, int32_t* fb_list,
+                             int32_t* fb_ctr, int32_t* iters, float* resid,
+                             uint32_t* status, int32_t* done_list, int32_t* done_ctr,
+                             hipStream_t s);
+hipError_t launch_fallback3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                            const int32_t* ctr, const float* M, const float* beta,
+                            const SolveParams& p,
+                            int32_t* next_list, int32_t* next_ctr, int32_t* iters,
+                            float* resid, uint32_t* status, int32_t* done_list,
+                            int32_t* done_ctr, hipStream_t s);
+hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                            const int32_t* ctr, const float* M, const float* beta, float tol,
+                            int32_t* out_list, int32_t* out_ctr, hipStream_t s);
+hipError_t launch_refine3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                          const int32_t* ctr, const float* M, float* beta, hipStream_t s);
+hipError_t launch_refine_final(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                               const int32_t* ctr, float tol_loose, float* resid,
+                               uint32_t* status, hipStream_t s);
+hipError_t launch_set_ctr(int32_t* ctr, int n, hipStream_t s);
+hipError_t launch_unpack3(mem_ctx_t c, int64_t n, float* E, float* H, hipStream_t s);
+hipError_t launch_flux3(mem_ctx_t c, int64_t n, const float* beta, const float* g,
+                        float* F, float* rho_or_lam, bool want_lam, bool radius_only,
+                        uint32_t* status, hipStream_t s);
+
+// time stepping
+hipError_t launch_collide3(mem_ctx_t c, int64_t n, float* M, const float* g,
+                           float h_scalar, const float* dt_prob, const int32_t* prob,
+                           float prandtl, float mu_ref, hipStream_t s);
+hipError_t launch_fv3(mem_ctx_t c, int64_t n, const float* M, const float* F,
+                      const float* rho, const float* g, const int32_t* prob,
+                      const int64_t* offsets, const float* dx, const float* dt,
+                      float* Mnew, int P, hipStream_t s);
+hipError_t launch_prob_map(mem_ctx_t c, const int64_t* offsets, int P, int32_t* prob,
+                           hipStream_t s);
+hipError_t launch_ghost_pack(mem_ctx_t c, const mem_batch_t* b, hipStream_t s);
+hipError_t launch_rho_max(mem_ctx_t c, int64_t n, const float* rho, const int32_t* prob,
+                          int P, hipStream_t s);
+hipError_t launch_dt_update(mem_ctx_t c, int P, const float* dx, float cfl, float* t,
+                            float* dt, bool advance_t, hipStream_t s);
+hipError_t launch_status_or(int64_t n, const uint32_t* src, uint32_t* dst, hipStream_t s);
+hipError_t launch_rmax_init(mem_ctx_t c, int P, hipStream_t s);
+hipError_t launch_copy(int64_t n, const float* src, float* dst, hipStream_t s);
+hipError_t launch_conserved(mem_ctx_t c, const mem_batch_t* b, const float* M,
+                            const float* g, double* out, hipStream_t s);
+
+}  // namespace memk
+
+// host table builder (tables.cpp)
+namespace memt {
+void gauss_hermite(int n, std::vector<double>& x, std::vector<double>& w);
+void build_host(int dim, int n, std::vector<double>& nodes, std::vector<double>& wts,
+                std::vector<double>& logw, std::vector<double>& phi, int& K, int& Q);
+void build_tables(mem_ctx_t c);   // fills host tables and uploads device layouts
+}

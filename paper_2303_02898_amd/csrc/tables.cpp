@@ -1,0 +1,210 @@
+// Host-side FP64 construction of the quadrature and basis tables, and their
+// conversion to the device operand layouts of the kernels.
+//
+// Quadrature (Sec. 3.1, eq. "Numerical integration"): tensor Gauss--Hermite
+// rule of the standard normal, nodes fixed in gauge coordinates.  The 1D rule
+// is computed from the Jacobi matrix of the probabilists' Hermite polynomials
+// (zero diagonal, off-diagonal sqrt(k)): eigenvalues by Sturm-sequence
+// bisection, polished by Newton on the orthonormal polynomial p_n, weights
+// w_i = 1 / (n p_{n-1}(x_i)^2) (total mass 1).  Lebesgue log weights:
+// log w~ = log w + |x|^2/2 + (d/2) log(2 pi).
+//
+// Basis (App. B, orthogonal form extended to 3D): phi_(a,b,c) = p_a(x) p_b(y)
+// p_c(z) with p_k = He_k / sqrt(k!), total degree <= 4, ordered by degree then
+// lexicographically descending.
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+#include "mem_internal.h"
+
+namespace memt {
+
+namespace {
+
+// orthonormal Hermite values p_0..p_m at x
+void ortho_hermite(int m, double x, double* p) {
+  p[0] = 1.0;
+  if (m >= 1) p[1] = x;
+  for (int k = 1; k < m; ++k)
+    p[k + 1] = (x * p[k] - std::sqrt((double)k) * p[k - 1]) / std::sqrt((double)(k + 1));
+}
+
+// number of eigenvalues of the n x n Jacobi matrix smaller than x
+int sturm_count(int n, double x) {
+  int cnt = 0;
+  double q = -x;
+  if (q == 0.0) q = -1e-300;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    q = -x - (double)i / q;
+    if (q == 0.0) q = -1e-300;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+}  // namespace
+
+void gauss_hermite(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double bound = 2.0 * std::sqrt((double)n) + 1.0;
+  std::vector<double> p(n + 1);
+  for (int k = 0; k < n; ++k) {
+    double lo = -bound, hi = bound;  // k-th smallest eigenvalue in (lo, hi)
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * (1.0 + std::fabs(lo)); ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (sturm_count(n, mid) > k) hi = mid; else lo = mid;
+    }
+    double r = 0.5 * (lo + hi);
+    for (int it = 0; it < 3; ++it) {  // Newton polish on p_n
+      ortho_hermite(n, r, p.data());
+      double d = std::sqrt((double)n) * p[n - 1];
+      if (d != 0.0) r -= p[n] / d;
+    }
+    ortho_hermite(n, r, p.data());
+    x[k] = r;
+    w[k] = 1.0 / ((double)n * p[n - 1] * p[n - 1]);
+  }
+  // symmetrise (rule is exactly symmetric) and normalise the mass
+  for (int k = 0; k < n / 2; ++k) {
+    double a = 0.5 * (x[n - 1 - k] - x[k]);
+    x[k] = -a; x[n - 1 - k] = a;
+    double b = 0.5 * (w[k] + w[n - 1 - k]);
+    w[k] = b; w[n - 1 - k] = b;
+  }
+  if (n % 2) x[n / 2] = 0.0;
+  double s = 0.0;
+  for (double v : w) s += v;
+  for (double& v : w) v /= s;
+}
+
+namespace {
+
+void multi_indices(int dim, std::vector<int>& a, std::vector<int>& b, std::vector<int>& c) {
+  a.clear(); b.clear(); c.clear();
+  for (int tot = 0; tot <= 4; ++tot) {
+    if (dim == 1) { a.push_back(tot); b.push_back(0); c.push_back(0); continue; }
+    for (int i = tot; i >= 0; --i)
+      for (int j = tot - i; j >= 0; --j) { a.push_back(i); b.push_back(j); c.push_back(tot - i - j); }
+  }
+}
+
+template <typename T>
+T* upload(const std::vector<T>& h) {
+  T* d = nullptr;
+  if (hipMalloc(&d, h.size() * sizeof(T)) != hipSuccess) throw std::runtime_error("hipMalloc (tables)");
+  if (hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    throw std::runtime_error("hipMemcpy (tables)");
+  return d;
+}
+
+}  // namespace
+
+void build_host(int dim, int n, std::vector<double>& nodes, std::vector<double>& wts,
+                std::vector<double>& logw, std::vector<double>& phi, int& K, int& Q) {
+  std::vector<double> x, w;
+  gauss_hermite(n, x, w);
+  std::vector<int> ia, ib, ic;
+  multi_indices(dim, ia, ib, ic);
+  K = (int)ia.size();
+  Q = dim == 1 ? n : n * n * n;
+  nodes.assign((size_t)Q * dim, 0.0);
+  wts.assign(Q, 0.0);
+  logw.assign(Q, 0.0);
+  phi.assign((size_t)Q * K, 0.0);
+  const double half_log_2pi = 0.5 * std::log(2.0 * M_PI);
+  std::vector<double> px(5), py(5), pz(5);
+  for (int p = 0; p < Q; ++p) {
+    int i0 = dim == 1 ? p : p / (n * n), i1 = dim == 1 ? 0 : (p / n) % n, i2 = dim == 1 ? 0 : p % n;
+    double ux = x[i0], uy = dim == 1 ? 0.0 : x[i1], uz = dim == 1 ? 0.0 : x[i2];
+    double wt = dim == 1 ? w[i0] : w[i0] * w[i1] * w[i2];
+    nodes[(size_t)p * dim + 0] = ux;
+    if (dim == 3) { nodes[(size_t)p * 3 + 1] = uy; nodes[(size_t)p * 3 + 2] = uz; }
+    wts[p] = wt;
+    logw[p] = std::log(wt) + 0.5 * (ux * ux + uy * uy + uz * uz) + dim * half_log_2pi;
+    ortho_hermite(4, ux, px.data());
+    ortho_hermite(4, uy, py.data());
+    ortho_hermite(4, uz, pz.data());
+    for (int k = 0; k < K; ++k) phi[(size_t)p * K + k] = px[ia[k]] * py[ib[k]] * pz[ic[k]];
+  }
+}
+
+void build_tables(mem_ctx_t ctx) {
+  const int dim = ctx->dim;
+  int K = 0, Q = 0;
+  build_host(dim, ctx->n1d, ctx->h_nodes, ctx->h_w, ctx->h_logw, ctx->h_phi, K, Q);
+  ctx->K = K;
+  ctx->Q = Q;
+
+  if (dim == 1) {
+    std::vector<float> t((size_t)Q * 8, 0.f);
+    for (int p = 0; p < Q; ++p) {
+      for (int k = 0; k < 5; ++k) t[(size_t)p * 8 + k] = (float)ctx->h_phi[(size_t)p * 5 + k];
+      t[(size_t)p * 8 + 5] = (float)ctx->h_logw[p];
+    }
+    ctx->d_tab1 = upload(t);
+    ctx->Qpad = Q;
+    ctx->ngroups = 0;
+    return;
+  }
+
+  using namespace memk;
+  const int Qpad = (Q + GRP - 1) / GRP * GRP;
+  const int ng = Qpad / GRP;
+  ctx->Qpad = Qpad;
+  ctx->ngroups = ng;
+  // exponent operand: PhiE[p][0] = log w~, PhiE[p][k] = phi_k (k = 1..34), [35] = 0
+  auto phiE = [&](int p, int k) -> double {
+    if (p >= Q) return k == 0 ? (double)NEG_BIG : 0.0;
+    if (k == 0) return ctx->h_logw[p];
+    if (k >= K3) return 0.0;
+    return ctx->h_phi[(size_t)p * K3 + k];
+  };
+  std::vector<float> A((size_t)ng * NJ * 64);
+  for (int g = 0; g < ng; ++g)
+    for (int j = 0; j < NJ; ++j)
+      for (int l = 0; l < 64; ++l)
+        A[((size_t)g * NJ + j) * 64 + l] = (float)phiE(GRP * g + (l & 15), 4 * j + (l >> 4));
+  ctx->d_phiA = upload(A);
+  // compensated-exponent tables: value = hi + lo with hi = fl32(value)
+  std::vector<float> AH((size_t)Qpad * 36), AL((size_t)Qpad * 36);
+  for (int p = 0; p < Qpad; ++p)
+    for (int k = 0; k < 36; ++k) {
+      const double v = phiE(p, k);
+      const float hi = (float)v;
+      AH[(size_t)p * 36 + k] = hi;
+      AL[(size_t)p * 36 + k] = p < Q ? (float)(v - (double)hi) : 0.f;
+    }
+  ctx->d_accHi = upload(AH);
+  ctx->d_accLo = upload(AL);
+  // pair index of each column
+  std::vector<int> ci(NCOL, -1), cj(NCOL, -1);
+  for (int i = 0; i < K3; ++i)
+    for (int j = i; j < K3; ++j) { ci[pair_col(i, j)] = i; cj[pair_col(i, j)] = j; }
+  auto psi = [&](int p, int col, bool withx) -> double {
+    if (p >= Q || ci[col] < 0) return 0.0;
+    double v = ctx->h_phi[(size_t)p * K3 + ci[col]] * ctx->h_phi[(size_t)p * K3 + cj[col]];
+    return withx ? v * ctx->h_nodes[(size_t)p * 3] : v;
+  };
+  // B operand of v_mfma_f32_16x16x4f32 for k-step r of group g:
+  // lane l supplies node 16g + 4(l/16) + r, column 16b + l%16; stored as
+  // [g][r][b/4][l][b%4] so each lane reads 4 blocks with one 16-byte load.
+  std::vector<float> B((size_t)ng * 4 * 10 * 64 * 4), BX(B.size());
+  for (int g = 0; g < ng; ++g)
+    for (int r = 0; r < 4; ++r)
+      for (int b4 = 0; b4 < 10; ++b4)
+        for (int l = 0; l < 64; ++l)
+          for (int q = 0; q < 4; ++q) {
+            size_t o = ((((size_t)g * 4 + r) * 10 + b4) * 64 + l) * 4 + q;
+            int p = GRP * g + 4 * (l >> 4) + r;
+            int col = 16 * (4 * b4 + q) + (l & 15);
+            B[o] = (float)psi(p, col, false);
+            BX[o] = (float)psi(p, col, true);
+          }
+  ctx->d_psi = upload(B);
+  ctx->d_psix = upload(BX);
+}
+
+}  // namespace memt

@@ -1,0 +1,60 @@
+"""Host-side checks of the HIP library (no GPU needed).
+
+* The shared library loads and exports every entry point that
+  ``include/mem.h`` declares with MEM_API.
+* The library's FP64 host tables (Gauss--Hermite nodes/weights, Lebesgue log
+  weights, orthonormal Hermite basis at the nodes) equal the oracle's, which
+  are built independently (NumPy's hermegauss and a separate recurrence).
+* Default options carry the constants of Alg. 1 (``tests/golden/alg1_defaults.json``).
+"""
+
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2303_02898_amd as mem
+from oracle import basis, quadrature
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mem.h")).read()
+    return re.findall(r"MEM_API\s+[\w\s\*]+?\b(mem_\w+)\s*\(", text)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mem.load_library()
+    names = _declared_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("dim,n", [(1, 16), (3, 12), (3, 8)])
+def test_host_tables_match_oracle(dim, n):
+    nodes = mem.host_table(dim, n, "nodes")
+    w = mem.host_table(dim, n, "weights")
+    phi = mem.host_table(dim, n, "phi")
+    logw = mem.host_table(dim, n, "logw")
+    on, ow = quadrature.tensor_rule(n, dim)
+    assert np.max(np.abs(nodes - on)) < 1e-12
+    assert np.max(np.abs(w - ow)) < 1e-14
+    assert np.max(np.abs(logw - quadrature.lebesgue_log_weights(on, ow))) < 1e-10
+    ophi = basis.evaluate(on, dim)
+    assert np.max(np.abs(phi - ophi)) < 1e-9 * max(1.0, np.max(np.abs(ophi)))
+
+
+def test_host_table_rejects_bad_arguments():
+    with pytest.raises(mem.MemError):
+        mem.host_table(2, 12, "nodes")
+
+
+def test_default_options_are_the_papers_constants():
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "alg1_defaults.json")))
+    o = mem.default_opts()
+    for key, val in gold["values"].items():
+        assert getattr(o, key) == pytest.approx(val, rel=1e-6), key

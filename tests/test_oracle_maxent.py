@@ -168,3 +168,24 @@ def test_config1_recovers_generating_beta(rule1):
     err = np.max(np.abs(out["beta"] - bgen), axis=1)
     assert np.median(err) < 1e-4
     assert np.max(err) < 5e-3
+
+
+def test_dual_value_lower_bound_at_solutions(rule3):
+    # at a minimiser: logZ - beta.M/n = sum sigma log w~ - sum sigma log sigma >= min log w~
+    cells = mem_inputs.mott_smith_cells(16, config=2, replica=12)
+    M = cells["M"]
+    out = maxent.newton_solve(M, mem_inputs.maxwellian_beta(16, 35, M[:, 0]),
+                              rule3["Phi"], rule3["logw"])
+    ok = out["converged"]
+    v = maxent.dual_value(out["beta"][ok], M[ok], rule3["Phi"], rule3["logw"])
+    sig = maxent.sigma(out["beta"][ok], rule3["Phi"], rule3["logw"])
+    ent = -np.sum(sig * np.log(np.maximum(sig, 1e-300)), axis=1)
+    assert np.allclose(v, sig @ rule3["logw"] + ent, rtol=1e-9, atol=1e-9)
+    assert np.all(v >= np.min(rule3["logw"]))
+
+
+def test_target_outside_node_hull_is_certified_nonrealizable(rule1):
+    # mean velocity beyond the largest node: no distribution on the nodes has it
+    M = np.array([[1.0, 7.0, 0.0, 0.0, 0.0]])
+    out = maxent.newton_solve(M, maxent.maxwellian_beta(M, 1), rule1["Phi"], rule1["logw"])
+    assert out["nonrealizable"][0] and not out["converged"][0]
