@@ -115,10 +115,13 @@ typedef struct {
                                compensated residual and a cell is CONVERGED only if it is
                                <= tol_grad_loose (else STAGNATED).  0 = off.               */
   float   beta_max;         /* |beta_i|, i >= 1, above this ends the cell as NONREALIZABLE
-                               (100; 0 = off).  In the Hermite gauge solvable targets have
-                               |beta| of order 1-10; iterates that run away along a ray
-                               of the dual (targets outside the nodes' moment set) are
-                               stopped here before the dual-value certificate fires.      */
+                               (25; 0 = off).  In the Hermite gauge solvable targets have
+                               |beta| of order 1-10 (Mott-Smith mixtures up to Mach 10:
+                               below 6); iterates that run away along a ray of the dual
+                               (targets outside the nodes' moment set) are stopped here
+                               long before the dual-value certificate fires.  Independent
+                               of it, a residual above 1e-3 that has not halved for 30
+                               iterations ends a cell as STAGNATED.                        */
 } mem_solve_opts_t;
 
 /* A ragged batch of independent 1D normal-shock problems (dim must be 3).

@@ -203,7 +203,7 @@ void mem_solve_opts_default(mem_solve_opts_t* o) {
   o->fp64_pivot_ratio = 1e-6f;
   o->check_every = 2;
   o->refine = 3;
-  o->beta_max = 100.f;
+  o->beta_max = 25.f;
 }
 
 mem_err_t mem_create(const mem_config_t* cfg, mem_ctx_t* out) {

@@ -16,6 +16,7 @@
 //                  trial is one log-sum-exp pass (Sec. 3.1) over the nodes.
 // beta_0 is held at n, which zeroes G_0 and decouples H_00 = n^2/beta_0^2, so
 // the Newton system is the 34 x 34 covariance block.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -285,10 +286,14 @@ struct DirOut {
 //    targets lie outside the moment set of distributions on the nodes);
 //  * stall: the FP32 residual has not halved for STALL_WINDOW iterations (its
 //    rounding floor); with refinement on, such a cell -- like a converged one
-//    -- is handed to the compensated refinement, which decides the status.
+//    -- is handed to the compensated refinement, which decides the status;
+//  * no progress: a residual above STALL_GATE that has not halved for
+//    NOPROGRESS_WINDOW iterations ends the cell as stagnated (iterates that
+//    drift along a ray of the dual without reducing the residual).
 // Returns 1 when the cell stays live, 2 when it goes to refinement, 0 otherwise.
 constexpr int STALL_WINDOW = 6;
 constexpr float STALL_GATE = 1e-3f;
+constexpr int NOPROGRESS_WINDOW = 30;  // residual above the gate not halved: give up
 
 __device__ __forceinline__ int finish_cell(bool valid, int64_t cell, float r, float res,
                                            bool dir_ok, uint32_t extra, const SolveParams& p,
@@ -313,7 +318,8 @@ __device__ __forceinline__ int finish_cell(bool valid, int64_t cell, float r, fl
   else if (Lval[cell] < p.lmin || (p.beta_max > 0.f && bmax > p.beta_max))
     st |= MEM_ST_NONREALIZABLE;
   else if (!isfinite(r) || !dir_ok) st |= MEM_ST_NONFINITE;
-  else if (alpha_w[cell] <= p.alpha_min) st |= MEM_ST_STAGNATED;
+  else if (alpha_w[cell] <= p.alpha_min || it - itbest_w[cell] >= NOPROGRESS_WINDOW)
+    st |= MEM_ST_STAGNATED;
   else if (it >= p.max_iter) st |= MEM_ST_MAXITER;
   else done = false;
   status_w[cell] = st;
@@ -327,24 +333,99 @@ __device__ __forceinline__ int finish_cell(bool valid, int64_t cell, float r, fl
   return 1;
 }
 
-__device__ bool chol_upper_lds(float* sh, int t, float& dmin, float& dmax) {
-  dmin = FLT_MAX; dmax = 0.f;
-  for (int k = 0; k < NH; ++k) {
-    const float dk = sh[sw(hidx(k, k), t)];
-    if (!(dk > 0.f) || !isfinite(dk)) return false;
-    dmin = fminf(dmin, dk); dmax = fmaxf(dmax, dk);
-    const float ukk = sqrtf(dk), inv = 1.f / ukk;
-    sh[sw(hidx(k, k), t)] = ukk;
-    for (int j = k + 1; j < NH; ++j) sh[sw(hidx(k, j), t)] *= inv;
-    for (int i = k + 1; i < NH; ++i) {
-      const float uki = sh[sw(hidx(k, i), t)];
-      for (int j = i; j < NH; ++j) sh[sw(hidx(i, j), t)] -= uki * sh[sw(hidx(k, j), t)];
-    }
-  }
-  return true;
+// Wave-cooperative Cholesky for one cell per wave.  Lane j < 34 holds column
+// j of the SPD matrix in registers (a[i] = A[i][j]); step k broadcasts the
+// pivot and the k-th column of L with readlane and updates the trailing
+// columns.  On return lane i holds row i of L in lrow[] and its diagonal in
+// diag; for i > j, lane j's a[i] equals L[i][j] * L[j][j].
+__device__ __forceinline__ float rl(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double rl(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__global__ __launch_bounds__(64) void k_direction3(
+template <typename T>
+__device__ __forceinline__ bool wave_chol(T (&a)[NH], T (&lrow)[NH], T& diag, int lane, T& dmin,
+                                          T& dmax) {
+  bool ok = true;
+  dmin = (T)FLT_MAX; dmax = 0;
+  diag = 1;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const T d = rl(a[k], k);
+    ok = ok && (d > (T)0) && isfinite(d);
+    dmin = d < dmin ? d : dmin;
+    dmax = d > dmax ? d : dmax;
+    const T lkk = sqrt(d);
+    const T l = lane >= k ? a[k] / lkk : (T)0;  // L[lane][k]; lane k gets L[k][k]
+    lrow[k] = l;
+    if (lane == k) diag = lkk;
+    T lb[NH];
+#pragma unroll
+    for (int i = k + 1; i < NH; ++i) lb[i] = rl(l, i);
+#pragma unroll
+    for (int i = k + 1; i < NH; ++i)
+      if (lane > k) a[i] = fma(-lb[i], l, a[i]);
+  }
+  return ok;
+}
+
+// Forward L w = b, backward L^T d = w; lane i holds b_i and gets w_i, d_i.
+template <typename T>
+__device__ __forceinline__ void wave_solve(const T (&a)[NH], const T (&lrow)[NH], T diag,
+                                           int lane, T b, T& w, T& d) {
+  const T inv = (T)1 / diag;
+  T acc = b;
+  w = 0;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const T wk = rl(acc * inv, k);
+    if (lane == k) w = wk;
+    if (lane > k) acc = fma(-lrow[k], wk, acc);
+  }
+  T acc2 = w;
+  d = 0;
+#pragma unroll
+  for (int i = NH - 1; i >= 0; --i) {
+    const T di = rl(acc2 * inv, i);
+    if (lane == i) d = di;
+    if (lane < i) acc2 = fma(-a[i] * inv, di, acc2);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Column `lane` of H = S/s00 - E E^T (i, j >= 1), plus lam on the diagonal.
+template <typename T>
+__device__ __forceinline__ void load_hcol(const float* Sc, T inv0, const T* E, int lane, T lam,
+                                          T (&a)[NH]) {
+  const int j = lane < NH ? lane : 0;
+  const T ej = E[j + 1];
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    a[i] = (T)Sc[pair_col(lo + 1, hi + 1)] * inv0 - E[i + 1] * ej + (i == j ? lam : (T)0);
+  }
+}
+
+constexpr int DIR_WAVES = 4;  // cells (waves) per workgroup of the wave-per-cell kernels
+
+__global__ __launch_bounds__(256) void k_direction3(
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
     const float* __restrict__ S, const float* __restrict__ M, float* __restrict__ dbeta,
     float* __restrict__ gdot, float* __restrict__ alpha_w, int32_t* __restrict__ iters_w,
@@ -352,119 +433,61 @@ __global__ __launch_bounds__(64) void k_direction3(
     const float* __restrict__ Lval, float* __restrict__ rbest_w, int32_t* __restrict__ itbest_w,
     const float* __restrict__ beta, SolveParams p, int32_t* fb_list, int32_t* fb_ctr, DirOut o) {
   const int64_t count = *ctr;
-  const int64_t base = (int64_t)blockIdx.x * 64;
-  if (base >= count) return;
-  const int t = threadIdx.x;
-  const int64_t slot = base + t;
-  const bool valid = slot < count;
-  const int64_t cell = valid ? (int64_t)list[slot] : 0;
-
-  __shared__ float sh[HPACK * 64];
-  __shared__ float sv[NH * 64];
-  // coalesced transposed load of the pair columns (i, j >= 1) of the tile's cells
-  for (int c = 0; c < 64; ++c) {
-    if (base + c >= count) break;
-    const float* src = S + (int64_t)list[base + c] * NCOL + K3;
-    for (int e = t; e < HPACK; e += 64) sh[sw(e, c)] = src[e];
-  }
-  __syncthreads();
-
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + (threadIdx.x >> 6);
+  if (slot >= count) return;  // whole wave
+  const int64_t cell = list[slot];
   const float* Sc = S + cell * NCOL;
-  const float s00 = valid ? Sc[0] : 1.f;
+  const float s00 = Sc[0];
   const float inv0 = 1.f / s00;
-  for (int a = 0; a < NH; ++a) sv[sw(a, t)] = valid ? Sc[a + 1] * inv0 : 0.f;
-  // H = S/s00 - E E^T, and r = max |G|
-  for (int i = 0; i < NH; ++i) {
-    const float ei = sv[sw(i, t)];
-    for (int j = i; j < NH; ++j) {
-      float* h = &sh[sw(hidx(i, j), t)];
-      *h = valid ? (*h * inv0 - ei * sv[sw(j, t)]) : (i == j ? 1.f : 0.f);
-    }
-  }
+  __shared__ float sE[DIR_WAVES][K3 + 1];
+  float* E = sE[threadIdx.x >> 6];
+  if (lane < K3) E[lane] = lane == 0 ? 1.f : Sc[lane] * inv0;
+  __builtin_amdgcn_wave_barrier();
   const float* Mc = M + cell * K3;
-  const float nn = valid ? Mc[0] : 1.f;
-  float r = 0.f;
-  for (int a = 0; a < NH; ++a)
-    r = fmaxf(r, fabsf(valid ? sv[sw(a, t)] - Mc[a + 1] / nn : 0.f));
+  const float nn = Mc[0];
+  const float g = lane < NH ? E[lane + 1] - Mc[lane + 1] / nn : 0.f;
+  float r = wave_max(fabsf(g));
   if (!isfinite(s00) || !(s00 > 0.f)) r = NAN;
 
-  float dmin, dmax;
-  bool ok = chol_upper_lds(sh, t, dmin, dmax);
+  float a[NH], lrow[NH], diag, dmin, dmax;
+  load_hcol(Sc, inv0, E, lane, 0.f, a);
+  bool ok = wave_chol(a, lrow, diag, lane, dmin, dmax);
   bool to_fp64 = false;
   uint32_t extra = 0;
   if (p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
-    to_fp64 = valid && isfinite(r);
-  } else if (!ok && valid && isfinite(r)) {
-    // Alg. 1: Cholesky of H + lambda I, lambda = lambda0 * mul^m
-    float lam = p.lambda0;
+    to_fp64 = isfinite(r);
+  } else if (!ok && isfinite(r)) {
+    float lam = p.lambda0;  // Alg. 1: Cholesky of H + lambda I
     extra |= MEM_ST_SHIFTED;
     for (int tries = 0; tries < 40 && !ok; ++tries, lam *= p.lambda_mul) {
-      for (int i = 0; i < NH; ++i)
-        for (int j = i; j < NH; ++j) {
-          const float v = Sc[pair_col(i + 1, j + 1)] * inv0 - sv[sw(i, t)] * sv[sw(j, t)];
-          sh[sw(hidx(i, j), t)] = v + (i == j ? lam : 0.f);
-        }
-      ok = chol_upper_lds(sh, t, dmin, dmax);
+      load_hcol(Sc, inv0, E, lane, lam, a);
+      ok = wave_chol(a, lrow, diag, lane, dmin, dmax);
     }
   }
-  float res = 0.f;
-  bool fin = ok;
-  const bool solve = valid && ok && !to_fp64;
-  if (solve) {
-    // forward U^T w = -G (w overwrites E in sv), backward U d = w in place
-    for (int i = 0; i < NH; ++i) {
-      float acc = -(sv[sw(i, t)] - Mc[i + 1] / nn);
-      for (int k = 0; k < i; ++k) acc -= sh[sw(hidx(k, i), t)] * sv[sw(k, t)];
-      const float wi = acc / sh[sw(hidx(i, i), t)];
-      sv[sw(i, t)] = wi;
-      res += wi * wi;
-    }
-    res *= 0.5f;
-    for (int i = NH - 1; i >= 0; --i) {
-      float acc = sv[sw(i, t)];
-      for (int j = i + 1; j < NH; ++j) acc -= sh[sw(hidx(i, j), t)] * sv[sw(j, t)];
-      const float di = acc / sh[sw(hidx(i, i), t)];
-      sv[sw(i, t)] = di;
-      fin = fin && isfinite(di);
-    }
+  float w = 0.f, d = 0.f;
+  if (ok && !to_fp64) wave_solve(a, lrow, diag, lane, -g, w, d);
+  const float res = 0.5f * wave_sum(lane < NH ? w * w : 0.f);
+  const bool dfin = ok && __all(lane >= NH || isfinite(d));
+  int code = 0;
+  if (lane == 0) {
+    if (to_fp64) fb_list[atomicAdd(fb_ctr, 1)] = (int)cell;
+    else code = finish_cell(true, cell, r, res, dfin, extra, p, gdot, alpha_w, iters_w, status_w,
+                            resid_w, Lval, rbest_w, itbest_w, beta, o);
+    if (code == 1) o.next_list[atomicAdd(o.next_ctr, 1)] = (int)cell;
+    if (code == 2 && o.done_list) o.done_list[atomicAdd(o.done_ctr, 1)] = (int)cell;
   }
-  wave_append(to_fp64, (int)cell, fb_list, fb_ctr);
-  const int code = to_fp64 ? 0 : finish_cell(valid, cell, r, res, fin, extra, p, gdot, alpha_w,
-                                              iters_w, status_w, resid_w, Lval, rbest_w, itbest_w,
-                                              beta, o);
-  const bool live = code == 1;
-  if (o.done_list) wave_append(code == 2, (int)cell, o.done_list, o.done_ctr);
-  if (live) {
-    float* db = dbeta + cell * 36;
-    db[0] = 0.f;
-    for (int a = 0; a < NH; ++a) db[1 + a] = sv[sw(a, t)];
-  }
-  wave_append(live, (int)cell, o.next_list, o.next_ctr);
+  code = __shfl(code, 0);
+  if (code == 1 && lane == 0) dbeta[cell * 36] = 0.f;
+  if (code == 1 && lane < NH) dbeta[cell * 36 + 1 + lane] = d;
 }
 
 // --------------------------------------------------------------------------
 // Newton direction in FP64 for cells with a small FP32 pivot ratio
 // --------------------------------------------------------------------------
-// 32 cells per workgroup (threads 32..63 idle); element e of cell c at
-// e*32 + (c ^ (e & 15)) in doubles.
-__device__ __forceinline__ int swd(int e, int c) { return e * 32 + (c ^ (e & 15)); }
-
-__device__ bool chol_upper_lds_d(double* sh, int t) {
-  for (int k = 0; k < NH; ++k) {
-    const double dk = sh[swd(hidx(k, k), t)];
-    if (!(dk > 0.0) || !isfinite(dk)) return false;
-    const double ukk = sqrt(dk), inv = 1.0 / ukk;
-    sh[swd(hidx(k, k), t)] = ukk;
-    for (int j = k + 1; j < NH; ++j) sh[swd(hidx(k, j), t)] *= inv;
-    for (int i = k + 1; i < NH; ++i) {
-      const double uki = sh[swd(hidx(k, i), t)];
-      for (int j = i; j < NH; ++j) sh[swd(hidx(i, j), t)] -= uki * sh[swd(hidx(k, j), t)];
-    }
-  }
-  return true;
-}
-
-__global__ __launch_bounds__(64) void k_fallback3(
+// Same wave-per-cell scheme as k_direction3 with the Hessian formed and
+// factorised in double precision (lambda*I shift of Alg. 1 if it still fails).
+__global__ __launch_bounds__(256) void k_fallback3(
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
     const float* __restrict__ S, const float* __restrict__ M, float* __restrict__ dbeta,
     float* __restrict__ gdot, float* __restrict__ alpha_w, int32_t* __restrict__ iters_w,
@@ -472,70 +495,46 @@ __global__ __launch_bounds__(64) void k_fallback3(
     const float* __restrict__ Lval, float* __restrict__ rbest_w, int32_t* __restrict__ itbest_w,
     const float* __restrict__ beta, SolveParams p, DirOut o) {
   const int64_t count = *ctr;
-  const int64_t base = (int64_t)blockIdx.x * 32;
-  if (base >= count) return;
-  const int t = threadIdx.x;
-  const int64_t slot = base + t;
-  const bool valid = t < 32 && slot < count;
-  const int64_t cell = valid ? (int64_t)list[slot] : 0;
-  const int tt = t & 31;
-  __shared__ double sh[HPACK * 32];
-  __shared__ double sv[NH * 32];
-
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + (threadIdx.x >> 6);
+  if (slot >= count) return;
+  const int64_t cell = list[slot];
   const float* Sc = S + cell * NCOL;
+  const double inv0 = 1.0 / (double)Sc[0];
+  __shared__ double sE[DIR_WAVES][K3 + 1];
+  double* E = sE[threadIdx.x >> 6];
+  if (lane < K3) E[lane] = lane == 0 ? 1.0 : (double)Sc[lane] * inv0;
+  __builtin_amdgcn_wave_barrier();
   const float* Mc = M + cell * K3;
-  const double inv0 = valid ? 1.0 / (double)Sc[0] : 1.0;
-  const double nn = valid ? (double)Mc[0] : 1.0;
-  bool ok = false, fin = false;
-  float r = 0.f, res = 0.f;
+  const double nn = Mc[0];
+  const double g = lane < NH ? E[lane + 1] - (double)Mc[lane + 1] / nn : 0.0;
+  const float r = wave_max((float)fabs(g));
+  double a[NH], lrow[NH], diag, dmin, dmax;
   uint32_t extra = MEM_ST_FP64;
-  if (t < 32) {
-    for (int a = 0; a < NH; ++a) sv[swd(a, tt)] = valid ? (double)Sc[a + 1] * inv0 : 0.0;
-    for (int a = 0; a < NH; ++a)
-      r = fmaxf(r, fabsf(valid ? (float)(sv[swd(a, tt)] - (double)Mc[a + 1] / nn) : 0.f));
-    double lam = 0.0;
-    for (int tries = 0; tries < 41; ++tries) {
-      for (int i = 0; i < NH; ++i)
-        for (int j = i; j < NH; ++j) {
-          const double v = valid ? ((double)Sc[pair_col(i + 1, j + 1)] * inv0 - sv[swd(i, tt)] * sv[swd(j, tt)])
-                                 : (i == j ? 1.0 : 0.0);
-          sh[swd(hidx(i, j), tt)] = v + (i == j ? lam : 0.0);
-        }
-      ok = chol_upper_lds_d(sh, tt);
-      if (ok) break;
-      lam = (tries == 0) ? (double)p.lambda0 : lam * (double)p.lambda_mul;
+  double lam = 0.0;
+  bool ok = false;
+  for (int tries = 0; tries < 41 && !ok; ++tries) {
+    load_hcol(Sc, inv0, E, lane, lam, a);
+    ok = wave_chol(a, lrow, diag, lane, dmin, dmax);
+    if (!ok) {
+      lam = tries == 0 ? (double)p.lambda0 : lam * (double)p.lambda_mul;
       extra |= MEM_ST_SHIFTED;
     }
-    fin = ok;
-    if (ok && valid) {
-      double rs = 0.0;
-      for (int i = 0; i < NH; ++i) {
-        double acc = -(sv[swd(i, tt)] - (double)Mc[i + 1] / nn);
-        for (int k = 0; k < i; ++k) acc -= sh[swd(hidx(k, i), tt)] * sv[swd(k, tt)];
-        const double wi = acc / sh[swd(hidx(i, i), tt)];
-        sv[swd(i, tt)] = wi;
-        rs += wi * wi;
-      }
-      res = (float)(0.5 * rs);
-      for (int i = NH - 1; i >= 0; --i) {
-        double acc = sv[swd(i, tt)];
-        for (int j = i + 1; j < NH; ++j) acc -= sh[swd(hidx(i, j), tt)] * sv[swd(j, tt)];
-        const double di = acc / sh[swd(hidx(i, i), tt)];
-        sv[swd(i, tt)] = di;
-        fin = fin && isfinite(di);
-      }
-    }
   }
-  const int code = finish_cell(valid, cell, r, res, fin, extra, p, gdot, alpha_w, iters_w,
-                               status_w, resid_w, Lval, rbest_w, itbest_w, beta, o);
-  const bool live = code == 1;
-  if (o.done_list) wave_append(code == 2, (int)cell, o.done_list, o.done_ctr);
-  if (live) {
-    float* db = dbeta + cell * 36;
-    db[0] = 0.f;
-    for (int a = 0; a < NH; ++a) db[1 + a] = (float)sv[swd(a, tt)];
+  double w = 0.0, d = 0.0;
+  if (ok) wave_solve(a, lrow, diag, lane, -g, w, d);
+  const float res = (float)(0.5 * wave_sum(lane < NH ? w * w : 0.0));
+  const bool dfin = ok && __all(lane >= NH || isfinite(d));
+  int code = 0;
+  if (lane == 0) {
+    code = finish_cell(true, cell, r, res, dfin, extra, p, gdot, alpha_w, iters_w, status_w,
+                       resid_w, Lval, rbest_w, itbest_w, beta, o);
+    if (code == 1) o.next_list[atomicAdd(o.next_ctr, 1)] = (int)cell;
+    if (code == 2 && o.done_list) o.done_list[atomicAdd(o.done_ctr, 1)] = (int)cell;
   }
-  wave_append(live, (int)cell, o.next_list, o.next_ctr);
+  code = __shfl(code, 0);
+  if (code == 1 && lane == 0) dbeta[cell * 36] = 0.f;
+  if (code == 1 && lane < NH) dbeta[cell * 36 + 1 + lane] = (float)d;
 }
 
 // --------------------------------------------------------------------------
@@ -556,136 +555,132 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = (a - (s - z)) + (b - z);
 }
 
-__global__ __launch_bounds__(64) void k_accurate3(
+// One wave per cell; lane l takes nodes p0 + l of each 64-node chunk (tables
+// staged in LDS transposed, [k][node], so the lane reads are conflict-free);
+// beta is wave-uniform.  Per-lane compensated partial sums are combined across
+// the wave with TwoSum.
+__global__ __launch_bounds__(256) void k_accurate3(
     const float* __restrict__ tabHi, const float* __restrict__ tabLo, int Q,
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
     const float* __restrict__ M, const float* __restrict__ beta, const float* __restrict__ logZ,
     float* __restrict__ Eacc, float* __restrict__ racc, float tol, int32_t* out_list,
     int32_t* out_ctr) {
   const int64_t count = *ctr;
-  const int64_t base = (int64_t)blockIdx.x * 64;
-  if (base >= count) return;
-  const int t = threadIdx.x;
-  const int64_t slot = base + t;
+  const int64_t first = (int64_t)blockIdx.x * DIR_WAVES;
+  if (first >= count) return;  // whole workgroup
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = first + (threadIdx.x >> 6);
   const bool valid = slot < count;
-  const int64_t cell = valid ? (int64_t)list[slot] : 0;
+  const int64_t cell = valid ? (int64_t)list[slot] : (int64_t)list[first];
   float b[36];
 #pragma unroll
-  for (int k = 0; k < 36; ++k) b[k] = k == 0 ? 1.f : ((valid && k < K3) ? beta[cell * K3 + k] : 0.f);
-  const float lz = valid ? logZ[cell] : 0.f;
-  // moment sums with exact-product Kahan compensation
+  for (int k = 0; k < 36; ++k) b[k] = k == 0 ? 1.f : (k < K3 ? beta[cell * K3 + k] : 0.f);
+  const float lz = logZ[cell];
   float S[K3], Cc[K3];
 #pragma unroll
   for (int i = 0; i < K3; ++i) { S[i] = 0.f; Cc[i] = 0.f; }
-  __shared__ float sH[ACC_CH * 36], sL[ACC_CH * 36];
+  __shared__ float sH[36 * ACC_CH], sL[36 * ACC_CH];
   for (int p0 = 0; p0 < Q; p0 += ACC_CH) {
     const int np = min(ACC_CH, Q - p0);
     __syncthreads();
-    for (int i = t; i < np * 36; i += 64) {
-      sH[i] = tabHi[(size_t)p0 * 36 + i];
-      sL[i] = tabLo[(size_t)p0 * 36 + i];
+    for (int i = threadIdx.x; i < 36 * ACC_CH; i += 256) {
+      const int k = i / ACC_CH, q = i % ACC_CH;
+      const bool in = q < np;
+      sH[i] = in ? tabHi[(size_t)(p0 + q) * 36 + k] : 0.f;
+      sL[i] = in ? tabLo[(size_t)(p0 + q) * 36 + k] : 0.f;
     }
     __syncthreads();
-    for (int q = 0; q < np; ++q) {
-      const float* h = sH + q * 36;
-      const float* l = sL + q * 36;
-      // e - log Z as an unevaluated sum s + c (error-free products and sums)
-      float s = -lz, c = 0.f;
+    if (lane >= np) continue;
+    // e - log Z as an unevaluated sum s + c (error-free products and sums)
+    float s = -lz, c = 0.f;
 #pragma unroll
-      for (int k = 0; k < 36; ++k) {
-        const float pr = b[k] * h[k];
-        const float pe = fmaf(b[k], h[k], -pr);
-        float ns, se;
-        two_sum(s, pr, ns, se);
-        s = ns;
-        c += pe + se + b[k] * l[k];
-      }
-      if (s + c < -60.f) continue;  // weight below 1e-26: no measurable moment
-      const float ex = expf(s);     // accurate to ~1 ulp for any |s|
-      const float w = fmaf(ex, c, ex);
-      {  // phi_0 = 1 (column 0 of the table holds log w~, the exponent's constant)
-        const float y = w - Cc[0];
-        const float tt = S[0] + y;
-        Cc[0] = (tt - S[0]) - y;
-        S[0] = tt;
-      }
-#pragma unroll
-      for (int i = 1; i < K3; ++i) {
-        const float pr = w * h[i];
-        const float y = (pr - Cc[i]) + fmaf(w, h[i], -pr);
-        const float tt = S[i] + y;
-        Cc[i] = (tt - S[i]) - y;
-        S[i] = tt;
-      }
+    for (int k = 0; k < 36; ++k) {
+      const float h = sH[k * ACC_CH + lane];
+      const float pr = b[k] * h;
+      const float pe = fmaf(b[k], h, -pr);
+      float ns, se;
+      two_sum(s, pr, ns, se);
+      s = ns;
+      c += pe + se + b[k] * sL[k * ACC_CH + lane];
     }
-  }
-  float r = 0.f;
-  const float inv0 = 1.f / (S[0] - Cc[0]);
-  const float nn = valid ? M[cell * K3] : 1.f;
-  if (valid) {
-    Eacc[cell * 36] = 1.f;
+    if (s + c < -60.f) continue;  // weight below 1e-26: no measurable moment
+    const float ex = expf(s);     // accurate to ~1 ulp for any |s|
+    const float w = fmaf(ex, c, ex);
+    {  // phi_0 = 1 (column 0 of the table holds log w~)
+      const float y = w - Cc[0];
+      const float tt = S[0] + y;
+      Cc[0] = (tt - S[0]) - y;
+      S[0] = tt;
+    }
 #pragma unroll
     for (int i = 1; i < K3; ++i) {
-      const float e = (S[i] - Cc[i]) * inv0;
-      Eacc[cell * 36 + i] = e;
+      const float h = sH[i * ACC_CH + lane];
+      const float pr = w * h;
+      const float y = (pr - Cc[i]) + fmaf(w, h, -pr);
+      const float tt = S[i] + y;
+      Cc[i] = (tt - S[i]) - y;
+      S[i] = tt;
+    }
+  }
+  // combine the 64 lanes: value = S - Cc, summed with TwoSum at each level
+  float r = 0.f;
+  float tot[K3];
+#pragma unroll
+  for (int i = 0; i < K3; ++i) {
+    float hi = S[i], lo = -Cc[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float oh = __shfl_xor(hi, off), ol = __shfl_xor(lo, off);
+      float ns, se;
+      two_sum(hi, oh, ns, se);
+      hi = ns;
+      lo = lo + ol + se;
+    }
+    tot[i] = hi + lo;
+  }
+  if (valid) {
+    const float inv0 = 1.f / tot[0];
+    const float nn = M[cell * K3];
+#pragma unroll
+    for (int i = 1; i < K3; ++i) {
+      const float e = tot[i] * inv0;
+      if (lane == i) Eacc[cell * 36 + i] = e;
       r = fmaxf(r, fabsf(e - M[cell * K3 + i] / nn));
     }
-    racc[cell] = r;
+    if (lane == 0) {
+      Eacc[cell * 36] = 1.f;
+      racc[cell] = r;
+      if (!(r <= tol)) out_list[atomicAdd(out_ctr, 1)] = (int)cell;
+    }
   }
-  wave_append(valid && !(r <= tol), (int)cell, out_list, out_ctr);
 }
 
 // One Newton correction with the accurate gradient and the FP32 Hessian of
-// the cell's last assembly (same LDS layout as k_direction3).
-__global__ __launch_bounds__(64) void k_refine3(
+// the cell's last assembly (wave per cell, as k_direction3).
+__global__ __launch_bounds__(256) void k_refine3(
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
     const float* __restrict__ S, const float* __restrict__ M, const float* __restrict__ Eacc,
     float* __restrict__ beta) {
   const int64_t count = *ctr;
-  const int64_t base = (int64_t)blockIdx.x * 64;
-  if (base >= count) return;
-  const int t = threadIdx.x;
-  const int64_t slot = base + t;
-  const bool valid = slot < count;
-  const int64_t cell = valid ? (int64_t)list[slot] : 0;
-  __shared__ float sh[HPACK * 64];
-  __shared__ float sv[NH * 64];
-  for (int c = 0; c < 64; ++c) {
-    if (base + c >= count) break;
-    const float* src = S + (int64_t)list[base + c] * NCOL + K3;
-    for (int e = t; e < HPACK; e += 64) sh[sw(e, c)] = src[e];
-  }
-  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + (threadIdx.x >> 6);
+  if (slot >= count) return;
+  const int64_t cell = list[slot];
   const float* Sc = S + cell * NCOL;
-  const float inv0 = valid ? 1.f / Sc[0] : 1.f;
-  for (int a = 0; a < NH; ++a) sv[sw(a, t)] = valid ? Sc[a + 1] * inv0 : 0.f;
-  for (int i = 0; i < NH; ++i) {
-    const float ei = sv[sw(i, t)];
-    for (int j = i; j < NH; ++j) {
-      float* h = &sh[sw(hidx(i, j), t)];
-      *h = valid ? (*h * inv0 - ei * sv[sw(j, t)]) : (i == j ? 1.f : 0.f);
-    }
-  }
-  float dmin, dmax;
-  const bool ok = chol_upper_lds(sh, t, dmin, dmax);
-  if (!(valid && ok)) return;
+  const float inv0 = 1.f / Sc[0];
+  __shared__ float sE[DIR_WAVES][K3 + 1];
+  float* E = sE[threadIdx.x >> 6];
+  if (lane < K3) E[lane] = lane == 0 ? 1.f : Sc[lane] * inv0;
+  __builtin_amdgcn_wave_barrier();
+  float a[NH], lrow[NH], diag, dmin, dmax;
+  load_hcol(Sc, inv0, E, lane, 0.f, a);
+  const bool ok = wave_chol(a, lrow, diag, lane, dmin, dmax);
+  if (!ok) return;
   const float* Mc = M + cell * K3;
-  const float nn = Mc[0];
-  const float* Ea = Eacc + cell * 36;
-  for (int i = 0; i < NH; ++i) {
-    float acc = -(Ea[i + 1] - Mc[i + 1] / nn);
-    for (int k = 0; k < i; ++k) acc -= sh[sw(hidx(k, i), t)] * sv[sw(k, t)];
-    sv[sw(i, t)] = acc / sh[sw(hidx(i, i), t)];
-  }
-  for (int i = NH - 1; i >= 0; --i) {
-    float acc = sv[sw(i, t)];
-    for (int j = i + 1; j < NH; ++j) acc -= sh[sw(hidx(i, j), t)] * sv[sw(j, t)];
-    sv[sw(i, t)] = acc / sh[sw(hidx(i, i), t)];
-  }
-  bool fin = true;
-  for (int a = 0; a < NH; ++a) fin = fin && isfinite(sv[sw(a, t)]);
-  if (fin)
-    for (int a = 0; a < NH; ++a) beta[cell * K3 + 1 + a] += sv[sw(a, t)];
+  const float g = lane < NH ? Eacc[cell * 36 + 1 + lane] - Mc[lane + 1] / Mc[0] : 0.f;
+  float w, d;
+  wave_solve(a, lrow, diag, lane, -g, w, d);
+  if (__all(lane >= NH || isfinite(d)) && lane < NH) beta[cell * K3 + 1 + lane] += d;
 }
 
 // Final status and residual of refined cells.
@@ -773,7 +768,7 @@ hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
                              int32_t* done_list, int32_t* done_ctr, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
   DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
-  k_direction3<<<nblocks(grid_cells, 64), 64, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
+  k_direction3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
                                                       c->w_alpha, c->w_iters, c->w_status,
                                                       c->w_resid, c->w_L, c->w_rbest, c->w_itbest,
                                                       beta, p, fb_list, fb_ctr, o);
@@ -788,7 +783,7 @@ hipError_t launch_fallback3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
                             hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
   DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
-  k_fallback3<<<nblocks(grid_cells, 32), 64, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
+  k_fallback3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
                                                      c->w_alpha, c->w_iters, c->w_status,
                                                      c->w_resid, c->w_L, c->w_rbest, c->w_itbest,
                                                      beta, p, o);
@@ -799,7 +794,7 @@ hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
                            const float* M, const float* beta, float tol, int32_t* out_list,
                            int32_t* out_ctr, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  k_accurate3<<<nblocks(grid_cells, 64), 64, 0, s>>>(c->d_accHi, c->d_accLo, c->Q, list, ctr, M,
+  k_accurate3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(c->d_accHi, c->d_accLo, c->Q, list, ctr, M,
                                                      beta, c->w_logZ, c->w_Eacc, c->w_racc, tol,
                                                      out_list, out_ctr);
   return hipGetLastError();
@@ -808,7 +803,7 @@ hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
 hipError_t launch_refine3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
                           const float* M, float* beta, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  k_refine3<<<nblocks(grid_cells, 64), 64, 0, s>>>(list, ctr, c->w_S, M, c->w_Eacc, beta);
+  k_refine3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, M, c->w_Eacc, beta);
   return hipGetLastError();
 }
 
