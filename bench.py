@@ -29,7 +29,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "35-moment MaxEnt solves/s at rel. residual ≤1e-5, FP32 vs mixed; cell-steps/s"
-FP32_MFMA_PEAK_TFLOPS = 157.3
 MFMA_PEAK = {"fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}
 
 
@@ -55,6 +54,70 @@ def cpu_baseline(M, b0, n_sample):
                       f"Alg. 1 to max|G| <= 1e-10, {el:.1f} s wall"}
 
 
+def run_solves(mem, ctx, Md, b0d, steps, warmup):
+    """Time `steps` cold-start solves of the resident batch; kernel times live."""
+    import torch
+    C = Md.shape[0]
+    bg = torch.empty_like(b0d)
+    iters = torch.zeros(C, dtype=torch.int32, device=Md.device)
+    resid = torch.zeros(C, dtype=torch.float32, device=Md.device)
+    status = torch.zeros(C, dtype=torch.int32, device=Md.device)
+    opts = mem.default_opts()
+    for _ in range(warmup):
+        bg.copy_(b0d)
+        ctx.solve(Md, bg, opts, iters, resid, status)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bg.copy_(b0d)
+        ctx.solve(Md, bg, opts, iters, resid, status)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = status.cpu().numpy()
+    rs = resid.cpu().numpy()
+    it = iters.cpu().numpy()
+    ok = ((st & mem.ST_CONVERGED) != 0) & (rs <= 1e-5)
+    prof = {k: ctx.profile_read(k) for k in ("assemble", "direction", "lse")}
+    ctx.profile(False)
+    asm_ms, asm_n = prof["assemble"]
+    total_flop = 2.0 * 1728 * 630 * float(it.sum()) * steps
+    return dict(
+        value=int(ok.sum()) * steps / elapsed, ms=1e3 * elapsed / steps, ok=ok, it=it, st=st,
+        asm_tflops=total_flop / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0,
+        asm_launches=asm_n, asm_avg_ms=asm_ms / max(asm_n, 1),
+        kernel_ms={k: v[0] / steps for k, v in prof.items()})
+
+
+def mixed_comparison(mem, torch, dev, cells, steps, warmup):
+    """FP32 vs BF16x3 vs FP16x3 on the Mach 5-10 Mott-Smith workload."""
+    import mem_inputs
+    ms = mem_inputs.mott_smith_cells(cells, 5.0, 10.0, config=4, replica=0)
+    M32 = ms["M"].astype(np.float32)
+    b032 = mem_inputs.maxwellian_beta(cells, 35, M32[:, 0].astype(np.float64)).astype(np.float32)
+    Md = torch.tensor(M32, device=dev)
+    b0d = torch.tensor(b032, device=dev)
+    out = {"workload": f"3D 35-moment MaxEnt dual solve, {cells} Mott-Smith cells "
+                       "(Mach U(5,10), nu U(0,1)), 12^3 nodes, cold start",
+           "cells": cells}
+    base = None
+    for prec in ("fp32", "bf16x3", "fp16x3"):
+        ctx = mem.Context(3, 12, prec)
+        ctx.reserve(cells)
+        r = run_solves(mem, ctx, Md, b0d, steps, warmup)
+        ctx.close()
+        if base is None:
+            base = r["value"]
+        out[prec] = {"solves_per_s": r["value"], "ms_per_solve": r["ms"],
+                     "speedup_vs_fp32": r["value"] / base if base else None,
+                     "converged_fraction": float(r["ok"].mean()),
+                     "iterations_mean": float(r["it"].mean()), "iterations_max": int(r["it"].max()),
+                     "assemble_ms_per_solve": r["kernel_ms"]["assemble"],
+                     "assemble_algorithmic_tflops": r["asm_tflops"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +127,8 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--cpu-sample", type=int, default=6144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-cells", type=int, default=262144,
+                    help="cells of the FP32-vs-mixed comparison (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -85,53 +150,18 @@ def main():
     ctx.reserve(C)
     Md = torch.tensor(M32, device=dev)
     b0d = torch.tensor(b032, device=dev)
-    bg = torch.empty_like(b0d)
-    iters = torch.zeros(C, dtype=torch.int32, device=dev)
-    resid = torch.zeros(C, dtype=torch.float32, device=dev)
-    status = torch.zeros(C, dtype=torch.int32, device=dev)
-    opts = mem.default_opts()
-
-    for _ in range(args.warmup):
-        bg.copy_(b0d)
-        ctx.solve(Md, bg, opts, iters, resid, status)
-    torch.cuda.synchronize()
-
-    ctx.profile(True)
-    it_total = 0
-    n_ok = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        bg.copy_(b0d)
-        ctx.solve(Md, bg, opts, iters, resid, status)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    st = status.cpu().numpy()
-    rs = resid.cpu().numpy()
-    it = iters.cpu().numpy()
-    ok = ((st & mem.ST_CONVERGED) != 0) & (rs <= 1e-5)
-    n_ok = int(ok.sum())
-    it_total = int(it.sum()) * args.steps
-    asm_ms, asm_n = ctx.profile_read("assemble")
-    dir_ms, dir_n = ctx.profile_read("direction")
-    lse_ms, lse_n = ctx.profile_read("lse")
-    ctx.profile(False)
-
-    Q = 1728
-    flop_per_row = 2.0 * Q * 630          # assembly GEMM per cell-iteration
-    total_flop = flop_per_row * it_total
-    achieved = total_flop / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0
+    r = run_solves(mem, ctx, Md, b0d, args.steps, args.warmup)
+    ctx.close()
     peak = MFMA_PEAK[args.prec]
-    value = n_ok * args.steps / elapsed
 
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": r["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": r["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -141,33 +171,35 @@ def main():
             "workload": f"3D 35-moment MaxEnt dual solve, {C} Mott-Smith cells "
                         "(Mach U(1.5,10), nu U(0,1), gamma 5/3), 12^3 Gauss-Hermite nodes, "
                         "cold start from the Maxwellian, Alg. 1 to max|G|<=2e-6",
-            "cells": C, "nodes": Q, "basis": 35, "prec": args.prec,
+            "cells": C, "nodes": 1728, "basis": 35, "prec": args.prec,
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_assemble3 (sigma . Psi, 630 pair columns)",
-            "achieved": achieved,
+            "kernel": "k_assemble3 (sigma . Psi, 630 pair columns)" if args.prec == "fp32"
+                      else "k_assemble3m (sigma . Psi, hi+lo 16-bit products)",
+            "achieved": r["asm_tflops"],
             "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / peak,
+            "frac": r["asm_tflops"] / peak,
             "traffic": None,
-            "flop_per_cell_iteration": flop_per_row,
-            "launches": asm_n,
-            "avg_launch_ms": asm_ms / max(asm_n, 1),
+            "flop_per_cell_iteration": 2.0 * 1728 * 630,
+            "launches": r["asm_launches"],
+            "avg_launch_ms": r["asm_avg_ms"],
         },
         "solver": {
-            "converged_fraction": float(ok.mean()),
-            "iterations_mean": float(it.mean()),
-            "iterations_max": int(it.max()),
-            "fp64_direction_fraction": float(np.mean((st & mem.ST_FP64) != 0)),
-            "kernel_ms_per_step": {"assemble": asm_ms / args.steps,
-                                   "direction": dir_ms / args.steps,
-                                   "lse_linesearch": lse_ms / args.steps},
+            "converged_fraction": float(r["ok"].mean()),
+            "iterations_mean": float(r["it"].mean()),
+            "iterations_max": int(r["it"].max()),
+            "fp64_direction_fraction": float(np.mean((r["st"] & mem.ST_FP64) != 0)),
+            "kernel_ms_per_step": {"assemble": r["kernel_ms"]["assemble"],
+                                   "direction": r["kernel_ms"]["direction"],
+                                   "lse_linesearch": r["kernel_ms"]["lse"]},
         },
     }
+    if args.mixed_cells > 0:
+        line["mixed"] = mixed_comparison(mem, torch, dev, args.mixed_cells, 3, 1)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(M32, b032, args.cpu_sample)
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

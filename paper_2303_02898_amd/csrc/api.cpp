@@ -40,7 +40,7 @@ void free_workspace(mem_ctx_t c) {
   dfree(c->w_alpha); dfree(c->w_gdot); dfree(c->w_resid); dfree(c->w_iters);
   dfree(c->w_status);
   for (auto& l : c->w_list) dfree(l);
-  dfree(c->w_Eacc); dfree(c->w_racc); dfree(c->w_rbest); dfree(c->w_itbest);
+  dfree(c->w_Gacc); dfree(c->w_racc); dfree(c->w_rbest); dfree(c->w_itbest);
   dfree(c->w_Mnew); dfree(c->w_F); dfree(c->w_rho); dfree(c->w_prob);
   c->cap_cells = 0;
 }
@@ -127,7 +127,10 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
     const int nxt = 1 - cur;
     {
       ProfScope ps(c, 0, s);
-      MEM_HIP(c, launch_assemble3(c, grid, c->w_list[cur], &ctr[cur], n, beta, c->d_psi, c->w_S, s));
+      if (c->prec == MEM_PREC_FP32)
+        MEM_HIP(c, launch_assemble3(c, grid, c->w_list[cur], &ctr[cur], n, beta, c->d_psi, c->w_S, s));
+      else
+        MEM_HIP(c, launch_assemble3m(c, grid, c->w_list[cur], &ctr[cur], n, beta, c->w_S, s));
     }
     {
       ProfScope ps(c, 1, s);
@@ -242,7 +245,7 @@ mem_err_t mem_destroy(mem_ctx_t c) {
   free_problems(c);
   dfree(c->d_phiA); dfree(c->d_psi); dfree(c->d_psix); dfree(c->d_tab1);
   dfree(c->d_accHi); dfree(c->d_accLo);
-  dfree(c->d_psi_hi); dfree(c->d_psi_lo); dfree(c->d_colscale);
+  dfree(c->d_psi_hi); dfree(c->d_psi_lo); dfree(c->d_phiA_m); dfree(c->d_psiF_m);
   dfree(c->w_ctr);
   if (c->h_ctr) (void)hipHostFree(c->h_ctr);
   for (auto& ev : c->prof_pool) (void)hipEventDestroy(ev);
@@ -262,7 +265,7 @@ mem_err_t mem_reserve(mem_ctx_t c, int64_t max_cells, int32_t max_problems) {
               dalloc(c->w_logZ, n) && dalloc(c->w_L, n) && dalloc(c->w_alpha, n) &&
               dalloc(c->w_gdot, n) && dalloc(c->w_resid, n) && dalloc(c->w_iters, n) &&
               dalloc(c->w_status, n) && dalloc(c->w_list[0], n) && dalloc(c->w_list[1], n) &&
-              dalloc(c->w_list[2], n) && dalloc(c->w_list[3], n) && dalloc(c->w_Eacc, n * 36) &&
+              dalloc(c->w_list[2], n) && dalloc(c->w_list[3], n) && dalloc(c->w_Gacc, n * 36) &&
               dalloc(c->w_racc, n) && dalloc(c->w_rbest, n) && dalloc(c->w_itbest, n) &&
               dalloc(c->w_Mnew, n * K3) && dalloc(c->w_F, n * K3) &&
               dalloc(c->w_rho, n) && dalloc(c->w_prob, n);
@@ -331,7 +334,6 @@ mem_err_t mem_maxent_solve(mem_ctx_t c, int64_t n, const float* M, float* beta,
     MEM_HIP(c, launch_solve1(c, n, M, beta, p, iters, resid, status, s));
     return MEM_OK;
   }
-  if (c->prec != MEM_PREC_FP32) return fail(c, MEM_ERR_UNSUPPORTED, "mixed precision not built");
   mem_err_t e = ensure_cells(c, n);
   if (e != MEM_OK) return e;
   mem_solve_opts_t d;
@@ -353,7 +355,10 @@ mem_err_t mem_dual(mem_ctx_t c, int64_t n, const float* beta, float* logZ, float
   SolveParams p = params_from(nullptr);
   float* b = const_cast<float*>(beta);
   MEM_HIP(c, launch_lse3(c, n, nullptr, nullptr, n, nullptr, b, false, p, nullptr, nullptr, s));
-  MEM_HIP(c, launch_assemble3(c, n, nullptr, nullptr, n, beta, c->d_psi, c->w_S, s));
+  if (c->prec == MEM_PREC_FP32)
+    MEM_HIP(c, launch_assemble3(c, n, nullptr, nullptr, n, beta, c->d_psi, c->w_S, s));
+  else
+    MEM_HIP(c, launch_assemble3m(c, n, nullptr, nullptr, n, beta, c->w_S, s));
   if (logZ) MEM_HIP(c, launch_copy(n, c->w_logZ, logZ, s));
   if (E || H) MEM_HIP(c, launch_unpack3(c, n, E, H, s));
   return MEM_OK;

@@ -549,7 +549,11 @@ __global__ __launch_bounds__(256) void k_fallback3(
 // iterative refinement, all in FP32 operations.
 constexpr int ACC_CH = 64;  // nodes per LDS chunk
 
+// Error-free transformations need every product and sum rounded on its own:
+// FP contraction (fusing a*b + c into one fma) is switched off where they are
+// used, or the product errors would be counted twice.
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
   s = a + b;
   const float z = s - a;
   e = (a - (s - z)) + (b - z);
@@ -563,8 +567,9 @@ __global__ __launch_bounds__(256) void k_accurate3(
     const float* __restrict__ tabHi, const float* __restrict__ tabLo, int Q,
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
     const float* __restrict__ M, const float* __restrict__ beta, const float* __restrict__ logZ,
-    float* __restrict__ Eacc, float* __restrict__ racc, float tol, int32_t* out_list,
+    float* __restrict__ Gacc, float* __restrict__ racc, float tol, int32_t* out_list,
     int32_t* out_ctr) {
+#pragma clang fp contract(off)
   const int64_t count = *ctr;
   const int64_t first = (int64_t)blockIdx.x * DIR_WAVES;
   if (first >= count) return;  // whole workgroup
@@ -616,15 +621,15 @@ __global__ __launch_bounds__(256) void k_accurate3(
     for (int i = 1; i < K3; ++i) {
       const float h = sH[i * ACC_CH + lane];
       const float pr = w * h;
-      const float y = (pr - Cc[i]) + fmaf(w, h, -pr);
+      const float y = (pr - Cc[i]) + (fmaf(w, h, -pr) + w * sL[i * ACC_CH + lane]);
       const float tt = S[i] + y;
       Cc[i] = (tt - S[i]) - y;
       S[i] = tt;
     }
   }
-  // combine the 64 lanes: value = S - Cc, summed with TwoSum at each level
-  float r = 0.f;
-  float tot[K3];
+  // combine the 64 lanes: value = S - Cc, summed with TwoSum at each level and
+  // kept as an unevaluated pair (th, tl)
+  float th[K3], tl[K3];
 #pragma unroll
   for (int i = 0; i < K3; ++i) {
     float hi = S[i], lo = -Cc[i];
@@ -636,19 +641,31 @@ __global__ __launch_bounds__(256) void k_accurate3(
       hi = ns;
       lo = lo + ol + se;
     }
-    tot[i] = hi + lo;
+    th[i] = hi;
+    tl[i] = lo;
   }
   if (valid) {
-    const float inv0 = 1.f / tot[0];
+    // G_i = T_i / T_0 - M_i / n without rounding either quotient to FP32 first:
+    // each quotient is q1 + q2 with q2 from the exact remainder (fma), so G is
+    // resolved far below one ulp of the moments themselves
+    const float h0 = th[0], l0 = tl[0];
+    const float inv0 = 1.f / h0;
     const float nn = M[cell * K3];
+    const float rn = 1.f / nn;
+    float r = 0.f;
 #pragma unroll
     for (int i = 1; i < K3; ++i) {
-      const float e = tot[i] * inv0;
-      if (lane == i) Eacc[cell * 36 + i] = e;
-      r = fmaxf(r, fabsf(e - M[cell * K3 + i] / nn));
+      const float e1 = th[i] * inv0;
+      const float e2 = (fmaf(-e1, h0, th[i]) + (tl[i] - e1 * l0)) * inv0;
+      const float mi = M[cell * K3 + i];
+      const float m1 = mi / nn;
+      const float m2 = fmaf(-m1, nn, mi) * rn;
+      const float g = (e1 - m1) + (e2 - m2);
+      if (lane == i) Gacc[cell * 36 + i] = g;
+      r = fmaxf(r, fabsf(g));
     }
     if (lane == 0) {
-      Eacc[cell * 36] = 1.f;
+      Gacc[cell * 36] = 0.f;
       racc[cell] = r;
       if (!(r <= tol)) out_list[atomicAdd(out_ctr, 1)] = (int)cell;
     }
@@ -659,8 +676,7 @@ __global__ __launch_bounds__(256) void k_accurate3(
 // the cell's last assembly (wave per cell, as k_direction3).
 __global__ __launch_bounds__(256) void k_refine3(
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
-    const float* __restrict__ S, const float* __restrict__ M, const float* __restrict__ Eacc,
-    float* __restrict__ beta) {
+    const float* __restrict__ S, const float* __restrict__ Gacc, float* __restrict__ beta) {
   const int64_t count = *ctr;
   const int lane = threadIdx.x & 63;
   const int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + (threadIdx.x >> 6);
@@ -676,8 +692,7 @@ __global__ __launch_bounds__(256) void k_refine3(
   load_hcol(Sc, inv0, E, lane, 0.f, a);
   const bool ok = wave_chol(a, lrow, diag, lane, dmin, dmax);
   if (!ok) return;
-  const float* Mc = M + cell * K3;
-  const float g = lane < NH ? Eacc[cell * 36 + 1 + lane] - Mc[lane + 1] / Mc[0] : 0.f;
+  const float g = lane < NH ? Gacc[cell * 36 + 1 + lane] : 0.f;
   float w, d;
   wave_solve(a, lrow, diag, lane, -g, w, d);
   if (__all(lane >= NH || isfinite(d)) && lane < NH) beta[cell * K3 + 1 + lane] += d;
@@ -795,7 +810,7 @@ hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
                            int32_t* out_ctr, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
   k_accurate3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(c->d_accHi, c->d_accLo, c->Q, list, ctr, M,
-                                                     beta, c->w_logZ, c->w_Eacc, c->w_racc, tol,
+                                                     beta, c->w_logZ, c->w_Gacc, c->w_racc, tol,
                                                      out_list, out_ctr);
   return hipGetLastError();
 }
@@ -803,7 +818,7 @@ hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
 hipError_t launch_refine3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
                           const float* M, float* beta, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  k_refine3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, M, c->w_Eacc, beta);
+  k_refine3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, c->w_Gacc, beta);
   return hipGetLastError();
 }
 

@@ -56,9 +56,12 @@ struct mem_ctx_s {
   float* d_phiA = nullptr;   // exponent A operand  [ngroups][NJ][64]
   float* d_psi = nullptr;    // assembly B operand  [ngroups][4][10][64][4]
   float* d_psix = nullptr;   // flux-Jacobian B operand, same layout
-  void* d_psi_hi = nullptr;  // mixed precision B operands (16-bit), see kernels
-  void* d_psi_lo = nullptr;
-  float* d_colscale = nullptr;  // per-column power-of-two scale for FP16 tables
+  // mixed precision (BF16 / FP16 hi + lo) assembly operands, 32-node groups
+  int nsg_m = 0;              // node groups of 32 (nodes padded with zero weight)
+  float* d_phiA_m = nullptr;  // exponent A operand [2*nsg_m][NJ][64] (FP16: log w~ + k_p ln 2)
+  float* d_psiF_m = nullptr;  // FP32 B operand of the 4 moment blocks [nsg_m][4][64][8]
+  void* d_psi_hi = nullptr;   // 16-bit B operand, high part [nsg_m][36][64][8]
+  void* d_psi_lo = nullptr;   // 16-bit B operand, low part
   float* d_accHi = nullptr;  // [Qpad][36] (log w~, phi_1..phi_34, 0), FP32 high part
   float* d_accLo = nullptr;  // [Qpad][36] FP32 low part (table - high part)
   // device tables, 1D
@@ -78,7 +81,7 @@ struct mem_ctx_s {
   uint32_t* w_status = nullptr;
   int32_t* w_list[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t* w_ctr = nullptr;   // [8] list counters
-  float* w_Eacc = nullptr;    // [cap][36] compensated moments
+  float* w_Gacc = nullptr;    // [cap][36] compensated gradient E[phi_i] - M_i/n
   float* w_racc = nullptr;    // [cap] compensated residual
   float* w_rbest = nullptr;   // [cap] best FP32 residual so far (stall test)
   int32_t* w_itbest = nullptr;// [cap] iteration of the last halving of the residual
@@ -125,6 +128,11 @@ hipError_t launch_lse3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
 hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                             const int32_t* ctr, int64_t n, const float* beta,
                             const float* table, float* S, hipStream_t s);
+// Mixed-precision variant of launch_assemble3 (the context's precision
+// selects BF16 or FP16); always the plain pair table Psi.
+hipError_t launch_assemble3m(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                             const int32_t* ctr, int64_t n, const float* beta, float* S,
+                             hipStream_t s);
 hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                              const int32_t* ctr, const float* M, const float* beta,
                              const SolveParams& p,

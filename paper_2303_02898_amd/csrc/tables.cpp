@@ -91,6 +91,21 @@ void multi_indices(int dim, std::vector<int>& a, std::vector<int>& b, std::vecto
   }
 }
 
+// bfloat16 = the high 16 bits of an IEEE binary32, rounded to nearest even
+// (finite inputs only).
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 template <typename T>
 T* upload(const std::vector<T>& h) {
   T* d = nullptr;
@@ -129,6 +144,67 @@ void build_host(int dim, int n, std::vector<double>& nodes, std::vector<double>&
     ortho_hermite(4, uz, pz.data());
     for (int k = 0; k < K; ++k) phi[(size_t)p * K + k] = px[ia[k]] * py[ib[k]] * pz[ic[k]];
   }
+}
+
+// Operands of the mixed-precision assembly (k_mixed3.hip) in 32-node groups.
+// For node group s, k-slot i (0..7) of lane l stands for node
+//   32 s + 16 (i / 4) + 4 (l / 16) + i % 4,
+// the order in which the exponent MFMA leaves sigma in a lane's registers.
+// FP16 tables carry a per-node power-of-two scale: log w~_p + k_p ln 2 in the
+// exponent table and Psi 2^-k_p, with k_p = min(15, floor(-log2 w_p)), so that
+// sigma 2^k_p <= 2^15 and the tail nodes' large Psi values shrink.
+template <typename PhiE, typename Psi>
+void build_mixed(mem_ctx_t ctx, const PhiE& phiE, const Psi& psi) {
+  using namespace memk;
+  const int Q = ctx->Q;
+  const int nsg = (Q + 31) / 32;
+  const bool f16 = ctx->prec == MEM_PREC_FP16X3;
+  ctx->nsg_m = nsg;
+  std::vector<int> ks((size_t)nsg * 32, 0);
+  if (f16)
+    for (int p = 0; p < Q; ++p) {
+      const int k = (int)std::floor(-std::log2(ctx->h_w[p]));
+      ks[p] = k < 0 ? 0 : (k > 15 ? 15 : k);
+    }
+  std::vector<float> A((size_t)2 * nsg * NJ * 64);
+  for (int g = 0; g < 2 * nsg; ++g)
+    for (int j = 0; j < NJ; ++j)
+      for (int l = 0; l < 64; ++l) {
+        const int p = GRP * g + (l & 15), k = 4 * j + (l >> 4);
+        double v = phiE(p, k);
+        if (k == 0 && p < Q) v += ks[p] * std::log(2.0);
+        A[((size_t)g * NJ + j) * 64 + l] = (float)v;
+      }
+  auto node = [](int s, int l, int i) { return 32 * s + 16 * (i >> 2) + 4 * (l >> 4) + (i & 3); };
+  std::vector<float> F((size_t)nsg * 4 * 64 * 8);
+  std::vector<uint16_t> Hh((size_t)nsg * 36 * 64 * 8), Hl(Hh.size());
+  for (int s = 0; s < nsg; ++s)
+    for (int l = 0; l < 64; ++l)
+      for (int i = 0; i < 8; ++i) {
+        const int p = node(s, l, i);
+        const double sc = std::ldexp(1.0, -ks[p]);
+        for (int b = 0; b < 4; ++b)
+          F[(((size_t)s * 4 + b) * 64 + l) * 8 + i] = (float)(psi(p, 16 * b + (l & 15), false) * sc);
+        for (int b = 4; b < NBLK; ++b) {
+          const double v = psi(p, 16 * b + (l & 15), false) * sc;
+          const size_t o = (((size_t)s * 36 + (b - 4)) * 64 + l) * 8 + i;
+          if (f16) {
+            const _Float16 h = (_Float16)(float)v;
+            const _Float16 lo = (_Float16)(float)(v - (double)(float)h);
+            Hh[o] = __builtin_bit_cast(uint16_t, h);
+            Hl[o] = __builtin_bit_cast(uint16_t, lo);
+          } else {
+            const uint16_t h = bf16_bits((float)v);
+            const uint16_t lo = bf16_bits((float)(v - (double)bf16_value(h)));
+            Hh[o] = h;
+            Hl[o] = lo;
+          }
+        }
+      }
+  ctx->d_phiA_m = upload(A);
+  ctx->d_psiF_m = upload(F);
+  ctx->d_psi_hi = upload(Hh);
+  ctx->d_psi_lo = upload(Hl);
 }
 
 void build_tables(mem_ctx_t ctx) {
@@ -205,6 +281,7 @@ void build_tables(mem_ctx_t ctx) {
           }
   ctx->d_psi = upload(B);
   ctx->d_psix = upload(BX);
+  if (ctx->prec != MEM_PREC_FP32) build_mixed(ctx, phiE, psi);
 }
 
 }  // namespace memt

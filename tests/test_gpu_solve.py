@@ -126,6 +126,13 @@ def test_solve_mott_smith_matches_oracle(ctx3, rule3):
     assert r[conv[good]].max() <= 1.0
     assert berr.max() <= 1e-4
     assert np.all(resid.cpu().numpy()[conv] <= 1e-5)
+    # the reported residual (compensated FP32) agrees with the FP64 residual
+    sel = good & conv
+    r64 = maxent.moment_residual(bg.cpu().numpy().astype(np.float64)[sel], M[sel], rule3["Phi"],
+                                 rule3["logw"])
+    dr = np.abs(resid.cpu().numpy()[sel] - r64)
+    print(f"[mott-smith] |resid - r_fp64| max {dr.max():.2e}")
+    assert np.all(dr <= 2e-7 + 0.01 * r64)
     it = iters.cpu().numpy()
     print(f"[mott-smith] iterations min {it.min()} median {np.median(it)} max {it.max()}")
 
