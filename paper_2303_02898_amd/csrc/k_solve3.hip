@@ -295,30 +295,59 @@ constexpr int STALL_WINDOW = 6;
 constexpr float STALL_GATE = 1e-3f;
 constexpr int NOPROGRESS_WINDOW = 30;  // residual above the gate not halved: give up
 
-__device__ __forceinline__ int finish_cell(bool valid, int64_t cell, float r, float res,
-                                           bool dir_ok, uint32_t extra, const SolveParams& p,
-                                           float* gdot, float* alpha_w, int32_t* iters_w,
-                                           uint32_t* status_w, float* resid_w,
-                                           const float* Lval, float* rbest_w, int32_t* itbest_w,
-                                           const float* beta, const DirOut& o) {
-  if (!valid) return 0;
-  float bmax = 0.f;
-  for (int k = 1; k < K3; ++k) bmax = fmaxf(bmax, fabsf(beta[cell * K3 + k]));
-  const int it = iters_w[cell] + 1;
+// Per-cell Newton state, read at kernel entry so that its latency hides
+// behind the factorisation.  bmax = max_{i>=1} |beta_i| (wave reduction).
+struct CellState {
+  int it, itbest;
+  uint32_t st;
+  float rbest, alpha, L, bmax;
+};
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+__device__ __forceinline__ CellState load_state(int64_t cell, int lane, const int32_t* iters_w,
+                                                const uint32_t* status_w, const float* rbest_w,
+                                                const int32_t* itbest_w, const float* alpha_w,
+                                                const float* Lval, const float* beta) {
+  // wave-uniform values: keep them in scalar registers
+  auto ui = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+  auto uf = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+  CellState cs;
+  cs.it = ui(iters_w[cell]);
+  cs.itbest = ui(itbest_w[cell]);
+  cs.st = (uint32_t)ui((int)status_w[cell]);
+  cs.rbest = uf(rbest_w[cell]);
+  cs.alpha = uf(alpha_w[cell]);
+  cs.L = uf(Lval[cell]);
+  cs.bmax = uf(wave_max(lane >= 1 && lane < K3 ? fabsf(beta[cell * K3 + lane]) : 0.f));
+  return cs;
+}
+
+__device__ __forceinline__ int finish_cell(int64_t cell, float r, float res, bool dir_ok,
+                                           uint32_t extra, const SolveParams& p,
+                                           const CellState& cs, float* gdot, int32_t* iters_w,
+                                           uint32_t* status_w, float* resid_w, float* rbest_w,
+                                           int32_t* itbest_w, const DirOut& o) {
+  const int it = cs.it + 1;
   iters_w[cell] = it;
-  uint32_t st = status_w[cell] | extra;
+  uint32_t st = cs.st | extra;
   resid_w[cell] = r;
-  if (r < 0.5f * rbest_w[cell]) { rbest_w[cell] = r; itbest_w[cell] = it; }
+  int itbest = cs.itbest;
+  if (r < 0.5f * cs.rbest) { rbest_w[cell] = r; itbest_w[cell] = it; itbest = it; }
   const bool conv = (r <= p.tol_grad) || (res <= p.tol_dec && r <= p.tol_loose);
   const bool near = r <= STALL_GATE && p.refine > 0;
-  const bool stall = near && (it - itbest_w[cell] >= STALL_WINDOW || alpha_w[cell] <= p.alpha_min ||
+  const bool stall = near && (it - itbest >= STALL_WINDOW || cs.alpha <= p.alpha_min ||
                               it >= p.max_iter);
   bool done = true, cand = false;
   if (conv || stall) { st |= MEM_ST_CONVERGED; cand = p.refine > 0; }
-  else if (Lval[cell] < p.lmin || (p.beta_max > 0.f && bmax > p.beta_max))
+  else if (cs.L < p.lmin || (p.beta_max > 0.f && cs.bmax > p.beta_max))
     st |= MEM_ST_NONREALIZABLE;
   else if (!isfinite(r) || !dir_ok) st |= MEM_ST_NONFINITE;
-  else if (alpha_w[cell] <= p.alpha_min || it - itbest_w[cell] >= NOPROGRESS_WINDOW)
+  else if (cs.alpha <= p.alpha_min || it - itbest >= NOPROGRESS_WINDOW)
     st |= MEM_ST_STAGNATED;
   else if (it >= p.max_iter) st |= MEM_ST_MAXITER;
   else done = false;
@@ -336,8 +365,8 @@ __device__ __forceinline__ int finish_cell(bool valid, int64_t cell, float r, fl
 // Wave-cooperative Cholesky for one cell per wave.  Lane j < 34 holds column
 // j of the SPD matrix in registers (a[i] = A[i][j]); step k broadcasts the
 // pivot and the k-th column of L with readlane and updates the trailing
-// columns.  On return lane i holds row i of L in lrow[] and its diagonal in
-// diag; for i > j, lane j's a[i] equals L[i][j] * L[j][j].
+// columns.  On return lane i holds row i of L in lrow[] and 1 / L[i][i] in
+// dinv; for i > j, lane j's a[i] equals L[i][j] * L[j][j].
 __device__ __forceinline__ float rl(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
@@ -348,22 +377,25 @@ __device__ __forceinline__ double rl(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
 template <typename T>
-__device__ __forceinline__ bool wave_chol(T (&a)[NH], T (&lrow)[NH], T& diag, int lane, T& dmin,
+__device__ __forceinline__ bool wave_chol(T (&a)[NH], T (&lrow)[NH], T& dinv, int lane, T& dmin,
                                           T& dmax) {
   bool ok = true;
   dmin = (T)FLT_MAX; dmax = 0;
-  diag = 1;
+  dinv = 1;
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
     const T d = rl(a[k], k);
     ok = ok && (d > (T)0) && isfinite(d);
     dmin = d < dmin ? d : dmin;
     dmax = d > dmax ? d : dmax;
-    const T lkk = sqrt(d);
-    const T l = lane >= k ? a[k] / lkk : (T)0;  // L[lane][k]; lane k gets L[k][k]
+    const T inv = rsq(d);
+    const T l = lane >= k ? a[k] * inv : (T)0;  // L[lane][k]; lane k gets L[k][k]
     lrow[k] = l;
-    if (lane == k) diag = lkk;
+    if (lane == k) dinv = inv;
     T lb[NH];
 #pragma unroll
     for (int i = k + 1; i < NH; ++i) lb[i] = rl(l, i);
@@ -376,9 +408,9 @@ __device__ __forceinline__ bool wave_chol(T (&a)[NH], T (&lrow)[NH], T& diag, in
 
 // Forward L w = b, backward L^T d = w; lane i holds b_i and gets w_i, d_i.
 template <typename T>
-__device__ __forceinline__ void wave_solve(const T (&a)[NH], const T (&lrow)[NH], T diag,
+__device__ __forceinline__ void wave_solve(const T (&a)[NH], const T (&lrow)[NH], T dinv,
                                            int lane, T b, T& w, T& d) {
-  const T inv = (T)1 / diag;
+  const T inv = dinv;
   T acc = b;
   w = 0;
 #pragma unroll
@@ -404,12 +436,6 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-  return v;
-}
-
 // Column `lane` of H = S/s00 - E E^T (i, j >= 1), plus lam on the diagonal.
 template <typename T>
 __device__ __forceinline__ void load_hcol(const float* Sc, T inv0, const T* E, int lane, T lam,
@@ -425,7 +451,7 @@ __device__ __forceinline__ void load_hcol(const float* Sc, T inv0, const T* E, i
 
 constexpr int DIR_WAVES = 4;  // cells (waves) per workgroup of the wave-per-cell kernels
 
-__global__ __launch_bounds__(256) void k_direction3(
+__global__ __launch_bounds__(256, 3) void k_direction3(
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
     const float* __restrict__ S, const float* __restrict__ M, float* __restrict__ dbeta,
     float* __restrict__ gdot, float* __restrict__ alpha_w, int32_t* __restrict__ iters_w,
@@ -434,25 +460,38 @@ __global__ __launch_bounds__(256) void k_direction3(
     const float* __restrict__ beta, SolveParams p, int32_t* fb_list, int32_t* fb_ctr, DirOut o) {
   const int64_t count = *ctr;
   const int lane = threadIdx.x & 63;
-  const int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + (threadIdx.x >> 6);
+  const int wv = threadIdx.x >> 6;
+  const int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + wv;
   if (slot >= count) return;  // whole wave
   const int64_t cell = list[slot];
-  const float* Sc = S + cell * NCOL;
-  const float s00 = Sc[0];
-  const float inv0 = 1.f / s00;
+  // the cell's row of S goes to LDS with coalesced 16-byte loads; the Hessian
+  // columns are then gathered from LDS
+  __shared__ float sS[DIR_WAVES][NCOL];
   __shared__ float sE[DIR_WAVES][K3 + 1];
-  float* E = sE[threadIdx.x >> 6];
-  if (lane < K3) E[lane] = lane == 0 ? 1.f : Sc[lane] * inv0;
-  __builtin_amdgcn_wave_barrier();
+  float* Sw = sS[wv];
+  {
+    const f4* src = reinterpret_cast<const f4*>(S + cell * NCOL);
+    f4* dst = reinterpret_cast<f4*>(Sw);
+    for (int i = lane; i < NCOL / 4; i += 64) dst[i] = src[i];
+  }
   const float* Mc = M + cell * K3;
   const float nn = Mc[0];
-  const float g = lane < NH ? E[lane + 1] - Mc[lane + 1] / nn : 0.f;
+  const float mi = lane < NH ? Mc[lane + 1] : 0.f;
+  const CellState cs = load_state(cell, lane, iters_w, status_w, rbest_w, itbest_w, alpha_w, Lval,
+                                  beta);
+  __builtin_amdgcn_wave_barrier();
+  const float s00 = Sw[0];
+  const float inv0 = 1.f / s00;
+  float* E = sE[wv];
+  if (lane < K3) E[lane] = lane == 0 ? 1.f : Sw[lane] * inv0;
+  __builtin_amdgcn_wave_barrier();
+  const float g = lane < NH ? E[lane + 1] - mi / nn : 0.f;
   float r = wave_max(fabsf(g));
   if (!isfinite(s00) || !(s00 > 0.f)) r = NAN;
 
-  float a[NH], lrow[NH], diag, dmin, dmax;
-  load_hcol(Sc, inv0, E, lane, 0.f, a);
-  bool ok = wave_chol(a, lrow, diag, lane, dmin, dmax);
+  float a[NH], lrow[NH], dinv, dmin, dmax;
+  load_hcol(Sw, inv0, E, lane, 0.f, a);
+  bool ok = wave_chol(a, lrow, dinv, lane, dmin, dmax);
   bool to_fp64 = false;
   uint32_t extra = 0;
   if (p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
@@ -461,19 +500,19 @@ __global__ __launch_bounds__(256) void k_direction3(
     float lam = p.lambda0;  // Alg. 1: Cholesky of H + lambda I
     extra |= MEM_ST_SHIFTED;
     for (int tries = 0; tries < 40 && !ok; ++tries, lam *= p.lambda_mul) {
-      load_hcol(Sc, inv0, E, lane, lam, a);
-      ok = wave_chol(a, lrow, diag, lane, dmin, dmax);
+      load_hcol(Sw, inv0, E, lane, lam, a);
+      ok = wave_chol(a, lrow, dinv, lane, dmin, dmax);
     }
   }
   float w = 0.f, d = 0.f;
-  if (ok && !to_fp64) wave_solve(a, lrow, diag, lane, -g, w, d);
+  if (ok && !to_fp64) wave_solve(a, lrow, dinv, lane, -g, w, d);
   const float res = 0.5f * wave_sum(lane < NH ? w * w : 0.f);
   const bool dfin = ok && __all(lane >= NH || isfinite(d));
   int code = 0;
   if (lane == 0) {
     if (to_fp64) fb_list[atomicAdd(fb_ctr, 1)] = (int)cell;
-    else code = finish_cell(true, cell, r, res, dfin, extra, p, gdot, alpha_w, iters_w, status_w,
-                            resid_w, Lval, rbest_w, itbest_w, beta, o);
+    else code = finish_cell(cell, r, res, dfin, extra, p, cs, gdot, iters_w, status_w, resid_w,
+                            rbest_w, itbest_w, o);
     if (code == 1) o.next_list[atomicAdd(o.next_ctr, 1)] = (int)cell;
     if (code == 2 && o.done_list) o.done_list[atomicAdd(o.done_ctr, 1)] = (int)cell;
   }
@@ -508,27 +547,29 @@ __global__ __launch_bounds__(256) void k_fallback3(
   const float* Mc = M + cell * K3;
   const double nn = Mc[0];
   const double g = lane < NH ? E[lane + 1] - (double)Mc[lane + 1] / nn : 0.0;
+  const CellState cs = load_state(cell, lane, iters_w, status_w, rbest_w, itbest_w, alpha_w, Lval,
+                                  beta);
   const float r = wave_max((float)fabs(g));
-  double a[NH], lrow[NH], diag, dmin, dmax;
+  double a[NH], lrow[NH], dinv, dmin, dmax;
   uint32_t extra = MEM_ST_FP64;
   double lam = 0.0;
   bool ok = false;
   for (int tries = 0; tries < 41 && !ok; ++tries) {
     load_hcol(Sc, inv0, E, lane, lam, a);
-    ok = wave_chol(a, lrow, diag, lane, dmin, dmax);
+    ok = wave_chol(a, lrow, dinv, lane, dmin, dmax);
     if (!ok) {
       lam = tries == 0 ? (double)p.lambda0 : lam * (double)p.lambda_mul;
       extra |= MEM_ST_SHIFTED;
     }
   }
   double w = 0.0, d = 0.0;
-  if (ok) wave_solve(a, lrow, diag, lane, -g, w, d);
+  if (ok) wave_solve(a, lrow, dinv, lane, -g, w, d);
   const float res = (float)(0.5 * wave_sum(lane < NH ? w * w : 0.0));
   const bool dfin = ok && __all(lane >= NH || isfinite(d));
   int code = 0;
   if (lane == 0) {
-    code = finish_cell(true, cell, r, res, dfin, extra, p, gdot, alpha_w, iters_w, status_w,
-                       resid_w, Lval, rbest_w, itbest_w, beta, o);
+    code = finish_cell(cell, r, res, dfin, extra, p, cs, gdot, iters_w, status_w, resid_w,
+                       rbest_w, itbest_w, o);
     if (code == 1) o.next_list[atomicAdd(o.next_ctr, 1)] = (int)cell;
     if (code == 2 && o.done_list) o.done_list[atomicAdd(o.done_ctr, 1)] = (int)cell;
   }
@@ -540,14 +581,24 @@ __global__ __launch_bounds__(256) void k_fallback3(
 // --------------------------------------------------------------------------
 // Residual refinement in compensated FP32 arithmetic
 // --------------------------------------------------------------------------
-// FP32 rounding of the exponent e_p = log w~_p + sum_k beta_k phi_k(p) (terms of
-// magnitude up to ~10 that cancel) limits the moment residual the FP32 Newton
-// iteration can certify to ~1e-5.  For converged cells the residual is
-// re-evaluated with the exponent as an error-free double-float dot product
-// (TwoProduct by FMA, TwoSum, tables split into hi + lo parts), then one Newton
-// correction uses the FP32 Hessian already assembled for the cell: classical
-// iterative refinement, all in FP32 operations.
-constexpr int ACC_CH = 64;  // nodes per LDS chunk
+// FP32 rounding of the exponent e_p = log w~_p + sum_k beta_k phi_k(p) (terms
+// that reach a few hundred and cancel) limits the moment residual the FP32
+// Newton iteration can certify to ~1e-5.  For converged cells the residual is
+// re-evaluated in double-float arithmetic: every product by TwoProduct (FMA),
+// every sum by TwoSum, the accumulated errors carried in a second FP32 word
+// (the compensated dot product "Dot2" of Ogita, Rump and Oishi); then one
+// Newton correction uses the Hessian already assembled for the cell --
+// classical iterative refinement, with FP32 operations only.
+//
+// The nodes are a tensor grid (x_i, x_j, x_l) and phi_(a,b,c) = h_a h_b h_c
+// with h_a = He_a / sqrt(a!), so both the exponent and the moments factor axis
+// by axis (sum factorisation):
+//   U[i][b,c] = sum_a beta_abc h_a(x_i),  V[i][j][c] = sum_b U[i][b,c] h_b(x_j),
+//   e(i,j,l)  = sum_c V[i][j][c] h_c(x_l) + lw_i + lw_j + lw_l - log Z,
+//   P[i][j][c] = sum_l sigma(i,j,l) h_c(x_l),  R[i][b,c] = sum_j P[i][j][c] h_b(x_j),
+//   E_abc = sum_i R[i][b,c] h_a(x_i),
+// where lw is the one-dimensional log w~ (log w~ of a node is the sum over its
+// three coordinates).  About 5 terms per node instead of 36 + 35.
 
 // Error-free transformations need every product and sum rounded on its own:
 // FP contraction (fusing a*b + c into one fma) is switched off where they are
@@ -559,116 +610,165 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
   e = (a - (s - z)) + (b - z);
 }
 
-// One wave per cell; lane l takes nodes p0 + l of each 64-node chunk (tables
-// staged in LDS transposed, [k][node], so the lane reads are conflict-free);
-// beta is wave-uniform.  Per-lane compensated partial sums are combined across
-// the wave with TwoSum.
-__global__ __launch_bounds__(256) void k_accurate3(
-    const float* __restrict__ tabHi, const float* __restrict__ tabLo, int Q,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
-    const float* __restrict__ M, const float* __restrict__ beta, const float* __restrict__ logZ,
-    float* __restrict__ Gacc, float* __restrict__ racc, float tol, int32_t* out_list,
-    int32_t* out_ctr) {
+struct dfl {  // unevaluated sum h + l
+  float h, l;
+};
+
+// acc += x * y (x, y double-float)
+__device__ __forceinline__ void df_acc(dfl& acc, dfl x, dfl y) {
+#pragma clang fp contract(off)
+  const float p = x.h * y.h;
+  const float pe = fmaf(x.h, y.h, -p);
+  float sh, se;
+  two_sum(acc.h, p, sh, se);
+  acc.h = sh;
+  acc.l = acc.l + (se + (pe + (x.h * y.l + x.l * y.h)));
+}
+
+// acc += x (x double-float)
+__device__ __forceinline__ void df_add(dfl& acc, dfl x) {
+#pragma clang fp contract(off)
+  float sh, se;
+  two_sum(acc.h, x.h, sh, se);
+  acc.h = sh;
+  acc.l = acc.l + (se + x.l);
+}
+
+__device__ __forceinline__ dfl df_norm(dfl a) {
+#pragma clang fp contract(off)
+  const float h = a.h + a.l;
+  return {h, a.l - (h - a.h)};
+}
+
+__device__ __forceinline__ int tri(int m) { return m * (m + 1) / 2; }
+__device__ __forceinline__ int bidx3(int a, int b, int c) {
+  const int t = a + b + c, m = b + c;
+  return t * (t + 1) * (t + 2) / 6 + tri(m) + c;
+}
+
+constexpr int NBC = 15;  // (b, c) with b + c <= 4
+
+// One 64-thread workgroup per cell.  t1 = one-dimensional tables, double-float:
+// t1[a * n + k] = h_a(x_k) (a = 0..4), t1[5 * n + k] = lw_k.
+__global__ __launch_bounds__(64) void k_accurate3(
+    const float2* __restrict__ t1, int n, const int32_t* __restrict__ list,
+    const int32_t* __restrict__ ctr, const float* __restrict__ M, const float* __restrict__ beta,
+    const float* __restrict__ logZ, float* __restrict__ Gacc, float* __restrict__ racc, float tol,
+    int32_t* out_list, int32_t* out_ctr) {
 #pragma clang fp contract(off)
   const int64_t count = *ctr;
-  const int64_t first = (int64_t)blockIdx.x * DIR_WAVES;
-  if (first >= count) return;  // whole workgroup
-  const int lane = threadIdx.x & 63;
-  const int64_t slot = first + (threadIdx.x >> 6);
-  const bool valid = slot < count;
-  const int64_t cell = valid ? (int64_t)list[slot] : (int64_t)list[first];
-  float b[36];
-#pragma unroll
-  for (int k = 0; k < 36; ++k) b[k] = k == 0 ? 1.f : (k < K3 ? beta[cell * K3 + k] : 0.f);
+  const int64_t slot = blockIdx.x;
+  if (slot >= count) return;
+  const int lane = threadIdx.x;
+  const int64_t cell = list[slot];
+  extern __shared__ float2 dyn[];
+  float2* sU = dyn;               // [n][15]  U, later R
+  float2* sV = dyn + n * NBC;     // [n*n][5] V, later P
+  auto H = [&](int a, int k) -> dfl { const float2 v = t1[a * n + k]; return {v.x, v.y}; };
+
+  // U[i][b,c] = sum_a beta_abc h_a(x_i)
+  for (int t = lane; t < n * NBC; t += 64) {
+    const int i = t / NBC, bc = t % NBC;
+    int m = 0;
+    while (tri(m + 1) <= bc) ++m;
+    const int c = bc - tri(m), b = m - c;
+    dfl u = {0.f, 0.f};
+    for (int a = 0; a <= 4 - m; ++a) {
+      const int k = bidx3(a, b, c);
+      const float bk = k == 0 ? 0.f : beta[cell * K3 + k];  // beta_0 enters as log Z
+      df_acc(u, {bk, 0.f}, H(a, i));
+    }
+    sU[t] = make_float2(u.h, u.l);
+  }
+  __builtin_amdgcn_wave_barrier();
+  // V[i][j][c] = sum_b U[i][b,c] h_b(x_j)
+  for (int t = lane; t < n * n * 5; t += 64) {
+    const int ij = t / 5, c = t % 5, i = ij / n, j = ij % n;
+    dfl v = {0.f, 0.f};
+    for (int b = 0; b <= 4 - c; ++b) {
+      const float2 u = sU[i * NBC + tri(b + c) + c];
+      df_acc(v, {u.x, u.y}, H(b, j));
+    }
+    sV[t] = make_float2(v.h, v.l);
+  }
+  __builtin_amdgcn_wave_barrier();
+  // exponent, sigma and P[i][j][c] = sum_l sigma h_c(x_l); lane <-> (i, j)
   const float lz = logZ[cell];
-  float S[K3], Cc[K3];
+  for (int q = lane; q < n * n; q += 64) {
+    const int i = q / n, j = q % n;
+    dfl V[5], P[5];
 #pragma unroll
-  for (int i = 0; i < K3; ++i) { S[i] = 0.f; Cc[i] = 0.f; }
-  __shared__ float sH[36 * ACC_CH], sL[36 * ACC_CH];
-  for (int p0 = 0; p0 < Q; p0 += ACC_CH) {
-    const int np = min(ACC_CH, Q - p0);
-    __syncthreads();
-    for (int i = threadIdx.x; i < 36 * ACC_CH; i += 256) {
-      const int k = i / ACC_CH, q = i % ACC_CH;
-      const bool in = q < np;
-      sH[i] = in ? tabHi[(size_t)(p0 + q) * 36 + k] : 0.f;
-      sL[i] = in ? tabLo[(size_t)(p0 + q) * 36 + k] : 0.f;
+    for (int c = 0; c < 5; ++c) {
+      const float2 v = sV[q * 5 + c];
+      V[c] = {v.x, v.y};
+      P[c] = {0.f, 0.f};
     }
-    __syncthreads();
-    if (lane >= np) continue;
-    // e - log Z as an unevaluated sum s + c (error-free products and sums)
-    float s = -lz, c = 0.f;
+    dfl base = {-lz, 0.f};
+    df_add(base, H(5, i));
+    df_add(base, H(5, j));
+    for (int l = 0; l < n; ++l) {
+      dfl e = base;
+      df_add(e, H(5, l));
 #pragma unroll
-    for (int k = 0; k < 36; ++k) {
-      const float h = sH[k * ACC_CH + lane];
-      const float pr = b[k] * h;
-      const float pe = fmaf(b[k], h, -pr);
-      float ns, se;
-      two_sum(s, pr, ns, se);
-      s = ns;
-      c += pe + se + b[k] * sL[k * ACC_CH + lane];
-    }
-    if (s + c < -60.f) continue;  // weight below 1e-26: no measurable moment
-    const float ex = expf(s);     // accurate to ~1 ulp for any |s|
-    const float w = fmaf(ex, c, ex);
-    {  // phi_0 = 1 (column 0 of the table holds log w~)
-      const float y = w - Cc[0];
-      const float tt = S[0] + y;
-      Cc[0] = (tt - S[0]) - y;
-      S[0] = tt;
+      for (int c = 0; c < 5; ++c) df_acc(e, V[c], H(c, l));
+      e = df_norm(e);
+      if (e.h < -60.f) continue;  // weight below 1e-26: no measurable moment
+      const float ex = expf(e.h);
+      const float w = fmaf(ex, e.l, ex);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) df_acc(P[c], {w, 0.f}, H(c, l));
     }
 #pragma unroll
-    for (int i = 1; i < K3; ++i) {
-      const float h = sH[i * ACC_CH + lane];
-      const float pr = w * h;
-      const float y = (pr - Cc[i]) + (fmaf(w, h, -pr) + w * sL[i * ACC_CH + lane]);
-      const float tt = S[i] + y;
-      Cc[i] = (tt - S[i]) - y;
-      S[i] = tt;
+    for (int c = 0; c < 5; ++c) sV[q * 5 + c] = make_float2(P[c].h, P[c].l);
+  }
+  __builtin_amdgcn_wave_barrier();
+  // R[i][b,c] = sum_j P[i][j][c] h_b(x_j)
+  for (int t = lane; t < n * NBC; t += 64) {
+    const int i = t / NBC, bc = t % NBC;
+    int m = 0;
+    while (tri(m + 1) <= bc) ++m;
+    const int c = bc - tri(m), b = m - c;
+    dfl r = {0.f, 0.f};
+    for (int j = 0; j < n; ++j) {
+      const float2 pv = sV[(i * n + j) * 5 + c];
+      df_acc(r, {pv.x, pv.y}, H(b, j));
+    }
+    sU[t] = make_float2(r.h, r.l);
+  }
+  __builtin_amdgcn_wave_barrier();
+  // E_abc = sum_i R[i][b,c] h_a(x_i) on lane k = bidx3(a, b, c)
+  dfl E = {0.f, 0.f};
+  if (lane < K3) {
+    int t = 0;
+    while ((t + 1) * (t + 2) * (t + 3) / 6 <= lane) ++t;
+    const int rr = lane - t * (t + 1) * (t + 2) / 6;
+    int m = 0;
+    while (tri(m + 1) <= rr) ++m;
+    const int c = rr - tri(m), b = m - c, a = t - m;
+    for (int i = 0; i < n; ++i) {
+      const float2 rv = sU[i * NBC + tri(m) + c];
+      df_acc(E, {rv.x, rv.y}, H(a, i));
     }
   }
-  // combine the 64 lanes: value = S - Cc, summed with TwoSum at each level and
-  // kept as an unevaluated pair (th, tl)
-  float th[K3], tl[K3];
-#pragma unroll
-  for (int i = 0; i < K3; ++i) {
-    float hi = S[i], lo = -Cc[i];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const float oh = __shfl_xor(hi, off), ol = __shfl_xor(lo, off);
-      float ns, se;
-      two_sum(hi, oh, ns, se);
-      hi = ns;
-      lo = lo + ol + se;
-    }
-    th[i] = hi;
-    tl[i] = lo;
+  // G_k = E_k / E_0 - M_k / n without rounding either quotient to FP32 first:
+  // each quotient is q1 + q2 with q2 from the exact remainder (fma)
+  const float h0 = __shfl(E.h, 0), l0 = __shfl(E.l, 0);
+  const float inv0 = 1.f / h0;
+  const float nn = M[cell * K3];
+  float g = 0.f;
+  if (lane >= 1 && lane < K3) {
+    const float e1 = E.h * inv0;
+    const float e2 = (fmaf(-e1, h0, E.h) + (E.l - e1 * l0)) * inv0;
+    const float mi = M[cell * K3 + lane];
+    const float m1 = mi / nn;
+    const float m2 = fmaf(-m1, nn, mi) / nn;
+    g = (e1 - m1) + (e2 - m2);
   }
-  if (valid) {
-    // G_i = T_i / T_0 - M_i / n without rounding either quotient to FP32 first:
-    // each quotient is q1 + q2 with q2 from the exact remainder (fma), so G is
-    // resolved far below one ulp of the moments themselves
-    const float h0 = th[0], l0 = tl[0];
-    const float inv0 = 1.f / h0;
-    const float nn = M[cell * K3];
-    const float rn = 1.f / nn;
-    float r = 0.f;
-#pragma unroll
-    for (int i = 1; i < K3; ++i) {
-      const float e1 = th[i] * inv0;
-      const float e2 = (fmaf(-e1, h0, th[i]) + (tl[i] - e1 * l0)) * inv0;
-      const float mi = M[cell * K3 + i];
-      const float m1 = mi / nn;
-      const float m2 = fmaf(-m1, nn, mi) * rn;
-      const float g = (e1 - m1) + (e2 - m2);
-      if (lane == i) Gacc[cell * 36 + i] = g;
-      r = fmaxf(r, fabsf(g));
-    }
-    if (lane == 0) {
-      Gacc[cell * 36] = 0.f;
-      racc[cell] = r;
-      if (!(r <= tol)) out_list[atomicAdd(out_ctr, 1)] = (int)cell;
-    }
+  if (lane < 36) Gacc[cell * 36 + lane] = g;
+  const float r = wave_max(fabsf(g));
+  if (lane == 0) {
+    racc[cell] = r;
+    if (!(r <= tol)) out_list[atomicAdd(out_ctr, 1)] = (int)cell;
   }
 }
 
@@ -688,13 +788,13 @@ __global__ __launch_bounds__(256) void k_refine3(
   float* E = sE[threadIdx.x >> 6];
   if (lane < K3) E[lane] = lane == 0 ? 1.f : Sc[lane] * inv0;
   __builtin_amdgcn_wave_barrier();
-  float a[NH], lrow[NH], diag, dmin, dmax;
+  float a[NH], lrow[NH], dinv, dmin, dmax;
   load_hcol(Sc, inv0, E, lane, 0.f, a);
-  const bool ok = wave_chol(a, lrow, diag, lane, dmin, dmax);
+  const bool ok = wave_chol(a, lrow, dinv, lane, dmin, dmax);
   if (!ok) return;
   const float g = lane < NH ? Gacc[cell * 36 + 1 + lane] : 0.f;
   float w, d;
-  wave_solve(a, lrow, diag, lane, -g, w, d);
+  wave_solve(a, lrow, dinv, lane, -g, w, d);
   if (__all(lane >= NH || isfinite(d)) && lane < NH) beta[cell * K3 + 1 + lane] += d;
 }
 
@@ -809,8 +909,9 @@ hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
                            const float* M, const float* beta, float tol, int32_t* out_list,
                            int32_t* out_ctr, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  k_accurate3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(c->d_accHi, c->d_accLo, c->Q, list, ctr, M,
-                                                     beta, c->w_logZ, c->w_Gacc, c->w_racc, tol,
+  const size_t lds = (size_t)(c->n1d * NBC + c->n1d * c->n1d * 5) * sizeof(float2);
+  k_accurate3<<<(unsigned)grid_cells, 64, lds, s>>>(c->d_t1, c->n1d, list, ctr, M, beta,
+                                                     c->w_logZ, c->w_Gacc, c->w_racc, tol,
                                                      out_list, out_ctr);
   return hipGetLastError();
 }

@@ -62,8 +62,7 @@ struct mem_ctx_s {
   float* d_psiF_m = nullptr;  // FP32 B operand of the 4 moment blocks [nsg_m][4][64][8]
   void* d_psi_hi = nullptr;   // 16-bit B operand, high part [nsg_m][36][64][8]
   void* d_psi_lo = nullptr;   // 16-bit B operand, low part
-  float* d_accHi = nullptr;  // [Qpad][36] (log w~, phi_1..phi_34, 0), FP32 high part
-  float* d_accLo = nullptr;  // [Qpad][36] FP32 low part (table - high part)
+  float2* d_t1 = nullptr;    // 1D tables (hi, lo): h_a(x_k) at [a*n + k], a <= 4; lw_k at [5n + k]
   // device tables, 1D
   float* d_tab1 = nullptr;   // [Q][8]: phi_0..phi_4, log w~, 0, 0
   // workspace (per cell unless stated)

@@ -244,17 +244,26 @@ void build_tables(mem_ctx_t ctx) {
       for (int l = 0; l < 64; ++l)
         A[((size_t)g * NJ + j) * 64 + l] = (float)phiE(GRP * g + (l & 15), 4 * j + (l >> 4));
   ctx->d_phiA = upload(A);
-  // compensated-exponent tables: value = hi + lo with hi = fl32(value)
-  std::vector<float> AH((size_t)Qpad * 36), AL((size_t)Qpad * 36);
-  for (int p = 0; p < Qpad; ++p)
-    for (int k = 0; k < 36; ++k) {
-      const double v = phiE(p, k);
-      const float hi = (float)v;
-      AH[(size_t)p * 36 + k] = hi;
-      AL[(size_t)p * 36 + k] = p < Q ? (float)(v - (double)hi) : 0.f;
+  // one-dimensional double-float tables of the compensated residual pass:
+  // h_a(x_k) = He_a(x_k) / sqrt(a!) for a <= 4 and lw_k = log w_k + x_k^2 / 2 +
+  // log(2 pi) / 2 (the 3D log w~ of a node is the sum over its coordinates)
+  {
+    const int n = ctx->n1d;
+    std::vector<double> x, w;
+    gauss_hermite(n, x, w);
+    std::vector<float2> T1((size_t)6 * n);
+    auto split = [](double v) {
+      const float h = (float)v;
+      return make_float2(h, (float)(v - (double)h));
+    };
+    double hp[5];
+    for (int k = 0; k < n; ++k) {
+      ortho_hermite(4, x[k], hp);
+      for (int a = 0; a < 5; ++a) T1[(size_t)a * n + k] = split(hp[a]);
+      T1[(size_t)5 * n + k] = split(std::log(w[k]) + 0.5 * x[k] * x[k] + 0.5 * std::log(2.0 * M_PI));
     }
-  ctx->d_accHi = upload(AH);
-  ctx->d_accLo = upload(AL);
+    ctx->d_t1 = upload(T1);
+  }
   // pair index of each column
   std::vector<int> ci(NCOL, -1), cj(NCOL, -1);
   for (int i = 0; i < K3; ++i)
