@@ -41,7 +41,7 @@ void free_workspace(mem_ctx_t c) {
   dfree(c->w_status);
   for (auto& l : c->w_list) dfree(l);
   dfree(c->w_Gacc); dfree(c->w_racc); dfree(c->w_rbest); dfree(c->w_itbest);
-  dfree(c->w_Mnew); dfree(c->w_F); dfree(c->w_rho); dfree(c->w_prob);
+  dfree(c->w_Mnew); dfree(c->w_F); dfree(c->w_rho); dfree(c->w_prob); dfree(c->w_code);
   c->cap_cells = 0;
 }
 
@@ -268,7 +268,7 @@ mem_err_t mem_reserve(mem_ctx_t c, int64_t max_cells, int32_t max_problems) {
               dalloc(c->w_list[2], n) && dalloc(c->w_list[3], n) && dalloc(c->w_Gacc, n * 36) &&
               dalloc(c->w_racc, n) && dalloc(c->w_rbest, n) && dalloc(c->w_itbest, n) &&
               dalloc(c->w_Mnew, n * K3) && dalloc(c->w_F, n * K3) &&
-              dalloc(c->w_rho, n) && dalloc(c->w_prob, n);
+              dalloc(c->w_rho, n) && dalloc(c->w_prob, n) && dalloc(c->w_code, n);
     if (!ok) { free_workspace(c); return fail(c, MEM_ERR_NOMEM, "workspace allocation"); }
     c->cap_cells = max_cells;
   }

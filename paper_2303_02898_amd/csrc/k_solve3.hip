@@ -364,9 +364,9 @@ __device__ __forceinline__ int finish_cell(int64_t cell, float r, float res, boo
 
 // Wave-cooperative Cholesky for one cell per wave.  Lane j < 34 holds column
 // j of the SPD matrix in registers (a[i] = A[i][j]); step k broadcasts the
-// pivot and the k-th column of L with readlane and updates the trailing
-// columns.  On return lane i holds row i of L in lrow[] and 1 / L[i][i] in
-// dinv; for i > j, lane j's a[i] equals L[i][j] * L[j][j].
+// pivot with readlane, shares column k of L through LDS and updates the
+// trailing columns.  On return lane i holds 1 / L[i][i] in dinv; for i > j,
+// lane j's a[i] equals L[i][j] * L[j][j].
 __device__ __forceinline__ float rl(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
@@ -380,9 +380,14 @@ __device__ __forceinline__ double rl(double v, int src) {
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 
+// Lm: this wave's LDS copy of L, row k = column k of L ([NH][LST]).  At step k
+// every lane publishes its L[lane][k] with one LDS write and reads column k
+// back with broadcast reads (all lanes read the same addresses): a step costs
+// one write, a few 16-byte reads and the trailing FMAs.
+constexpr int LST = NH + 2;  // row stride of Lm (16-byte aligned rows)
+
 template <typename T>
-__device__ __forceinline__ bool wave_chol(T (&a)[NH], T (&lrow)[NH], T& dinv, int lane, T& dmin,
-                                          T& dmax) {
+__device__ __forceinline__ bool wave_chol(T (&a)[NH], T& dinv, int lane, T& dmin, T& dmax, T* Lm) {
   bool ok = true;
   dmin = (T)FLT_MAX; dmax = 0;
   dinv = 1;
@@ -394,22 +399,28 @@ __device__ __forceinline__ bool wave_chol(T (&a)[NH], T (&lrow)[NH], T& dinv, in
     dmax = d > dmax ? d : dmax;
     const T inv = rsq(d);
     const T l = lane >= k ? a[k] * inv : (T)0;  // L[lane][k]; lane k gets L[k][k]
-    lrow[k] = l;
     if (lane == k) dinv = inv;
+    if (lane < NH) Lm[k * LST + lane] = l;
+    if (k == NH - 1) break;
+    __builtin_amdgcn_wave_barrier();
     T lb[NH];
 #pragma unroll
-    for (int i = k + 1; i < NH; ++i) lb[i] = rl(l, i);
+    for (int i = k + 1; i < NH; ++i) lb[i] = Lm[k * LST + i];
+    if (lane > k) {
 #pragma unroll
-    for (int i = k + 1; i < NH; ++i)
-      if (lane > k) a[i] = fma(-lb[i], l, a[i]);
+      for (int i = k + 1; i < NH; ++i) a[i] = fma(-lb[i], l, a[i]);
+    }
   }
+  __builtin_amdgcn_wave_barrier();
   return ok;
 }
 
 // Forward L w = b, backward L^T d = w; lane i holds b_i and gets w_i, d_i.
+// The forward sweep reads L[lane][k] from Lm; the backward sweep uses lane j's
+// a[i] = L[i][j] L[j][j] (i > j) left by wave_chol.
 template <typename T>
-__device__ __forceinline__ void wave_solve(const T (&a)[NH], const T (&lrow)[NH], T dinv,
-                                           int lane, T b, T& w, T& d) {
+__device__ __forceinline__ void wave_solve(const T (&a)[NH], const T* Lm, T dinv, int lane, T b,
+                                           T& w, T& d) {
   const T inv = dinv;
   T acc = b;
   w = 0;
@@ -417,7 +428,7 @@ __device__ __forceinline__ void wave_solve(const T (&a)[NH], const T (&lrow)[NH]
   for (int k = 0; k < NH; ++k) {
     const T wk = rl(acc * inv, k);
     if (lane == k) w = wk;
-    if (lane > k) acc = fma(-lrow[k], wk, acc);
+    if (lane > k && lane < NH) acc = fma(-Lm[k * LST + lane], wk, acc);
   }
   T acc2 = w;
   d = 0;
@@ -451,13 +462,13 @@ __device__ __forceinline__ void load_hcol(const float* Sc, T inv0, const T* E, i
 
 constexpr int DIR_WAVES = 4;  // cells (waves) per workgroup of the wave-per-cell kernels
 
-__global__ __launch_bounds__(256, 3) void k_direction3(
+__global__ __launch_bounds__(256) void k_direction3(
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
     const float* __restrict__ S, const float* __restrict__ M, float* __restrict__ dbeta,
     float* __restrict__ gdot, float* __restrict__ alpha_w, int32_t* __restrict__ iters_w,
     uint32_t* __restrict__ status_w, float* __restrict__ resid_w,
     const float* __restrict__ Lval, float* __restrict__ rbest_w, int32_t* __restrict__ itbest_w,
-    const float* __restrict__ beta, SolveParams p, int32_t* fb_list, int32_t* fb_ctr, DirOut o) {
+    const float* __restrict__ beta, SolveParams p, int8_t* __restrict__ codes, DirOut o) {
   const int64_t count = *ctr;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -468,6 +479,7 @@ __global__ __launch_bounds__(256, 3) void k_direction3(
   // columns are then gathered from LDS
   __shared__ float sS[DIR_WAVES][NCOL];
   __shared__ float sE[DIR_WAVES][K3 + 1];
+  __shared__ __align__(16) float sL[DIR_WAVES][NH * LST];
   float* Sw = sS[wv];
   {
     const f4* src = reinterpret_cast<const f4*>(S + cell * NCOL);
@@ -489,9 +501,9 @@ __global__ __launch_bounds__(256, 3) void k_direction3(
   float r = wave_max(fabsf(g));
   if (!isfinite(s00) || !(s00 > 0.f)) r = NAN;
 
-  float a[NH], lrow[NH], dinv, dmin, dmax;
+  float a[NH], dinv, dmin, dmax;
   load_hcol(Sw, inv0, E, lane, 0.f, a);
-  bool ok = wave_chol(a, lrow, dinv, lane, dmin, dmax);
+  bool ok = wave_chol(a, dinv, lane, dmin, dmax, sL[wv]);
   bool to_fp64 = false;
   uint32_t extra = 0;
   if (p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
@@ -501,24 +513,66 @@ __global__ __launch_bounds__(256, 3) void k_direction3(
     extra |= MEM_ST_SHIFTED;
     for (int tries = 0; tries < 40 && !ok; ++tries, lam *= p.lambda_mul) {
       load_hcol(Sw, inv0, E, lane, lam, a);
-      ok = wave_chol(a, lrow, dinv, lane, dmin, dmax);
+      ok = wave_chol(a, dinv, lane, dmin, dmax, sL[wv]);
     }
   }
   float w = 0.f, d = 0.f;
-  if (ok && !to_fp64) wave_solve(a, lrow, dinv, lane, -g, w, d);
+  if (ok && !to_fp64) wave_solve(a, sL[wv], dinv, lane, -g, w, d);
   const float res = 0.5f * wave_sum(lane < NH ? w * w : 0.f);
   const bool dfin = ok && __all(lane >= NH || isfinite(d));
+  // outcome of the slot, compacted into the lists by k_compact3
   int code = 0;
   if (lane == 0) {
-    if (to_fp64) fb_list[atomicAdd(fb_ctr, 1)] = (int)cell;
-    else code = finish_cell(cell, r, res, dfin, extra, p, cs, gdot, iters_w, status_w, resid_w,
-                            rbest_w, itbest_w, o);
-    if (code == 1) o.next_list[atomicAdd(o.next_ctr, 1)] = (int)cell;
-    if (code == 2 && o.done_list) o.done_list[atomicAdd(o.done_ctr, 1)] = (int)cell;
+    code = to_fp64 ? 3
+                   : finish_cell(cell, r, res, dfin, extra, p, cs, gdot, iters_w, status_w,
+                                 resid_w, rbest_w, itbest_w, o);
+    codes[slot] = (int8_t)code;
   }
   code = __shfl(code, 0);
   if (code == 1 && lane == 0) dbeta[cell * 36] = 0.f;
   if (code == 1 && lane < NH) dbeta[cell * 36 + 1 + lane] = d;
+}
+
+// Stream compaction of the per-slot outcomes of k_direction3 (0 finished,
+// 1 live, 2 refinement candidate, 3 FP64 direction) into three cell lists,
+// with one atomic per list and workgroup instead of one per cell.
+__global__ __launch_bounds__(256) void k_compact3(
+    const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
+    const int8_t* __restrict__ codes, int32_t* l1, int32_t* c1, int32_t* l2, int32_t* c2,
+    int32_t* l3, int32_t* c3) {
+  const int64_t count = *ctr;
+  if ((int64_t)blockIdx.x * 256 >= count) return;  // whole workgroup
+  const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int code = slot < count ? (int)codes[slot] : 0;
+  const int cell = slot < count ? list[slot] : 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ int cnt[3][4], base[3][4];
+  unsigned long long m[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    m[q] = __ballot(code == q + 1);
+    if (lane == 0) cnt[q][wv] = __popcll(m[q]);
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int q = threadIdx.x;
+    int32_t* cq = q == 0 ? c1 : (q == 1 ? c2 : c3);
+    int tot = 0, off[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) { off[w] = tot; tot += cnt[q][w]; }
+    const int b = (tot > 0 && cq) ? atomicAdd(cq, tot) : 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) base[q][w] = b + off[w];
+  }
+  __syncthreads();
+  if (code >= 1 && code <= 3) {
+    const int q = code - 1;
+    int32_t* lq = q == 0 ? l1 : (q == 1 ? l2 : l3);
+    if (lq) {
+      const unsigned long long below = lane ? (m[q] & ((1ull << lane) - 1ull)) : 0ull;
+      lq[base[q][wv] + __popcll(below)] = cell;
+    }
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -535,13 +589,16 @@ __global__ __launch_bounds__(256) void k_fallback3(
     const float* __restrict__ beta, SolveParams p, DirOut o) {
   const int64_t count = *ctr;
   const int lane = threadIdx.x & 63;
-  const int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + (threadIdx.x >> 6);
-  if (slot >= count) return;
+  const int wv = threadIdx.x >> 6;
+  __shared__ double sE[DIR_WAVES][K3 + 1];
+  __shared__ __align__(16) double sL[DIR_WAVES][NH * LST];
+  // persistent: few cells take this path, so a small grid strides over them
+  for (int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + wv; slot < count;
+       slot += (int64_t)gridDim.x * DIR_WAVES) {
   const int64_t cell = list[slot];
   const float* Sc = S + cell * NCOL;
   const double inv0 = 1.0 / (double)Sc[0];
-  __shared__ double sE[DIR_WAVES][K3 + 1];
-  double* E = sE[threadIdx.x >> 6];
+  double* E = sE[wv];
   if (lane < K3) E[lane] = lane == 0 ? 1.0 : (double)Sc[lane] * inv0;
   __builtin_amdgcn_wave_barrier();
   const float* Mc = M + cell * K3;
@@ -550,20 +607,20 @@ __global__ __launch_bounds__(256) void k_fallback3(
   const CellState cs = load_state(cell, lane, iters_w, status_w, rbest_w, itbest_w, alpha_w, Lval,
                                   beta);
   const float r = wave_max((float)fabs(g));
-  double a[NH], lrow[NH], dinv, dmin, dmax;
+  double a[NH], dinv, dmin, dmax;
   uint32_t extra = MEM_ST_FP64;
   double lam = 0.0;
   bool ok = false;
   for (int tries = 0; tries < 41 && !ok; ++tries) {
     load_hcol(Sc, inv0, E, lane, lam, a);
-    ok = wave_chol(a, lrow, dinv, lane, dmin, dmax);
+    ok = wave_chol(a, dinv, lane, dmin, dmax, sL[wv]);
     if (!ok) {
       lam = tries == 0 ? (double)p.lambda0 : lam * (double)p.lambda_mul;
       extra |= MEM_ST_SHIFTED;
     }
   }
   double w = 0.0, d = 0.0;
-  if (ok) wave_solve(a, lrow, dinv, lane, -g, w, d);
+  if (ok) wave_solve(a, sL[wv], dinv, lane, -g, w, d);
   const float res = (float)(0.5 * wave_sum(lane < NH ? w * w : 0.0));
   const bool dfin = ok && __all(lane >= NH || isfinite(d));
   int code = 0;
@@ -576,6 +633,8 @@ __global__ __launch_bounds__(256) void k_fallback3(
   code = __shfl(code, 0);
   if (code == 1 && lane == 0) dbeta[cell * 36] = 0.f;
   if (code == 1 && lane < NH) dbeta[cell * 36 + 1 + lane] = (float)d;
+  __builtin_amdgcn_wave_barrier();  // sE / sL are reused by the next cell
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -785,16 +844,17 @@ __global__ __launch_bounds__(256) void k_refine3(
   const float* Sc = S + cell * NCOL;
   const float inv0 = 1.f / Sc[0];
   __shared__ float sE[DIR_WAVES][K3 + 1];
+  __shared__ __align__(16) float sL[DIR_WAVES][NH * LST];
   float* E = sE[threadIdx.x >> 6];
   if (lane < K3) E[lane] = lane == 0 ? 1.f : Sc[lane] * inv0;
   __builtin_amdgcn_wave_barrier();
-  float a[NH], lrow[NH], dinv, dmin, dmax;
+  float a[NH], dinv, dmin, dmax;
   load_hcol(Sc, inv0, E, lane, 0.f, a);
-  const bool ok = wave_chol(a, lrow, dinv, lane, dmin, dmax);
+  const bool ok = wave_chol(a, dinv, lane, dmin, dmax, sL[threadIdx.x >> 6]);
   if (!ok) return;
   const float g = lane < NH ? Gacc[cell * 36 + 1 + lane] : 0.f;
   float w, d;
-  wave_solve(a, lrow, dinv, lane, -g, w, d);
+  wave_solve(a, sL[threadIdx.x >> 6], dinv, lane, -g, w, d);
   if (__all(lane >= NH || isfinite(d)) && lane < NH) beta[cell * K3 + 1 + lane] += d;
 }
 
@@ -886,7 +946,9 @@ hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
   k_direction3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
                                                       c->w_alpha, c->w_iters, c->w_status,
                                                       c->w_resid, c->w_L, c->w_rbest, c->w_itbest,
-                                                      beta, p, fb_list, fb_ctr, o);
+                                                      beta, p, c->w_code, o);
+  k_compact3<<<nblocks(grid_cells, 256), 256, 0, s>>>(list, ctr, c->w_code, next_list, next_ctr,
+                                                      done_list, done_ctr, fb_list, fb_ctr);
   return hipGetLastError();
 }
 
@@ -898,7 +960,7 @@ hipError_t launch_fallback3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
                             hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
   DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
-  k_fallback3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
+  k_fallback3<<<(unsigned)std::min<int64_t>(nblocks(grid_cells, DIR_WAVES), 256), 256, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
                                                      c->w_alpha, c->w_iters, c->w_status,
                                                      c->w_resid, c->w_L, c->w_rbest, c->w_itbest,
                                                      beta, p, o);

@@ -80,6 +80,7 @@ struct mem_ctx_s {
   uint32_t* w_status = nullptr;
   int32_t* w_list[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t* w_ctr = nullptr;   // [8] list counters
+  int8_t* w_code = nullptr;   // [cap] per-slot outcome of the direction kernel
   float* w_Gacc = nullptr;    // [cap][36] compensated gradient E[phi_i] - M_i/n
   float* w_racc = nullptr;    // [cap] compensated residual
   float* w_rbest = nullptr;   // [cap] best FP32 residual so far (stall test)
