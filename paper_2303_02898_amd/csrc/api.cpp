@@ -29,6 +29,10 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+// rows of the node-range split buffer (42 MB): splits are used for launches of
+// at most a few thousand live cells
+constexpr int64_t SP_ROWS = 16384;
+
 template <typename T>
 bool dalloc(T*& p, size_t count) {
   dfree(p);
@@ -41,7 +45,8 @@ void free_workspace(mem_ctx_t c) {
   dfree(c->w_status);
   for (auto& l : c->w_list) dfree(l);
   dfree(c->w_Gacc); dfree(c->w_racc); dfree(c->w_rbest); dfree(c->w_itbest);
-  dfree(c->w_Mnew); dfree(c->w_F); dfree(c->w_rho); dfree(c->w_prob); dfree(c->w_code);
+  dfree(c->w_Mnew); dfree(c->w_F); dfree(c->w_rho); dfree(c->w_prob); dfree(c->w_code); dfree(c->w_Sp);
+  c->sp_rows = 0;
   c->cap_cells = 0;
 }
 
@@ -268,9 +273,11 @@ mem_err_t mem_reserve(mem_ctx_t c, int64_t max_cells, int32_t max_problems) {
               dalloc(c->w_list[2], n) && dalloc(c->w_list[3], n) && dalloc(c->w_Gacc, n * 36) &&
               dalloc(c->w_racc, n) && dalloc(c->w_rbest, n) && dalloc(c->w_itbest, n) &&
               dalloc(c->w_Mnew, n * K3) && dalloc(c->w_F, n * K3) &&
-              dalloc(c->w_rho, n) && dalloc(c->w_prob, n) && dalloc(c->w_code, n);
+              dalloc(c->w_rho, n) && dalloc(c->w_prob, n) && dalloc(c->w_code, n) &&
+              dalloc(c->w_Sp, (size_t)SP_ROWS * NCOL);
     if (!ok) { free_workspace(c); return fail(c, MEM_ERR_NOMEM, "workspace allocation"); }
     c->cap_cells = max_cells;
+    c->sp_rows = SP_ROWS;
   }
   if (max_problems > c->cap_problems) {
     const size_t P = (size_t)max_problems;

@@ -71,13 +71,17 @@ __global__ __launch_bounds__(256, 1) void k_assemble3m(
     const uint4* __restrict__ psiH,   // [nsg][36][64]     16-bit B operand, high part
     const uint4* __restrict__ psiL,   // [nsg][36][64]     16-bit B operand, low part
     int nsg, const int32_t* __restrict__ list, const int32_t* __restrict__ ctr, int64_t n,
-    const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ S) {
+    const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ S,
+    int ntile, int nsplit, float* __restrict__ Sp) {
   using H = Half<F16>;
   using T = typename H::T;
   using V = typename H::V;
   const int64_t count = ctr ? (int64_t)(*ctr) : n;
-  const int64_t tile0 = (int64_t)blockIdx.x * TILE;
+  const int split = (int)(blockIdx.x / ntile);
+  const int64_t tile0 = (int64_t)(blockIdx.x % ntile) * TILE;
   if (tile0 >= count) return;
+  const int sbeg = (int)((int64_t)split * nsg / nsplit);
+  const int send = (int)((int64_t)(split + 1) * nsg / nsplit);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
   const int64_t slot = tile0 + wave * 16 + (lane & 15);
@@ -122,9 +126,9 @@ __global__ __launch_bounds__(256, 1) void k_assemble3m(
       pl[b] = psiL[hb + (size_t)b * 64];
     }
   };
-  load(0);
+  load(sbeg);
 
-  for (int s = 0; s < nsg; ++s) {
+  for (int s = sbeg; s < send; ++s) {
     const int buf = s & 1;
     float ca[2 * NJ];
 #pragma unroll
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(256, 1) void k_assemble3m(
     uint4 ch[MB], cl[MB];
 #pragma unroll
     for (int b = 0; b < MB; ++b) { ch[b] = ph[b]; cl[b] = pl[b]; }
-    if (s + 1 < nsg) load(s + 1);
+    if (s + 1 < send) load(s + 1);
 
     // sigma of this wave's 16 cells at nodes 32s + 16h + 4(l/16) + r
     f4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = {0.f, 0.f, 0.f, 0.f};
@@ -184,8 +188,13 @@ __global__ __launch_bounds__(256, 1) void k_assemble3m(
     for (int q = 0; q < 4; ++q) {
       const int64_t sl = tile0 + 16 * t + 4 * kq + q;
       if (sl < count) {
-        const int64_t cw = list ? (int64_t)list[sl] : sl;
-        float* dst = S + cw * NCOL + (lane & 15);
+        float* dst;
+        if (nsplit > 1) {
+          dst = Sp + ((size_t)split * ntile * TILE + sl) * NCOL + (lane & 15);
+        } else {
+          const int64_t cw = list ? (int64_t)list[sl] : sl;
+          dst = S + cw * NCOL + (lane & 15);
+        }
         dst[16 * wave] = accF[t][q];
 #pragma unroll
         for (int b = 0; b < MB; ++b) dst[16 * (NFB + MB * wave + b)] = acc[t][b][q];
@@ -202,17 +211,22 @@ hipError_t launch_assemble3m(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
                              const int32_t* ctr, int64_t n, const float* beta, float* S,
                              hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)nblocks(grid_cells, TILE);
+  const int ntile = (int)nblocks(grid_cells, TILE);
+  const int nsplit = assembly_splits(c, ntile, 2 * c->nsg_m);
+  const unsigned grid = (unsigned)(ntile * nsplit);
   if (c->prec == MEM_PREC_FP16X3)
     k_assemble3m<true><<<grid, 256, 0, s>>>(c->d_phiA_m, c->d_psiF_m,
                                             static_cast<const uint4*>(c->d_psi_hi),
                                             static_cast<const uint4*>(c->d_psi_lo), c->nsg_m,
-                                            list, ctr, n, beta, c->w_logZ, S);
+                                            list, ctr, n, beta, c->w_logZ, S, ntile, nsplit,
+                                            c->w_Sp);
   else
     k_assemble3m<false><<<grid, 256, 0, s>>>(c->d_phiA_m, c->d_psiF_m,
                                              static_cast<const uint4*>(c->d_psi_hi),
                                              static_cast<const uint4*>(c->d_psi_lo), c->nsg_m,
-                                             list, ctr, n, beta, c->w_logZ, S);
+                                             list, ctr, n, beta, c->w_logZ, S, ntile, nsplit,
+                                             c->w_Sp);
+  if (nsplit > 1) return launch_sum_splits(c, list, ctr, n, ntile, nsplit, S, s);
   return hipGetLastError();
 }
 

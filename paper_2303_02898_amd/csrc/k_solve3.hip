@@ -46,6 +46,13 @@ __device__ __forceinline__ void wave_append(bool pred, int cell, int32_t* list, 
   }
 }
 
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
 // Row-major packed upper triangle of the 34 x 34 block: (i <= j).
 __device__ __forceinline__ int hidx(int i, int j) { return 34 * i - (i * (i + 1)) / 2 + j; }
 
@@ -91,12 +98,64 @@ __global__ void k_set_ctr(int32_t* ctr, int n) {
 // --------------------------------------------------------------------------
 // log-sum-exp pass and the Armijo backtracking line search of Alg. 1
 // --------------------------------------------------------------------------
-constexpr int LSE_CH = 8;  // node groups staged in LDS per barrier
+// One wavefront per cell.  The exponent on the tensor grid factors axis by
+// axis (sum factorisation, phi_(a,b,c) = h_a h_b h_c):
+//   U[i][b,c] = sum_a beta_abc h_a(x_i),  V[i][j][c] = sum_b U[i][b,c] h_b(x_j),
+//   e(i,j,l)  = lw_i + lw_j + lw_l + sum_c V[i][j][c] h_c(x_l),
+// and it is linear in beta, so for the trial point beta + alpha dbeta the
+// coefficients are V_beta + alpha V_dbeta: the factors are built once and each
+// trial of the backtracking search costs 5 FMAs and one exp per node.
+// t1 holds the one-dimensional tables (h_a(x_k) at [a n + k], lw_k at
+// [5 n + k]); only the high parts are used here.
+constexpr int NBC = 15;  // (b, c) with b + c <= 4
+__device__ __forceinline__ int tri(int m) { return m * (m + 1) / 2; }
+__device__ __forceinline__ int bidx3(int a, int b, int c) {
+  const int t = a + b + c, m = b + c;
+  return t * (t + 1) * (t + 2) / 6 + tri(m) + c;
+}
 
-template <bool LS>
-__global__ __launch_bounds__(256) void k_lse3(
-    const float* __restrict__ phiA, int ngroups, const int32_t* __restrict__ list,
-    const int32_t* __restrict__ ctr, int64_t n, const float* __restrict__ M,
+// Partial log-sum-exp (max, sum) of this lane's node pairs (i, j), all l,
+// for the coefficients V_beta + alpha V_dbeta.  NT = n when it is known at
+// compile time (exponents of a pair kept in registers), 0 otherwise (two
+// sweeps over l).
+template <bool LS, int NT>
+__device__ __forceinline__ void lse_pairs(int n, int lane, float alpha, const float* sH,
+                                          const float* sVb, const float* sVd, float& mx,
+                                          float& sm) {
+  const int nn = NT > 0 ? NT : n;
+  for (int q = lane; q < nn * nn; q += 64) {
+    const int i = q / nn, j = q % nn;
+    const float base = sH[5 * nn + i] + sH[5 * nn + j];
+    float v[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = LS ? fmaf(alpha, sVd[q * 5 + c], sVb[q * 5 + c]) : sVb[q * 5 + c];
+    auto ex = [&](int l) {
+      float x = base + sH[5 * nn + l];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) x = fmaf(v[c], sH[c * nn + l], x);
+      return x;
+    };
+    if constexpr (NT > 0) {
+      float e[NT];
+      float gm = -FLT_MAX;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) { e[l] = ex(l); gm = fmaxf(gm, e[l]); }
+      if (gm > mx) { sm *= __expf(mx - gm); mx = gm; }
+#pragma unroll
+      for (int l = 0; l < NT; ++l) sm += __expf(e[l] - mx);
+    } else {
+      float gm = -FLT_MAX;
+      for (int l = 0; l < nn; ++l) gm = fmaxf(gm, ex(l));
+      if (gm > mx) { sm *= __expf(mx - gm); mx = gm; }
+      for (int l = 0; l < nn; ++l) sm += __expf(ex(l) - mx);
+    }
+  }
+}
+
+template <bool LS, int NT>
+__global__ __launch_bounds__(64) void k_lse3(
+    const float2* __restrict__ t1, int n, const int32_t* __restrict__ list,
+    const int32_t* __restrict__ ctr, int64_t ncell, const float* __restrict__ M,
     float* __restrict__ beta, const float* __restrict__ dbeta, float* __restrict__ logZ,
     float* __restrict__ Lval, float* __restrict__ alpha_w, const float* __restrict__ gdot,
     SolveParams p, int32_t* reset_a, int32_t* reset_b) {
@@ -104,103 +163,109 @@ __global__ __launch_bounds__(256) void k_lse3(
     if (reset_a) *reset_a = 0;
     if (reset_b) *reset_b = 0;
   }
-  const int64_t count = ctr ? (int64_t)(*ctr) : n;
-  const int64_t tile = (int64_t)blockIdx.x * TILE;
-  if (tile >= count) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int kq = lane >> 4;
-  const int64_t slot = tile + wave * 16 + (lane & 15);
-  const bool valid = slot < count;
-  const int64_t cell = valid ? (list ? (int64_t)list[slot] : slot) : 0;
+  if (NT > 0) n = NT;
+  const int64_t count = ctr ? (int64_t)(*ctr) : ncell;
+  const int64_t slot = blockIdx.x;
+  if (slot >= count) return;
+  const int lane = threadIdx.x;
+  const int64_t cell = list ? (int64_t)list[slot] : slot;
+  extern __shared__ float dynf[];
+  float* sB = dynf;               // [36] beta, then dbeta at [36..71]
+  float* sH = dynf + 72;          // [6][n]: h_a(x_k), lw_k (high parts)
+  float* sUb = sH + 6 * n;        // [n][15]
+  float* sUd = sUb + n * NBC;     // [n][15]
+  float* sVb = sUd + n * NBC;     // [n*n][5]
+  float* sVd = sVb + n * n * 5;   // [n*n][5]
 
-  // lane holds coefficients k = 4j + kq of its cell (k = 0 multiplies log w~)
-  float b[NJ], d[NJ], m[NJ];
+  const bool kin = lane >= 1 && lane < K3;
+  const float bk = kin ? beta[cell * K3 + lane] : 0.f;
+  const float dk = (LS && kin) ? dbeta[cell * 36 + lane] : 0.f;
   // M may be null (log Z only): the linear term of L is then dropped
-  const float nn = (valid && M) ? M[cell * K3] : 1.f;
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int k = 4 * j + kq;
-    const bool in = valid && k >= 1 && k < K3;
-    b[j] = k == 0 ? 1.f : (in ? beta[cell * K3 + k] : 0.f);
-    d[j] = (LS && in) ? dbeta[cell * 36 + k] : 0.f;
-    m[j] = (in && M) ? M[cell * K3 + k] / nn : 0.f;
-  }
-  float L0 = 0.f, gd = 0.f;
-  if (LS && valid) { L0 = Lval[cell]; gd = gdot[cell]; }
-  float alpha = 1.f;
-  bool active = valid;
-
-  __shared__ float sA[LSE_CH * NJ * 64];
-  for (int s = 0;; ++s) {
-    float bt[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) bt[j] = (4 * j + kq == 0) ? 1.f : b[j] + alpha * d[j];
-    float mx = -FLT_MAX, sm = 0.f;
-    for (int g0 = 0; g0 < ngroups; g0 += LSE_CH) {
-      const int nch = min(LSE_CH, ngroups - g0);
-      __syncthreads();
-      const f4* src = reinterpret_cast<const f4*>(phiA + (size_t)g0 * NJ * 64);
-      for (int i = threadIdx.x; i < nch * NJ * 16; i += 256) reinterpret_cast<f4*>(sA)[i] = src[i];
-      __syncthreads();
-      for (int g = 0; g < nch; ++g) {
-        f4 e = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) e = mfma4(sA[(g * NJ + j) * 64 + lane], bt[j], e);
-        const float gm = fmaxf(fmaxf(e[0], e[1]), fmaxf(e[2], e[3]));
-        if (gm > mx) { sm *= __expf(mx - gm); mx = gm; }
-        sm += __expf(e[0] - mx) + __expf(e[1] - mx) + __expf(e[2] - mx) + __expf(e[3] - mx);
-      }
+  const float nn = M ? M[cell * K3] : 1.f;
+  const float mk = (M && kin) ? M[cell * K3 + lane] / nn : 0.f;
+  if (lane < 36) { sB[lane] = bk; sB[36 + lane] = dk; }
+  for (int t = lane; t < 6 * n; t += 64) sH[t] = t1[t].x;
+  __builtin_amdgcn_wave_barrier();
+  for (int t = lane; t < n * NBC; t += 64) {
+    const int i = t / NBC, bc = t % NBC;
+    int m = 0;
+    while (tri(m + 1) <= bc) ++m;
+    const int c = bc - tri(m), b = m - c;
+    float ub = 0.f, ud = 0.f;
+    for (int a = 0; a <= 4 - m; ++a) {
+      const int k = bidx3(a, b, c);
+      const float ha = sH[a * n + i];
+      ub = fmaf(sB[k], ha, ub);       // sB[0] = 0: beta_0 enters through log Z
+      if (LS) ud = fmaf(sB[36 + k], ha, ud);
     }
-    // combine the four lanes that hold the same cell (lanes l, l^16, l^32, l^48)
+    sUb[t] = ub;
+    if (LS) sUd[t] = ud;
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (int t = lane; t < n * n * 5; t += 64) {
+    const int ij = t / 5, c = t % 5, i = ij / n, j = ij % n;
+    float vb = 0.f, vd = 0.f;
+    for (int b = 0; b <= 4 - c; ++b) {
+      const float hb = sH[b * n + j];
+      vb = fmaf(sUb[i * NBC + tri(b + c) + c], hb, vb);
+      if (LS) vd = fmaf(sUd[i * NBC + tri(b + c) + c], hb, vd);
+    }
+    sVb[t] = vb;
+    if (LS) sVd[t] = vd;
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  float L0 = 0.f, gd = 0.f;
+  if (LS) { L0 = Lval[cell]; gd = gdot[cell]; }
+  float alpha = 1.f;
+  for (int s = 0;; ++s) {
+    float mx = -FLT_MAX, sm = 0.f;
+    lse_pairs<LS, NT>(n, lane, alpha, sH, sVb, sVd, mx, sm);
 #pragma unroll
-    for (int off = 16; off <= 32; off <<= 1) {
+    for (int off = 32; off > 0; off >>= 1) {
       const float om = __shfl_xor(mx, off), os = __shfl_xor(sm, off);
       const float nm = fmaxf(mx, om);
       sm = sm * __expf(mx - nm) + os * __expf(om - nm);
       mx = nm;
     }
     const float lz = mx + __logf(sm);
-    float dot = 0.f;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) dot += bt[j] * m[j];
-    dot += __shfl_xor(dot, 16);
-    dot += __shfl_xor(dot, 32);
-    const float Lt = lz - dot;  // dual objective up to the constant beta_0 term
-
+    const float bt = fmaf(alpha, dk, bk);
+    const float Lt = lz - wave_sum(bt * mk);  // dual objective up to the beta_0 term
     if (!LS) {
-      if (valid && kq == 0) { logZ[cell] = lz; Lval[cell] = Lt; }
-      break;
+      if (lane == 0) { logZ[cell] = lz; Lval[cell] = Lt; }
+      return;
     }
     // Armijo test with the floating-point tolerance (Alg. 1, ArmijoCondition)
     const float LD = L0 - Lt;
     const float gradD = -p.c * alpha * gd;
     const bool sat = (LD - gradD) >= -(p.atol + p.rtol * fabsf(LD));
-    const bool finish = active && (sat || s >= p.max_ls);  // last trial is kept (Alg. 1)
-    if (finish) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int k = 4 * j + kq;
-        if (k >= 1 && k < K3) beta[cell * K3 + k] = bt[j];
-      }
-      if (kq == 0) { logZ[cell] = lz; Lval[cell] = Lt; alpha_w[cell] = alpha; }
-      active = false;
-    } else if (active) {
-      alpha *= 0.5f;
+    if (sat || s >= p.max_ls) {  // the last trial is kept (Alg. 1)
+      if (kin) beta[cell * K3 + lane] = bt;
+      if (lane == 0) { logZ[cell] = lz; Lval[cell] = Lt; alpha_w[cell] = alpha; }
+      return;
     }
-    if (!__syncthreads_or(active ? 1 : 0)) break;
+    alpha *= 0.5f;
   }
 }
 
 // --------------------------------------------------------------------------
 // assembly: S[cell][col] = sum_p sigma_p Psi[p][col] on FP32 MFMA
 // --------------------------------------------------------------------------
+// Split mode (nsplit > 1, few live cells): workgroup b takes tile b % ntile
+// and node groups [split * ngroups / nsplit, (split + 1) * ngroups / nsplit)
+// of split = b / ntile, and writes its partial sums to
+// Sp[split][slot][NCOL]; k_sum_splits adds them in a fixed order.
 __global__ __launch_bounds__(256, 2) void k_assemble3(
     const float* __restrict__ phiA, const float* __restrict__ psi, int ngroups,
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr, int64_t n,
-    const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ S) {
+    const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ S,
+    int ntile, int nsplit, float* __restrict__ Sp) {
   const int64_t count = ctr ? (int64_t)(*ctr) : n;
-  const int64_t tile = (int64_t)blockIdx.x * TILE;
+  const int split = (int)(blockIdx.x / ntile);
+  const int64_t tile = (int64_t)(blockIdx.x % ntile) * TILE;
   if (tile >= count) return;
+  const int gbeg = (int)((int64_t)split * ngroups / nsplit);
+  const int gend = (int)((int64_t)(split + 1) * ngroups / nsplit);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
   const int64_t slot = tile + wave * 16 + (lane & 15);
@@ -221,7 +286,7 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
 
   __shared__ f4 sB[4 * 10 * 64];   // 40 KB: Psi operand of one node group
   __shared__ float sA[NJ * 64];    // exponent operand of one node group
-  for (int g = 0; g < ngroups; ++g) {
+  for (int g = gbeg; g < gend; ++g) {
     __syncthreads();
     {
       const f4* src = reinterpret_cast<const f4*>(psi) + (size_t)g * (4 * 10 * 64);
@@ -254,12 +319,37 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
   for (int q = 0; q < 4; ++q) {
     const int64_t sl = tile + wave * 16 + 4 * kq + q;
     if (sl < count) {
-      const int64_t cw = list ? (int64_t)list[sl] : sl;
-      float* dst = S + cw * NCOL + (lane & 15);
+      float* dst;
+      if (nsplit > 1) {
+        dst = Sp + ((size_t)split * ntile * TILE + sl) * NCOL + (lane & 15);
+      } else {
+        const int64_t cw = list ? (int64_t)list[sl] : sl;
+        dst = S + cw * NCOL + (lane & 15);
+      }
 #pragma unroll
       for (int b = 0; b < NBLK; ++b) dst[16 * b] = acc[b][q];
     }
   }
+}
+
+// S[cell] = sum over splits of Sp[split][slot] (fixed order: deterministic).
+__global__ void k_sum_splits(const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
+                             int64_t n, int ntile, int nsplit, const float* __restrict__ Sp,
+                             float* __restrict__ S) {
+  const int64_t count = ctr ? (int64_t)(*ctr) : n;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t slot = t / (NCOL / 4);
+  const int q = (int)(t % (NCOL / 4));
+  if (slot >= count) return;
+  const int64_t cell = list ? (int64_t)list[slot] : slot;
+  const size_t stride = (size_t)ntile * TILE * NCOL;
+  const f4* src = reinterpret_cast<const f4*>(Sp + (size_t)slot * NCOL) + q;
+  f4 acc = src[0];
+  for (int k = 1; k < nsplit; ++k) {
+    const f4 v = *reinterpret_cast<const f4*>(Sp + k * stride + (size_t)slot * NCOL + 4 * q);
+    acc += v;
+  }
+  reinterpret_cast<f4*>(S + cell * NCOL)[q] = acc;
 }
 
 // --------------------------------------------------------------------------
@@ -438,13 +528,6 @@ __device__ __forceinline__ void wave_solve(const T (&a)[NH], const T* Lm, T dinv
     if (lane == i) d = di;
     if (lane < i) acc2 = fma(-a[i] * inv, di, acc2);
   }
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
 }
 
 // Column `lane` of H = S/s00 - E E^T (i, j >= 1), plus lam on the diagonal.
@@ -699,14 +782,6 @@ __device__ __forceinline__ dfl df_norm(dfl a) {
   return {h, a.l - (h - a.h)};
 }
 
-__device__ __forceinline__ int tri(int m) { return m * (m + 1) / 2; }
-__device__ __forceinline__ int bidx3(int a, int b, int c) {
-  const int t = a + b + c, m = b + c;
-  return t * (t + 1) * (t + 2) / 6 + tri(m) + c;
-}
-
-constexpr int NBC = 15;  // (b, c) with b + c <= 4
-
 // One 64-thread workgroup per cell.  t1 = one-dimensional tables, double-float:
 // t1[a * n + k] = h_a(x_k) (a = 0..4), t1[5 * n + k] = lw_k.
 __global__ __launch_bounds__(64) void k_accurate3(
@@ -916,13 +991,37 @@ hipError_t launch_init3(mem_ctx_t c, int64_t n, const float* M, float* beta, int
 hipError_t launch_lse3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
                        int64_t n, const float* M, float* beta, bool line_search,
                        const SolveParams& p, int32_t* reset_a, int32_t* reset_b, hipStream_t s) {
-  const unsigned nb = nblocks(grid_cells > 0 ? grid_cells : 1, TILE);
-  if (line_search)
-    k_lse3<true><<<nb, 256, 0, s>>>(c->d_phiA, c->ngroups, list, ctr, n, M, beta, c->w_dbeta,
-                                    c->w_logZ, c->w_L, c->w_alpha, c->w_gdot, p, reset_a, reset_b);
-  else
-    k_lse3<false><<<nb, 256, 0, s>>>(c->d_phiA, c->ngroups, list, ctr, n, M, beta, c->w_dbeta,
-                                     c->w_logZ, c->w_L, c->w_alpha, c->w_gdot, p, reset_a, reset_b);
+  const unsigned nb = (unsigned)(grid_cells > 0 ? grid_cells : 1);
+  const int n1 = c->n1d;
+  const size_t lds = (size_t)(72 + 6 * n1 + 2 * n1 * NBC + 2 * n1 * n1 * 5) * sizeof(float);
+#define MEM_LSE(LS, NT)                                                                         \
+  k_lse3<LS, NT><<<nb, 64, lds, s>>>(c->d_t1, n1, list, ctr, n, M, beta, c->w_dbeta, c->w_logZ, \
+                                     c->w_L, c->w_alpha, c->w_gdot, p, reset_a, reset_b)
+  if (line_search) {
+    if (n1 == 12) MEM_LSE(true, 12); else MEM_LSE(true, 0);
+  } else {
+    if (n1 == 12) MEM_LSE(false, 12); else MEM_LSE(false, 0);
+  }
+#undef MEM_LSE
+  return hipGetLastError();
+}
+
+// Node-range splits for a launch of ntile 64-cell tiles: enough workgroups to
+// fill the chip when few cells are live, at least 4 node groups per split,
+// partial sums within the split buffer.
+int assembly_splits(mem_ctx_t c, int ntile, int ngroups) {
+  const int want = 512;  // workgroups
+  if (ntile >= want / 2 || !c->w_Sp) return 1;
+  int ns = (want + ntile - 1) / ntile;
+  ns = std::min(ns, std::max(1, ngroups / 4));
+  while (ns > 1 && (int64_t)ns * ntile * TILE > c->sp_rows) --ns;
+  return ns;
+}
+
+hipError_t launch_sum_splits(mem_ctx_t c, const int32_t* list, const int32_t* ctr, int64_t n,
+                             int ntile, int nsplit, float* S, hipStream_t s) {
+  k_sum_splits<<<(unsigned)nblocks((int64_t)ntile * TILE * (NCOL / 4), 256), 256, 0, s>>>(
+      list, ctr, n, ntile, nsplit, c->w_Sp, S);
   return hipGetLastError();
 }
 
@@ -930,8 +1029,13 @@ hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
                             const int32_t* ctr, int64_t n, const float* beta, const float* table,
                             float* S, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  k_assemble3<<<nblocks(grid_cells, TILE), 256, 0, s>>>(c->d_phiA, table, c->ngroups, list, ctr, n,
-                                                        beta, c->w_logZ, S);
+  const int ntile = (int)nblocks(grid_cells, TILE);
+  const int nsplit = assembly_splits(c, ntile, c->ngroups);
+  k_assemble3<<<(unsigned)(ntile * nsplit), 256, 0, s>>>(c->d_phiA, table, c->ngroups, list, ctr, n,
+                                                         beta, c->w_logZ, S, ntile, nsplit, c->w_Sp);
+  if (nsplit > 1)
+    k_sum_splits<<<(unsigned)nblocks((int64_t)ntile * TILE * (NCOL / 4), 256), 256, 0, s>>>(
+        list, ctr, n, ntile, nsplit, c->w_Sp, S);
   return hipGetLastError();
 }
 

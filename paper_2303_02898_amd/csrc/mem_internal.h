@@ -81,6 +81,8 @@ struct mem_ctx_s {
   int32_t* w_list[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t* w_ctr = nullptr;   // [8] list counters
   int8_t* w_code = nullptr;   // [cap] per-slot outcome of the direction kernel
+  float* w_Sp = nullptr;      // [sp_rows][NCOL] partial sums of node-range splits
+  int64_t sp_rows = 0;
   float* w_Gacc = nullptr;    // [cap][36] compensated gradient E[phi_i] - M_i/n
   float* w_racc = nullptr;    // [cap] compensated residual
   float* w_rbest = nullptr;   // [cap] best FP32 residual so far (stall test)
@@ -133,6 +135,10 @@ hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
 hipError_t launch_assemble3m(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                              const int32_t* ctr, int64_t n, const float* beta, float* S,
                              hipStream_t s);
+// Splits of the node range for small launches (1 = none) and their sum.
+int assembly_splits(mem_ctx_t c, int ntile, int ngroups);
+hipError_t launch_sum_splits(mem_ctx_t c, const int32_t* list, const int32_t* ctr, int64_t n,
+                             int ntile, int nsplit, float* S, hipStream_t s);
 hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                              const int32_t* ctr, const float* M, const float* beta,
                              const SolveParams& p,
