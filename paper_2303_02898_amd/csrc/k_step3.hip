@@ -154,154 +154,224 @@ __global__ void k_flux3(int64_t n, const float* __restrict__ S, const float* __r
 
 // ---- characteristic speeds -------------------------------------------------------
 // Eigenvalues of dF/dM solve C v = mu B v with B = E[phi phi^T], C = E[u_bar_x
-// phi phi^T] (35 x 35, phi_0 included); lambda = w + s_x mu.  Per cell:
-// Cholesky B = L L^T, A = L^-1 C L^-T, Householder tridiagonalisation of A,
-// Sturm bisection for the extreme eigenvalues.  One thread per cell, matrices
-// in LDS (cell-interleaved).
-constexpr int EIG_CPW = 20;  // cells per workgroup (LDS bound)
-constexpr int EIG_L = 630, EIG_A = K3 * K3;
-constexpr int EIG_PER = EIG_L + EIG_A + 4 * K3;
+// phi phi^T] (35 x 35, phi_0 included); lambda = w + s_x mu.  One wavefront per
+// cell, lane j holding column j of the current matrix in registers:
+//   * Cholesky B = L L^T (pivot by readlane, column k of L shared through LDS);
+//   * A = L^-1 C L^-T by two lane-parallel forward substitutions (each lane
+//     solves for its own column), the transposes through LDS;
+//   * Householder tridiagonalisation of A (Householder vector and p - K v
+//     shared through LDS, lane-parallel rank-2 updates);
+//   * extreme eigenvalues of the tridiagonal matrix by multisection: every
+//     lane evaluates a Sturm count at its own shift, 64 subintervals per round.
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int EIG_WAVES = 4;
+constexpr int EST = 36;  // row stride of the per-wave LDS matrices
 
-__device__ __forceinline__ int lidx(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
+__device__ __forceinline__ float rlf(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ float wsum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ float wmin(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ float wmax(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
 
-__global__ __launch_bounds__(64) void k_eig3(int64_t n, const float* __restrict__ S,
-                                             const float* __restrict__ Sx,
-                                             const float* __restrict__ g, float umax,
-                                             float* __restrict__ out, int radius_only,
-                                             uint32_t* status) {
-  __shared__ float sh[EIG_PER * EIG_CPW];
-  const int t = threadIdx.x;
-  const int64_t c = (int64_t)blockIdx.x * EIG_CPW + t;
-  if (t >= EIG_CPW || c >= n) return;
-#define LL(i, j) sh[(lidx(i, j)) * EIG_CPW + t]
-#define AA(i, j) sh[(EIG_L + (i) * K3 + (j)) * EIG_CPW + t]
-#define VV(i) sh[(EIG_L + EIG_A + (i)) * EIG_CPW + t]
-#define PP(i) sh[(EIG_L + EIG_A + K3 + (i)) * EIG_CPW + t]
-#define DD(i) sh[(EIG_L + EIG_A + 2 * K3 + (i)) * EIG_CPW + t]
-#define EE(i) sh[(EIG_L + EIG_A + 3 * K3 + (i)) * EIG_CPW + t]
-  const float* Sc = S + c * NCOL;
-  const float* Xc = Sx + c * NCOL;
-  const float inv0 = 1.f / Sc[0];
+__global__ __launch_bounds__(256) void k_eig3(int64_t n, const float* __restrict__ S,
+                                              const float* __restrict__ Sx,
+                                              const float* __restrict__ g, float umax,
+                                              float* __restrict__ out, int radius_only,
+                                              uint32_t* status) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * EIG_WAVES + wv;
+  if (c >= n) return;  // whole wave
+  __shared__ __align__(16) float sbuf[EIG_WAVES][2 * K3 * EST];  // S, Sx rows; then L and T
+  __shared__ float svec[EIG_WAVES][5][EST];                     // 1/L_kk, v, q, d, e
+  float* W = sbuf[wv];
+  float* Lm = W;              // row k = column k of L
+  float* T = W + K3 * EST;    // transposes
+  float* invd = svec[wv][0];
+  float* vb = svec[wv][1];
+  float* qb = svec[wv][2];
+  float* dd = svec[wv][3];
+  float* ee = svec[wv][4];
+  {
+    const f4* s4 = reinterpret_cast<const f4*>(S + c * NCOL);
+    const f4* x4 = reinterpret_cast<const f4*>(Sx + c * NCOL);
+    f4* w4 = reinterpret_cast<f4*>(W);
+    for (int i = lane; i < NCOL / 4; i += 64) { w4[i] = s4[i]; w4[NCOL / 4 + i] = x4[i]; }
+  }
+  __builtin_amdgcn_wave_barrier();
+  const float inv0 = 1.f / W[0];
   bool ok = isfinite(inv0) && inv0 > 0.f;
-  for (int i = 0; i < K3; ++i)
-    for (int j = 0; j <= i; ++j) {
-      LL(i, j) = Sc[pair_col(j, i)] * inv0;
-      const float cv = Xc[pair_col(j, i)] * inv0;
-      AA(i, j) = cv;
-      AA(j, i) = cv;
-    }
-  // Cholesky of B (lower)
-  for (int k = 0; k < K3 && ok; ++k) {
-    float d = LL(k, k);
-    for (int j = 0; j < k; ++j) d -= LL(k, j) * LL(k, j);
-    if (!(d > 0.f) || !isfinite(d)) { ok = false; break; }
-    const float lkk = sqrtf(d);
-    LL(k, k) = lkk;
-    for (int i = k + 1; i < K3; ++i) {
-      float s = LL(i, k);
-      for (int j = 0; j < k; ++j) s -= LL(i, j) * LL(k, j);
-      LL(i, k) = s / lkk;
+  const int j = lane < K3 ? lane : 0;
+  float a[K3], x[K3];
+#pragma unroll
+  for (int i = 0; i < K3; ++i) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    a[i] = W[pair_col(lo, hi)] * inv0;
+    x[i] = W[NCOL + pair_col(lo, hi)] * inv0;
+  }
+  __builtin_amdgcn_wave_barrier();  // the staging area becomes L and T
+
+  // Cholesky of B
+  float dinv = 1.f;
+#pragma unroll
+  for (int k = 0; k < K3; ++k) {
+    const float d = rlf(a[k], k);
+    ok = ok && d > 0.f && isfinite(d);
+    const float inv = __builtin_amdgcn_rsqf(d);
+    const float l = lane >= k ? a[k] * inv : 0.f;
+    if (lane == k) dinv = inv;
+    if (lane < K3) Lm[k * EST + lane] = l;
+    if (k == K3 - 1) break;
+    __builtin_amdgcn_wave_barrier();
+    float lb[K3];
+#pragma unroll
+    for (int i = k + 1; i < K3; ++i) lb[i] = Lm[k * EST + i];
+    if (lane > k) {
+#pragma unroll
+      for (int i = k + 1; i < K3; ++i) a[i] = fmaf(-lb[i], l, a[i]);
     }
   }
-  float mu_lo = 0.f, mu_hi = 0.f;
-  if (ok) {
-    // Y = L^-1 C (columns), then A = L^-1 Y^T (rows, in place)
-    for (int j = 0; j < K3; ++j)
-      for (int i = 0; i < K3; ++i) {
-        float s = AA(i, j);
-        for (int k = 0; k < i; ++k) s -= LL(i, k) * AA(k, j);
-        AA(i, j) = s / LL(i, i);
-      }
-    for (int j = 0; j < K3; ++j)
-      for (int i = 0; i < K3; ++i) {
-        float s = AA(j, i);
-        for (int k = 0; k < i; ++k) s -= LL(i, k) * AA(j, k);
-        AA(j, i) = s / LL(i, i);
-      }
-    // symmetrise against rounding
-    for (int i = 0; i < K3; ++i)
-      for (int j = 0; j < i; ++j) {
-        const float v = 0.5f * (AA(i, j) + AA(j, i));
-        AA(i, j) = v; AA(j, i) = v;
-      }
-    // Householder tridiagonalisation
-    for (int k = 0; k < K3 - 2; ++k) {
-      float sig = 0.f;
-      for (int i = k + 1; i < K3; ++i) sig += AA(i, k) * AA(i, k);
-      const float nx = sqrtf(sig);
-      if (nx == 0.f) { DD(k) = AA(k, k); EE(k) = 0.f; continue; }
-      const float x0 = AA(k + 1, k);
-      const float al = x0 > 0.f ? -nx : nx;
-      for (int i = k + 1; i < K3; ++i) VV(i) = AA(i, k);
-      VV(k + 1) = x0 - al;
-      float vn = 0.f;
-      for (int i = k + 1; i < K3; ++i) vn += VV(i) * VV(i);
-      DD(k) = AA(k, k);
-      EE(k) = al;
-      if (vn == 0.f) continue;
-      const float bet = 2.f / vn;
-      float vp = 0.f;
-      for (int i = k + 1; i < K3; ++i) {
-        float s = 0.f;
-        for (int j = k + 1; j < K3; ++j) s += AA(i, j) * VV(j);
-        PP(i) = bet * s;
-        vp += VV(i) * PP(i);
-      }
-      const float Kc = 0.5f * bet * vp;
-      for (int i = k + 1; i < K3; ++i) PP(i) -= Kc * VV(i);
-      for (int i = k + 1; i < K3; ++i)
-        for (int j = k + 1; j < K3; ++j) AA(i, j) -= VV(i) * PP(j) + PP(i) * VV(j);
+  if (lane < K3) invd[lane] = dinv;
+  __builtin_amdgcn_wave_barrier();
+  // forward substitution L y = x on this lane's column
+  auto fsolve = [&](float (&y)[K3]) {
+#pragma unroll
+    for (int k = 0; k < K3; ++k) {
+      const float yk = y[k] * invd[k];
+      y[k] = yk;
+#pragma unroll
+      for (int i = k + 1; i < K3; ++i) y[i] = fmaf(-Lm[k * EST + i], yk, y[i]);
     }
-    DD(K3 - 2) = AA(K3 - 2, K3 - 2);
-    DD(K3 - 1) = AA(K3 - 1, K3 - 1);
-    EE(K3 - 2) = AA(K3 - 1, K3 - 2);
-    // Gershgorin bracket, then Sturm bisection for the smallest and largest
-    float lo = FLT_MAX, hi = -FLT_MAX;
+  };
+  // column j of the transpose: T[j][i] = y[i] written by lane j, read back as T[i][j]
+  auto transpose = [&](float (&y)[K3], bool average) {
+    if (lane < K3) {
+#pragma unroll
+      for (int i = 0; i < K3; ++i) T[lane * EST + i] = y[i];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
     for (int i = 0; i < K3; ++i) {
-      const float r = (i > 0 ? fabsf(EE(i - 1)) : 0.f) + (i < K3 - 1 ? fabsf(EE(i)) : 0.f);
-      lo = fminf(lo, DD(i) - r);
-      hi = fmaxf(hi, DD(i) + r);
+      const float t = T[i * EST + j];
+      y[i] = average ? 0.5f * (y[i] + t) : t;
     }
-    auto count_below = [&](float x) {
-      int cnt = 0;
-      float q = DD(0) - x;
+    __builtin_amdgcn_wave_barrier();
+  };
+  fsolve(x);              // column j of Y = L^-1 C
+  transpose(x, false);    // column j of Y^T (C symmetric: Y^T = C L^-T)
+  fsolve(x);              // column j of A = L^-1 C L^-T
+  transpose(x, true);     // symmetrised against rounding
+
+  // Householder tridiagonalisation: d_k = A[k][k], e_k = A[k+1][k] of the result
+#pragma unroll
+  for (int k = 0; k < K3 - 2; ++k) {
+    if (lane == k) {
+      dd[k] = x[k];
+#pragma unroll
+      for (int i = k + 1; i < K3; ++i) vb[i] = x[i];
+    }
+    __builtin_amdgcn_wave_barrier();
+    float sig = 0.f;
+#pragma unroll
+    for (int i = k + 1; i < K3; ++i) sig = fmaf(vb[i], vb[i], sig);
+    const float x0 = vb[k + 1];
+    const float nx = sqrtf(sig);
+    const float al = x0 > 0.f ? -nx : nx;
+    const float v1 = x0 - al;           // first entry of the Householder vector
+    const float vn = sig - x0 * x0 + v1 * v1;
+    if (lane == 0) ee[k] = al;
+    if (nx > 0.f && vn > 0.f) {
+      const float bet = 2.f / vn;
+      float w = 0.f;
+#pragma unroll
+      for (int i = k + 1; i < K3; ++i) w = fmaf(x[i], i == k + 1 ? v1 : vb[i], w);
+      const bool act = lane > k && lane < K3;
+      const float vj = act ? (lane == k + 1 ? v1 : vb[j]) : 0.f;
+      const float pj = act ? bet * w : 0.f;
+      const float Kc = 0.5f * bet * wsum(vj * pj);
+      const float qj = pj - Kc * vj;
+      if (lane < K3) qb[lane] = qj;
+      __builtin_amdgcn_wave_barrier();
+      if (act) {
+#pragma unroll
+        for (int i = k + 1; i < K3; ++i) {
+          const float vi = i == k + 1 ? v1 : vb[i];
+          x[i] = x[i] - (vi * qj + qb[i] * vj);
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane == K3 - 2) { dd[K3 - 2] = x[K3 - 2]; ee[K3 - 2] = x[K3 - 1]; }
+  if (lane == K3 - 1) dd[K3 - 1] = x[K3 - 1];
+  __builtin_amdgcn_wave_barrier();
+
+  // Gershgorin bracket, then multisection with Sturm counts
+  float glo = FLT_MAX, ghi = -FLT_MAX;
+  if (lane < K3) {
+    const float r = (lane > 0 ? fabsf(ee[lane - 1]) : 0.f) + (lane < K3 - 1 ? fabsf(ee[lane]) : 0.f);
+    glo = dd[lane] - r;
+    ghi = dd[lane] + r;
+  }
+  glo = wmin(glo);
+  ghi = wmax(ghi);
+  auto count_below = [&](float xs) {
+    int cnt = 0;
+    float q = dd[0] - xs;
+    if (q == 0.f) q = -1e-30f;
+    if (q < 0.f) ++cnt;
+    for (int i = 1; i < K3; ++i) {
+      q = dd[i] - xs - ee[i - 1] * ee[i - 1] / q;
       if (q == 0.f) q = -1e-30f;
       if (q < 0.f) ++cnt;
-      for (int i = 1; i < K3; ++i) {
-        q = DD(i) - x - EE(i - 1) * EE(i - 1) / q;
-        if (q == 0.f) q = -1e-30f;
-        if (q < 0.f) ++cnt;
-      }
-      return cnt;
-    };
-    float a = lo, b = hi;
-    for (int it = 0; it < 48; ++it) {
-      const float mid = 0.5f * (a + b);
-      if (count_below(mid) >= 1) b = mid; else a = mid;
     }
-    mu_lo = 0.5f * (a + b);
-    a = lo; b = hi;
-    for (int it = 0; it < 48; ++it) {
-      const float mid = 0.5f * (a + b);
-      if (count_below(mid) >= K3) b = mid; else a = mid;
+    return cnt;
+  };
+  // smallest x with count_below(x) >= need: the bracket [lo, hi] always has
+  // count_below(hi) >= need, and lane 63 samples hi itself
+  auto extreme = [&](int need) {
+    float lo = glo, hi = ghi;
+    for (int round = 0; round < 5; ++round) {
+      const float wdt = hi - lo;
+      const float xs = lane == 63 ? hi : lo + wdt * (float)(lane + 1) * (1.f / 64.f);
+      const unsigned long long m = __ballot(count_below(xs) >= need);
+      if (m == 0ull) break;
+      const int f = __ffsll((long long)m) - 1;
+      const float nh = f == 63 ? hi : lo + wdt * (float)(f + 1) * (1.f / 64.f);
+      lo = lo + wdt * (float)f * (1.f / 64.f);
+      hi = nh;
     }
-    mu_hi = 0.5f * (a + b);
+    return 0.5f * (lo + hi);
+  };
+  float mu_lo = 0.f, mu_hi = 0.f;
+  if (ok) {
+    mu_lo = extreme(1);
+    mu_hi = extreme(K3);
     ok = isfinite(mu_lo) && isfinite(mu_hi);
   }
   if (!ok) {  // bound |mu| <= max_p |u_bar_x,p|
-    mu_lo = -umax; mu_hi = umax;
-    if (status) status[c] |= MEM_ST_LAMBDA_FAIL;
+    mu_lo = -umax;
+    mu_hi = umax;
   }
-  const float w = g[c * 3], sx = g[c * 3 + 1];
-  const float l0 = w + sx * mu_lo, l1 = w + sx * mu_hi;
-  if (radius_only) out[c] = fmaxf(fabsf(l0), fabsf(l1));
-  else { out[c * 2] = l0; out[c * 2 + 1] = l1; }
-#undef LL
-#undef AA
-#undef VV
-#undef PP
-#undef DD
-#undef EE
+  if (lane == 0) {
+    if (!ok && status) status[c] |= MEM_ST_LAMBDA_FAIL;
+    const float w = g[c * 3], sx = g[c * 3 + 1];
+    const float l0 = w + sx * mu_lo, l1 = w + sx * mu_hi;
+    if (radius_only) out[c] = fmaxf(fabsf(l0), fabsf(l1));
+    else { out[c * 2] = l0; out[c * 2 + 1] = l1; }
+  }
 }
 
 // ---- ES-BGK collision -----------------------------------------------------------
@@ -534,7 +604,7 @@ hipError_t launch_flux3(mem_ctx_t c, int64_t n, const float* beta, const float* 
     if (e != hipSuccess) return e;
     double um = 0.0;
     for (int p = 0; p < c->Q; ++p) um = fmax(um, fabs(c->h_nodes[(size_t)p * 3]));
-    k_eig3<<<nb(n, EIG_CPW), 64, 0, s>>>(n, c->w_S, c->w_Sx, g, (float)um, out, radius_only ? 1 : 0,
+    k_eig3<<<nb(n, EIG_WAVES), 256, 0, s>>>(n, c->w_S, c->w_Sx, g, (float)um, out, radius_only ? 1 : 0,
                                          status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
