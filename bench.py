@@ -118,6 +118,108 @@ def mixed_comparison(mem, torch, dev, cells, steps, warmup):
     return out
 
 
+def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph):
+    """Device state and batch for a list of shock problems (gauge applied)."""
+    import mem_inputs
+    M = np.concatenate([p["M"] for p in probs]).astype(np.float32)
+    g = np.concatenate([p["g"] for p in probs]).astype(np.float32)
+    counts = [p["M"].shape[0] for p in probs]
+    off = np.concatenate([[0], np.cumsum(counts)])
+    Md, gd = torch.tensor(M, device=dev), torch.tensor(g, device=dev)
+    ctx.gauge(Md, None, gd)
+    bd = torch.tensor(mem_inputs.maxwellian_beta(M.shape[0], 35, Md[:, 0].cpu().numpy())
+                      .astype(np.float32), device=dev)
+    batch = mem.ShockBatch(off, dx, np.stack([p["M_left"] for p in probs]),
+                           np.stack([p["M_right"] for p in probs]),
+                           np.stack([p["g_left"] for p in probs]),
+                           np.stack([p["g_right"] for p in probs]), device=dev,
+                           use_graph=use_graph)
+    P = len(probs)
+    return batch, Md, bd, gd, torch.zeros(P, device=dev), torch.zeros(P, device=dev)
+
+
+def shock_steady(mem, torch, dev, max_steps):
+    """Mach-3 normal shock, 1000 cells on [-20, 20]: step rate and time to steady state."""
+    import mem_inputs
+    ctx = mem.Context(3, 12)
+    pr = mem_inputs.shock_problem(3.0, 1000, -20.0, 20.0, 5.44)
+    b, M, be, g, t, dt = shock_setup(mem, torch, dev, ctx, [pr], [pr["dx"]], True)
+    ctx.step(b, M, be, g, t, dt, 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(b, M, be, g, t, dt, 500)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / 500
+    (n1, v1, T1), (n2, v2, T2) = pr["states"]
+    prev = M[:, 0].clone()
+    steps, change = 510, float("inf")
+    t0 = time.perf_counter()
+    while steps < max_steps and change > 2e-5:
+        ctx.step(b, M, be, g, t, dt, 100)
+        steps += 100
+        cur = M[:, 0].clone()
+        change = (cur - prev).abs().max().item() / (n2 - n1)
+        prev = cur
+    wall = time.perf_counter() - t0
+    n = M[:, 0].cpu().numpy()
+    ctx.close()
+    return {"workload": "Mach-3 normal shock, 1000 cells on [-20, 20] (upstream mean free "
+                        "path 1), ES-BGK Pr 2/3, LLF, CFL 0.5, 12^3 nodes, 8 Newton iterations "
+                        "per step, hipGraph replay",
+            "ms_per_step": ms, "cell_steps_per_s": 1000 / (ms * 1e-3),
+            "steady": {"criterion": "max |n(k+100) - n(k)| / (n+ - n-) <= 2e-5",
+                       "steps": steps, "t": float(t.item()), "wall_s": wall + ms * 510e-3,
+                       "last_change": change, "reached": change <= 2e-5,
+                       "n_ends": [float(n[0]), float(n[-1])], "n_rankine_hugoniot": [n1, n2]}}
+
+
+def ragged_rate(mem, torch, dev, steps):
+    """2048 independent shocks, log-uniform cell counts in [64, 4096]: cell-steps/s."""
+    import mem_inputs
+    rb = mem_inputs.ragged_batch(2048)
+    ctx = mem.Context(3, 12)
+    b, M, be, g, t, dt = shock_setup(mem, torch, dev, ctx, rb["problems"], [rb["dx"]] * 2048, True)
+    ctx.step(b, M, be, g, t, dt, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(b, M, be, g, t, dt, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": f"2048 normal shocks (Mach U(1.2,10), tanh initial profiles), cell counts "
+                        f"log-uniform in [64, 4096] ({b.n_cells} cells), dx = 1, {steps} steps, "
+                        "hipGraph replay",
+            "cells": b.n_cells, "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "cell_steps_per_s": b.n_cells * steps / el}
+
+
+def latency_1d(mem, torch, dev, calls=200):
+    """1D 5-moment solve of 1024 cells (16 nodes): wall time per call."""
+    import mem_inputs
+    d = mem_inputs.mixture_1d(1024)
+    ctx = mem.Context(1, 16)
+    Md = torch.tensor(d["M"].astype(np.float32), device=dev)
+    gd = torch.tensor(d["g"].astype(np.float32), device=dev)
+    b0 = np.zeros((1024, 5), np.float32)
+    b0[:, 0] = d["M"][:, 0]
+    b0[:, 2] = -1.0 / np.sqrt(2.0)
+    b0d = torch.tensor(b0, device=dev)
+    bg = b0d.clone()
+    it, rs, st = ctx.solve(Md, bg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        bg.copy_(b0d)
+        ctx.solve(Md, bg, None, it, rs, st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    conv = float(np.mean((st.cpu().numpy() & mem.ST_CONVERGED) != 0))
+    ctx.close()
+    return {"workload": "1D 5-moment solve, 1024 two-Gaussian mixtures in their Hermite "
+                        "gauge, 16 nodes, cold start", "us_per_call": 1e6 * el / calls,
+            "solves_per_s": 1024 * calls / el, "converged_fraction": conv}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +231,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-cells", type=int, default=262144,
                     help="cells of the FP32-vs-mixed comparison (0 = skip)")
+    ap.add_argument("--ragged-steps", type=int, default=200)
+    ap.add_argument("--shock-max-steps", type=int, default=40000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 1D, shock and ragged-batch measurements")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (a known-size "
                          "kernel for calibrating hardware byte counters)")
@@ -208,6 +314,11 @@ def main():
     }
     if args.mixed_cells > 0:
         line["mixed"] = mixed_comparison(mem, torch, dev, args.mixed_cells, 3, 1)
+    if not args.no_extras:
+        line["latency_1d"] = latency_1d(mem, torch, dev)
+        line["shock"] = shock_steady(mem, torch, dev, args.shock_max_steps)
+        if args.ragged_steps > 0:
+            line["ragged"] = ragged_rate(mem, torch, dev, args.ragged_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(M32, b032, args.cpu_sample)
     print(json.dumps(line), flush=True)

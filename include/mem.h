@@ -142,6 +142,12 @@ typedef struct {
   float          prandtl;        /* 2/3 for monatomic gas (App. A)                          */
   float          mu_ref;         /* viscosity at T = 1; tau = mu_ref / (Pr n)  (sqrt(2/pi)) */
   int32_t        newton_per_step;/* Newton iteration budget per time step (8)               */
+  int32_t        use_graph;      /* 1: the first call captures one time step into a hipGraph
+                                    (on a private stream of default priority) and every
+                                    step replays it with hipGraphLaunch on `stream`; the
+                                    graph is kept while the batch, state pointers and
+                                    options stay the same.  0: plain launches.  Results
+                                    are identical either way.                              */
 } mem_batch_t;
 
 /* ---- context -------------------------------------------------------------- */

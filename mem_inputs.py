@@ -107,6 +107,29 @@ def rankine_hugoniot(mach, gamma=GAMMA):
 # --------------------------------------------------------------------------
 # workload 1: 1D perturbed Maxwellians (targets built by the density evaluator)
 # --------------------------------------------------------------------------
+def mixture_1d(n_cells, replica=0):
+    """1D two-Gaussian mixtures given in their own Hermite gauge (closed form).
+
+    Weights nu ~ U(0, 1), densities n ~ U(0.5, 2), component means ~ N(0, 1),
+    variances ~ U(0.5, 2).  Returns M [n_cells][5] (orthonormal He_k / sqrt(k!)
+    moments times the density) and g [n_cells][2] = (mean, standard deviation).
+    """
+    rng = np.random.default_rng(seed_for(1, 100 + replica))
+    n = rng.uniform(0.5, 2.0, n_cells)
+    nu = rng.uniform(0.0, 1.0, n_cells)
+    v1, v2 = rng.normal(0.0, 1.0, n_cells), rng.normal(0.0, 1.0, n_cells)
+    T1, T2 = rng.uniform(0.5, 2.0, n_cells), rng.uniform(0.5, 2.0, n_cells)
+    mean = (1 - nu) * v1 + nu * v2
+    var = (1 - nu) * (T1 + v1 ** 2) + nu * (T2 + v2 ** 2) - mean ** 2
+    s = np.sqrt(var)
+    M = np.zeros((n_cells, 5))
+    for k in range(5):
+        e1 = hermite_gauss_moment(k, (v1 - mean) / s, T1 / var)
+        e2 = hermite_gauss_moment(k, (v2 - mean) / s, T2 / var)
+        M[:, k] = n * ((1 - nu) * e1 + nu * e2) / math.sqrt(math.factorial(k))
+    return dict(M=M, g=np.stack([mean, s], axis=1))
+
+
 def config1_candidates(n_pool=4096, replica=0):
     rng = np.random.default_rng(seed_for(1, replica))
     n = rng.uniform(0.5, 2.0, n_pool)

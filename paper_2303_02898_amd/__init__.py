@@ -46,7 +46,7 @@ class Batch(ctypes.Structure):
     _fields_ = [("n_cells", _c_i64), ("n_problems", _c_i32), ("collision", _c_i32),
                 ("cell_offsets", _vp), ("dx", _vp), ("M_left", _vp), ("M_right", _vp),
                 ("g_left", _vp), ("g_right", _vp), ("cfl", _c_f32), ("prandtl", _c_f32),
-                ("mu_ref", _c_f32), ("newton_per_step", _c_i32)]
+                ("mu_ref", _c_f32), ("newton_per_step", _c_i32), ("use_graph", _c_i32)]
 
 
 _lib = None
@@ -293,7 +293,7 @@ class ShockBatch:
 
     def __init__(self, offsets, dx, M_left, M_right, g_left, g_right, device="cuda",
                  cfl=0.5, prandtl=2.0 / 3.0, mu_ref=0.7978845608028654, collision=1,
-                 newton_per_step=8):
+                 newton_per_step=8, use_graph=False):
         import torch
         f32 = dict(dtype=torch.float32, device=device)
         self.offsets = torch.as_tensor(offsets, dtype=torch.int64, device=device).contiguous()
@@ -307,4 +307,5 @@ class ShockBatch:
         self.struct = Batch(self.n_cells, self.n_problems, int(collision), self.offsets.data_ptr(),
                             self.dx.data_ptr(), self.M_left.data_ptr(), self.M_right.data_ptr(),
                             self.g_left.data_ptr(), self.g_right.data_ptr(), float(cfl),
-                            float(prandtl), float(mu_ref), int(newton_per_step))
+                            float(prandtl), float(mu_ref), int(newton_per_step),
+                            int(bool(use_graph)))

@@ -253,6 +253,8 @@ mem_err_t mem_destroy(mem_ctx_t c) {
   dfree(c->d_psi_hi); dfree(c->d_psi_lo); dfree(c->d_phiA_m); dfree(c->d_psiF_m);
   dfree(c->w_ctr);
   if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& ev : c->prof_pool) (void)hipEventDestroy(ev);
   delete c;
   return MEM_OK;
@@ -401,7 +403,8 @@ static mem_err_t check_batch(mem_ctx_t c, const mem_batch_t* b) {
   if (!b || b->n_problems <= 0 || b->n_cells < b->n_problems || !b->cell_offsets || !b->dx ||
       !b->M_left || !b->M_right || !b->g_left || !b->g_right || !(b->cfl > 0.f) ||
       !(b->prandtl > 0.5f) || !(b->mu_ref > 0.f) || b->newton_per_step < 1 ||
-      b->newton_per_step > 1000 || (b->collision != 0 && b->collision != 1))
+      b->newton_per_step > 1000 || (b->collision != 0 && b->collision != 1) ||
+      (b->use_graph != 0 && b->use_graph != 1))
     return fail(c, MEM_ERR_INVALID_ARG, "mem_batch_t");
   std::vector<int64_t> off((size_t)b->n_problems + 1);
   MEM_HIP(c, hipMemcpy(off.data(), b->cell_offsets, off.size() * sizeof(int64_t),
@@ -451,20 +454,54 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
   MEM_HIP(c, launch_flux3(c, n, beta, g, nullptr, c->w_rho, true, true, status, s));
   MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, s));
   MEM_HIP(c, launch_dt_update(c, P, b->dx, b->cfl, t, dt, false, s));
-  for (int step = 0; step < n_steps; ++step) {
-    MEM_HIP(c, launch_collide3(c, n, M, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, s));
-    e = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, s);
-    if (e != MEM_OK) return e;
-    if (status) MEM_HIP(c, launch_status_or(n, c->w_status, status, s));
-    MEM_HIP(c, launch_flux3(c, n, beta, g, c->w_F, c->w_rho, true, true, status, s));
-    MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, s));
+  // one step of Alg. 2 on stream st (no host synchronisation inside)
+  auto step_once = [&](hipStream_t st) -> mem_err_t {
+    MEM_HIP(c, launch_collide3(c, n, M, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, st));
+    mem_err_t er = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, st);
+    if (er != MEM_OK) return er;
+    if (status) MEM_HIP(c, launch_status_or(n, c->w_status, status, st));
+    MEM_HIP(c, launch_flux3(c, n, beta, g, c->w_F, c->w_rho, true, true, status, st));
+    MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, st));
     MEM_HIP(c, launch_fv3(c, n, M, c->w_F, c->w_rho, g, c->w_prob, b->cell_offsets, b->dx, dt,
-                          c->w_Mnew, P, s));
-    MEM_HIP(c, launch_collide3(c, n, c->w_Mnew, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, s));
-    MEM_HIP(c, launch_gauge3(c, n, c->w_Mnew, beta, g, s));
-    MEM_HIP(c, launch_copy(n * K3, c->w_Mnew, M, s));
-    MEM_HIP(c, launch_dt_update(c, P, b->dx, b->cfl, t, dt, true, s));
+                          c->w_Mnew, P, st));
+    MEM_HIP(c, launch_collide3(c, n, c->w_Mnew, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, st));
+    MEM_HIP(c, launch_gauge3(c, n, c->w_Mnew, beta, g, st));
+    MEM_HIP(c, launch_copy(n * K3, c->w_Mnew, M, st));
+    MEM_HIP(c, launch_dt_update(c, P, b->dx, b->cfl, t, dt, true, st));
+    return MEM_OK;
+  };
+  if (!b->use_graph || n_steps == 0) {
+    for (int step = 0; step < n_steps; ++step) {
+      e = step_once(s);
+      if (e != MEM_OK) return e;
+    }
+    return MEM_OK;
   }
+  // graph path: capture one step on the private stream (kernels only: no
+  // memset or copy nodes), keep it while every pointer and option is the same
+  StepKey key{};
+  key.b = *b;
+  key.M = M; key.beta = beta; key.g = g; key.t = t; key.dt = dt; key.status = status;
+  key.p = p; key.refine = refine;
+  key.ws = c->w_S;
+  if (!c->step_exec || std::memcmp(&key, &c->step_key, sizeof(key)) != 0) {
+    if (c->step_exec) { (void)hipGraphExecDestroy(c->step_exec); c->step_exec = nullptr; }
+    if (!c->cap_stream) MEM_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const bool prof = c->prof;
+    c->prof = false;  // no event nodes in the graph
+    MEM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    e = step_once(c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t he = hipStreamEndCapture(c->cap_stream, &graph);
+    c->prof = prof;
+    if (e != MEM_OK) { if (graph) (void)hipGraphDestroy(graph); return e; }
+    if (he != hipSuccess) return fail(c, MEM_ERR_HIP, "hipStreamEndCapture");
+    const hipError_t ie = hipGraphInstantiate(&c->step_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) { c->step_exec = nullptr; return fail(c, MEM_ERR_HIP, "hipGraphInstantiate"); }
+    c->step_key = key;
+  }
+  for (int step = 0; step < n_steps; ++step) MEM_HIP(c, hipGraphLaunch(c->step_exec, s));
   return MEM_OK;
 }
 

@@ -47,6 +47,16 @@ struct SolveParams {
 }  // namespace memk
 
 // ---- context -----------------------------------------------------------------
+// Everything a captured time step depends on (compared bytewise).
+struct StepKey {
+  mem_batch_t b;
+  float *M, *beta, *g, *t, *dt;
+  uint32_t* status;
+  memk::SolveParams p;
+  int refine;
+  float* ws;  // workspace generation (mem_reserve reallocates)
+};
+
 struct mem_ctx_s {
   int dim = 3, n1d = 12, K = 35, Q = 0, Qpad = 0, ngroups = 0, prec = 0;
   int device = 0;
@@ -99,6 +109,10 @@ struct mem_ctx_s {
   float* w_gF = nullptr;      // ghost fluxes    [2*P][K]
   float* w_gR = nullptr;      // ghost radius    [2*P]
   uint32_t* w_rmax = nullptr; // per-problem max radius (float bits) [P]
+  // captured time step of mem_step (use_graph)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t step_exec = nullptr;
+  StepKey step_key{};
   // kernel timing (mem_profile_enable / mem_profile_read)
   bool prof = false;
   std::vector<hipEvent_t> prof_pool;

@@ -124,14 +124,15 @@ def test_collision_matches_oracle(ctx3):
     assert np.max(np.abs(Md.cpu().numpy() - ref) / scale) < 2e-5
 
 
-def _gpu_shock(problem, ctx, n_steps, newton_per_step=8):
+def _gpu_shock(problem, ctx, n_steps, newton_per_step=8, use_graph=False):
     M, g = f32(problem["M"]), f32(problem["g"])
     Md, gd = dev(M), dev(g)
     ctx.gauge(Md, None, gd)
     bd = dev(f32(mem_inputs.maxwellian_beta(M.shape[0], 35, Md[:, 0].cpu().numpy())))
     batch = mem.ShockBatch([0, M.shape[0]], [problem["dx"]], problem["M_left"][None],
                            problem["M_right"][None], problem["g_left"][None],
-                           problem["g_right"][None], device=DEV, newton_per_step=newton_per_step)
+                           problem["g_right"][None], device=DEV, newton_per_step=newton_per_step,
+                           use_graph=use_graph)
     t = torch.zeros(1, device=DEV)
     dt = torch.zeros(1, device=DEV)
     status = torch.zeros(M.shape[0], dtype=torch.int32, device=DEV)
@@ -196,3 +197,82 @@ def test_ragged_batch_runs_and_matches_single(ctx3):
         sl = slice(off[k], off[k + 1])
         assert torch.allclose(Md[sl], M1, rtol=1e-5, atol=1e-6), k
         assert t[k].item() == pytest.approx(t1.item(), rel=1e-6)
+
+
+def test_graph_step_matches_eager(ctx3):
+    # the captured time step, replayed call after call with the program's own
+    # work and synchronisations in between, reproduces the plain launches bit for bit
+    problem = mem_inputs.shock_problem(3.0, 1000, -20.0, 20.0, 5.44)
+    runs = {}
+    for graph in (False, True):
+        batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0, use_graph=graph)
+        snaps = []
+        for call in range(4):
+            ctx3.step(batch, Md, bd, gd, t, dt, 1 + call, status=status)
+            junk = torch.randn(4096, device=DEV).sum()   # unrelated work between replays
+            torch.cuda.synchronize()
+            snaps.append([x.clone() for x in (Md, bd, gd, t, dt, status)] + [junk])
+        runs[graph] = snaps
+    for call, (ea, gr) in enumerate(zip(runs[False], runs[True])):
+        for k, (x, y) in enumerate(zip(ea[:6], gr[:6])):
+            assert torch.equal(x, y), (call, k)
+    print(f"[graph] 4 calls (1..4 steps) identical to plain launches, t = {runs[True][-1][3].item():.4f}")
+
+
+def test_shock_reaches_steady_state(ctx3):
+    """Mach-3 shock to its steady state (FP32 criterion: max |n(k+100) - n(k)|
+    <= 2e-5 (n+ - n-)), pinned to what the problem fixes: Rankine-Hugoniot end
+    states, a monotone density profile, unchanged conserved totals, and a state
+    that the FP64 oracle's own time step leaves in place."""
+    problem = mem_inputs.shock_problem(3.0, 1000, -20.0, 20.0, 5.44)
+    batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0, use_graph=True)
+    (n1, v1, T1), (n2, v2, T2) = problem["states"]
+    ctx3.step(batch, Md, bd, gd, t, dt, 10)
+    prev = Md[:, 0].clone()
+    steps, change, rate_gpu = 10, 1.0, 0.0
+    while steps < 40000 and change > 2e-5:
+        t_prev = t.item()
+        ctx3.step(batch, Md, bd, gd, t, dt, 100, status=status)
+        steps += 100
+        cur = Md[:, 0].clone()
+        dn = (cur - prev).abs().max().item()
+        change = dn / (n2 - n1)
+        rate_gpu = dn / (t.item() - t_prev)   # max |dn/dt| of the GPU's own last 100 steps
+        prev = cur
+    print(f"\n[steady] {steps} steps, t = {t.item():.2f}, change per 100 steps {change:.2e}", flush=True)
+    assert change <= 2e-5
+    st = status.cpu().numpy()
+    assert not np.any(st & (mem.ST_NONFINITE | mem.ST_NONREALIZABLE | mem.ST_LAMBDA_FAIL))
+    M = Md.cpu().numpy().astype(np.float64)
+    g = gd.cpu().numpy().astype(np.float64)
+    mg = kinetics.macroscopic(M, g)
+    # end states and monotone profile
+    assert mg["n"][0] == pytest.approx(n1, rel=1e-3) and mg["n"][-1] == pytest.approx(n2, rel=1e-3)
+    assert mg["T"][0] == pytest.approx(T1, rel=1e-3) and mg["T"][-1] == pytest.approx(T2, rel=1e-3)
+    assert np.all(np.diff(mg["n"]) >= -1e-5 * (n2 - n1))
+    # steady: the FP64 totals stay put over 500 more steps (boundary fluxes cancel by RH)
+    tot0 = ctx3.conserved(batch, Md, gd).cpu().numpy()
+    t0 = t.item()
+    ctx3.step(batch, Md, bd, gd, t, dt, 500)
+    tot1 = ctx3.conserved(batch, Md, gd).cpu().numpy()
+    dmass = abs(tot1[0, 0] - tot0[0, 0]) / ((t.item() - t0) * n1 * v1)
+    print(f"[steady] mass change over {t.item() - t0:.2f} time units: {dmass:.2e} of the inflow")
+    assert dmass < 1e-3
+    # the oracle's FP64 step from the GPU's steady state (and, for scale, from the initial profile)
+    ora = kinetics.ShockSolver(3.0, 1000, -20.0, 20.0, 5.44, nodes_1d=12)
+    n_init = ora.M[:, 0].copy()
+    dt0 = ora.step()
+    rate_init = np.max(np.abs(ora.M[:, 0] - n_init)) / dt0
+    ora.M, ora.g = Md.cpu().numpy().astype(np.float64), gd.cpu().numpy().astype(np.float64)
+    ora.beta = ora._solve(ora.M, bd.cpu().numpy().astype(np.float64))
+    ora.dt = float(dt.item())
+    n_gpu = ora.M[:, 0].copy()
+    dts = ora.step()
+    rate_steady = np.max(np.abs(ora.M[:, 0] - n_gpu)) / dts
+    print(f"[steady] oracle max |dn/dt|: initial profile {rate_init:.3e}, GPU steady state "
+          f"{rate_steady:.3e} (ratio {rate_steady / rate_init:.2e}); GPU's own last rate "
+          f"{rate_gpu:.3e}")
+    # the GPU's fixed point is the oracle scheme's: from it the FP64 step moves the
+    # profile no faster than the slow drift that is left on the GPU itself
+    assert rate_steady <= 0.05 * rate_init
+    assert rate_steady <= 4.0 * rate_gpu
