@@ -54,9 +54,13 @@ def cpu_baseline(M, b0, n_sample):
                       f"Alg. 1 to max|G| <= 1e-10, {el:.1f} s wall"}
 
 
-def run_solves(mem, ctx, Md, b0d, steps, warmup):
-    """Time `steps` cold-start solves of the resident batch; kernel times live."""
+def run_solves(mem, ctx, Md, b0d, steps, warmup, tune=True):
+    """Time `steps` cold-start solves of the resident batch; kernel times live.
+
+    With tune, mem_autotune first picks the launch parameters on this batch
+    (outside the timed region)."""
     import torch
+    tuning = ctx.autotune(Md, b0d) if tune else ctx.tuning()
     C = Md.shape[0]
     bg = torch.empty_like(b0d)
     iters = torch.zeros(C, dtype=torch.int32, device=Md.device)
@@ -85,7 +89,7 @@ def run_solves(mem, ctx, Md, b0d, steps, warmup):
     total_flop = 2.0 * 1728 * 630 * float(it.sum()) * steps
     return dict(
         value=int(ok.sum()) * steps / elapsed, ms=1e3 * elapsed / steps, ok=ok, it=it, st=st,
-        asm_tflops=total_flop / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0,
+        asm_tflops=total_flop / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0, tuning=tuning,
         asm_launches=asm_n, asm_avg_ms=asm_ms / max(asm_n, 1),
         kernel_ms={k: v[0] / steps for k, v in prof.items()})
 
@@ -307,6 +311,7 @@ def main():
             "iterations_mean": float(r["it"].mean()),
             "iterations_max": int(r["it"].max()),
             "fp64_direction_fraction": float(np.mean((r["st"] & mem.ST_FP64) != 0)),
+            "tuning": r["tuning"],
             "kernel_ms_per_step": {"assemble": r["kernel_ms"]["assemble"],
                                    "direction": r["kernel_ms"]["direction"],
                                    "lse_linesearch": r["kernel_ms"]["lse"]},

@@ -241,6 +241,32 @@ MEM_API mem_err_t mem_step(mem_ctx_t ctx, const mem_batch_t* batch, float* M, fl
 MEM_API mem_err_t mem_conserved(mem_ctx_t ctx, const mem_batch_t* batch, const float* M,
                                 const float* g, double* out, hipStream_t stream);
 
+/* ---- launch tuning ------------------------------------------------------------- */
+
+/* Launch parameters of the 3D Newton kernels (per context).  They change how
+ * work is mapped to workgroups, never what is computed; results differ only by
+ * the order of floating-point sums. */
+typedef struct {
+  int32_t dir_waves;   /* cells (wavefronts) per workgroup of the Newton-direction
+                          kernel: 2, 4 or 8 (default 4)                            */
+  int32_t split_want;  /* workgroups a small assembly launch is spread over by
+                          splitting the quadrature nodes into ranges (the node tile
+                          of a workgroup is Q / splits); 0 = never split (512)     */
+  double  tuned_ms;    /* time of the best trial in mem_autotune (0 = not tuned)   */
+} mem_tuning_t;
+
+/* Time full solves of this batch with every candidate (dir_waves in {2, 4, 8},
+ * then split_want in {0, 256, 512, 1024, 2048}, one coordinate at a time, each
+ * trial warm and timed with HIP events on `stream`), keep the fastest in the
+ * context and return it in *out (nullable).  beta_init is not modified; the
+ * trials run in beta_work [n_cells][35] (device, caller-owned).  Synchronous. */
+MEM_API mem_err_t mem_autotune(mem_ctx_t ctx, int64_t n_cells, const float* M,
+                               const float* beta_init, float* beta_work,
+                               const mem_solve_opts_t* opts, mem_tuning_t* out,
+                               hipStream_t stream);
+MEM_API mem_err_t mem_get_tuning(mem_ctx_t ctx, mem_tuning_t* out);
+MEM_API mem_err_t mem_set_tuning(mem_ctx_t ctx, const mem_tuning_t* in);
+
 /* ---- measurement -------------------------------------------------------------- */
 
 /* Kernel timing with HIP events recorded on the launch stream around every

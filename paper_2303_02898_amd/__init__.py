@@ -52,6 +52,10 @@ class Batch(ctypes.Structure):
 _lib = None
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("dir_waves", _c_i32), ("split_want", _c_i32), ("tuned_ms", ctypes.c_double)]
+
+
 def load_library():
     """Load libmem_mi355x.so (raises if it has not been built)."""
     global _lib
@@ -81,6 +85,10 @@ def load_library():
         "mem_step": ([P, ctypes.POINTER(Batch), P, P, P, P, P, _c_i32,
                       ctypes.POINTER(SolveOpts), P, P], E),
         "mem_conserved": ([P, ctypes.POINTER(Batch), P, P, P, P], E),
+        "mem_autotune": ([P, _c_i64, P, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(Tuning),
+                          P], E),
+        "mem_get_tuning": ([P, ctypes.POINTER(Tuning)], E),
+        "mem_set_tuning": ([P, ctypes.POINTER(Tuning)], E),
         "mem_profile_enable": ([P, _c_i32], E),
         "mem_profile_read": ([P, _c_i32, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(_c_i64)], E),
@@ -181,6 +189,27 @@ class Context:
         if err != 0:
             detail = self._lib.mem_last_error(self._h).decode()
             raise MemError(f"{what}: {self._lib.mem_strerror(err).decode()} ({detail})")
+
+    def autotune(self, M, beta_init, opts=None, stream=None):
+        """Time solves of this batch over the launch candidates; keep the fastest."""
+        import torch
+        work = torch.empty_like(beta_init)
+        t = Tuning()
+        o = ctypes.byref(opts) if opts is not None else None
+        self._check(self._lib.mem_autotune(self._h, M.shape[0], _ptr(M, torch.float32, (self.K,), "M"),
+                                           _ptr(beta_init, torch.float32, (self.K,), "beta_init"),
+                                           work.data_ptr(), o, ctypes.byref(t), _stream(stream)),
+                    "mem_autotune")
+        return {"dir_waves": t.dir_waves, "split_want": t.split_want, "tuned_ms": t.tuned_ms}
+
+    def tuning(self):
+        t = Tuning()
+        self._check(self._lib.mem_get_tuning(self._h, ctypes.byref(t)), "mem_get_tuning")
+        return {"dir_waves": t.dir_waves, "split_want": t.split_want, "tuned_ms": t.tuned_ms}
+
+    def set_tuning(self, dir_waves=4, split_want=512):
+        t = Tuning(int(dir_waves), int(split_want), 0.0)
+        self._check(self._lib.mem_set_tuning(self._h, ctypes.byref(t)), "mem_set_tuning")
 
     def reserve(self, max_cells, max_problems=0):
         self._check(self._lib.mem_reserve(self._h, int(max_cells), int(max_problems)), "mem_reserve")

@@ -516,6 +516,83 @@ mem_err_t mem_conserved(mem_ctx_t c, const mem_batch_t* b, const float* M, const
   return MEM_OK;
 }
 
+mem_err_t mem_get_tuning(mem_ctx_t c, mem_tuning_t* out) {
+  if (!c || !out) return MEM_ERR_INVALID_ARG;
+  *out = c->tune;
+  return MEM_OK;
+}
+
+mem_err_t mem_set_tuning(mem_ctx_t c, const mem_tuning_t* in) {
+  if (!c || !in) return MEM_ERR_INVALID_ARG;
+  if ((in->dir_waves != 2 && in->dir_waves != 4 && in->dir_waves != 8) || in->split_want < 0 ||
+      in->split_want > 65536)
+    return fail(c, MEM_ERR_INVALID_ARG, "mem_set_tuning: dir_waves in {2,4,8}, split_want in [0, 65536]");
+  c->tune = *in;
+  return MEM_OK;
+}
+
+mem_err_t mem_autotune(mem_ctx_t c, int64_t n, const float* M, const float* beta_init,
+                       float* beta_work, const mem_solve_opts_t* opts, mem_tuning_t* out,
+                       hipStream_t s) {
+  if (!c || n <= 0 || !M || !beta_init || !beta_work) return MEM_ERR_INVALID_ARG;
+  if (!opts_ok(opts)) return fail(c, MEM_ERR_INVALID_ARG, "mem_autotune: options");
+  if (c->dim != 3) {  // the 1D solver has no launch parameters
+    if (out) *out = c->tune;
+    return MEM_OK;
+  }
+  mem_err_t e = ensure_cells(c, n);
+  if (e != MEM_OK) return e;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  MEM_HIP(c, hipEventCreate(&ev[0]));
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(c, MEM_ERR_HIP, "hipEventCreate");
+  }
+  const size_t bytes = (size_t)n * K3 * sizeof(float);
+  // one warm run, then the faster of two timed runs
+  auto trial = [&](const mem_tuning_t& t, double& ms) -> mem_err_t {
+    c->tune = t;
+    ms = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+      MEM_HIP(c, hipMemcpyAsync(beta_work, beta_init, bytes, hipMemcpyDeviceToDevice, s));
+      MEM_HIP(c, hipEventRecord(ev[0], s));
+      mem_err_t r = mem_maxent_solve(c, n, M, beta_work, opts, nullptr, nullptr, nullptr, s);
+      if (r != MEM_OK) return r;
+      MEM_HIP(c, hipEventRecord(ev[1], s));
+      MEM_HIP(c, hipEventSynchronize(ev[1]));
+      float x = 0.f;
+      MEM_HIP(c, hipEventElapsedTime(&x, ev[0], ev[1]));
+      if (rep > 0) ms = std::min(ms, (double)x);
+    }
+    return MEM_OK;
+  };
+  mem_tuning_t best = c->tune;
+  double best_ms = 1e30;
+  const int dws[] = {2, 4, 8};
+  const int sws[] = {0, 256, 512, 1024, 2048};
+  for (int dw : dws) {
+    mem_tuning_t t = best;
+    t.dir_waves = dw;
+    double ms = 0.0;
+    if ((e = trial(t, ms)) != MEM_OK) break;
+    if (ms < best_ms) { best_ms = ms; best = t; }
+  }
+  for (int sw : sws) {
+    if (e != MEM_OK) break;
+    mem_tuning_t t = best;
+    t.split_want = sw;
+    double ms = 0.0;
+    if ((e = trial(t, ms)) != MEM_OK) break;
+    if (ms < best_ms) { best_ms = ms; best = t; }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  best.tuned_ms = best_ms;
+  c->tune = best;
+  if (out) *out = best;
+  return e;
+}
+
 mem_err_t mem_profile_enable(mem_ctx_t c, int32_t enable) {
   if (!c) return MEM_ERR_INVALID_ARG;
   c->prof = enable != 0;

@@ -545,7 +545,8 @@ __device__ __forceinline__ void load_hcol(const float* Sc, T inv0, const T* E, i
 
 constexpr int DIR_WAVES = 4;  // cells (waves) per workgroup of the wave-per-cell kernels
 
-__global__ __launch_bounds__(256) void k_direction3(
+template <int DW>  // cells (wavefronts) per workgroup
+__global__ __launch_bounds__(64 * DW) void k_direction3(
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
     const float* __restrict__ S, const float* __restrict__ M, float* __restrict__ dbeta,
     float* __restrict__ gdot, float* __restrict__ alpha_w, int32_t* __restrict__ iters_w,
@@ -555,14 +556,14 @@ __global__ __launch_bounds__(256) void k_direction3(
   const int64_t count = *ctr;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + wv;
+  const int64_t slot = (int64_t)blockIdx.x * DW + wv;
   if (slot >= count) return;  // whole wave
   const int64_t cell = list[slot];
   // the cell's row of S goes to LDS with coalesced 16-byte loads; the Hessian
   // columns are then gathered from LDS
-  __shared__ float sS[DIR_WAVES][NCOL];
-  __shared__ float sE[DIR_WAVES][K3 + 1];
-  __shared__ __align__(16) float sL[DIR_WAVES][NH * LST];
+  __shared__ float sS[DW][NCOL];
+  __shared__ float sE[DW][K3 + 1];
+  __shared__ __align__(16) float sL[DW][NH * LST];
   float* Sw = sS[wv];
   {
     const f4* src = reinterpret_cast<const f4*>(S + cell * NCOL);
@@ -1010,8 +1011,8 @@ hipError_t launch_lse3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, con
 // fill the chip when few cells are live, at least 4 node groups per split,
 // partial sums within the split buffer.
 int assembly_splits(mem_ctx_t c, int ntile, int ngroups) {
-  const int want = 512;  // workgroups
-  if (ntile >= want / 2 || !c->w_Sp) return 1;
+  const int want = c->tune.split_want;  // workgroups
+  if (want <= 0 || ntile >= want / 2 || !c->w_Sp) return 1;
   int ns = (want + ntile - 1) / ntile;
   ns = std::min(ns, std::max(1, ngroups / 4));
   while (ns > 1 && (int64_t)ns * ntile * TILE > c->sp_rows) --ns;
@@ -1047,10 +1048,16 @@ hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
                              int32_t* done_list, int32_t* done_ctr, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
   DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
-  k_direction3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot,
-                                                      c->w_alpha, c->w_iters, c->w_status,
-                                                      c->w_resid, c->w_L, c->w_rbest, c->w_itbest,
-                                                      beta, p, c->w_code, o);
+#define MEM_DIR(DW)                                                                        \
+  k_direction3<DW><<<nblocks(grid_cells, DW), 64 * DW, 0, s>>>(                           \
+      list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot, c->w_alpha, c->w_iters, c->w_status,   \
+      c->w_resid, c->w_L, c->w_rbest, c->w_itbest, beta, p, c->w_code, o)
+  switch (c->tune.dir_waves) {
+    case 2: MEM_DIR(2); break;
+    case 8: MEM_DIR(8); break;
+    default: MEM_DIR(4); break;
+  }
+#undef MEM_DIR
   k_compact3<<<nblocks(grid_cells, 256), 256, 0, s>>>(list, ctr, c->w_code, next_list, next_ctr,
                                                       done_list, done_ctr, fb_list, fb_ctr);
   return hipGetLastError();

@@ -59,6 +59,7 @@ struct StepKey {
 
 struct mem_ctx_s {
   int dim = 3, n1d = 12, K = 35, Q = 0, Qpad = 0, ngroups = 0, prec = 0;
+  mem_tuning_t tune{4, 512, 0.0};  // launch parameters (mem_autotune / mem_set_tuning)
   int device = 0;
   // host FP64 tables (checked against the oracle by the tests)
   std::vector<double> h_nodes, h_w, h_phi, h_logw;

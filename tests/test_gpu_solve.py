@@ -266,3 +266,40 @@ def test_solve_is_deterministic(ctx3):
         torch.cuda.synchronize()
         out.append(bg.cpu().numpy())
     assert np.array_equal(out[0], out[1])
+
+
+def test_autotune_keeps_results(ctx3, rule3):
+    """Launch tuning changes how work maps to workgroups, never what is computed:
+    the direction-kernel variants (2, 4, 8 cells per workgroup) give identical
+    results, and the tuned solve meets the oracle bars."""
+    C = 4096
+    cells = mem_inputs.mott_smith_cells(C, config=2, replica=9)
+    M = f32(cells["M"])
+    b0 = f32(mem_inputs.maxwellian_beta(C, 35, M[:, 0]))
+    Md, b0d = dev(M), dev(b0)
+    outs = []
+    for dw in (2, 4, 8):
+        ctx3.set_tuning(dir_waves=dw, split_want=0)
+        bg = b0d.clone()
+        _, _, st = ctx3.solve(Md, bg)
+        torch.cuda.synchronize()
+        outs.append((bg.clone(), st.clone()))
+    for bg, st in outs[1:]:
+        assert torch.equal(bg, outs[0][0]) and torch.equal(st, outs[0][1])
+    tuned = ctx3.autotune(Md, b0d)
+    print(f"\n[autotune] {tuned}", flush=True)
+    assert tuned["dir_waves"] in (2, 4, 8) and tuned["split_want"] in (0, 256, 512, 1024, 2048)
+    assert tuned["tuned_ms"] > 0.0
+    assert torch.equal(b0d, dev(b0))   # the initial guess is left alone
+    bg = b0d.clone()
+    _, _, st = ctx3.solve(Md, bg)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    idx = np.arange(0, C, 64)
+    ref = maxent.newton_solve(M[idx], b0[idx], rule3["Phi"], rule3["logw"])
+    good = _split_by_oracle(st[idx], ref, "autotuned")
+    r, berr = _check_solution(bg.cpu().numpy().astype(np.float64)[idx][good], M[idx][good], rule3,
+                              ref["beta"][good], "autotuned")
+    conv = (st[idx][good] & mem.ST_CONVERGED) != 0
+    assert r[conv].max() <= 1.0 and berr.max() <= 1e-4
+    ctx3.set_tuning(4, 512)
