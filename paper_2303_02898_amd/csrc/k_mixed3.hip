@@ -14,14 +14,19 @@
 // inside the FP16 range.  The Newton iteration keeps using the FP32 gradient,
 // so the Hessian's rounding only changes the contraction rate.
 //
-// Work split (64 cells per workgroup, 4 wavefronts):
-//   * wave w computes sigma for cells 16w..16w+15 over a 32-node group with
-//     the FP32 exponent MFMA (A = [log w~ | phi] table, B = beta) and shares it
-//     through LDS, as FP32 and as 16-bit hi/lo fragments (double-buffered);
-//   * wave w then owns column block w (FP32, 16 columns) and 16-bit blocks
-//     4 + 9w .. 12 + 9w for all 64 cells, reading its Psi operands straight
-//     from global memory one node group ahead (no LDS staging: no two waves
-//     of a workgroup share a Psi element).
+// Work split (64 cells per workgroup, 8 wavefronts, two per SIMD):
+//   * wave w computes sigma for the 16 cells of tile w % 4 over half w / 4 of a
+//     32-node group with the FP32 exponent MFMA (A = [log w~ | phi] table,
+//     B = beta) and shares it through LDS, as FP32 and as 16-bit hi/lo
+//     fragments (double-buffered, one barrier per node group);
+//   * the 40 column blocks are split so that each SIMD's pair of waves does
+//     the same MFMA work: waves 0..2 own FP32 block w (columns 0..47 hold the
+//     35 moment columns) and 16-bit block 3 + w; waves 3..7 own 16-bit blocks
+//     6..39 in runs of seven (the last wave six), all four tiles each;
+//   * Psi operands go from global memory straight to registers (no two waves
+//     of a workgroup share a Psi element); each register is refilled with the
+//     next node group right after its last MFMA, and the exponent of the next
+//     group is computed among the MFMAs of the current one.
 #include "mem_internal.h"
 
 namespace memk {
@@ -32,9 +37,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
-constexpr int SGN = 32;       // nodes per 16x16x32 k-step
-constexpr int MB = 9;         // 16-bit column blocks per wave
-constexpr int NFB = 4;        // FP32 column blocks (columns 0..63 hold the moments)
+constexpr int MW = 8;                // wavefronts per workgroup
+constexpr int MAXB = 7;              // most 16-bit column blocks owned by one wave
+constexpr int NHB = NBLK - MIX_FB;   // 16-bit column blocks (37)
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -65,17 +70,18 @@ __device__ __forceinline__ V as_v(uint4 u) {
 }
 
 template <bool F16>
-__global__ __launch_bounds__(256, 1) void k_assemble3m(
-    const float* __restrict__ phiA,   // [2*nsg][NJ][64]   exponent A operand
-    const float* __restrict__ psiF,   // [nsg][NFB][64][8] FP32 B operand, blocks 0..3
-    const uint4* __restrict__ psiH,   // [nsg][36][64]     16-bit B operand, high part
-    const uint4* __restrict__ psiL,   // [nsg][36][64]     16-bit B operand, low part
+__global__ __launch_bounds__(64 * MW) void k_assemble3m(
+    const float* __restrict__ phiA,   // [2*nsg][NJ][64]       exponent A operand
+    const float* __restrict__ psiF,   // [nsg][MIX_FB][64][8]  FP32 B operand, blocks 0..2
+    const uint4* __restrict__ psiH,   // [nsg][NHB][64]        16-bit B operand, high part
+    const uint4* __restrict__ psiL,   // [nsg][NHB][64]        16-bit B operand, low part
     int nsg, const int32_t* __restrict__ list, const int32_t* __restrict__ ctr, int64_t n,
     const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ S,
     int ntile, int nsplit, float* __restrict__ Sp) {
   using H = Half<F16>;
   using T = typename H::T;
   using V = typename H::V;
+  typedef T T4 __attribute__((ext_vector_type(4)));
   const int64_t count = ctr ? (int64_t)(*ctr) : n;
   const int split = (int)(blockIdx.x / ntile);
   const int64_t tile0 = (int64_t)(blockIdx.x % ntile) * TILE;
@@ -84,9 +90,15 @@ __global__ __launch_bounds__(256, 1) void k_assemble3m(
   const int send = (int)((int64_t)(split + 1) * nsg / nsplit);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
-  const int64_t slot = tile0 + wave * 16 + (lane & 15);
+  // sigma duty: tile ts, node half hs
+  const int ts = wave & 3, hs = wave >> 2;
+  const int64_t slot = tile0 + 16 * ts + (lane & 15);
   const bool valid = slot < count;
   const int64_t cell = valid ? (list ? (int64_t)list[slot] : slot) : 0;
+  // column duty
+  const bool has_f = wave < MIX_FB;
+  const int hb0 = wave < MIX_FB ? wave : 3 + 7 * (wave - MIX_FB);  // first 16-bit block (0-based)
+  const int nb = wave < MIX_FB ? 1 : (wave == MW - 1 ? 6 : 7);
 
   float bt[NJ];
 #pragma unroll
@@ -97,88 +109,99 @@ __global__ __launch_bounds__(256, 1) void k_assemble3m(
   const float lz = valid ? logZ[cell] : 0.f;
 
   f4 accF[4];
-  f4 acc[4][MB];
+  f4 acc[4][MAXB];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     accF[t] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int b = 0; b < MB; ++b) acc[t][b] = (f4){0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < MAXB; ++b) acc[t][b] = (f4){0.f, 0.f, 0.f, 0.f};
   }
 
   __shared__ float sF[2][4][8][64];   // sigma (FP32) [buffer][tile][k-step][lane]
   __shared__ uint4 sH[2][4][64];      // 16-bit hi fragments [buffer][tile][lane]
   __shared__ uint4 sL[2][4][64];      // 16-bit lo fragments
 
-  // operands of node group s, loaded one group ahead
-  float pa[2 * NJ];
-  float4 pf[2];
-  uint4 ph[MB], pl[MB];
-  auto load = [&](int s) {
-#pragma unroll
-    for (int j = 0; j < 2 * NJ; ++j) pa[j] = phiA[((size_t)2 * s * NJ + j) * 64 + lane];
-    const float4* f = reinterpret_cast<const float4*>(psiF + (((size_t)s * NFB + wave) * 64 + lane) * 8);
-    pf[0] = f[0];
-    pf[1] = f[1];
-    const size_t hb = ((size_t)s * 36 + MB * wave) * 64 + lane;
-#pragma unroll
-    for (int b = 0; b < MB; ++b) {
-      ph[b] = psiH[hb + (size_t)b * 64];
-      pl[b] = psiL[hb + (size_t)b * 64];
+  // Psi operands of one node group (registers; refilled block by block)
+  float cf[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  uint4 ph[MAXB], pl[MAXB];
+  auto loadF = [&](int s) {
+    if (has_f) {
+      const float4* f = reinterpret_cast<const float4*>(psiF + (((size_t)s * MIX_FB + wave) * 64 + lane) * 8);
+      const float4 f0 = f[0], f1 = f[1];
+      cf[0] = f0.x; cf[1] = f0.y; cf[2] = f0.z; cf[3] = f0.w;
+      cf[4] = f1.x; cf[5] = f1.y; cf[6] = f1.z; cf[7] = f1.w;
     }
   };
-  load(sbeg);
-
-  for (int s = sbeg; s < send; ++s) {
-    const int buf = s & 1;
-    float ca[2 * NJ];
+  auto loadH = [&](int s, int b) {
+    const size_t hb = ((size_t)s * NHB + hb0 + b) * 64 + lane;
+    ph[b] = psiH[hb];
+    pl[b] = psiL[hb];
+  };
+  // sigma of tile ts at nodes 32s + 16hs + 4(l/16) + r, into LDS buffer buf
+  auto sigma = [&](int s, int buf) {
+    f4 e = {0.f, 0.f, 0.f, 0.f};
+    const float* pa = phiA + ((size_t)(2 * s + hs) * NJ) * 64 + lane;
 #pragma unroll
-    for (int j = 0; j < 2 * NJ; ++j) ca[j] = pa[j];
-    const float cf[8] = {pf[0].x, pf[0].y, pf[0].z, pf[0].w, pf[1].x, pf[1].y, pf[1].z, pf[1].w};
-    uint4 ch[MB], cl[MB];
-#pragma unroll
-    for (int b = 0; b < MB; ++b) { ch[b] = ph[b]; cl[b] = pl[b]; }
-    if (s + 1 < send) load(s + 1);
-
-    // sigma of this wave's 16 cells at nodes 32s + 16h + 4(l/16) + r
-    f4 e0 = {0.f, 0.f, 0.f, 0.f}, e1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      e0 = mfma4(ca[j], bt[j], e0);
-      e1 = mfma4(ca[NJ + j], bt[j], e1);
-    }
-    float sg[8];
+    for (int j = 0; j < NJ; ++j) e = mfma4(pa[j * 64], bt[j], e);
+    T4 hv, lv;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      sg[r] = valid ? __expf(e0[r] - lz) : 0.f;
-      sg[4 + r] = valid ? __expf(e1[r] - lz) : 0.f;
+      const float sg = valid ? __expf(e[r] - lz) : 0.f;
+      sF[buf][ts][4 * hs + r][lane] = sg;
+      const T h = (T)sg;
+      hv[r] = h;
+      lv[r] = (T)(sg - (float)h);
     }
-    V hv, lv;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      sF[buf][wave][i][lane] = sg[i];
-      const T h = (T)sg[i];
-      hv[i] = h;
-      lv[i] = (T)(sg[i] - (float)h);
-    }
-    sH[buf][wave][lane] = __builtin_bit_cast(uint4, hv);
-    sL[buf][wave][lane] = __builtin_bit_cast(uint4, lv);
-    __syncthreads();
+    reinterpret_cast<uint2*>(&sH[buf][ts][lane])[hs] = __builtin_bit_cast(uint2, hv);
+    reinterpret_cast<uint2*>(&sL[buf][ts][lane])[hs] = __builtin_bit_cast(uint2, lv);
+  };
 
+  // prologue: operands and sigma of the first group
+  loadF(sbeg);
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    if (b < nb) loadH(sbeg, b);
+    else { ph[b] = make_uint4(0, 0, 0, 0); pl[b] = make_uint4(0, 0, 0, 0); }
+  }
+  sigma(sbeg, 0);
+  __syncthreads();
+
+  // iteration s: sigma of group s + 1 into the other buffer, the MFMAs of group
+  // s from LDS buffer (s - sbeg) & 1, and each Psi register refilled with group
+  // s + 1 right after its last use
+  for (int s = sbeg; s < send; ++s) {
+    const int buf = (s - sbeg) & 1;
+    const bool more = s + 1 < send;
+    if (more) sigma(s + 1, buf ^ 1);
+
+    if (has_f) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) accF[t] = mfma4(sF[buf][t][i][lane], cf[i], accF[t]);
+      }
+      if (more) loadF(s + 1);
+    }
+    V ah[4], al[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
+      ah[t] = as_v<V>(sH[buf][t][lane]);
+      al[t] = as_v<V>(sL[buf][t][lane]);
+    }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) accF[t] = mfma4(sF[buf][t][i][lane], cf[i], accF[t]);
-      const V ah = as_v<V>(sH[buf][t][lane]);
-      const V al = as_v<V>(sL[buf][t][lane]);
+    for (int b = 0; b < MAXB; ++b) {
+      if (b < nb) {
+        const V bh = as_v<V>(ph[b]), bl = as_v<V>(pl[b]);
 #pragma unroll
-      for (int b = 0; b < MB; ++b) {
-        const V bh = as_v<V>(ch[b]);
-        const V bl = as_v<V>(cl[b]);
-        acc[t][b] = H::mma(al, bh, acc[t][b]);
-        acc[t][b] = H::mma(ah, bl, acc[t][b]);
-        acc[t][b] = H::mma(ah, bh, acc[t][b]);
+        for (int t = 0; t < 4; ++t) acc[t][b] = H::mma(al[t], bh, acc[t][b]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t][b] = H::mma(ah[t], bl, acc[t][b]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t][b] = H::mma(ah[t], bh, acc[t][b]);
+        if (more) loadH(s + 1, b);
       }
     }
+    __syncthreads();
   }
 
   // D layout: lane l, register q -> row 4(l/16) + q of the tile, column l%16
@@ -195,9 +218,10 @@ __global__ __launch_bounds__(256, 1) void k_assemble3m(
           const int64_t cw = list ? (int64_t)list[sl] : sl;
           dst = S + cw * NCOL + (lane & 15);
         }
-        dst[16 * wave] = accF[t][q];
+        if (has_f) dst[16 * wave] = accF[t][q];
 #pragma unroll
-        for (int b = 0; b < MB; ++b) dst[16 * (NFB + MB * wave + b)] = acc[t][b][q];
+        for (int b = 0; b < MAXB; ++b)
+          if (b < nb) dst[16 * (MIX_FB + hb0 + b)] = acc[t][b][q];
       }
     }
   }
@@ -215,13 +239,13 @@ hipError_t launch_assemble3m(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
   const int nsplit = assembly_splits(c, ntile, 2 * c->nsg_m);
   const unsigned grid = (unsigned)(ntile * nsplit);
   if (c->prec == MEM_PREC_FP16X3)
-    k_assemble3m<true><<<grid, 256, 0, s>>>(c->d_phiA_m, c->d_psiF_m,
+    k_assemble3m<true><<<grid, 64 * MW, 0, s>>>(c->d_phiA_m, c->d_psiF_m,
                                             static_cast<const uint4*>(c->d_psi_hi),
                                             static_cast<const uint4*>(c->d_psi_lo), c->nsg_m,
                                             list, ctr, n, beta, c->w_logZ, S, ntile, nsplit,
                                             c->w_Sp);
   else
-    k_assemble3m<false><<<grid, 256, 0, s>>>(c->d_phiA_m, c->d_psiF_m,
+    k_assemble3m<false><<<grid, 64 * MW, 0, s>>>(c->d_phiA_m, c->d_psiF_m,
                                              static_cast<const uint4*>(c->d_psi_hi),
                                              static_cast<const uint4*>(c->d_psi_lo), c->nsg_m,
                                              list, ctr, n, beta, c->w_logZ, S, ntile, nsplit,

@@ -21,6 +21,7 @@ constexpr int GRP = 16;       // quadrature nodes per MFMA node group
 constexpr int NJ = 9;         // 4-wide k-chunks of the exponent GEMM (36 = 9*4)
 constexpr int HPACK = 595;    // packed upper triangle of the 34x34 Hessian
 constexpr int TILE = 64;      // cells per assembly / line-search workgroup
+constexpr int MIX_FB = 3;     // FP32 column blocks of the mixed assembly (columns 0..47)
 constexpr float NEG_BIG = -1.0e30f;  // log weight of padding nodes (exp -> 0)
 
 // Column of the pair (i, j), i <= j, in the row-major upper-triangle order.
@@ -70,8 +71,8 @@ struct mem_ctx_s {
   // mixed precision (BF16 / FP16 hi + lo) assembly operands, 32-node groups
   int nsg_m = 0;              // node groups of 32 (nodes padded with zero weight)
   float* d_phiA_m = nullptr;  // exponent A operand [2*nsg_m][NJ][64] (FP16: log w~ + k_p ln 2)
-  float* d_psiF_m = nullptr;  // FP32 B operand of the 4 moment blocks [nsg_m][4][64][8]
-  void* d_psi_hi = nullptr;   // 16-bit B operand, high part [nsg_m][36][64][8]
+  float* d_psiF_m = nullptr;  // FP32 B operand of the moment blocks [nsg_m][MIX_FB][64][8]
+  void* d_psi_hi = nullptr;   // 16-bit B operand, high part [nsg_m][NBLK-MIX_FB][64][8]
   void* d_psi_lo = nullptr;   // 16-bit B operand, low part
   float2* d_t1 = nullptr;    // 1D tables (hi, lo): h_a(x_k) at [a*n + k], a <= 4; lw_k at [5n + k]
   // device tables, 1D

@@ -176,18 +176,20 @@ void build_mixed(mem_ctx_t ctx, const PhiE& phiE, const Psi& psi) {
         A[((size_t)g * NJ + j) * 64 + l] = (float)v;
       }
   auto node = [](int s, int l, int i) { return 32 * s + 16 * (i >> 2) + 4 * (l >> 4) + (i & 3); };
-  std::vector<float> F((size_t)nsg * 4 * 64 * 8);
-  std::vector<uint16_t> Hh((size_t)nsg * 36 * 64 * 8), Hl(Hh.size());
+  // FP32 blocks 0..MIX_FB-1 (the 35 moment columns), 16-bit blocks MIX_FB..NBLK-1
+  const int nhb = NBLK - MIX_FB;
+  std::vector<float> F((size_t)nsg * MIX_FB * 64 * 8);
+  std::vector<uint16_t> Hh((size_t)nsg * nhb * 64 * 8), Hl(Hh.size());
   for (int s = 0; s < nsg; ++s)
     for (int l = 0; l < 64; ++l)
       for (int i = 0; i < 8; ++i) {
         const int p = node(s, l, i);
         const double sc = std::ldexp(1.0, -ks[p]);
-        for (int b = 0; b < 4; ++b)
-          F[(((size_t)s * 4 + b) * 64 + l) * 8 + i] = (float)(psi(p, 16 * b + (l & 15), false) * sc);
-        for (int b = 4; b < NBLK; ++b) {
+        for (int b = 0; b < MIX_FB; ++b)
+          F[(((size_t)s * MIX_FB + b) * 64 + l) * 8 + i] = (float)(psi(p, 16 * b + (l & 15), false) * sc);
+        for (int b = MIX_FB; b < NBLK; ++b) {
           const double v = psi(p, 16 * b + (l & 15), false) * sc;
-          const size_t o = (((size_t)s * 36 + (b - 4)) * 64 + l) * 8 + i;
+          const size_t o = (((size_t)s * nhb + (b - MIX_FB)) * 64 + l) * 8 + i;
           if (f16) {
             const _Float16 h = (_Float16)(float)v;
             const _Float16 lo = (_Float16)(float)(v - (double)(float)h);
