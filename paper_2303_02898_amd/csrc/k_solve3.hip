@@ -30,6 +30,18 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Wait for every outstanding vector-memory load of this wave, direct-to-LDS
+// loads included.
+__device__ __forceinline__ void vm_wait_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Third descriptor word of a raw buffer resource on CDNA (gfx9 family).
+constexpr int BUF_DW3 = 0x00020000;
+
+// Generic -> LDS address space, for the direct global -> LDS loads.
+__device__ __forceinline__ __attribute__((address_space(3))) void* lds_ptr(const void* p) {
+  return (__attribute__((address_space(3))) void*)(p);
+}
+
 // Wave-aggregated append of `cell` to a work list.  Every lane of the wave
 // must call it (it uses a ballot).
 __device__ __forceinline__ void wave_append(bool pred, int cell, int32_t* list, int32_t* ctr) {
@@ -272,11 +284,13 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
   const bool valid = slot < count;
   const int64_t cell = valid ? (list ? (int64_t)list[slot] : slot) : 0;
 
-  float bt[NJ];
+  // exponent B operand (beta, lane l holding k = 4j + l/16), kept in LDS to
+  // leave the registers to the 160 accumulators
+  __shared__ float sBt[NJ * 256];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int k = 4 * j + kq;
-    bt[j] = k == 0 ? 1.f : ((valid && k < K3) ? beta[cell * K3 + k] : 0.f);
+    sBt[j * 256 + threadIdx.x] = k == 0 ? 1.f : ((valid && k < K3) ? beta[cell * K3 + k] : 0.f);
   }
   const float lz = valid ? logZ[cell] : 0.f;
 
@@ -284,36 +298,71 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
 #pragma unroll
   for (int b = 0; b < NBLK; ++b) acc[b] = (f4){0.f, 0.f, 0.f, 0.f};
 
-  __shared__ f4 sB[4 * 10 * 64];   // 40 KB: Psi operand of one node group
-  __shared__ float sA[NJ * 64];    // exponent operand of one node group
-  for (int g = gbeg; g < gend; ++g) {
-    __syncthreads();
-    {
-      const f4* src = reinterpret_cast<const f4*>(psi) + (size_t)g * (4 * 10 * 64);
+  // Half-group ping-pong: half h of the node range holds Psi rows 2(h%2),
+  // 2(h%2)+1 (20 KB) of group h/2 and lives in buffer h%2; the exponent table
+  // of a group travels with its first half.  Halves move global -> LDS with
+  // direct (register-free) loads: half h+1 is issued right after the barrier
+  // that opens half h and waited for at the next barrier, so its latency runs
+  // under the MFMAs of half h.
+  __shared__ f4 sB0[2 * 10 * 64];  // 20 KB each
+  __shared__ f4 sB1[2 * 10 * 64];
+  __shared__ f4 sA4[NJ * 16];      // exponent operand of one node group
+  const float* sA = reinterpret_cast<const float*>(sA4);
+  // buffer resources (bounds = the tables); lane l of wave w moves the 16 bytes
+  // at offset 16 (64 w + l) + 4096 i of a half into LDS element 64 w + 256 i + l
+  const __amdgpu_buffer_rsrc_t rB =
+      __builtin_amdgcn_make_buffer_rsrc((void*)psi, (short)0, ngroups * (4 * 10 * 64 * 16), BUF_DW3);
+  const __amdgpu_buffer_rsrc_t rA =
+      __builtin_amdgcn_make_buffer_rsrc((void*)phiA, (short)0, ngroups * (NJ * 64 * 4), BUF_DW3);
+  const int voff = (int)threadIdx.x * 16;
+  const int hend = 2 * gend;
+  auto fetch = [&](f4* dst, int h, bool first) {
 #pragma unroll
-      for (int i = 0; i < 10; ++i) sB[threadIdx.x + 256 * i] = src[threadIdx.x + 256 * i];
-      const f4* srcA = reinterpret_cast<const f4*>(phiA + (size_t)g * NJ * 64);
-      if (threadIdx.x < NJ * 16) reinterpret_cast<f4*>(sA)[threadIdx.x] = srcA[threadIdx.x];
+    for (int i = 0; i < 5; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, lds_ptr(dst + 64 * wave + 256 * i), 16, voff,
+                                               h * (2 * 10 * 64 * 16) + 4096 * i, 0, 0);
+    if (first && threadIdx.x < NJ * 16)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rA, lds_ptr(sA4 + 64 * wave), 16, voff,
+                                               (h >> 1) * (NJ * 64 * 4), 0, 0);
+    __builtin_amdgcn_sched_barrier(0);  // issue here, ahead of the MFMAs it hides under
+  };
+  auto half = [&](const f4* buf, float s0, float s1) {
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      const float sgr = rr ? s1 : s0;
+#pragma unroll
+      for (int b4 = 0; b4 < 10; ++b4) {
+        const f4 bv = buf[(rr * 10 + b4) * 64 + lane];
+        acc[4 * b4 + 0] = mfma4(sgr, bv[0], acc[4 * b4 + 0]);
+        acc[4 * b4 + 1] = mfma4(sgr, bv[1], acc[4 * b4 + 1]);
+        acc[4 * b4 + 2] = mfma4(sgr, bv[2], acc[4 * b4 + 2]);
+        acc[4 * b4 + 3] = mfma4(sgr, bv[3], acc[4 * b4 + 3]);
+      }
     }
-    __syncthreads();
+  };
+  fetch(sB0, 2 * gbeg, true);
+  for (int g = gbeg; g < gend; ++g) {
+    const int h = 2 * g;
+    // this wave's direct loads have landed before the barrier lets the other
+    // waves read them (the barrier alone does not order them)
+    vm_wait_all();
+    __syncthreads();  // half h is in LDS; every wave is done with buffer 1
+    fetch(sB1, h + 1, false);
     f4 e = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) e = mfma4(sA[j * 64 + lane], bt[j], e);
+    for (int j = 0; j < NJ; ++j) e = mfma4(sA[j * 64 + lane], sBt[j * 256 + threadIdx.x], e);
     float sg[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) sg[r] = valid ? __expf(e[r] - lz) : 0.f;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-#pragma unroll
-      for (int b4 = 0; b4 < 10; ++b4) {
-        const f4 bv = sB[(r * 10 + b4) * 64 + lane];
-        acc[4 * b4 + 0] = mfma4(sg[r], bv[0], acc[4 * b4 + 0]);
-        acc[4 * b4 + 1] = mfma4(sg[r], bv[1], acc[4 * b4 + 1]);
-        acc[4 * b4 + 2] = mfma4(sg[r], bv[2], acc[4 * b4 + 2]);
-        acc[4 * b4 + 3] = mfma4(sg[r], bv[3], acc[4 * b4 + 3]);
-      }
-    }
+    half(sB0, sg[0], sg[1]);
+    vm_wait_all();
+    __syncthreads();  // half h+1 is in LDS; every wave is done with buffer 0 and sA
+    // the last group re-fetches its own first half (never read again), which
+    // keeps the loop free of a conditional load
+    fetch(sB0, min(h + 2, hend - 2), true);
+    half(sB1, sg[2], sg[3]);
   }
+  vm_wait_all();  // no direct load may still target LDS when the workgroup ends
   // D layout: lane l, register q -> row 4(l/16) + q of the wave's 16 cells, column l%16
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
