@@ -18,6 +18,7 @@ Prints ONE JSON line.  Single-GPU build: --gpus above 1 exits with a message.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +31,43 @@ sys.path.insert(0, ROOT)
 
 METRIC = "35-moment MaxEnt solves/s at rel. residual ≤1e-5, FP32 vs mixed; cell-steps/s"
 MFMA_PEAK = {"fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}
+
+# HBM bytes per k_assemble3 launch on this bench's timed solve (65536 cells,
+# launch parameters 2,2048): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per
+# dispatch averaged over the solve's 26 launches, each scaled by what the
+# counter reads for a 1 GiB device-to-device copy (FETCH x 2.0, WRITE x 1.0).
+# It describes one version of the kernel: the source text it was measured on
+# is pinned by hash, and any other version reports null.
+ASM_TRAFFIC = {
+    "kernel_sha256": "ee059f5022951c683d372888febc7c08df268ccd9845ccbdd6972f26e65318ff",
+    "fetch_kib": 30996.1, "fetch_scale": 1.99995,
+    "write_kib": 65375.3, "write_scale": 1.0,
+    "cells": 65536, "tuning": [2, 2048],
+}
+_ASM_SRC = ("paper_2303_02898_amd/csrc/k_solve3.hip",
+            "__global__ __launch_bounds__(256, 2) void k_assemble3(",
+            "// S[cell] = sum over splits")
+
+
+def assembly_source_sha():
+    """sha256 of the k_assemble3 kernel text (None if it cannot be found)."""
+    path, begin, end = _ASM_SRC
+    try:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), path)) as f:
+            txt = f.read()
+        a = txt.index(begin)
+        return hashlib.sha256(txt[a:txt.index(end, a)].encode()).hexdigest()
+    except (OSError, ValueError):
+        return None
+
+
+def assembly_traffic(prec, cells):
+    """Calibrated HBM bytes per launch, or None when they were not measured for
+    this kernel version and workload."""
+    t = ASM_TRAFFIC
+    if prec != "fp32" or cells != t["cells"] or assembly_source_sha() != t["kernel_sha256"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
 def cpu_baseline(M, b0, n_sample):
@@ -239,6 +277,9 @@ def main():
     ap.add_argument("--shock-max-steps", type=int, default=40000)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 1D, shock and ragged-batch measurements")
+    ap.add_argument("--tuning", default=None, metavar="DIR_WAVES,SPLIT_WANT",
+                    help="fixed launch parameters instead of the autotuner (e.g. to profile "
+                         "exactly the launches a tuned run timed)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (a known-size "
                          "kernel for calibrating hardware byte counters)")
@@ -270,7 +311,10 @@ def main():
     ctx.reserve(C)
     Md = torch.tensor(M32, device=dev)
     b0d = torch.tensor(b032, device=dev)
-    r = run_solves(mem, ctx, Md, b0d, args.steps, args.warmup)
+    if args.tuning:
+        dw, sw = (int(v) for v in args.tuning.split(","))
+        ctx.set_tuning(dir_waves=dw, split_want=sw)
+    r = run_solves(mem, ctx, Md, b0d, args.steps, args.warmup, tune=not args.tuning)
     ctx.close()
     peak = MFMA_PEAK[args.prec]
 
@@ -301,7 +345,9 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": r["asm_tflops"] / peak,
-            "traffic": None,
+            "traffic": assembly_traffic(args.prec, C),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_tuning": ASM_TRAFFIC["tuning"],
             "flop_per_cell_iteration": 2.0 * 1728 * 630,
             "launches": r["asm_launches"],
             "avg_launch_ms": r["asm_avg_ms"],
