@@ -112,8 +112,8 @@ __global__ void k_set_ctr(int32_t* ctr, int n) {
 // --------------------------------------------------------------------------
 // One wavefront per cell.  The exponent on the tensor grid factors axis by
 // axis (sum factorisation, phi_(a,b,c) = h_a h_b h_c):
-//   U[i][b,c] = sum_a beta_abc h_a(x_i),  V[i][j][c] = sum_b U[i][b,c] h_b(x_j),
-//   e(i,j,l)  = lw_i + lw_j + lw_l + sum_c V[i][j][c] h_c(x_l),
+//   V[i][j][c] = sum_{a,b} beta_abc h_a(x_i) h_b(x_j),
+//   e(i,j,l)   = lw_i + lw_j + lw_l + sum_c V[i][j][c] h_c(x_l),
 // and it is linear in beta, so for the trial point beta + alpha dbeta the
 // coefficients are V_beta + alpha V_dbeta: the factors are built once and each
 // trial of the backtracking search costs 5 FMAs and one exp per node.
@@ -184,9 +184,7 @@ __global__ __launch_bounds__(64) void k_lse3(
   extern __shared__ float dynf[];
   float* sB = dynf;               // [36] beta, then dbeta at [36..71]
   float* sH = dynf + 72;          // [6][n]: h_a(x_k), lw_k (high parts)
-  float* sUb = sH + 6 * n;        // [n][15]
-  float* sUd = sUb + n * NBC;     // [n][15]
-  float* sVb = sUd + n * NBC;     // [n*n][5]
+  float* sVb = sH + 6 * n;        // [n*n][5]
   float* sVd = sVb + n * n * 5;   // [n*n][5]
 
   const bool kin = lane >= 1 && lane < K3;
@@ -198,32 +196,37 @@ __global__ __launch_bounds__(64) void k_lse3(
   if (lane < 36) { sB[lane] = bk; sB[36 + lane] = dk; }
   for (int t = lane; t < 6 * n; t += 64) sH[t] = t1[t].x;
   __builtin_amdgcn_wave_barrier();
-  for (int t = lane; t < n * NBC; t += 64) {
-    const int i = t / NBC, bc = t % NBC;
-    int m = 0;
-    while (tri(m + 1) <= bc) ++m;
-    const int c = bc - tri(m), b = m - c;
-    float ub = 0.f, ud = 0.f;
-    for (int a = 0; a <= 4 - m; ++a) {
-      const int k = bidx3(a, b, c);
-      const float ha = sH[a * n + i];
-      ub = fmaf(sB[k], ha, ub);       // sB[0] = 0: beta_0 enters through log Z
-      if (LS) ud = fmaf(sB[36 + k], ha, ud);
-    }
-    sUb[t] = ub;
-    if (LS) sUd[t] = ud;
+  // coefficients of pair (i, j): v_c = sum_{a+b+c<=4} beta_abc h_a(x_i) h_b(x_j),
+  // straight from the 15 products h_a(x_i) h_b(x_j) with compile-time indices
+  float bb[K3], bd[K3];
+#pragma unroll
+  for (int k = 0; k < K3; ++k) {
+    bb[k] = sB[k];  // sB[0] = 0: beta_0 enters through log Z
+    bd[k] = LS ? sB[36 + k] : 0.f;
   }
-  __builtin_amdgcn_wave_barrier();
-  for (int t = lane; t < n * n * 5; t += 64) {
-    const int ij = t / 5, c = t % 5, i = ij / n, j = ij % n;
-    float vb = 0.f, vd = 0.f;
-    for (int b = 0; b <= 4 - c; ++b) {
-      const float hb = sH[b * n + j];
-      vb = fmaf(sUb[i * NBC + tri(b + c) + c], hb, vb);
-      if (LS) vd = fmaf(sUd[i * NBC + tri(b + c) + c], hb, vd);
+  for (int q = lane; q < n * n; q += 64) {
+    const int i = q / n, j = q - (q / n) * n;
+    float ha[5], hb[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) { ha[a] = sH[a * n + i]; hb[a] = sH[a * n + j]; }
+    float vb[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, vd[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+#pragma unroll
+      for (int b = 0; a + b < 5; ++b) {
+        const float pab = ha[a] * hb[b];
+#pragma unroll
+        for (int c = 0; a + b + c < 5; ++c) {
+          vb[c] = fmaf(bb[bidx3(a, b, c)], pab, vb[c]);
+          if (LS) vd[c] = fmaf(bd[bidx3(a, b, c)], pab, vd[c]);
+        }
+      }
     }
-    sVb[t] = vb;
-    if (LS) sVd[t] = vd;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      sVb[q * 5 + c] = vb[c];
+      if (LS) sVd[q * 5 + c] = vd[c];
+    }
   }
   __builtin_amdgcn_wave_barrier();
 
@@ -1043,7 +1046,7 @@ hipError_t launch_lse3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, con
                        const SolveParams& p, int32_t* reset_a, int32_t* reset_b, hipStream_t s) {
   const unsigned nb = (unsigned)(grid_cells > 0 ? grid_cells : 1);
   const int n1 = c->n1d;
-  const size_t lds = (size_t)(72 + 6 * n1 + 2 * n1 * NBC + 2 * n1 * n1 * 5) * sizeof(float);
+  const size_t lds = (size_t)(72 + 6 * n1 + 2 * n1 * n1 * 5) * sizeof(float);
 #define MEM_LSE(LS, NT)                                                                         \
   k_lse3<LS, NT><<<nb, 64, lds, s>>>(c->d_t1, n1, list, ctr, n, M, beta, c->w_dbeta, c->w_logZ, \
                                      c->w_L, c->w_alpha, c->w_gdot, p, reset_a, reset_b)
