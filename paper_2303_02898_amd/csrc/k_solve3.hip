@@ -597,7 +597,33 @@ __device__ __forceinline__ void load_hcol(const float* Sc, T inv0, const T* E, i
 
 constexpr int DIR_WAVES = 4;  // cells (waves) per workgroup of the wave-per-cell kernels
 
-template <int DW>  // cells (wavefronts) per workgroup
+// Newton direction, two cells per wavefront: lanes 32h .. 32h + 31 serve cell
+// h of the pair.  Lane j holds column j < 32 of the 34 x 34 matrix over all
+// 34 rows, and the right-hand side as row 34; the block of columns 32, 33 that
+// no lane holds is tracked as three scalars (its off-diagonal rows are rows
+// 32, 33 of the lanes' columns).  The factorisation is H = L D L^T,
+// right-looking and free of square roots: step k writes column k of the
+// current matrix, pivot d_k included, to LDS; the lanes read it back with
+// broadcast reads and subtract A[i][k] A[j][k] / d_k from their columns.
+// Eliminating the right-hand-side row is the forward substitution L z = b,
+// so afterwards lane j holds z_j and the Newton decrement is
+// 1/2 sum z_k^2 / d_k; the backward sweep L^T delta = D^-1 z uses each lane's
+// own frozen column entries A[m][j] (m > j).
+constexpr int HROWS = 32;  // columns held by lanes
+constexpr int HST = 36;    // LDS row stride (16-byte rows): entries 0..31, 32, 33, rhs 34
+
+__device__ __forceinline__ float half_max(float v) {
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ float half_sum(float v) {
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+template <int DW>  // wavefronts per workgroup (2 DW cells)
 __global__ __launch_bounds__(64 * DW) void k_direction3(
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
     const float* __restrict__ S, const float* __restrict__ M, float* __restrict__ dbeta,
@@ -608,65 +634,191 @@ __global__ __launch_bounds__(64 * DW) void k_direction3(
   const int64_t count = *ctr;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int64_t slot = (int64_t)blockIdx.x * DW + wv;
-  if (slot >= count) return;  // whole wave
-  const int64_t cell = list[slot];
-  // the cell's row of S goes to LDS with coalesced 16-byte loads; the Hessian
-  // columns are then gathered from LDS
-  __shared__ float sS[DW][NCOL];
-  __shared__ float sE[DW][K3 + 1];
-  __shared__ __align__(16) float sL[DW][NH * LST];
-  float* Sw = sS[wv];
-  {
+  const int hf = lane >> 5, j = lane & 31;
+  const int64_t slot0 = ((int64_t)blockIdx.x * DW + wv) * 2;
+  if (slot0 >= count) return;  // whole wave
+  const int64_t slot = slot0 + hf;
+  const bool live = slot < count;  // an odd count leaves the second half a read-only copy
+  const int64_t cell = list[live ? slot : slot0];
+  // per cell: the S row, later the rows of the factor (union), plus 4 floats
+  // that take the discarded extras write of the last row
+  constexpr int CW = HROWS * HST + 4;
+  static_assert(CW >= NCOL, "factor rows must cover the S row");
+  __shared__ __align__(16) float sW[DW][2][CW];
+  __shared__ float sE[DW][2][K3 + 1];
+  float* W = sW[wv][hf];
+  float* E = sE[wv][hf];
+  auto stage_S = [&]() {
     const f4* src = reinterpret_cast<const f4*>(S + cell * NCOL);
-    f4* dst = reinterpret_cast<f4*>(Sw);
-    for (int i = lane; i < NCOL / 4; i += 64) dst[i] = src[i];
-  }
+    f4* dst = reinterpret_cast<f4*>(W);
+#pragma unroll
+    for (int i = 0; i < NCOL / 4 / 32; ++i) dst[j + 32 * i] = src[j + 32 * i];
+  };
+  stage_S();
   const float* Mc = M + cell * K3;
   const float nn = Mc[0];
-  const float mi = lane < NH ? Mc[lane + 1] : 0.f;
-  const CellState cs = load_state(cell, lane, iters_w, status_w, rbest_w, itbest_w, alpha_w, Lval,
-                                  beta);
+  const float mj = Mc[j + 1], m32 = Mc[33], m33 = Mc[34];
+  CellState cs;
+  cs.it = iters_w[cell];
+  cs.itbest = itbest_w[cell];
+  cs.st = status_w[cell];
+  cs.rbest = rbest_w[cell];
+  cs.alpha = alpha_w[cell];
+  cs.L = Lval[cell];
+  {
+    const float* bc = beta + cell * K3;
+    const float bm = fmaxf(fabsf(bc[j + 1]), j < 2 ? fabsf(bc[33 + j]) : 0.f);
+    cs.bmax = half_max(bm);
+  }
   __builtin_amdgcn_wave_barrier();
-  const float s00 = Sw[0];
+  const float s00 = W[0];
   const float inv0 = 1.f / s00;
-  float* E = sE[wv];
-  if (lane < K3) E[lane] = lane == 0 ? 1.f : Sw[lane] * inv0;
+  E[j] = j == 0 ? 1.f : W[j] * inv0;
+  if (j < 3) E[32 + j] = W[32 + j] * inv0;
   __builtin_amdgcn_wave_barrier();
-  const float g = lane < NH ? E[lane + 1] - mi / nn : 0.f;
-  float r = wave_max(fabsf(g));
+  const float e33 = E[33], e34 = E[34];
+  const float g = E[j + 1] - mj / nn;
+  const float g32 = e33 - m32 / nn, g33 = e34 - m33 / nn;
+  float r = half_max(fmaxf(fabsf(g), fmaxf(fabsf(g32), fabsf(g33))));
   if (!isfinite(s00) || !(s00 > 0.f)) r = NAN;
 
-  float a[NH], dinv, dmin, dmax;
-  load_hcol(Sw, inv0, E, lane, 0.f, a);
-  bool ok = wave_chol(a, dinv, lane, dmin, dmax, sL[wv]);
+  float a[NH + 1];  // column j, rows 0..33; a[NH] = right-hand side
+  float t00, t10, t11, b32, b33;
+  auto load_h = [&](float lam) {
+    // the column index and E's offset pass through an empty asm so that the
+    // addresses and E values are not hoisted out of the retry loop below
+    // (they would stay live across the whole factorisation)
+    int jj = j, eo = 0;
+    asm volatile("" : "+v"(jj), "+v"(eo));
+    const float ej = E[eo + jj + 1];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+      const int lo = i < jj ? i : jj, hi = i < jj ? jj : i;
+      a[i] = W[pair_col(lo + 1, hi + 1)] * inv0 - E[eo + i + 1] * ej + (i == jj ? lam : 0.f);
+    }
+    a[NH] = -g;
+    t00 = W[pair_col(33, 33)] * inv0 - e33 * e33 + lam;
+    t10 = W[pair_col(33, 34)] * inv0 - e33 * e34;
+    t11 = W[pair_col(34, 34)] * inv0 - e34 * e34 + lam;
+    b32 = -g32;
+    b33 = -g33;
+  };
+  bool ok;
+  float dmin, dmax, dj = 1.f;
+  auto factor = [&]() {
+    __builtin_amdgcn_wave_barrier();  // the S row is dead: its space takes the factor
+    int jf = j;  // per-step lane tests stay inside the retry loop (see load_h)
+    asm volatile("" : "+v"(jf));
+    ok = true;
+    dmin = FLT_MAX;
+    dmax = 0.f;
+#pragma unroll
+    for (int k = 0; k < HROWS; ++k) {
+      float* row = W + k * HST;
+      row[jf] = a[k];
+      // rows 32, 33 and the right-hand side of column k come from lane k; the
+      // other lanes write theirs to entries 35..37 (row padding and the first
+      // entries of row k + 1, which step k + 1 overwrites): no branch, so the
+      // compiler keeps the update right-looking
+      {
+        float* dst = row + (jf == k ? 32 : 35);
+        dst[0] = a[32];
+        dst[1] = a[33];
+        dst[2] = a[NH];
+      }
+      __builtin_amdgcn_wave_barrier();
+      float u[HST];
+      const f4* r4 = reinterpret_cast<const f4*>(row);
+#pragma unroll
+      for (int q = k / 4; q < HST / 4; ++q) {
+        const f4 v = r4[q];
+        u[4 * q] = v[0]; u[4 * q + 1] = v[1]; u[4 * q + 2] = v[2]; u[4 * q + 3] = v[3];
+      }
+      const float d = u[k];
+      ok = ok && (d > 0.f) && isfinite(d);
+      dmin = fminf(dmin, d);
+      dmax = fmaxf(dmax, d);
+      const float rd = __builtin_amdgcn_rcpf(d);
+      if (jf == k) dj = d;
+      const float cj = jf > k ? a[k] * rd : 0.f;
+#pragma unroll
+      for (int i = k + 1; i <= NH; ++i) a[i] = fmaf(-u[i], cj, a[i]);
+      const float c32 = u[32] * rd, c33 = u[33] * rd;
+      t00 = fmaf(-u[32], c32, t00);
+      t10 = fmaf(-u[33], c32, t10);
+      t11 = fmaf(-u[33], c33, t11);
+      b32 = fmaf(-u[NH], c32, b32);
+      b33 = fmaf(-u[NH], c33, b33);
+      // materialise the running block here: left to itself the compiler defers
+      // these short chains to their use and keeps every step's row alive
+      asm volatile("" : "+v"(t00), "+v"(t10), "+v"(t11), "+v"(b32), "+v"(b33), "+v"(dj),
+                   "+v"(dmin), "+v"(dmax));
+      __builtin_amdgcn_wave_barrier();
+    }
+    // the last two pivots
+    const float d33 = fmaf(-t10 / t00, t10, t11);
+    ok = ok && (t00 > 0.f) && isfinite(t00) && (d33 > 0.f) && isfinite(d33);
+    dmin = fminf(dmin, fminf(t00, d33));
+    dmax = fmaxf(dmax, fmaxf(t00, d33));
+  };
+  // One copy of the factorisation: a cell whose factorisation fails (and that
+  // does not go to the FP64 kernel) goes round again with H + lambda I (Alg. 1),
+  // lambda = lambda0 lambda_mul^t for up to 40 retries.
   bool to_fp64 = false;
   uint32_t extra = 0;
-  if (p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
-    to_fp64 = isfinite(r);
-  } else if (!ok && isfinite(r)) {
-    float lam = p.lambda0;  // Alg. 1: Cholesky of H + lambda I
-    extra |= MEM_ST_SHIFTED;
-    for (int tries = 0; tries < 40 && !ok; ++tries, lam *= p.lambda_mul) {
-      load_hcol(Sw, inv0, E, lane, lam, a);
-      ok = wave_chol(a, dinv, lane, dmin, dmax, sL[wv]);
+  float lam = 0.f;
+  for (int tries = 0;; ++tries) {
+    load_h(lam);
+    factor();
+    if (tries == 0 && p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
+      to_fp64 = isfinite(r);
+      break;
     }
+    if (ok || !isfinite(r) || tries >= 40) break;
+    lam = tries == 0 ? p.lambda0 : lam * p.lambda_mul;
+    extra |= MEM_ST_SHIFTED;
+    stage_S();  // the factor overwrote the S row
+    __builtin_amdgcn_wave_barrier();
   }
-  float w = 0.f, d = 0.f;
-  if (ok && !to_fp64) wave_solve(a, sL[wv], dinv, lane, -g, w, d);
-  const float res = 0.5f * wave_sum(lane < NH ? w * w : 0.f);
-  const bool dfin = ok && __all(lane >= NH || isfinite(d));
+  // forward results: z_j on lane j, z_32, z_33; pivots dj, t00, d33
+  const float l3332 = t10 / t00;
+  const float d33 = fmaf(-l3332, t10, t11);
+  const float z32 = b32, z33 = fmaf(-l3332, z32, b33);
+  const float zj = a[NH];
+  const float res = (ok && !to_fp64)
+                        ? 0.5f * (half_sum(zj * zj / dj) + z32 * z32 / t00 + z33 * z33 / d33)
+                        : 0.f;
+  // backward: delta_m = (z_m - sum_{m' > m} A[m'][m] delta_m') / d_m, lane m's column
+  const float dl33 = z33 / d33;
+  const float dl32 = (z32 - t10 * dl33) / t00;
+  float sacc = fmaf(a[32], dl32, a[33] * dl33);
+  const float rdj = __builtin_amdgcn_rcpf(dj);
+  float dout = 0.f;
+#pragma unroll
+  for (int m = HROWS - 1; m >= 0; --m) {
+    const float v = (zj - sacc) * rdj;
+    const float dA = rl(v, m), dB = rl(v, 32 + m);
+    const float dm = hf ? dB : dA;
+    if (j == m) dout = dm;
+    sacc = fmaf(a[m], dm, sacc);
+  }
+  const unsigned long long bad = __ballot(!isfinite(dout));
+  const bool dfin = ok && ((bad >> (32 * hf)) & 0xffffffffull) == 0ull && isfinite(dl32) &&
+                    isfinite(dl33);
   // outcome of the slot, compacted into the lists by k_compact3
   int code = 0;
-  if (lane == 0) {
+  if (j == 0 && live) {
     code = to_fp64 ? 3
                    : finish_cell(cell, r, res, dfin, extra, p, cs, gdot, iters_w, status_w,
                                  resid_w, rbest_w, itbest_w, o);
     codes[slot] = (int8_t)code;
   }
-  code = __shfl(code, 0);
-  if (code == 1 && lane == 0) dbeta[cell * 36] = 0.f;
-  if (code == 1 && lane < NH) dbeta[cell * 36 + 1 + lane] = d;
+  code = __shfl(code, lane & 32);
+  if (code == 1 && live) {
+    float* db = dbeta + cell * 36;
+    db[1 + j] = dout;
+    if (j == 0) { db[0] = 0.f; db[33] = dl32; db[34] = dl33; }
+  }
 }
 
 // Stream compaction of the per-slot outcomes of k_direction3 (0 finished,
@@ -1101,7 +1253,7 @@ hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
   if (grid_cells <= 0) return hipSuccess;
   DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
 #define MEM_DIR(DW)                                                                        \
-  k_direction3<DW><<<nblocks(grid_cells, DW), 64 * DW, 0, s>>>(                           \
+  k_direction3<DW><<<nblocks(grid_cells, 2 * DW), 64 * DW, 0, s>>>(                       \
       list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot, c->w_alpha, c->w_iters, c->w_status,   \
       c->w_resid, c->w_L, c->w_rbest, c->w_itbest, beta, p, c->w_code, o)
   switch (c->tune.dir_waves) {
