@@ -129,7 +129,41 @@ def run_solves(mem, ctx, Md, b0d, steps, warmup, tune=True):
         value=int(ok.sum()) * steps / elapsed, ms=1e3 * elapsed / steps, ok=ok, it=it, st=st,
         asm_tflops=total_flop / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0, tuning=tuning,
         asm_launches=asm_n, asm_avg_ms=asm_ms / max(asm_n, 1),
-        kernel_ms={k: v[0] / steps for k, v in prof.items()})
+        kernel_ms={k: v[0] / steps for k, v in prof.items()}, beta=bg)
+
+
+def passes(mem, torch, ctx, Md, gd, r, reps=20):
+    """Achieved HBM bandwidth of the exp (log-sum-exp + line search) and flux passes
+    against the 8 TB/s peak.  Both are arithmetic-bound by design: the exponent is
+    sum-factorised (a few FMAs per node from the 1D tables in LDS), so a cell moves
+    a few hundred bytes against ~10^4 node evaluations."""
+    n = Md.shape[0]
+    beta = r["beta"]
+    F, lam = ctx.flux(beta, gd)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.flux(beta, gd)
+    e1.record()
+    torch.cuda.synchronize()
+    flux_ms = e0.elapsed_time(e1) / reps
+    flux_bytes = 4 * n * (35 + 3 + 35 + 2)            # beta, g in; F, (lam_min, lam_max) out
+    # line search per live cell-iteration: beta, dbeta, M, L, G.dbeta, list in;
+    # beta, log Z, L, alpha out (the 1D node tables stay in LDS / L2)
+    lse_bytes = 4 * float(r["it"].sum()) * (35 + 36 + 35 + 3 + 35 + 3)
+    lse_ms = r["kernel_ms"]["lse"]
+    return {
+        "exp_lse": {"kernels": "k_lse3 (log-sum-exp pass and Armijo trials)",
+                    "ms_per_solve": lse_ms, "bytes_per_cell_iteration": 4 * 147,
+                    "achieved_GBps": lse_bytes / (lse_ms * 1e-3) / 1e9, "peak_GBps": 8000.0,
+                    "bound": "valu (sum-factorised exponent)"},
+        "flux": {"kernels": "k_flux3 + k_eig3 (moment fluxes and extreme speeds)",
+                 "cells": n, "ms": flux_ms, "bytes_per_cell": 4 * 75,
+                 "achieved_GBps": flux_bytes / (flux_ms * 1e-3) / 1e9, "peak_GBps": 8000.0,
+                 "bound": "valu (quadrature over 1728 nodes per cell)"},
+    }
 
 
 def mixed_comparison(mem, torch, dev, cells, steps, warmup):
@@ -144,23 +178,36 @@ def mixed_comparison(mem, torch, dev, cells, steps, warmup):
                        "(Mach U(5,10), nu U(0,1)), 12^3 nodes, cold start",
            "cells": cells}
     base = None
+    beta32 = None
     for prec in ("fp32", "bf16x3", "fp16x3"):
         ctx = mem.Context(3, 12, prec)
         ctx.reserve(cells)
         r = run_solves(mem, ctx, Md, b0d, steps, warmup)
+        # per-moment residual G_k = E[phi_k]/E[phi_0] - M_k/n of the converged cells,
+        # evaluated in compensated arithmetic (agrees with FP64 to a few 1e-8)
+        G = ctx.moment_residual(Md, r["beta"]).abs().cpu().numpy()
+        beta = r["beta"].cpu().numpy().astype(np.float64)
         ctx.close()
+        ok = r["ok"]
         if base is None:
             base = r["value"]
+            beta32, ok32 = beta, ok
+        both = ok & ok32
+        scale = np.maximum(1.0, np.abs(beta32[both]).max(axis=1))
         out[prec] = {"solves_per_s": r["value"], "ms_per_solve": r["ms"],
                      "speedup_vs_fp32": r["value"] / base if base else None,
-                     "converged_fraction": float(r["ok"].mean()),
+                     "converged_fraction": float(ok.mean()),
                      "iterations_mean": float(r["it"].mean()), "iterations_max": int(r["it"].max()),
                      "assemble_ms_per_solve": r["kernel_ms"]["assemble"],
-                     "assemble_algorithmic_tflops": r["asm_tflops"]}
+                     "assemble_algorithmic_tflops": r["asm_tflops"],
+                     "residual_max": float(G[ok].max()),
+                     "residual_per_moment_max": [float(f"{v:.3g}") for v in G[ok].max(axis=0)[1:]],
+                     "beta_vs_fp32_max": float(np.max(np.abs(beta[both] - beta32[both]).max(axis=1)
+                                                      / scale))}
     return out
 
 
-def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph):
+def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph, iter_hist=None):
     """Device state and batch for a list of shock problems (gauge applied)."""
     import mem_inputs
     M = np.concatenate([p["M"] for p in probs]).astype(np.float32)
@@ -175,7 +222,7 @@ def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph):
                            np.stack([p["M_right"] for p in probs]),
                            np.stack([p["g_left"] for p in probs]),
                            np.stack([p["g_right"] for p in probs]), device=dev,
-                           use_graph=use_graph)
+                           use_graph=use_graph, iter_hist=iter_hist)
     P = len(probs)
     return batch, Md, bd, gd, torch.zeros(P, device=dev), torch.zeros(P, device=dev)
 
@@ -220,19 +267,46 @@ def ragged_rate(mem, torch, dev, steps):
     import mem_inputs
     rb = mem_inputs.ragged_batch(2048)
     ctx = mem.Context(3, 12)
-    b, M, be, g, t, dt = shock_setup(mem, torch, dev, ctx, rb["problems"], [rb["dx"]] * 2048, True)
-    ctx.step(b, M, be, g, t, dt, 1)
+    budget = 8
+    hist = torch.zeros(budget + 1, dtype=torch.int64, device=dev)
+    b, M, be, g, t, dt = shock_setup(mem, torch, dev, ctx, rb["problems"], [rb["dx"]] * 2048, True,
+                                     iter_hist=hist)
+    status = torch.zeros(b.n_cells, dtype=torch.int32, device=dev)
+    ctx.step(b, M, be, g, t, dt, 1, status=status)
+    torch.cuda.synchronize()
+    hist.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.step(b, M, be, g, t, dt, steps)
+    ctx.step(b, M, be, g, t, dt, steps, status=status)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.close()
+    st = status.cpu().numpy()
+    off = b.offsets.cpu().numpy()
+    fin = torch.isfinite(M).all(dim=1).cpu().numpy() & (M[:, 0] > 0).cpu().numpy()
+    mx = (st & mem.ST_MAXWELL_FLUX) != 0
+    prob_mx = np.array([mx[off[p]:off[p + 1]].any() for p in range(2048)])
+    prob_fin = np.array([fin[off[p]:off[p + 1]].all() for p in range(2048)])
+    h = hist.cpu().numpy().astype(np.int64)
+    cdf = np.cumsum(h) / max(int(h.sum()), 1)
+    pct = {f"p{q}": int(np.searchsorted(cdf, q / 100.0)) for q in (50, 90, 99)}
     return {"workload": f"2048 normal shocks (Mach U(1.2,10), tanh initial profiles), cell counts "
                         f"log-uniform in [64, 4096] ({b.n_cells} cells), dx = 1, {steps} steps, "
                         "hipGraph replay",
             "cells": b.n_cells, "steps": steps, "ms_per_step": 1e3 * el / steps,
-            "cell_steps_per_s": b.n_cells * steps / el}
+            "cell_steps_per_s": b.n_cells * steps / el,
+            "newton_iterations": {
+                "per_cell_step_histogram": h.tolist(),
+                "budget": budget,
+                "mean": float((h * np.arange(budget + 1)).sum() / max(int(h.sum()), 1)),
+                **pct, "max": int(np.nonzero(h)[0].max()) if h.any() else 0},
+            "problems_finite": int(prob_fin.sum()),
+            "maxwell_flux": {
+                "cells": int(mx.sum()), "problems": int(prob_mx.sum()),
+                "lowest_mach": float(rb["mach"][prob_mx].min()) if prob_mx.any() else None,
+                "note": "cells whose moments the 12^3 Gauss-Hermite nodes cannot represent "
+                        "(solve certifies non-realizability) step with the Maxwellian of "
+                        "their gauge"}}
 
 
 def latency_1d(mem, torch, dev, calls=200):
@@ -315,6 +389,8 @@ def main():
         dw, sw = (int(v) for v in args.tuning.split(","))
         ctx.set_tuning(dir_waves=dw, split_want=sw)
     r = run_solves(mem, ctx, Md, b0d, args.steps, args.warmup, tune=not args.tuning)
+    pass_rates = passes(mem, torch, ctx, Md, torch.tensor(cells["g"].astype(np.float32),
+                                                           device=dev), r)
     ctx.close()
     peak = MFMA_PEAK[args.prec]
 
@@ -363,6 +439,7 @@ def main():
                                    "lse_linesearch": r["kernel_ms"]["lse"]},
         },
     }
+    line["passes"] = pass_rates
     if args.mixed_cells > 0:
         line["mixed"] = mixed_comparison(mem, torch, dev, args.mixed_cells, 3, 1)
     if not args.no_extras:

@@ -78,6 +78,9 @@ typedef enum {
                                        certifies that no minimiser exists on the node set, or
                                        |beta| exceeded beta_max                                */
 #define MEM_ST_LAMBDA_FAIL   0x80u  /* characteristic speeds could not be computed                 */
+#define MEM_ST_MAXWELL_FLUX  0x100u /* mem_step: the solve ended NONREALIZABLE or NONFINITE, so the
+                                       cell's fluxes, speeds and next warm start use the Maxwellian
+                                       of its gauge instead                                       */
 
 typedef struct {
   int32_t dim;          /* 1 or 3                                                      */
@@ -148,6 +151,10 @@ typedef struct {
                                     graph is kept while the batch, state pointers and
                                     options stay the same.  0: plain launches.  Results
                                     are identical either way.                              */
+  int64_t*       iter_hist;      /* device [newton_per_step + 1] or NULL: after each step's
+                                    MaxEnt solve, bin k is incremented by the number of
+                                    cells whose solve took k Newton iterations (Alg. 1
+                                    directions).  Accumulates over calls; never cleared. */
 } mem_batch_t;
 
 /* ---- context -------------------------------------------------------------- */
@@ -206,6 +213,17 @@ MEM_API mem_err_t mem_maxent_solve(mem_ctx_t ctx, int64_t n_cells, const float* 
 MEM_API mem_err_t mem_dual(mem_ctx_t ctx, int64_t n_cells, const float* beta,
                            float* logZ, float* E, float* H, hipStream_t stream);
 
+/* Per-moment residual of a solution: G[n][K] with G[:,0] = 0 and, for k >= 1,
+ * G_k = E_sigma[phi_k] / E_sigma[phi_0] - M_k / M_0, the gradient of the dual
+ * objective whose size is the stopping quantity of Alg. 1 (max_k |G_k| is
+ * what mem_maxent_solve returns as resid).  Evaluated at the context's nodes
+ * in compensated FP32 arithmetic (double-float exponent and sums, Ogita-Rump-
+ * Oishi Dot2), which agrees with an FP64 evaluation to a few 1e-8 near a
+ * solution.  Cells with M_0 <= 0 or non-finite inputs give non-finite G.
+ * M, beta, G: device [n_cells][K].  dim must be 3. */
+MEM_API mem_err_t mem_moment_residual(mem_ctx_t ctx, int64_t n_cells, const float* M,
+                                      const float* beta, float* G, hipStream_t stream);
+
 /* Moment fluxes (eq. "The ME equation", flux line; Alg. 2 ComputeFluxes):
  * F[n][K] = int u_x phi_i(u_bar) f du in each cell's gauge, from beta
  * (beta[:,0] = n) and g.  lam[n][2] (may be NULL) = (min, max) eigenvalue of
@@ -229,7 +247,13 @@ MEM_API mem_err_t mem_collide(mem_ctx_t ctx, int64_t n_cells, float* M, const fl
  * step for the first step (a value <= 0 requests one from a solve of the
  * current state), out = step for the next call (CFL rule from the last
  * transport's speeds).  status (may be NULL): device [n_cells], OR of the
- * cells' solve status over the steps.  No host synchronisation. */
+ * cells' solve status over the steps.  A cell whose moments the nodes cannot
+ * represent (solve ends NONREALIZABLE or NONFINITE with finite moments, n > 0)
+ * takes beta of the Maxwellian of its gauge (beta_0 = n, -1/sqrt(2) on the
+ * pure second-degree statistics) for that step's fluxes and speeds and as the
+ * next warm start, and gets MEM_ST_MAXWELL_FLUX: the update stays conservative
+ * and finite while the closure there drops to the Maxwellian.  No host
+ * synchronisation. */
 MEM_API mem_err_t mem_step(mem_ctx_t ctx, const mem_batch_t* batch, float* M, float* beta,
                            float* g, float* t, float* dt, int32_t n_steps,
                            const mem_solve_opts_t* opts, uint32_t* status,

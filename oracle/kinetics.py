@@ -170,8 +170,20 @@ class ShockSolver:
         self.dt = self._dt(rho)
 
     def _solve(self, M, beta):
+        """Alg. 1 per cell.  Where the nodes cannot represent a cell's moments (the
+        solve certifies non-realizability, or its iterate is not finite) the cell
+        takes the Maxwellian of its gauge, so that fluxes and speeds stay defined
+        (the paper integrates over a wide fixed velocity box and does not meet this
+        case; the GPU step applies the same rule)."""
         out = _maxent.newton_solve(M, beta, self.Phi, self.logw, **self.newton)
-        return out["beta"]
+        b = out["beta"]
+        ok_M = np.all(np.isfinite(M), axis=1) & (M[:, 0] > 0)
+        bad = ok_M & (out["nonrealizable"] | ~np.all(np.isfinite(b), axis=1))
+        if np.any(bad):
+            b = b.copy()
+            b[bad] = _maxent.maxwellian_beta(M[bad], DIM)
+        self.maxwell_cells = bad
+        return b
 
     def _dt(self, rho):
         rmax = max(np.max(rho), self.ghost_left[2], self.ghost_right[2])

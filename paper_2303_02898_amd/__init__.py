@@ -23,6 +23,7 @@ ST_FP64 = 0x10
 ST_NONFINITE = 0x20
 ST_NONREALIZABLE = 0x40
 ST_LAMBDA_FAIL = 0x80
+ST_MAXWELL_FLUX = 0x100
 
 PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
 
@@ -46,7 +47,8 @@ class Batch(ctypes.Structure):
     _fields_ = [("n_cells", _c_i64), ("n_problems", _c_i32), ("collision", _c_i32),
                 ("cell_offsets", _vp), ("dx", _vp), ("M_left", _vp), ("M_right", _vp),
                 ("g_left", _vp), ("g_right", _vp), ("cfl", _c_f32), ("prandtl", _c_f32),
-                ("mu_ref", _c_f32), ("newton_per_step", _c_i32), ("use_graph", _c_i32)]
+                ("mu_ref", _c_f32), ("newton_per_step", _c_i32), ("use_graph", _c_i32),
+                ("iter_hist", _vp)]
 
 
 _lib = None
@@ -80,6 +82,7 @@ def load_library():
         "mem_gauge": ([P, _c_i64, P, P, P, P], E),
         "mem_maxent_solve": ([P, _c_i64, P, P, ctypes.POINTER(SolveOpts), P, P, P, P], E),
         "mem_dual": ([P, _c_i64, P, P, P, P, P], E),
+        "mem_moment_residual": ([P, _c_i64, P, P, P, P], E),
         "mem_flux": ([P, _c_i64, P, P, P, P, P], E),
         "mem_collide": ([P, _c_i64, P, P, _c_f32, _c_f32, _c_f32, P], E),
         "mem_step": ([P, ctypes.POINTER(Batch), P, P, P, P, P, _c_i32,
@@ -280,6 +283,17 @@ class Context:
                                        _stream(stream)), "mem_dual")
         return logZ, E, H
 
+    def moment_residual(self, M, beta, stream=None):
+        """Per-moment residual G[n][K] (G_k = E[phi_k]/E[phi_0] - M_k/M_0), compensated."""
+        import torch
+        n = beta.shape[0]
+        G = torch.empty(n, self.K, dtype=torch.float32, device=beta.device)
+        self._check(self._lib.mem_moment_residual(
+            self._h, n, _ptr(M, torch.float32, (self.K,), "M"),
+            _ptr(beta, torch.float32, (self.K,), "beta"), G.data_ptr(), _stream(stream)),
+            "mem_moment_residual")
+        return G
+
     def flux(self, beta, g, want_lam=True, stream=None):
         import torch
         n = beta.shape[0]
@@ -322,7 +336,7 @@ class ShockBatch:
 
     def __init__(self, offsets, dx, M_left, M_right, g_left, g_right, device="cuda",
                  cfl=0.5, prandtl=2.0 / 3.0, mu_ref=0.7978845608028654, collision=1,
-                 newton_per_step=8, use_graph=False):
+                 newton_per_step=8, use_graph=False, iter_hist=None):
         import torch
         f32 = dict(dtype=torch.float32, device=device)
         self.offsets = torch.as_tensor(offsets, dtype=torch.int64, device=device).contiguous()
@@ -337,4 +351,13 @@ class ShockBatch:
                             self.dx.data_ptr(), self.M_left.data_ptr(), self.M_right.data_ptr(),
                             self.g_left.data_ptr(), self.g_right.data_ptr(), float(cfl),
                             float(prandtl), float(mu_ref), int(newton_per_step),
-                            int(bool(use_graph)))
+                            int(bool(use_graph)), None)
+        # iteration histogram (device int64 [newton_per_step + 1]), accumulated by mem_step
+        self.iter_hist = None
+        if iter_hist is not None:
+            if (iter_hist.dtype != torch.int64 or not iter_hist.is_contiguous()
+                    or iter_hist.numel() != int(newton_per_step) + 1 or not iter_hist.is_cuda):
+                raise ValueError("iter_hist must be a contiguous device int64 tensor of "
+                                 "newton_per_step + 1 bins")
+            self.iter_hist = iter_hist
+            self.struct.iter_hist = iter_hist.data_ptr()

@@ -373,6 +373,23 @@ mem_err_t mem_dual(mem_ctx_t c, int64_t n, const float* beta, float* logZ, float
   return MEM_OK;
 }
 
+mem_err_t mem_moment_residual(mem_ctx_t c, int64_t n, const float* M, const float* beta,
+                              float* G, hipStream_t s) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  if (c->dim != 3) return fail(c, MEM_ERR_UNSUPPORTED, "mem_moment_residual: dim 3 only");
+  if (n < 0 || (n > 0 && (!M || !beta || !G)))
+    return fail(c, MEM_ERR_INVALID_ARG, "mem_moment_residual: arguments");
+  if (n == 0) return MEM_OK;
+  mem_err_t e = ensure_cells(c, n);
+  if (e != MEM_OK) return e;
+  SolveParams p = params_from(nullptr);
+  // log Z in FP32 only shifts the exponent: the quotients E_k / E_0 cancel it
+  MEM_HIP(c, launch_lse3(c, n, nullptr, nullptr, n, nullptr, const_cast<float*>(beta), false, p,
+                         nullptr, nullptr, s));
+  MEM_HIP(c, launch_moment_residual3(c, n, M, beta, G, s));
+  return MEM_OK;
+}
+
 mem_err_t mem_flux(mem_ctx_t c, int64_t n, const float* beta, const float* g, float* F, float* lam,
                    hipStream_t s) {
   if (!c) return MEM_ERR_INVALID_ARG;
@@ -451,6 +468,7 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
   // solve the current state; set dt where the caller asked for one
   e = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, s);
   if (e != MEM_OK) return e;
+  MEM_HIP(c, launch_maxwell_fallback(c, n, M, beta, s));
   MEM_HIP(c, launch_flux3(c, n, beta, g, nullptr, c->w_rho, true, true, status, s));
   MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, s));
   MEM_HIP(c, launch_dt_update(c, P, b->dx, b->cfl, t, dt, false, s));
@@ -459,7 +477,9 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
     MEM_HIP(c, launch_collide3(c, n, M, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, st));
     mem_err_t er = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, st);
     if (er != MEM_OK) return er;
+    MEM_HIP(c, launch_maxwell_fallback(c, n, M, beta, st));
     if (status) MEM_HIP(c, launch_status_or(n, c->w_status, status, st));
+    if (b->iter_hist) MEM_HIP(c, launch_iter_hist(n, c->w_iters, budget + 1, b->iter_hist, st));
     MEM_HIP(c, launch_flux3(c, n, beta, g, c->w_F, c->w_rho, true, true, status, st));
     MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, st));
     MEM_HIP(c, launch_fv3(c, n, M, c->w_F, c->w_rho, g, c->w_prob, b->cell_offsets, b->dx, dt,

@@ -972,6 +972,17 @@ __device__ __forceinline__ void df_acc(dfl& acc, dfl x, dfl y) {
   acc.l = acc.l + (se + (pe + (x.h * y.l + x.l * y.h)));
 }
 
+// acc += x * y (x a plain FP32 value, y double-float): df_acc with x.l = 0
+__device__ __forceinline__ void df_acc1(dfl& acc, float x, dfl y) {
+#pragma clang fp contract(off)
+  const float p = x * y.h;
+  const float pe = fmaf(x, y.h, -p);
+  float sh, se;
+  two_sum(acc.h, p, sh, se);
+  acc.h = sh;
+  acc.l = acc.l + (se + (pe + x * y.l));
+}
+
 // acc += x (x double-float)
 __device__ __forceinline__ void df_add(dfl& acc, dfl x) {
 #pragma clang fp contract(off)
@@ -989,21 +1000,26 @@ __device__ __forceinline__ dfl df_norm(dfl a) {
 
 // One 64-thread workgroup per cell.  t1 = one-dimensional tables, double-float:
 // t1[a * n + k] = h_a(x_k) (a = 0..4), t1[5 * n + k] = lw_k.
+// list / ctr may be null (cells 0 .. ncell - 1); racc and out_list may be
+// null; G row stride gst (36 for the refinement workspace, K for callers).
 __global__ __launch_bounds__(64) void k_accurate3(
     const float2* __restrict__ t1, int n, const int32_t* __restrict__ list,
-    const int32_t* __restrict__ ctr, const float* __restrict__ M, const float* __restrict__ beta,
-    const float* __restrict__ logZ, float* __restrict__ Gacc, float* __restrict__ racc, float tol,
-    int32_t* out_list, int32_t* out_ctr) {
+    const int32_t* __restrict__ ctr, int64_t ncell, const float* __restrict__ M,
+    const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ Gacc,
+    int gst, float* __restrict__ racc, float tol, int32_t* out_list, int32_t* out_ctr) {
 #pragma clang fp contract(off)
-  const int64_t count = *ctr;
+  const int64_t count = ctr ? (int64_t)(*ctr) : ncell;
   const int64_t slot = blockIdx.x;
   if (slot >= count) return;
   const int lane = threadIdx.x;
-  const int64_t cell = list[slot];
+  const int64_t cell = list ? (int64_t)list[slot] : slot;
   extern __shared__ float2 dyn[];
   float2* sU = dyn;               // [n][15]  U, later R
   float2* sV = dyn + n * NBC;     // [n*n][5] V, later P
-  auto H = [&](int a, int k) -> dfl { const float2 v = t1[a * n + k]; return {v.x, v.y}; };
+  float2* sT = sV + n * n * 5;    // [6][n]   the 1D tables
+  for (int t = lane; t < 6 * n; t += 64) sT[t] = t1[t];
+  __builtin_amdgcn_wave_barrier();
+  auto H = [&](int a, int k) -> dfl { const float2 v = sT[a * n + k]; return {v.x, v.y}; };
 
   // U[i][b,c] = sum_a beta_abc h_a(x_i)
   for (int t = lane; t < n * NBC; t += 64) {
@@ -1015,7 +1031,7 @@ __global__ __launch_bounds__(64) void k_accurate3(
     for (int a = 0; a <= 4 - m; ++a) {
       const int k = bidx3(a, b, c);
       const float bk = k == 0 ? 0.f : beta[cell * K3 + k];  // beta_0 enters as log Z
-      df_acc(u, {bk, 0.f}, H(a, i));
+      df_acc1(u, bk, H(a, i));
     }
     sU[t] = make_float2(u.h, u.l);
   }
@@ -1055,7 +1071,7 @@ __global__ __launch_bounds__(64) void k_accurate3(
       const float ex = expf(e.h);
       const float w = fmaf(ex, e.l, ex);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) df_acc(P[c], {w, 0.f}, H(c, l));
+      for (int c = 0; c < 5; ++c) df_acc1(P[c], w, H(c, l));
     }
 #pragma unroll
     for (int c = 0; c < 5; ++c) sV[q * 5 + c] = make_float2(P[c].h, P[c].l);
@@ -1103,11 +1119,11 @@ __global__ __launch_bounds__(64) void k_accurate3(
     const float m2 = fmaf(-m1, nn, mi) / nn;
     g = (e1 - m1) + (e2 - m2);
   }
-  if (lane < 36) Gacc[cell * 36 + lane] = g;
+  if (lane < gst) Gacc[cell * gst + lane] = g;
   const float r = wave_max(fabsf(g));
   if (lane == 0) {
-    racc[cell] = r;
-    if (!(r <= tol)) out_list[atomicAdd(out_ctr, 1)] = (int)cell;
+    if (racc) racc[cell] = r;
+    if (out_list && !(r <= tol)) out_list[atomicAdd(out_ctr, 1)] = (int)cell;
   }
 }
 
@@ -1286,10 +1302,19 @@ hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
                            const float* M, const float* beta, float tol, int32_t* out_list,
                            int32_t* out_ctr, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  const size_t lds = (size_t)(c->n1d * NBC + c->n1d * c->n1d * 5) * sizeof(float2);
-  k_accurate3<<<(unsigned)grid_cells, 64, lds, s>>>(c->d_t1, c->n1d, list, ctr, M, beta,
-                                                     c->w_logZ, c->w_Gacc, c->w_racc, tol,
-                                                     out_list, out_ctr);
+  const size_t lds = (size_t)(c->n1d * NBC + c->n1d * c->n1d * 5 + 6 * c->n1d) * sizeof(float2);
+  k_accurate3<<<(unsigned)grid_cells, 64, lds, s>>>(c->d_t1, c->n1d, list, ctr, grid_cells, M,
+                                                     beta, c->w_logZ, c->w_Gacc, 36, c->w_racc,
+                                                     tol, out_list, out_ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_moment_residual3(mem_ctx_t c, int64_t n, const float* M, const float* beta,
+                                   float* G, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t lds = (size_t)(c->n1d * NBC + c->n1d * c->n1d * 5 + 6 * c->n1d) * sizeof(float2);
+  k_accurate3<<<(unsigned)n, 64, lds, s>>>(c->d_t1, c->n1d, nullptr, nullptr, n, M, beta,
+                                            c->w_logZ, G, K3, nullptr, 0.f, nullptr, nullptr);
   return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 // with h_m(b; c) = E[He_m(X)], X ~ N(b, 1 + c); the 3D matrix is the
 // Kronecker product of the three axis matrices, applied axis by axis on the
 // total-degree-<=4 index set (which the lower-triangular factors preserve).
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -162,7 +163,8 @@ __global__ void k_flux3(int64_t n, const float* __restrict__ S, const float* __r
 //   * Householder tridiagonalisation of A (Householder vector and p - K v
 //     shared through LDS, lane-parallel rank-2 updates);
 //   * extreme eigenvalues of the tridiagonal matrix by multisection: every
-//     lane evaluates a Sturm count at its own shift, 64 subintervals per round.
+//     lane evaluates a Sturm count at its own shift, the two halves of the
+//     wave bracketing the two extremes, 32 subintervals each per round.
 typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int EIG_WAVES = 4;
 constexpr int EST = 36;  // row stride of the per-wave LDS matrices
@@ -327,38 +329,53 @@ __global__ __launch_bounds__(256) void k_eig3(int64_t n, const float* __restrict
   }
   glo = wmin(glo);
   ghi = wmax(ghi);
+  // Sturm count below xs (number of negative pivots of T - xs I), with d_k and
+  // e_k^2 in registers and the hardware reciprocal in place of the division
+  float dk[K3], e2[K3 - 1];
+#pragma unroll
+  for (int i = 0; i < K3; ++i) dk[i] = dd[i];
+#pragma unroll
+  for (int i = 0; i < K3 - 1; ++i) e2[i] = ee[i] * ee[i];
   auto count_below = [&](float xs) {
     int cnt = 0;
-    float q = dd[0] - xs;
+    float q = dk[0] - xs;
     if (q == 0.f) q = -1e-30f;
-    if (q < 0.f) ++cnt;
+    cnt += q < 0.f;
+#pragma unroll
     for (int i = 1; i < K3; ++i) {
-      q = dd[i] - xs - ee[i - 1] * ee[i - 1] / q;
+      q = fmaf(-e2[i - 1], __builtin_amdgcn_rcpf(q), dk[i] - xs);
       if (q == 0.f) q = -1e-30f;
-      if (q < 0.f) ++cnt;
+      cnt += q < 0.f;
     }
     return cnt;
   };
-  // smallest x with count_below(x) >= need: the bracket [lo, hi] always has
-  // count_below(hi) >= need, and lane 63 samples hi itself
-  auto extreme = [&](int need) {
-    float lo = glo, hi = ghi;
-    for (int round = 0; round < 5; ++round) {
-      const float wdt = hi - lo;
-      const float xs = lane == 63 ? hi : lo + wdt * (float)(lane + 1) * (1.f / 64.f);
-      const unsigned long long m = __ballot(count_below(xs) >= need);
-      if (m == 0ull) break;
-      const int f = __ffsll((long long)m) - 1;
-      const float nh = f == 63 ? hi : lo + wdt * (float)(f + 1) * (1.f / 64.f);
-      lo = lo + wdt * (float)f * (1.f / 64.f);
-      hi = nh;
+  // Both extremes at once: lanes 0..31 bracket the smallest eigenvalue (first x
+  // with count >= 1), lanes 32..63 the largest (first x with count >= K); each
+  // half samples 32 shifts per round, its last lane the bracket's upper end,
+  // where count >= need always holds.
+  float lo2[2] = {glo, glo}, hi2[2] = {ghi, ghi};
+  const int half = lane >> 5, sub = lane & 31;
+  const int need = half ? K3 : 1;
+  for (int round = 0; round < 5; ++round) {
+    const float lo = half ? lo2[1] : lo2[0], hi = half ? hi2[1] : hi2[0];
+    const float wdt = hi - lo;
+    const float xs = sub == 31 ? hi : lo + wdt * (float)(sub + 1) * (1.f / 32.f);
+    const unsigned long long m = __ballot(count_below(xs) >= need);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const unsigned int mh = (unsigned int)(m >> (32 * h));
+      if (mh == 0u) continue;
+      const int f = __ffs((int)mh) - 1;
+      const float w2 = hi2[h] - lo2[h];
+      const float nh = f == 31 ? hi2[h] : lo2[h] + w2 * (float)(f + 1) * (1.f / 32.f);
+      lo2[h] = lo2[h] + w2 * (float)f * (1.f / 32.f);
+      hi2[h] = nh;
     }
-    return 0.5f * (lo + hi);
-  };
+  }
   float mu_lo = 0.f, mu_hi = 0.f;
   if (ok) {
-    mu_lo = extreme(1);
-    mu_hi = extreme(K3);
+    mu_lo = 0.5f * (lo2[0] + hi2[0]);
+    mu_hi = 0.5f * (lo2[1] + hi2[1]);
     ok = isfinite(mu_lo) && isfinite(mu_hi);
   }
   if (!ok) {  // bound |mu| <= max_p |u_bar_x,p|
@@ -533,6 +550,42 @@ __global__ void k_status_or(int64_t n, const uint32_t* __restrict__ src, uint32_
   if (c < n) dst[c] |= src[c];
 }
 
+// Cells whose step solve could not represent the moments on the nodes take the
+// Maxwellian of their gauge (standard normal in gauge coordinates: -1/sqrt(2)
+// on the pure second-degree Hermite statistics, indices 4, 7, 9).
+__global__ void k_maxwell_fallback(int64_t n, const float* __restrict__ M, float* __restrict__ beta,
+                                   uint32_t* __restrict__ status_w) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const uint32_t st = status_w[c];
+  if (!(st & (MEM_ST_NONREALIZABLE | MEM_ST_NONFINITE))) return;
+  const float* m = M + c * K3;
+  bool fin = m[0] > 0.f;
+  for (int k = 0; k < K3; ++k) fin = fin && isfinite(m[k]);
+  if (!fin) return;
+  float* b = beta + c * K3;
+  for (int k = 0; k < K3; ++k) b[k] = 0.f;
+  b[0] = m[0];
+  b[4] = b[7] = b[9] = -0.70710678118654752f;
+  status_w[c] = st | MEM_ST_MAXWELL_FLUX;
+}
+
+// Distribution of per-cell Newton iterations of one step's solve: an LDS
+// histogram per workgroup, added to the device histogram at the end.
+__global__ __launch_bounds__(256) void k_iter_hist(int64_t n, const int32_t* __restrict__ iters,
+                                                   int nbins, unsigned long long* hist) {
+  extern __shared__ unsigned int sh_bins[];
+  for (int i = threadIdx.x; i < nbins; i += 256) sh_bins[i] = 0u;
+  __syncthreads();
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
+    const int k = min(max(iters[c], 0), nbins - 1);
+    atomicAdd(&sh_bins[k], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbins; i += 256)
+    if (sh_bins[i]) atomicAdd(&hist[i], (unsigned long long)sh_bins[i]);
+}
+
 __global__ void k_copy(int64_t n, const float* __restrict__ src, float* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -661,6 +714,22 @@ hipError_t launch_dt_update(mem_ctx_t c, int P, const float* dx, float cfl, floa
 
 hipError_t launch_rmax_init(mem_ctx_t c, int P, hipStream_t s) {
   k_rmax_init<<<nb(P, 128), 128, 0, s>>>(P, c->w_gR, c->w_rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxwell_fallback(mem_ctx_t c, int64_t n, const float* M, float* beta,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_maxwell_fallback<<<nb(n, 256), 256, 0, s>>>(n, M, beta, c->w_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_iter_hist(int64_t n, const int32_t* iters, int nbins, int64_t* hist,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>(nb(n, 256), 1024);
+  k_iter_hist<<<grid, 256, (size_t)nbins * sizeof(unsigned int), s>>>(
+      n, iters, nbins, reinterpret_cast<unsigned long long*>(hist));
   return hipGetLastError();
 }
 

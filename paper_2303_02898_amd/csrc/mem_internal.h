@@ -171,6 +171,8 @@ hipError_t launch_fallback3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
 hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                             const int32_t* ctr, const float* M, const float* beta, float tol,
                             int32_t* out_list, int32_t* out_ctr, hipStream_t s);
+hipError_t launch_moment_residual3(mem_ctx_t c, int64_t n, const float* M, const float* beta,
+                                   float* G, hipStream_t s);
 hipError_t launch_refine3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                           const int32_t* ctr, const float* M, float* beta, hipStream_t s);
 hipError_t launch_refine_final(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
@@ -198,6 +200,10 @@ hipError_t launch_rho_max(mem_ctx_t c, int64_t n, const float* rho, const int32_
 hipError_t launch_dt_update(mem_ctx_t c, int P, const float* dx, float cfl, float* t,
                             float* dt, bool advance_t, hipStream_t s);
 hipError_t launch_status_or(int64_t n, const uint32_t* src, uint32_t* dst, hipStream_t s);
+hipError_t launch_maxwell_fallback(mem_ctx_t c, int64_t n, const float* M, float* beta,
+                                   hipStream_t s);
+hipError_t launch_iter_hist(int64_t n, const int32_t* iters, int nbins, int64_t* hist,
+                            hipStream_t s);
 hipError_t launch_rmax_init(mem_ctx_t c, int P, hipStream_t s);
 hipError_t launch_copy(int64_t n, const float* src, float* dst, hipStream_t s);
 hipError_t launch_conserved(mem_ctx_t c, const mem_batch_t* b, const float* M,

@@ -303,3 +303,40 @@ def test_autotune_keeps_results(ctx3, rule3):
     conv = (st[idx][good] & mem.ST_CONVERGED) != 0
     assert r[conv].max() <= 1.0 and berr.max() <= 1e-4
     ctx3.set_tuning(4, 512)
+
+
+def test_moment_residual_matches_fp64(ctx3, rule3):
+    """mem_moment_residual against the oracle's FP64 evaluation, per moment.
+    Compensated arithmetic leaves each node weight sigma_p with a relative error
+    of a few 2^-24 (FP32 exp of the double-float exponent), so
+    |G_k - G_k^fp64| <= 2^-20 (sum_p sigma_p |phi_k(p)| + |E_k|) / E_0 + 2^-23 |G_k|,
+    near a solution (after a solve) and far from one (the Maxwellian start)."""
+    C = 333
+    cells = mem_inputs.mott_smith_cells(C, config=2, replica=13)
+    M = f32(cells["M"])
+    b0 = f32(mem_inputs.maxwellian_beta(C, 35, M[:, 0]))
+    bg = dev(b0)
+    ctx3.solve(dev(M), bg)
+    torch.cuda.synchronize()
+    Phi, logw = rule3["Phi"], rule3["logw"]
+    for what, beta in (("solution", bg.cpu().numpy().astype(np.float64)), ("start", b0)):
+        G = ctx3.moment_residual(dev(M), dev(beta)).cpu().numpy().astype(np.float64)
+        sig = maxent.sigma(beta, Phi, logw)
+        E = sig @ Phi
+        A = sig @ np.abs(Phi)
+        G_o = E / E[:, :1] - M / M[:, :1]
+        G_o[:, 0] = 0.0
+        bound = 2.0 ** -20 * (A + np.abs(E)) / E[:, :1] + 2.0 ** -23 * np.abs(G_o) + 1e-12
+        err = np.abs(G - G_o)
+        print(f"[moment residual, {what}] max |G| {np.abs(G_o).max():.2e}, max err "
+              f"{err.max():.2e}, err/bound max {np.max(err / bound):.3f}")
+        assert G[:, 0].max() == 0.0 and G[:, 0].min() == 0.0
+        assert np.all(err <= bound)
+    # its max-norm is the residual the solve reports for the same beta (the solve's
+    # own log Z shift differs in rounding, hence the 2e-7 + 1% agreement)
+    b2 = dev(b0)
+    _, resid, st = ctx3.solve(dev(M), b2)
+    torch.cuda.synchronize()
+    G2 = ctx3.moment_residual(dev(M), b2).abs().max(dim=1).values
+    conv = (st & mem.ST_CONVERGED) != 0
+    assert torch.allclose(G2[conv], resid[conv], rtol=1e-2, atol=2e-7)

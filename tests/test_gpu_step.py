@@ -182,14 +182,20 @@ def test_ragged_batch_runs_and_matches_single(ctx3):
     Md, gd = dev(f32(M)), dev(f32(g))
     ctx3.gauge(Md, None, gd)
     bd = dev(f32(mem_inputs.maxwellian_beta(M.shape[0], 35, Md[:, 0].cpu().numpy())))
+    hist = torch.zeros(9, dtype=torch.int64, device=DEV)
     batch = mem.ShockBatch(off, [p["dx"] for p in probs], np.stack([p["M_left"] for p in probs]),
                            np.stack([p["M_right"] for p in probs]),
                            np.stack([p["g_left"] for p in probs]),
-                           np.stack([p["g_right"] for p in probs]), device=DEV)
+                           np.stack([p["g_right"] for p in probs]), device=DEV, iter_hist=hist)
     t = torch.zeros(3, device=DEV)
     dt = torch.zeros(3, device=DEV)
     ctx3.step(batch, Md, bd, gd, t, dt, 5)
     torch.cuda.synchronize()
+    # every cell is counted once per step, in a bin within the iteration budget
+    h = hist.cpu().numpy()
+    assert h.sum() == 5 * M.shape[0], h
+    assert h[0] == 0, h   # every valid cell takes at least one Newton direction
+    print(f"[ragged] Newton iterations per cell-step: {h.tolist()}")
     for k, p in enumerate(probs):
         b1, M1, b1d, g1, t1, dt1, _ = _gpu_shock(p, ctx3, 0)
         ctx3.step(b1, M1, b1d, g1, t1, dt1, 5)

@@ -138,3 +138,25 @@ def test_fv_update_is_conservative():
     fR = 0.5 * (F[-1, 0] + (TR @ FRg)[0]) + 0.5 * max(rho[-1], rR) * (M[-1, 0] - (TR @ MRg)[0])
     dm = np.sum(M2[:, 0] - M[:, 0]) * s.dx
     assert dm == pytest.approx(dt * (fL - fR), rel=1e-10, abs=1e-13)
+
+
+def test_unrepresentable_cell_takes_its_maxwellian():
+    """On a positive discrete measure E[phi_k] lies between min_p and max_p of
+    phi_k over the nodes: a target above the maximum is certainly not
+    representable.  Such a cell takes the Maxwellian of its gauge; a Maxwellian
+    cell beside it solves to the Maxwellian as usual."""
+    from oracle import maxent
+    s = kinetics.ShockSolver(1.5, 8, -4.0, 4.0, 2.0, nodes_1d=8)
+    M = np.zeros((2, 35))            # Hermite moments of n N(0, I) in its own gauge
+    M[:, 0] = (1.3, 0.7)
+    k4 = [i for i, e in enumerate(basis_indices()) if e == (4, 0, 0)][0]
+    M[1, k4] = 1.5 * M[1, 0] * np.max(s.Phi[:, k4])     # beyond every node value
+    beta = s._solve(M, maxent.maxwellian_beta(M, 3))
+    assert s.maxwell_cells.tolist() == [False, True]
+    assert np.allclose(beta[1], maxent.maxwellian_beta(M[1:], 3)[0])
+    assert np.allclose(beta[0], maxent.maxwellian_beta(M[:1], 3)[0], atol=1e-9)
+
+
+def basis_indices():
+    from oracle import basis
+    return [tuple(e) for e in basis.multi_indices(3)]
