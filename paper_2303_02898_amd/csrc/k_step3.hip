@@ -188,6 +188,19 @@ __device__ __forceinline__ float wmax(float v) {
   return v;
 }
 
+// An empty asm that reads and writes every entry of a 35-value column, so
+// that the values exist in registers at this point of the program.
+__device__ __forceinline__ void eig_keep(float (&v)[K3]) {
+  asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]),
+               "+v"(v[6]), "+v"(v[7]), "+v"(v[8]));
+  asm volatile("" : "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]),
+               "+v"(v[14]), "+v"(v[15]), "+v"(v[16]), "+v"(v[17]));
+  asm volatile("" : "+v"(v[18]), "+v"(v[19]), "+v"(v[20]), "+v"(v[21]), "+v"(v[22]),
+               "+v"(v[23]), "+v"(v[24]), "+v"(v[25]), "+v"(v[26]));
+  asm volatile("" : "+v"(v[27]), "+v"(v[28]), "+v"(v[29]), "+v"(v[30]), "+v"(v[31]),
+               "+v"(v[32]), "+v"(v[33]), "+v"(v[34]));
+}
+
 __global__ __launch_bounds__(256) void k_eig3(int64_t n, const float* __restrict__ S,
                                               const float* __restrict__ Sx,
                                               const float* __restrict__ g, float umax,
@@ -197,7 +210,7 @@ __global__ __launch_bounds__(256) void k_eig3(int64_t n, const float* __restrict
   const int64_t c = (int64_t)blockIdx.x * EIG_WAVES + wv;
   if (c >= n) return;  // whole wave
   __shared__ __align__(16) float sbuf[EIG_WAVES][2 * K3 * EST];  // S, Sx rows; then L and T
-  __shared__ float svec[EIG_WAVES][5][EST];                     // 1/L_kk, v, q, d, e
+  __shared__ __align__(16) float svec[EIG_WAVES][5][EST];       // 1/L_kk, v, q, d, e
   float* W = sbuf[wv];
   float* Lm = W;              // row k = column k of L
   float* T = W + K3 * EST;    // transposes
@@ -210,7 +223,9 @@ __global__ __launch_bounds__(256) void k_eig3(int64_t n, const float* __restrict
     const f4* s4 = reinterpret_cast<const f4*>(S + c * NCOL);
     const f4* x4 = reinterpret_cast<const f4*>(Sx + c * NCOL);
     f4* w4 = reinterpret_cast<f4*>(W);
-    for (int i = lane; i < NCOL / 4; i += 64) { w4[i] = s4[i]; w4[NCOL / 4 + i] = x4[i]; }
+    // S in the rows that become L, Sx in the area that becomes T (read only
+    // after the Cholesky, so that one 35-value column is live at a time)
+    for (int i = lane; i < NCOL / 4; i += 64) { w4[i] = s4[i]; w4[K3 * EST / 4 + i] = x4[i]; }
   }
   __builtin_amdgcn_wave_barrier();
   const float inv0 = 1.f / W[0];
@@ -221,40 +236,67 @@ __global__ __launch_bounds__(256) void k_eig3(int64_t n, const float* __restrict
   for (int i = 0; i < K3; ++i) {
     const int lo = i < j ? i : j, hi = i < j ? j : i;
     a[i] = W[pair_col(lo, hi)] * inv0;
-    x[i] = W[NCOL + pair_col(lo, hi)] * inv0;
   }
-  __builtin_amdgcn_wave_barrier();  // the staging area becomes L and T
+  __builtin_amdgcn_wave_barrier();  // the S rows become L
 
-  // Cholesky of B
+  // Cholesky of B, right-looking: step k writes column k of the current matrix
+  // to LDS, reads it back with aligned broadcast reads (pivot included), updates
+  // the trailing columns unpredicated (multiplier 0 on lanes <= k) and then
+  // stores column k of L in the same row
   float dinv = 1.f;
 #pragma unroll
   for (int k = 0; k < K3; ++k) {
-    const float d = rlf(a[k], k);
+    float* row = Lm + k * EST;
+    if (lane < K3) row[lane] = a[k];
+    __builtin_amdgcn_wave_barrier();
+    float u[EST];
+    const f4* r4 = reinterpret_cast<const f4*>(row);
+#pragma unroll
+    for (int q = k / 4; q < EST / 4; ++q) {
+      const f4 v = r4[q];
+      u[4 * q] = v[0]; u[4 * q + 1] = v[1]; u[4 * q + 2] = v[2]; u[4 * q + 3] = v[3];
+    }
+    const float d = u[k];
     ok = ok && d > 0.f && isfinite(d);
     const float inv = __builtin_amdgcn_rsqf(d);
-    const float l = lane >= k ? a[k] * inv : 0.f;
     if (lane == k) dinv = inv;
-    if (lane < K3) Lm[k * EST + lane] = l;
-    if (k == K3 - 1) break;
+    const float cj = lane > k ? a[k] * (inv * inv) : 0.f;
+#pragma unroll
+    for (int i = k + 1; i < K3; ++i) a[i] = fmaf(-u[i], cj, a[i]);
     __builtin_amdgcn_wave_barrier();
-    float lb[K3];
-#pragma unroll
-    for (int i = k + 1; i < K3; ++i) lb[i] = Lm[k * EST + i];
-    if (lane > k) {
-#pragma unroll
-      for (int i = k + 1; i < K3; ++i) a[i] = fmaf(-lb[i], l, a[i]);
-    }
+    if (lane < K3) row[lane] = lane >= k ? a[k] * inv : 0.f;  // L[lane][k]
+    // materialise the updated column here: left to itself the compiler turns the
+    // right-looking update into a left-looking one (each entry recomputed when
+    // first needed) and keeps every earlier step's row and multiplier alive
+    eig_keep(a);
+    asm volatile("" : "+v"(dinv));
+    __builtin_amdgcn_wave_barrier();
   }
   if (lane < K3) invd[lane] = dinv;
-  __builtin_amdgcn_wave_barrier();
-  // forward substitution L y = x on this lane's column
+#pragma unroll
+  for (int i = 0; i < K3; ++i) {
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    x[i] = T[pair_col(lo, hi)] * inv0;
+  }
+  __builtin_amdgcn_wave_barrier();  // the Sx staging becomes T
+  // forward substitution L y = x on this lane's column (rows of L read 16 bytes
+  // at a time)
   auto fsolve = [&](float (&y)[K3]) {
 #pragma unroll
     for (int k = 0; k < K3; ++k) {
       const float yk = y[k] * invd[k];
       y[k] = yk;
+      const f4* r4 = reinterpret_cast<const f4*>(Lm + k * EST);
 #pragma unroll
-      for (int i = k + 1; i < K3; ++i) y[i] = fmaf(-Lm[k * EST + i], yk, y[i]);
+      for (int q = (k + 1) / 4; q < EST / 4; ++q) {
+        const f4 v = r4[q];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = 4 * q + t;
+          if (i > k && i < K3) y[i] = fmaf(-v[t], yk, y[i]);
+        }
+      }
+      eig_keep(y);  // keep the substitution column-oriented (see the Cholesky)
     }
   };
   // column j of the transpose: T[j][i] = y[i] written by lane j, read back as T[i][j]
@@ -276,19 +318,17 @@ __global__ __launch_bounds__(256) void k_eig3(int64_t n, const float* __restrict
   fsolve(x);              // column j of A = L^-1 C L^-T
   transpose(x, true);     // symmetrised against rounding
 
-  // Householder tridiagonalisation: d_k = A[k][k], e_k = A[k+1][k] of the result
+  // Householder tridiagonalisation: d_k = A[k][k], e_k = A[k+1][k] of the result.
+  // Lane i holds column i, so its x[k] is A[i][k]: every lane contributes its own
+  // entry of the reflector, the norm is a wave reduction.
+  const bool in = lane < K3;
 #pragma unroll
   for (int k = 0; k < K3 - 2; ++k) {
-    if (lane == k) {
-      dd[k] = x[k];
-#pragma unroll
-      for (int i = k + 1; i < K3; ++i) vb[i] = x[i];
-    }
-    __builtin_amdgcn_wave_barrier();
-    float sig = 0.f;
-#pragma unroll
-    for (int i = k + 1; i < K3; ++i) sig = fmaf(vb[i], vb[i], sig);
-    const float x0 = vb[k + 1];
+    const float xk = x[k];
+    const float vl = (lane > k && in) ? xk : 0.f;
+    const float sig = wsum(vl * vl);
+    const float x0 = rlf(xk, k + 1);
+    if (lane == 0) dd[k] = rlf(xk, k);
     const float nx = sqrtf(sig);
     const float al = x0 > 0.f ? -nx : nx;
     const float v1 = x0 - al;           // first entry of the Householder vector
@@ -296,24 +336,36 @@ __global__ __launch_bounds__(256) void k_eig3(int64_t n, const float* __restrict
     if (lane == 0) ee[k] = al;
     if (nx > 0.f && vn > 0.f) {
       const float bet = 2.f / vn;
+      const float vj = lane == k + 1 ? v1 : vl;
+      if (lane < EST) vb[lane] = vj;
+      __builtin_amdgcn_wave_barrier();
+      float vv[EST];
+      const f4* v4 = reinterpret_cast<const f4*>(vb);
+#pragma unroll
+      for (int q = (k + 1) / 4; q < EST / 4; ++q) {
+        const f4 v = v4[q];
+        vv[4 * q] = v[0]; vv[4 * q + 1] = v[1]; vv[4 * q + 2] = v[2]; vv[4 * q + 3] = v[3];
+      }
       float w = 0.f;
 #pragma unroll
-      for (int i = k + 1; i < K3; ++i) w = fmaf(x[i], i == k + 1 ? v1 : vb[i], w);
-      const bool act = lane > k && lane < K3;
-      const float vj = act ? (lane == k + 1 ? v1 : vb[j]) : 0.f;
-      const float pj = act ? bet * w : 0.f;
+      for (int i = k + 1; i < K3; ++i) w = fmaf(x[i], vv[i], w);
+      const float pj = (lane > k && in) ? bet * w : 0.f;
       const float Kc = 0.5f * bet * wsum(vj * pj);
       const float qj = pj - Kc * vj;
-      if (lane < K3) qb[lane] = qj;
+      if (lane < EST) qb[lane] = qj;
       __builtin_amdgcn_wave_barrier();
-      if (act) {
+      const f4* q4 = reinterpret_cast<const f4*>(qb);
 #pragma unroll
-        for (int i = k + 1; i < K3; ++i) {
-          const float vi = i == k + 1 ? v1 : vb[i];
-          x[i] = x[i] - (vi * qj + qb[i] * vj);
+      for (int q = (k + 1) / 4; q < EST / 4; ++q) {
+        const f4 qv = q4[q];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = 4 * q + t;
+          if (i > k && i < K3) x[i] = x[i] - (vv[i] * qj + qv[t] * vj);
         }
       }
     }
+    eig_keep(x);
     __builtin_amdgcn_wave_barrier();
   }
   if (lane == K3 - 2) { dd[K3 - 2] = x[K3 - 2]; ee[K3 - 2] = x[K3 - 1]; }
