@@ -163,12 +163,12 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
     // Newton correction and are evaluated again
     int32_t* la = c->w_list[0];
     int32_t* lb = c->w_list[1];
-    MEM_HIP(c, launch_set_ctr(&ctr[4], 1, s));
+    // ctr[4] is still zero from the reset above; each refinement pass zeroes the
+    // counter the following residual pass appends to
     MEM_HIP(c, launch_accurate3(c, n, c->w_list[3], &ctr[3], M, beta, p.tol_grad, la, &ctr[4], s));
     int ca = 4, cb = 5;
     for (int pass = 0; pass < refine; ++pass) {
-      MEM_HIP(c, launch_refine3(c, n, la, &ctr[ca], M, beta, s));
-      MEM_HIP(c, launch_set_ctr(&ctr[cb], 1, s));
+      MEM_HIP(c, launch_refine3(c, n, la, &ctr[ca], M, beta, &ctr[cb], s));
       MEM_HIP(c, launch_accurate3(c, n, la, &ctr[ca], M, beta, p.tol_grad, lb, &ctr[cb], s));
       std::swap(la, lb);
       std::swap(ca, cb);

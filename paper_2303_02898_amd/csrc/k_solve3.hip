@@ -1002,7 +1002,8 @@ __device__ __forceinline__ dfl df_norm(dfl a) {
 // t1[a * n + k] = h_a(x_k) (a = 0..4), t1[5 * n + k] = lw_k.
 // list / ctr may be null (cells 0 .. ncell - 1); racc and out_list may be
 // null; G row stride gst (36 for the refinement workspace, K for callers).
-__global__ __launch_bounds__(64) void k_accurate3(
+template <int NW>  // wavefronts per cell: 1 for throughput, 4 for the latency of small launches
+__global__ __launch_bounds__(64 * NW) void k_accurate3(
     const float2* __restrict__ t1, int n, const int32_t* __restrict__ list,
     const int32_t* __restrict__ ctr, int64_t ncell, const float* __restrict__ M,
     const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ Gacc,
@@ -1011,18 +1012,24 @@ __global__ __launch_bounds__(64) void k_accurate3(
   const int64_t count = ctr ? (int64_t)(*ctr) : ncell;
   const int64_t slot = blockIdx.x;
   if (slot >= count) return;
-  const int lane = threadIdx.x;
+  constexpr int NTH = 64 * NW;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int64_t cell = list ? (int64_t)list[slot] : slot;
+  auto sync = [] {
+    if constexpr (NW > 1) __syncthreads();
+    else __builtin_amdgcn_wave_barrier();
+  };
   extern __shared__ float2 dyn[];
   float2* sU = dyn;               // [n][15]  U, later R
   float2* sV = dyn + n * NBC;     // [n*n][5] V, later P
   float2* sT = sV + n * n * 5;    // [6][n]   the 1D tables
-  for (int t = lane; t < 6 * n; t += 64) sT[t] = t1[t];
-  __builtin_amdgcn_wave_barrier();
+  for (int t = tid; t < 6 * n; t += NTH) sT[t] = t1[t];
+  sync();
   auto H = [&](int a, int k) -> dfl { const float2 v = sT[a * n + k]; return {v.x, v.y}; };
 
   // U[i][b,c] = sum_a beta_abc h_a(x_i)
-  for (int t = lane; t < n * NBC; t += 64) {
+  for (int t = tid; t < n * NBC; t += NTH) {
     const int i = t / NBC, bc = t % NBC;
     int m = 0;
     while (tri(m + 1) <= bc) ++m;
@@ -1035,9 +1042,9 @@ __global__ __launch_bounds__(64) void k_accurate3(
     }
     sU[t] = make_float2(u.h, u.l);
   }
-  __builtin_amdgcn_wave_barrier();
+  sync();
   // V[i][j][c] = sum_b U[i][b,c] h_b(x_j)
-  for (int t = lane; t < n * n * 5; t += 64) {
+  for (int t = tid; t < n * n * 5; t += NTH) {
     const int ij = t / 5, c = t % 5, i = ij / n, j = ij % n;
     dfl v = {0.f, 0.f};
     for (int b = 0; b <= 4 - c; ++b) {
@@ -1046,10 +1053,10 @@ __global__ __launch_bounds__(64) void k_accurate3(
     }
     sV[t] = make_float2(v.h, v.l);
   }
-  __builtin_amdgcn_wave_barrier();
+  sync();
   // exponent, sigma and P[i][j][c] = sum_l sigma h_c(x_l); lane <-> (i, j)
   const float lz = logZ[cell];
-  for (int q = lane; q < n * n; q += 64) {
+  for (int q = tid; q < n * n; q += NTH) {
     const int i = q / n, j = q % n;
     dfl V[5], P[5];
 #pragma unroll
@@ -1076,9 +1083,9 @@ __global__ __launch_bounds__(64) void k_accurate3(
 #pragma unroll
     for (int c = 0; c < 5; ++c) sV[q * 5 + c] = make_float2(P[c].h, P[c].l);
   }
-  __builtin_amdgcn_wave_barrier();
+  sync();
   // R[i][b,c] = sum_j P[i][j][c] h_b(x_j)
-  for (int t = lane; t < n * NBC; t += 64) {
+  for (int t = tid; t < n * NBC; t += NTH) {
     const int i = t / NBC, bc = t % NBC;
     int m = 0;
     while (tri(m + 1) <= bc) ++m;
@@ -1090,7 +1097,8 @@ __global__ __launch_bounds__(64) void k_accurate3(
     }
     sU[t] = make_float2(r.h, r.l);
   }
-  __builtin_amdgcn_wave_barrier();
+  sync();
+  if (tid >= 64) return;  // the quotients and the reduction stay on the first wave
   // E_abc = sum_i R[i][b,c] h_a(x_i) on lane k = bidx3(a, b, c)
   dfl E = {0.f, 0.f};
   if (lane < K3) {
@@ -1129,9 +1137,13 @@ __global__ __launch_bounds__(64) void k_accurate3(
 
 // One Newton correction with the accurate gradient and the FP32 Hessian of
 // the cell's last assembly (wave per cell, as k_direction3).
+// reset (may be null) is zeroed by the first thread: the counter the next
+// residual pass appends to, which this kernel does not read.
 __global__ __launch_bounds__(256) void k_refine3(
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
-    const float* __restrict__ S, const float* __restrict__ Gacc, float* __restrict__ beta) {
+    const float* __restrict__ S, const float* __restrict__ Gacc, float* __restrict__ beta,
+    int32_t* reset) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && reset) *reset = 0;
   const int64_t count = *ctr;
   const int lane = threadIdx.x & 63;
   const int64_t slot = (int64_t)blockIdx.x * DIR_WAVES + (threadIdx.x >> 6);
@@ -1298,14 +1310,23 @@ hipError_t launch_fallback3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
   return hipGetLastError();
 }
 
+// Below this many cells a launch runs four wavefronts per cell (one node pair
+// per thread): the grid is too small to fill the chip, so latency decides.
+constexpr int64_t ACC_WIDE_BELOW = 16384;
+
 hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
                            const float* M, const float* beta, float tol, int32_t* out_list,
                            int32_t* out_ctr, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
   const size_t lds = (size_t)(c->n1d * NBC + c->n1d * c->n1d * 5 + 6 * c->n1d) * sizeof(float2);
-  k_accurate3<<<(unsigned)grid_cells, 64, lds, s>>>(c->d_t1, c->n1d, list, ctr, grid_cells, M,
-                                                     beta, c->w_logZ, c->w_Gacc, 36, c->w_racc,
-                                                     tol, out_list, out_ctr);
+  if (grid_cells < ACC_WIDE_BELOW)
+    k_accurate3<4><<<(unsigned)grid_cells, 256, lds, s>>>(c->d_t1, c->n1d, list, ctr, grid_cells,
+                                                          M, beta, c->w_logZ, c->w_Gacc, 36,
+                                                          c->w_racc, tol, out_list, out_ctr);
+  else
+    k_accurate3<1><<<(unsigned)grid_cells, 64, lds, s>>>(c->d_t1, c->n1d, list, ctr, grid_cells,
+                                                         M, beta, c->w_logZ, c->w_Gacc, 36,
+                                                         c->w_racc, tol, out_list, out_ctr);
   return hipGetLastError();
 }
 
@@ -1313,15 +1334,20 @@ hipError_t launch_moment_residual3(mem_ctx_t c, int64_t n, const float* M, const
                                    float* G, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const size_t lds = (size_t)(c->n1d * NBC + c->n1d * c->n1d * 5 + 6 * c->n1d) * sizeof(float2);
-  k_accurate3<<<(unsigned)n, 64, lds, s>>>(c->d_t1, c->n1d, nullptr, nullptr, n, M, beta,
-                                            c->w_logZ, G, K3, nullptr, 0.f, nullptr, nullptr);
+  if (n < ACC_WIDE_BELOW)
+    k_accurate3<4><<<(unsigned)n, 256, lds, s>>>(c->d_t1, c->n1d, nullptr, nullptr, n, M, beta,
+                                                 c->w_logZ, G, K3, nullptr, 0.f, nullptr, nullptr);
+  else
+    k_accurate3<1><<<(unsigned)n, 64, lds, s>>>(c->d_t1, c->n1d, nullptr, nullptr, n, M, beta,
+                                                c->w_logZ, G, K3, nullptr, 0.f, nullptr, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_refine3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
-                          const float* M, float* beta, hipStream_t s) {
+                          const float* M, float* beta, int32_t* reset, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  k_refine3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, c->w_Gacc, beta);
+  k_refine3<<<nblocks(grid_cells, DIR_WAVES), 256, 0, s>>>(list, ctr, c->w_S, c->w_Gacc, beta,
+                                                           reset);
   return hipGetLastError();
 }
 

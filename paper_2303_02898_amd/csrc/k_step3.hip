@@ -572,12 +572,26 @@ __global__ void k_rmax_init(int P, const float* __restrict__ gR, uint32_t* rmax)
   rmax[p] = __float_as_uint(fmaxf(gR[2 * p], gR[2 * p + 1]));
 }
 
+// Per-problem maximum of the spectral radii.  Neighbouring cells almost always
+// belong to the same problem: a wave whose lanes share one problem reduces first
+// and issues a single atomic, otherwise every lane issues its own.  Non-negative
+// floats order like their bit patterns, hence the unsigned maximum.
 __global__ void k_rho_max(int64_t n, const float* __restrict__ rho, const int32_t* __restrict__ prob,
                           uint32_t* rmax) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const float r = rho[c];
-  if (isfinite(r) && r >= 0.f) atomicMax(&rmax[prob[c]], __float_as_uint(r));
+  const bool in = c < n;
+  const float r = in ? rho[c] : 0.f;
+  const uint32_t v = (in && isfinite(r) && r >= 0.f) ? __float_as_uint(r) : 0u;
+  const int p = in ? prob[c] : -1;
+  const int p0 = __shfl(p, 0);
+  if (__all(!in || p == p0)) {
+    uint32_t m = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0 && p0 >= 0 && m > 0u) atomicMax(&rmax[p0], m);
+  } else if (in && v > 0u) {
+    atomicMax(&rmax[p], v);
+  }
 }
 
 // mode 0: set dt where dt <= 0; mode 1: t += dt, dt = CFL dx / max radius.

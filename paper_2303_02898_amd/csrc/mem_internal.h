@@ -174,7 +174,7 @@ hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
 hipError_t launch_moment_residual3(mem_ctx_t c, int64_t n, const float* M, const float* beta,
                                    float* G, hipStream_t s);
 hipError_t launch_refine3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
-                          const int32_t* ctr, const float* M, float* beta, hipStream_t s);
+                          const int32_t* ctr, const float* M, float* beta, int32_t* reset, hipStream_t s);
 hipError_t launch_refine_final(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                                const int32_t* ctr, float tol_loose, float* resid,
                                uint32_t* status, hipStream_t s);
