@@ -128,7 +128,9 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
   }
   int cur = 0;
   int64_t grid = n;  // live cells never increase: the last polled count bounds the grids
-  for (int it = 0; it <= max_iter; ++it) {
+  // every live cell takes one direction per pass and ends, at the latest, as
+  // MAXITER at its max_iter-th: max_iter passes leave no live cell
+  for (int it = 0; it < max_iter; ++it) {
     const int nxt = 1 - cur;
     {
       ProfScope ps(c, 0, s);

@@ -81,8 +81,9 @@ __global__ void k_init3(int64_t n, const float* __restrict__ M, float* __restric
   if (c < n) {
     const float* m = M + c * K3;
     float* b = beta + c * K3;
-    bool fin = true;
-    for (int k = 0; k < K3; ++k) fin = fin && isfinite(m[k]) && (k == 0 || isfinite(b[k]));
+    bool fin = true;  // & rather than &&: the 70 loads issue together
+#pragma unroll
+    for (int k = 0; k < K3; ++k) fin = fin & isfinite(m[k]) & (k == 0 || isfinite(b[k]));
     uint32_t st = 0;
     if (!fin) st = MEM_ST_NONFINITE;
     else if (!(m[0] > 0.f)) st = MEM_ST_NONREALIZABLE;

@@ -282,3 +282,26 @@ def test_shock_reaches_steady_state(ctx3):
     # profile no faster than the slow drift that is left on the GPU itself
     assert rate_steady <= 0.05 * rate_init
     assert rate_steady <= 4.0 * rate_gpu
+
+
+def test_strong_shock_stays_finite_and_conservative(ctx3):
+    """Mach 8: cells inside the layer are not representable on the 12^3 rule and
+    step with their Maxwellian (MEM_ST_MAXWELL_FLUX).  The state must stay
+    finite with n > 0, and, the layer being far from the ends, the totals of
+    mass, momentum and energy (FP64 sums) must not move: the ghost states carry
+    equal fluxes of all three (Rankine-Hugoniot)."""
+    problem = mem_inputs.shock_problem(8.0, 256, -128.0, 128.0, 10.0)
+    batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0)
+    tot0 = ctx3.conserved(batch, Md, gd).cpu().numpy()[0]
+    ctx3.step(batch, Md, bd, gd, t, dt, 20, status=status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    M = Md.cpu().numpy()
+    tot = ctx3.conserved(batch, Md, gd).cpu().numpy()[0]
+    nfb = int(((st & mem.ST_MAXWELL_FLUX) != 0).sum())
+    rel = np.abs(tot - tot0) / np.abs(tot0)
+    print(f"\n[mach 8] t {t.item():.3f}, Maxwell-flux cells {nfb}, totals moved by {rel.tolist()}")
+    assert nfb > 0                               # the fallback path ran
+    assert np.all(np.isfinite(M)) and np.all(M[:, 0] > 0)
+    assert np.all(np.isfinite(gd.cpu().numpy())) and np.all(gd.cpu().numpy()[:, 1:] > 0)
+    assert np.all(rel <= 1e-5), rel
