@@ -506,10 +506,10 @@ __device__ __forceinline__ int finish_cell(int64_t cell, float r, float res, boo
 }
 
 // Wave-cooperative Cholesky for one cell per wave.  Lane j < 34 holds column
-// j of the SPD matrix in registers (a[i] = A[i][j]); step k broadcasts the
-// pivot with readlane, shares column k of L through LDS and updates the
-// trailing columns.  On return lane i holds 1 / L[i][i] in dinv; for i > j,
-// lane j's a[i] equals L[i][j] * L[j][j].
+// j of the SPD matrix in registers (a[i] = A[i][j]); step k shares column k of
+// the current matrix (pivot included) through LDS, updates the trailing
+// columns and stores column k of L in the same row.  On return lane i holds
+// 1 / L[i][i] in dinv; for i > j, lane j's a[i] equals L[i][j] * L[j][j].
 __device__ __forceinline__ float rl(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
@@ -529,6 +529,21 @@ __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 // one write, a few 16-byte reads and the trailing FMAs.
 constexpr int LST = NH + 2;  // row stride of Lm (16-byte aligned rows)
 
+// An empty asm that reads and writes every entry of a 34-value column, so that
+// the values exist in registers at this point (keeps the factorisation
+// right-looking; see wave_chol).
+template <typename T>
+__device__ __forceinline__ void keep_col(T (&v)[NH]) {
+  asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]),
+               "+v"(v[6]), "+v"(v[7]), "+v"(v[8]));
+  asm volatile("" : "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]),
+               "+v"(v[14]), "+v"(v[15]), "+v"(v[16]), "+v"(v[17]));
+  asm volatile("" : "+v"(v[18]), "+v"(v[19]), "+v"(v[20]), "+v"(v[21]), "+v"(v[22]),
+               "+v"(v[23]), "+v"(v[24]), "+v"(v[25]));
+  asm volatile("" : "+v"(v[26]), "+v"(v[27]), "+v"(v[28]), "+v"(v[29]), "+v"(v[30]),
+               "+v"(v[31]), "+v"(v[32]), "+v"(v[33]));
+}
+
 template <typename T>
 __device__ __forceinline__ bool wave_chol(T (&a)[NH], T& dinv, int lane, T& dmin, T& dmax, T* Lm) {
   bool ok = true;
@@ -536,25 +551,28 @@ __device__ __forceinline__ bool wave_chol(T (&a)[NH], T& dinv, int lane, T& dmin
   dinv = 1;
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
-    const T d = rl(a[k], k);
+    // column k of the current matrix, pivot included, through row k of Lm
+    T* row = Lm + k * LST;
+    if (lane < NH) row[lane] = a[k];
+    __builtin_amdgcn_wave_barrier();
+    T u[NH];
+#pragma unroll
+    for (int i = k; i < NH; ++i) u[i] = row[i];
+    const T d = u[k];
     ok = ok && (d > (T)0) && isfinite(d);
     dmin = d < dmin ? d : dmin;
     dmax = d > dmax ? d : dmax;
     const T inv = rsq(d);
-    const T l = lane >= k ? a[k] * inv : (T)0;  // L[lane][k]; lane k gets L[k][k]
     if (lane == k) dinv = inv;
-    if (lane < NH) Lm[k * LST + lane] = l;
-    if (k == NH - 1) break;
+    // A[i][j] -= A[i][k] A[k][j] / d for j > k (multiplier 0 on lanes <= k)
+    const T cj = lane > k ? a[k] * (inv * inv) : (T)0;
+#pragma unroll
+    for (int i = k + 1; i < NH; ++i) a[i] = fma(-u[i], cj, a[i]);
     __builtin_amdgcn_wave_barrier();
-    T lb[NH];
-#pragma unroll
-    for (int i = k + 1; i < NH; ++i) lb[i] = Lm[k * LST + i];
-    if (lane > k) {
-#pragma unroll
-      for (int i = k + 1; i < NH; ++i) a[i] = fma(-lb[i], l, a[i]);
-    }
+    if (lane < NH) row[lane] = lane >= k ? a[k] * inv : (T)0;  // L[lane][k]
+    keep_col(a);
+    __builtin_amdgcn_wave_barrier();
   }
-  __builtin_amdgcn_wave_barrier();
   return ok;
 }
 
@@ -901,8 +919,13 @@ __global__ __launch_bounds__(256) void k_fallback3(
   double lam = 0.0;
   bool ok = false;
   for (int tries = 0; tries < 41 && !ok; ++tries) {
-    load_hcol(Sc, inv0, E, lane, lam, a);
-    ok = wave_chol(a, dinv, lane, dmin, dmax, sL[wv]);
+    // the lane index passes through an empty asm so that the gathers and lane
+    // tests of the (rarely repeated) factorisation are not hoisted out of the
+    // retry loop, where they would stay live across it
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    load_hcol(Sc, inv0, E, ln, lam, a);
+    ok = wave_chol(a, dinv, ln, dmin, dmax, sL[wv]);
     if (!ok) {
       lam = tries == 0 ? (double)p.lambda0 : lam * (double)p.lambda_mul;
       extra |= MEM_ST_SHIFTED;

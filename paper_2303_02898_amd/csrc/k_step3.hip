@@ -201,7 +201,9 @@ __device__ __forceinline__ void eig_keep(float (&v)[K3]) {
                "+v"(v[32]), "+v"(v[33]), "+v"(v[34]));
 }
 
-__global__ __launch_bounds__(256) void k_eig3(int64_t n, const float* __restrict__ S,
+// Three wavefronts per SIMD (at most 168 VGPRs; one cold 16-byte spill) hide
+// more of the per-step LDS and reduction latency than two.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_eig3(int64_t n, const float* __restrict__ S,
                                               const float* __restrict__ Sx,
                                               const float* __restrict__ g, float umax,
                                               float* __restrict__ out, int radius_only,
