@@ -65,8 +65,6 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Row-major packed upper triangle of the 34 x 34 block: (i <= j).
-__device__ __forceinline__ int hidx(int i, int j) { return 34 * i - (i * (i + 1)) / 2 + j; }
 
 // --------------------------------------------------------------------------
 // init: validate, beta_0 = n, seed the live list
@@ -408,11 +406,6 @@ __global__ void k_sum_splits(const int32_t* __restrict__ list, const int32_t* __
 // --------------------------------------------------------------------------
 // Newton direction (FP32) with the lambda*I shift of Alg. 1
 // --------------------------------------------------------------------------
-// One thread per cell; the 34 x 34 packed matrix of each cell lives in LDS,
-// element e of cell c at e*64 + (c ^ (e & 31)) (conflict-free both for the
-// cooperative transposed load and for per-thread access).  A 34-vector per
-// cell holds E[phi] and is overwritten by the forward-substitution result.
-__device__ __forceinline__ int sw(int e, int c) { return e * 64 + (c ^ (e & 31)); }
 
 struct DirOut {
   int32_t* next_list; int32_t* next_ctr;
@@ -421,10 +414,8 @@ struct DirOut {
 };
 
 // Stopping tests of Alg. 1 (residual sign read as 1/2 G^T (H + lambda I)^-1 G)
-// and book-keeping shared by the FP32 and FP64 direction kernels.  Returns
-// true when the cell stays live; then the caller stores the direction.
-// Stopping tests of Alg. 1 (residual sign read as 1/2 G^T (H + lambda I)^-1 G),
-// plus two exits for FP32 arithmetic:
+// and the book-keeping shared by the FP32 and FP64 direction kernels, plus
+// three exits the paper does not need in FP64:
 //  * a dual value below min_p log w~_p certifies that no minimiser exists (the
 //    targets lie outside the moment set of distributions on the nodes);
 //  * stall: the FP32 residual has not halved for STALL_WINDOW iterations (its

@@ -157,7 +157,8 @@ __global__ void k_flux3(int64_t n, const float* __restrict__ S, const float* __r
 // Eigenvalues of dF/dM solve C v = mu B v with B = E[phi phi^T], C = E[u_bar_x
 // phi phi^T] (35 x 35, phi_0 included); lambda = w + s_x mu.  One wavefront per
 // cell, lane j holding column j of the current matrix in registers:
-//   * Cholesky B = L L^T (pivot by readlane, column k of L shared through LDS);
+//   * Cholesky B = L L^T (column k of the current matrix, pivot included,
+//     shared through LDS; column k of L stored in the same row);
 //   * A = L^-1 C L^-T by two lane-parallel forward substitutions (each lane
 //     solves for its own column), the transposes through LDS;
 //   * Householder tridiagonalisation of A (Householder vector and p - K v
