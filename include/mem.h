@@ -227,7 +227,9 @@ MEM_API mem_err_t mem_moment_residual(mem_ctx_t ctx, int64_t n_cells, const floa
 /* Moment fluxes (eq. "The ME equation", flux line; Alg. 2 ComputeFluxes):
  * F[n][K] = int u_x phi_i(u_bar) f du in each cell's gauge, from beta
  * (beta[:,0] = n) and g.  lam[n][2] (may be NULL) = (min, max) eigenvalue of
- * dF/dM in physical units (local Lax--Friedrichs speeds, Sec. 3.4). */
+ * dF/dM in physical units (local Lax--Friedrichs speeds, Sec. 3.4); each
+ * gauge-frame eigenvalue is clamped to the node span [-max|u_x|, max|u_x|],
+ * where every eigenvalue of the quadrature pencil lies exactly. */
 MEM_API mem_err_t mem_flux(mem_ctx_t ctx, int64_t n_cells, const float* beta,
                            const float* g, float* F, float* lam, hipStream_t stream);
 
@@ -246,7 +248,9 @@ MEM_API mem_err_t mem_collide(mem_ctx_t ctx, int64_t n_cells, float* M, const fl
  * in/out.  t: device [n_problems], advanced.  dt: device [n_problems], in =
  * step for the first step (a value <= 0 requests one from a solve of the
  * current state), out = step for the next call (CFL rule from the last
- * transport's speeds).  status (may be NULL): device [n_cells], OR of the
+ * transport's speeds).  Within a step the transport and the second collision
+ * half use min(dt, CFL dx / max speed of that step), so a rise of the speeds
+ * never breaks the CFL limit.  status (may be NULL): device [n_cells], OR of the
  * cells' solve status over the steps.  A cell whose moments the nodes cannot
  * represent (solve ends NONREALIZABLE or NONFINITE with finite moments, n > 0)
  * takes beta of the Maxwellian of its gauge (beta_0 = n, -1/sqrt(2) on the

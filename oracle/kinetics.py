@@ -215,6 +215,9 @@ class ShockSolver:
         beta = self._solve(M, self.beta)
         F = _flux.fluxes(beta, self.g, self.nodes, self.Phi, self.logw)
         rho = _flux.spectral_radius(beta, self.g, self.nodes, self.Phi, self.logw)
+        # the transport (and the second collision half) never exceed the CFL
+        # limit of this step's own speeds; dt came from the previous step's
+        dt = min(dt, self._dt(rho))
         M = self._fv(M, F, rho, dt)
         M = collision(M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
         self.M, self.beta, self.g = _gauge.to_hermite_gauge(M, beta, self.g, DIM)

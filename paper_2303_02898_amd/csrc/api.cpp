@@ -484,6 +484,8 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
     if (b->iter_hist) MEM_HIP(c, launch_iter_hist(n, c->w_iters, budget + 1, b->iter_hist, st));
     MEM_HIP(c, launch_flux3(c, n, beta, g, c->w_F, c->w_rho, true, true, status, st));
     MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, st));
+    // the transport step never exceeds the CFL limit of its own speeds
+    MEM_HIP(c, launch_dt_cap(c, P, b->dx, b->cfl, dt, st));
     MEM_HIP(c, launch_fv3(c, n, M, c->w_F, c->w_rho, g, c->w_prob, b->cell_offsets, b->dx, dt,
                           c->w_Mnew, P, st));
     MEM_HIP(c, launch_collide3(c, n, c->w_Mnew, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, st));

@@ -432,6 +432,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     mu_lo = 0.5f * (lo2[0] + hi2[0]);
     mu_hi = 0.5f * (lo2[1] + hi2[1]);
     ok = isfinite(mu_lo) && isfinite(mu_hi);
+    // C v = mu B v with B, C weighted sums over the nodes: every eigenvalue is a
+    // Rayleigh quotient of u_bar_x, so |mu| <= max_p |u_bar_x,p| for any beta;
+    // a value beyond that is rounding of an ill-conditioned B
+    mu_lo = fmaxf(mu_lo, -umax);
+    mu_hi = fminf(mu_hi, umax);
   }
   if (!ok) {  // bound |mu| <= max_p |u_bar_x,p|
     mu_lo = -umax;
@@ -597,14 +602,20 @@ __global__ void k_rho_max(int64_t n, const float* __restrict__ rho, const int32_
   }
 }
 
-// mode 0: set dt where dt <= 0; mode 1: t += dt, dt = CFL dx / max radius.
-// Either way the running maximum is reset to the ghost radii afterwards.
+// mode 0: set dt where dt <= 0; mode 1: t += dt, dt = CFL dx / max radius;
+// both then reset the running maximum to the ghost radii.  mode 2: cap this
+// step's dt by the CFL limit of the radii just computed (the transport and the
+// second collision half use it), keeping the maximum for mode 1.
 __global__ void k_dt3(int P, const float* __restrict__ dx, float cfl, float* t, float* dt,
                       uint32_t* rmax, const float* __restrict__ gR, int mode) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   const float r = __uint_as_float(rmax[p]);
   const float ndt = cfl * dx[p] / r;
+  if (mode == 2) {
+    if (ndt < dt[p]) dt[p] = ndt;
+    return;
+  }
   if (mode == 0) {
     if (!(dt[p] > 0.f)) dt[p] = ndt;
   } else {
@@ -778,6 +789,12 @@ hipError_t launch_rho_max(mem_ctx_t c, int64_t n, const float* rho, const int32_
 hipError_t launch_dt_update(mem_ctx_t c, int P, const float* dx, float cfl, float* t, float* dt,
                             bool advance_t, hipStream_t s) {
   k_dt3<<<nb(P, 128), 128, 0, s>>>(P, dx, cfl, t, dt, c->w_rmax, c->w_gR, advance_t ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt_cap(mem_ctx_t c, int P, const float* dx, float cfl, float* dt,
+                         hipStream_t s) {
+  k_dt3<<<nb(P, 128), 128, 0, s>>>(P, dx, cfl, nullptr, dt, c->w_rmax, c->w_gR, 2);
   return hipGetLastError();
 }
 

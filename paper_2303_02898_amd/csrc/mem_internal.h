@@ -197,6 +197,8 @@ hipError_t launch_prob_map(mem_ctx_t c, const int64_t* offsets, int P, int32_t* 
 hipError_t launch_ghost_pack(mem_ctx_t c, const mem_batch_t* b, hipStream_t s);
 hipError_t launch_rho_max(mem_ctx_t c, int64_t n, const float* rho, const int32_t* prob,
                           int P, hipStream_t s);
+hipError_t launch_dt_cap(mem_ctx_t c, int P, const float* dx, float cfl, float* dt,
+                         hipStream_t s);
 hipError_t launch_dt_update(mem_ctx_t c, int P, const float* dx, float cfl, float* t,
                             float* dt, bool advance_t, hipStream_t s);
 hipError_t launch_status_or(int64_t n, const uint32_t* src, uint32_t* dst, hipStream_t s);

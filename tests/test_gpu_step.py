@@ -124,7 +124,7 @@ def test_collision_matches_oracle(ctx3):
     assert np.max(np.abs(Md.cpu().numpy() - ref) / scale) < 2e-5
 
 
-def _gpu_shock(problem, ctx, n_steps, newton_per_step=8, use_graph=False):
+def _gpu_shock(problem, ctx, n_steps, newton_per_step=8, use_graph=False, iter_hist=None):
     M, g = f32(problem["M"]), f32(problem["g"])
     Md, gd = dev(M), dev(g)
     ctx.gauge(Md, None, gd)
@@ -132,7 +132,7 @@ def _gpu_shock(problem, ctx, n_steps, newton_per_step=8, use_graph=False):
     batch = mem.ShockBatch([0, M.shape[0]], [problem["dx"]], problem["M_left"][None],
                            problem["M_right"][None], problem["g_left"][None],
                            problem["g_right"][None], device=DEV, newton_per_step=newton_per_step,
-                           use_graph=use_graph)
+                           use_graph=use_graph, iter_hist=iter_hist)
     t = torch.zeros(1, device=DEV)
     dt = torch.zeros(1, device=DEV)
     status = torch.zeros(M.shape[0], dtype=torch.int32, device=DEV)
@@ -211,17 +211,21 @@ def test_graph_step_matches_eager(ctx3):
     problem = mem_inputs.shock_problem(3.0, 1000, -20.0, 20.0, 5.44)
     runs = {}
     for graph in (False, True):
-        batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0, use_graph=graph)
+        hist = torch.zeros(9, dtype=torch.int64, device=DEV)
+        batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0, use_graph=graph,
+                                                      iter_hist=hist)
         snaps = []
         for call in range(4):
             ctx3.step(batch, Md, bd, gd, t, dt, 1 + call, status=status)
             junk = torch.randn(4096, device=DEV).sum()   # unrelated work between replays
             torch.cuda.synchronize()
-            snaps.append([x.clone() for x in (Md, bd, gd, t, dt, status)] + [junk])
+            snaps.append([x.clone() for x in (Md, bd, gd, t, dt, status, hist)] + [junk])
         runs[graph] = snaps
     for call, (ea, gr) in enumerate(zip(runs[False], runs[True])):
-        for k, (x, y) in enumerate(zip(ea[:6], gr[:6])):
+        for k, (x, y) in enumerate(zip(ea[:7], gr[:7])):
             assert torch.equal(x, y), (call, k)
+    # 1 + 2 + 3 + 4 steps of 1000 cells, each counted once per step
+    assert int(runs[True][-1][6].sum().item()) == 10 * 1000
     print(f"[graph] 4 calls (1..4 steps) identical to plain launches, t = {runs[True][-1][3].item():.4f}")
 
 
