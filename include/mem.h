@@ -131,6 +131,9 @@ typedef struct {
  * Cells of problem p are cell_offsets[p] .. cell_offsets[p+1]-1 of the flat
  * M/beta/g arrays, ordered left to right.  Boundary (ghost) states are
  * Maxwellian moments M_left/M_right in their own gauges g_left/g_right. */
+#define MEM_FLUX_LLF  0  /* local Lax--Friedrichs (first order, eq. "The lax F")             */
+#define MEM_FLUX_LW   1  /* two-step Lax--Wendroff (eq. "The lax W")                         */
+#define MEM_FLUX_FLIC 2  /* LLF + van Leer-limited Lax--Wendroff correction (eq. "The FLIC") */
 typedef struct {
   int64_t        n_cells;        /* host copy of cell_offsets[n_problems]                   */
   int32_t        n_problems;
@@ -155,6 +158,7 @@ typedef struct {
                                     MaxEnt solve, bin k is incremented by the number of
                                     cells whose solve took k Newton iterations (Alg. 1
                                     directions).  Accumulates over calls; never cleared. */
+  int32_t        flux_scheme;    /* MEM_FLUX_LLF, MEM_FLUX_LW or MEM_FLUX_FLIC (Sec. 3.4)  */
 } mem_batch_t;
 
 /* ---- context -------------------------------------------------------------- */
@@ -256,7 +260,17 @@ MEM_API mem_err_t mem_collide(mem_ctx_t ctx, int64_t n_cells, float* M, const fl
  * takes beta of the Maxwellian of its gauge (beta_0 = n, -1/sqrt(2) on the
  * pure second-degree statistics) for that step's fluxes and speeds and as the
  * next warm start, and gets MEM_ST_MAXWELL_FLUX: the update stays conservative
- * and finite while the closure there drops to the Maxwellian.  No host
+ * and finite while the closure there drops to the Maxwellian.
+ * flux_scheme LW / FLIC (Sec. 3.4): every interface (n_cells + n_problems of
+ * them, boundaries included) is evaluated once, in the gauge of the element
+ * to its right, from its neighbours moved into that gauge: the half-step
+ * moments (M_l + M_r)/2 + dt/(2 dx) (F_l - F_r) are solved (warm start from
+ * the right element's beta, same iteration budget) and their flux is the
+ * Lax--Wendroff flux; FLIC adds it to the LLF flux with the van Leer limiter
+ * of r = (M_l - M_ll)/(M_r - M_l) per moment (ghosts extend beyond the
+ * boundary).  An interface whose half-step state the nodes cannot represent
+ * keeps the LLF flux.  The cell to an interface's left takes the same flux
+ * moved into its own gauge, so the update stays conservative.  No host
  * synchronisation. */
 MEM_API mem_err_t mem_step(mem_ctx_t ctx, const mem_batch_t* batch, float* M, float* beta,
                            float* g, float* t, float* dt, int32_t n_steps,

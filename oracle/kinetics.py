@@ -22,8 +22,24 @@ along x.  Paper passages followed:
 * local Lax--Friedrichs flux and conservative update in each cell's own gauge,
   neighbours moved into it by T (eqs. "The lax F", "The ME equation fvm 2",
   "The lax F convert");
+* second-order interface fluxes (Sec. 3.4): two-step Lax--Wendroff (eq. "The
+  lax W": half-step interface moments, their MaxEnt solve, the flux of that
+  solution) and FLIC (eq. "The FLIC": LLF plus a van Leer-limited share of
+  the Lax--Wendroff correction, the ratio r taken per moment);
 * Alg. 2 Step: Collision(dt/2), Transport(dt), Collision(dt/2), then the
   Hermite-gauge update.
+
+Readings for the second-order fluxes with per-cell gauges (the paper states the
+schemes for one gauge): each interface is evaluated once, in the gauge of the
+cell to its right (the right ghost for the last one), from its neighbours
+moved into that gauge; the cell to its left receives the same flux moved into
+its own gauge by T, so the update stays conservative.  The half-step state is
+solved from the right cell's beta.  Where it cannot be represented (the solve
+certifies non-realizability or does not stay finite) the interface takes the
+LLF flux.  The limiter is the van Leer function (r + |r|)/(1 + |r|); the
+printed denominator 1 + r agrees with it for r >= 0 and only differs where
+the numerator is zero.  The ghost states continue beyond the boundary, so the
+first interface has r = 0.
 
 Reading for the step size (paper gives only a CFL relation): the step taken at
 step k is CFL*dx/max rho from the characteristic speeds of the transport of
@@ -137,12 +153,33 @@ def shock_initial(mach, n_cells, x_lo, x_hi, thickness, gamma=5.0 / 3.0):
     return M, g, dx
 
 
-class ShockSolver:
-    """Oracle time stepper for one 1D shock problem (Alg. 2 with LLF)."""
+SCHEMES = ("llf", "lw", "flic")
 
-    def __init__(self, mach, n_cells, x_lo, x_hi, thickness, nodes_1d=12,
-                 cfl=0.5, prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi),
-                 gamma=5.0 / 3.0, newton=None):
+
+def van_leer(a, b):
+    """Van Leer limiter phi(r) = (r + |r|) / (1 + |r|) at r = a / b, elementwise.
+
+    For a b > 0 this is 2 a / (a + b); it is zero where a and b differ in sign
+    or either is zero."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    out = np.zeros(np.broadcast(a, b).shape)
+    pos = a * b > 0
+    out[pos] = 2.0 * a[pos] / (a[pos] + b[pos])
+    return out
+
+
+class FVSolver:
+    """Oracle time stepper (Alg. 2) for one 1D problem: cells in their Hermite
+    gauges between two fixed ghost Maxwellians.  scheme: "llf", "lw" or "flic";
+    collide=False leaves out the relaxation (pure transport)."""
+
+    def __init__(self, M0, g0, dx, left, right, nodes_1d=12, cfl=0.5,
+                 prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), newton=None,
+                 scheme="llf", collide=True):
+        if scheme not in SCHEMES:
+            raise ValueError(f"scheme must be one of {SCHEMES}")
+        self.scheme, self.collide = scheme, collide
         self.nodes, w = _quad.tensor_rule(nodes_1d, DIM)
         self.logw = _quad.lebesgue_log_weights(self.nodes, w)
         self.Phi = _basis.evaluate(self.nodes, DIM)
@@ -150,20 +187,21 @@ class ShockSolver:
         self.newton = dict(tol_grad=1e-11, max_iter=100)
         if newton:
             self.newton.update(newton)
-        (n1, v1, T1), (n2, v2, T2) = rankine_hugoniot(mach, gamma)
-        self.rh = ((n1, v1, T1), (n2, v2, T2))
-        M0, g0, self.dx = shock_initial(mach, n_cells, x_lo, x_hi, thickness, gamma)
+        self.dx = dx
         self.M, _, self.g = _gauge.to_hermite_gauge(M0, None, g0, DIM)
         self.beta = _maxent.maxwellian_beta(self.M, DIM)
-        # ghost cells: upstream / downstream Maxwellians in their own gauge
+        # ghost cells: Maxwellians (n, v, T) in their own gauge
         gh = []
-        for (n, v, T) in self.rh:
+        for (n, v, T) in (left, right):
             Mg, gg = maxwellian_state(n, v, T)
             bg = self._solve(Mg, _maxent.maxwellian_beta(Mg, DIM))
             Fg = _flux.fluxes(bg, gg, self.nodes, self.Phi, self.logw)
             rg = _flux.spectral_radius(bg, gg, self.nodes, self.Phi, self.logw)
-            gh.append((Mg[0], Fg[0], rg[0], gg[0]))
+            gh.append((Mg[0], Fg[0], rg[0], gg[0], bg[0]))
         self.ghost_left, self.ghost_right = gh
+        self._start()
+
+    def _start(self):
         self.t = 0.0
         self.beta = self._solve(self.M, self.beta)
         rho = _flux.spectral_radius(self.beta, self.g, self.nodes, self.Phi, self.logw)
@@ -192,8 +230,8 @@ class ShockSolver:
     def _fv(self, M, F, rho, dt):
         N = M.shape[0]
         g = self.g
-        MLg, FLg, rL, gL = self.ghost_left
-        MRg, FRg, rR, gR = self.ghost_right
+        MLg, FLg, rL, gL, _ = self.ghost_left
+        MRg, FRg, rR, gR, _ = self.ghost_right
         # neighbour data (left and right), each in its own gauge
         Ml = np.vstack([MLg[None], M[:-1]]); Fl = np.vstack([FLg[None], F[:-1]])
         gl = np.vstack([gL[None], g[:-1]]); rl = np.concatenate([[rL], rho[:-1]])
@@ -209,18 +247,92 @@ class ShockSolver:
         f_plus = 0.5 * (F + Fr) + 0.5 * lp * (M - Mr)
         return M + dt / self.dx * (f_minus - f_plus)
 
+    def interface_fluxes(self, M, F, beta, rho, dt):
+        """Numerical flux at each of the N + 1 interfaces (Sec. 3.4, eqs. "The
+        lax F", "The lax W", "The FLIC"), interface j between element j and
+        j + 1 of [left ghost, cells, right ghost], in the gauge of element j + 1.
+        Returns (fluxes, lw_failed mask)."""
+        MLg, FLg, rL, gL, bL = self.ghost_left
+        MRg, FRg, rR, gR, bR = self.ghost_right
+        Me = np.vstack([MLg[None], M, MRg[None]])
+        Fe = np.vstack([FLg[None], F, FRg[None]])
+        ge = np.vstack([gL[None], self.g, gR[None]])
+        be = np.vstack([bL[None], beta, bR[None]])
+        re = np.concatenate([[rL], rho, [rR]])
+        N = M.shape[0]
+        R = np.arange(1, N + 2)
+        L = R - 1
+        LL = np.maximum(L - 1, 0)   # the left ghost continues beyond the boundary
+        gI = ge[R]
+        TL = _gauge.change_matrix(gI, ge[L], DIM)
+        ML = np.einsum("cij,cj->ci", TL, Me[L])
+        FL = np.einsum("cij,cj->ci", TL, Fe[L])
+        MR, FR = Me[R], Fe[R]
+        lam = np.maximum(re[L], re[R])[:, None]
+        f_lf = 0.5 * (FL + FR) + 0.5 * lam * (ML - MR)
+        failed = np.zeros(N + 1, dtype=bool)
+        if self.scheme == "llf":
+            return f_lf, failed
+        # two-step Lax--Wendroff: half-step interface state, its MaxEnt solve
+        Mh = 0.5 * (ML + MR) + 0.5 * (dt / self.dx) * (FL - FR)
+        out = _maxent.newton_solve(Mh, be[R], self.Phi, self.logw, **self.newton)
+        bh = out["beta"]
+        failed = (out["nonrealizable"] | ~np.all(np.isfinite(bh), axis=1)
+                  | ~np.all(np.isfinite(Mh), axis=1) | ~(Mh[:, 0] > 0))
+        bh = np.where(failed[:, None], be[R], bh)
+        f_lw = _flux.fluxes(bh, gI, self.nodes, self.Phi, self.logw)
+        if self.scheme == "lw":
+            phi = np.ones_like(f_lw)
+        else:
+            TLL = _gauge.change_matrix(gI, ge[LL], DIM)
+            MLL = np.einsum("cij,cj->ci", TLL, Me[LL])
+            phi = van_leer(ML - MLL, MR - ML)
+        f = f_lf + phi * (f_lw - f_lf)
+        f[failed] = f_lf[failed]
+        return f, failed
+
+    def _fv2(self, M, F, beta, rho, dt):
+        """Conservative update from interface fluxes: cell n takes interface n
+        (already in its gauge) and interface n + 1 moved from the gauge of its
+        right neighbour (eq. "The ME equation fvm 2")."""
+        f, failed = self.interface_fluxes(M, F, beta, rho, dt)
+        self.lw_failed = failed
+        gR = self.ghost_right[3]
+        g_right = np.vstack([self.g[1:], gR[None]])
+        T = _gauge.change_matrix(self.g, g_right, DIM)
+        f_plus = np.einsum("cij,cj->ci", T, f[1:])
+        return M + dt / self.dx * (f[:-1] - f_plus)
+
     def step(self):
         dt = self.dt
-        M = collision(self.M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
+        M = self.M
+        if self.collide:
+            M = collision(M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
         beta = self._solve(M, self.beta)
         F = _flux.fluxes(beta, self.g, self.nodes, self.Phi, self.logw)
         rho = _flux.spectral_radius(beta, self.g, self.nodes, self.Phi, self.logw)
         # the transport (and the second collision half) never exceed the CFL
         # limit of this step's own speeds; dt came from the previous step's
         dt = min(dt, self._dt(rho))
-        M = self._fv(M, F, rho, dt)
-        M = collision(M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
+        if self.scheme == "llf":
+            M = self._fv(M, F, rho, dt)
+        else:
+            M = self._fv2(M, F, beta, rho, dt)
+        if self.collide:
+            M = collision(M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
         self.M, self.beta, self.g = _gauge.to_hermite_gauge(M, beta, self.g, DIM)
         self.t += dt
         self.dt = self._dt(rho)
         return dt
+
+
+class ShockSolver(FVSolver):
+    """Oracle time stepper for one normal-shock problem (App. D set-up)."""
+
+    def __init__(self, mach, n_cells, x_lo, x_hi, thickness, nodes_1d=12,
+                 cfl=0.5, prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi),
+                 gamma=5.0 / 3.0, newton=None, scheme="llf"):
+        self.rh = rankine_hugoniot(mach, gamma)
+        M0, g0, dx = shock_initial(mach, n_cells, x_lo, x_hi, thickness, gamma)
+        super().__init__(M0, g0, dx, self.rh[0], self.rh[1], nodes_1d=nodes_1d, cfl=cfl,
+                         prandtl=prandtl, mu_ref=mu_ref, newton=newton, scheme=scheme)

@@ -24,6 +24,7 @@ ST_NONFINITE = 0x20
 ST_NONREALIZABLE = 0x40
 ST_LAMBDA_FAIL = 0x80
 ST_MAXWELL_FLUX = 0x100
+FLUX_SCHEMES = {"llf": 0, "lw": 1, "flic": 2}
 
 PREC = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}
 
@@ -48,7 +49,7 @@ class Batch(ctypes.Structure):
                 ("cell_offsets", _vp), ("dx", _vp), ("M_left", _vp), ("M_right", _vp),
                 ("g_left", _vp), ("g_right", _vp), ("cfl", _c_f32), ("prandtl", _c_f32),
                 ("mu_ref", _c_f32), ("newton_per_step", _c_i32), ("use_graph", _c_i32),
-                ("iter_hist", _vp)]
+                ("iter_hist", _vp), ("flux_scheme", _c_i32)]
 
 
 _lib = None
@@ -336,8 +337,10 @@ class ShockBatch:
 
     def __init__(self, offsets, dx, M_left, M_right, g_left, g_right, device="cuda",
                  cfl=0.5, prandtl=2.0 / 3.0, mu_ref=0.7978845608028654, collision=1,
-                 newton_per_step=8, use_graph=False, iter_hist=None):
+                 newton_per_step=8, use_graph=False, iter_hist=None, flux_scheme="llf"):
         import torch
+        if flux_scheme not in FLUX_SCHEMES:
+            raise ValueError(f"flux_scheme must be one of {sorted(FLUX_SCHEMES)}")
         f32 = dict(dtype=torch.float32, device=device)
         self.offsets = torch.as_tensor(offsets, dtype=torch.int64, device=device).contiguous()
         self.n_problems = int(self.offsets.numel() - 1)
@@ -351,7 +354,7 @@ class ShockBatch:
                             self.dx.data_ptr(), self.M_left.data_ptr(), self.M_right.data_ptr(),
                             self.g_left.data_ptr(), self.g_right.data_ptr(), float(cfl),
                             float(prandtl), float(mu_ref), int(newton_per_step),
-                            int(bool(use_graph)), None)
+                            int(bool(use_graph)), None, FLUX_SCHEMES[flux_scheme])
         # iteration histogram (device int64 [newton_per_step + 1]), accumulated by mem_step
         self.iter_hist = None
         if iter_hist is not None:

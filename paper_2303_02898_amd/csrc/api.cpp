@@ -46,6 +46,7 @@ void free_workspace(mem_ctx_t c) {
   for (auto& l : c->w_list) dfree(l);
   dfree(c->w_Gacc); dfree(c->w_racc); dfree(c->w_rbest); dfree(c->w_itbest);
   dfree(c->w_Mnew); dfree(c->w_F); dfree(c->w_rho); dfree(c->w_prob); dfree(c->w_code); dfree(c->w_Sp);
+  dfree(c->w_hM); dfree(c->w_hB); dfree(c->w_hG); dfree(c->w_hF); dfree(c->w_hLF); dfree(c->w_hPhi);
   c->sp_rows = 0;
   c->cap_cells = 0;
 }
@@ -278,7 +279,9 @@ mem_err_t mem_reserve(mem_ctx_t c, int64_t max_cells, int32_t max_problems) {
               dalloc(c->w_racc, n) && dalloc(c->w_rbest, n) && dalloc(c->w_itbest, n) &&
               dalloc(c->w_Mnew, n * K3) && dalloc(c->w_F, n * K3) &&
               dalloc(c->w_rho, n) && dalloc(c->w_prob, n) && dalloc(c->w_code, n) &&
-              dalloc(c->w_Sp, (size_t)SP_ROWS * NCOL);
+              dalloc(c->w_Sp, (size_t)SP_ROWS * NCOL) && dalloc(c->w_hM, n * K3) &&
+              dalloc(c->w_hB, n * K3) && dalloc(c->w_hG, n * 3) && dalloc(c->w_hF, n * K3) &&
+              dalloc(c->w_hLF, n * K3) && dalloc(c->w_hPhi, n * K3);
     if (!ok) { free_workspace(c); return fail(c, MEM_ERR_NOMEM, "workspace allocation"); }
     c->cap_cells = max_cells;
     c->sp_rows = SP_ROWS;
@@ -423,7 +426,8 @@ static mem_err_t check_batch(mem_ctx_t c, const mem_batch_t* b) {
       !b->M_left || !b->M_right || !b->g_left || !b->g_right || !(b->cfl > 0.f) ||
       !(b->prandtl > 0.5f) || !(b->mu_ref > 0.f) || b->newton_per_step < 1 ||
       b->newton_per_step > 1000 || (b->collision != 0 && b->collision != 1) ||
-      (b->use_graph != 0 && b->use_graph != 1))
+      (b->use_graph != 0 && b->use_graph != 1) || b->flux_scheme < MEM_FLUX_LLF ||
+      b->flux_scheme > MEM_FLUX_FLIC)
     return fail(c, MEM_ERR_INVALID_ARG, "mem_batch_t");
   std::vector<int64_t> off((size_t)b->n_problems + 1);
   MEM_HIP(c, hipMemcpy(off.data(), b->cell_offsets, off.size() * sizeof(int64_t),
@@ -446,9 +450,9 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
     return fail(c, MEM_ERR_INVALID_ARG, "mem_step: arguments");
   const int64_t n = b->n_cells;
   const int P = b->n_problems;
-  if (std::max<int64_t>(n, 2 * (int64_t)P) > c->cap_cells || P > c->cap_problems) {
-    e = mem_reserve(c, std::max<int64_t>(std::max<int64_t>(n, 2 * (int64_t)P), c->cap_cells),
-                    std::max(P, c->cap_problems));
+  // rows for the cells, the 2P ghosts and the n + P interfaces (n >= P)
+  if (n + P > c->cap_cells || P > c->cap_problems) {
+    e = mem_reserve(c, std::max<int64_t>(n + P, c->cap_cells), std::max(P, c->cap_problems));
     if (e != MEM_OK) return e;
   }
   SolveParams p = params_from(opts);
@@ -486,8 +490,22 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
     MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, st));
     // the transport step never exceeds the CFL limit of its own speeds
     MEM_HIP(c, launch_dt_cap(c, P, b->dx, b->cfl, dt, st));
-    MEM_HIP(c, launch_fv3(c, n, M, c->w_F, c->w_rho, g, c->w_prob, b->cell_offsets, b->dx, dt,
-                          c->w_Mnew, P, st));
+    if (b->flux_scheme == MEM_FLUX_LLF) {
+      MEM_HIP(c, launch_fv3(c, n, M, c->w_F, c->w_rho, g, c->w_prob, b->cell_offsets, b->dx, dt,
+                            c->w_Mnew, P, st));
+    } else {
+      // second order: half-step interface states, their MaxEnt solve (from the
+      // right element's beta), the flux of that solution, then the update
+      const bool flic = b->flux_scheme == MEM_FLUX_FLIC;
+      const int64_t ni = n + P;
+      MEM_HIP(c, launch_iface3(c, n, P, M, c->w_F, beta, c->w_rho, g, c->w_prob, b->cell_offsets,
+                               b->dx, dt, flic, st));
+      er = newton3(c, ni, c->w_hM, c->w_hB, p, budget, 0, refine, nullptr, nullptr, nullptr, st);
+      if (er != MEM_OK) return er;
+      MEM_HIP(c, launch_flux3(c, ni, c->w_hB, c->w_hG, c->w_hF, nullptr, false, false, nullptr, st));
+      MEM_HIP(c, launch_fv3i(c, n, M, g, c->w_prob, b->cell_offsets, b->dx, dt, flic, c->w_Mnew,
+                             st));
+    }
     MEM_HIP(c, launch_collide3(c, n, c->w_Mnew, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, st));
     MEM_HIP(c, launch_gauge3(c, n, c->w_Mnew, beta, g, st));
     MEM_HIP(c, launch_copy(n * K3, c->w_Mnew, M, st));

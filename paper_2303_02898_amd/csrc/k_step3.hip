@@ -549,6 +549,134 @@ __global__ __launch_bounds__(64) void k_fv3(int64_t n, const float* __restrict__
   for (int i = 0; i < K3; ++i) Mnew[c * K3 + i] = acc[i];
 }
 
+// ---- second-order interface fluxes (two-step Lax--Wendroff, FLIC) -----------------------
+// Interfaces of problem p are numbered off[p] + p ... off[p + 1] + p: interface
+// c + p lies left of cell c, off[p + 1] + p is the right boundary.  Each one is
+// evaluated in the gauge of the element to its right (cell or right ghost).
+// Per interface: the LLF flux, the Lax--Wendroff half-step moments (to be solved),
+// the right element's beta as the solve's start, that gauge and, for FLIC, the
+// van Leer limiter per moment.  Ghost rows: 2p left, 2p + 1 right.
+__global__ __launch_bounds__(64) void k_iface3(int64_t n, int P, const float* __restrict__ M,
+                      const float* __restrict__ F, const float* __restrict__ beta,
+                      const float* __restrict__ rho, const float* __restrict__ g,
+                      const int32_t* __restrict__ prob, const int64_t* __restrict__ off,
+                      const float* __restrict__ dx, const float* __restrict__ dt,
+                      const float* __restrict__ gM, const float* __restrict__ gF,
+                      const float* __restrict__ gB, const float* __restrict__ gR,
+                      const float* __restrict__ gG, int flic, float* __restrict__ hM,
+                      float* __restrict__ hB, float* __restrict__ hG, float* __restrict__ hLF,
+                      float* __restrict__ hPhi) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n + P) return;
+  int p;
+  int64_t r, l, ll, iface;  // element indices; -1 = left ghost, -2 = right ghost
+  if (t < n) {
+    r = t;
+    p = prob[r];
+    l = r - 1 >= off[p] ? r - 1 : -1;
+    ll = r - 2 >= off[p] ? r - 2 : -1;
+    iface = r + p;
+  } else {
+    p = (int)(t - n);
+    r = -2;
+    l = off[p + 1] - 1;
+    ll = l - 1 >= off[p] ? l - 1 : -1;
+    iface = off[p + 1] + p;
+  }
+  const int64_t gl_row = 2 * (int64_t)p, gr_row = 2 * (int64_t)p + 1;
+  auto row = [&](const float* cells, const float* ghosts, int64_t e, int w) -> const float* {
+    return e >= 0 ? cells + e * w : ghosts + (e == -1 ? gl_row : gr_row) * w;
+  };
+  const float* gI = row(g, gG, r, 3);
+  const float* gl = row(g, gG, l, 3);
+  const float* MR = row(M, gM, r, K3);
+  const float* FR = row(F, gF, r, K3);
+  const float rr = r >= 0 ? rho[r] : gR[gr_row];
+  const float rl = l >= 0 ? rho[l] : gR[gl_row];
+  const float lam = fmaxf(rl, rr);
+  const float k = dt[p] / dx[p];
+  float ml[K3];
+  {
+    const float* src = row(M, gM, l, K3);
+#pragma unroll
+    for (int i = 0; i < K3; ++i) ml[i] = src[i];
+  }
+  change_gauge(ml, gI, gl);
+  if (flic) {
+    float u[K3];
+    const float* src = row(M, gM, ll, K3);
+#pragma unroll
+    for (int i = 0; i < K3; ++i) u[i] = src[i];
+    change_gauge(u, gI, row(g, gG, ll, 3));
+    // van Leer phi(r) = (r + |r|) / (1 + |r|), r = (M_l - M_ll) / (M_r - M_l)
+#pragma unroll
+    for (int i = 0; i < K3; ++i) {
+      const float a = ml[i] - u[i], b = MR[i] - ml[i];
+      hPhi[iface * K3 + i] = a * b > 0.f ? 2.f * a / (a + b) : 0.f;
+    }
+  }
+  float fl[K3];
+  {
+    const float* src = row(F, gF, l, K3);
+#pragma unroll
+    for (int i = 0; i < K3; ++i) fl[i] = src[i];
+  }
+  change_gauge(fl, gI, gl);
+#pragma unroll
+  for (int i = 0; i < K3; ++i) {
+    const float mr = MR[i], fr = FR[i];
+    hLF[iface * K3 + i] = 0.5f * (fl[i] + fr) + 0.5f * lam * (ml[i] - mr);
+    hM[iface * K3 + i] = 0.5f * (ml[i] + mr) + 0.5f * k * (fl[i] - fr);
+  }
+  const float* bR = row(beta, gB, r, K3);
+#pragma unroll
+  for (int i = 0; i < K3; ++i) hB[iface * K3 + i] = bR[i];
+  for (int i = 0; i < 3; ++i) hG[iface * 3 + i] = gI[i];
+}
+
+// Conservative update from interface fluxes: cell c takes interface c + p (in its
+// own gauge) and interface c + p + 1 moved from its right neighbour's gauge.  The
+// interface flux is LLF + phi (LW - LLF), phi = 1 for Lax--Wendroff; an interface
+// whose half-step solve failed (not representable, not finite) keeps LLF.
+__device__ __forceinline__ void iface_flux(int64_t i, const float* __restrict__ hLF,
+                                           const float* __restrict__ hF,
+                                           const float* __restrict__ hPhi,
+                                           const uint32_t* __restrict__ st, float (&f)[K3]) {
+  float lw[K3];
+  bool ok = !(st[i] & (MEM_ST_NONREALIZABLE | MEM_ST_NONFINITE));
+#pragma unroll
+  for (int j = 0; j < K3; ++j) {
+    lw[j] = hF[i * K3 + j];
+    f[j] = hLF[i * K3 + j];
+    ok = ok && isfinite(lw[j]);
+  }
+  if (!ok) return;
+#pragma unroll
+  for (int j = 0; j < K3; ++j) f[j] += (hPhi ? hPhi[i * K3 + j] : 1.f) * (lw[j] - f[j]);
+}
+
+__global__ __launch_bounds__(64) void k_fv3i(int64_t n, const float* __restrict__ M,
+                      const float* __restrict__ g, const int32_t* __restrict__ prob,
+                      const int64_t* __restrict__ off, const float* __restrict__ dx,
+                      const float* __restrict__ dt, const float* __restrict__ gG,
+                      const float* __restrict__ hLF, const float* __restrict__ hF,
+                      const float* __restrict__ hPhi, const uint32_t* __restrict__ st,
+                      float* __restrict__ Mnew) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int p = prob[c];
+  const bool last = c == off[p + 1] - 1;
+  const float* gr = last ? gG + (2 * (int64_t)p + 1) * 3 : g + (c + 1) * 3;
+  const float k = dt[p] / dx[p];
+  float fp[K3];
+  iface_flux(c + p + 1, hLF, hF, hPhi, st, fp);
+  change_gauge(fp, g + c * 3, gr);
+  float fm[K3];
+  iface_flux(c + p, hLF, hF, hPhi, st, fm);
+#pragma unroll
+  for (int i = 0; i < K3; ++i) Mnew[c * K3 + i] = M[c * K3 + i] + k * (fm[i] - fp[i]);
+}
+
 // ---- batch book-keeping ---------------------------------------------------------------
 __global__ void k_prob_map(const int64_t* __restrict__ off, int P, int32_t* __restrict__ prob) {
   const int p = blockIdx.x;
@@ -760,6 +888,26 @@ hipError_t launch_fv3(mem_ctx_t c, int64_t n, const float* M, const float* F, co
   if (n <= 0) return hipSuccess;
   k_fv3<<<nb(n, 64), 64, 0, s>>>(n, M, F, rho, g, prob, offsets, dx, dt, c->w_gM, c->w_gF, c->w_gR,
                                  c->w_gG, Mnew);
+  return hipGetLastError();
+}
+
+hipError_t launch_iface3(mem_ctx_t c, int64_t n, int P, const float* M, const float* F,
+                        const float* beta, const float* rho, const float* g, const int32_t* prob,
+                        const int64_t* offsets, const float* dx, const float* dt, bool flic,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_iface3<<<nb(n + P, 64), 64, 0, s>>>(n, P, M, F, beta, rho, g, prob, offsets, dx, dt, c->w_gM,
+                                        c->w_gF, c->w_gB, c->w_gR, c->w_gG, flic ? 1 : 0, c->w_hM,
+                                        c->w_hB, c->w_hG, c->w_hLF, c->w_hPhi);
+  return hipGetLastError();
+}
+
+hipError_t launch_fv3i(mem_ctx_t c, int64_t n, const float* M, const float* g, const int32_t* prob,
+                       const int64_t* offsets, const float* dx, const float* dt, bool flic,
+                       float* Mnew, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fv3i<<<nb(n, 64), 64, 0, s>>>(n, M, g, prob, offsets, dx, dt, c->w_gG, c->w_hLF, c->w_hF,
+                                  flic ? c->w_hPhi : nullptr, c->w_status, Mnew);
   return hipGetLastError();
 }
 

@@ -104,6 +104,13 @@ struct mem_ctx_s {
   float* w_Mnew = nullptr;    // [cap][K]
   float* w_F = nullptr;       // [cap][K]
   float* w_rho = nullptr;     // [cap]
+  // second-order interface fluxes: one row per interface (cells + problems <= cap)
+  float* w_hM = nullptr;      // Lax--Wendroff half-step moments [cap][K]
+  float* w_hB = nullptr;      // their beta [cap][K]
+  float* w_hG = nullptr;      // interface gauge (right element's) [cap][3]
+  float* w_hF = nullptr;      // Lax--Wendroff flux [cap][K]
+  float* w_hLF = nullptr;     // LLF flux [cap][K]
+  float* w_hPhi = nullptr;    // FLIC limiter per moment [cap][K]
   int32_t* w_prob = nullptr;  // [cap] problem of each cell
   float* w_gM = nullptr;      // ghost moments   [2*P][K]
   float* w_gB = nullptr;      // ghost beta      [2*P][K]
@@ -197,6 +204,13 @@ hipError_t launch_prob_map(mem_ctx_t c, const int64_t* offsets, int P, int32_t* 
 hipError_t launch_ghost_pack(mem_ctx_t c, const mem_batch_t* b, hipStream_t s);
 hipError_t launch_rho_max(mem_ctx_t c, int64_t n, const float* rho, const int32_t* prob,
                           int P, hipStream_t s);
+hipError_t launch_iface3(mem_ctx_t c, int64_t n, int P, const float* M, const float* F,
+                        const float* beta, const float* rho, const float* g, const int32_t* prob,
+                        const int64_t* offsets, const float* dx, const float* dt, bool flic,
+                        hipStream_t s);
+hipError_t launch_fv3i(mem_ctx_t c, int64_t n, const float* M, const float* g, const int32_t* prob,
+                       const int64_t* offsets, const float* dx, const float* dt, bool flic,
+                       float* Mnew, hipStream_t s);
 hipError_t launch_dt_cap(mem_ctx_t c, int P, const float* dx, float cfl, float* dt,
                          hipStream_t s);
 hipError_t launch_dt_update(mem_ctx_t c, int P, const float* dx, float cfl, float* t,

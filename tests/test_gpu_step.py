@@ -124,7 +124,8 @@ def test_collision_matches_oracle(ctx3):
     assert np.max(np.abs(Md.cpu().numpy() - ref) / scale) < 2e-5
 
 
-def _gpu_shock(problem, ctx, n_steps, newton_per_step=8, use_graph=False, iter_hist=None):
+def _gpu_shock(problem, ctx, n_steps, newton_per_step=8, use_graph=False, iter_hist=None,
+               flux_scheme="llf"):
     M, g = f32(problem["M"]), f32(problem["g"])
     Md, gd = dev(M), dev(g)
     ctx.gauge(Md, None, gd)
@@ -132,7 +133,7 @@ def _gpu_shock(problem, ctx, n_steps, newton_per_step=8, use_graph=False, iter_h
     batch = mem.ShockBatch([0, M.shape[0]], [problem["dx"]], problem["M_left"][None],
                            problem["M_right"][None], problem["g_left"][None],
                            problem["g_right"][None], device=DEV, newton_per_step=newton_per_step,
-                           use_graph=use_graph, iter_hist=iter_hist)
+                           use_graph=use_graph, iter_hist=iter_hist, flux_scheme=flux_scheme)
     t = torch.zeros(1, device=DEV)
     dt = torch.zeros(1, device=DEV)
     status = torch.zeros(M.shape[0], dtype=torch.int32, device=DEV)
@@ -227,6 +228,64 @@ def test_graph_step_matches_eager(ctx3):
     # 1 + 2 + 3 + 4 steps of 1000 cells, each counted once per step
     assert int(runs[True][-1][6].sum().item()) == 10 * 1000
     print(f"[graph] 4 calls (1..4 steps) identical to plain launches, t = {runs[True][-1][3].item():.4f}")
+
+
+@pytest.mark.parametrize("scheme", ["lw", "flic"])
+def test_second_order_steps_match_oracle(ctx3, scheme):
+    # Mach 3, 240 cells of 0.1 upstream mean free paths: both interface schemes
+    # against the oracle's, cell by cell
+    args = (3.0, 240, -12.0, 12.0, 3.0)
+    problem = mem_inputs.shock_problem(*args)
+    batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0, flux_scheme=scheme)
+    tot0 = ctx3.conserved(batch, Md, gd).cpu().numpy()
+    n_steps = 8
+    print(f"\n[{scheme}] GPU {n_steps} steps, 240 cells", flush=True)
+    ctx3.step(batch, Md, bd, gd, t, dt, n_steps, status=status)
+    torch.cuda.synchronize()
+    print(f"[{scheme}] oracle run", flush=True)
+    ora = kinetics.ShockSolver(*args, nodes_1d=12, scheme=scheme)
+    dts = [ora.step() for _ in range(n_steps)]
+    assert not np.any(ora.lw_failed)
+    assert t.item() == pytest.approx(sum(dts), rel=1e-5)
+    mg = kinetics.macroscopic(Md.cpu().numpy().astype(np.float64), gd.cpu().numpy().astype(np.float64))
+    mo = kinetics.macroscopic(ora.M, ora.g)
+    for key in ("n", "v", "T"):
+        err = np.max(np.abs(mg[key] - mo[key]) / np.abs(mo[key]))
+        print(f"[{scheme}] {key} rel err {err:.2e}")
+        assert err < 1e-4, key
+    qs = np.max(np.abs(mg["qx"] - mo["qx"]))
+    print(f"[{scheme}] q_x abs err {qs:.2e}")
+    assert qs < 1e-3
+    # the moments themselves, in each cell's gauge
+    scale = np.maximum(1.0, np.max(np.abs(ora.M), axis=1, keepdims=True))
+    em = np.max(np.abs(Md.cpu().numpy() - ora.M) / scale)
+    print(f"[{scheme}] moments rel err {em:.2e}")
+    assert em < 2e-4
+    tot1 = ctx3.conserved(batch, Md, gd).cpu().numpy()
+    (n1, v1, _), (n2, v2, _) = problem["states"]
+    assert tot1[0, 0] - tot0[0, 0] == pytest.approx(t.item() * (n1 * v1 - n2 * v2), rel=2e-2, abs=1e-5)
+    st = status.cpu().numpy()
+    assert not np.any(st & (mem.ST_NONFINITE | mem.ST_NONREALIZABLE | mem.ST_LAMBDA_FAIL))
+
+
+def test_flic_graph_matches_eager(ctx3):
+    # the FLIC step holds two solves per step; captured and replayed it equals
+    # the plain launches bit for bit
+    problem = mem_inputs.shock_problem(3.0, 500, -20.0, 20.0, 5.44)
+    runs = {}
+    for graph in (False, True):
+        batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0, use_graph=graph,
+                                                      flux_scheme="flic")
+        snaps = []
+        for call in range(3):
+            ctx3.step(batch, Md, bd, gd, t, dt, 2, status=status)
+            junk = torch.randn(4096, device=DEV).sum()
+            torch.cuda.synchronize()
+            snaps.append([x.clone() for x in (Md, bd, gd, t, dt, status)] + [junk])
+        runs[graph] = snaps
+    for call, (ea, gr) in enumerate(zip(runs[False], runs[True])):
+        for k, (x, y) in enumerate(zip(ea[:6], gr[:6])):
+            assert torch.equal(x, y), (call, k)
 
 
 def test_shock_reaches_steady_state(ctx3):

@@ -130,8 +130,8 @@ def test_fv_update_is_conservative():
     dt = s.dt
     M2 = s._fv(M, F, rho, dt)
     # mass (M_0 is gauge invariant): change equals boundary flux difference
-    MLg, FLg, rL, _ = s.ghost_left
-    MRg, FRg, rR, _ = s.ghost_right
+    MLg, FLg, rL, _, _ = s.ghost_left
+    MRg, FRg, rR, _, _ = s.ghost_right
     TL = gauge.change_matrix(g[:1], s.ghost_left[3][None], 3)[0]
     TR = gauge.change_matrix(g[-1:], s.ghost_right[3][None], 3)[0]
     fL = 0.5 * ((TL @ FLg)[0] + F[0, 0]) + 0.5 * max(rL, rho[0]) * ((TL @ MLg)[0] - M[0, 0])
