@@ -207,7 +207,7 @@ def mixed_comparison(mem, torch, dev, cells, steps, warmup):
     return out
 
 
-def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph, iter_hist=None):
+def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph, iter_hist=None, flux_scheme="llf"):
     """Device state and batch for a list of shock problems (gauge applied)."""
     import mem_inputs
     M = np.concatenate([p["M"] for p in probs]).astype(np.float32)
@@ -222,17 +222,18 @@ def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph, iter_hist=None):
                            np.stack([p["M_right"] for p in probs]),
                            np.stack([p["g_left"] for p in probs]),
                            np.stack([p["g_right"] for p in probs]), device=dev,
-                           use_graph=use_graph, iter_hist=iter_hist)
+                           use_graph=use_graph, iter_hist=iter_hist, flux_scheme=flux_scheme)
     P = len(probs)
     return batch, Md, bd, gd, torch.zeros(P, device=dev), torch.zeros(P, device=dev)
 
 
-def shock_steady(mem, torch, dev, max_steps):
-    """Mach-3 normal shock, 1000 cells on [-20, 20]: step rate and time to steady state."""
+def shock_steady(mem, torch, dev, max_steps, scheme="llf", cells=1000):
+    """Mach-3 normal shock on [-20, 20]: step rate and time to steady state."""
     import mem_inputs
     ctx = mem.Context(3, 12)
-    pr = mem_inputs.shock_problem(3.0, 1000, -20.0, 20.0, 5.44)
-    b, M, be, g, t, dt = shock_setup(mem, torch, dev, ctx, [pr], [pr["dx"]], True)
+    pr = mem_inputs.shock_problem(3.0, cells, -20.0, 20.0, 5.44)
+    b, M, be, g, t, dt = shock_setup(mem, torch, dev, ctx, [pr], [pr["dx"]], True,
+                                     flux_scheme=scheme)
     ctx.step(b, M, be, g, t, dt, 10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -252,14 +253,19 @@ def shock_steady(mem, torch, dev, max_steps):
     wall = time.perf_counter() - t0
     n = M[:, 0].cpu().numpy()
     ctx.close()
-    return {"workload": "Mach-3 normal shock, 1000 cells on [-20, 20] (upstream mean free "
-                        "path 1), ES-BGK Pr 2/3, LLF, CFL 0.5, 12^3 nodes, 8 Newton iterations "
-                        "per step, hipGraph replay",
-            "ms_per_step": ms, "cell_steps_per_s": 1000 / (ms * 1e-3),
+    # density thickness (n+ - n-) / max |dn/dx|, in upstream mean free paths
+    thick = (n2 - n1) / (np.max(np.abs(np.diff(n))) / pr["dx"])
+    names = {"llf": "LLF", "lw": "two-step Lax-Wendroff", "flic": "FLIC (van Leer)"}
+    return {"workload": f"Mach-3 normal shock, {cells} cells on [-20, 20] (upstream mean free "
+                        f"path 1), ES-BGK Pr 2/3, {names[scheme]}, CFL 0.5, 12^3 nodes, 8 Newton "
+                        "iterations per solve, hipGraph replay",
+            "ms_per_step": ms, "cell_steps_per_s": cells / (ms * 1e-3),
             "steady": {"criterion": "max |n(k+100) - n(k)| / (n+ - n-) <= 2e-5",
                        "steps": steps, "t": float(t.item()), "wall_s": wall + ms * 510e-3,
                        "last_change": change, "reached": change <= 2e-5,
-                       "n_ends": [float(n[0]), float(n[-1])], "n_rankine_hugoniot": [n1, n2]}}
+                       "n_ends": [float(n[0]), float(n[-1])], "n_rankine_hugoniot": [n1, n2],
+                       "density_thickness_mfp": float(thick),
+                       "finite": bool(np.isfinite(n).all())}}
 
 
 def ragged_rate(mem, torch, dev, steps):
@@ -445,6 +451,11 @@ def main():
     if not args.no_extras:
         line["latency_1d"] = latency_1d(mem, torch, dev)
         line["shock"] = shock_steady(mem, torch, dev, args.shock_max_steps)
+        # second order at the paper's resolutions (0.13-0.63 mean free paths per
+        # cell), against LLF on the same grid
+        line["shock_flic"] = {"flic": shock_steady(mem, torch, dev, args.shock_max_steps, "flic", 250),
+                              "llf_same_grid": shock_steady(mem, torch, dev, args.shock_max_steps,
+                                                            "llf", 250)}
         if args.ragged_steps > 0:
             line["ragged"] = ragged_rate(mem, torch, dev, args.ragged_steps)
     if not args.no_cpu_baseline:

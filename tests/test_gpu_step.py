@@ -347,6 +347,79 @@ def test_shock_reaches_steady_state(ctx3):
     assert rate_steady <= 4.0 * rate_gpu
 
 
+def _run_steady(ctx, problem, scheme, max_steps=40000):
+    batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx, 0, use_graph=True,
+                                                  flux_scheme=scheme)
+    (n1, _, _), (n2, _, _) = problem["states"]
+    prev = Md[:, 0].clone()
+    steps, change, rate = 0, 1.0, 0.0
+    while steps < max_steps and change > 2e-5:
+        t_prev = t.item()
+        ctx.step(batch, Md, bd, gd, t, dt, 100, status=status)
+        steps += 100
+        cur = Md[:, 0].clone()
+        dn = (cur - prev).abs().max().item()
+        change, rate = dn / (n2 - n1), dn / (t.item() - t_prev)
+        prev = cur
+    return batch, Md, bd, gd, t, dt, status, steps, change, rate
+
+
+def test_flic_shock_reaches_steady_state(ctx3):
+    """FLIC at the paper's resolutions (here 0.16 upstream mean free paths per
+    cell, Mach 3, 250 cells): steady state with the Rankine-Hugoniot end states,
+    conserved totals, one step from it equal to the FP64 oracle's FLIC step, and
+    a shock sharper than the LLF one on the same grid."""
+    problem = mem_inputs.shock_problem(3.0, 250, -20.0, 20.0, 5.44)
+    (n1, v1, T1), (n2, v2, T2) = problem["states"]
+    batch, Md, bd, gd, t, dt, status, steps, change, _ = _run_steady(ctx3, problem, "flic")
+    print(f"\n[flic steady] {steps} steps, t = {t.item():.2f}, change per 100 steps {change:.2e}",
+          flush=True)
+    assert change <= 2e-5
+    st = status.cpu().numpy()
+    assert not np.any(st & (mem.ST_NONFINITE | mem.ST_NONREALIZABLE | mem.ST_LAMBDA_FAIL))
+    M = Md.cpu().numpy().astype(np.float64)
+    g = gd.cpu().numpy().astype(np.float64)
+    mg = kinetics.macroscopic(M, g)
+    assert mg["n"][0] == pytest.approx(n1, rel=1e-3) and mg["n"][-1] == pytest.approx(n2, rel=1e-3)
+    assert mg["T"][0] == pytest.approx(T1, rel=1e-3) and mg["T"][-1] == pytest.approx(T2, rel=1e-3)
+    tot0 = ctx3.conserved(batch, Md, gd).cpu().numpy()
+    t0 = t.item()
+    ctx3.step(batch, Md, bd, gd, t, dt, 500)
+    tot1 = ctx3.conserved(batch, Md, gd).cpu().numpy()
+    dmass = abs(tot1[0, 0] - tot0[0, 0]) / ((t.item() - t0) * n1 * v1)
+    print(f"[flic steady] mass change over {t.item() - t0:.2f} time units: {dmass:.2e} of the inflow")
+    assert dmass < 1e-3
+    # At the sub-shock the limiter switches from step to step: the state is a
+    # short limit cycle whose average no longer moves.  One step from it, GPU and
+    # FP64 oracle agree cell by cell.
+    ora = kinetics.ShockSolver(3.0, 250, -20.0, 20.0, 5.44, nodes_1d=12, scheme="flic")
+    ora.M, ora.g = Md.cpu().numpy().astype(np.float64), gd.cpu().numpy().astype(np.float64)
+    ora.beta = ora._solve(ora.M, bd.cpu().numpy().astype(np.float64))
+    ora.dt = float(dt.item())
+    n_before = ora.M[:, 0].copy()
+    dto = ora.step()
+    t_prev = t.item()
+    ctx3.step(batch, Md, bd, gd, t, dt, 1)
+    assert t.item() - t_prev == pytest.approx(dto, abs=1e-5)   # t is FP32 near 50
+    n_gpu = Md[:, 0].cpu().numpy().astype(np.float64)
+    step_o = ora.M[:, 0] - n_before
+    step_g = n_gpu - n_before
+    err = np.max(np.abs(step_g - step_o)) / np.max(np.abs(step_o))
+    print(f"[flic steady] one step from the steady state: max |dn| {np.max(np.abs(step_o)):.3e}, "
+          f"GPU vs oracle {err:.2e} of it; drift per 100 steps {change:.2e}")
+    assert err < 2e-2
+    mo = kinetics.macroscopic(ora.M, ora.g)
+    mgs = kinetics.macroscopic(Md.cpu().numpy().astype(np.float64), gd.cpu().numpy().astype(np.float64))
+    assert np.max(np.abs(mgs["n"] - mo["n"]) / mo["n"]) < 1e-5
+    # second order: a thinner (less smeared) profile than LLF on the same grid
+    n_flic = Md[:, 0].cpu().numpy()
+    _, Ml, *_ = _run_steady(ctx3, problem, "llf")
+    n_llf = Ml[:, 0].cpu().numpy()
+    thick = lambda n: (n2 - n1) / (np.max(np.abs(np.diff(n))) / problem["dx"])
+    print(f"[flic steady] density thickness FLIC {thick(n_flic):.3f}, LLF {thick(n_llf):.3f}")
+    assert thick(n_flic) < 0.85 * thick(n_llf)
+
+
 def test_strong_shock_stays_finite_and_conservative(ctx3):
     """Mach 8: cells inside the layer are not representable on the 12^3 rule and
     step with their Maxwellian (MEM_ST_MAXWELL_FLUX).  The state must stay
