@@ -269,6 +269,9 @@ __global__ __launch_bounds__(64) void k_lse3(
 // and node groups [split * ngroups / nsplit, (split + 1) * ngroups / nsplit)
 // of split = b / ntile, and writes its partial sums to
 // Sp[split][slot][NCOL]; k_sum_splits adds them in a fixed order.
+// NB4 quadruples of 16-column blocks: 10 (S, 640 columns) or 2 (the 128
+// columns of the degree-5 products used by the characteristic speeds).
+template <int NB4>
 __global__ __launch_bounds__(256, 2) void k_assemble3(
     const float* __restrict__ phiA, const float* __restrict__ psi, int ngroups,
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr, int64_t n,
@@ -296,9 +299,11 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
   }
   const float lz = valid ? logZ[cell] : 0.f;
 
-  f4 acc[NBLK];
+  constexpr int NB = 4 * NB4;       // accumulator tiles
+  constexpr int WIDTH = 16 * NB;    // output row width
+  f4 acc[NB];
 #pragma unroll
-  for (int b = 0; b < NBLK; ++b) acc[b] = (f4){0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < NB; ++b) acc[b] = (f4){0.f, 0.f, 0.f, 0.f};
 
   // Half-group ping-pong: half h of the node range holds Psi rows 2(h%2),
   // 2(h%2)+1 (20 KB) of group h/2 and lives in buffer h%2; the exponent table
@@ -306,23 +311,23 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
   // direct (register-free) loads: half h+1 is issued right after the barrier
   // that opens half h and waited for at the next barrier, so its latency runs
   // under the MFMAs of half h.
-  __shared__ f4 sB0[2 * 10 * 64];  // 20 KB each
-  __shared__ f4 sB1[2 * 10 * 64];
+  __shared__ f4 sB0[2 * NB4 * 64];  // 20 KB each for S
+  __shared__ f4 sB1[2 * NB4 * 64];
   __shared__ f4 sA4[NJ * 16];      // exponent operand of one node group
   const float* sA = reinterpret_cast<const float*>(sA4);
   // buffer resources (bounds = the tables); lane l of wave w moves the 16 bytes
   // at offset 16 (64 w + l) + 4096 i of a half into LDS element 64 w + 256 i + l
   const __amdgpu_buffer_rsrc_t rB =
-      __builtin_amdgcn_make_buffer_rsrc((void*)psi, (short)0, ngroups * (4 * 10 * 64 * 16), BUF_DW3);
+      __builtin_amdgcn_make_buffer_rsrc((void*)psi, (short)0, ngroups * (4 * NB4 * 64 * 16), BUF_DW3);
   const __amdgpu_buffer_rsrc_t rA =
       __builtin_amdgcn_make_buffer_rsrc((void*)phiA, (short)0, ngroups * (NJ * 64 * 4), BUF_DW3);
   const int voff = (int)threadIdx.x * 16;
   const int hend = 2 * gend;
   auto fetch = [&](f4* dst, int h, bool first) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < NB4 / 2; ++i)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, lds_ptr(dst + 64 * wave + 256 * i), 16, voff,
-                                               h * (2 * 10 * 64 * 16) + 4096 * i, 0, 0);
+                                               h * (2 * NB4 * 64 * 16) + 4096 * i, 0, 0);
     if (first && threadIdx.x < NJ * 16)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rA, lds_ptr(sA4 + 64 * wave), 16, voff,
                                                (h >> 1) * (NJ * 64 * 4), 0, 0);
@@ -333,8 +338,8 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
     for (int rr = 0; rr < 2; ++rr) {
       const float sgr = rr ? s1 : s0;
 #pragma unroll
-      for (int b4 = 0; b4 < 10; ++b4) {
-        const f4 bv = buf[(rr * 10 + b4) * 64 + lane];
+      for (int b4 = 0; b4 < NB4; ++b4) {
+        const f4 bv = buf[(rr * NB4 + b4) * 64 + lane];
         acc[4 * b4 + 0] = mfma4(sgr, bv[0], acc[4 * b4 + 0]);
         acc[4 * b4 + 1] = mfma4(sgr, bv[1], acc[4 * b4 + 1]);
         acc[4 * b4 + 2] = mfma4(sgr, bv[2], acc[4 * b4 + 2]);
@@ -372,35 +377,37 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
     if (sl < count) {
       float* dst;
       if (nsplit > 1) {
-        dst = Sp + ((size_t)split * ntile * TILE + sl) * NCOL + (lane & 15);
+        dst = Sp + ((size_t)split * ntile * TILE + sl) * WIDTH + (lane & 15);
       } else {
         const int64_t cw = list ? (int64_t)list[sl] : sl;
-        dst = S + cw * NCOL + (lane & 15);
+        dst = S + cw * WIDTH + (lane & 15);
       }
 #pragma unroll
-      for (int b = 0; b < NBLK; ++b) dst[16 * b] = acc[b][q];
+      for (int b = 0; b < NB; ++b) dst[16 * b] = acc[b][q];
     }
   }
 }
 
-// S[cell] = sum over splits of Sp[split][slot] (fixed order: deterministic).
+// S[cell] = sum over splits of Sp[split][slot] (fixed order: deterministic);
+// rows of W floats.
+template <int W>
 __global__ void k_sum_splits(const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
                              int64_t n, int ntile, int nsplit, const float* __restrict__ Sp,
                              float* __restrict__ S) {
   const int64_t count = ctr ? (int64_t)(*ctr) : n;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t slot = t / (NCOL / 4);
-  const int q = (int)(t % (NCOL / 4));
+  const int64_t slot = t / (W / 4);
+  const int q = (int)(t % (W / 4));
   if (slot >= count) return;
   const int64_t cell = list ? (int64_t)list[slot] : slot;
-  const size_t stride = (size_t)ntile * TILE * NCOL;
-  const f4* src = reinterpret_cast<const f4*>(Sp + (size_t)slot * NCOL) + q;
+  const size_t stride = (size_t)ntile * TILE * W;
+  const f4* src = reinterpret_cast<const f4*>(Sp + (size_t)slot * W) + q;
   f4 acc = src[0];
   for (int k = 1; k < nsplit; ++k) {
-    const f4 v = *reinterpret_cast<const f4*>(Sp + k * stride + (size_t)slot * NCOL + 4 * q);
+    const f4 v = *reinterpret_cast<const f4*>(Sp + k * stride + (size_t)slot * W + 4 * q);
     acc += v;
   }
-  reinterpret_cast<f4*>(S + cell * NCOL)[q] = acc;
+  reinterpret_cast<f4*>(S + cell * W)[q] = acc;
 }
 
 // --------------------------------------------------------------------------
@@ -1268,7 +1275,7 @@ int assembly_splits(mem_ctx_t c, int ntile, int ngroups) {
 
 hipError_t launch_sum_splits(mem_ctx_t c, const int32_t* list, const int32_t* ctr, int64_t n,
                              int ntile, int nsplit, float* S, hipStream_t s) {
-  k_sum_splits<<<(unsigned)nblocks((int64_t)ntile * TILE * (NCOL / 4), 256), 256, 0, s>>>(
+  k_sum_splits<NCOL><<<(unsigned)nblocks((int64_t)ntile * TILE * (NCOL / 4), 256), 256, 0, s>>>(
       list, ctr, n, ntile, nsplit, c->w_Sp, S);
   return hipGetLastError();
 }
@@ -1279,11 +1286,24 @@ hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
   if (grid_cells <= 0) return hipSuccess;
   const int ntile = (int)nblocks(grid_cells, TILE);
   const int nsplit = assembly_splits(c, ntile, c->ngroups);
-  k_assemble3<<<(unsigned)(ntile * nsplit), 256, 0, s>>>(c->d_phiA, table, c->ngroups, list, ctr, n,
-                                                         beta, c->w_logZ, S, ntile, nsplit, c->w_Sp);
+  k_assemble3<NBLK / 4><<<(unsigned)(ntile * nsplit), 256, 0, s>>>(
+      c->d_phiA, table, c->ngroups, list, ctr, n, beta, c->w_logZ, S, ntile, nsplit, c->w_Sp);
   if (nsplit > 1)
-    k_sum_splits<<<(unsigned)nblocks((int64_t)ntile * TILE * (NCOL / 4), 256), 256, 0, s>>>(
+    k_sum_splits<NCOL><<<(unsigned)nblocks((int64_t)ntile * TILE * (NCOL / 4), 256), 256, 0, s>>>(
         list, ctr, n, ntile, nsplit, c->w_Sp, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble5(mem_ctx_t c, int64_t n, const float* beta, float* S5, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int ntile = (int)nblocks(n, TILE);
+  const int nsplit = assembly_splits(c, ntile, c->ngroups);
+  k_assemble3<NC5 / 64><<<(unsigned)(ntile * nsplit), 256, 0, s>>>(
+      c->d_phiA, c->d_psi5, c->ngroups, nullptr, nullptr, n, beta, c->w_logZ, S5, ntile, nsplit,
+      c->w_Sp);
+  if (nsplit > 1)
+    k_sum_splits<NC5><<<(unsigned)nblocks((int64_t)ntile * TILE * (NC5 / 4), 256), 256, 0, s>>>(
+        nullptr, nullptr, n, ntile, nsplit, c->w_Sp, S5);
   return hipGetLastError();
 }
 

@@ -205,14 +205,16 @@ __device__ __forceinline__ void eig_keep(float (&v)[K3]) {
 // Three wavefronts per SIMD (at most 168 VGPRs; one cold 16-byte spill) hide
 // more of the per-step LDS and reduction latency than two.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_eig3(int64_t n, const float* __restrict__ S,
-                                              const float* __restrict__ Sx,
+                                              const float* __restrict__ S5,
+                                              const int32_t* __restrict__ ux_src,
+                                              const float2* __restrict__ ux_w,
                                               const float* __restrict__ g, float umax,
                                               float* __restrict__ out, int radius_only,
                                               uint32_t* status) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t c = (int64_t)blockIdx.x * EIG_WAVES + wv;
   if (c >= n) return;  // whole wave
-  __shared__ __align__(16) float sbuf[EIG_WAVES][2 * K3 * EST];  // S, Sx rows; then L and T
+  __shared__ __align__(16) float sbuf[EIG_WAVES][2 * K3 * EST];  // S, C rows; then L and T
   __shared__ __align__(16) float svec[EIG_WAVES][5][EST];       // 1/L_kk, v, q, d, e
   float* W = sbuf[wv];
   float* Lm = W;              // row k = column k of L
@@ -223,12 +225,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   float* dd = svec[wv][3];
   float* ee = svec[wv][4];
   {
+    // S in the rows that become L, the S5 row behind the area that becomes T
     const f4* s4 = reinterpret_cast<const f4*>(S + c * NCOL);
-    const f4* x4 = reinterpret_cast<const f4*>(Sx + c * NCOL);
+    const f4* x4 = reinterpret_cast<const f4*>(S5 + c * NC5);
     f4* w4 = reinterpret_cast<f4*>(W);
-    // S in the rows that become L, Sx in the area that becomes T (read only
-    // after the Cholesky, so that one 35-value column is live at a time)
-    for (int i = lane; i < NCOL / 4; i += 64) { w4[i] = s4[i]; w4[K3 * EST / 4 + i] = x4[i]; }
+    for (int i = lane; i < NCOL / 4; i += 64) w4[i] = s4[i];
+    if (lane < NC5 / 4) w4[(K3 * EST + NCOL) / 4 + lane] = x4[lane];
+  }
+  __builtin_amdgcn_wave_barrier();
+  // C = E[u_x phi phi^T] in packed pair order into the T area (read only after
+  // the Cholesky, so that one 35-value column is live at a time): each entry is
+  // two weighted entries of S or S5 (Hermite three-term recurrence)
+  for (int q = lane; q < NPAIR; q += 64) {
+    const int sr = ux_src[q];
+    const float2 wq = ux_w[q];
+    const int s1 = sr & 0xffff, s2 = sr >> 16;
+    const float v1 = s1 < 1024 ? W[s1] : T[NCOL + s1 - 1024];
+    const float v2 = s2 < 1024 ? W[s2] : T[NCOL + s2 - 1024];
+    T[q] = fmaf(wq.x, v1, wq.y * v2);
   }
   __builtin_amdgcn_wave_barrier();
   const float inv0 = 1.f / W[0];
@@ -861,12 +875,12 @@ hipError_t launch_flux3(mem_ctx_t c, int64_t n, const float* beta, const float* 
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (want_lam) {
-    e = launch_assemble3(c, n, nullptr, nullptr, n, beta, c->d_psix, c->w_Sx, s);
+    e = launch_assemble5(c, n, beta, c->w_Sx, s);  // S5 rows of NC5 floats
     if (e != hipSuccess) return e;
     double um = 0.0;
     for (int p = 0; p < c->Q; ++p) um = fmax(um, fabs(c->h_nodes[(size_t)p * 3]));
-    k_eig3<<<nb(n, EIG_WAVES), 256, 0, s>>>(n, c->w_S, c->w_Sx, g, (float)um, out, radius_only ? 1 : 0,
-                                         status);
+    k_eig3<<<nb(n, EIG_WAVES), 256, 0, s>>>(n, c->w_S, c->w_Sx, c->d_ux_src, c->d_ux_w, g,
+                                            (float)um, out, radius_only ? 1 : 0, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;

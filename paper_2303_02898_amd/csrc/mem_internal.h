@@ -21,6 +21,9 @@ constexpr int GRP = 16;       // quadrature nodes per MFMA node group
 constexpr int NJ = 9;         // 4-wide k-chunks of the exponent GEMM (36 = 9*4)
 constexpr int HPACK = 595;    // packed upper triangle of the 34x34 Hessian
 constexpr int TILE = 64;      // cells per assembly / line-search workgroup
+constexpr int ND4 = 15;       // basis functions of total degree 4 (indices 20..34)
+constexpr int NP5 = 120;      // pairs (i <= j) of degree-4 functions
+constexpr int NC5 = 128;      // their columns padded to 8 MFMA blocks
 constexpr int MIX_FB = 3;     // FP32 column blocks of the mixed assembly (columns 0..47)
 constexpr float NEG_BIG = -1.0e30f;  // log weight of padding nodes (exp -> 0)
 
@@ -67,7 +70,13 @@ struct mem_ctx_s {
   // device tables, 3D
   float* d_phiA = nullptr;   // exponent A operand  [ngroups][NJ][64]
   float* d_psi = nullptr;    // assembly B operand  [ngroups][4][10][64][4]
-  float* d_psix = nullptr;   // flux-Jacobian B operand, same layout
+  // speeds: B operand of the degree-5 products phi_{i+e_x} phi_j (i <= j both of
+  // degree 4) [ngroups][4][2][64][4], and for each pair column of
+  // C = E[u_x phi phi^T] two sources and weights: src < 1024 is a column of S,
+  // src >= 1024 column src - 1024 of S5 (ux_src packs src1 | src2 << 16)
+  float* d_psi5 = nullptr;
+  int32_t* d_ux_src = nullptr;  // [NPAIR]
+  float2* d_ux_w = nullptr;     // [NPAIR]
   // mixed precision (BF16 / FP16 hi + lo) assembly operands, 32-node groups
   int nsg_m = 0;              // node groups of 32 (nodes padded with zero weight)
   float* d_phiA_m = nullptr;  // exponent A operand [2*nsg_m][NJ][64] (FP16: log w~ + k_p ln 2)
@@ -150,6 +159,7 @@ hipError_t launch_lse3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                        const int32_t* ctr, int64_t n, const float* M, float* beta,
                        bool line_search, const SolveParams& p, int32_t* reset_a,
                        int32_t* reset_b, hipStream_t s);
+hipError_t launch_assemble5(mem_ctx_t c, int64_t n, const float* beta, float* S5, hipStream_t s);
 hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                             const int32_t* ctr, int64_t n, const float* beta,
                             const float* table, float* S, hipStream_t s);

@@ -12,6 +12,7 @@
 // Basis (App. B, orthogonal form extended to 3D): phi_(a,b,c) = p_a(x) p_b(y)
 // p_c(z) with p_k = He_k / sqrt(k!), total degree <= 4, ordered by degree then
 // lexicographically descending.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
@@ -278,20 +279,73 @@ void build_tables(mem_ctx_t ctx) {
   // B operand of v_mfma_f32_16x16x4f32 for k-step r of group g:
   // lane l supplies node 16g + 4(l/16) + r, column 16b + l%16; stored as
   // [g][r][b/4][l][b%4] so each lane reads 4 blocks with one 16-byte load.
-  std::vector<float> B((size_t)ng * 4 * 10 * 64 * 4), BX(B.size());
-  for (int g = 0; g < ng; ++g)
-    for (int r = 0; r < 4; ++r)
-      for (int b4 = 0; b4 < 10; ++b4)
-        for (int l = 0; l < 64; ++l)
-          for (int q = 0; q < 4; ++q) {
-            size_t o = ((((size_t)g * 4 + r) * 10 + b4) * 64 + l) * 4 + q;
-            int p = GRP * g + 4 * (l >> 4) + r;
-            int col = 16 * (4 * b4 + q) + (l & 15);
-            B[o] = (float)psi(p, col, false);
-            BX[o] = (float)psi(p, col, true);
-          }
-  ctx->d_psi = upload(B);
-  ctx->d_psix = upload(BX);
+  auto operand = [&](int nb4, auto&& value) {
+    std::vector<float> B((size_t)ng * 4 * nb4 * 64 * 4);
+    for (int g = 0; g < ng; ++g)
+      for (int r = 0; r < 4; ++r)
+        for (int b4 = 0; b4 < nb4; ++b4)
+          for (int l = 0; l < 64; ++l)
+            for (int q = 0; q < 4; ++q) {
+              size_t o = ((((size_t)g * 4 + r) * nb4 + b4) * 64 + l) * 4 + q;
+              B[o] = (float)value(GRP * g + 4 * (l >> 4) + r, 16 * (4 * b4 + q) + (l & 15));
+            }
+    return B;
+  };
+  ctx->d_psi = upload(operand(10, [&](int p, int col) { return psi(p, col, false); }));
+
+  // Characteristic speeds need C = E[u_x phi phi^T].  Orthonormal Hermite
+  // polynomials satisfy x p_a(x) = sqrt(a+1) p_{a+1}(x) + sqrt(a) p_{a-1}(x) at
+  // every point, so u_x phi_i = sqrt(a_i+1) phi_{i+e_x} + sqrt(a_i) phi_{i-e_x}
+  // node by node and C_ij is a two-term combination of entries of S, except
+  // where i and j both have degree 4: there phi_{i+e_x} has degree 5 and
+  // E[phi_{i+e_x} phi_j] comes from 120 extra columns (S5).
+  std::vector<int> ea, eb, ec;
+  multi_indices(3, ea, eb, ec);
+  auto index_of = [&](int a, int b, int c) {
+    for (int k = 0; k < K3; ++k)
+      if (ea[k] == a && eb[k] == b && ec[k] == c) return k;
+    return -1;
+  };
+  auto deg = [&](int k) { return ea[k] + eb[k] + ec[k]; };
+  std::vector<int> d4;
+  for (int k = 0; k < K3; ++k)
+    if (deg(k) == 4) d4.push_back(k);
+  std::vector<int> p5i, p5j;  // S5 column -> (i, j), i <= j
+  std::vector<int> col5((size_t)K3 * K3, -1);
+  for (size_t x = 0; x < d4.size(); ++x)
+    for (size_t y = x; y < d4.size(); ++y) {
+      col5[(size_t)d4[x] * K3 + d4[y]] = (int)p5i.size();
+      p5i.push_back(d4[x]);
+      p5j.push_back(d4[y]);
+    }
+  if ((int)d4.size() != ND4 || (int)p5i.size() != NP5) throw std::runtime_error("degree-4 set");
+  std::vector<double> hx(6), hy(6), hz(6);
+  ctx->d_psi5 = upload(operand(NC5 / 64, [&](int p, int col) -> double {
+    if (p >= Q || col >= NP5) return 0.0;
+    const int i = p5i[col], j = p5j[col];
+    ortho_hermite(5, ctx->h_nodes[(size_t)p * 3], hx.data());
+    ortho_hermite(5, ctx->h_nodes[(size_t)p * 3 + 1], hy.data());
+    ortho_hermite(5, ctx->h_nodes[(size_t)p * 3 + 2], hz.data());
+    return hx[ea[i] + 1] * hy[eb[i]] * hz[ec[i]] * ctx->h_phi[(size_t)p * K3 + j];
+  }));
+  std::vector<int32_t> src(NPAIR);
+  std::vector<float2> wts(NPAIR);
+  auto scol = [&](int u, int v) { return pair_col(std::min(u, v), std::max(u, v)); };
+  for (int i = 0; i < K3; ++i)
+    for (int j = i; j < K3; ++j) {
+      // raise the lower-degree index (C is symmetric); both of degree 4: S5
+      const int r = deg(i) <= 3 ? i : (deg(j) <= 3 ? j : i);
+      const int o = r == i ? j : i;
+      const int up = index_of(ea[r] + 1, eb[r], ec[r]);
+      const int s1 = up >= 0 ? scol(up, o) : 1024 + col5[(size_t)r * K3 + o];
+      const int dn = ea[r] > 0 ? index_of(ea[r] - 1, eb[r], ec[r]) : -1;
+      const int s2 = dn >= 0 ? scol(dn, o) : s1;
+      src[pair_col(i, j)] = s1 | (s2 << 16);
+      wts[pair_col(i, j)] = make_float2((float)std::sqrt((double)(ea[r] + 1)),
+                                        dn >= 0 ? (float)std::sqrt((double)ea[r]) : 0.f);
+    }
+  ctx->d_ux_src = upload(src);
+  ctx->d_ux_w = upload(wts);
   if (ctx->prec != MEM_PREC_FP32) build_mixed(ctx, phiE, psi);
 }
 
