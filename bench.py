@@ -268,6 +268,45 @@ def shock_steady(mem, torch, dev, max_steps, scheme="llf", cells=1000):
                        "finite": bool(np.isfinite(n).all())}}
 
 
+def gauge_study(mem, torch, dev):
+    """Upstream Maxwellians of Mach 2..12 solved in FP32 from the uniform start,
+    in each state's Hermite gauge and in the fixed gauge (0, 1, 1)."""
+    import math
+    import mem_inputs
+    ctx = mem.Context(3, 12)
+    machs = np.arange(2, 13, dtype=np.float64)
+    v = math.sqrt(5.0 / 3.0) * machs
+    N = machs.size
+    out = {"workload": "upstream Maxwellians n = 1, T = 1, Mach 2..12, 12^3 nodes, FP32, "
+                       "start beta_i = 0 (i >= 1)", "mach": machs.tolist()}
+    names = [(mem.ST_CONVERGED, "converged"), (mem.ST_STAGNATED, "stagnated"),
+             (mem.ST_NONREALIZABLE, "nonrealizable"), (mem.ST_MAXITER, "maxiter")]
+    for gauge in ("hermite", "fixed"):
+        w = v if gauge == "hermite" else np.zeros(N)
+        g = np.stack([w, np.ones(N), np.ones(N)], axis=1)
+        M = mem_inputs.gaussian_moments(np.ones(N), v, np.ones(N), np.ones(N), g)
+        b = np.zeros((N, 35), dtype=np.float32)
+        b[:, 0] = 1.0
+        Md = torch.tensor(M.astype(np.float32), device=dev)
+        bd = torch.tensor(b, device=dev)
+        it = torch.zeros(N, dtype=torch.int32, device=dev)
+        rs = torch.zeros(N, device=dev)
+        st = torch.zeros(N, dtype=torch.int32, device=dev)
+        ctx.solve(Md, bd, iters=it, resid=rs, status=st)
+        torch.cuda.synchronize()
+        stv = st.cpu().numpy()
+        row = {"iterations": it.cpu().tolist(), "residual": [float(x) for x in rs.cpu()],
+               "status": [next((nm for bit, nm in names if s & bit), hex(int(s))) for s in stv]}
+        if gauge == "hermite":
+            # the answer is the state's Maxwellian: -1/sqrt(2) on the three squares, else 0
+            ref = np.zeros((N, 34))
+            ref[:, [3, 6, 8]] = -math.sqrt(0.5)
+            row["beta_error_max"] = float(np.max(np.abs(bd.cpu().numpy()[:, 1:] - ref)))
+        out[gauge] = row
+    ctx.close()
+    return out
+
+
 def ragged_rate(mem, torch, dev, steps):
     """2048 independent shocks, log-uniform cell counts in [64, 4096]: cell-steps/s."""
     import mem_inputs
@@ -450,6 +489,7 @@ def main():
         line["mixed"] = mixed_comparison(mem, torch, dev, args.mixed_cells, 3, 1)
     if not args.no_extras:
         line["latency_1d"] = latency_1d(mem, torch, dev)
+        line["gauge_study"] = gauge_study(mem, torch, dev)
         line["shock"] = shock_steady(mem, torch, dev, args.shock_max_steps)
         # second order at the paper's resolutions (0.13-0.63 mean free paths per
         # cell), against LLF on the same grid
