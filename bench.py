@@ -207,7 +207,8 @@ def mixed_comparison(mem, torch, dev, cells, steps, warmup):
     return out
 
 
-def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph, iter_hist=None, flux_scheme="llf"):
+def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph, iter_hist=None, flux_scheme="llf",
+                cond_max=None):
     """Device state and batch for a list of shock problems (gauge applied)."""
     import mem_inputs
     M = np.concatenate([p["M"] for p in probs]).astype(np.float32)
@@ -222,7 +223,8 @@ def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph, iter_hist=None, flux
                            np.stack([p["M_right"] for p in probs]),
                            np.stack([p["g_left"] for p in probs]),
                            np.stack([p["g_right"] for p in probs]), device=dev,
-                           use_graph=use_graph, iter_hist=iter_hist, flux_scheme=flux_scheme)
+                           use_graph=use_graph, iter_hist=iter_hist, flux_scheme=flux_scheme,
+                           cond_max=cond_max)
     P = len(probs)
     return batch, Md, bd, gd, torch.zeros(P, device=dev), torch.zeros(P, device=dev)
 
@@ -303,6 +305,37 @@ def gauge_study(mem, torch, dev):
             ref[:, [3, 6, 8]] = -math.sqrt(0.5)
             row["beta_error_max"] = float(np.max(np.abs(bd.cpu().numpy()[:, 1:] - ref)))
         out[gauge] = row
+    ctx.close()
+    return out
+
+
+def cond_study(mem, torch, dev):
+    """Conditioning against resolution (the paper's cell-count study): Mach-4
+    shock on [-16.3, 16.3], run to t = 10, then the largest pivot-ratio bound of
+    cond(H) met by any cell over the next 200 steps."""
+    import mem_inputs
+    ctx = mem.Context(3, 12)
+    out = {"workload": "Mach-4 normal shock on [-16.3, 16.3], tanh thickness 5.44, ES-BGK, "
+                       "12^3 nodes; bound max d_k / min d_k of cond(H) over steps t > 10 "
+                       "(200 steps)", "runs": []}
+    for scheme, cells in (("llf", 125), ("llf", 250), ("llf", 500), ("llf", 1000),
+                          ("flic", 125), ("flic", 250)):
+        pr = mem_inputs.shock_problem(4.0, cells, -16.3, 16.3, 5.44)
+        cm = torch.zeros(1, device=dev)
+        b, M, be, g, t, dt = shock_setup(mem, torch, dev, ctx, [pr], [pr["dx"]], True,
+                                         flux_scheme=scheme, cond_max=cm)
+        steps = 0
+        while t.item() < 10.0 and steps < 20000:
+            ctx.step(b, M, be, g, t, dt, 100)
+            steps += 100
+            if steps % 1000 == 0 and not torch.isfinite(M).all().item():
+                break
+        cm.zero_()
+        ctx.step(b, M, be, g, t, dt, 200)
+        torch.cuda.synchronize()
+        out["runs"].append({"scheme": scheme, "cells": cells, "dx": pr["dx"],
+                            "cond_bound_max": float(cm.item()), "t": float(t.item()),
+                            "finite": bool(torch.isfinite(M).all().item())})
     ctx.close()
     return out
 
@@ -490,6 +523,7 @@ def main():
     if not args.no_extras:
         line["latency_1d"] = latency_1d(mem, torch, dev)
         line["gauge_study"] = gauge_study(mem, torch, dev)
+        line["cond_study"] = cond_study(mem, torch, dev)
         line["shock"] = shock_steady(mem, torch, dev, args.shock_max_steps)
         # second order at the paper's resolutions (0.13-0.63 mean free paths per
         # cell), against LLF on the same grid

@@ -159,6 +159,15 @@ typedef struct {
                                     cells whose solve took k Newton iterations (Alg. 1
                                     directions).  Accumulates over calls; never cleared. */
   int32_t        flux_scheme;    /* MEM_FLUX_LLF, MEM_FLUX_LW or MEM_FLUX_FLIC (Sec. 3.4)  */
+  float*         cond_max;       /* device [n_problems] or NULL: running maximum, over the
+                                    steps and the problem's cells, of max d_k / min d_k over
+                                    the LDL^T pivots of the unshifted Hessian of every Newton
+                                    direction of the cells' solves -- a lower bound of
+                                    cond(H) (each pivot of an SPD matrix lies between its
+                                    extreme eigenvalues); +inf where an FP32 pivot was not
+                                    positive.  The conditioning monitor of the paper's
+                                    cell-count study (Sec. 3.5, Sec. 4.6).  Accumulates over
+                                    calls; never cleared.                                   */
 } mem_batch_t;
 
 /* ---- context -------------------------------------------------------------- */

@@ -214,6 +214,7 @@ class FVSolver:
         (the paper integrates over a wide fixed velocity box and does not meet this
         case; the GPU step applies the same rule)."""
         out = _maxent.newton_solve(M, beta, self.Phi, self.logw, **self.newton)
+        self.last_solve = out
         b = out["beta"]
         ok_M = np.all(np.isfinite(M), axis=1) & (M[:, 0] > 0)
         bad = ok_M & (out["nonrealizable"] | ~np.all(np.isfinite(b), axis=1))

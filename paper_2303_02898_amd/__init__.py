@@ -49,7 +49,7 @@ class Batch(ctypes.Structure):
                 ("cell_offsets", _vp), ("dx", _vp), ("M_left", _vp), ("M_right", _vp),
                 ("g_left", _vp), ("g_right", _vp), ("cfl", _c_f32), ("prandtl", _c_f32),
                 ("mu_ref", _c_f32), ("newton_per_step", _c_i32), ("use_graph", _c_i32),
-                ("iter_hist", _vp), ("flux_scheme", _c_i32)]
+                ("iter_hist", _vp), ("flux_scheme", _c_i32), ("cond_max", _vp)]
 
 
 _lib = None
@@ -337,7 +337,8 @@ class ShockBatch:
 
     def __init__(self, offsets, dx, M_left, M_right, g_left, g_right, device="cuda",
                  cfl=0.5, prandtl=2.0 / 3.0, mu_ref=0.7978845608028654, collision=1,
-                 newton_per_step=8, use_graph=False, iter_hist=None, flux_scheme="llf"):
+                 newton_per_step=8, use_graph=False, iter_hist=None, flux_scheme="llf",
+                 cond_max=None):
         import torch
         if flux_scheme not in FLUX_SCHEMES:
             raise ValueError(f"flux_scheme must be one of {sorted(FLUX_SCHEMES)}")
@@ -364,3 +365,12 @@ class ShockBatch:
                                  "newton_per_step + 1 bins")
             self.iter_hist = iter_hist
             self.struct.iter_hist = iter_hist.data_ptr()
+        # conditioning monitor (device float32 [n_problems]), accumulated by mem_step
+        self.cond_max = None
+        if cond_max is not None:
+            if (cond_max.dtype != torch.float32 or not cond_max.is_contiguous()
+                    or cond_max.numel() != self.n_problems or not cond_max.is_cuda):
+                raise ValueError("cond_max must be a contiguous device float32 tensor of "
+                                 "n_problems entries")
+            self.cond_max = cond_max
+            self.struct.cond_max = cond_max.data_ptr()

@@ -46,6 +46,7 @@ void free_workspace(mem_ctx_t c) {
   for (auto& l : c->w_list) dfree(l);
   dfree(c->w_Gacc); dfree(c->w_racc); dfree(c->w_rbest); dfree(c->w_itbest);
   dfree(c->w_Mnew); dfree(c->w_F); dfree(c->w_rho); dfree(c->w_prob); dfree(c->w_code); dfree(c->w_Sp);
+  dfree(c->w_cond);
   dfree(c->w_hM); dfree(c->w_hB); dfree(c->w_hG); dfree(c->w_hF); dfree(c->w_hLF); dfree(c->w_hPhi);
   c->sp_rows = 0;
   c->cap_cells = 0;
@@ -118,7 +119,7 @@ struct ProfScope {
 // 4/5 refinement lists.
 mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const SolveParams& p,
                   int max_iter, int poll, int refine, int32_t* iters, float* resid,
-                  uint32_t* status, hipStream_t s) {
+                  uint32_t* status, hipStream_t s, float* cond = nullptr) {
   int32_t* ctr = c->w_ctr;
   int32_t* done = refine > 0 ? c->w_list[3] : nullptr;
   MEM_HIP(c, launch_set_ctr(ctr, 8, s));
@@ -144,7 +145,7 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
       ProfScope ps(c, 1, s);
       MEM_HIP(c, launch_direction3(c, grid, c->w_list[cur], &ctr[cur], M, beta, p, c->w_list[nxt],
                                    &ctr[nxt], c->w_list[2], &ctr[2], iters, resid, status, done,
-                                   &ctr[3], s));
+                                   &ctr[3], s, cond));
     }
     MEM_HIP(c, launch_fallback3(c, grid, c->w_list[2], &ctr[2], M, beta, p, c->w_list[nxt], &ctr[nxt],
                                 iters, resid, status, done, &ctr[3], s));
@@ -282,7 +283,7 @@ mem_err_t mem_reserve(mem_ctx_t c, int64_t max_cells, int32_t max_problems) {
               dalloc(c->w_rho, n) && dalloc(c->w_prob, n) && dalloc(c->w_code, n) &&
               dalloc(c->w_Sp, (size_t)SP_ROWS * NCOL) && dalloc(c->w_hM, n * K3) &&
               dalloc(c->w_hB, n * K3) && dalloc(c->w_hG, n * 3) && dalloc(c->w_hF, n * K3) &&
-              dalloc(c->w_hLF, n * K3) && dalloc(c->w_hPhi, n * K3);
+              dalloc(c->w_hLF, n * K3) && dalloc(c->w_hPhi, n * K3) && dalloc(c->w_cond, n);
     if (!ok) { free_workspace(c); return fail(c, MEM_ERR_NOMEM, "workspace allocation"); }
     c->cap_cells = max_cells;
     c->sp_rows = SP_ROWS;
@@ -482,8 +483,11 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
   // one step of Alg. 2 on stream st (no host synchronisation inside)
   auto step_once = [&](hipStream_t st) -> mem_err_t {
     MEM_HIP(c, launch_collide3(c, n, M, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, st));
-    mem_err_t er = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, st);
+    float* cond = b->cond_max ? c->w_cond : nullptr;
+    if (cond) MEM_HIP(c, launch_zero(n, cond, st));
+    mem_err_t er = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, st, cond);
     if (er != MEM_OK) return er;
+    if (cond) MEM_HIP(c, launch_cond_max(n, cond, c->w_prob, b->cond_max, st));
     MEM_HIP(c, launch_maxwell_fallback(c, n, M, beta, st));
     if (status) MEM_HIP(c, launch_status_or(n, c->w_status, status, st));
     if (b->iter_hist) MEM_HIP(c, launch_iter_hist(n, c->w_iters, budget + 1, b->iter_hist, st));

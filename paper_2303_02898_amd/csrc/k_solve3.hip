@@ -418,6 +418,11 @@ struct DirOut {
   int32_t* next_list; int32_t* next_ctr;
   int32_t* iters_out; float* resid_out; uint32_t* status_out;
   int32_t* done_list; int32_t* done_ctr;  // converged cells (for refinement), may be null
+  // running max per cell of max d_k / min d_k over the LDL^T pivots of the
+  // unshifted Hessian of each direction (every pivot of an SPD matrix lies
+  // between its extreme eigenvalues, so this bounds cond(H) from below); +inf
+  // where a pivot was not positive.  May be null.
+  float* cond;
 };
 
 // Stopping tests of Alg. 1 (residual sign read as 1/2 G^T (H + lambda I)^-1 G)
@@ -784,9 +789,11 @@ __global__ __launch_bounds__(64 * DW) void k_direction3(
   bool to_fp64 = false;
   uint32_t extra = 0;
   float lam = 0.f;
+  float cnd = 0.f;
   for (int tries = 0;; ++tries) {
     load_h(lam);
     factor();
+    if (tries == 0) cnd = ok ? dmax / dmin : __builtin_inff();
     if (tries == 0 && p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
       to_fp64 = isfinite(r);
       break;
@@ -829,6 +836,7 @@ __global__ __launch_bounds__(64 * DW) void k_direction3(
                    : finish_cell(cell, r, res, dfin, extra, p, cs, gdot, iters_w, status_w,
                                  resid_w, rbest_w, itbest_w, o);
     codes[slot] = (int8_t)code;
+    if (o.cond && isfinite(r)) o.cond[cell] = fmaxf(o.cond[cell], cnd);
   }
   code = __shfl(code, lane & 32);
   if (code == 1 && live) {
@@ -1312,9 +1320,9 @@ hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
                              const SolveParams& p,
                              int32_t* next_list, int32_t* next_ctr, int32_t* fb_list,
                              int32_t* fb_ctr, int32_t* iters, float* resid, uint32_t* status,
-                             int32_t* done_list, int32_t* done_ctr, hipStream_t s) {
+                             int32_t* done_list, int32_t* done_ctr, hipStream_t s, float* cond) {
   if (grid_cells <= 0) return hipSuccess;
-  DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
+  DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr, cond};
 #define MEM_DIR(DW)                                                                        \
   k_direction3<DW><<<nblocks(grid_cells, 2 * DW), 64 * DW, 0, s>>>(                       \
       list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot, c->w_alpha, c->w_iters, c->w_status,   \

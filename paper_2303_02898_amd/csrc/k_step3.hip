@@ -744,6 +744,31 @@ __global__ void k_rho_max(int64_t n, const float* __restrict__ rho, const int32_
   }
 }
 
+// Per-problem maximum of the cells' condition bounds (non-negative, +inf kept;
+// NaN ignored), wave-aggregated as in k_rho_max.
+__global__ void k_cond_max(int64_t n, const float* __restrict__ cond, const int32_t* __restrict__ prob,
+                           uint32_t* out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = c < n;
+  const float r = in ? cond[c] : 0.f;
+  const uint32_t v = (in && r >= 0.f) ? __float_as_uint(r) : 0u;
+  const int p = in ? prob[c] : -1;
+  const int p0 = __shfl(p, 0);
+  if (__all(!in || p == p0)) {
+    uint32_t m = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0 && p0 >= 0 && m > 0u) atomicMax(&out[p0], m);
+  } else if (in && v > 0u) {
+    atomicMax(&out[p], v);
+  }
+}
+
+__global__ void k_zero(int64_t n, float* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.f;
+}
+
 // mode 0: set dt where dt <= 0; mode 1: t += dt, dt = CFL dx / max radius;
 // both then reset the running maximum to the ghost radii.  mode 2: cap this
 // step's dt by the CFL limit of the radii just computed (the transport and the
@@ -945,6 +970,19 @@ hipError_t launch_rho_max(mem_ctx_t c, int64_t n, const float* rho, const int32_
   (void)P;
   if (n <= 0) return hipSuccess;
   k_rho_max<<<nb(n, 256), 256, 0, s>>>(n, rho, prob, c->w_rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(int64_t n, float* x, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_zero<<<nb(n, 256), 256, 0, s>>>(n, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_cond_max(int64_t n, const float* cond, const int32_t* prob, float* out,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_cond_max<<<nb(n, 256), 256, 0, s>>>(n, cond, prob, reinterpret_cast<uint32_t*>(out));
   return hipGetLastError();
 }
 

@@ -113,6 +113,7 @@ struct mem_ctx_s {
   float* w_Mnew = nullptr;    // [cap][K]
   float* w_F = nullptr;       // [cap][K]
   float* w_rho = nullptr;     // [cap]
+  float* w_cond = nullptr;    // [cap] pivot-ratio bound of cond(H) of the cells' solves
   // second-order interface fluxes: one row per interface (cells + problems <= cap)
   float* w_hM = nullptr;      // Lax--Wendroff half-step moments [cap][K]
   float* w_hB = nullptr;      // their beta [cap][K]
@@ -178,7 +179,7 @@ hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
                              int32_t* next_list, int32_t* next_ctr, int32_t* fb_list,
                              int32_t* fb_ctr, int32_t* iters, float* resid,
                              uint32_t* status, int32_t* done_list, int32_t* done_ctr,
-                             hipStream_t s);
+                             hipStream_t s, float* cond = nullptr);
 hipError_t launch_fallback3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                             const int32_t* ctr, const float* M, const float* beta,
                             const SolveParams& p,
@@ -221,6 +222,9 @@ hipError_t launch_iface3(mem_ctx_t c, int64_t n, int P, const float* M, const fl
 hipError_t launch_fv3i(mem_ctx_t c, int64_t n, const float* M, const float* g, const int32_t* prob,
                        const int64_t* offsets, const float* dx, const float* dt, bool flic,
                        float* Mnew, hipStream_t s);
+hipError_t launch_zero(int64_t n, float* x, hipStream_t s);
+hipError_t launch_cond_max(int64_t n, const float* cond, const int32_t* prob, float* out,
+                           hipStream_t s);
 hipError_t launch_dt_cap(mem_ctx_t c, int P, const float* dx, float cfl, float* dt,
                          hipStream_t s);
 hipError_t launch_dt_update(mem_ctx_t c, int P, const float* dx, float cfl, float* t,

@@ -1,4 +1,4 @@
-"""The gauge experiment of Sec. 4 ("Gauge transformation accelerates the
+"""The gauge experiment of Sec. 4.3 ("Gauge transformation accelerates the
 convergence of optimization"), on this build's discretisation: upstream
 Maxwellians of normal shocks for Mach 2..12 (n = 1, T = 1, v = sqrt(5/3) Ma),
 solved in FP32 from the uniform start (beta_i = 0 for i >= 1) once in the

@@ -420,6 +420,43 @@ def test_flic_shock_reaches_steady_state(ctx3):
     assert thick(n_flic) < 0.85 * thick(n_llf)
 
 
+def test_cond_monitor_is_one_at_equilibrium(ctx3):
+    # a uniform Maxwellian in its Hermite gauge: H = E[phi phi^T] - E E^T is the
+    # identity on orthonormal statistics, so every LDL^T pivot is 1
+    problem = mem_inputs.shock_problem(1.0, 200, -10.0, 10.0, 2.0)
+    cm = torch.zeros(1, device=DEV)
+    batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0)
+    batch = mem.ShockBatch([0, 200], [problem["dx"]], problem["M_left"][None],
+                           problem["M_right"][None], problem["g_left"][None],
+                           problem["g_right"][None], device=DEV, cond_max=cm)
+    ctx3.step(batch, Md, bd, gd, t, dt, 3)
+    torch.cuda.synchronize()
+    print(f"\n[cond] equilibrium bound {cm.item():.7f}")
+    assert cm.item() == pytest.approx(1.0, abs=1e-4)
+
+
+def test_cond_monitor_bounds_the_oracle_condition_number(ctx3):
+    # the pivot ratio bounds cond(H) from below; the oracle computes cond(H)
+    # exactly (eigenvalues of the covariance block at each cell's solution)
+    args = (3.0, 240, -12.0, 12.0, 3.0)
+    problem = mem_inputs.shock_problem(*args)
+    cm = torch.zeros(1, device=DEV)
+    _, Md, bd, gd, t, dt, _ = _gpu_shock(problem, ctx3, 0)
+    batch = mem.ShockBatch([0, 240], [problem["dx"]], problem["M_left"][None],
+                           problem["M_right"][None], problem["g_left"][None],
+                           problem["g_right"][None], device=DEV, cond_max=cm)
+    ctx3.step(batch, Md, bd, gd, t, dt, 8)
+    torch.cuda.synchronize()
+    ora = kinetics.ShockSolver(*args, nodes_1d=12, newton={"want_cond": True})
+    conds = []
+    for _ in range(8):
+        ora.step()
+        conds.append(float(np.max(ora.last_solve["cond"])))
+    exact = max(conds)
+    print(f"\n[cond] GPU bound {cm.item():.1f}, oracle max cond(H) {exact:.1f}")
+    assert exact / 20.0 <= cm.item() <= 1.05 * exact
+
+
 def test_strong_shock_stays_finite_and_conservative(ctx3):
     """Mach 8: cells inside the layer are not representable on the 12^3 rule and
     step with their Maxwellian (MEM_ST_MAXWELL_FLUX).  The state must stay
