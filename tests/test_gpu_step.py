@@ -172,8 +172,10 @@ def test_shock_steps_match_oracle(ctx3):
     assert not np.any(st & (mem.ST_NONFINITE | mem.ST_NONREALIZABLE | mem.ST_LAMBDA_FAIL))
 
 
-def test_ragged_batch_runs_and_matches_single(ctx3):
+@pytest.mark.parametrize("scheme", ["llf", "lw", "flic"])
+def test_ragged_batch_runs_and_matches_single(ctx3, scheme):
     # three problems of uneven length; each must equal the same problem run alone
+    # (for LW and FLIC this covers the interface numbering across problems)
     probs = [mem_inputs.shock_problem(m, nc, -0.5 * nc, 0.5 * nc, 10.0)
              for m, nc in ((1.5, 37), (4.0, 64), (2.5, 101))]
     counts = [p["M"].shape[0] for p in probs]
@@ -184,10 +186,12 @@ def test_ragged_batch_runs_and_matches_single(ctx3):
     ctx3.gauge(Md, None, gd)
     bd = dev(f32(mem_inputs.maxwellian_beta(M.shape[0], 35, Md[:, 0].cpu().numpy())))
     hist = torch.zeros(9, dtype=torch.int64, device=DEV)
+    cm = torch.zeros(3, device=DEV)
     batch = mem.ShockBatch(off, [p["dx"] for p in probs], np.stack([p["M_left"] for p in probs]),
                            np.stack([p["M_right"] for p in probs]),
                            np.stack([p["g_left"] for p in probs]),
-                           np.stack([p["g_right"] for p in probs]), device=DEV, iter_hist=hist)
+                           np.stack([p["g_right"] for p in probs]), device=DEV, iter_hist=hist,
+                           flux_scheme=scheme, cond_max=cm)
     t = torch.zeros(3, device=DEV)
     dt = torch.zeros(3, device=DEV)
     ctx3.step(batch, Md, bd, gd, t, dt, 5)
@@ -196,14 +200,20 @@ def test_ragged_batch_runs_and_matches_single(ctx3):
     h = hist.cpu().numpy()
     assert h.sum() == 5 * M.shape[0], h
     assert h[0] == 0, h   # every valid cell takes at least one Newton direction
-    print(f"[ragged] Newton iterations per cell-step: {h.tolist()}")
+    print(f"\n[ragged {scheme}] Newton iterations per cell-step: {h.tolist()}, "
+          f"cond bounds {cm.cpu().tolist()}")
     for k, p in enumerate(probs):
-        b1, M1, b1d, g1, t1, dt1, _ = _gpu_shock(p, ctx3, 0)
+        _, M1, b1d, g1, t1, dt1, _ = _gpu_shock(p, ctx3, 0)
+        c1 = torch.zeros(1, device=DEV)
+        b1 = mem.ShockBatch([0, counts[k]], [p["dx"]], p["M_left"][None], p["M_right"][None],
+                            p["g_left"][None], p["g_right"][None], device=DEV,
+                            flux_scheme=scheme, cond_max=c1)
         ctx3.step(b1, M1, b1d, g1, t1, dt1, 5)
         torch.cuda.synchronize()
         sl = slice(off[k], off[k + 1])
         assert torch.allclose(Md[sl], M1, rtol=1e-5, atol=1e-6), k
         assert t[k].item() == pytest.approx(t1.item(), rel=1e-6)
+        assert cm[k].item() == pytest.approx(c1.item(), rel=1e-5), k
 
 
 def test_graph_step_matches_eager(ctx3):
