@@ -40,7 +40,7 @@ bool dalloc(T*& p, size_t count) {
 }
 
 void free_workspace(mem_ctx_t c) {
-  dfree(c->w_S); dfree(c->w_Sx); dfree(c->w_dbeta); dfree(c->w_logZ); dfree(c->w_L);
+  dfree(c->w_S); dfree(c->w_S5); dfree(c->w_dbeta); dfree(c->w_logZ); dfree(c->w_L);
   dfree(c->w_alpha); dfree(c->w_gdot); dfree(c->w_resid); dfree(c->w_iters);
   dfree(c->w_status);
   for (auto& l : c->w_list) dfree(l);
@@ -273,7 +273,7 @@ mem_err_t mem_reserve(mem_ctx_t c, int64_t max_cells, int32_t max_problems) {
   if (max_cells > c->cap_cells) {
     const size_t n = (size_t)max_cells;
     free_workspace(c);
-    bool ok = dalloc(c->w_S, n * NCOL) && dalloc(c->w_Sx, n * NCOL) && dalloc(c->w_dbeta, n * 36) &&
+    bool ok = dalloc(c->w_S, n * NCOL) && dalloc(c->w_S5, n * NC5) && dalloc(c->w_dbeta, n * 36) &&
               dalloc(c->w_logZ, n) && dalloc(c->w_L, n) && dalloc(c->w_alpha, n) &&
               dalloc(c->w_gdot, n) && dalloc(c->w_resid, n) && dalloc(c->w_iters, n) &&
               dalloc(c->w_status, n) && dalloc(c->w_list[0], n) && dalloc(c->w_list[1], n) &&

@@ -900,11 +900,11 @@ hipError_t launch_flux3(mem_ctx_t c, int64_t n, const float* beta, const float* 
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (want_lam) {
-    e = launch_assemble5(c, n, beta, c->w_Sx, s);  // S5 rows of NC5 floats
+    e = launch_assemble5(c, n, beta, c->w_S5, s);
     if (e != hipSuccess) return e;
     double um = 0.0;
     for (int p = 0; p < c->Q; ++p) um = fmax(um, fabs(c->h_nodes[(size_t)p * 3]));
-    k_eig3<<<nb(n, EIG_WAVES), 256, 0, s>>>(n, c->w_S, c->w_Sx, c->d_ux_src, c->d_ux_w, g,
+    k_eig3<<<nb(n, EIG_WAVES), 256, 0, s>>>(n, c->w_S, c->w_S5, c->d_ux_src, c->d_ux_w, g,
                                             (float)um, out, radius_only ? 1 : 0, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

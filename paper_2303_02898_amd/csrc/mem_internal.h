@@ -90,7 +90,7 @@ struct mem_ctx_s {
   int64_t cap_cells = 0;
   int32_t cap_problems = 0;
   float* w_S = nullptr;       // [cap][NCOL]
-  float* w_Sx = nullptr;      // [cap][NCOL]
+  float* w_S5 = nullptr;      // [cap][NC5] degree-5 columns (characteristic speeds)
   float* w_dbeta = nullptr;   // [cap][36]
   float* w_logZ = nullptr;    // [cap]
   float* w_L = nullptr;
