@@ -1032,35 +1032,44 @@ __device__ __forceinline__ dfl df_norm(dfl a) {
 // t1[a * n + k] = h_a(x_k) (a = 0..4), t1[5 * n + k] = lw_k.
 // list / ctr may be null (cells 0 .. ncell - 1); racc and out_list may be
 // null; G row stride gst (36 for the refinement workspace, K for callers).
-template <int NW>  // wavefronts per cell: 1 for throughput, 4 for the latency of small launches
-__global__ __launch_bounds__(64 * NW) void k_accurate3(
+// CPB cells per workgroup of NTH threads: (1, 256) for the latency of small
+// launches, (1, 64) and (4, 576) for throughput -- four cells on nine waves give
+// each of the 4 x 144 node pairs of a 12-point rule its own lane.
+template <int CPB, int NTH>
+__global__ __launch_bounds__(NTH) void k_accurate3(
     const float2* __restrict__ t1, int n, const int32_t* __restrict__ list,
     const int32_t* __restrict__ ctr, int64_t ncell, const float* __restrict__ M,
     const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ Gacc,
     int gst, float* __restrict__ racc, float tol, int32_t* out_list, int32_t* out_ctr) {
 #pragma clang fp contract(off)
   const int64_t count = ctr ? (int64_t)(*ctr) : ncell;
-  const int64_t slot = blockIdx.x;
-  if (slot >= count) return;
-  constexpr int NTH = 64 * NW;
+  const int64_t slot0 = (int64_t)blockIdx.x * CPB;
+  if (slot0 >= count) return;
+  const int nc = (int)(count - slot0 < CPB ? count - slot0 : CPB);  // cells of this workgroup
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int64_t cell = list ? (int64_t)list[slot] : slot;
   auto sync = [] {
-    if constexpr (NW > 1) __syncthreads();
+    if constexpr (NTH > 64) __syncthreads();
     else __builtin_amdgcn_wave_barrier();
   };
+  __shared__ int64_t scell[CPB];
+  if (tid < nc) scell[tid] = list ? (int64_t)list[slot0 + tid] : slot0 + tid;
   extern __shared__ float2 dyn[];
-  float2* sU = dyn;               // [n][15]  U, later R
-  float2* sV = dyn + n * NBC;     // [n*n][5] V, later P
-  float2* sT = sV + n * n * 5;    // [6][n]   the 1D tables
+  // per cell: U (later R) [n][15] and V (later P) [n*n][5]; then the 1D tables
+  const int per = n * NBC + n * n * 5;
+  float2* sT = dyn + CPB * per;  // [6][n]
+  auto sU = [&](int q) { return dyn + q * per; };
+  auto sV = [&](int q) { return dyn + q * per + n * NBC; };
   for (int t = tid; t < 6 * n; t += NTH) sT[t] = t1[t];
   sync();
   auto H = [&](int a, int k) -> dfl { const float2 v = sT[a * n + k]; return {v.x, v.y}; };
 
   // U[i][b,c] = sum_a beta_abc h_a(x_i)
-  for (int t = tid; t < n * NBC; t += NTH) {
-    const int i = t / NBC, bc = t % NBC;
+  const int nu = n * NBC;
+  for (int t = tid; t < nc * nu; t += NTH) {
+    const int q = t / nu, tt = t - q * nu;
+    const int64_t cell = scell[q];
+    const int i = tt / NBC, bc = tt % NBC;
     int m = 0;
     while (tri(m + 1) <= bc) ++m;
     const int c = bc - tri(m), b = m - c;
@@ -1070,28 +1079,34 @@ __global__ __launch_bounds__(64 * NW) void k_accurate3(
       const float bk = k == 0 ? 0.f : beta[cell * K3 + k];  // beta_0 enters as log Z
       df_acc1(u, bk, H(a, i));
     }
-    sU[t] = make_float2(u.h, u.l);
+    sU(q)[tt] = make_float2(u.h, u.l);
   }
   sync();
   // V[i][j][c] = sum_b U[i][b,c] h_b(x_j)
-  for (int t = tid; t < n * n * 5; t += NTH) {
-    const int ij = t / 5, c = t % 5, i = ij / n, j = ij % n;
+  const int nv = n * n * 5;
+  for (int t = tid; t < nc * nv; t += NTH) {
+    const int q = t / nv, tt = t - q * nv;
+    const int ij = tt / 5, c = tt % 5, i = ij / n, j = ij % n;
+    const float2* U = sU(q);
     dfl v = {0.f, 0.f};
     for (int b = 0; b <= 4 - c; ++b) {
-      const float2 u = sU[i * NBC + tri(b + c) + c];
+      const float2 u = U[i * NBC + tri(b + c) + c];
       df_acc(v, {u.x, u.y}, H(b, j));
     }
-    sV[t] = make_float2(v.h, v.l);
+    sV(q)[tt] = make_float2(v.h, v.l);
   }
   sync();
-  // exponent, sigma and P[i][j][c] = sum_l sigma h_c(x_l); lane <-> (i, j)
-  const float lz = logZ[cell];
-  for (int q = tid; q < n * n; q += NTH) {
-    const int i = q / n, j = q % n;
+  // exponent, sigma and P[i][j][c] = sum_l sigma h_c(x_l); thread <-> (cell, i, j)
+  const int np = n * n;
+  for (int t = tid; t < nc * np; t += NTH) {
+    const int q = t / np, qq = t - q * np;
+    const int i = qq / n, j = qq % n;
+    float2* Vq = sV(q);
+    const float lz = logZ[scell[q]];
     dfl V[5], P[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      const float2 v = sV[q * 5 + c];
+      const float2 v = Vq[qq * 5 + c];
       V[c] = {v.x, v.y};
       P[c] = {0.f, 0.f};
     }
@@ -1111,24 +1126,30 @@ __global__ __launch_bounds__(64 * NW) void k_accurate3(
       for (int c = 0; c < 5; ++c) df_acc1(P[c], w, H(c, l));
     }
 #pragma unroll
-    for (int c = 0; c < 5; ++c) sV[q * 5 + c] = make_float2(P[c].h, P[c].l);
+    for (int c = 0; c < 5; ++c) Vq[qq * 5 + c] = make_float2(P[c].h, P[c].l);
   }
   sync();
   // R[i][b,c] = sum_j P[i][j][c] h_b(x_j)
-  for (int t = tid; t < n * NBC; t += NTH) {
-    const int i = t / NBC, bc = t % NBC;
+  for (int t = tid; t < nc * nu; t += NTH) {
+    const int q = t / nu, tt = t - q * nu;
+    const int i = tt / NBC, bc = tt % NBC;
     int m = 0;
     while (tri(m + 1) <= bc) ++m;
     const int c = bc - tri(m), b = m - c;
+    const float2* Pq = sV(q);
     dfl r = {0.f, 0.f};
     for (int j = 0; j < n; ++j) {
-      const float2 pv = sV[(i * n + j) * 5 + c];
+      const float2 pv = Pq[(i * n + j) * 5 + c];
       df_acc(r, {pv.x, pv.y}, H(b, j));
     }
-    sU[t] = make_float2(r.h, r.l);
+    sU(q)[tt] = make_float2(r.h, r.l);
   }
   sync();
-  if (tid >= 64) return;  // the quotients and the reduction stay on the first wave
+  // wave q finishes cell q: the quotients and the reduction
+  const int q = tid >> 6;
+  if (q >= nc) return;
+  const int64_t cell = scell[q];
+  const float2* R = sU(q);
   // E_abc = sum_i R[i][b,c] h_a(x_i) on lane k = bidx3(a, b, c)
   dfl E = {0.f, 0.f};
   if (lane < K3) {
@@ -1139,7 +1160,7 @@ __global__ __launch_bounds__(64 * NW) void k_accurate3(
     while (tri(m + 1) <= rr) ++m;
     const int c = rr - tri(m), b = m - c, a = t - m;
     for (int i = 0; i < n; ++i) {
-      const float2 rv = sU[i * NBC + tri(m) + c];
+      const float2 rv = R[i * NBC + tri(m) + c];
       df_acc(E, {rv.x, rv.y}, H(a, i));
     }
   }
@@ -1357,33 +1378,39 @@ hipError_t launch_fallback3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
 // per thread): the grid is too small to fill the chip, so latency decides.
 constexpr int64_t ACC_WIDE_BELOW = 16384;
 
+// Variant choice: one cell on four waves for small launches (latency), four
+// cells on nine waves for large ones when the rule has 12 points (every lane of
+// the exponent phase busy), one cell per wave otherwise.
+static hipError_t accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
+                            const int32_t* ctr, const float* M, const float* beta, float* G,
+                            int gst, float* racc, float tol, int32_t* out_list, int32_t* out_ctr,
+                            hipStream_t s) {
+  if (grid_cells <= 0) return hipSuccess;
+  const int n = c->n1d;
+  const size_t per = (size_t)(n * NBC + n * n * 5) * sizeof(float2);
+  const size_t tab = (size_t)6 * n * sizeof(float2);
+  if (grid_cells < ACC_WIDE_BELOW)
+    k_accurate3<1, 256><<<(unsigned)grid_cells, 256, per + tab, s>>>(
+        c->d_t1, n, list, ctr, grid_cells, M, beta, c->w_logZ, G, gst, racc, tol, out_list, out_ctr);
+  else if (n == 12)
+    k_accurate3<4, 576><<<(unsigned)nblocks(grid_cells, 4), 576, 4 * per + tab, s>>>(
+        c->d_t1, n, list, ctr, grid_cells, M, beta, c->w_logZ, G, gst, racc, tol, out_list, out_ctr);
+  else
+    k_accurate3<1, 64><<<(unsigned)grid_cells, 64, per + tab, s>>>(
+        c->d_t1, n, list, ctr, grid_cells, M, beta, c->w_logZ, G, gst, racc, tol, out_list, out_ctr);
+  return hipGetLastError();
+}
+
 hipError_t launch_accurate3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
                            const float* M, const float* beta, float tol, int32_t* out_list,
                            int32_t* out_ctr, hipStream_t s) {
-  if (grid_cells <= 0) return hipSuccess;
-  const size_t lds = (size_t)(c->n1d * NBC + c->n1d * c->n1d * 5 + 6 * c->n1d) * sizeof(float2);
-  if (grid_cells < ACC_WIDE_BELOW)
-    k_accurate3<4><<<(unsigned)grid_cells, 256, lds, s>>>(c->d_t1, c->n1d, list, ctr, grid_cells,
-                                                          M, beta, c->w_logZ, c->w_Gacc, 36,
-                                                          c->w_racc, tol, out_list, out_ctr);
-  else
-    k_accurate3<1><<<(unsigned)grid_cells, 64, lds, s>>>(c->d_t1, c->n1d, list, ctr, grid_cells,
-                                                         M, beta, c->w_logZ, c->w_Gacc, 36,
-                                                         c->w_racc, tol, out_list, out_ctr);
-  return hipGetLastError();
+  return accurate3(c, grid_cells, list, ctr, M, beta, c->w_Gacc, 36, c->w_racc, tol, out_list,
+                   out_ctr, s);
 }
 
 hipError_t launch_moment_residual3(mem_ctx_t c, int64_t n, const float* M, const float* beta,
                                    float* G, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const size_t lds = (size_t)(c->n1d * NBC + c->n1d * c->n1d * 5 + 6 * c->n1d) * sizeof(float2);
-  if (n < ACC_WIDE_BELOW)
-    k_accurate3<4><<<(unsigned)n, 256, lds, s>>>(c->d_t1, c->n1d, nullptr, nullptr, n, M, beta,
-                                                 c->w_logZ, G, K3, nullptr, 0.f, nullptr, nullptr);
-  else
-    k_accurate3<1><<<(unsigned)n, 64, lds, s>>>(c->d_t1, c->n1d, nullptr, nullptr, n, M, beta,
-                                                c->w_logZ, G, K3, nullptr, 0.f, nullptr, nullptr);
-  return hipGetLastError();
+  return accurate3(c, n, nullptr, nullptr, M, beta, G, K3, nullptr, 0.f, nullptr, nullptr, s);
 }
 
 hipError_t launch_refine3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, const int32_t* ctr,
