@@ -29,7 +29,12 @@ def fluxes(beta, g, nodes, Phi, logw):
 
 
 def char_speeds(beta, g, nodes, Phi, logw):
-    """(lambda_min, lambda_max) per cell, physical units."""
+    """(lambda_min, lambda_max) per cell, physical units.
+
+    Where B is not positive definite in FP64 (sigma concentrated on too few
+    nodes) the eigenvalues are undefined; the cell then takes the bound
+    |mu| <= max_p |u_x,p| that every eigenvalue of the pencil obeys, as the GPU
+    path does (its MEM_ST_LAMBDA_FAIL)."""
     beta = np.asarray(beta, dtype=np.float64)
     g = np.asarray(g, dtype=np.float64)
     sig = _maxent.sigma(beta, Phi, logw)
@@ -40,9 +45,14 @@ def char_speeds(beta, g, nodes, Phi, logw):
     for c in range(C):
         B = (Phi * sig[c][:, None]).T @ Phi
         Cx = (Phi * (sig[c] * ux)[:, None]).T @ Phi
-        mu = scipy.linalg.eigh(Cx, B, eigvals_only=True)
-        lo[c] = g[c, 0] + g[c, 1] * mu[0]
-        hi[c] = g[c, 0] + g[c, 1] * mu[-1]
+        try:
+            mu = scipy.linalg.eigh(Cx, B, eigvals_only=True)
+            m0, m1 = mu[0], mu[-1]
+        except np.linalg.LinAlgError:
+            m1 = np.max(np.abs(ux))
+            m0 = -m1
+        lo[c] = g[c, 0] + g[c, 1] * m0
+        hi[c] = g[c, 0] + g[c, 1] * m1
     return lo, hi
 
 

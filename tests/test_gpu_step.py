@@ -216,6 +216,45 @@ def test_ragged_batch_runs_and_matches_single(ctx3, scheme):
         assert cm[k].item() == pytest.approx(c1.item(), rel=1e-5), k
 
 
+@pytest.mark.parametrize("scheme", ["llf", "lw", "flic"])
+def test_tiny_problems_match_oracle(ctx3, scheme):
+    # degenerate problems in one batch: one cell (both interfaces touch a ghost,
+    # the limiter's far neighbour is the ghost too), two, three and five cells;
+    # each against the oracle's run of the same problem.  The half-step states of
+    # such coarse grids sit far from the cells' beta: a budget of 40 Newton
+    # iterations lets every solve converge, as the oracle's do.
+    sizes, mach = (1, 2, 3, 5), 2.0
+    probs = [mem_inputs.shock_problem(mach, nc, -0.5 * nc, 0.5 * nc, 4.0) for nc in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    M = np.concatenate([p["M"] for p in probs])
+    g = np.concatenate([p["g"] for p in probs])
+    Md, gd = dev(f32(M)), dev(f32(g))
+    ctx3.gauge(Md, None, gd)
+    bd = dev(f32(mem_inputs.maxwellian_beta(M.shape[0], 35, Md[:, 0].cpu().numpy())))
+    batch = mem.ShockBatch(off, [p["dx"] for p in probs], np.stack([p["M_left"] for p in probs]),
+                           np.stack([p["M_right"] for p in probs]),
+                           np.stack([p["g_left"] for p in probs]),
+                           np.stack([p["g_right"] for p in probs]), device=DEV,
+                           flux_scheme=scheme, newton_per_step=40)
+    t = torch.zeros(len(sizes), device=DEV)
+    dt = torch.zeros(len(sizes), device=DEV)
+    n_steps = 4
+    ctx3.step(batch, Md, bd, gd, t, dt, n_steps)
+    torch.cuda.synchronize()
+    Mg = Md.cpu().numpy().astype(np.float64)
+    gg = gd.cpu().numpy().astype(np.float64)
+    for k, nc in enumerate(sizes):
+        ora = kinetics.ShockSolver(mach, nc, -0.5 * nc, 0.5 * nc, 4.0, nodes_1d=12, scheme=scheme)
+        dts = [ora.step() for _ in range(n_steps)]
+        assert t[k].item() == pytest.approx(sum(dts), rel=1e-5), k
+        sl = slice(off[k], off[k + 1])
+        mg = kinetics.macroscopic(Mg[sl], gg[sl])
+        mo = kinetics.macroscopic(ora.M, ora.g)
+        err = max(np.max(np.abs(mg[key] - mo[key]) / np.abs(mo[key])) for key in ("n", "v", "T"))
+        print(f"\n[tiny {scheme}] {nc} cells: n, v, T rel err {err:.2e}")
+        assert err < 1e-4, (k, err)
+
+
 def test_graph_step_matches_eager(ctx3):
     # the captured time step, replayed call after call with the program's own
     # work and synchronisations in between, reproduces the plain launches bit for bit
