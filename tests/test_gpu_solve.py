@@ -340,3 +340,63 @@ def test_moment_residual_matches_fp64(ctx3, rule3):
     G2 = ctx3.moment_residual(dev(M), b2).abs().max(dim=1).values
     conv = (st & mem.ST_CONVERGED) != 0
     assert torch.allclose(G2[conv], resid[conv], rtol=1e-2, atol=2e-7)
+
+
+@pytest.mark.parametrize("n1d", [8, 16])
+def test_other_rules_match_oracle(n1d):
+    """The generic paths for rules other than 12 points per axis (line search
+    without the unrolled node loop, the one-cell-per-wave compensated pass of
+    large launches, the tables, the degree-5 speed columns) against the oracle
+    on the same rule: a Mott-Smith solve, fluxes and speeds, and the residual of
+    a 16,384-cell batch on sampled cells."""
+    ctx = mem.Context(3, n1d)
+    try:
+        nodes, w = quadrature.tensor_rule(n1d, 3)
+        rule = dict(nodes=nodes, w=w, logw=quadrature.lebesgue_log_weights(nodes, w),
+                    Phi=basis.evaluate(nodes, 3))
+        C = 160
+        cells = mem_inputs.mott_smith_cells(C, mach_lo=1.5, mach_hi=4.0, config=2, replica=7)
+        M = f32(cells["M"])
+        b0 = f32(mem_inputs.maxwellian_beta(C, 35, M[:, 0]))
+        bg = dev(b0)
+        iters, resid, status = ctx.solve(dev(M), bg)
+        torch.cuda.synchronize()
+        st = status.cpu().numpy()
+        ref = maxent.newton_solve(M, b0, rule["Phi"], rule["logw"])
+        good = _split_by_oracle(st, ref, f"{n1d}^3")
+        conv = good & ((st & mem.ST_CONVERGED) != 0)
+        beta = bg.cpu().numpy().astype(np.float64)
+        berr = np.max(np.abs(beta[conv] - ref["beta"][conv]), axis=1) / np.maximum(
+            1.0, np.max(np.abs(ref["beta"][conv]), axis=1))
+        r64 = maxent.moment_residual(beta[conv], M[conv], rule["Phi"], rule["logw"])
+        print(f"\n[{n1d}^3] converged {conv.sum()}/{C}, max beta err {berr.max():.2e}, "
+              f"max FP64 residual {r64.max():.2e}")
+        assert berr.max() <= 1e-4 and r64.max() <= 1e-5
+        # fluxes and speeds at the solutions, each cell in its own Hermite gauge
+        g = np.tile([0.3, 1.1, 0.9], (int(conv.sum()), 1))
+        F, lam = ctx.flux(dev(beta[conv]), dev(g))
+        torch.cuda.synchronize()
+        from oracle import flux as oflux
+        Fo = oflux.fluxes(beta[conv], g, rule["nodes"], rule["Phi"], rule["logw"])
+        lo, hi = oflux.char_speeds(beta[conv], g, rule["nodes"], rule["Phi"], rule["logw"])
+        scale = beta[conv][:, :1] * (np.abs(g[:, :1]) + g[:, 1:2])
+        ef = np.max(np.abs(F.cpu().numpy() - Fo) / scale)
+        el = np.max(np.abs(lam.cpu().numpy() - np.stack([lo, hi], 1)) / np.abs(np.stack([lo, hi], 1)))
+        print(f"[{n1d}^3] flux rel err {ef:.2e}, speeds rel err {el:.2e}")
+        assert ef <= 1e-5 and el <= 1e-4
+        # a launch large enough for the throughput variant of the compensated pass
+        big = 16384
+        Mb = np.tile(M, (big // C + 1, 1))[:big]
+        bb = np.tile(beta.astype(np.float32), (big // C + 1, 1))[:big]
+        G = ctx.moment_residual(dev(Mb), dev(bb)).cpu().numpy().astype(np.float64)
+        sel = np.arange(0, big, 997)
+        sig = maxent.sigma(bb[sel].astype(np.float64), rule["Phi"], rule["logw"])
+        E = sig @ rule["Phi"]
+        G_o = E / E[:, :1] - Mb[sel] / Mb[sel][:, :1]
+        G_o[:, 0] = 0.0
+        bound = 2.0 ** -20 * ((sig @ np.abs(rule["Phi"])) + np.abs(E)) / E[:, :1] + 1e-12
+        err = np.abs(G[sel] - G_o)
+        print(f"[{n1d}^3] residual of {big} cells, sampled: err/bound max {np.max(err / bound):.3f}")
+        assert np.all(err <= bound + 2.0 ** -23 * np.abs(G_o))
+    finally:
+        ctx.close()
