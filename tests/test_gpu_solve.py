@@ -342,7 +342,7 @@ def test_moment_residual_matches_fp64(ctx3, rule3):
     assert torch.allclose(G2[conv], resid[conv], rtol=1e-2, atol=2e-7)
 
 
-@pytest.mark.parametrize("n1d", [8, 16])
+@pytest.mark.parametrize("n1d", [8, 16, 20])
 def test_other_rules_match_oracle(n1d):
     """The generic paths for rules other than 12 points per axis (line search
     without the unrolled node loop, the one-cell-per-wave compensated pass of
