@@ -84,7 +84,7 @@ typedef enum {
 
 typedef struct {
   int32_t dim;          /* 1 or 3                                                      */
-  int32_t n_nodes_1d;   /* Gauss--Hermite nodes per velocity axis (2..64)              */
+  int32_t n_nodes_1d;   /* Gauss--Hermite nodes per velocity axis (2..64 in 1D, 2..32 in 3D) */
   int32_t prec;         /* mem_prec_t used by the Newton Hessian assembly              */
   int32_t reserved;     /* must be 0                                                   */
 } mem_config_t;
@@ -177,7 +177,9 @@ typedef struct {
 MEM_API mem_err_t mem_create(const mem_config_t* cfg, mem_ctx_t* out);
 MEM_API mem_err_t mem_destroy(mem_ctx_t ctx);
 /* Pre-size the per-cell workspace for up to max_cells cells and max_problems
- * problems (graph- and timing-safe calls afterwards).  Allocates. */
+ * problems (graph- and timing-safe calls afterwards).  mem_step needs rows for
+ * n_cells + n_problems (the cells and every interface) and grows the workspace
+ * itself, before any capture, when they are missing.  Allocates. */
 MEM_API mem_err_t mem_reserve(mem_ctx_t ctx, int64_t max_cells, int32_t max_problems);
 MEM_API const char* mem_strerror(mem_err_t err);
 /* Detail of the last error on this context (host string, valid until the next call). */
