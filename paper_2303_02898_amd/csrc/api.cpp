@@ -252,7 +252,8 @@ mem_err_t mem_destroy(mem_ctx_t c) {
   (void)hipDeviceSynchronize();
   free_workspace(c);
   free_problems(c);
-  dfree(c->d_phiA); dfree(c->d_psi); dfree(c->d_psi5); dfree(c->d_ux_src); dfree(c->d_ux_w);
+  dfree(c->d_phiA); dfree(c->d_psi); dfree(c->d_psi5); dfree(c->d_psiF); dfree(c->d_ux_src);
+  dfree(c->d_ux_w);
   dfree(c->d_tab1);
   dfree(c->d_t1);
   dfree(c->d_psi_hi); dfree(c->d_psi_lo); dfree(c->d_phiA_m); dfree(c->d_psiF_m);

@@ -1323,12 +1323,13 @@ hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
   return hipGetLastError();
 }
 
-hipError_t launch_assemble5(mem_ctx_t c, int64_t n, const float* beta, float* S5, hipStream_t s) {
+hipError_t launch_assemble5(mem_ctx_t c, int64_t n, const float* beta, const float* table,
+                            float* S5, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int ntile = (int)nblocks(n, TILE);
   const int nsplit = assembly_splits(c, ntile, c->ngroups);
   k_assemble3<NC5 / 64><<<(unsigned)(ntile * nsplit), 256, 0, s>>>(
-      c->d_phiA, c->d_psi5, c->ngroups, nullptr, nullptr, n, beta, c->w_logZ, S5, ntile, nsplit,
+      c->d_phiA, table, c->ngroups, nullptr, nullptr, n, beta, c->w_logZ, S5, ntile, nsplit,
       c->w_Sp);
   if (nsplit > 1)
     k_sum_splits<NC5><<<(unsigned)nblocks((int64_t)ntile * TILE * (NC5 / 4), 256), 256, 0, s>>>(

@@ -138,18 +138,21 @@ __global__ __launch_bounds__(128) void k_gauge3(int64_t n, float* __restrict__ M
 // ---- fluxes from the assembled moments --------------------------------------------
 // F_i = n (w E[phi_i] + s_x E[u_bar_x phi_i]); phi_1 = u_bar_x so E[u_bar_x phi_i]
 // is the (1, i) pair column of S.
+// F_i = n (w E[phi_i] + s_x E[u_x phi_i]) from rows of S (flux_rows = 0: pair
+// columns (0, i) and (1, i), phi_(100) = u_x) or of the 128-column flux operand
+// (flux_rows = 1: E[phi_i] in columns 0..34, E[u_x phi_i] in 35..69).
 __global__ void k_flux3(int64_t n, const float* __restrict__ S, const float* __restrict__ beta,
-                        const float* __restrict__ g, float* __restrict__ F) {
+                        const float* __restrict__ g, float* __restrict__ F, int flux_rows) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  const float* Sc = S + c * NCOL;
+  const float* Sc = S + c * (flux_rows ? NC5 : NCOL);
   const float inv0 = 1.f / Sc[0];
   const float nn = beta[c * K3];
   const float w = g[c * 3], sx = g[c * 3 + 1];
   for (int i = 0; i < K3; ++i) {
     const float e = Sc[i] * inv0;
-    const float x = (i == 0 ? Sc[1] : Sc[pair_col(i < 1 ? i : 1, i < 1 ? 1 : i)]) * inv0;
-    F[c * K3 + i] = nn * (w * e + sx * x);
+    const int xc = flux_rows ? K3 + i : (i == 0 ? 1 : pair_col(1, i));
+    F[c * K3 + i] = nn * (w * e + sx * Sc[xc] * inv0);
   }
 }
 
@@ -888,19 +891,28 @@ hipError_t launch_flux3(mem_ctx_t c, int64_t n, const float* beta, const float* 
                         float* out, bool want_lam, bool radius_only, uint32_t* status,
                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  // log Z at beta, then S = sigma . Psi (and Sx = sigma . Psi_x for the speeds)
+  // log Z at beta; then, with speeds, S = sigma . Psi and the degree-5 columns S5,
+  // without, only the 128 flux columns
   SolveParams dummy{};
   hipError_t e = launch_lse3(c, n, nullptr, nullptr, n, nullptr, const_cast<float*>(beta), false,
                              dummy, nullptr, nullptr, s);
   if (e != hipSuccess) return e;
+  if (!want_lam) {
+    // fluxes only: the 70 columns E[phi_i], E[u_x phi_i] (128-column operand)
+    if (!F) return hipSuccess;
+    e = launch_assemble5(c, n, beta, c->d_psiF, c->w_S5, s);
+    if (e != hipSuccess) return e;
+    k_flux3<<<nb(n, 128), 128, 0, s>>>(n, c->w_S5, beta, g, F, 1);
+    return hipGetLastError();
+  }
   e = launch_assemble3(c, n, nullptr, nullptr, n, beta, c->d_psi, c->w_S, s);
   if (e != hipSuccess) return e;
   if (F) {
-    k_flux3<<<nb(n, 128), 128, 0, s>>>(n, c->w_S, beta, g, F);
+    k_flux3<<<nb(n, 128), 128, 0, s>>>(n, c->w_S, beta, g, F, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (want_lam) {
-    e = launch_assemble5(c, n, beta, c->w_S5, s);
+  {
+    e = launch_assemble5(c, n, beta, c->d_psi5, c->w_S5, s);
     if (e != hipSuccess) return e;
     double um = 0.0;
     for (int p = 0; p < c->Q; ++p) um = fmax(um, fabs(c->h_nodes[(size_t)p * 3]));

@@ -75,6 +75,7 @@ struct mem_ctx_s {
   // C = E[u_x phi phi^T] two sources and weights: src < 1024 is a column of S,
   // src >= 1024 column src - 1024 of S5 (ux_src packs src1 | src2 << 16)
   float* d_psi5 = nullptr;
+  float* d_psiF = nullptr;      // flux-only operand: phi_i (columns 0..34), u_x phi_i (35..69)
   int32_t* d_ux_src = nullptr;  // [NPAIR]
   float2* d_ux_w = nullptr;     // [NPAIR]
   // mixed precision (BF16 / FP16 hi + lo) assembly operands, 32-node groups
@@ -160,7 +161,9 @@ hipError_t launch_lse3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                        const int32_t* ctr, int64_t n, const float* M, float* beta,
                        bool line_search, const SolveParams& p, int32_t* reset_a,
                        int32_t* reset_b, hipStream_t s);
-hipError_t launch_assemble5(mem_ctx_t c, int64_t n, const float* beta, float* S5, hipStream_t s);
+// 128-column assembly (k_assemble3<2>) with the table d_psi5 or d_psiF
+hipError_t launch_assemble5(mem_ctx_t c, int64_t n, const float* beta, const float* table,
+                            float* S5, hipStream_t s);
 hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                             const int32_t* ctr, int64_t n, const float* beta,
                             const float* table, float* S, hipStream_t s);

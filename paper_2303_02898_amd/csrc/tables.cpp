@@ -328,6 +328,12 @@ void build_tables(mem_ctx_t ctx) {
     ortho_hermite(5, ctx->h_nodes[(size_t)p * 3 + 2], hz.data());
     return hx[ea[i] + 1] * hy[eb[i]] * hz[ec[i]] * ctx->h_phi[(size_t)p * K3 + j];
   }));
+  // flux-only operand: the 70 columns a flux needs (phi_(100) = u_x)
+  ctx->d_psiF = upload(operand(NC5 / 64, [&](int p, int col) -> double {
+    if (p >= Q || col >= 2 * K3) return 0.0;
+    const double f = ctx->h_phi[(size_t)p * K3 + (col % K3)];
+    return col < K3 ? f : f * ctx->h_nodes[(size_t)p * 3];
+  }));
   std::vector<int32_t> src(NPAIR);
   std::vector<float2> wts(NPAIR);
   auto scol = [&](int u, int v) { return pair_col(std::min(u, v), std::max(u, v)); };

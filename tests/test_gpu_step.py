@@ -89,6 +89,13 @@ def test_flux_and_speeds_match_oracle(ctx3, rule3):
     err = np.max(np.abs(F.cpu().numpy() - F_o) / scale)
     print(f"[flux] rel err {err:.2e}")
     assert err <= 1e-5
+    # without speeds the fluxes come from the 128-column flux operand
+    F2, none = ctx3.flux(dev(beta), dev(g), want_lam=False)
+    torch.cuda.synchronize()
+    assert none is None
+    err2 = np.max(np.abs(F2.cpu().numpy() - F_o) / scale)
+    print(f"[flux, no speeds] rel err {err2:.2e}")
+    assert err2 <= 1e-5
     lam = lam.cpu().numpy()
     ls = np.abs(g[:, 0]) + 3 * g[:, 1]
     e0 = np.max(np.abs(lam[:, 0] - lo) / ls)
@@ -253,6 +260,27 @@ def test_tiny_problems_match_oracle(ctx3, scheme):
         err = max(np.max(np.abs(mg[key] - mo[key]) / np.abs(mo[key])) for key in ("n", "v", "T"))
         print(f"\n[tiny {scheme}] {nc} cells: n, v, T rel err {err:.2e}")
         assert err < 1e-4, (k, err)
+
+
+def test_step_rejects_bad_batch_fields(ctx3):
+    # the C ABI validates the new batch fields itself (the binding's checks aside)
+    problem = mem_inputs.shock_problem(3.0, 64, -5.0, 5.0, 2.0)
+    batch, Md, bd, gd, t, dt, _ = _gpu_shock(problem, ctx3, 0)
+    M0 = Md.clone()
+    for bad in (-1, 3):
+        batch.struct.flux_scheme = bad
+        with pytest.raises(mem.MemError, match="mem_batch_t"):
+            ctx3.step(batch, Md, bd, gd, t, dt, 1)
+    assert torch.equal(Md, M0)   # nothing ran
+    with pytest.raises(ValueError):
+        mem.ShockBatch([0, 64], [problem["dx"]], problem["M_left"][None],
+                       problem["M_right"][None], problem["g_left"][None],
+                       problem["g_right"][None], device=DEV, flux_scheme="upwind")
+    with pytest.raises(ValueError):
+        mem.ShockBatch([0, 64], [problem["dx"]], problem["M_left"][None],
+                       problem["M_right"][None], problem["g_left"][None],
+                       problem["g_right"][None], device=DEV,
+                       cond_max=torch.zeros(2, device=DEV))
 
 
 def test_graph_step_matches_eager(ctx3):
