@@ -202,6 +202,8 @@ def mixed_comparison(mem, torch, dev, cells, steps, warmup):
                      "assemble_algorithmic_tflops": r["asm_tflops"],
                      "residual_max": float(G[ok].max()),
                      "residual_per_moment_max": [float(f"{v:.3g}") for v in G[ok].max(axis=0)[1:]],
+                     "residual_per_moment_p99": [float(f"{v:.3g}")
+                                                 for v in np.percentile(G[ok], 99, axis=0)[1:]],
                      "beta_vs_fp32_max": float(np.max(np.abs(beta[both] - beta32[both]).max(axis=1)
                                                       / scale))}
     return out
