@@ -283,6 +283,54 @@ def test_step_rejects_bad_batch_fields(ctx3):
                        cond_max=torch.zeros(2, device=DEV))
 
 
+def test_ragged_workload_sample_matches_oracle(ctx3):
+    # problems of the 2048-problem ragged batch itself (dx = 1, tanh thickness 10),
+    # five of its short ones spread over its Mach range, stepped together as one
+    # batch and each against the oracle's run of the same problem; the two above
+    # Mach 6.3 hold cells that both sides step with their Maxwellian.  A budget of
+    # 40 Newton iterations lets every solve converge or be certified, as the
+    # oracle's do (with 8, a cell can stop at MAXITER before its certificate and
+    # keep an unconverged beta, a different branch from the oracle's)
+    rb = mem_inputs.ragged_batch(2048)
+    picks = [518, 395, 58, 11, 115]   # Mach 1.50, 3.77, 5.74, 7.45, 9.56; 64-80 cells each
+    probs = [rb["problems"][p] for p in picks]
+    counts = [int(rb["counts"][p]) for p in picks]
+    off = np.concatenate([[0], np.cumsum(counts)])
+    M = np.concatenate([p["M"] for p in probs])
+    g = np.concatenate([p["g"] for p in probs])
+    Md, gd = dev(f32(M)), dev(f32(g))
+    ctx3.gauge(Md, None, gd)
+    bd = dev(f32(mem_inputs.maxwellian_beta(M.shape[0], 35, Md[:, 0].cpu().numpy())))
+    batch = mem.ShockBatch(off, [rb["dx"]] * len(picks), np.stack([p["M_left"] for p in probs]),
+                           np.stack([p["M_right"] for p in probs]),
+                           np.stack([p["g_left"] for p in probs]),
+                           np.stack([p["g_right"] for p in probs]), device=DEV,
+                           newton_per_step=40)
+    t = torch.zeros(len(picks), device=DEV)
+    dt = torch.zeros(len(picks), device=DEV)
+    status = torch.zeros(M.shape[0], dtype=torch.int32, device=DEV)
+    n_steps = 5
+    ctx3.step(batch, Md, bd, gd, t, dt, n_steps, status=status)
+    torch.cuda.synchronize()
+    Mg = Md.cpu().numpy().astype(np.float64)
+    gg = gd.cpu().numpy().astype(np.float64)
+    st = status.cpu().numpy()
+    for k, p in enumerate(picks):
+        nc, mach = counts[k], float(rb["mach"][p])
+        ora = kinetics.ShockSolver(mach, nc, -0.5 * nc, 0.5 * nc, 10.0, nodes_1d=12)
+        dts = [ora.step() for _ in range(n_steps)]
+        # dt = CFL dx / max speed: the FP32 speeds' tolerance (1e-4) carries over
+        assert t[k].item() == pytest.approx(sum(dts), rel=1e-4), k
+        sl = slice(off[k], off[k + 1])
+        mg = kinetics.macroscopic(Mg[sl], gg[sl])
+        mo = kinetics.macroscopic(ora.M, ora.g)
+        err = max(np.max(np.abs(mg[key] - mo[key]) / np.abs(mo[key])) for key in ("n", "v", "T"))
+        nmx = int(np.sum((st[sl] & mem.ST_MAXWELL_FLUX) != 0))
+        print(f"\n[ragged sample] Mach {mach:.2f}, {nc} cells: n, v, T rel err {err:.2e}, "
+              f"Maxwell-flux cells GPU {nmx}, oracle (last step) {int(ora.maxwell_cells.sum())}")
+        assert err < 1e-4, (k, err)
+
+
 def test_graph_step_matches_eager(ctx3):
     # the captured time step, replayed call after call with the program's own
     # work and synchronisations in between, reproduces the plain launches bit for bit
