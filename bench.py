@@ -87,9 +87,20 @@ def cpu_baseline(M, b0, n_sample):
     out = maxent.newton_solve(Ms, bs, Phi, logw, tol_grad=1e-10)
     el = time.perf_counter() - t0
     ok = int(np.sum(out["converged"]))
-    return {"value": ok / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {n_sample} cells of the same 65,536-cell batch, FP64 NumPy "
-                      f"Alg. 1 to max|G| <= 1e-10, {el:.1f} s wall"}
+    res = {"value": ok / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"first {n_sample} cells of the same 65,536-cell batch, FP64 NumPy "
+                     f"Alg. 1 to max|G| <= 1e-10, {el:.1f} s wall"}
+    # the oracle's time step beside the shock workloads: Mach-3 shock, 240 cells,
+    # 4 LLF steps after the set-up (cell-steps/s, warm solves)
+    from oracle import kinetics
+    sh = kinetics.ShockSolver(3.0, 240, -12.0, 12.0, 3.0, nodes_1d=12)
+    t0 = time.perf_counter()
+    for _ in range(4):
+        sh.step()
+    el2 = time.perf_counter() - t0
+    res["time_step"] = {"value": 240 * 4 / el2, "unit": "cell-steps/s",
+                        "sample": f"Mach-3 shock, 240 cells, 4 LLF steps, FP64, {el2:.1f} s wall"}
+    return res
 
 
 def run_solves(mem, ctx, Md, b0d, steps, warmup, tune=True):
