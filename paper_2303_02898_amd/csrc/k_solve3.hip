@@ -563,6 +563,9 @@ __device__ __forceinline__ bool wave_chol(T (&a)[NH], T& dinv, int lane, T& dmin
     for (int i = k; i < NH; ++i) u[i] = row[i];
     const T d = u[k];
     ok = ok && (d > (T)0) && isfinite(d);
+    // the pivot is the same on every lane (read back from LDS): a failed
+    // factorisation stops here, uniformly, instead of finishing the sweep
+    if (!ok) return false;
     dmin = d < dmin ? d : dmin;
     dmax = d > dmax ? d : dmax;
     const T inv = rsq(d);
