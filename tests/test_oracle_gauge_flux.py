@@ -168,3 +168,17 @@ def test_characteristic_speeds_within_node_span(rule3):
     assert np.all(hi <= g[:, 0] + g[:, 1] * umax + 1e-9)
     assert np.all(lo >= g[:, 0] - g[:, 1] * umax - 1e-9)
     assert np.all(hi > lo)
+
+
+def test_speeds_take_the_node_span_bound_when_B_is_singular(rule3):
+    # beta that puts essentially all mass on one node: B = E[phi phi^T] has rank 1
+    # in FP64, the eigenvalues are undefined and the speeds take the bound
+    # |mu| <= max_p |u_x,p| that every eigenvalue of the pencil obeys
+    beta = np.zeros((1, 35))
+    beta[0, 0] = 1.0
+    beta[0, 1] = 400.0           # exponent 400 u_x: the largest-u_x nodes dominate
+    g = np.array([[0.5, 2.0, 1.0]])
+    lo, hi = flux.char_speeds(beta, g, rule3["nodes"], rule3["Phi"], rule3["logw"])
+    umax = np.max(np.abs(rule3["nodes"][:, 0]))
+    assert hi[0] == pytest.approx(0.5 + 2.0 * umax, rel=1e-12)
+    assert lo[0] == pytest.approx(0.5 - 2.0 * umax, rel=1e-12)

@@ -104,3 +104,14 @@ def test_order_of_accuracy_on_a_smooth_pulse(scheme, lo, hi):
     ratio = e1 / e2
     print(f"\n[{scheme}] errors {e1:.3e} {e2:.3e} ratio {ratio:.2f} (order {math.log2(ratio):.2f})")
     assert lo < ratio < hi
+
+
+@pytest.mark.parametrize("scheme", ["lw", "flic"])
+def test_uniform_equilibrium_is_stationary_second_order(scheme):
+    # Mach -> 1: one Maxwellian everywhere; the half-step states equal the cells'
+    s = kinetics.ShockSolver(1.0 + 1e-12, 12, -6.0, 6.0, 2.0, nodes_1d=8, scheme=scheme)
+    M0 = s.M.copy()
+    for _ in range(3):
+        s.step()
+    assert np.max(np.abs(s.M - M0)) < 1e-9
+    assert not np.any(s.lw_failed)
