@@ -130,3 +130,37 @@ def test_mixed_solve_matches_oracle(ctxm, rule3, config, mach):
     dr = np.abs(res[sel] - r)
     print(f"[{ctxm.prec_name} config {config}] |resid - r_fp64| max {dr.max():.2e}")
     assert np.all(dr <= 2e-7 + 0.01 * r)
+
+
+def test_mixed_precision_steps_match_oracle(ctxm):
+    """mem_step on a mixed-precision context: the cells' Newton Hessians come from
+    the hi+lo 16-bit assembly, gradients, fluxes and speeds stay FP32.  Mach-3
+    shock, 240 cells, 8 steps, against the oracle's FP64 steps."""
+    from oracle import kinetics
+    args = (3.0, 240, -12.0, 12.0, 3.0)
+    problem = mem_inputs.shock_problem(*args)
+    M = problem["M"].astype(np.float32)
+    g = problem["g"].astype(np.float32)
+    Md = torch.tensor(M, device=DEV)
+    gd = torch.tensor(g, device=DEV)
+    ctxm.gauge(Md, None, gd)
+    bd = torch.tensor(mem_inputs.maxwellian_beta(M.shape[0], 35, Md[:, 0].cpu().numpy())
+                      .astype(np.float32), device=DEV)
+    batch = mem.ShockBatch([0, M.shape[0]], [problem["dx"]], problem["M_left"][None],
+                           problem["M_right"][None], problem["g_left"][None],
+                           problem["g_right"][None], device=DEV)
+    t = torch.zeros(1, device=DEV)
+    dt = torch.zeros(1, device=DEV)
+    status = torch.zeros(M.shape[0], dtype=torch.int32, device=DEV)
+    ctxm.step(batch, Md, bd, gd, t, dt, 8, status=status)
+    torch.cuda.synchronize()
+    ora = kinetics.ShockSolver(*args, nodes_1d=12)
+    dts = [ora.step() for _ in range(8)]
+    assert t.item() == pytest.approx(sum(dts), rel=1e-5)
+    mg = kinetics.macroscopic(Md.cpu().numpy().astype(np.float64), gd.cpu().numpy().astype(np.float64))
+    mo = kinetics.macroscopic(ora.M, ora.g)
+    err = max(np.max(np.abs(mg[k] - mo[k]) / np.abs(mo[k])) for k in ("n", "v", "T"))
+    print(f"\n[{ctxm.prec_name} step] n, v, T rel err {err:.2e}")
+    assert err < 1e-4
+    st = status.cpu().numpy()
+    assert not np.any(st & (mem.ST_NONFINITE | mem.ST_NONREALIZABLE | mem.ST_LAMBDA_FAIL))
