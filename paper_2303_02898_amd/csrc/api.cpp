@@ -119,7 +119,8 @@ struct ProfScope {
 // 4/5 refinement lists.
 mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const SolveParams& p,
                   int max_iter, int poll, int refine, int32_t* iters, float* resid,
-                  uint32_t* status, hipStream_t s, float* cond = nullptr) {
+                  uint32_t* status, hipStream_t s, float* cond = nullptr,
+                  bool try_closed_start = false) {
   int32_t* ctr = c->w_ctr;
   int32_t* done = refine > 0 ? c->w_list[3] : nullptr;
   MEM_HIP(c, launch_set_ctr(ctr, 8, s));
@@ -130,22 +131,33 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
   }
   int cur = 0;
   int64_t grid = n;  // live cells never increase: the last polled count bounds the grids
+  // Cells that start at the Maxwellian of their gauge take their first direction
+  // in closed form: there sigma_p = w_p, and a rule of >= 5 points per axis
+  // integrates the degree <= 8 products exactly, so E[phi] = e_0 and H = I.  The
+  // first pass then assembles only the other cells (list 4, counter 6).
+  const bool closed_start = try_closed_start && c->n1d >= 5;
+  if (closed_start)
+    MEM_HIP(c, launch_start3(c, n, c->w_list[0], &ctr[0], M, beta, p, c->w_list[1], &ctr[1],
+                             c->w_list[4], &ctr[6], iters, resid, status, done, &ctr[3], cond, s));
   // every live cell takes one direction per pass and ends, at the latest, as
   // MAXITER at its max_iter-th: max_iter passes leave no live cell
   for (int it = 0; it < max_iter; ++it) {
     const int nxt = 1 - cur;
+    // this pass's assembly list: list 4 after a closed-form start, else the live list
+    int32_t* la = (it == 0 && closed_start) ? c->w_list[4] : c->w_list[cur];
+    int32_t* ca = (it == 0 && closed_start) ? &ctr[6] : &ctr[cur];
     {
       ProfScope ps(c, 0, s);
       if (c->prec == MEM_PREC_FP32)
-        MEM_HIP(c, launch_assemble3(c, grid, c->w_list[cur], &ctr[cur], n, beta, c->d_psi, c->w_S, s));
+        MEM_HIP(c, launch_assemble3(c, grid, la, ca, n, beta, c->d_psi, c->w_S, s));
       else
-        MEM_HIP(c, launch_assemble3m(c, grid, c->w_list[cur], &ctr[cur], n, beta, c->w_S, s));
+        MEM_HIP(c, launch_assemble3m(c, grid, la, ca, n, beta, c->w_S, s));
     }
     {
       ProfScope ps(c, 1, s);
-      MEM_HIP(c, launch_direction3(c, grid, c->w_list[cur], &ctr[cur], M, beta, p, c->w_list[nxt],
-                                   &ctr[nxt], c->w_list[2], &ctr[2], iters, resid, status, done,
-                                   &ctr[3], s, cond));
+      MEM_HIP(c, launch_direction3(c, grid, la, ca, M, beta, p, c->w_list[nxt], &ctr[nxt],
+                                   c->w_list[2], &ctr[2], iters, resid, status, done, &ctr[3], s,
+                                   cond));
     }
     MEM_HIP(c, launch_fallback3(c, grid, c->w_list[2], &ctr[2], M, beta, p, c->w_list[nxt], &ctr[nxt],
                                 iters, resid, status, done, &ctr[3], s));
@@ -278,7 +290,8 @@ mem_err_t mem_reserve(mem_ctx_t c, int64_t max_cells, int32_t max_problems) {
               dalloc(c->w_logZ, n) && dalloc(c->w_L, n) && dalloc(c->w_alpha, n) &&
               dalloc(c->w_gdot, n) && dalloc(c->w_resid, n) && dalloc(c->w_iters, n) &&
               dalloc(c->w_status, n) && dalloc(c->w_list[0], n) && dalloc(c->w_list[1], n) &&
-              dalloc(c->w_list[2], n) && dalloc(c->w_list[3], n) && dalloc(c->w_Gacc, n * 36) &&
+              dalloc(c->w_list[2], n) && dalloc(c->w_list[3], n) && dalloc(c->w_list[4], n) &&
+              dalloc(c->w_Gacc, n * 36) &&
               dalloc(c->w_racc, n) && dalloc(c->w_rbest, n) && dalloc(c->w_itbest, n) &&
               dalloc(c->w_Mnew, n * K3) && dalloc(c->w_F, n * K3) &&
               dalloc(c->w_rho, n) && dalloc(c->w_prob, n) && dalloc(c->w_code, n) &&
@@ -358,7 +371,8 @@ mem_err_t mem_maxent_solve(mem_ctx_t c, int64_t n, const float* M, float* beta,
   const int poll = opts ? opts->check_every : d.check_every;
   const int refine = opts ? opts->refine : d.refine;
   p.refine = refine;
-  return newton3(c, n, M, beta, p, p.max_iter, poll, refine, iters, resid, status, s);
+  return newton3(c, n, M, beta, p, p.max_iter, poll, refine, iters, resid, status, s, nullptr,
+                 true);
 }
 
 mem_err_t mem_dual(mem_ctx_t c, int64_t n, const float* beta, float* logZ, float* E, float* H,
@@ -470,12 +484,13 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
   mem_solve_opts_default(&dflt);
   const int refine = opts ? opts->refine : dflt.refine;
   p.refine = refine;
-  e = newton3(c, 2 * (int64_t)P, c->w_gM, c->w_gB, p, budget, 0, refine, nullptr, nullptr, nullptr, s);
+  e = newton3(c, 2 * (int64_t)P, c->w_gM, c->w_gB, p, budget, 0, refine, nullptr, nullptr, nullptr, s,
+              nullptr, true);
   if (e != MEM_OK) return e;
   MEM_HIP(c, launch_flux3(c, 2 * (int64_t)P, c->w_gB, c->w_gG, c->w_gF, c->w_gR, true, true, nullptr, s));
   MEM_HIP(c, launch_rmax_init(c, P, s));
   // solve the current state; set dt where the caller asked for one
-  e = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, s);
+  e = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, s, nullptr, true);
   if (e != MEM_OK) return e;
   MEM_HIP(c, launch_maxwell_fallback(c, n, M, beta, s));
   MEM_HIP(c, launch_flux3(c, n, beta, g, nullptr, c->w_rho, true, true, status, s));

@@ -849,6 +849,72 @@ __global__ __launch_bounds__(64 * DW) void k_direction3(
   }
 }
 
+// First Newton pass in closed form for a cell whose beta is exactly the
+// Maxwellian of its gauge (beta_(200) = beta_(020) = beta_(002) = -1/sqrt(2),
+// every other beta_i, i >= 1, zero).  Then sigma_p = w_p: the expectations are
+// Gauss--Hermite sums of polynomials of degree <= 8, exact for >= 5 points per
+// axis, so E[phi_i] = delta_i0 and H = I (orthonormal statistics).  Hence
+// G_i = -M_i/n, the Newton direction is dbeta_i = M_i/n and the decrement is
+// 1/2 |G|^2.  The outcome goes through the bookkeeping of every other
+// direction; cells of any other beta get code 3 (ordinary first assembly).
+__global__ __launch_bounds__(256) void k_start3(
+    const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
+    const float* __restrict__ M, const float* __restrict__ beta, float* __restrict__ dbeta,
+    float* __restrict__ gdot, const float* __restrict__ alpha_w, int32_t* __restrict__ iters_w,
+    uint32_t* __restrict__ status_w, float* __restrict__ resid_w, const float* __restrict__ Lval,
+    float* __restrict__ rbest_w, int32_t* __restrict__ itbest_w, SolveParams p,
+    int8_t* __restrict__ codes, float* __restrict__ S, DirOut o) {
+  const int64_t count = *ctr;
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= count) return;
+  const int64_t cell = list[slot];
+  const float* b = beta + cell * K3;
+  const float sq = -0.70710678118654752f;
+  bool maxw = true;
+#pragma unroll
+  for (int k = 1; k < K3; ++k) {
+    const bool square = k == bidx3(2, 0, 0) || k == bidx3(0, 2, 0) || k == bidx3(0, 0, 2);
+    maxw = maxw && (b[k] == (square ? sq : 0.f));
+  }
+  if (!maxw) { codes[slot] = 3; return; }
+  const float* Mc = M + cell * K3;
+  const float nn = Mc[0];
+  float r = 0.f, res = 0.f;
+#pragma unroll
+  for (int k = 1; k < K3; ++k) {
+    const float gk = -(Mc[k] / nn);
+    r = fmaxf(r, fabsf(gk));
+    res = fmaf(gk, gk, res);
+  }
+  res *= 0.5f;
+  if (!(nn > 0.f) || !isfinite(res)) r = NAN;
+  CellState cs;
+  cs.it = iters_w[cell];
+  cs.itbest = itbest_w[cell];
+  cs.st = status_w[cell];
+  cs.rbest = rbest_w[cell];
+  cs.alpha = alpha_w[cell];
+  cs.L = Lval[cell];
+  cs.bmax = 0.70710678118654752f;
+  const int code = finish_cell(cell, r, res, true, 0u, p, cs, gdot, iters_w, status_w, resid_w,
+                               rbest_w, itbest_w, o);
+  if (o.cond && isfinite(r)) o.cond[cell] = fmaxf(o.cond[cell], 1.f);
+  if (code == 1) {
+    float* db = dbeta + cell * 36;
+    db[0] = 0.f;
+#pragma unroll
+    for (int k = 1; k < K3; ++k) db[k] = Mc[k] / nn;
+  } else if (code == 2) {
+    // a refinement candidate: the refinement's Newton correction reads the
+    // cell's S row, here E[phi_i phi_j] = delta_ij exactly (the cell was never
+    // assembled in this solve)
+    float* Sc = S + cell * NCOL;
+    for (int col = 0; col < NCOL; ++col) Sc[col] = 0.f;
+    for (int k = 0; k < K3; ++k) Sc[pair_col(k, k)] = 1.f;
+  }
+  codes[slot] = (int8_t)code;
+}
+
 // Stream compaction of the per-slot outcomes of k_direction3 (0 finished,
 // 1 live, 2 refinement candidate, 3 FP64 direction) into three cell lists,
 // with one atomic per list and workgroup instead of one per cell.
@@ -1337,6 +1403,22 @@ hipError_t launch_assemble5(mem_ctx_t c, int64_t n, const float* beta, const flo
   if (nsplit > 1)
     k_sum_splits<NC5><<<(unsigned)nblocks((int64_t)ntile * TILE * (NC5 / 4), 256), 256, 0, s>>>(
         nullptr, nullptr, n, ntile, nsplit, c->w_Sp, S5);
+  return hipGetLastError();
+}
+
+hipError_t launch_start3(mem_ctx_t c, int64_t n, const int32_t* list, const int32_t* ctr,
+                         const float* M, const float* beta, const SolveParams& p,
+                         int32_t* next_list, int32_t* next_ctr, int32_t* asm_list, int32_t* asm_ctr,
+                         int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
+                         int32_t* done_ctr, float* cond, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr, cond};
+  k_start3<<<nblocks(n, 256), 256, 0, s>>>(list, ctr, M, beta, c->w_dbeta, c->w_gdot, c->w_alpha,
+                                           c->w_iters, c->w_status, c->w_resid, c->w_L,
+                                           c->w_rbest, c->w_itbest, p, c->w_code, c->w_S, o);
+  // 1: live with its direction, 2: converged (refinement), 3: first assembly
+  k_compact3<<<nblocks(n, 256), 256, 0, s>>>(list, ctr, c->w_code, next_list, next_ctr, done_list,
+                                             done_ctr, asm_list, asm_ctr);
   return hipGetLastError();
 }
 

@@ -100,7 +100,7 @@ struct mem_ctx_s {
   float* w_resid = nullptr;
   int32_t* w_iters = nullptr;
   uint32_t* w_status = nullptr;
-  int32_t* w_list[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t* w_list[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int32_t* w_ctr = nullptr;   // [8] list counters
   int8_t* w_code = nullptr;   // [cap] per-slot outcome of the direction kernel
   float* w_Sp = nullptr;      // [sp_rows][NCOL] partial sums of node-range splits
@@ -176,6 +176,14 @@ hipError_t launch_assemble3m(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
 int assembly_splits(mem_ctx_t c, int ntile, int ngroups);
 hipError_t launch_sum_splits(mem_ctx_t c, const int32_t* list, const int32_t* ctr, int64_t n,
                              int ntile, int nsplit, float* S, hipStream_t s);
+// First Newton pass of the cells whose beta is exactly the Maxwellian of their
+// gauge (closed form: H = I, E = e_0); the others go to asm_list/asm_ctr for
+// the ordinary first assembly.
+hipError_t launch_start3(mem_ctx_t c, int64_t n, const int32_t* list, const int32_t* ctr,
+                         const float* M, const float* beta, const SolveParams& p,
+                         int32_t* next_list, int32_t* next_ctr, int32_t* asm_list, int32_t* asm_ctr,
+                         int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
+                         int32_t* done_ctr, float* cond, hipStream_t s);
 hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                              const int32_t* ctr, const float* M, const float* beta,
                              const SolveParams& p,
