@@ -400,3 +400,45 @@ def test_other_rules_match_oracle(n1d):
         assert np.all(err <= bound + 2.0 ** -23 * np.abs(G_o))
     finally:
         ctx.close()
+
+
+def test_closed_form_first_pass(ctx3, rule3):
+    """The first Newton pass from the exact gauge Maxwellian is taken in closed
+    form (H = I, G = -M/n).  A start one ulp away takes the ordinary first
+    assembly: both reach the same solution, in the same number of iterations up
+    to one.  Equilibrium targets converge in that first pass with beta untouched."""
+    C = 200
+    cells = mem_inputs.mott_smith_cells(C, config=2, replica=21)
+    M = f32(cells["M"])
+    b0 = f32(mem_inputs.maxwellian_beta(C, 35, M[:, 0]))
+    b1 = b0.copy()
+    b1[:, 4] = np.nextafter(b0[:, 4].astype(np.float32), np.float32(0)).astype(np.float64)
+    out = {}
+    for name, start in (("closed", b0), ("assembled", b1)):
+        bg = dev(start)
+        iters, resid, status = ctx3.solve(dev(M), bg)
+        torch.cuda.synchronize()
+        out[name] = (bg.cpu().numpy().astype(np.float64), iters.cpu().numpy(), status.cpu().numpy())
+    (ba, ia, sa), (bb, ib, sb) = out["closed"], out["assembled"]
+    both = ((sa & mem.ST_CONVERGED) != 0) & ((sb & mem.ST_CONVERGED) != 0)
+    assert both.mean() >= 0.97
+    ref = maxent.newton_solve(M, b0, rule3["Phi"], rule3["logw"])
+    for beta in (ba, bb):
+        err = np.max(np.abs(beta[both] - ref["beta"][both]), axis=1) / np.maximum(
+            1.0, np.max(np.abs(ref["beta"][both]), axis=1))
+        assert err.max() <= 1e-4
+    print(f"\n[closed start] iterations mean {ia.mean():.2f} vs {ib.mean():.2f}, "
+          f"max |dbeta| {np.max(np.abs(ba[both] - bb[both])):.1e}")
+    assert np.max(np.abs(ia[both] - ib[both])) <= 1
+    # equilibrium targets: converged in the closed-form pass, beta exactly kept
+    Me = np.zeros((64, 35))
+    Me[:, 0] = np.linspace(0.5, 2.0, 64)
+    be = f32(mem_inputs.maxwellian_beta(64, 35, Me[:, 0]))
+    bg = dev(be)
+    iters, resid, status = ctx3.solve(dev(f32(Me)), bg)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    assert np.all(st & mem.ST_CONVERGED)
+    assert np.all(iters.cpu().numpy() == 1)
+    assert np.all(resid.cpu().numpy() <= 1e-7)
+    assert np.array_equal(bg.cpu().numpy(), be.astype(np.float32))
