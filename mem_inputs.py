@@ -29,6 +29,9 @@ Workloads (seed = 1000*config + replica):
    upstream/downstream Maxwellian moments in a common gauge, Maxwellian
    boundary states in their own gauges.
 5. ``ragged_batch``: many shock problems with log-uniform cell counts.
+6. ``mott_smith_cells9``: the Mott-Smith mixtures of workload 2 on the paper's
+   nine statistics of (u_x, u_r), by default at Mach 10 (the paper's Mach-10
+   shock; its box ``AXI_MACH10_BOX``).
 """
 
 import math
@@ -208,3 +211,51 @@ def ragged_batch(n_problems=2048, lo=64, hi=4096, mach_lo=1.2, mach_hi=10.0,
         half = 0.5 * counts[p] * dx
         probs.append(shock_problem(mach[p], int(counts[p]), -half, half, thickness))
     return dict(counts=counts, mach=mach, offsets=offsets, problems=probs, dx=dx)
+
+
+# --------------------------------------------------------------------------
+# the paper's own discretisation: nine statistics of (u_x, u_r) on a
+# block-wise Gauss--Legendre box fixed in physical velocity
+# --------------------------------------------------------------------------
+# The Mach-10 shock set-up: box [-24.8, 31.4] x [0, 28.1], 6 x 4 blocks of
+# 8 x 8 Gauss--Legendre points (1536 nodes).
+AXI_MACH10_BOX = dict(ux_lo=-24.8, ux_hi=31.4, ur_hi=28.1, blocks_x=6, blocks_r=4, order=8)
+
+
+def gaussian_moments9(n, v, Txx, Trr, g):
+    """Nine moments in gauge g of n * N((v,0,0), diag(Txx, Trr, Trr)).
+
+    With x = u_bar_x ~ N(mu, s^2) and y = u_bar_r^2/2 ~ Exp(mean theta),
+    theta = Trr/s_r^2, independent: E[He_k(x)] = h_k(mu; s^2 - 1),
+    E[y - 1] = theta - 1, E[y^2/2 - 2y + 1] = (theta - 1)^2.  Statistic order:
+    1, x, He_2/sqrt2, y-1, He_3/sqrt6, He_4/sqrt24, y^2/2-2y+1, x(y-1),
+    He_2/sqrt2 (y-1).
+    """
+    n, v, Txx, Trr = (np.asarray(a, dtype=np.float64) for a in (n, v, Txx, Trr))
+    g = np.asarray(g, dtype=np.float64)
+    mx = (v - g[:, 0]) / g[:, 1]
+    hx = [hermite_gauss_moment(k, mx, Txx / g[:, 1] ** 2) for k in range(5)]
+    th = Trr / g[:, 2] ** 2
+    l1, l2 = th - 1.0, (th - 1.0) ** 2
+    one = np.ones_like(mx)
+    cols = [one, hx[1], hx[2] / math.sqrt(2.0), l1, hx[3] / math.sqrt(6.0),
+            hx[4] / math.sqrt(24.0), l2, hx[1] * l1, hx[2] / math.sqrt(2.0) * l1]
+    return n[:, None] * np.stack(cols, axis=1)
+
+
+def mott_smith_cells9(n_cells, mach_lo=10.0, mach_hi=10.0, config=6, replica=0):
+    """Mott-Smith mixtures (as ``mott_smith_cells``) on the nine statistics,
+    in the mixture's exact Hermite gauge."""
+    rng = np.random.default_rng(seed_for(config, replica))
+    mach = rng.uniform(mach_lo, mach_hi, n_cells)
+    nu = rng.uniform(0.0, 1.0, n_cells)
+    (n1, v1, T1), (n2, v2, T2) = rankine_hugoniot(mach)
+    a1, a2 = (1.0 - nu) * n1, nu * n2
+    N = a1 + a2
+    mean = (a1 * v1 + a2 * v2) / N
+    varx = (a1 * (T1 + v1 ** 2) + a2 * (T2 + v2 ** 2)) / N - mean ** 2
+    varr = (a1 * T1 + a2 * T2) / N
+    g = np.stack([mean, np.sqrt(varx), np.sqrt(varr)], axis=1)
+    M = ((1.0 - nu)[:, None] * gaussian_moments9(n1, v1, T1, T1, g)
+         + nu[:, None] * gaussian_moments9(n2, v2, T2, T2, g))
+    return dict(M=M, g=g, mach=mach, nu=nu)

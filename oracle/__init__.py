@@ -25,9 +25,13 @@ the algorithm steps in the paper's order.  Module map (paper sections):
   LLF finite volume in local gauges and the time step of Alg. 2.
 * ``workloads``  -- oracle-side construction of targets that need the
   parameter-to-moment map (the 1D perturbed-multiplier workload).
+* ``axisym``     -- the paper's own discretisation: nine statistics of
+  (u_x, u_r), block-wise Gauss--Legendre on a truncated box fixed in physical
+  velocity, the integration-domain formula, per-cell Phi in the gauge, moments,
+  fluxes, Hermite gauge and Alg. 1 on it.
 
 Pins: every function here is checked in ``tests/test_oracle_*.py`` against
 closed forms, invariants or brute force (never against itself or the GPU).
 """
 
-from . import quadrature, basis, maxent, gauge, flux, kinetics  # noqa: F401
+from . import quadrature, basis, maxent, gauge, flux, kinetics, axisym  # noqa: F401

@@ -1,0 +1,176 @@
+"""The paper's own velocity discretisation for 1D flow (oracle).
+
+Test infrastructure only.  For flow along x with cylindrical symmetry in
+velocity the paper works with nine statistics of (u_x, u_r),
+u_r = sqrt(u_y^2 + u_z^2), integrated over a truncated box (u_x, u_r) in
+[a_x, b_x] x [0, b_r] with block-wise Gauss--Legendre quadrature:
+
+* statistics: the orthogonal form of the nine-statistic system (appendix on the
+  exponential family of the 35-moment system).  Written with x = u_bar_x and
+  y = u_bar_r^2 / 2 they are products of probabilists' Hermite polynomials in
+  x and Laguerre polynomials in y:
+  1, x, He_2(x)/sqrt2, y - 1, He_3(x)/sqrt6, He_4(x)/sqrt24,
+  y^2/2 - 2y + 1, x (y - 1), He_2(x)/sqrt2 (y - 1).
+  Reading: the printed eighth statistic u_x (u_r^2 - 1)/2 is neither
+  orthogonal to u_x nor of unit norm under the standard Maxwellian, although
+  the paper calls the set orthogonal; it is read as u_x (u_r^2 - 2)/2, the
+  product of the second and fourth statistics, which matches the factor
+  (u_r^2 - 2) of the ninth.
+* gauge (Sec. 3.3): u_bar = ((u_x - w_x)/s_x, u_r/s_r).  The quadrature nodes
+  stay fixed in physical velocity, so every cell evaluates the statistics at
+  its own u_bar_p (a per-cell Phi).
+* quadrature (end of Sec. 3.1): the box is cut into equal blocks, each
+  integrated with the tensor product of the 1D Gauss--Legendre rule.  The
+  integrands are axisymmetric, so d^3u = 2 pi u_r du_r du_x and the weight of
+  node p is 2 pi u_r,p times the product of the two scaled Gauss--Legendre
+  weights (the integral over the angle is exact).
+* integration domain (appendix on the normal-shock set-up): a_x, b_x, b_r from
+  the upstream and downstream states with integer multipliers n_a, n_b, n_r.
+* Hermite gauge of the nine moments (Sec. 3.3): w_H = w + s_x E[x],
+  s_xH^2 = s_x^2 Var(x), s_rH^2 = s_r^2 E[u_bar_r^2]/2 with
+  E[x^2] = sqrt2 M_2/n + 1 and E[u_bar_r^2] = 2 (M_3/n + 1).
+* solve: Alg. 1 through ``maxent.newton_solve`` cell by cell, each with its
+  own Phi (nodes fixed in physical velocity) and the common log weights.
+
+Units are non-dimensional with m = k_B = 1, so sqrt(k_B T/m) = sqrt(T).
+"""
+
+import math
+
+import numpy as np
+
+from . import maxent
+
+K9 = 9
+SQ2 = math.sqrt(2.0)
+SQ6 = math.sqrt(6.0)
+SQ24 = math.sqrt(24.0)
+
+
+def statistics(x, ur):
+    """The nine statistics at gauge coordinates (x, u_bar_r): shape (..., 9)."""
+    x = np.asarray(x, dtype=np.float64)
+    ur = np.asarray(ur, dtype=np.float64)
+    y = 0.5 * ur * ur
+    he2 = x * x - 1.0
+    he3 = x * x * x - 3.0 * x
+    he4 = x ** 4 - 6.0 * x * x + 3.0
+    return np.stack([np.ones_like(x), x, he2 / SQ2, y - 1.0, he3 / SQ6, he4 / SQ24,
+                     0.5 * y * y - 2.0 * y + 1.0, x * (y - 1.0), he2 / SQ2 * (y - 1.0)], axis=-1)
+
+
+def gauss_legendre(order):
+    """1D Gauss--Legendre nodes and weights on [-1, 1] (NumPy's leggauss)."""
+    x, w = np.polynomial.legendre.leggauss(order)
+    return x.astype(np.float64), w.astype(np.float64)
+
+
+def blockwise_rule(ux_lo, ux_hi, ur_hi, blocks_x, blocks_r, order):
+    """Nodes (u_x, u_r) and log weights of the block-wise rule on the box.
+
+    Nodes run over blocks in x (outer), blocks in r, then the Gauss--Legendre
+    points in x, then in r.  log w_p = log(2 pi u_r,p hx hr wx wr) with the
+    half-widths hx, hr of a block.
+    """
+    gx, gw = gauss_legendre(order)
+    hx = 0.5 * (ux_hi - ux_lo) / blocks_x
+    hr = 0.5 * ur_hi / blocks_r
+    ux, ur, w = [], [], []
+    for bx in range(blocks_x):
+        cx = ux_lo + (2 * bx + 1) * hx
+        for br in range(blocks_r):
+            cr = (2 * br + 1) * hr
+            for i in range(order):
+                for j in range(order):
+                    u_r = cr + hr * gx[j]
+                    ux.append(cx + hx * gx[i])
+                    ur.append(u_r)
+                    w.append(2.0 * math.pi * u_r * hx * hr * gw[i] * gw[j])
+    return dict(ux=np.array(ux), ur=np.array(ur), logw=np.log(np.array(w)))
+
+
+def integration_domain(v_minus, T_minus, v_plus, T_plus, n_a, n_b, n_r):
+    """(a_x, b_x, b_r) of the normal-shock set-up (m = k_B = 1)."""
+    sm, sp = math.sqrt(T_minus), math.sqrt(T_plus)
+    a_x = min(v_plus - n_a * sp, v_minus - n_a * sm)
+    b_x = max(v_minus + n_b * sm, v_plus + n_b * sp)
+    b_r = max(n_r * sm, n_r * sp)
+    return a_x, b_x, b_r
+
+
+def cell_phi(rule, g):
+    """Phi of one cell in gauge g = (w_x, s_x, s_r): (P, 9)."""
+    w, sx, sr = g
+    return statistics((rule["ux"] - w) / sx, rule["ur"] / sr)
+
+
+def moments(beta, g, rule):
+    """M_i = beta_0 sum_p sigma_p phi_i(u_bar_p) per cell (Sec. 3.1)."""
+    beta = np.asarray(beta, dtype=np.float64)
+    out = np.empty((beta.shape[0], K9))
+    for c in range(beta.shape[0]):
+        out[c] = maxent.model_moments(beta[c:c + 1], cell_phi(rule, g[c]), rule["logw"])[0]
+    return out
+
+
+def fluxes(beta, g, rule):
+    """F_i = beta_0 sum_p sigma_p u_x,p phi_i(u_bar_p), u_x in physical velocity."""
+    beta = np.asarray(beta, dtype=np.float64)
+    out = np.empty((beta.shape[0], K9))
+    for c in range(beta.shape[0]):
+        Phi = cell_phi(rule, g[c])
+        sig = maxent.sigma(beta[c:c + 1], Phi, rule["logw"])[0]
+        out[c] = beta[c, 0] * (sig * rule["ux"]) @ Phi
+    return out
+
+
+def moment_residual(beta, M, g, rule):
+    """max_{i>=1} |E_sigma[phi_i] - M_i/n| in FP64, per cell."""
+    beta = np.asarray(beta, dtype=np.float64)
+    M = np.asarray(M, dtype=np.float64)
+    r = np.empty(M.shape[0])
+    for c in range(M.shape[0]):
+        r[c] = maxent.moment_residual(beta[c:c + 1], M[c:c + 1], cell_phi(rule, g[c]),
+                                      rule["logw"])[0]
+    return r
+
+
+def hermite_gauge(M, g):
+    """Hermite gauge parameters from the nine moments in gauge g (Sec. 3.3)."""
+    M = np.asarray(M, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    n = M[:, 0]
+    m1 = M[:, 1] / n
+    exx = SQ2 * M[:, 2] / n + 1.0
+    err = 2.0 * (M[:, 3] / n + 1.0)
+    wH = g[:, 0] + g[:, 1] * m1
+    sxH = g[:, 1] * np.sqrt(exx - m1 * m1)
+    srH = g[:, 2] * np.sqrt(err / 2.0)
+    return np.stack([wH, sxH, srH], axis=1)
+
+
+def maxwellian_beta(n, g):
+    """Cold start: the Maxwellian of the cell's own Hermite gauge, beta_0 = n.
+
+    exp(-x^2/2 - u_bar_r^2/2) = exp(-(He_2(x)/sqrt2)/sqrt2 - (y - 1)) up to a
+    constant absorbed by log Z: beta_2 = -1/sqrt2, beta_3 = -1.
+    """
+    n = np.asarray(n, dtype=np.float64)
+    beta = np.zeros((n.size, K9))
+    beta[:, 0] = n
+    beta[:, 2] = -1.0 / SQ2
+    beta[:, 3] = -1.0
+    return beta
+
+
+def solve(M, g, beta_init, rule, **kw):
+    """Alg. 1 per cell on the nine statistics; returns maxent.newton_solve's fields."""
+    M = np.asarray(M, dtype=np.float64)
+    keys = ("beta", "iters", "resid", "converged", "stagnated", "nonrealizable", "shifted")
+    out = {k: [] for k in keys}
+    for c in range(M.shape[0]):
+        r = maxent.newton_solve(M[c:c + 1], np.asarray(beta_init[c:c + 1], np.float64),
+                                cell_phi(rule, g[c]), rule["logw"], **kw)
+        for k in keys:
+            out[k].append(r[k][0])
+    return {k: np.array(v) for k, v in out.items()}

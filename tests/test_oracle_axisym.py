@@ -1,0 +1,171 @@
+"""Pins for the oracle's nine-statistic discretisation (no GPU).
+
+* Block-wise Gauss--Legendre (end of Sec. 3.1): exact on polynomials of the
+  rule's degree, against closed-form integrals over the box with the
+  axisymmetric measure 2 pi u_r du_r du_x.
+* Statistics (appendix on the 35-moment system, orthogonal form): orthonormal
+  under the standard Maxwellian, inside the span of the 35 three-dimensional
+  Hermite statistics (the 35 -> 9 reduction), and the printed eighth statistic
+  is not orthogonal (the reading the oracle takes).
+* Moments and fluxes of Maxwellians in arbitrary gauges (Sec. 3.1, Sec. 3.3)
+  against closed-form Gaussian expectations; Hermite gauge of a Maxwellian.
+* Alg. 1 on the nine statistics returns the closed-form Maxwellian
+  multipliers; the integration-domain formula reproduces the paper's printed
+  boxes (``tests/golden/axisym_domains.json``).
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import mem_inputs
+from oracle import axisym, basis
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("order", [1, 2, 5, 8, 12, 16])
+def test_gauss_legendre_exact(order):
+    x, w = axisym.gauss_legendre(order)
+    for k in range(2 * order):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.sum(w * x ** k) - exact) < 1e-13
+
+
+def test_blockwise_rule_exact_on_polynomials():
+    lo, hi, rh = -3.1, 4.7, 5.3
+    rule = axisym.blockwise_rule(lo, hi, rh, 3, 2, 4)
+    assert rule["ux"].size == 3 * 2 * 16
+    w = np.exp(rule["logw"])
+    for a in range(8):
+        for b in range(7):   # u_r^(b+1) must stay within degree 7 per axis
+            num = np.sum(w * rule["ux"] ** a * rule["ur"] ** b)
+            exact = (2 * math.pi * (hi ** (a + 1) - lo ** (a + 1)) / (a + 1)
+                     * rh ** (b + 2) / (b + 2))
+            assert abs(num - exact) <= 1e-12 * max(1.0, abs(exact))
+
+
+def _wide_rule():
+    return axisym.blockwise_rule(-22.0, 22.0, 22.0, 22, 11, 12)
+
+
+def test_statistics_orthonormal_under_standard_maxwellian():
+    rule = _wide_rule()
+    f = np.exp(rule["logw"] - 0.5 * (rule["ux"] ** 2 + rule["ur"] ** 2)) / (2 * math.pi) ** 1.5
+    Phi = axisym.statistics(rule["ux"], rule["ur"])
+    G = (Phi * f[:, None]).T @ Phi
+    assert np.max(np.abs(G - np.eye(9))) < 1e-12
+    # the printed eighth statistic u_x (u_r^2 - 1)/2 is not orthogonal to u_x
+    printed = 0.5 * rule["ux"] * (rule["ur"] ** 2 - 1.0)
+    assert abs(np.sum(f * printed * rule["ux"]) - 0.5) < 1e-12
+
+
+def test_statistics_in_span_of_3d_hermite_basis():
+    rng = np.random.default_rng(7)
+    u = rng.normal(size=(400, 3)) * 1.7
+    P35 = basis.evaluate(u, 3)
+    P9 = axisym.statistics(u[:, 0], np.sqrt(u[:, 1] ** 2 + u[:, 2] ** 2))
+    coef, *_ = np.linalg.lstsq(P35, P9, rcond=None)
+    assert np.max(np.abs(P35 @ coef - P9)) < 1e-10
+    # symmetric in (u_y, u_z): swapping them leaves every statistic unchanged
+    assert np.allclose(axisym.statistics(u[:, 0], np.hypot(u[:, 2], u[:, 1])), P9, atol=1e-13)
+
+
+def _raw_gauss(mu, s2, kmax):
+    m = [1.0, mu]
+    for k in range(2, kmax + 1):
+        m.append(mu * m[k - 1] + (k - 1) * s2 * m[k - 2])
+    return m
+
+
+def _closed_form(n, v, T, g, with_ux=False):
+    """Closed-form n E[phi_i] (or n E[u_x phi_i]) for a Maxwellian, gauge g."""
+    w, sx, sr = g
+    mu, s2, th = (v - w) / sx, T / sx ** 2, T / sr ** 2
+    mx = _raw_gauss(mu, s2, 6)
+    Ey = [math.factorial(k) * th ** k for k in range(3)]
+    # x-polynomials (coefficients of x^0..x^4) and y-polynomials of each statistic
+    xp = {0: [1], 1: [0, 1], 2: [-1 / math.sqrt(2), 0, 1 / math.sqrt(2)],
+          3: [0, -3 / math.sqrt(6), 0, 1 / math.sqrt(6)],
+          4: [3 / math.sqrt(24), 0, -6 / math.sqrt(24), 0, 1 / math.sqrt(24)]}
+    stats = [(0, [1]), (1, [1]), (2, [1]), (0, [-1, 1]), (3, [1]), (4, [1]),
+             (0, [1, -2, 0.5]), (1, [-1, 1]), (2, [-1, 1])]
+    out = []
+    for xi, yp in stats:
+        c = list(xp[xi])
+        if with_ux:   # u_x = w + s_x x
+            c = [w * a for a in c] + [0.0]
+            for k, a in enumerate(xp[xi]):
+                c[k + 1] += sx * a
+        ex = sum(a * mx[k] for k, a in enumerate(c))
+        ey = sum(a * Ey[k] for k, a in enumerate(yp))
+        out.append(n * ex * ey)
+    return np.array(out)
+
+
+def _maxwellian_beta_in_gauge(n, v, T, g):
+    w, sx, sr = g
+    b = np.zeros(9)
+    b[0] = n
+    b[1] = -sx * (w - v) / T
+    b[2] = -sx ** 2 / (math.sqrt(2) * T)
+    b[3] = -sr ** 2 / T
+    return b
+
+
+CASES = [(1.0, 0.0, 1.0, (0.0, 1.0, 1.0)), (2.3, 1.7, 0.6, (1.2, 0.9, 0.7)),
+         (0.4, -2.0, 3.1, (-1.5, 1.6, 2.1))]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_maxwellian_moments_and_fluxes_closed_form(case):
+    n, v, T, g = case
+    rule = _wide_rule()
+    beta = _maxwellian_beta_in_gauge(n, v, T, g)[None, :]
+    M = axisym.moments(beta, np.array([g]), rule)[0]
+    F = axisym.fluxes(beta, np.array([g]), rule)[0]
+    assert np.max(np.abs(M - _closed_form(n, v, T, g))) < 1e-10
+    assert np.max(np.abs(F - _closed_form(n, v, T, g, with_ux=True))) < 1e-10
+    # the shared input generator's closed form agrees
+    Mi = mem_inputs.gaussian_moments9(np.array([n]), np.array([v]), np.array([T]),
+                                      np.array([T]), np.array([g]))[0]
+    assert np.max(np.abs(Mi - M)) < 1e-10
+    gH = axisym.hermite_gauge(M[None, :], np.array([g]))[0]
+    assert np.allclose(gH, [v, math.sqrt(T), math.sqrt(T)], atol=1e-10)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_solve_returns_maxwellian_multipliers(case):
+    n, v, T, g = case
+    rule = _wide_rule()
+    M = _closed_form(n, v, T, g)[None, :]
+    b0 = axisym.maxwellian_beta(np.array([n]), np.array([g]))
+    r = axisym.solve(M, np.array([g]), b0, rule, tol_grad=1e-12, max_iter=100)
+    assert r["converged"][0]
+    assert np.max(np.abs(r["beta"][0] - _maxwellian_beta_in_gauge(n, v, T, g))) < 1e-8
+
+
+def test_solve_mott_smith_cells_on_paper_box():
+    cells = mem_inputs.mott_smith_cells9(12, replica=3)
+    rule = axisym.blockwise_rule(**mem_inputs.AXI_MACH10_BOX)
+    assert rule["ux"].size == 1536
+    b0 = axisym.maxwellian_beta(cells["M"][:, 0], cells["g"])
+    r = axisym.solve(cells["M"], cells["g"], b0, rule, tol_grad=1e-11, max_iter=200)
+    assert np.all(r["converged"])
+    res = axisym.moment_residual(r["beta"], cells["M"], cells["g"], rule)
+    assert np.all(res <= 1e-11)
+    # the certificate of Alg. 1: the gradient is zero, so the model reproduces M
+    Mm = axisym.moments(r["beta"], cells["g"], rule)
+    assert np.max(np.abs(Mm - cells["M"]) / cells["M"][:, :1]) < 1e-10
+
+
+def test_integration_domain_reproduces_printed_boxes():
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "axisym_domains.json")))
+    for c in gold["cases"]:
+        (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(c["mach"])
+        box = axisym.integration_domain(float(v1), float(T1), float(v2), float(T2),
+                                        c["n_a"], c["n_b"], c["n_r"])
+        assert [round(b, 1) for b in box] == c["box"]
