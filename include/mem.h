@@ -320,6 +320,75 @@ MEM_API mem_err_t mem_autotune(mem_ctx_t ctx, int64_t n_cells, const float* M,
 MEM_API mem_err_t mem_get_tuning(mem_ctx_t ctx, mem_tuning_t* out);
 MEM_API mem_err_t mem_set_tuning(mem_ctx_t ctx, const mem_tuning_t* in);
 
+/* ---- the paper's own discretisation: nine statistics on a box ---------------- */
+
+/* For 1D flow with cylindrical symmetry in velocity the paper works with nine
+ * statistics of (u_x, u_r), u_r = sqrt(u_y^2 + u_z^2), in the gauge
+ * u_bar = ((u_x - w_x)/s_x, u_r/s_r) (Sec. 3.3; orthogonal form of the
+ * appendix on the 35-moment system).  With x = u_bar_x, y = u_bar_r^2/2 they
+ * are, in this order:
+ *   1, x, He_2(x)/sqrt2, y - 1, He_3(x)/sqrt6, He_4(x)/sqrt24,
+ *   y^2/2 - 2y + 1, x (y - 1), He_2(x)/sqrt2 (y - 1)
+ * (the printed eighth statistic, u_x (u_r^2 - 1)/2, is read as
+ * u_x (u_r^2 - 2)/2, which makes the set orthonormal under the standard
+ * Maxwellian as the paper states).  Integrals run over the box
+ * (u_x, u_r) in [ux_lo, ux_hi] x [0, ur_hi] cut into blocks_x x blocks_r equal
+ * blocks, each with the tensor Gauss--Legendre rule of `order` points per axis
+ * (end of Sec. 3.1); the node weight is 2 pi u_r times the two scaled
+ * Gauss--Legendre weights (axisymmetric measure).  The nodes stay fixed in
+ * physical velocity, so each cell evaluates the statistics in its own gauge.
+ * Units: m = k_B = 1. */
+typedef struct {
+  double ux_lo, ux_hi;   /* a_x < b_x */
+  double ur_hi;          /* b_r > 0 */
+  int32_t blocks_x, blocks_r;  /* 1..256 each */
+  int32_t order;         /* Gauss--Legendre points per block and axis, 1..32 */
+  int32_t reserved;      /* must be 0 */
+} mem_axi_rule_t;
+
+typedef struct mem_axi_s* mem_axi_t;
+
+/* Integration-domain formula of the normal-shock set-up (appendix on the
+ * shock problem): box[0] = a_x = min(v+ - n_a sqrt(T+), v- - n_a sqrt(T-)),
+ * box[1] = b_x = max(v- + n_b sqrt(T-), v+ + n_b sqrt(T+)),
+ * box[2] = b_r = n_r max(sqrt(T-), sqrt(T+)).  Host only. */
+MEM_API mem_err_t mem_axi_domain(double v_minus, double T_minus, double v_plus, double T_plus,
+                                 int32_t n_a, int32_t n_b, int32_t n_r, double* box);
+
+/* Number of nodes P = blocks_x blocks_r order^2 of a rule, or -1 if the rule
+ * is invalid.  Host only. */
+MEM_API int64_t mem_axi_rule_nodes(const mem_axi_rule_t* rule);
+
+/* The rule's nodes in FP64 on the host, no device needed: ux[P], ur[P],
+ * logw[P] (caller-owned, any may be NULL; n_nodes must equal P).  Node order:
+ * blocks in x (outer), blocks in r, Gauss--Legendre points in x, then in r. */
+MEM_API mem_err_t mem_axi_host_rule(const mem_axi_rule_t* rule, double* ux, double* ur,
+                                    double* logw, int64_t n_nodes);
+
+/* Handle holding the rule's node table (u_x as an FP32 pair hi + lo, u_r, log w) on the
+ * current device.  MEM_ERR_INVALID_ARG for an invalid rule. */
+MEM_API mem_err_t mem_axi_create(const mem_axi_rule_t* rule, mem_axi_t* out);
+MEM_API mem_err_t mem_axi_destroy(mem_axi_t h);
+MEM_API int64_t mem_axi_n_nodes(mem_axi_t h);
+
+/* Alg. 1 on the nine statistics, one wave per cell (FP32; FP64 direction for
+ * a small pivot ratio as in mem_maxent_solve).  M[n][9] targets and g[n][3] =
+ * (w_x, s_x, s_r) per cell; beta[n][9] in: start multipliers (beta[:,0]
+ * ignored), out: solution with beta[:,0] = n.  Stopping rules and status bits
+ * as mem_maxent_solve (no compensated refinement: resid is the FP32
+ * max_{i>=1} |G_i| of the last assembly).  iters, resid, status may be NULL.
+ * All arrays are device memory, row-major.  Asynchronous on stream. */
+MEM_API mem_err_t mem_axi_solve(mem_axi_t h, int64_t n_cells, const float* M, const float* g,
+                                float* beta, const mem_solve_opts_t* opts, int32_t* iters,
+                                float* resid, uint32_t* status, hipStream_t stream);
+
+/* Parameter-to-moment map (Sec. 3.1) and fluxes: M[n][9] = beta_0
+ * E_sigma[phi_i], F[n][9] = beta_0 E_sigma[u_x phi_i] with u_x the physical
+ * velocity of the node, at beta[n][9] and g[n][3] (E_sigma normalised by
+ * sum_p sigma_p).  M or F may be NULL.  Device memory, asynchronous. */
+MEM_API mem_err_t mem_axi_moments(mem_axi_t h, int64_t n_cells, const float* beta,
+                                  const float* g, float* M, float* F, hipStream_t stream);
+
 /* ---- measurement -------------------------------------------------------------- */
 
 /* Kernel timing with HIP events recorded on the launch stream around every

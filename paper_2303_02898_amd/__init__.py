@@ -55,6 +55,11 @@ class Batch(ctypes.Structure):
 _lib = None
 
 
+class AxiRuleStruct(ctypes.Structure):
+    _fields_ = [("ux_lo", ctypes.c_double), ("ux_hi", ctypes.c_double), ("ur_hi", ctypes.c_double),
+                ("blocks_x", _c_i32), ("blocks_r", _c_i32), ("order", _c_i32), ("reserved", _c_i32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("dir_waves", _c_i32), ("split_want", _c_i32), ("tuned_ms", ctypes.c_double)]
 
@@ -93,6 +98,14 @@ def load_library():
                           P], E),
         "mem_get_tuning": ([P, ctypes.POINTER(Tuning)], E),
         "mem_set_tuning": ([P, ctypes.POINTER(Tuning)], E),
+        "mem_axi_domain": ([ctypes.c_double] * 4 + [_c_i32] * 3 + [P], E),
+        "mem_axi_rule_nodes": ([ctypes.POINTER(AxiRuleStruct)], _c_i64),
+        "mem_axi_host_rule": ([ctypes.POINTER(AxiRuleStruct), P, P, P, _c_i64], E),
+        "mem_axi_create": ([ctypes.POINTER(AxiRuleStruct), ctypes.POINTER(_vp)], E),
+        "mem_axi_destroy": ([P], E),
+        "mem_axi_n_nodes": ([P], _c_i64),
+        "mem_axi_solve": ([P, _c_i64, P, P, P, ctypes.POINTER(SolveOpts), P, P, P, P], E),
+        "mem_axi_moments": ([P, _c_i64, P, P, P, P, P], E),
         "mem_profile_enable": ([P, _c_i32], E),
         "mem_profile_read": ([P, _c_i32, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(_c_i64)], E),
@@ -330,6 +343,90 @@ class Context:
                                             _ptr(g, torch.float32, (3,), "g"), out.data_ptr(),
                                             _stream(stream)), "mem_conserved")
         return out
+
+
+def axi_domain(v_minus, T_minus, v_plus, T_plus, n_a, n_b, n_r):
+    """Integration box (a_x, b_x, b_r) of the normal-shock set-up (host)."""
+    lib = load_library()
+    box = (ctypes.c_double * 3)()
+    err = lib.mem_axi_domain(v_minus, T_minus, v_plus, T_plus, n_a, n_b, n_r, box)
+    if err != 0:
+        raise MemError(f"mem_axi_domain: {lib.mem_strerror(err).decode()}")
+    return tuple(box)
+
+
+def _axi_rule(ux_lo, ux_hi, ur_hi, blocks_x, blocks_r, order):
+    return AxiRuleStruct(ux_lo, ux_hi, ur_hi, blocks_x, blocks_r, order, 0)
+
+
+def axi_host_rule(ux_lo, ux_hi, ur_hi, blocks_x, blocks_r, order):
+    """FP64 nodes (ux, ur, logw) of a block-wise Gauss--Legendre box, built by
+    the library's host code (no device needed)."""
+    import numpy as np
+    lib = load_library()
+    r = _axi_rule(ux_lo, ux_hi, ur_hi, blocks_x, blocks_r, order)
+    P = lib.mem_axi_rule_nodes(ctypes.byref(r))
+    if P < 0:
+        raise MemError("mem_axi_rule_nodes: invalid rule")
+    ux, ur, lw = (np.empty(P, dtype=np.float64) for _ in range(3))
+    err = lib.mem_axi_host_rule(ctypes.byref(r), ux.ctypes.data, ur.ctypes.data, lw.ctypes.data, P)
+    if err != 0:
+        raise MemError(f"mem_axi_host_rule: {lib.mem_strerror(err).decode()}")
+    return dict(ux=ux, ur=ur, logw=lw)
+
+
+class AxiRule:
+    """The paper's nine-statistic discretisation: a block-wise Gauss--Legendre
+    box fixed in physical velocity, on the current device."""
+
+    K = 9
+
+    def __init__(self, ux_lo, ux_hi, ur_hi, blocks_x, blocks_r, order):
+        self._lib = load_library()
+        r = _axi_rule(ux_lo, ux_hi, ur_hi, blocks_x, blocks_r, order)
+        h = _vp()
+        err = self._lib.mem_axi_create(ctypes.byref(r), ctypes.byref(h))
+        if err != 0:
+            raise MemError(f"mem_axi_create: {self._lib.mem_strerror(err).decode()}")
+        self._h = h
+        self.n_nodes = int(self._lib.mem_axi_n_nodes(h))
+
+    def close(self):
+        if self._h:
+            self._lib.mem_axi_destroy(self._h)
+            self._h = None
+
+    def _check(self, err, what):
+        if err != 0:
+            raise MemError(f"{what}: {self._lib.mem_strerror(err).decode()}")
+
+    def solve(self, M, g, beta, opts=None, iters=None, resid=None, status=None, stream=None):
+        import torch
+        n = M.shape[0]
+        dev = M.device
+        if iters is None:
+            iters = torch.zeros(n, dtype=torch.int32, device=dev)
+        if resid is None:
+            resid = torch.zeros(n, dtype=torch.float32, device=dev)
+        if status is None:
+            status = torch.zeros(n, dtype=torch.int32, device=dev)
+        o = ctypes.byref(opts) if opts is not None else None
+        self._check(self._lib.mem_axi_solve(
+            self._h, n, _ptr(M, torch.float32, (9,), "M"), _ptr(g, torch.float32, (3,), "g"),
+            _ptr(beta, torch.float32, (9,), "beta"), o, _ptr(iters, torch.int32),
+            _ptr(resid, torch.float32), _ptr(status, torch.int32), _stream(stream)), "mem_axi_solve")
+        return iters, resid, status
+
+    def moments(self, beta, g, want_flux=True, stream=None):
+        import torch
+        n = beta.shape[0]
+        M = torch.empty(n, 9, dtype=torch.float32, device=beta.device)
+        F = torch.empty(n, 9, dtype=torch.float32, device=beta.device) if want_flux else None
+        self._check(self._lib.mem_axi_moments(
+            self._h, n, _ptr(beta, torch.float32, (9,), "beta"), _ptr(g, torch.float32, (3,), "g"),
+            M.data_ptr(), F.data_ptr() if F is not None else None, _stream(stream)),
+            "mem_axi_moments")
+        return M, F
 
 
 class ShockBatch:

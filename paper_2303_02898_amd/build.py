@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmem_mi355x.so")
-SOURCES = ["tables.cpp", "api.cpp", "k_solve3.hip", "k_mixed3.hip", "k_small1.hip", "k_step3.hip"]
+SOURCES = ["tables.cpp", "api.cpp", "axi.cpp", "k_solve3.hip", "k_mixed3.hip", "k_small1.hip",
+           "k_step3.hip", "k_axi9.hip"]
 ARCH = "gfx950"
 
 

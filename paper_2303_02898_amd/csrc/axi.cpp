@@ -1,0 +1,223 @@
+// C ABI of the nine-statistic discretisation: block-wise Gauss--Legendre rule
+// on a box fixed in physical velocity (end of Sec. 3.1), the integration-domain
+// formula of the normal-shock set-up, and the solve / moment entry points.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "mem_internal.h"
+
+using namespace memk;
+
+struct mem_axi_s {
+  mem_axi_rule_t rule;
+  int64_t P = 0;
+  std::vector<double> ux, ur, logw;
+  float4* d_tab = nullptr;  // (u_x, u_r, log w, u_x - fl(u_x)) per node
+  float lmin = 0.f;
+};
+
+namespace {
+
+// Gauss--Legendre nodes and weights on [-1, 1]: Newton's method on P_n from
+// the Chebyshev-like start cos(pi (i + 3/4) / (n + 1/2)), with P_n and P_n'
+// from the three-term recurrence (n + 1) P_{n+1} = (2n + 1) x P_n - n P_{n-1};
+// w_i = 2 / ((1 - x_i^2) P_n'(x_i)^2).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int iter = 0; iter < 100; ++iter) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    {  // derivative at the converged node
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+    }
+    const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = wi;
+    w[n - 1 - i] = wi;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+bool rule_ok(const mem_axi_rule_t* r) {
+  return r && std::isfinite(r->ux_lo) && std::isfinite(r->ux_hi) && std::isfinite(r->ur_hi) &&
+         r->ux_hi > r->ux_lo && r->ur_hi > 0.0 && r->blocks_x >= 1 && r->blocks_x <= 256 &&
+         r->blocks_r >= 1 && r->blocks_r <= 256 && r->order >= 1 && r->order <= 32 &&
+         r->reserved == 0 &&
+         (int64_t)r->blocks_x * r->blocks_r * r->order * r->order <= (int64_t)1 << 22;
+}
+
+// nodes: blocks in x (outer), blocks in r, Gauss--Legendre points in x, in r;
+// weight 2 pi u_r hx hr wx wr (the angle integrated exactly)
+void build_rule(const mem_axi_rule_t& r, std::vector<double>& ux, std::vector<double>& ur,
+                std::vector<double>& logw) {
+  std::vector<double> gx, gw;
+  gauss_legendre(r.order, gx, gw);
+  const double hx = 0.5 * (r.ux_hi - r.ux_lo) / r.blocks_x;
+  const double hr = 0.5 * r.ur_hi / r.blocks_r;
+  const double two_pi = 6.28318530717958647692;
+  ux.clear(); ur.clear(); logw.clear();
+  for (int bx = 0; bx < r.blocks_x; ++bx) {
+    const double cx = r.ux_lo + (2 * bx + 1) * hx;
+    for (int br = 0; br < r.blocks_r; ++br) {
+      const double cr = (2 * br + 1) * hr;
+      for (int i = 0; i < r.order; ++i)
+        for (int j = 0; j < r.order; ++j) {
+          const double vr = cr + hr * gx[j];
+          ux.push_back(cx + hx * gx[i]);
+          ur.push_back(vr);
+          logw.push_back(std::log(two_pi * vr * hx * hr * gw[i] * gw[j]));
+        }
+    }
+  }
+}
+
+mem_err_t params_axi(const mem_axi_s* h, const mem_solve_opts_t* o, SolveParams& p) {
+  mem_solve_opts_t d;
+  mem_solve_opts_default(&d);
+  if (!o) o = &d;
+  if (o->max_iter < 1 || o->max_iter > 100000 || o->max_ls < 0 || o->max_ls > 60 ||
+      !(o->lambda0 > 0.f) || !(o->lambda_mul > 1.f) || !(o->fp64_pivot_ratio >= 0.f) ||
+      !(o->fp64_pivot_ratio < 1.f) || !std::isfinite(o->tol_grad) || !(o->beta_max >= 0.f))
+    return MEM_ERR_INVALID_ARG;
+  p.tol_grad = o->tol_grad; p.tol_dec = o->tol_dec; p.tol_loose = o->tol_grad_loose;
+  p.max_iter = o->max_iter; p.max_ls = o->max_ls;
+  p.c = o->armijo_c; p.atol = o->atol; p.rtol = o->rtol;
+  p.lambda0 = o->lambda0; p.lambda_mul = o->lambda_mul; p.alpha_min = o->alpha_min;
+  p.fp64_ratio = o->fp64_pivot_ratio;
+  p.beta_max = o->beta_max;
+  p.lmin = h->lmin;
+  p.refine = 0;
+  return MEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mem_err_t mem_axi_domain(double v_minus, double T_minus, double v_plus, double T_plus,
+                         int32_t n_a, int32_t n_b, int32_t n_r, double* box) {
+  if (!box || !(T_minus > 0.0) || !(T_plus > 0.0) || !std::isfinite(v_minus) ||
+      !std::isfinite(v_plus) || !std::isfinite(T_minus) || !std::isfinite(T_plus) || n_a < 0 ||
+      n_b < 0 || n_r < 1)
+    return MEM_ERR_INVALID_ARG;
+  const double sm = std::sqrt(T_minus), sp = std::sqrt(T_plus);
+  box[0] = std::min(v_plus - n_a * sp, v_minus - n_a * sm);
+  box[1] = std::max(v_minus + n_b * sm, v_plus + n_b * sp);
+  box[2] = std::max(n_r * sm, n_r * sp);
+  return MEM_OK;
+}
+
+int64_t mem_axi_rule_nodes(const mem_axi_rule_t* rule) {
+  if (!rule_ok(rule)) return -1;
+  return (int64_t)rule->blocks_x * rule->blocks_r * rule->order * rule->order;
+}
+
+mem_err_t mem_axi_host_rule(const mem_axi_rule_t* rule, double* ux, double* ur, double* logw,
+                            int64_t n_nodes) {
+  if (!rule_ok(rule)) return MEM_ERR_INVALID_ARG;
+  if (n_nodes != mem_axi_rule_nodes(rule)) return MEM_ERR_INVALID_ARG;
+  std::vector<double> a, b, c;
+  build_rule(*rule, a, b, c);
+  if (ux) std::copy(a.begin(), a.end(), ux);
+  if (ur) std::copy(b.begin(), b.end(), ur);
+  if (logw) std::copy(c.begin(), c.end(), logw);
+  return MEM_OK;
+}
+
+mem_err_t mem_axi_create(const mem_axi_rule_t* rule, mem_axi_t* out) {
+  if (!out) return MEM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!rule_ok(rule)) return MEM_ERR_INVALID_ARG;
+  mem_axi_s* h = new (std::nothrow) mem_axi_s;
+  if (!h) return MEM_ERR_NOMEM;
+  h->rule = *rule;
+  try {
+    build_rule(*rule, h->ux, h->ur, h->logw);
+  } catch (...) {
+    delete h;
+    return MEM_ERR_NOMEM;
+  }
+  h->P = (int64_t)h->ux.size();
+  std::vector<float4> tab(h->P);
+  double mn = 1e300;
+  for (int64_t q = 0; q < h->P; ++q) {
+    const float hi = (float)h->ux[q];
+    tab[q] = make_float4(hi, (float)h->ur[q], (float)h->logw[q], (float)(h->ux[q] - (double)hi));
+    mn = std::min(mn, h->logw[q]);
+  }
+  // a dual value below min_p log w_p certifies that no minimiser exists
+  h->lmin = (float)(mn - 1e-3 * (1.0 + std::fabs(mn)));
+  if (hipMalloc((void**)&h->d_tab, tab.size() * sizeof(float4)) != hipSuccess) {
+    delete h;
+    return MEM_ERR_NOMEM;
+  }
+  if (hipMemcpy(h->d_tab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    (void)hipFree(h->d_tab);
+    delete h;
+    return MEM_ERR_HIP;
+  }
+  *out = h;
+  return MEM_OK;
+}
+
+mem_err_t mem_axi_destroy(mem_axi_t h) {
+  if (!h) return MEM_ERR_INVALID_ARG;
+  (void)hipDeviceSynchronize();
+  if (h->d_tab) (void)hipFree(h->d_tab);
+  delete h;
+  return MEM_OK;
+}
+
+int64_t mem_axi_n_nodes(mem_axi_t h) { return h ? h->P : -1; }
+
+mem_err_t mem_axi_solve(mem_axi_t h, int64_t n, const float* M, const float* g, float* beta,
+                        const mem_solve_opts_t* opts, int32_t* iters, float* resid,
+                        uint32_t* status, hipStream_t s) {
+  if (!h || n < 0 || n > (int64_t)INT32_MAX - 4) return MEM_ERR_INVALID_ARG;
+  if (n == 0) return MEM_OK;
+  if (!M || !g || !beta) return MEM_ERR_INVALID_ARG;
+  SolveParams p;
+  if (params_axi(h, opts, p) != MEM_OK) return MEM_ERR_INVALID_ARG;
+  if (launch_axi_solve(n, (int)h->P, h->d_tab, M, g, beta, p, iters, resid, status, s) !=
+      hipSuccess)
+    return MEM_ERR_HIP;
+  return MEM_OK;
+}
+
+mem_err_t mem_axi_moments(mem_axi_t h, int64_t n, const float* beta, const float* g, float* M,
+                          float* F, hipStream_t s) {
+  if (!h || n < 0 || n > (int64_t)INT32_MAX - 4) return MEM_ERR_INVALID_ARG;
+  if (n == 0) return MEM_OK;
+  if (!beta || !g) return MEM_ERR_INVALID_ARG;
+  if (launch_axi_moments(n, (int)h->P, h->d_tab, beta, g, M, F, s) != hipSuccess)
+    return MEM_ERR_HIP;
+  return MEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,452 @@
+// The paper's own velocity discretisation on gfx950: nine statistics of
+// (u_x, u_r) for 1D flow with cylindrical symmetry (appendix on the 35-moment
+// system, orthogonal form), integrated with block-wise Gauss--Legendre over a
+// truncated box fixed in physical velocity (end of Sec. 3.1).
+//
+// Because the nodes do not move with the gauge, every cell evaluates the
+// statistics at its own u_bar_p = ((u_x,p - w_x)/s_x, u_r,p/s_r) (Sec. 3.3):
+// there is no Phi shared by the batch and the moment/Hessian assembly is a
+// per-cell weighted Gram matrix of 9 columns (45 distinct sums), work for the
+// vector ALU rather than the matrix cores.  One wave runs the whole of Alg. 1
+// for one cell: the lanes stride over the nodes, the 45 sums are reduced
+// through LDS in a fixed order, and every lane then holds the same 8 x 8
+// Hessian, factorises it and takes the same uniform decisions.
+//
+// Statistics, x = u_bar_x and y = u_bar_r^2/2 (Hermite in x, Laguerre in y):
+//   1, x, He_2/sqrt2, y-1, He_3/sqrt6, He_4/sqrt24, y^2/2-2y+1, x(y-1),
+//   He_2/sqrt2 (y-1).
+#include <cfloat>
+#include <cmath>
+
+#include "mem_internal.h"
+
+namespace memk {
+
+namespace {
+
+constexpr int NA = 45;          // sum sigma, 8 first moments, 36 second moments
+constexpr int AXW = 4;          // waves (cells) per workgroup
+constexpr int RSTRIDE = NA;     // odd row stride of the reduction area: no bank conflicts
+
+struct AxGauge { double w, isx, isr; };
+
+// The exponent lw + sum_i beta_i phi_i adds terms of size ~10 that largely
+// cancel where sigma is not small; in FP32 its rounding (~1e-5 absolute)
+// shows up directly as relative error of sigma.  The coordinates, the
+// statistics inside the exponent and the exponent itself are therefore
+// evaluated in FP64 (on this chip FP64 FMA runs at the rate of unpacked FP32);
+// sigma, the statistics used in the sums and the sums stay FP32.
+// u_x arrives as a pair hi + lo (the FP32 rounding of the FP64 node and its
+// remainder).
+__device__ __forceinline__ float expo9(const float4& nd, const AxGauge& g, const double (&b)[9],
+                                       float (&f)[9]) {
+  const double x = (((double)nd.x - g.w) + (double)nd.w) * g.isx;
+  const double t = (double)nd.y * g.isr;
+  const double y = 0.5 * t * t;
+  const double x2 = x * x;
+  const double ym = y - 1.0;
+  const double p2 = (x2 - 1.0) * 0.70710678118654752;
+  double h[9];
+  h[1] = x;
+  h[2] = p2;
+  h[3] = ym;
+  h[4] = x * (x2 - 3.0) * 0.40824829046386302;
+  h[5] = fma(x2, x2 - 6.0, 3.0) * 0.20412414523193151;
+  h[6] = fma(0.5 * y, y, fma(-2.0, y, 1.0));
+  h[7] = x * ym;
+  h[8] = p2 * ym;
+  double e = (double)nd.z;
+  f[0] = 1.f;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    e = fma(b[i], h[i], e);
+    f[i] = (float)h[i];
+  }
+  return (float)e;
+}
+
+// log Z(b) by the log-sum-exp of Sec. 3.1: a running (max, scaled sum) per
+// lane over groups of four nodes (one rescale per group), then a butterfly
+// over the wave.  Every lane returns the same value.
+__device__ float lse9(const float4* __restrict__ tab, int P, const AxGauge& g, const double (&b)[9],
+                      int lane) {
+  float mx = -FLT_MAX, sm = 0.f;
+  for (int q0 = lane; q0 < P; q0 += 4 * 64) {
+    float e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = q0 + 64 * k;
+      float f[9];
+      e[k] = q < P ? expo9(tab[q], g, b, f) : -INFINITY;
+    }
+    const float m = fmaxf(fmaxf(mx, fmaxf(e[0], e[1])), fmaxf(e[2], e[3]));
+    float s = sm * __expf(mx - m);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += __expf(e[k] - m);
+    sm = s;
+    mx = m;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float om = __shfl_xor(mx, off), os = __shfl_xor(sm, off);
+    const float m = fmaxf(mx, om);
+    sm = sm * __expf(mx - m) + os * __expf(om - m);
+    mx = m;
+  }
+  return mx + __logf(sm);
+}
+
+// The 45 sums of sigma, sigma phi_i and sigma phi_i phi_j (1 <= i <= j <= 8) at
+// b with sigma_p = exp(e_p - logZ), reduced over the wave in a fixed order;
+// every lane gets all 45 in A.
+__device__ void assemble9(const float4* __restrict__ tab, int P, const AxGauge& g,
+                          const double (&b)[9], float logZ, int lane, float* red,
+                          float (&A)[NA]) {
+#pragma unroll
+  for (int k = 0; k < NA; ++k) A[k] = 0.f;
+  for (int q = lane; q < P; q += 64) {
+    float f[9];
+    const float s = __expf(expo9(tab[q], g, b, f) - logZ);
+    A[0] += s;
+    float t[9];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      t[i] = s * f[i];
+      A[i] += t[i];
+    }
+    int k = 9;
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+#pragma unroll
+      for (int j = i; j < 9; ++j) {
+        A[k] = fmaf(t[i], f[j], A[k]);
+        ++k;
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < NA; ++k) red[lane * RSTRIDE + k] = A[k];
+  __builtin_amdgcn_wave_barrier();
+  float tot = 0.f;
+  if (lane < NA)
+    for (int l = 0; l < 64; ++l) tot += red[l * RSTRIDE + lane];
+  __builtin_amdgcn_wave_barrier();
+  if (lane < NA) red[64 * RSTRIDE + lane] = tot;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int k = 0; k < NA; ++k) A[k] = red[64 * RSTRIDE + k];
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Packed lower triangle of an 8 x 8 matrix: entry (i, j), j <= i, at PK(i, j).
+__host__ __device__ constexpr int PK(int i, int j) { return i * (i + 1) / 2 + j; }
+// Upper-triangle position of E_sigma[phi_i phi_j] (1 <= i <= j <= 8 as 0-based
+// i <= j < 8) among the 45 sums.
+__host__ __device__ constexpr int UA(int i, int j) { return 9 + 8 * i - i * (i - 1) / 2 + (j - i); }
+
+// Cholesky of an 8 x 8 SPD matrix in packed lower storage (in place); false on
+// a bad pivot
+template <typename T>
+__device__ __forceinline__ bool chol8(T (&A)[36], T& dmin, T& dmax) {
+  dmin = (T)3.0e38f; dmax = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    T d = A[PK(k, k)];
+#pragma unroll
+    for (int j = 0; j < k; ++j) d -= A[PK(k, j)] * A[PK(k, j)];
+    if (!(d > 0) || !isfinite(d)) return false;
+    dmin = d < dmin ? d : dmin; dmax = d > dmax ? d : dmax;
+    const T lkk = sqrt(d);
+    A[PK(k, k)] = lkk;
+#pragma unroll
+    for (int i = k + 1; i < 8; ++i) {
+      T s = A[PK(i, k)];
+#pragma unroll
+      for (int j = 0; j < k; ++j) s -= A[PK(i, j)] * A[PK(k, j)];
+      A[PK(i, k)] = s / lkk;
+    }
+  }
+  return true;
+}
+
+// direction d = -(L L^T)^-1 G and decrement 1/2 |L^-1 G|^2 (L packed)
+template <typename T>
+__device__ __forceinline__ void solve8(const T (&L)[36], const T (&G)[8], T (&d)[8], T& res) {
+  T w[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    T s = -G[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= L[PK(i, k)] * w[k];
+    w[i] = s / L[PK(i, i)];
+  }
+  res = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) res += w[i] * w[i];
+  res *= (T)0.5;
+#pragma unroll
+  for (int i = 7; i >= 0; --i) {
+    T s = w[i];
+#pragma unroll
+    for (int k = i + 1; k < 8; ++k) s -= L[PK(k, i)] * d[k];
+    d[i] = s / L[PK(i, i)];
+  }
+}
+
+// FP32 residual floor.  A residual that has not halved for AX_FLOOR_WINDOW
+// iterations has reached the rounding floor of the FP32 moments.  Where that
+// floor lies at or below half of tol_grad_loose the cell is converged: the
+// moments carry ~1e-6 of FP32 evaluation error (exponent in FP64, sums in
+// FP32), so its residual in exact arithmetic stays within tol_grad_loose.
+// A floor above that ends the cell as stagnated after AX_STALL_WINDOW
+// iterations below AX_STALL_GATE.  Above the gate there is no such window:
+// on a wide box the damped phase of Newton from the Maxwellian start can keep
+// the residual from halving for 30-40 iterations (the FP64 oracle shows the
+// same), and only the step-size and iteration-budget exits apply.
+constexpr int AX_FLOOR_WINDOW = 6;
+constexpr int AX_STALL_WINDOW = 20;
+constexpr float AX_STALL_GATE = 1e-3f;
+
+struct Lse9 { float logZ, L; };
+
+__device__ __forceinline__ Lse9 value9(const float4* tab, int P, const AxGauge& g, const float (&b)[9],
+                                       const float (&mn)[9], int lane) {
+  double bd[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) bd[i] = (double)b[i];
+  const float lz = lse9(tab, P, g, bd, lane);
+  float bm = 0.f;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) bm = fmaf(b[i], mn[i], bm);
+  return {lz, lz - bm};
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
+                                                        const float4* __restrict__ tab,
+                                                        const float* __restrict__ M,
+                                                        const float* __restrict__ gin,
+                                                        float* __restrict__ beta, SolveParams p,
+                                                        int32_t* iters_out, float* resid_out,
+                                                        uint32_t* status_out) {
+  __shared__ float sred[AXW][65 * RSTRIDE];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * AXW + wv;
+  if (c >= n) return;  // whole waves leave; no workgroup barrier follows
+  float* red = sred[wv];
+  float m[9], b[9];
+  bool fin = true;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    m[k] = M[c * 9 + k];
+    b[k] = beta[c * 9 + k];
+    fin = fin && isfinite(m[k]) && (k == 0 || isfinite(b[k]));
+  }
+  const float gw = gin[c * 3], gsx = gin[c * 3 + 1], gsr = gin[c * 3 + 2];
+  fin = fin && isfinite(gw) && isfinite(gsx) && isfinite(gsr);
+  uint32_t st = 0;
+  int it = 0;
+  float r = INFINITY;
+  if (!fin) st = MEM_ST_NONFINITE;
+  else if (!(m[0] > 0.f) || !(gsx > 0.f) || !(gsr > 0.f)) st = MEM_ST_NONREALIZABLE;
+  if (st == 0) {
+    const AxGauge g{(double)gw, 1.0 / (double)gsx, 1.0 / (double)gsr};
+    const float nn = m[0];
+    float mn[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mn[k] = m[k] / nn;
+    b[0] = nn;
+    Lse9 cur = value9(tab, P, g, b, mn, lane);
+    float d[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = 0.f;
+    float alpha = 1.f, gdot = 0.f, rbest = INFINITY;
+    int itbest = 0;
+    for (;;) {
+      if (it > 0) {  // BackTrackingLineSearch of Alg. 1
+        float a = 1.f;
+        for (int s = 0;; ++s) {
+          float bt[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) bt[k] = b[k] + a * d[k];
+          const Lse9 tr = value9(tab, P, g, bt, mn, lane);
+          const float LD = cur.L - tr.L;
+          const float gradD = -p.c * a * gdot;
+          const bool sat = (LD - gradD) >= -(p.atol + p.rtol * fabsf(LD));
+          if (sat || s >= p.max_ls) {
+#pragma unroll
+            for (int k = 1; k < 9; ++k) b[k] = bt[k];
+            cur = tr;
+            alpha = a;
+            break;
+          }
+          a *= 0.5f;
+        }
+      }
+      // moments, gradient and covariance Hessian at b (App. C)
+      float A[NA];
+      {
+        double bd[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) bd[i] = (double)b[i];
+        assemble9(tab, P, g, bd, cur.logZ, lane, red, A);
+      }
+      const float inv0 = 1.f / A[0];
+      float E[8], G[8], Hp[36];
+      r = 0.f;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        E[i] = A[1 + i] * inv0;
+        G[i] = E[i] - mn[1 + i];
+        r = fmaxf(r, fabsf(G[i]));
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) Hp[PK(i, j)] = A[UA(j, i)] * inv0 - E[i] * E[j];
+      ++it;
+      if (r < 0.5f * rbest) { rbest = r; itbest = it; }
+      float dd[8], res = 0.f;
+      bool ok;
+      {
+        float Af[36], dmin, dmax;
+#pragma unroll
+        for (int k = 0; k < 36; ++k) Af[k] = Hp[k];
+        ok = chol8(Af, dmin, dmax);
+        if (p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
+          // FP64 direction for a small pivot ratio, with the lambda*I shift
+          double Ad[36], Gd[8], ddd[8], rs, dn, dx;
+          st |= MEM_ST_FP64;
+          double lam = 0.0;
+          for (int tries = 0; tries < 41; ++tries) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+              for (int j = 0; j <= i; ++j)
+                Ad[PK(i, j)] = (double)Hp[PK(i, j)] + (i == j ? lam : 0.0);
+            ok = chol8(Ad, dn, dx);
+            if (ok) break;
+            lam = tries == 0 ? (double)p.lambda0 : lam * (double)p.lambda_mul;
+            st |= MEM_ST_SHIFTED;
+          }
+#pragma unroll
+          for (int i = 0; i < 8; ++i) Gd[i] = (double)G[i];
+          solve8(Ad, Gd, ddd, rs);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) dd[i] = (float)ddd[i];
+          res = (float)rs;
+        } else {
+          float lam = p.lambda0;
+          for (int tries = 0; tries < 40 && !ok; ++tries, lam *= p.lambda_mul) {
+            st |= MEM_ST_SHIFTED;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+              for (int j = 0; j <= i; ++j) Af[PK(i, j)] = Hp[PK(i, j)] + (i == j ? lam : 0.f);
+            ok = chol8(Af, dmin, dmax);
+          }
+          solve8(Af, G, dd, res);
+        }
+      }
+      gdot = 0.f;
+      bool dfin = ok;
+      float bmax = 0.f;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        d[i + 1] = dd[i];
+        gdot += G[i] * dd[i];
+        dfin = dfin && isfinite(dd[i]);
+        bmax = fmaxf(bmax, fabsf(b[i + 1]));
+      }
+      if (r <= p.tol_grad || (res <= p.tol_dec && r <= p.tol_loose) ||
+          (r <= 0.5f * p.tol_loose && it - itbest >= AX_FLOOR_WINDOW)) {
+        st |= MEM_ST_CONVERGED;
+        break;
+      }
+      if (cur.L < p.lmin) { st |= MEM_ST_NONREALIZABLE; break; }  // no minimiser exists
+      if (p.beta_max > 0.f && bmax > p.beta_max) { st |= MEM_ST_NONREALIZABLE; break; }
+      if (!isfinite(r) || !dfin) { st |= MEM_ST_NONFINITE; break; }
+      if (alpha <= p.alpha_min || (r <= AX_STALL_GATE && it - itbest >= AX_STALL_WINDOW)) {
+        st |= MEM_ST_STAGNATED;
+        break;
+      }
+      if (it >= p.max_iter) { st |= MEM_ST_MAXITER; break; }
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) beta[c * 9 + k] = b[k];
+    if (iters_out) iters_out[c] = it;
+    if (resid_out) resid_out[c] = r;
+    if (status_out) status_out[c] = st;
+  }
+}
+
+// Moments and fluxes from multipliers (Sec. 3.1; flux line of the moment
+// equations): M_i = beta_0 E_sigma[phi_i], F_i = beta_0 E_sigma[u_x phi_i] with
+// u_x the physical velocity of the node; E_sigma normalised by sum_p sigma_p.
+__global__ __launch_bounds__(64 * AXW) void k_axi_moments(int64_t n, int P,
+                                                          const float4* __restrict__ tab,
+                                                          const float* __restrict__ beta,
+                                                          const float* __restrict__ gin,
+                                                          float* __restrict__ M, float* __restrict__ F) {
+  __shared__ float sred[AXW][65 * 19];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * AXW + wv;
+  if (c >= n) return;
+  float* red = sred[wv];
+  double b[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) b[k] = (double)beta[c * 9 + k];
+  const AxGauge g{(double)gin[c * 3], 1.0 / (double)gin[c * 3 + 1], 1.0 / (double)gin[c * 3 + 2]};
+  const float lz = lse9(tab, P, g, b, lane);
+  float acc[18];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) acc[k] = 0.f;
+  for (int q = lane; q < P; q += 64) {
+    const float4 nd = tab[q];
+    float f[9];
+    const float s = __expf(expo9(nd, g, b, f) - lz);
+    const float su = s * (nd.x + nd.w);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      acc[i] = fmaf(s, f[i], acc[i]);
+      acc[9 + i] = fmaf(su, f[i], acc[9 + i]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 18; ++k) red[lane * 19 + k] = acc[k];
+  __builtin_amdgcn_wave_barrier();
+  if (lane < 18) {
+    float tot = 0.f;
+    for (int l = 0; l < 64; ++l) tot += red[l * 19 + lane];
+    red[64 * 19 + lane] = tot;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < 9) {
+    const float s0 = red[64 * 19];
+    const float scale = (float)b[0] / s0;
+    if (M) M[c * 9 + lane] = red[64 * 19 + lane] * scale;
+    if (F) F[c * 9 + lane] = red[64 * 19 + 9 + lane] * scale;
+  }
+}
+
+hipError_t launch_axi_solve(int64_t n, int P, const float4* tab, const float* M, const float* g,
+                            float* beta, const SolveParams& p, int32_t* iters, float* resid,
+                            uint32_t* status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axi_solve<<<(unsigned)((n + AXW - 1) / AXW), 64 * AXW, 0, s>>>(n, P, tab, M, g, beta, p, iters,
+                                                                 resid, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_axi_moments(int64_t n, int P, const float4* tab, const float* beta,
+                              const float* g, float* M, float* F, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axi_moments<<<(unsigned)((n + AXW - 1) / AXW), 64 * AXW, 0, s>>>(n, P, tab, beta, g, M, F);
+  return hipGetLastError();
+}
+
+}  // namespace memk

@@ -15,6 +15,7 @@ import re
 import numpy as np
 import pytest
 
+import mem_inputs
 import paper_2303_02898_amd as mem
 from oracle import basis, quadrature
 
@@ -58,3 +59,28 @@ def test_default_options_are_the_papers_constants():
     o = mem.default_opts()
     for key, val in gold["values"].items():
         assert getattr(o, key) == pytest.approx(val, rel=1e-6), key
+
+
+def test_axi_host_rule_matches_oracle():
+    from oracle import axisym
+    for box in (mem_inputs.AXI_MACH10_BOX,
+                dict(ux_lo=-3.1, ux_hi=4.7, ur_hi=5.3, blocks_x=3, blocks_r=2, order=5),
+                dict(ux_lo=-1.0, ux_hi=1.0, ur_hi=1.0, blocks_x=1, blocks_r=1, order=1)):
+        lib = mem.axi_host_rule(**box)
+        ref = axisym.blockwise_rule(**box)
+        for k in ("ux", "ur", "logw"):
+            assert np.max(np.abs(lib[k] - ref[k])) <= 1e-13 * max(1.0, np.max(np.abs(ref[k]))), k
+
+
+def test_axi_domain_and_bad_rules():
+    from oracle import axisym
+    got = mem.axi_domain(12.9, 1.0, 3.3, 32.1, 5, 5, 5)
+    assert np.allclose(got, axisym.integration_domain(12.9, 1.0, 3.3, 32.1, 5, 5, 5), atol=1e-14)
+    with pytest.raises(mem.MemError):
+        mem.axi_domain(0.0, -1.0, 0.0, 1.0, 1, 1, 1)
+    for bad in (dict(ux_lo=1.0, ux_hi=1.0, ur_hi=1.0, blocks_x=1, blocks_r=1, order=4),
+                dict(ux_lo=-1.0, ux_hi=1.0, ur_hi=0.0, blocks_x=1, blocks_r=1, order=4),
+                dict(ux_lo=-1.0, ux_hi=1.0, ur_hi=1.0, blocks_x=0, blocks_r=1, order=4),
+                dict(ux_lo=-1.0, ux_hi=1.0, ur_hi=1.0, blocks_x=1, blocks_r=1, order=33)):
+        with pytest.raises(mem.MemError):
+            mem.axi_host_rule(**bad)
