@@ -108,7 +108,89 @@ def cpu_baseline(M, b0, n_sample):
     el2 = time.perf_counter() - t0
     res["time_step"] = {"value": 240 * 4 / el2, "unit": "cell-steps/s",
                         "sample": f"Mach-3 shock, 240 cells, 4 LLF steps, FP64, {el2:.1f} s wall"}
+    # the oracle on the paper's own discretisation (nine statistics, Mach-10 box)
+    import mem_inputs
+    from oracle import axisym
+    rule = axisym.blockwise_rule(**mem_inputs.AXI_MACH10_BOX)
+    cells = mem_inputs.mott_smith_cells9(AXI_CELLS)
+    na = 256
+    Ma, ga = cells["M"][:na].astype(np.float32), cells["g"][:na].astype(np.float32)
+    t0 = time.perf_counter()
+    oa = axisym.solve(Ma.astype(np.float64), ga.astype(np.float64),
+                      axisym.maxwellian_beta(Ma[:, 0].astype(np.float64), ga), rule,
+                      tol_grad=1e-10, max_iter=300)
+    el3 = time.perf_counter() - t0
+    res["axi_solve"] = {"value": float(np.sum(oa["converged"])) / el3, "unit": "solves/s",
+                        "sample": f"first {na} cells of the nine-statistic Mach-10 batch, FP64 "
+                                  f"Alg. 1 cell by cell to max|G| <= 1e-10, {el3:.1f} s wall"}
     return res
+
+
+# the paper's own discretisation: Mach-10 Mott-Smith cells on its Mach-10 box
+AXI_CELLS = 65536
+# algorithmic flops per node: exponent (8 FMAs in FP64) per pass; the 45 sums
+# (sigma, 8 sigma phi_i, 36 sigma phi_i phi_j: 8 products, 9 adds, 36 FMAs)
+# per assembly pass
+AXI_FLOP_LSE = 16
+AXI_FLOP_ASM = 16 + 89
+# unpacked FP32 / FP64 vector FMA rate: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+VALU_PEAK_TFLOPS = 78.6
+
+
+def paper_discretisation(mem, torch, dev, reps=5):
+    """Alg. 1 on the paper's nine statistics and block-wise Gauss--Legendre box."""
+    import mem_inputs
+    box = mem_inputs.AXI_MACH10_BOX
+    cells = mem_inputs.mott_smith_cells9(AXI_CELLS)
+    C = AXI_CELLS
+    rule = mem.AxiRule(**box)
+    P = rule.n_nodes
+    Md = torch.tensor(cells["M"].astype(np.float32), device=dev)
+    gd = torch.tensor(cells["g"].astype(np.float32), device=dev)
+    # cold start: the Maxwellian of each cell's own Hermite gauge
+    b0 = np.zeros((C, 9), np.float32)
+    b0[:, 0] = cells["M"][:, 0]
+    b0[:, 2] = -1.0 / np.sqrt(2.0)
+    b0[:, 3] = -1.0
+    b0d = torch.tensor(b0, device=dev)
+    bg = b0d.clone()
+    it = torch.zeros(C, dtype=torch.int32, device=dev)
+    rs = torch.zeros(C, dtype=torch.float32, device=dev)
+    st = torch.zeros(C, dtype=torch.int32, device=dev)
+    rule.solve(Md, gd, bg, None, it, rs, st)   # warm-up
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        bg.copy_(b0d)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rule.solve(Md, gd, bg, None, it, rs, st)   # one kernel launch
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    rule.close()
+    ms = float(np.mean(times))
+    s = st.cpu().numpy()
+    conv = (s & mem.ST_CONVERGED) != 0
+    good = conv & (rs.cpu().numpy() <= 1e-5)
+    iters = it.cpu().numpy().astype(np.float64)
+    # every Newton iteration is one assembly pass and at least one exponent pass
+    flop = P * (np.sum(iters) * (AXI_FLOP_ASM + AXI_FLOP_LSE) + C * AXI_FLOP_LSE)
+    achieved = flop / (ms * 1e-3) / 1e12
+    return {"workload": f"nine-statistic Alg. 1, {C} Mach-10 Mott-Smith cells in their Hermite "
+                        f"gauge, box [{box['ux_lo']}, {box['ux_hi']}] x [0, {box['ur_hi']}], "
+                        f"{box['blocks_x']}x{box['blocks_r']} blocks of {box['order']}x"
+                        f"{box['order']} Gauss-Legendre points ({P} nodes), FP32 with FP64 "
+                        "exponent, cold start",
+            "ms_per_solve": ms, "solves_per_s": float(np.sum(good)) / (ms * 1e-3),
+            "converged_fraction": float(np.mean(conv)),
+            "stagnated_fraction": float(np.mean((s & mem.ST_STAGNATED) != 0)),
+            "iterations_mean": float(iters.mean()), "iterations_max": int(iters.max()),
+            "roofline": {"bound": "alu", "kernel": "k_axi_solve", "achieved": achieved,
+                         "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / VALU_PEAK_TFLOPS,
+                         "flop_note": "lower bound: one exponent pass per iteration counted, "
+                                      "statistics evaluation and exp not counted"}}
 
 
 def run_solves(mem, ctx, Md, b0d, steps, warmup, tune=True):
@@ -456,6 +538,8 @@ def main():
                     help="cells of the FP32-vs-mixed comparison (0 = skip)")
     ap.add_argument("--ragged-steps", type=int, default=200)
     ap.add_argument("--shock-max-steps", type=int, default=40000)
+    ap.add_argument("--only-paper-discretisation", action="store_true",
+                    help="run only the nine-statistic leg and print it (for profiling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 1D, shock and ragged-batch measurements")
     ap.add_argument("--tuning", default=None, metavar="DIR_WAVES,SPLIT_WANT",
@@ -477,6 +561,10 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.only_paper_discretisation:
+        print(json.dumps({"paper_discretisation": paper_discretisation(mem, torch, dev)}),
+              flush=True)
+        return
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -552,6 +640,7 @@ def main():
         line["mixed"] = mixed_comparison(mem, torch, dev, args.mixed_cells, 3, 1)
     if not args.no_extras:
         line["latency_1d"] = latency_1d(mem, torch, dev)
+        line["paper_discretisation"] = paper_discretisation(mem, torch, dev)
         line["gauge_study"] = gauge_study(mem, torch, dev)
         line["cond_study"] = cond_study(mem, torch, dev)
         line["shock"] = shock_steady(mem, torch, dev, args.shock_max_steps)
