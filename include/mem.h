@@ -382,6 +382,18 @@ MEM_API mem_err_t mem_axi_solve(mem_axi_t h, int64_t n_cells, const float* M, co
                                 float* beta, const mem_solve_opts_t* opts, int32_t* iters,
                                 float* resid, uint32_t* status, hipStream_t stream);
 
+/* Change of gauge on the nine statistics (Sec. 3.3, eqs. "Hermite Gauge
+ * moments" and "Change gauge M F"): per cell, the Hermite gauge g_H of M
+ * (w_H = w + s_x E[x], s_xH^2 = s_x^2 Var(x), s_rH^2 = s_r^2 E[u_bar_r^2]/2),
+ * then M <- T(g_H, g) M, beta_i <- sum_j T(g, g_H)_ji beta_j for i >= 1
+ * (beta_0 kept; beta may be NULL) and g <- g_H.  T is the closed form: 1D
+ * Hermite connection coefficients in x times the Laguerre dilation in
+ * y = u_bar_r^2/2, evaluated in FP64.  Cells with M_0 <= 0, a non-positive
+ * variance or non-finite values are left unchanged.  M[n][9], beta[n][9],
+ * g[n][3]: device, in place.  No handle needed. */
+MEM_API mem_err_t mem_axi_gauge(int64_t n_cells, float* M, float* beta, float* g,
+                                hipStream_t stream);
+
 /* Parameter-to-moment map (Sec. 3.1) and fluxes: M[n][9] = beta_0
  * E_sigma[phi_i], F[n][9] = beta_0 E_sigma[u_x phi_i] with u_x the physical
  * velocity of the node, at beta[n][9] and g[n][3] (E_sigma normalised by

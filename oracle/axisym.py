@@ -29,6 +29,8 @@ u_r = sqrt(u_y^2 + u_z^2), integrated over a truncated box (u_x, u_r) in
 * Hermite gauge of the nine moments (Sec. 3.3): w_H = w + s_x E[x],
   s_xH^2 = s_x^2 Var(x), s_rH^2 = s_r^2 E[u_bar_r^2]/2 with
   E[x^2] = sqrt2 M_2/n + 1 and E[u_bar_r^2] = 2 (M_3/n + 1).
+* change of gauge (Sec. 3.3): T(g', g) by projection onto the orthonormal
+  statistics with an exact Gauss--Hermite x Gauss--Laguerre rule.
 * solve: Alg. 1 through ``maxent.newton_solve`` cell by cell, each with its
   own Phi (nodes fixed in physical velocity) and the common log weights.
 
@@ -174,3 +176,51 @@ def solve(M, g, beta_init, rule, **kw):
         for k in keys:
             out[k].append(r[k][0])
     return {k: np.array(v) for k, v in out.items()}
+
+
+def _xy_coords(g_to, g_from, x, y):
+    """Gauge coordinates in g_to of the velocity whose g_from coordinates are
+    (x, y = u_bar_r^2/2)."""
+    w, sx, sr = g_from
+    w2, sx2, sr2 = g_to
+    x2 = (w + sx * x - w2) / sx2
+    y2 = y * (sr / sr2) ** 2
+    return x2, y2
+
+
+def change_matrix(g_to, g_from):
+    """T(g', g) with M(g') = T M(g) (Sec. 3.3, eq. "Change gauge M F").
+
+    Built by projection: the statistics are orthonormal under x ~ N(0, 1),
+    y ~ Exp(1), and phi_i(u_bar') is a polynomial in the span, so
+    T_ij = E[phi_i(u_bar'(x, y)) phi_j(x, y)], integrated exactly with
+    Gauss--Hermite in x and Gauss--Laguerre in y.
+    """
+    xh, wh = np.polynomial.hermite_e.hermegauss(12)
+    wh = wh / math.sqrt(2.0 * math.pi)
+    yl, wl = np.polynomial.laguerre.laggauss(8)
+    X, Y = np.meshgrid(xh, yl, indexing="ij")
+    W = np.outer(wh, wl).ravel()
+    X, Y = X.ravel(), Y.ravel()
+    Pj = statistics(X, np.sqrt(2.0 * Y))
+    x2, y2 = _xy_coords(g_to, g_from, X, Y)
+    Pi = statistics(x2, np.sqrt(2.0 * y2))
+    return (Pi * W[:, None]).T @ Pj
+
+
+def to_hermite_gauge(M, beta, g):
+    """Moments (and multipliers) moved into the Hermite gauge of M (Sec. 3.3).
+
+    M' = T(g_H, g) M; beta'_i = sum_j T(g, g_H)_ji beta_j for i >= 1, beta'_0 = beta_0.
+    """
+    M = np.asarray(M, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    gH = hermite_gauge(M, g)
+    Mo = np.empty_like(M)
+    bo = None if beta is None else np.array(beta, dtype=np.float64, copy=True)
+    for c in range(M.shape[0]):
+        Mo[c] = change_matrix(gH[c], g[c]) @ M[c]
+        if bo is not None:
+            Ti = change_matrix(g[c], gH[c])
+            bo[c, 1:] = (Ti.T @ np.asarray(beta[c], np.float64))[1:]
+    return Mo, bo, gH

@@ -106,6 +106,7 @@ def load_library():
         "mem_axi_n_nodes": ([P], _c_i64),
         "mem_axi_solve": ([P, _c_i64, P, P, P, ctypes.POINTER(SolveOpts), P, P, P, P], E),
         "mem_axi_moments": ([P, _c_i64, P, P, P, P, P], E),
+        "mem_axi_gauge": ([_c_i64, P, P, P, P], E),
         "mem_profile_enable": ([P, _c_i32], E),
         "mem_profile_read": ([P, _c_i32, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(_c_i64)], E),
@@ -416,6 +417,15 @@ class AxiRule:
             _ptr(beta, torch.float32, (9,), "beta"), o, _ptr(iters, torch.int32),
             _ptr(resid, torch.float32), _ptr(status, torch.int32), _stream(stream)), "mem_axi_solve")
         return iters, resid, status
+
+    def gauge(self, M, beta, g, stream=None):
+        """Move M (and beta, if given) into the Hermite gauge of M; g updated."""
+        import torch
+        n = M.shape[0]
+        self._check(self._lib.mem_axi_gauge(
+            n, _ptr(M, torch.float32, (9,), "M"),
+            _ptr(beta, torch.float32, (9,), "beta") if beta is not None else None,
+            _ptr(g, torch.float32, (3,), "g"), _stream(stream)), "mem_axi_gauge")
 
     def moments(self, beta, g, want_flux=True, stream=None):
         import torch

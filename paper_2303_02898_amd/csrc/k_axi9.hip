@@ -441,6 +441,104 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_moments(int64_t n, int P,
   }
 }
 
+// ---- change of gauge (Sec. 3.3) ------------------------------------------------
+// Statistic i is p_a(x) l_k(y) with p_a = He_a/sqrt(a!) and l_0 = 1,
+// l_1 = y - 1, l_2 = y^2/2 - 2y + 1; (a, k) per index:
+__constant__ int AX_A[9] = {0, 1, 2, 0, 3, 4, 0, 1, 2};
+__constant__ int AX_K[9] = {0, 0, 0, 1, 0, 0, 2, 1, 1};
+
+// p_n(a x + b) = sum_k t[n][k] p_k(x): t = C(n,k) a^k h_{n-k}(b; a^2 - 1) sqrt(k!/n!),
+// h_m(b; c) = E[He_m(X)], X ~ N(b, 1 + c)
+__device__ __forceinline__ void conn_x(double a, double b, double (&t)[5][5]) {
+  const double c = a * a - 1.0;
+  const double h[5] = {1.0, b, b * b + c, b * b * b + 3.0 * b * c,
+                       b * b * b * b + 6.0 * b * b * c + 3.0 * c * c};
+  const double binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0},
+                              {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+  const double sf[5] = {1.0, 1.0, 1.41421356237309505, 2.44948974278317810,
+                        4.89897948556635620};
+  double ak = 1.0;
+  double apow[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) { apow[k] = ak; ak *= a; }
+#pragma unroll
+  for (int n = 0; n < 5; ++n)
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      t[n][k] = k <= n ? binom[n][k] * apow[k] * h[n - k] * sf[k] / sf[n] : 0.0;
+}
+
+// l_k(c y) = sum_k' r[k][k'] l_k'(y) (dilation of the radial variable)
+__device__ __forceinline__ void conn_y(double c, double (&r)[3][3]) {
+  r[0][0] = 1.0; r[0][1] = 0.0; r[0][2] = 0.0;
+  r[1][0] = c - 1.0; r[1][1] = c; r[1][2] = 0.0;
+  r[2][0] = (c - 1.0) * (c - 1.0); r[2][1] = 2.0 * c * (c - 1.0); r[2][2] = c * c;
+}
+
+// T(g', g)_ij = t[a_i][a_j] r[k_i][k_j] with a = s_x/s_x', b = (w - w')/s_x',
+// c = (s_r/s_r')^2
+__device__ __forceinline__ double tij(const double (&t)[5][5], const double (&r)[3][3], int i,
+                                      int j) {
+  return t[AX_A[i]][AX_A[j]] * r[AX_K[i]][AX_K[j]];
+}
+
+// One thread per cell: Hermite gauge of the nine moments, M <- T(g_H, g) M,
+// beta_i <- sum_j T(g, g_H)_ji beta_j (i >= 1), g <- g_H.  Cells with n <= 0,
+// a non-positive variance or non-finite values are left unchanged.
+__global__ void k_axi_gauge(int64_t n, float* __restrict__ M, float* __restrict__ beta,
+                            float* __restrict__ g) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double m[9];
+  bool fin = true;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    m[k] = (double)M[c * 9 + k];
+    fin = fin && isfinite(m[k]);
+  }
+  const double w = g[c * 3], sx = g[c * 3 + 1], sr = g[c * 3 + 2];
+  if (!fin || !(m[0] > 0.0) || !(sx > 0.0) || !(sr > 0.0)) return;
+  const double m1 = m[1] / m[0];
+  const double exx = 1.41421356237309505 * m[2] / m[0] + 1.0;
+  const double err = 2.0 * (m[3] / m[0] + 1.0);
+  const double vx = exx - m1 * m1;
+  if (!(vx > 0.0) || !(err > 0.0) || !isfinite(vx) || !isfinite(err)) return;
+  const double wH = w + sx * m1, sxH = sx * sqrt(vx), srH = sr * sqrt(0.5 * err);
+  double t[5][5], r[3][3];
+  conn_x(sx / sxH, (w - wH) / sxH, t);
+  conn_y((sr / srH) * (sr / srH), r);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc += tij(t, r, i, j) * m[j];
+    M[c * 9 + i] = (float)acc;
+  }
+  if (beta) {
+    double b[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) b[k] = (double)beta[c * 9 + k];
+    conn_x(sxH / sx, (wH - w) / sx, t);
+    conn_y((srH / sr) * (srH / sr), r);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 1; j < 9; ++j) acc += tij(t, r, j, i) * b[j];
+      beta[c * 9 + i] = (float)acc;
+    }
+  }
+  g[c * 3] = (float)wH;
+  g[c * 3 + 1] = (float)sxH;
+  g[c * 3 + 2] = (float)srH;
+}
+
+hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axi_gauge<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, M, beta, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_axi_solve(int64_t n, int P, const float4* tab, const float* M, const float* g,
                             float* beta, const SolveParams& p, int32_t* iters, float* resid,
                             uint32_t* status, hipStream_t s) {

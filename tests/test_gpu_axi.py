@@ -198,3 +198,43 @@ def test_axi_full_size_sample(rule, orule):
     sub = {k: v[cs] for k, v in ref.items()}
     ratio, berr = _check(bg[cs], Ms[cs], gs[cs], sub, orule, "sample")
     assert ratio.max() <= 1.0 and berr.max() <= 1e-3
+
+
+def test_axi_gauge_then_solve_matches_oracle(rule, orule):
+    print("\n[gpu] axi change of gauge + solve, 97 cells given in off-Hermite gauges", flush=True)
+    C = 97
+    cells = mem_inputs.mott_smith_cells9(C, mach_lo=1.5, mach_hi=10.0, replica=4)
+    gh = cells["g"]
+    g_in = np.stack([gh[:, 0] + 0.3 * gh[:, 1], 1.2 * gh[:, 1], 0.85 * gh[:, 2]], axis=1)
+    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(cells["mach"])
+    nu = cells["nu"]
+    M_in = ((1.0 - nu)[:, None] * mem_inputs.gaussian_moments9(n1, v1, T1, T1, g_in)
+            + nu[:, None] * mem_inputs.gaussian_moments9(n2, v2, T2, T2, g_in))
+    M_in, g_in = f32(M_in).astype(np.float64), f32(g_in).astype(np.float64)
+    b_in = axisym.maxwellian_beta(M_in[:, 0], g_in)
+    b_in[:, 1] = 0.05
+    b_in = f32(b_in).astype(np.float64)
+    Md, bd, gd = dev(M_in), dev(b_in), dev(g_in)
+    rule.gauge(Md, bd, gd)
+    torch.cuda.synchronize()
+    Mo, bo, gH = axisym.to_hermite_gauge(M_in, b_in, g_in)
+    eg = np.max(np.abs(gd.cpu().numpy() - gH) / np.abs(gH).clip(1e-3))
+    em = np.max(np.abs(Md.cpu().numpy() - Mo) / M_in[:, :1])
+    eb = np.max(np.abs(bd.cpu().numpy() - bo) / np.maximum(1.0, np.abs(bo)))
+    print(f"gauge err {eg:.2e}, moments err {em:.2e}, beta err {eb:.2e}", flush=True)
+    assert eg < 1e-5 and em < 2e-5 and eb < 2e-5
+    # the gauge reproduces the mixture's exact Hermite gauge
+    assert np.max(np.abs(gd.cpu().numpy() - gh) / gh.clip(1e-3)) < 1e-5
+    # then Alg. 1 in that gauge, from the Maxwellian start
+    Mh, gh32 = Md.cpu().numpy().astype(np.float64), gd.cpu().numpy().astype(np.float64)
+    b0 = axisym.maxwellian_beta(Mh[:, 0], gh32)
+    bs = dev(b0)
+    iters, resid, status = rule.solve(Md, gd, bs)
+    torch.cuda.synchronize()
+    ref = axisym.solve(Mh, gh32, b0, orule, tol_grad=1e-11, max_iter=300)
+    assert np.all(ref["converged"])
+    bg = bs.cpu().numpy().astype(np.float64)
+    conv = _split(status.cpu().numpy(), bg, Mh, gh32, ref, orule)
+    sub = {k: v[conv] for k, v in ref.items()}
+    ratio, berr = _check(bg[conv], Mh[conv], gh32[conv], sub, orule, "gauge+solve")
+    assert ratio.max() <= 1.0 and berr.max() <= 1e-3

@@ -169,3 +169,42 @@ def test_integration_domain_reproduces_printed_boxes():
         box = axisym.integration_domain(float(v1), float(T1), float(v2), float(T2),
                                         c["n_a"], c["n_b"], c["n_r"])
         assert [round(b, 1) for b in box] == c["box"]
+
+
+G_A, G_B, G_C = (0.3, 1.1, 0.9), (-1.2, 1.7, 1.4), (2.0, 0.8, 1.3)
+
+
+def test_change_matrix_group_and_identity():
+    assert np.max(np.abs(axisym.change_matrix(G_A, G_A) - np.eye(9))) < 1e-13
+    T = axisym.change_matrix(G_C, G_B) @ axisym.change_matrix(G_B, G_A)
+    assert np.max(np.abs(T - axisym.change_matrix(G_C, G_A))) < 1e-12
+    # lower triangular in (x degree, y degree): statistic (a, k) only draws on a' <= a, k' <= k
+    deg = [(0, 0), (1, 0), (2, 0), (0, 1), (3, 0), (4, 0), (0, 2), (1, 1), (2, 1)]
+    T = axisym.change_matrix(G_B, G_A)
+    for i, (a, k) in enumerate(deg):
+        for j, (a2, k2) in enumerate(deg):
+            if a2 > a or k2 > k:
+                assert abs(T[i, j]) < 1e-13
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_change_of_gauge_moves_maxwellian_moments(case):
+    n, v, T, _ = case
+    Ma = _closed_form(n, v, T, G_A)
+    Mb = axisym.change_matrix(G_B, G_A) @ Ma
+    assert np.max(np.abs(Mb - _closed_form(n, v, T, G_B))) < 1e-11
+
+
+def test_to_hermite_gauge_keeps_the_distribution():
+    rule = _wide_rule()
+    beta = _maxwellian_beta_in_gauge(1.2, 0.7, 1.4, G_A)
+    beta[4] += 0.01
+    beta[5] -= 0.004
+    beta[8] += 0.003
+    M = axisym.moments(beta[None, :], np.array([G_A]), rule)
+    Mo, bo, gH = axisym.to_hermite_gauge(M, beta[None, :], np.array([G_A]))
+    # the same distribution: its moments in the Hermite gauge from the moved beta
+    M2 = axisym.moments(bo, gH, rule)
+    assert np.max(np.abs(M2 - Mo)) < 1e-10
+    # the Hermite gauge zeroes the first and the two second-degree moments
+    assert np.max(np.abs(Mo[0, 1:4])) < 1e-12
