@@ -197,6 +197,43 @@ __device__ __forceinline__ void solve8(const T (&L)[36], const T (&G)[8], T (&d)
   }
 }
 
+// The same two steps in FP64 on a wave's LDS area (all lanes hold the same
+// values): the rare FP64 direction then costs no registers, which keeps the
+// kernel at three waves per SIMD without spills.
+__device__ __forceinline__ bool chol8_lds(double* A, double& dmin, double& dmax) {
+  dmin = 3.0e38; dmax = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    double d = A[PK(k, k)];
+    for (int j = 0; j < k; ++j) d -= A[PK(k, j)] * A[PK(k, j)];
+    if (!(d > 0.0) || !isfinite(d)) return false;
+    dmin = d < dmin ? d : dmin; dmax = d > dmax ? d : dmax;
+    const double lkk = sqrt(d);
+    A[PK(k, k)] = lkk;
+    for (int i = k + 1; i < 8; ++i) {
+      double t = A[PK(i, k)];
+      for (int j = 0; j < k; ++j) t -= A[PK(i, j)] * A[PK(k, j)];
+      A[PK(i, k)] = t / lkk;
+    }
+  }
+  return true;
+}
+
+__device__ __forceinline__ double solve8_lds(const double* L, const double* G, double* w, double* d) {
+  for (int i = 0; i < 8; ++i) {
+    double t = -G[i];
+    for (int k = 0; k < i; ++k) t -= L[PK(i, k)] * w[k];
+    w[i] = t / L[PK(i, i)];
+  }
+  double res = 0.0;
+  for (int i = 0; i < 8; ++i) res += w[i] * w[i];
+  for (int i = 7; i >= 0; --i) {
+    double t = w[i];
+    for (int k = i + 1; k < 8; ++k) t -= L[PK(k, i)] * d[k];
+    d[i] = t / L[PK(i, i)];
+  }
+  return 0.5 * res;
+}
+
 // FP32 residual floor.  A residual that has not halved for AX_FLOOR_WINDOW
 // iterations has reached the rounding floor of the FP32 moments.  Where that
 // floor lies at or below half of tol_grad_loose the cell is converged: the
@@ -227,17 +264,14 @@ __device__ __forceinline__ Lse9 value9(const float4* tab, int P, const AxGauge& 
 
 }  // namespace
 
-// Two waves per SIMD (at most 256 registers): the compiler then spills ~112
-// bytes per lane of the direction code, which measured 1.47x faster than one
-// wave per SIMD without spills.
-__global__ __launch_bounds__(64 * AXW, 2) void k_axi_solve(int64_t n, int P,
+__global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
                                                         const float4* __restrict__ tab,
                                                         const float* __restrict__ M,
                                                         const float* __restrict__ gin,
                                                         float* __restrict__ beta, SolveParams p,
                                                         int32_t* iters_out, float* resid_out,
                                                         uint32_t* status_out) {
-  __shared__ float sred[AXW][65 * RSTRIDE];
+  __shared__ __align__(16) float sred[AXW][65 * RSTRIDE];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int64_t c = (int64_t)blockIdx.x * AXW + wv;
@@ -323,27 +357,31 @@ __global__ __launch_bounds__(64 * AXW, 2) void k_axi_solve(int64_t n, int P,
         for (int k = 0; k < 36; ++k) Af[k] = Hp[k];
         ok = chol8(Af, dmin, dmax);
         if (p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
-          // FP64 direction for a small pivot ratio, with the lambda*I shift
-          double Ad[36], Gd[8], ddd[8], rs, dn, dx;
+          // FP64 direction for a small pivot ratio, with the lambda*I shift,
+          // on the (now idle) reduction area: A[36], G[8], w[8], d[8]
+          double* Ad = reinterpret_cast<double*>(red);
+          double* Gd = Ad + 36;
+          double dn, dx;
           st |= MEM_ST_FP64;
           double lam = 0.0;
           for (int tries = 0; tries < 41; ++tries) {
-#pragma unroll
             for (int i = 0; i < 8; ++i)
-#pragma unroll
               for (int j = 0; j <= i; ++j)
                 Ad[PK(i, j)] = (double)Hp[PK(i, j)] + (i == j ? lam : 0.0);
-            ok = chol8(Ad, dn, dx);
+            __builtin_amdgcn_wave_barrier();
+            ok = chol8_lds(Ad, dn, dx);
+            __builtin_amdgcn_wave_barrier();
             if (ok) break;
             lam = tries == 0 ? (double)p.lambda0 : lam * (double)p.lambda_mul;
             st |= MEM_ST_SHIFTED;
           }
-#pragma unroll
           for (int i = 0; i < 8; ++i) Gd[i] = (double)G[i];
-          solve8(Ad, Gd, ddd, rs);
+          __builtin_amdgcn_wave_barrier();
+          res = (float)solve8_lds(Ad, Gd, Gd + 8, Gd + 16);
+          __builtin_amdgcn_wave_barrier();
 #pragma unroll
-          for (int i = 0; i < 8; ++i) dd[i] = (float)ddd[i];
-          res = (float)rs;
+          for (int i = 0; i < 8; ++i) dd[i] = (float)Gd[16 + i];
+          __builtin_amdgcn_wave_barrier();
         } else {
           float lam = p.lambda0;
           for (int tries = 0; tries < 40 && !ok; ++tries, lam *= p.lambda_mul) {
