@@ -382,6 +382,17 @@ MEM_API mem_err_t mem_axi_solve(mem_axi_t h, int64_t n_cells, const float* M, co
                                 float* beta, const mem_solve_opts_t* opts, int32_t* iters,
                                 float* resid, uint32_t* status, hipStream_t stream);
 
+/* Characteristic speeds (Sec. 3.4, the local Lax--Friedrichs bound):
+ * lam[n][2] = (min, max) eigenvalue of dF/dM in physical velocity at beta[n][9]
+ * and g[n][3]: the extreme generalised eigenvalues of (E[x phi phi^T],
+ * E[phi phi^T]) in gauge coordinates (FP32 sums, FP64 reduction and cyclic
+ * Jacobi), mapped to w_x + s_x lambda and clamped to the node span
+ * [min u_x, max u_x], where every eigenvalue of the quadrature pencil lies; a
+ * pencil that cannot be reduced gives the node span itself.  One wave per
+ * cell.  Device memory, asynchronous. */
+MEM_API mem_err_t mem_axi_speeds(mem_axi_t h, int64_t n_cells, const float* beta,
+                                 const float* g, float* lam, hipStream_t stream);
+
 /* Change of gauge on the nine statistics (Sec. 3.3, eqs. "Hermite Gauge
  * moments" and "Change gauge M F"): per cell, the Hermite gauge g_H of M
  * (w_H = w + s_x E[x], s_xH^2 = s_x^2 Var(x), s_rH^2 = s_r^2 E[u_bar_r^2]/2),

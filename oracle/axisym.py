@@ -224,3 +224,23 @@ def to_hermite_gauge(M, beta, g):
             Ti = change_matrix(g[c], gH[c])
             bo[c, 1:] = (Ti.T @ np.asarray(beta[c], np.float64))[1:]
     return Mo, bo, gH
+
+
+def char_speeds(beta, g, rule):
+    """(min, max) eigenvalue of dF/dM per cell (the local Lax--Friedrichs speeds
+    of Sec. 3.4): the extreme generalised eigenvalues of (E[x phi phi^T],
+    E[phi phi^T]) in gauge coordinates, mapped to physical velocity
+    w_x + s_x lambda.  scipy's generalised symmetric eigen-solver."""
+    import scipy.linalg
+    beta = np.asarray(beta, dtype=np.float64)
+    out = np.empty((beta.shape[0], 2))
+    for c in range(beta.shape[0]):
+        w, sx, sr = g[c]
+        Phi = cell_phi(rule, g[c])
+        sig = maxent.sigma(beta[c:c + 1], Phi, rule["logw"])[0]
+        x = (rule["ux"] - w) / sx
+        B = (Phi * sig[:, None]).T @ Phi
+        C = (Phi * (sig * x)[:, None]).T @ Phi
+        ev = scipy.linalg.eigh(C, B, eigvals_only=True)
+        out[c] = (w + sx * ev[0], w + sx * ev[-1])
+    return out

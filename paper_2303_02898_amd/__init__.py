@@ -107,6 +107,7 @@ def load_library():
         "mem_axi_solve": ([P, _c_i64, P, P, P, ctypes.POINTER(SolveOpts), P, P, P, P], E),
         "mem_axi_moments": ([P, _c_i64, P, P, P, P, P], E),
         "mem_axi_gauge": ([_c_i64, P, P, P, P], E),
+        "mem_axi_speeds": ([P, _c_i64, P, P, P, P], E),
         "mem_profile_enable": ([P, _c_i32], E),
         "mem_profile_read": ([P, _c_i32, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(_c_i64)], E),
@@ -417,6 +418,16 @@ class AxiRule:
             _ptr(beta, torch.float32, (9,), "beta"), o, _ptr(iters, torch.int32),
             _ptr(resid, torch.float32), _ptr(status, torch.int32), _stream(stream)), "mem_axi_solve")
         return iters, resid, status
+
+    def speeds(self, beta, g, stream=None):
+        """(min, max) characteristic speed per cell in physical velocity."""
+        import torch
+        n = beta.shape[0]
+        lam = torch.empty(n, 2, dtype=torch.float32, device=beta.device)
+        self._check(self._lib.mem_axi_speeds(
+            self._h, n, _ptr(beta, torch.float32, (9,), "beta"), _ptr(g, torch.float32, (3,), "g"),
+            lam.data_ptr(), _stream(stream)), "mem_axi_speeds")
+        return lam
 
     def gauge(self, M, beta, g, stream=None):
         """Move M (and beta, if given) into the Hermite gauge of M; g updated."""

@@ -16,6 +16,7 @@ struct mem_axi_s {
   std::vector<double> ux, ur, logw;
   float4* d_tab = nullptr;  // (u_x, u_r, log w, u_x - fl(u_x)) per node
   float lmin = 0.f;
+  float ux_min = 0.f, ux_max = 0.f;  // node span in u_x
 };
 
 namespace {
@@ -170,6 +171,8 @@ mem_err_t mem_axi_create(const mem_axi_rule_t* rule, mem_axi_t* out) {
     tab[q] = make_float4(hi, (float)h->ur[q], (float)h->logw[q], (float)(h->ux[q] - (double)hi));
     mn = std::min(mn, h->logw[q]);
   }
+  h->ux_min = (float)*std::min_element(h->ux.begin(), h->ux.end());
+  h->ux_max = (float)*std::max_element(h->ux.begin(), h->ux.end());
   // a dual value below min_p log w_p certifies that no minimiser exists
   h->lmin = (float)(mn - 1e-3 * (1.0 + std::fabs(mn)));
   if (hipMalloc((void**)&h->d_tab, tab.size() * sizeof(float4)) != hipSuccess) {
@@ -208,6 +211,17 @@ mem_err_t mem_axi_solve(mem_axi_t h, int64_t n, const float* M, const float* g, 
       hipSuccess)
     return MEM_ERR_HIP;
   return MEM_OK;
+}
+
+mem_err_t mem_axi_speeds(mem_axi_t h, int64_t n, const float* beta, const float* g, float* lam,
+                         hipStream_t s) {
+  if (!h || n < 0 || n > (int64_t)INT32_MAX - 4) return MEM_ERR_INVALID_ARG;
+  if (n == 0) return MEM_OK;
+  if (!beta || !g || !lam) return MEM_ERR_INVALID_ARG;
+  return launch_axi_speeds(n, (int)h->P, h->d_tab, beta, g, h->ux_min, h->ux_max, lam, s) ==
+                 hipSuccess
+             ? MEM_OK
+             : MEM_ERR_HIP;
 }
 
 mem_err_t mem_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s) {

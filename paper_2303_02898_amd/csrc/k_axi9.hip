@@ -571,6 +571,158 @@ __global__ void k_axi_gauge(int64_t n, float* __restrict__ M, float* __restrict_
   g[c * 3 + 2] = (float)srH;
 }
 
+// ---- characteristic speeds (Sec. 3.4) ----------------------------------------
+// dF/dM has the eigenvalues of the pencil (C, B), B = E[phi phi^T] and
+// C = E[x phi phi^T] in gauge coordinates x = u_bar_x; physical speeds are
+// w_x + s_x lambda.  One wave per cell accumulates the 2 x 45 sums, reduced in
+// LDS; lane 0 then reduces the pencil to A = L^-1 C L^-T (B = L L^T) and runs
+// cyclic Jacobi rotations (Golub & Van Loan, symmetric Schur decomposition) on
+// A in FP64 in LDS.  A pencil whose B is not positive definite leaves the
+// node span [min u_x, max u_x] as the speeds (every eigenvalue lies there).
+constexpr int SP_NS = 90;
+constexpr int SP_ROW = SP_NS + 1;  // odd row stride
+
+__global__ __launch_bounds__(64) void k_axi_speeds(int64_t n, int P, const float4* __restrict__ tab,
+                                                   const float* __restrict__ beta,
+                                                   const float* __restrict__ gin, float ux_min,
+                                                   float ux_max, float* __restrict__ lam) {
+  __shared__ __align__(16) float red[65 * SP_ROW];
+  __shared__ double W[3 * 81];
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  if (c >= n) return;
+  double b[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) b[k] = (double)beta[c * 9 + k];
+  const double gw = gin[c * 3], gsx = gin[c * 3 + 1];
+  const AxGauge g{gw, 1.0 / gsx, 1.0 / (double)gin[c * 3 + 2]};
+  const float lz = lse9(tab, P, g, b, lane);
+  float acc[SP_NS];
+#pragma unroll
+  for (int k = 0; k < SP_NS; ++k) acc[k] = 0.f;
+  for (int q = lane; q < P; q += 64) {
+    const float4 nd = tab[q];
+    float f[9];
+    const float sg = __expf(expo9(nd, g, b, f) - lz);
+    const float x = f[1];
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float t = sg * f[i];
+      const float tx = t * x;
+#pragma unroll
+      for (int j = i; j < 9; ++j) {
+        acc[k] = fmaf(t, f[j], acc[k]);
+        acc[45 + k] = fmaf(tx, f[j], acc[45 + k]);
+        ++k;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < SP_NS; ++k) red[lane * SP_ROW + k] = acc[k];
+  __syncthreads();
+  for (int k = lane; k < SP_NS; k += 64) {
+    float t = 0.f;
+    for (int l = 0; l < 64; ++l) t += red[l * SP_ROW + k];
+    red[64 * SP_ROW + k] = t;
+  }
+  __syncthreads();
+  if (lane != 0) return;
+  const float* S = red + 64 * SP_ROW;
+  double* B = W;
+  double* C = W + 81;
+  double* A = W + 162;
+  {
+    int k = 0;
+    for (int i = 0; i < 9; ++i)
+      for (int j = i; j < 9; ++j) {
+        B[i * 9 + j] = B[j * 9 + i] = (double)S[k];
+        C[i * 9 + j] = C[j * 9 + i] = (double)S[45 + k];
+        ++k;
+      }
+  }
+  float lo = ux_min, hi = ux_max;
+  bool ok = true;
+  // B = L L^T (L in the lower triangle of B)
+  for (int k = 0; k < 9 && ok; ++k) {
+    double d = B[k * 9 + k];
+    for (int j = 0; j < k; ++j) d -= B[k * 9 + j] * B[k * 9 + j];
+    if (!(d > 0.0) || !isfinite(d)) { ok = false; break; }
+    const double l = sqrt(d);
+    B[k * 9 + k] = l;
+    for (int i = k + 1; i < 9; ++i) {
+      double t = B[i * 9 + k];
+      for (int j = 0; j < k; ++j) t -= B[i * 9 + j] * B[k * 9 + j];
+      B[i * 9 + k] = t / l;
+    }
+  }
+  if (ok) {
+    // Y = L^-1 C (columnwise forward substitution), then A = L^-1 Y^T
+    for (int col = 0; col < 9; ++col)
+      for (int i = 0; i < 9; ++i) {
+        double t = C[i * 9 + col];
+        for (int j = 0; j < i; ++j) t -= B[i * 9 + j] * A[j * 9 + col];
+        A[i * 9 + col] = t / B[i * 9 + i];
+      }
+    for (int i = 0; i < 9; ++i)
+      for (int j = 0; j < 9; ++j) C[i * 9 + j] = A[j * 9 + i];  // C <- Y^T
+    for (int col = 0; col < 9; ++col)
+      for (int i = 0; i < 9; ++i) {
+        double t = C[i * 9 + col];
+        for (int j = 0; j < i; ++j) t -= B[i * 9 + j] * A[j * 9 + col];
+        A[i * 9 + col] = t / B[i * 9 + i];
+      }
+    for (int i = 0; i < 9; ++i)  // symmetrise the rounding
+      for (int j = i + 1; j < 9; ++j) A[i * 9 + j] = A[j * 9 + i] = 0.5 * (A[i * 9 + j] + A[j * 9 + i]);
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      double off = 0.0, nrm = 0.0;
+      for (int i = 0; i < 9; ++i)
+        for (int j = 0; j < 9; ++j) {
+          const double v = A[i * 9 + j] * A[i * 9 + j];
+          nrm += v;
+          if (i != j) off += v;
+        }
+      if (!(off > 1e-30 * nrm)) break;
+      for (int p = 0; p < 8; ++p)
+        for (int q = p + 1; q < 9; ++q) {
+          const double apq = A[p * 9 + q];
+          if (fabs(apq) < 1e-300) continue;
+          const double th = (A[q * 9 + q] - A[p * 9 + p]) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+          for (int k = 0; k < 9; ++k) {  // columns p, q
+            const double akp = A[k * 9 + p], akq = A[k * 9 + q];
+            A[k * 9 + p] = cs * akp - sn * akq;
+            A[k * 9 + q] = sn * akp + cs * akq;
+          }
+          for (int k = 0; k < 9; ++k) {  // rows p, q
+            const double apk = A[p * 9 + k], aqk = A[q * 9 + k];
+            A[p * 9 + k] = cs * apk - sn * aqk;
+            A[q * 9 + k] = sn * apk + cs * aqk;
+          }
+        }
+    }
+    double emin = A[0], emax = A[0];
+    for (int i = 1; i < 9; ++i) {
+      emin = fmin(emin, A[i * 9 + i]);
+      emax = fmax(emax, A[i * 9 + i]);
+    }
+    if (isfinite(emin) && isfinite(emax)) {
+      lo = fmaxf((float)(gw + gsx * emin), ux_min);
+      hi = fminf((float)(gw + gsx * emax), ux_max);
+    }
+  }
+  lam[c * 2] = lo;
+  lam[c * 2 + 1] = hi;
+}
+
+hipError_t launch_axi_speeds(int64_t n, int P, const float4* tab, const float* beta, const float* g,
+                             float ux_min, float ux_max, float* lam, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axi_speeds<<<(unsigned)n, 64, 0, s>>>(n, P, tab, beta, g, ux_min, ux_max, lam);
+  return hipGetLastError();
+}
+
 hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_axi_gauge<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, M, beta, g);

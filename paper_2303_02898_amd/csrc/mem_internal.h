@@ -152,6 +152,8 @@ hipError_t launch_gauge1(mem_ctx_t c, int64_t n, float* M, float* beta, float* g
 hipError_t launch_axi_solve(int64_t n, int P, const float4* tab, const float* M, const float* g,
                             float* beta, const SolveParams& p, int32_t* iters, float* resid,
                             uint32_t* status, hipStream_t s);
+hipError_t launch_axi_speeds(int64_t n, int P, const float4* tab, const float* beta, const float* g,
+                             float ux_min, float ux_max, float* lam, hipStream_t s);
 hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s);
 hipError_t launch_axi_moments(int64_t n, int P, const float4* tab, const float* beta,
                               const float* g, float* M, float* F, hipStream_t s);

@@ -238,3 +238,32 @@ def test_axi_gauge_then_solve_matches_oracle(rule, orule):
     sub = {k: v[conv] for k, v in ref.items()}
     ratio, berr = _check(bg[conv], Mh[conv], gh32[conv], sub, orule, "gauge+solve")
     assert ratio.max() <= 1.0 and berr.max() <= 1e-3
+
+
+def test_axi_speeds_match_oracle_and_hermite_roots(rule, orule):
+    print("\n[gpu] axi characteristic speeds", flush=True)
+    # Maxwellians in their Hermite gauge on a wide box: +-sqrt(5 + sqrt(10)) s_x
+    box = dict(ux_lo=-22.0, ux_hi=22.0, ur_hi=22.0, blocks_x=22, blocks_r=11, order=12)
+    wide = mem.AxiRule(**box)
+    nvT = np.array([[1.4, 0.8, 2.3], [0.7, -1.5, 0.6], [2.0, 0.0, 1.0]])
+    g = np.stack([nvT[:, 1], np.sqrt(nvT[:, 2]), np.sqrt(nvT[:, 2])], axis=1)
+    beta = axisym.maxwellian_beta(nvT[:, 0], g)
+    lam = wide.speeds(dev(beta), dev(g)).cpu().numpy()
+    torch.cuda.synchronize()
+    wide.close()
+    r5 = math.sqrt(5.0 + math.sqrt(10.0))
+    ref = np.stack([g[:, 0] - g[:, 1] * r5, g[:, 0] + g[:, 1] * r5], axis=1)
+    e0 = np.max(np.abs(lam - ref) / np.maximum(1.0, np.abs(ref)))
+    # Mott-Smith solutions on the paper's box against the oracle
+    C = 41
+    cells = mem_inputs.mott_smith_cells9(C, mach_lo=1.5, mach_hi=10.0, replica=6)
+    gm = f32(cells["g"]).astype(np.float64)
+    sol = axisym.solve(cells["M"], gm, axisym.maxwellian_beta(cells["M"][:, 0], gm), orule,
+                       tol_grad=1e-10, max_iter=300)
+    bm = f32(sol["beta"]).astype(np.float64)
+    lam2 = rule.speeds(dev(bm), dev(gm)).cpu().numpy()
+    torch.cuda.synchronize()
+    ref2 = axisym.char_speeds(bm, gm, orule)
+    e1 = np.max(np.abs(lam2 - ref2) / np.maximum(1.0, np.abs(ref2)))
+    print(f"Maxwellian speed err {e0:.2e}, Mott-Smith speed err {e1:.2e}", flush=True)
+    assert e0 < 1e-4 and e1 < 1e-4

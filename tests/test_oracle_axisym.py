@@ -208,3 +208,29 @@ def test_to_hermite_gauge_keeps_the_distribution():
     assert np.max(np.abs(M2 - Mo)) < 1e-10
     # the Hermite gauge zeroes the first and the two second-degree moments
     assert np.max(np.abs(Mo[0, 1:4])) < 1e-12
+
+
+def test_char_speeds_of_maxwellian_are_hermite_roots():
+    # in its own Hermite gauge a Maxwellian makes x and y independent; the pencil
+    # splits by y-degree into {1..x^4}, {1, x, x^2} (y - 1) and the y^2 block,
+    # whose eigenvalues are the roots of He_5, He_3 and 0: the extremes are the
+    # outermost root of He_5 (the five-point Gauss--Hermite node)
+    rule = _wide_rule()
+    n, v, T = 1.4, 0.8, 2.3
+    g = (v, math.sqrt(T), math.sqrt(T))
+    beta = _maxwellian_beta_in_gauge(n, v, T, g)[None, :]
+    lam = axisym.char_speeds(beta, np.array([g]), rule)[0]
+    r5 = math.sqrt(5.0 + math.sqrt(10.0))
+    assert abs(lam[0] - (v - math.sqrt(T) * r5)) < 1e-9
+    assert abs(lam[1] - (v + math.sqrt(T) * r5)) < 1e-9
+
+
+def test_char_speeds_within_node_span():
+    cells = mem_inputs.mott_smith_cells9(6, mach_lo=2.0, mach_hi=10.0, replica=8)
+    rule = axisym.blockwise_rule(**mem_inputs.AXI_MACH10_BOX)
+    sol = axisym.solve(cells["M"], cells["g"], axisym.maxwellian_beta(cells["M"][:, 0], cells["g"]),
+                       rule, tol_grad=1e-10, max_iter=300)
+    lam = axisym.char_speeds(sol["beta"], cells["g"], rule)
+    assert np.all(lam[:, 0] >= rule["ux"].min() - 1e-9)
+    assert np.all(lam[:, 1] <= rule["ux"].max() + 1e-9)
+    assert np.all(lam[:, 0] < lam[:, 1])
