@@ -244,3 +244,144 @@ def char_speeds(beta, g, rule):
         ev = scipy.linalg.eigh(C, B, eigvals_only=True)
         out[c] = (w + sx * ev[0], w + sx * ev[-1])
     return out
+
+
+# ---- the time step of Alg. 2 on the nine statistics --------------------------
+def macroscopic(M, g):
+    """n, v_x, T, P_xx/n and P_rr/n (= (P_yy + P_zz)/2n) from the nine moments."""
+    M = np.asarray(M, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    n = M[:, 0]
+    ex = M[:, 1] / n
+    exx = SQ2 * M[:, 2] / n + 1.0
+    err = 2.0 * (M[:, 3] / n + 1.0)          # E[u_bar_r^2]
+    w, sx, sr = g[:, 0], g[:, 1], g[:, 2]
+    pxx = sx ** 2 * (exx - ex ** 2)
+    prr = 0.5 * sr ** 2 * err
+    return dict(n=n, v=w + sx * ex, T=(pxx + 2.0 * prr) / 3.0, pxx=pxx, prr=prr)
+
+
+def gaussian_moments(n, v, Sxx, Srr, g, rule_1d=16):
+    """Nine moments in gauge g of n N((v,0,0), diag(Sxx, Srr, Srr)), by
+    Gauss--Hermite in x and Gauss--Laguerre in y (exact for these degrees)."""
+    xh, wh = np.polynomial.hermite_e.hermegauss(rule_1d)
+    wh = wh / math.sqrt(2.0 * math.pi)
+    yl, wl = np.polynomial.laguerre.laggauss(rule_1d)
+    out = np.empty((len(n), K9))
+    for c in range(len(n)):
+        ux = v[c] + math.sqrt(Sxx[c]) * xh            # physical u_x
+        y = Srr[c] * yl                                # u_r^2/2 for u_y, u_z ~ N(0, Srr)
+        X, Y = np.meshgrid((ux - g[c][0]) / g[c][1], y / g[c][2] ** 2, indexing="ij")
+        W = np.outer(wh, wl)
+        out[c] = n[c] * np.einsum("ij,ijk->k", W, statistics(X, np.sqrt(2.0 * Y)))
+    return out
+
+
+def collision(M, g, h, prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi)):
+    """ES-BGK relaxation over h (appendix on the ES-BGK model): M <- (1 - h/tau) M
+    + (h/tau) M~, M~ the Gaussian with Sigma = T/Pr + (1 - 1/Pr) P/n,
+    tau = mu_ref/(Pr n) (Maxwell molecules)."""
+    mac = macroscopic(M, g)
+    Sxx = mac["T"] / prandtl + (1.0 - 1.0 / prandtl) * mac["pxx"]
+    Srr = mac["T"] / prandtl + (1.0 - 1.0 / prandtl) * mac["prr"]
+    Mt = gaussian_moments(mac["n"], mac["v"], Sxx, Srr, np.asarray(g, np.float64))
+    tau = mu_ref / (prandtl * mac["n"])
+    r = (h / tau)[:, None]
+    return (1.0 - r) * M + r * Mt
+
+
+class ShockSolver:
+    """Alg. 2 with local Lax--Friedrichs fluxes on the nine statistics: a normal
+    shock between two fixed ghost Maxwellians, cells in their Hermite gauges,
+    neighbour moments and fluxes moved into each cell's gauge by T(g_i, g_j),
+    the ES-BGK source in two half steps around the transport (Sec. 3.4)."""
+
+    def __init__(self, mach, n_cells, x_lo, x_hi, thickness, box, cfl=0.5,
+                 prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), newton=None):
+        import mem_inputs
+        self.rule = blockwise_rule(**box)
+        self.cfl, self.prandtl, self.mu_ref = cfl, prandtl, mu_ref
+        self.newton = dict(tol_grad=1e-11, max_iter=300)
+        if newton:
+            self.newton.update(newton)
+        (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(mach)
+        n1, v1, T1, n2, v2, T2 = (float(a) for a in (n1, v1, T1, n2, v2, T2))
+        gm = np.array([[0.5 * (v1 + v2), 1.0, 1.0]])
+        Mm = mem_inputs.gaussian_moments9(np.array([n1]), np.array([v1]), np.array([T1]),
+                                          np.array([T1]), gm)[0]
+        Mp = mem_inputs.gaussian_moments9(np.array([n2]), np.array([v2]), np.array([T2]),
+                                          np.array([T2]), gm)[0]
+        self.dx = (x_hi - x_lo) / n_cells
+        x = x_lo + self.dx * (np.arange(n_cells) + 0.5)
+        th = thickness / 2.0
+        frac = ((np.tanh(x / th) - math.tanh(x_lo / th))
+                / (math.tanh(x_hi / th) - math.tanh(x_lo / th)) - 0.5)
+        M0 = (Mp - Mm)[None, :] * frac[:, None] + 0.5 * (Mp + Mm)[None, :]
+        self.M, _, self.g = to_hermite_gauge(M0, None, np.repeat(gm, n_cells, axis=0))
+        self.beta = maxwellian_beta(self.M[:, 0], self.g)
+        self.states = ((n1, v1, T1), (n2, v2, T2))
+        gh = []
+        for (n, v, T) in self.states:
+            gg = np.array([[v, math.sqrt(T), math.sqrt(T)]])
+            bg = maxwellian_beta(np.array([n]), gg)
+            Mg = moments(bg, gg, self.rule)
+            Fg = fluxes(bg, gg, self.rule)
+            lam = char_speeds(bg, gg, self.rule)[0]
+            gh.append((Mg[0], Fg[0], float(np.max(np.abs(lam))), gg[0]))
+        self.ghost_left, self.ghost_right = gh
+        self.t = 0.0
+        self.beta = self._solve(self.M, self.beta)
+        self.dt = self._dt(self._rho(self.beta))
+
+    def _solve(self, M, beta):
+        """Alg. 1 per cell; a cell the box cannot represent takes the Maxwellian
+        of its gauge (the GPU step applies the same rule)."""
+        out = solve(M, self.g, beta, self.rule, **self.newton)
+        b = out["beta"].copy()
+        bad = out["nonrealizable"] | ~np.all(np.isfinite(b), axis=1)
+        if np.any(bad):
+            b[bad] = maxwellian_beta(M[bad, 0], self.g[bad])
+        return b
+
+    def _rho(self, beta):
+        lam = char_speeds(beta, self.g, self.rule)
+        return np.max(np.abs(lam), axis=1)
+
+    def _dt(self, rho):
+        rmax = max(np.max(rho), self.ghost_left[2], self.ghost_right[2])
+        return self.cfl * self.dx / rmax
+
+    def _fv(self, M, F, rho, dt):
+        N = M.shape[0]
+        g = self.g
+        MLg, FLg, rL, gL = self.ghost_left
+        MRg, FRg, rR, gR = self.ghost_right
+        out = np.empty_like(M)
+        for i in range(N):
+            if i > 0:
+                Tl = change_matrix(g[i], g[i - 1]); Ml, Fl, rl = Tl @ M[i - 1], Tl @ F[i - 1], rho[i - 1]
+            else:
+                Tl = change_matrix(g[i], gL); Ml, Fl, rl = Tl @ MLg, Tl @ FLg, rL
+            if i < N - 1:
+                Tr = change_matrix(g[i], g[i + 1]); Mr, Fr, rr = Tr @ M[i + 1], Tr @ F[i + 1], rho[i + 1]
+            else:
+                Tr = change_matrix(g[i], gR); Mr, Fr, rr = Tr @ MRg, Tr @ FRg, rR
+            lm, lp = max(rl, rho[i]), max(rho[i], rr)
+            f_minus = 0.5 * (Fl + F[i]) + 0.5 * lm * (Ml - M[i])
+            f_plus = 0.5 * (F[i] + Fr) + 0.5 * lp * (M[i] - Mr)
+            out[i] = M[i] + dt / self.dx * (f_minus - f_plus)
+        return out
+
+    def step(self):
+        dt = self.dt
+        M = collision(self.M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
+        beta = self._solve(M, self.beta)
+        F = fluxes(beta, self.g, self.rule)
+        rho = self._rho(beta)
+        dt = min(dt, self._dt(rho))
+        M = self._fv(M, F, rho, dt)
+        M = collision(M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
+        self.M, self.beta, self.g = to_hermite_gauge(M, beta, self.g)
+        self.t += dt
+        self.dt = self._dt(rho)
+        return dt
