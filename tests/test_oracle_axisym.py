@@ -290,9 +290,10 @@ def test_uniform_equilibrium_is_stationary():
     sh.M = axisym.moments(sh.beta, sh.g, sh.rule)
     mac0 = axisym.macroscopic(sh.M, sh.g)
     sh.step()
-    # identical ghost and cell representations: the transport cancels exactly;
-    # the source and the re-gauging keep n, v, T (the higher moments move by the
-    # box's quadrature error against the exact Gaussian target, ~1e-5)
+    # the source and the re-gauging keep n, v, T; the higher moments move by the
+    # box's quadrature error against the exact Gaussian target (~1e-5), which
+    # leaves the two boundary cells a flux imbalance of that order times dt
     mac1 = axisym.macroscopic(sh.M, sh.g)
     for k in ("n", "v", "T"):
-        assert np.max(np.abs(mac1[k] - mac0[k])) < 1e-10, k
+        assert np.max(np.abs(mac1[k] - mac0[k])) < 1e-7, k
+        assert np.max(np.abs(mac1[k][1:-1] - mac0[k][1:-1])) < 1e-10, k
