@@ -382,6 +382,34 @@ MEM_API mem_err_t mem_axi_solve(mem_axi_t h, int64_t n_cells, const float* M, co
                                 float* beta, const mem_solve_opts_t* opts, int32_t* iters,
                                 float* resid, uint32_t* status, hipStream_t stream);
 
+/* One normal-shock problem on the nine statistics (Alg. 2, Sec. 3.4): n_cells
+ * cells of width dx between two fixed ghost Maxwellians given as (n, v, T);
+ * cfl in (0, 1]; ES-BGK source with the Prandtl number and the viscosity
+ * coefficient mu_ref of tau = mu_ref/(Pr n) (Maxwell molecules). */
+typedef struct {
+  int32_t n_cells;
+  float dx, cfl, prandtl, mu_ref;
+  float ghost_left[3], ghost_right[3];  /* (n, v, T) */
+  int32_t reserved;                     /* must be 0 */
+} mem_axi_shock_t;
+
+/* Time steps of Alg. 2 on the nine statistics with local Lax--Friedrichs
+ * fluxes: per step, ES-BGK relaxation over dt/2, Alg. 1 per cell (warm start
+ * from beta; a cell the box cannot represent takes the Maxwellian of its
+ * gauge), fluxes and speeds, dt_used = min(dt, cfl dx / max speed over cells
+ * and ghosts), the update in local gauges (neighbour moments and fluxes moved
+ * into each cell's gauge by T(g_i, g_j); both cells of a face use
+ * max(rho_i, rho_j), rho = max |speed|), ES-BGK over dt_used/2, the Hermite
+ * gauge of each cell, then t += dt_used and dt <- cfl dx / max speed.  With
+ * n_steps = 0 it only sets up: solves the initial state and writes dt.  M[n][9],
+ * beta[n][9], g[n][3], t[1], dt[1]: device, in place; status[n] (may be NULL)
+ * gets the last solve's status.  Allocates its workspace on first use (and
+ * when n_cells grows); launches asynchronously on stream. */
+MEM_API mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* problem, float* M,
+                               float* beta, float* g, float* t, float* dt, int32_t n_steps,
+                               const mem_solve_opts_t* opts, uint32_t* status,
+                               hipStream_t stream);
+
 /* Characteristic speeds (Sec. 3.4, the local Lax--Friedrichs bound):
  * lam[n][2] = (min, max) eigenvalue of dF/dM in physical velocity at beta[n][9]
  * and g[n][3]: the extreme generalised eigenvalues of (E[x phi phi^T],

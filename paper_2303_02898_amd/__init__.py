@@ -10,6 +10,7 @@ Entry points mirror ``include/mem.h``: ``gauge``, ``solve`` (mem_maxent_solve),
 """
 
 import ctypes
+import math
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -60,6 +61,12 @@ class AxiRuleStruct(ctypes.Structure):
                 ("blocks_x", _c_i32), ("blocks_r", _c_i32), ("order", _c_i32), ("reserved", _c_i32)]
 
 
+class AxiShockStruct(ctypes.Structure):
+    _fields_ = [("n_cells", _c_i32), ("dx", _c_f32), ("cfl", _c_f32), ("prandtl", _c_f32),
+                ("mu_ref", _c_f32), ("ghost_left", _c_f32 * 3), ("ghost_right", _c_f32 * 3),
+                ("reserved", _c_i32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("dir_waves", _c_i32), ("split_want", _c_i32), ("tuned_ms", ctypes.c_double)]
 
@@ -108,6 +115,8 @@ def load_library():
         "mem_axi_moments": ([P, _c_i64, P, P, P, P, P], E),
         "mem_axi_gauge": ([_c_i64, P, P, P, P], E),
         "mem_axi_speeds": ([P, _c_i64, P, P, P, P], E),
+        "mem_axi_step": ([P, ctypes.POINTER(AxiShockStruct), P, P, P, P, P, _c_i32,
+                          ctypes.POINTER(SolveOpts), P, P], E),
         "mem_profile_enable": ([P, _c_i32], E),
         "mem_profile_read": ([P, _c_i32, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(_c_i64)], E),
@@ -418,6 +427,23 @@ class AxiRule:
             _ptr(beta, torch.float32, (9,), "beta"), o, _ptr(iters, torch.int32),
             _ptr(resid, torch.float32), _ptr(status, torch.int32), _stream(stream)), "mem_axi_solve")
         return iters, resid, status
+
+    def step(self, M, beta, g, t, dt, dx, left, right, n_steps=1, cfl=0.5,
+             prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), opts=None, status=None,
+             stream=None):
+        """Alg. 2 time steps of one shock problem (n_steps = 0: set-up only).
+        left/right: ghost (n, v, T); t, dt: one-element device tensors."""
+        import torch
+        n = M.shape[0]
+        pb = AxiShockStruct(n, dx, cfl, prandtl, mu_ref, (_c_f32 * 3)(*left),
+                            (_c_f32 * 3)(*right), 0)
+        o = ctypes.byref(opts) if opts is not None else None
+        self._check(self._lib.mem_axi_step(
+            self._h, ctypes.byref(pb), _ptr(M, torch.float32, (9,), "M"),
+            _ptr(beta, torch.float32, (9,), "beta"), _ptr(g, torch.float32, (3,), "g"),
+            _ptr(t, torch.float32), _ptr(dt, torch.float32), n_steps, o,
+            _ptr(status, torch.int32) if status is not None else None, _stream(stream)),
+            "mem_axi_step")
 
     def speeds(self, beta, g, stream=None):
         """(min, max) characteristic speed per cell in physical velocity."""

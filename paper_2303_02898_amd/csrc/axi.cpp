@@ -17,6 +17,10 @@ struct mem_axi_s {
   float4* d_tab = nullptr;  // (u_x, u_r, log w, u_x - fl(u_x)) per node
   float lmin = 0.f;
   float ux_min = 0.f, ux_max = 0.f;  // node span in u_x
+  // time-step workspace (mem_axi_step), grown on demand
+  int64_t cap = 0;
+  float *w_F = nullptr, *w_lam = nullptr, *w_Mn = nullptr, *w_gh = nullptr, *w_scal = nullptr;
+  uint32_t* w_st = nullptr;
 };
 
 namespace {
@@ -189,9 +193,17 @@ mem_err_t mem_axi_create(const mem_axi_rule_t* rule, mem_axi_t* out) {
   return MEM_OK;
 }
 
+void free_step(mem_axi_s* h) {
+  for (float** p : {&h->w_F, &h->w_lam, &h->w_Mn, &h->w_gh, &h->w_scal})
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+  if (h->w_st) { (void)hipFree(h->w_st); h->w_st = nullptr; }
+  h->cap = 0;
+}
+
 mem_err_t mem_axi_destroy(mem_axi_t h) {
   if (!h) return MEM_ERR_INVALID_ARG;
   (void)hipDeviceSynchronize();
+  free_step(h);
   if (h->d_tab) (void)hipFree(h->d_tab);
   delete h;
   return MEM_OK;
@@ -222,6 +234,90 @@ mem_err_t mem_axi_speeds(mem_axi_t h, int64_t n, const float* beta, const float*
                  hipSuccess
              ? MEM_OK
              : MEM_ERR_HIP;
+}
+
+#define AXI_HIP(x)                                     \
+  do {                                                 \
+    if ((x) != hipSuccess) return MEM_ERR_HIP;         \
+  } while (0)
+
+// Alg. 2 on the nine statistics for one normal-shock problem (see mem.h).
+// Ghost rows: gh = [M 2x9 | beta 2x9 | g 2x3 | F 2x9 | lam 2x2].
+mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* beta, float* g,
+                       float* t, float* dt, int32_t n_steps, const mem_solve_opts_t* opts,
+                       uint32_t* status, hipStream_t s) {
+  if (!h || !pb || !M || !beta || !g || !t || !dt || n_steps < 0) return MEM_ERR_INVALID_ARG;
+  const int64_t n = pb->n_cells;
+  if (n < 1 || n > (int64_t)1 << 24 || !(pb->dx > 0.f) || !(pb->cfl > 0.f) || !(pb->cfl <= 1.f) ||
+      !(pb->prandtl > 0.f) || !(pb->mu_ref > 0.f) || pb->reserved != 0)
+    return MEM_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(pb->ghost_left[k]) || !std::isfinite(pb->ghost_right[k]))
+      return MEM_ERR_INVALID_ARG;
+  if (!(pb->ghost_left[0] > 0.f) || !(pb->ghost_left[2] > 0.f) || !(pb->ghost_right[0] > 0.f) ||
+      !(pb->ghost_right[2] > 0.f))
+    return MEM_ERR_INVALID_ARG;
+  SolveParams p;
+  if (params_axi(h, opts, p) != MEM_OK) return MEM_ERR_INVALID_ARG;
+  if (n > h->cap) {
+    AXI_HIP(hipStreamSynchronize(s));
+    free_step(h);
+    if (hipMalloc((void**)&h->w_F, n * 9 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_lam, n * 2 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_Mn, n * 9 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_gh, 64 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_scal, 4 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_st, n * sizeof(uint32_t)) != hipSuccess) {
+      free_step(h);
+      return MEM_ERR_NOMEM;
+    }
+    h->cap = n;
+  }
+  float* gM = h->w_gh;
+  float* gB = gM + 18;
+  float* gG = gB + 18;
+  float* gF = gG + 6;
+  float* gL = gF + 18;
+  {  // ghost Maxwellians in their own Hermite gauges: the discrete moments,
+     // fluxes and speeds of beta = (n, 0, -1/sqrt2, -1, 0, ...)
+    float host[42] = {0.f};
+    const float* st3[2] = {pb->ghost_left, pb->ghost_right};
+    for (int k = 0; k < 2; ++k) {
+      host[18 + 9 * k] = st3[k][0];
+      host[18 + 9 * k + 2] = -0.70710678118654752f;
+      host[18 + 9 * k + 3] = -1.f;
+      host[36 + 3 * k] = st3[k][1];
+      host[36 + 3 * k + 1] = std::sqrt(st3[k][2]);
+      host[36 + 3 * k + 2] = std::sqrt(st3[k][2]);
+    }
+    AXI_HIP(hipMemcpyAsync(gB, host + 18, 24 * sizeof(float), hipMemcpyHostToDevice, s));
+    AXI_HIP(hipStreamSynchronize(s));  // the host array goes out of scope
+    AXI_HIP(launch_axi_moments(2, (int)h->P, h->d_tab, gB, gG, gM, gF, s));
+    AXI_HIP(launch_axi_speeds(2, (int)h->P, h->d_tab, gB, gG, h->ux_min, h->ux_max, gL, s));
+  }
+  uint32_t* st = status ? status : h->w_st;
+  const int tpb = (int)h->P;
+  if (n_steps == 0) {  // set-up: the solve of the initial state and its dt
+    AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, p, nullptr, nullptr, st, s));
+    AXI_HIP(launch_axi_fix(n, M, beta, st, s));
+    AXI_HIP(launch_axi_speeds(n, tpb, h->d_tab, beta, g, h->ux_min, h->ux_max, h->w_lam, s));
+    AXI_HIP(launch_axi_dt(n, h->w_lam, gL, pb->cfl, pb->dx, dt, h->w_scal, 1, s));
+    return MEM_OK;
+  }
+  for (int k = 0; k < n_steps; ++k) {
+    AXI_HIP(launch_axi_collide(n, M, g, dt, 0.5f, pb->prandtl, pb->mu_ref, s));
+    AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, p, nullptr, nullptr, st, s));
+    AXI_HIP(launch_axi_fix(n, M, beta, st, s));
+    AXI_HIP(launch_axi_moments(n, tpb, h->d_tab, beta, g, nullptr, h->w_F, s));
+    AXI_HIP(launch_axi_speeds(n, tpb, h->d_tab, beta, g, h->ux_min, h->ux_max, h->w_lam, s));
+    AXI_HIP(launch_axi_dt(n, h->w_lam, gL, pb->cfl, pb->dx, dt, h->w_scal, 0, s));
+    AXI_HIP(launch_axi_fv(n, M, h->w_F, h->w_lam, g, gM, gF, gL, gG, h->w_scal, pb->dx, h->w_Mn, s));
+    AXI_HIP(hipMemcpyAsync(M, h->w_Mn, n * 9 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    AXI_HIP(launch_axi_collide(n, M, g, h->w_scal, 0.5f, pb->prandtl, pb->mu_ref, s));
+    AXI_HIP(launch_axi_gauge(n, M, beta, g, s));
+    AXI_HIP(launch_axi_finish(t, dt, h->w_scal, s));
+  }
+  return MEM_OK;
 }
 
 mem_err_t mem_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s) {

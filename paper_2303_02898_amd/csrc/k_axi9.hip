@@ -723,6 +723,186 @@ hipError_t launch_axi_speeds(int64_t n, int P, const float4* tab, const float* b
   return hipGetLastError();
 }
 
+// ---- the time step of Alg. 2 (Sec. 3.4; ES-BGK source of the appendix) -------
+// ES-BGK relaxation over f * dt[0]: M <- (1 - r) M + r M~, r = h/tau,
+// tau = mu_ref/(Pr n); M~ the Gaussian n N((v,0,0), diag(Sxx, Srr, Srr)),
+// Sigma = T/Pr + (1 - 1/Pr) P/n, in the cell's gauge: x ~ N(mu, var) gives
+// E[He_k(x)] = h_k(mu; var - 1), y ~ Exp(theta) gives E[l_1] = theta - 1 and
+// E[l_2] = (theta - 1)^2.  One thread per cell.
+__global__ void k_axi_collide(int64_t n, float* __restrict__ M, const float* __restrict__ g,
+                              const float* __restrict__ dtp, float f, float prandtl, float mu_ref) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double m[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) m[k] = (double)M[c * 9 + k];
+  const double w = g[c * 3], sx = g[c * 3 + 1], sr = g[c * 3 + 2];
+  const double nn = m[0];
+  if (!(nn > 0.0) || !isfinite(nn)) return;
+  const double ex = m[1] / nn;
+  const double exx = 1.41421356237309505 * m[2] / nn + 1.0;
+  const double err = 2.0 * (m[3] / nn + 1.0);
+  const double pxx = sx * sx * (exx - ex * ex), prr = 0.5 * sr * sr * err;
+  const double T = (pxx + 2.0 * prr) / 3.0;
+  const double Pr = prandtl;
+  const double sxx = T / Pr + (1.0 - 1.0 / Pr) * pxx, srr = T / Pr + (1.0 - 1.0 / Pr) * prr;
+  const double mu = ex;  // (v - w)/s_x with v = w + s_x E[x]
+  const double cv = sxx / (sx * sx) - 1.0;
+  const double hx[5] = {1.0, mu, mu * mu + cv, mu * mu * mu + 3.0 * mu * cv,
+                        mu * mu * mu * mu + 6.0 * mu * mu * cv + 3.0 * cv * cv};
+  const double px[5] = {hx[0], hx[1], hx[2] * 0.70710678118654752, hx[3] * 0.40824829046386302,
+                        hx[4] * 0.20412414523193151};
+  const double th = srr / (sr * sr);
+  const double ly[3] = {1.0, th - 1.0, (th - 1.0) * (th - 1.0)};
+  const double r = (double)f * (double)dtp[0] * Pr * nn / (double)mu_ref;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double mt = nn * px[AX_A[i]] * ly[AX_K[i]];
+    M[c * 9 + i] = (float)((1.0 - r) * m[i] + r * mt);
+  }
+}
+
+// Cells the box cannot represent (the solve ended NONREALIZABLE or NONFINITE on
+// finite targets) take the Maxwellian of their gauge, so that fluxes and speeds
+// stay defined.
+__global__ void k_axi_fix(int64_t n, const float* __restrict__ M, float* __restrict__ beta,
+                          const uint32_t* __restrict__ st) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  if (!(st[c] & (MEM_ST_NONREALIZABLE | MEM_ST_NONFINITE))) return;
+  const float nn = M[c * 9];
+  if (!(nn > 0.f) || !isfinite(nn)) return;
+  const float mb[9] = {nn, 0.f, -0.70710678118654752f, -1.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) beta[c * 9 + k] = mb[k];
+}
+
+// dt of this step: min(previous dt, cfl dx / max speed) (cells and ghosts);
+// scal[0] = dt used, scal[1] = cfl dx / max speed (the next step's dt).  With
+// init, dt[0] <- scal[1] and nothing else.
+__global__ __launch_bounds__(256) void k_axi_dt(int64_t n, const float* __restrict__ lam,
+                                                const float* __restrict__ glam, float cfl, float dx,
+                                                float* __restrict__ dt, float* __restrict__ scal,
+                                                int init) {
+  __shared__ float sm[256];
+  float r = 0.f;
+  for (int64_t c = threadIdx.x; c < n; c += 256)
+    r = fmaxf(r, fmaxf(fabsf(lam[c * 2]), fabsf(lam[c * 2 + 1])));
+  if (threadIdx.x < 2)
+    r = fmaxf(r, fmaxf(fabsf(glam[threadIdx.x * 2]), fabsf(glam[threadIdx.x * 2 + 1])));
+  sm[threadIdx.x] = r;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float dn = cfl * dx / sm[0];
+    if (init) {
+      dt[0] = dn;
+    } else {
+      scal[0] = fminf(dt[0], dn);
+      scal[1] = dn;
+    }
+  }
+}
+
+__device__ __forceinline__ void axi_T(const float* gto, const float* gfrom, double (&t)[5][5],
+                                      double (&r)[3][3]) {
+  const double sxt = gto[1], sx = gfrom[1], srt = gto[2], sr = gfrom[2];
+  conn_x(sx / sxt, ((double)gfrom[0] - (double)gto[0]) / sxt, t);
+  conn_y((sr / srt) * (sr / srt), r);
+}
+
+// LLF in local gauges: neighbour moments and fluxes moved into the cell's gauge
+// by T(g_i, g_j); both cells of a face use max(rho_i, rho_j), rho = max |lam|.
+// Row -1 and row n are the ghosts (gM, gF, glam, gG rows 0 and 1).
+__global__ void k_axi_fv(int64_t n, const float* __restrict__ M, const float* __restrict__ F,
+                         const float* __restrict__ lam, const float* __restrict__ g,
+                         const float* __restrict__ gM, const float* __restrict__ gF,
+                         const float* __restrict__ glam, const float* __restrict__ gG,
+                         const float* __restrict__ scal, float dx, float* __restrict__ Mout) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double dt = scal[0];
+  auto rho_of = [](const float* l) { return (double)fmaxf(fabsf(l[0]), fabsf(l[1])); };
+  const double ri = rho_of(lam + c * 2);
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = (double)M[c * 9 + k];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const bool ghost = side == 0 ? (c == 0) : (c == n - 1);
+    const int64_t j = side == 0 ? c - 1 : c + 1;
+    const float* Mj = ghost ? gM + side * 9 : M + j * 9;
+    const float* Fj = ghost ? gF + side * 9 : F + j * 9;
+    const float* gj = ghost ? gG + side * 3 : g + j * 3;
+    const double rj = rho_of(ghost ? glam + side * 2 : lam + j * 2);
+    const double a = fmax(ri, rj);
+    double t[5][5], r[3][3];
+    axi_T(g + c * 3, gj, t, r);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      double mj = 0.0, fj = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const double tk = tij(t, r, i, k);
+        mj += tk * (double)Mj[k];
+        fj += tk * (double)Fj[k];
+      }
+      const double mi = M[c * 9 + i], fi = F[c * 9 + i];
+      // left face: + dt/dx (1/2 (F_l + F_i) + 1/2 a (M_l - M_i));
+      // right face: - dt/dx (1/2 (F_i + F_r) + 1/2 a (M_i - M_r))
+      const double face = side == 0 ? 0.5 * (fj + fi) + 0.5 * a * (mj - mi)
+                                    : -(0.5 * (fi + fj) + 0.5 * a * (mi - mj));
+      acc[i] += dt / dx * face;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Mout[c * 9 + k] = (float)acc[k];
+}
+
+__global__ void k_axi_finish(float* __restrict__ t, float* __restrict__ dt,
+                             const float* __restrict__ scal) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    t[0] += scal[0];
+    dt[0] = scal[1];
+  }
+}
+
+hipError_t launch_axi_collide(int64_t n, float* M, const float* g, const float* dtp, float f,
+                              float prandtl, float mu_ref, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axi_collide<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, M, g, dtp, f, prandtl, mu_ref);
+  return hipGetLastError();
+}
+
+hipError_t launch_axi_fix(int64_t n, const float* M, float* beta, const uint32_t* st, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axi_fix<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, M, beta, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_axi_dt(int64_t n, const float* lam, const float* glam, float cfl, float dx,
+                         float* dt, float* scal, int init, hipStream_t s) {
+  k_axi_dt<<<1, 256, 0, s>>>(n, lam, glam, cfl, dx, dt, scal, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_axi_fv(int64_t n, const float* M, const float* F, const float* lam, const float* g,
+                         const float* gM, const float* gF, const float* glam, const float* gG,
+                         const float* scal, float dx, float* Mout, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axi_fv<<<(unsigned)((n + 127) / 128), 128, 0, s>>>(n, M, F, lam, g, gM, gF, glam, gG, scal, dx,
+                                                      Mout);
+  return hipGetLastError();
+}
+
+hipError_t launch_axi_finish(float* t, float* dt, const float* scal, hipStream_t s) {
+  k_axi_finish<<<1, 64, 0, s>>>(t, dt, scal);
+  return hipGetLastError();
+}
+
 hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_axi_gauge<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, M, beta, g);

@@ -154,6 +154,15 @@ hipError_t launch_axi_solve(int64_t n, int P, const float4* tab, const float* M,
                             uint32_t* status, hipStream_t s);
 hipError_t launch_axi_speeds(int64_t n, int P, const float4* tab, const float* beta, const float* g,
                              float ux_min, float ux_max, float* lam, hipStream_t s);
+hipError_t launch_axi_collide(int64_t n, float* M, const float* g, const float* dtp, float f,
+                              float prandtl, float mu_ref, hipStream_t s);
+hipError_t launch_axi_fix(int64_t n, const float* M, float* beta, const uint32_t* st, hipStream_t s);
+hipError_t launch_axi_dt(int64_t n, const float* lam, const float* glam, float cfl, float dx,
+                         float* dt, float* scal, int init, hipStream_t s);
+hipError_t launch_axi_fv(int64_t n, const float* M, const float* F, const float* lam, const float* g,
+                         const float* gM, const float* gF, const float* glam, const float* gG,
+                         const float* scal, float dx, float* Mout, hipStream_t s);
+hipError_t launch_axi_finish(float* t, float* dt, const float* scal, hipStream_t s);
 hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s);
 hipError_t launch_axi_moments(int64_t n, int P, const float4* tab, const float* beta,
                               const float* g, float* M, float* F, hipStream_t s);

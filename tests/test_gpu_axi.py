@@ -267,3 +267,37 @@ def test_axi_speeds_match_oracle_and_hermite_roots(rule, orule):
     e1 = np.max(np.abs(lam2 - ref2) / np.maximum(1.0, np.abs(ref2)))
     print(f"Maxwellian speed err {e0:.2e}, Mott-Smith speed err {e1:.2e}", flush=True)
     assert e0 < 1e-4 and e1 < 1e-4
+
+
+def test_axi_shock_steps_match_oracle():
+    print("\n[gpu] axi Mach-3 shock, 24 cells, set-up + 6 LLF steps against the oracle",
+          flush=True)
+    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(3.0)
+    a_x, b_x, b_r = axisym.integration_domain(float(v1), float(T1), float(v2), float(T2), 10, 6, 6)
+    box = dict(ux_lo=a_x, ux_hi=b_x, ur_hi=b_r, blocks_x=6, blocks_r=4, order=8)
+    sh = axisym.ShockSolver(3.0, 24, -12.0, 12.0, 5.44, box)
+    r = mem.AxiRule(**box)
+    M0 = f32(sh.M).astype(np.float64)
+    g0 = f32(sh.g).astype(np.float64)
+    Md, gd = dev(M0), dev(g0)
+    bd = dev(axisym.maxwellian_beta(M0[:, 0], g0))
+    t = torch.zeros(1, device=DEV)
+    dt = torch.zeros(1, device=DEV)
+    left, right = (n1, v1, T1), (n2, v2, T2)
+    left = tuple(float(a) for a in left)
+    right = tuple(float(a) for a in right)
+    r.step(Md, bd, gd, t, dt, sh.dx, left, right, n_steps=0)
+    torch.cuda.synchronize()
+    assert abs(dt.item() - sh.dt) < 1e-5 * sh.dt, (dt.item(), sh.dt)
+    st = torch.zeros(24, dtype=torch.int32, device=DEV)
+    for k in range(6):
+        sh.step()
+        r.step(Md, bd, gd, t, dt, sh.dx, left, right, n_steps=1, status=st)
+    torch.cuda.synchronize()
+    r.close()
+    eM = np.max(np.abs(Md.cpu().numpy() - sh.M) / sh.M[:, :1])
+    eg = np.max(np.abs(gd.cpu().numpy() - sh.g) / sh.g.clip(1e-3))
+    et = abs(t.item() - sh.t) / sh.t
+    print(f"after 6 steps: M err {eM:.2e}, g err {eg:.2e}, t err {et:.2e}; statuses "
+          f"{np.unique(st.cpu().numpy())}", flush=True)
+    assert eM < 1e-4 and eg < 1e-4 and et < 1e-5
