@@ -137,6 +137,51 @@ AXI_FLOP_ASM = 16 + 89
 VALU_PEAK_TFLOPS = 78.6
 
 
+def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400):
+    """Alg. 2 steps of the Mach-10 shock on the nine statistics (wall time)."""
+    import math
+    import mem_inputs
+    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(10.0)
+    n1, v1, T1, n2, v2, T2 = (float(a) for a in (n1, v1, T1, n2, v2, T2))
+    x_lo, x_hi, th = -47.1, 47.1, 15.7 / 2.0
+    dx = (x_hi - x_lo) / n_cells
+    x = x_lo + dx * (np.arange(n_cells) + 0.5)
+    frac = ((np.tanh(x / th) - math.tanh(x_lo / th))
+            / (math.tanh(x_hi / th) - math.tanh(x_lo / th)) - 0.5)
+    gm = np.array([[0.5 * (v1 + v2), 1.0, 1.0]])
+    Mm = mem_inputs.gaussian_moments9(np.array([n1]), np.array([v1]), np.array([T1]),
+                                      np.array([T1]), gm)[0]
+    Mp = mem_inputs.gaussian_moments9(np.array([n2]), np.array([v2]), np.array([T2]),
+                                      np.array([T2]), gm)[0]
+    M0 = (Mp - Mm)[None, :] * frac[:, None] + 0.5 * (Mp + Mm)[None, :]
+    Md = torch.tensor(M0.astype(np.float32), device=dev)
+    gd = torch.tensor(np.repeat(gm, n_cells, axis=0).astype(np.float32), device=dev)
+    rule.gauge(Md, None, gd)
+    b0 = np.zeros((n_cells, 9), np.float32)
+    b0[:, 2] = -1.0 / np.sqrt(2.0)
+    b0[:, 3] = -1.0
+    bd = torch.tensor(b0, device=dev)
+    bd[:, 0] = Md[:, 0]
+    t = torch.zeros(1, device=dev)
+    dt = torch.zeros(1, device=dev)
+    st = torch.zeros(n_cells, dtype=torch.int32, device=dev)
+    args = (Md, bd, gd, t, dt, dx, (n1, v1, T1), (n2, v2, T2))
+    rule.step(*args, n_steps=0, status=st)
+    rule.step(*args, n_steps=20, status=st)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rule.step(*args, n_steps=steps, status=st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    Mh = Md.cpu().numpy()
+    return {"workload": f"Mach-10 normal shock, {n_cells} cells on [-47.1, 47.1], tanh "
+                        "thickness 15.7, LLF in local gauges with ES-BGK halves, same box",
+            "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "cell_steps_per_s": n_cells * steps / el, "t": float(t.item()),
+            "finite": bool(np.all(np.isfinite(Mh))),
+            "density_ends": [float(Mh[0, 0]), float(Mh[-1, 0])]}
+
+
 def paper_discretisation(mem, torch, dev, reps=5):
     """Alg. 1 on the paper's nine statistics and block-wise Gauss--Legendre box."""
     import mem_inputs
@@ -168,6 +213,9 @@ def paper_discretisation(mem, torch, dev, reps=5):
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
+    # the paper's Mach-10 shock on its own discretisation: 150 cells on
+    # [-47.1, 47.1], tanh thickness 15.7, the same box; LLF steps
+    shock = _axi_shock_rate(mem, torch, dev, rule)
     rule.close()
     ms = float(np.mean(times))
     s = st.cpu().numpy()
@@ -186,6 +234,7 @@ def paper_discretisation(mem, torch, dev, reps=5):
             "converged_fraction": float(np.mean(conv)),
             "stagnated_fraction": float(np.mean((s & mem.ST_STAGNATED) != 0)),
             "iterations_mean": float(iters.mean()), "iterations_max": int(iters.max()),
+            "shock_llf": shock,
             "roofline": {"bound": "alu", "kernel": "k_axi_solve", "achieved": achieved,
                          "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / VALU_PEAK_TFLOPS,
