@@ -297,8 +297,12 @@ class ShockSolver:
     the ES-BGK source in two half steps around the transport (Sec. 3.4)."""
 
     def __init__(self, mach, n_cells, x_lo, x_hi, thickness, box, cfl=0.5,
-                 prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), newton=None):
+                 prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), newton=None,
+                 scheme="llf"):
         import mem_inputs
+        if scheme not in ("llf", "lw", "flic"):
+            raise ValueError("scheme must be llf, lw or flic")
+        self.scheme = scheme
         self.rule = blockwise_rule(**box)
         self.cfl, self.prandtl, self.mu_ref = cfl, prandtl, mu_ref
         self.newton = dict(tol_grad=1e-11, max_iter=300)
@@ -327,7 +331,7 @@ class ShockSolver:
             Mg = moments(bg, gg, self.rule)
             Fg = fluxes(bg, gg, self.rule)
             lam = char_speeds(bg, gg, self.rule)[0]
-            gh.append((Mg[0], Fg[0], float(np.max(np.abs(lam))), gg[0]))
+            gh.append((Mg[0], Fg[0], float(np.max(np.abs(lam))), gg[0], bg[0]))
         self.ghost_left, self.ghost_right = gh
         self.t = 0.0
         self.beta = self._solve(self.M, self.beta)
@@ -354,8 +358,8 @@ class ShockSolver:
     def _fv(self, M, F, rho, dt):
         N = M.shape[0]
         g = self.g
-        MLg, FLg, rL, gL = self.ghost_left
-        MRg, FRg, rR, gR = self.ghost_right
+        MLg, FLg, rL, gL, _ = self.ghost_left
+        MRg, FRg, rR, gR, _ = self.ghost_right
         out = np.empty_like(M)
         for i in range(N):
             if i > 0:
@@ -372,6 +376,63 @@ class ShockSolver:
             out[i] = M[i] + dt / self.dx * (f_minus - f_plus)
         return out
 
+    def interface_fluxes(self, M, F, beta, rho, dt):
+        """Flux at each of the N + 1 interfaces (Sec. 3.4: LF, two-step LW, FLIC
+        with the per-moment van Leer limiter), interface j between elements j
+        and j + 1 of [left ghost, cells, right ghost], in the gauge of element
+        j + 1.  One MaxEnt solve per interface; an interface whose half-step
+        state cannot be solved keeps F_LF."""
+        from .kinetics import van_leer
+        MLg, FLg, rL, gL, bL = self.ghost_left
+        MRg, FRg, rR, gR, bR = self.ghost_right
+        Me = np.vstack([MLg[None], M, MRg[None]])
+        Fe = np.vstack([FLg[None], F, FRg[None]])
+        ge = np.vstack([gL[None], self.g, gR[None]])
+        be = np.vstack([bL[None], beta, bR[None]])
+        re = np.concatenate([[rL], rho, [rR]])
+        N = M.shape[0]
+        out = np.empty((N + 1, K9))
+        Mh = np.empty((N + 1, K9))
+        for j in range(N + 1):
+            L, R = j, j + 1
+            T = change_matrix(ge[R], ge[L])
+            ML, FL = T @ Me[L], T @ Fe[L]
+            lam = max(re[L], re[R])
+            out[j] = 0.5 * (FL + Fe[R]) + 0.5 * lam * (ML - Me[R])
+            Mh[j] = 0.5 * (ML + Me[R]) + 0.5 * (dt / self.dx) * (FL - Fe[R])
+        if self.scheme == "llf":
+            return out
+        sol = solve(Mh, ge[1:], be[1:], self.rule, **self.newton)
+        for j in range(N + 1):
+            L, R = j, j + 1
+            bh = sol["beta"][j]
+            if (sol["nonrealizable"][j] or not np.all(np.isfinite(bh))
+                    or not np.all(np.isfinite(Mh[j])) or not Mh[j, 0] > 0):
+                continue
+            f_lw = fluxes(bh[None, :], ge[R][None, :], self.rule)[0]
+            if self.scheme == "lw":
+                phi = np.ones(K9)
+            else:
+                LL = max(L - 1, 0)   # the left ghost continues beyond the boundary
+                ML = change_matrix(ge[R], ge[L]) @ Me[L]
+                MLL = change_matrix(ge[R], ge[LL]) @ Me[LL]
+                phi = van_leer(ML - MLL, Me[R] - ML)
+            out[j] = out[j] + phi * (f_lw - out[j])
+        return out
+
+    def _fv2(self, M, F, beta, rho, dt):
+        """Conservative update from the interface fluxes: cell i receives the
+        flux of its left face as given (its own gauge) and that of its right
+        face moved into its gauge by T(g_i, g_{i+1})."""
+        f = self.interface_fluxes(M, F, beta, rho, dt)
+        gR = self.ghost_right[3]
+        out = np.empty_like(M)
+        for i in range(M.shape[0]):
+            gn = self.g[i + 1] if i + 1 < M.shape[0] else gR
+            fr = change_matrix(self.g[i], gn) @ f[i + 1]
+            out[i] = M[i] + dt / self.dx * (f[i] - fr)
+        return out
+
     def step(self):
         dt = self.dt
         M = collision(self.M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
@@ -379,7 +440,7 @@ class ShockSolver:
         F = fluxes(beta, self.g, self.rule)
         rho = self._rho(beta)
         dt = min(dt, self._dt(rho))
-        M = self._fv(M, F, rho, dt)
+        M = self._fv(M, F, rho, dt) if self.scheme == "llf" else self._fv2(M, F, beta, rho, dt)
         M = collision(M, self.g, 0.5 * dt, self.prandtl, self.mu_ref)
         self.M, self.beta, self.g = to_hermite_gauge(M, beta, self.g)
         self.t += dt

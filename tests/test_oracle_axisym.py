@@ -268,8 +268,8 @@ def test_transport_is_conservative_in_the_interior():
     rho = sh._rho(sh.beta)
     dt = sh.dt
     Mn = sh._fv(sh.M, F, rho, dt)
-    MLg, FLg, rL, _ = sh.ghost_left
-    MRg, FRg, rR, _ = sh.ghost_right
+    MLg, FLg, rL, _, _ = sh.ghost_left
+    MRg, FRg, rR, _, _ = sh.ghost_right
     fL = 0.5 * (FLg[0] + F[0, 0]) + 0.5 * max(rL, rho[0]) * (MLg[0] - sh.M[0, 0])
     fR = 0.5 * (F[-1, 0] + FRg[0]) + 0.5 * max(rho[-1], rR) * (sh.M[-1, 0] - MRg[0])
     dmass = np.sum(Mn[:, 0] - sh.M[:, 0]) * sh.dx
@@ -297,3 +297,19 @@ def test_uniform_equilibrium_is_stationary():
     for k in ("n", "v", "T"):
         assert np.max(np.abs(mac1[k] - mac0[k])) < 1e-7, k
         assert np.max(np.abs(mac1[k][1:-1] - mac0[k][1:-1])) < 1e-10, k
+
+
+def test_second_order_interface_fluxes_reduce_to_lf():
+    # with the limiter forced to zero FLIC is LF; the LF interface fluxes of the
+    # second-order path equal those the LLF update uses
+    sh = axisym.ShockSolver(3.0, 12, -6.0, 6.0, 5.44, _small_shock(), scheme="flic")
+    F = axisym.fluxes(sh.beta, sh.g, sh.rule)
+    rho = sh._rho(sh.beta)
+    sh.scheme = "llf"
+    Ml = sh._fv(sh.M, F, rho, sh.dt)
+    M2 = sh._fv2(sh.M, F, sh.beta, rho, sh.dt)
+    assert np.max(np.abs(Ml - M2)) < 1e-12
+    sh.scheme = "flic"
+    for _ in range(2):
+        sh.step()
+    assert np.all(np.isfinite(sh.M))
