@@ -385,12 +385,13 @@ MEM_API mem_err_t mem_axi_solve(mem_axi_t h, int64_t n_cells, const float* M, co
 /* One normal-shock problem on the nine statistics (Alg. 2, Sec. 3.4): n_cells
  * cells of width dx between two fixed ghost Maxwellians given as (n, v, T);
  * cfl in (0, 1]; ES-BGK source with the Prandtl number and the viscosity
- * coefficient mu_ref of tau = mu_ref/(Pr n) (Maxwell molecules). */
+ * coefficient mu_ref of tau = mu_ref/(Pr n) (Maxwell molecules); scheme one of
+ * MEM_FLUX_LLF, MEM_FLUX_LW, MEM_FLUX_FLIC. */
 typedef struct {
   int32_t n_cells;
   float dx, cfl, prandtl, mu_ref;
   float ghost_left[3], ghost_right[3];  /* (n, v, T) */
-  int32_t reserved;                     /* must be 0 */
+  int32_t scheme;
 } mem_axi_shock_t;
 
 /* Time steps of Alg. 2 on the nine statistics with local Lax--Friedrichs
@@ -399,7 +400,11 @@ typedef struct {
  * gauge), fluxes and speeds, dt_used = min(dt, cfl dx / max speed over cells
  * and ghosts), the update in local gauges (neighbour moments and fluxes moved
  * into each cell's gauge by T(g_i, g_j); both cells of a face use
- * max(rho_i, rho_j), rho = max |speed|), ES-BGK over dt_used/2, the Hermite
+ * max(rho_i, rho_j), rho = max |speed|; with MEM_FLUX_LW or MEM_FLUX_FLIC
+ * each interface instead blends F_LF with the flux of a MaxEnt solve of the
+ * half-step state in the right element's gauge, by 1 (LW) or the per-moment van
+ * Leer limiter (FLIC), F_LF where that solve fails, and the left cell receives
+ * the interface flux moved into its gauge), ES-BGK over dt_used/2, the Hermite
  * gauge of each cell, then t += dt_used and dt <- cfl dx / max speed.  With
  * n_steps = 0 it only sets up: solves the initial state and writes dt.  M[n][9],
  * beta[n][9], g[n][3], t[1], dt[1]: device, in place; status[n] (may be NULL)

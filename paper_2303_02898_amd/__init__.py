@@ -64,7 +64,7 @@ class AxiRuleStruct(ctypes.Structure):
 class AxiShockStruct(ctypes.Structure):
     _fields_ = [("n_cells", _c_i32), ("dx", _c_f32), ("cfl", _c_f32), ("prandtl", _c_f32),
                 ("mu_ref", _c_f32), ("ghost_left", _c_f32 * 3), ("ghost_right", _c_f32 * 3),
-                ("reserved", _c_i32)]
+                ("scheme", _c_i32)]
 
 
 class Tuning(ctypes.Structure):
@@ -430,13 +430,13 @@ class AxiRule:
 
     def step(self, M, beta, g, t, dt, dx, left, right, n_steps=1, cfl=0.5,
              prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), opts=None, status=None,
-             stream=None):
+             scheme="llf", stream=None):
         """Alg. 2 time steps of one shock problem (n_steps = 0: set-up only).
         left/right: ghost (n, v, T); t, dt: one-element device tensors."""
         import torch
         n = M.shape[0]
         pb = AxiShockStruct(n, dx, cfl, prandtl, mu_ref, (_c_f32 * 3)(*left),
-                            (_c_f32 * 3)(*right), 0)
+                            (_c_f32 * 3)(*right), FLUX_SCHEMES[scheme])
         o = ctypes.byref(opts) if opts is not None else None
         self._check(self._lib.mem_axi_step(
             self._h, ctypes.byref(pb), _ptr(M, torch.float32, (9,), "M"),

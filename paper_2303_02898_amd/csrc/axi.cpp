@@ -21,6 +21,11 @@ struct mem_axi_s {
   int64_t cap = 0;
   float *w_F = nullptr, *w_lam = nullptr, *w_Mn = nullptr, *w_gh = nullptr, *w_scal = nullptr;
   uint32_t* w_st = nullptr;
+  // interface rows (n + 1): F_LF, half-step state, gauge, multipliers, limiter,
+  // F_LW, status
+  float *w_fLF = nullptr, *w_Mh = nullptr, *w_gI = nullptr, *w_bI = nullptr, *w_phi = nullptr,
+        *w_fLW = nullptr;
+  uint32_t* w_stI = nullptr;
 };
 
 namespace {
@@ -194,9 +199,11 @@ mem_err_t mem_axi_create(const mem_axi_rule_t* rule, mem_axi_t* out) {
 }
 
 void free_step(mem_axi_s* h) {
-  for (float** p : {&h->w_F, &h->w_lam, &h->w_Mn, &h->w_gh, &h->w_scal})
+  for (float** p : {&h->w_F, &h->w_lam, &h->w_Mn, &h->w_gh, &h->w_scal, &h->w_fLF, &h->w_Mh,
+                    &h->w_gI, &h->w_bI, &h->w_phi, &h->w_fLW})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
   if (h->w_st) { (void)hipFree(h->w_st); h->w_st = nullptr; }
+  if (h->w_stI) { (void)hipFree(h->w_stI); h->w_stI = nullptr; }
   h->cap = 0;
 }
 
@@ -249,7 +256,8 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
   if (!h || !pb || !M || !beta || !g || !t || !dt || n_steps < 0) return MEM_ERR_INVALID_ARG;
   const int64_t n = pb->n_cells;
   if (n < 1 || n > (int64_t)1 << 24 || !(pb->dx > 0.f) || !(pb->cfl > 0.f) || !(pb->cfl <= 1.f) ||
-      !(pb->prandtl > 0.f) || !(pb->mu_ref > 0.f) || pb->reserved != 0)
+      !(pb->prandtl > 0.f) || !(pb->mu_ref > 0.f) || pb->scheme < MEM_FLUX_LLF ||
+      pb->scheme > MEM_FLUX_FLIC)
     return MEM_ERR_INVALID_ARG;
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(pb->ghost_left[k]) || !std::isfinite(pb->ghost_right[k]))
@@ -267,7 +275,14 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
         hipMalloc((void**)&h->w_Mn, n * 9 * sizeof(float)) != hipSuccess ||
         hipMalloc((void**)&h->w_gh, 64 * sizeof(float)) != hipSuccess ||
         hipMalloc((void**)&h->w_scal, 4 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_st, n * sizeof(uint32_t)) != hipSuccess) {
+        hipMalloc((void**)&h->w_st, n * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void**)&h->w_fLF, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_Mh, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_gI, (n + 1) * 3 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_bI, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_phi, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_fLW, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&h->w_stI, (n + 1) * sizeof(uint32_t)) != hipSuccess) {
       free_step(h);
       return MEM_ERR_NOMEM;
     }
@@ -311,7 +326,19 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
     AXI_HIP(launch_axi_moments(n, tpb, h->d_tab, beta, g, nullptr, h->w_F, s));
     AXI_HIP(launch_axi_speeds(n, tpb, h->d_tab, beta, g, h->ux_min, h->ux_max, h->w_lam, s));
     AXI_HIP(launch_axi_dt(n, h->w_lam, gL, pb->cfl, pb->dx, dt, h->w_scal, 0, s));
-    AXI_HIP(launch_axi_fv(n, M, h->w_F, h->w_lam, g, gM, gF, gL, gG, h->w_scal, pb->dx, h->w_Mn, s));
+    if (pb->scheme == MEM_FLUX_LLF) {
+      AXI_HIP(launch_axi_fv(n, M, h->w_F, h->w_lam, g, gM, gF, gL, gG, h->w_scal, pb->dx, h->w_Mn,
+                            s));
+    } else {  // one MaxEnt solve per interface, in the right element's gauge
+      AXI_HIP(launch_axi_iface(n, M, h->w_F, h->w_lam, g, beta, gM, gF, gL, gG, gB, h->w_scal,
+                               pb->dx, pb->scheme == MEM_FLUX_FLIC, h->w_fLF, h->w_Mh, h->w_gI,
+                               h->w_bI, h->w_phi, s));
+      AXI_HIP(launch_axi_solve(n + 1, tpb, h->d_tab, h->w_Mh, h->w_gI, h->w_bI, p, nullptr,
+                               nullptr, h->w_stI, s));
+      AXI_HIP(launch_axi_moments(n + 1, tpb, h->d_tab, h->w_bI, h->w_gI, nullptr, h->w_fLW, s));
+      AXI_HIP(launch_axi_fv2(n, M, g, gG, h->w_fLF, h->w_fLW, h->w_phi, h->w_stI, h->w_scal,
+                             pb->dx, h->w_Mn, s));
+    }
     AXI_HIP(hipMemcpyAsync(M, h->w_Mn, n * 9 * sizeof(float), hipMemcpyDeviceToDevice, s));
     AXI_HIP(launch_axi_collide(n, M, g, h->w_scal, 0.5f, pb->prandtl, pb->mu_ref, s));
     AXI_HIP(launch_axi_gauge(n, M, beta, g, s));

@@ -862,6 +862,121 @@ __global__ void k_axi_fv(int64_t n, const float* __restrict__ M, const float* __
   for (int k = 0; k < 9; ++k) Mout[c * 9 + k] = (float)acc[k];
 }
 
+// ---- second-order fluxes (Sec. 3.4: two-step LW, FLIC) ------------------------
+// Elements e = 0..n+1 are [left ghost, cells, right ghost]; interface j lies
+// between elements j and j + 1 and works in the gauge of element j + 1.
+struct AxElem { const float *M, *F, *g, *b, *lam; };
+__device__ __forceinline__ AxElem axi_elem(int64_t e, int64_t n, const float* M, const float* F,
+                                           const float* g, const float* beta, const float* lam,
+                                           const float* gM, const float* gF, const float* gG,
+                                           const float* gB, const float* glam) {
+  if (e == 0) return {gM, gF, gG, gB, glam};
+  if (e == n + 1) return {gM + 9, gF + 9, gG + 3, gB + 9, glam + 2};
+  const int64_t c = e - 1;
+  return {M + c * 9, F + c * 9, g + c * 3, beta + c * 9, lam + c * 2};
+}
+
+// One thread per interface: F_LF and the half-step state
+// Mh = (M_L + M_R)/2 + dt/(2 dx) (F_L - F_R) in the right element's gauge, the
+// per-moment van Leer limiter of FLIC (1 for LW), and the right element's
+// gauge and multipliers as the interface solve's gauge and start.
+__global__ void k_axi_iface(int64_t n, const float* __restrict__ M, const float* __restrict__ F,
+                            const float* __restrict__ lam, const float* __restrict__ g,
+                            const float* __restrict__ beta, const float* __restrict__ gM,
+                            const float* __restrict__ gF, const float* __restrict__ glam,
+                            const float* __restrict__ gG, const float* __restrict__ gB,
+                            const float* __restrict__ scal, float dx, int flic,
+                            float* __restrict__ fLF, float* __restrict__ Mh,
+                            float* __restrict__ gI, float* __restrict__ bI,
+                            float* __restrict__ phi) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > n) return;
+  const double dt = scal[0];
+  const AxElem L = axi_elem(j, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
+  const AxElem R = axi_elem(j + 1, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
+  const AxElem LL = axi_elem(j > 0 ? j - 1 : 0, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
+  auto rho_of = [](const float* l) { return (double)fmaxf(fabsf(l[0]), fabsf(l[1])); };
+  const double a = fmax(rho_of(L.lam), rho_of(R.lam));
+  double t[5][5], r[3][3], t2[5][5], r2[3][3];
+  axi_T(R.g, L.g, t, r);
+  axi_T(R.g, LL.g, t2, r2);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    double ml = 0.0, fl = 0.0, mll = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double tk = tij(t, r, i, k);
+      ml += tk * (double)L.M[k];
+      fl += tk * (double)L.F[k];
+      mll += tij(t2, r2, i, k) * (double)LL.M[k];
+    }
+    const double mr = R.M[i], fr = R.F[i];
+    fLF[j * 9 + i] = (float)(0.5 * (fl + fr) + 0.5 * a * (ml - mr));
+    Mh[j * 9 + i] = (float)(0.5 * (ml + mr) + 0.5 * (dt / dx) * (fl - fr));
+    double ph = 1.0;
+    if (flic) {  // van Leer: 2 a / (a + b) for a b > 0, else 0
+      const double da = ml - mll, db = mr - ml;
+      ph = da * db > 0.0 ? 2.0 * da / (da + db) : 0.0;
+    }
+    phi[j * 9 + i] = (float)ph;
+    bI[j * 9 + i] = R.b[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gI[j * 3 + k] = R.g[k];
+}
+
+// Blend F = F_LF + phi (F_LW - F_LF) (F_LF where the interface solve failed)
+// and apply: cell i takes its left face as given and its right face moved into
+// its gauge by T(g_i, g_{i+1}).
+__global__ void k_axi_fv2(int64_t n, const float* __restrict__ M, const float* __restrict__ g,
+                          const float* __restrict__ gG, const float* __restrict__ fLF,
+                          const float* __restrict__ fLW, const float* __restrict__ phi,
+                          const uint32_t* __restrict__ stI, const float* __restrict__ scal,
+                          float dx, float* __restrict__ Mout) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double dt = scal[0];
+  auto face = [&](int64_t j, int i) {
+    const bool bad = (stI[j] & (MEM_ST_NONREALIZABLE | MEM_ST_NONFINITE)) != 0;
+    const double lf = fLF[j * 9 + i];
+    return bad ? lf : lf + (double)phi[j * 9 + i] * ((double)fLW[j * 9 + i] - lf);
+  };
+  const float* gn = c + 1 < n ? g + (c + 1) * 3 : gG + 3;
+  double t[5][5], r[3][3];
+  axi_T(g + c * 3, gn, t, r);
+  double fr[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) fr[k] = face(c + 1, k);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc += tij(t, r, i, k) * fr[k];
+    Mout[c * 9 + i] = (float)((double)M[c * 9 + i] + dt / dx * (face(c, i) - acc));
+  }
+}
+
+hipError_t launch_axi_iface(int64_t n, const float* M, const float* F, const float* lam,
+                            const float* g, const float* beta, const float* gM, const float* gF,
+                            const float* glam, const float* gG, const float* gB,
+                            const float* scal, float dx, int flic, float* fLF, float* Mh,
+                            float* gI, float* bI, float* phi, hipStream_t s) {
+  k_axi_iface<<<(unsigned)((n + 1 + 127) / 128), 128, 0, s>>>(n, M, F, lam, g, beta, gM, gF, glam,
+                                                             gG, gB, scal, dx, flic, fLF, Mh, gI,
+                                                             bI, phi);
+  return hipGetLastError();
+}
+
+hipError_t launch_axi_fv2(int64_t n, const float* M, const float* g, const float* gG,
+                          const float* fLF, const float* fLW, const float* phi,
+                          const uint32_t* stI, const float* scal, float dx, float* Mout,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axi_fv2<<<(unsigned)((n + 127) / 128), 128, 0, s>>>(n, M, g, gG, fLF, fLW, phi, stI, scal, dx,
+                                                       Mout);
+  return hipGetLastError();
+}
+
 __global__ void k_axi_finish(float* __restrict__ t, float* __restrict__ dt,
                              const float* __restrict__ scal) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {

@@ -162,6 +162,15 @@ hipError_t launch_axi_dt(int64_t n, const float* lam, const float* glam, float c
 hipError_t launch_axi_fv(int64_t n, const float* M, const float* F, const float* lam, const float* g,
                          const float* gM, const float* gF, const float* glam, const float* gG,
                          const float* scal, float dx, float* Mout, hipStream_t s);
+hipError_t launch_axi_iface(int64_t n, const float* M, const float* F, const float* lam,
+                            const float* g, const float* beta, const float* gM, const float* gF,
+                            const float* glam, const float* gG, const float* gB,
+                            const float* scal, float dx, int flic, float* fLF, float* Mh,
+                            float* gI, float* bI, float* phi, hipStream_t s);
+hipError_t launch_axi_fv2(int64_t n, const float* M, const float* g, const float* gG,
+                          const float* fLF, const float* fLW, const float* phi,
+                          const uint32_t* stI, const float* scal, float dx, float* Mout,
+                          hipStream_t s);
 hipError_t launch_axi_finish(float* t, float* dt, const float* scal, hipStream_t s);
 hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s);
 hipError_t launch_axi_moments(int64_t n, int P, const float4* tab, const float* beta,

@@ -269,13 +269,14 @@ def test_axi_speeds_match_oracle_and_hermite_roots(rule, orule):
     assert e0 < 1e-4 and e1 < 1e-4
 
 
-def test_axi_shock_steps_match_oracle():
-    print("\n[gpu] axi Mach-3 shock, 24 cells, set-up + 6 LLF steps against the oracle",
+@pytest.mark.parametrize("scheme", ["llf", "lw", "flic"])
+def test_axi_shock_steps_match_oracle(scheme):
+    print(f"\n[gpu] axi Mach-3 shock, 24 cells, set-up + 6 {scheme} steps against the oracle",
           flush=True)
     (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(3.0)
     a_x, b_x, b_r = axisym.integration_domain(float(v1), float(T1), float(v2), float(T2), 10, 6, 6)
     box = dict(ux_lo=a_x, ux_hi=b_x, ur_hi=b_r, blocks_x=6, blocks_r=4, order=8)
-    sh = axisym.ShockSolver(3.0, 24, -12.0, 12.0, 5.44, box)
+    sh = axisym.ShockSolver(3.0, 24, -12.0, 12.0, 5.44, box, scheme=scheme)
     r = mem.AxiRule(**box)
     M0 = f32(sh.M).astype(np.float64)
     g0 = f32(sh.g).astype(np.float64)
@@ -292,7 +293,7 @@ def test_axi_shock_steps_match_oracle():
     st = torch.zeros(24, dtype=torch.int32, device=DEV)
     for k in range(6):
         sh.step()
-        r.step(Md, bd, gd, t, dt, sh.dx, left, right, n_steps=1, status=st)
+        r.step(Md, bd, gd, t, dt, sh.dx, left, right, n_steps=1, status=st, scheme=scheme)
     torch.cuda.synchronize()
     r.close()
     eM = np.max(np.abs(Md.cpu().numpy() - sh.M) / sh.M[:, :1])
