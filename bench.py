@@ -137,7 +137,7 @@ AXI_FLOP_ASM = 16 + 89
 VALU_PEAK_TFLOPS = 78.6
 
 
-def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400):
+def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400, scheme="llf"):
     """Alg. 2 steps of the Mach-10 shock on the nine statistics (wall time)."""
     import math
     import mem_inputs
@@ -166,16 +166,17 @@ def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400):
     dt = torch.zeros(1, device=dev)
     st = torch.zeros(n_cells, dtype=torch.int32, device=dev)
     args = (Md, bd, gd, t, dt, dx, (n1, v1, T1), (n2, v2, T2))
-    rule.step(*args, n_steps=0, status=st)
-    rule.step(*args, n_steps=20, status=st)   # warm-up
+    rule.step(*args, n_steps=0, status=st, scheme=scheme)
+    rule.step(*args, n_steps=20, status=st, scheme=scheme)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rule.step(*args, n_steps=steps, status=st)
+    rule.step(*args, n_steps=steps, status=st, scheme=scheme)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     Mh = Md.cpu().numpy()
     return {"workload": f"Mach-10 normal shock, {n_cells} cells on [-47.1, 47.1], tanh "
-                        "thickness 15.7, LLF in local gauges with ES-BGK halves, same box",
+                        f"thickness 15.7, {scheme.upper()} in local gauges with ES-BGK halves, "
+                        "same box",
             "steps": steps, "ms_per_step": 1e3 * el / steps,
             "cell_steps_per_s": n_cells * steps / el, "t": float(t.item()),
             "finite": bool(np.all(np.isfinite(Mh))),
@@ -216,6 +217,7 @@ def paper_discretisation(mem, torch, dev, reps=5):
     # the paper's Mach-10 shock on its own discretisation: 150 cells on
     # [-47.1, 47.1], tanh thickness 15.7, the same box; LLF steps
     shock = _axi_shock_rate(mem, torch, dev, rule)
+    shock_flic = _axi_shock_rate(mem, torch, dev, rule, scheme="flic")
     rule.close()
     ms = float(np.mean(times))
     s = st.cpu().numpy()
@@ -234,7 +236,7 @@ def paper_discretisation(mem, torch, dev, reps=5):
             "converged_fraction": float(np.mean(conv)),
             "stagnated_fraction": float(np.mean((s & mem.ST_STAGNATED) != 0)),
             "iterations_mean": float(iters.mean()), "iterations_max": int(iters.max()),
-            "shock_llf": shock,
+            "shock_llf": shock, "shock_flic": shock_flic,
             "roofline": {"bound": "alu", "kernel": "k_axi_solve", "achieved": achieved,
                          "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / VALU_PEAK_TFLOPS,
