@@ -71,6 +71,7 @@ SolveParams params_from(const mem_solve_opts_t* o) {
   p.beta_max = o->beta_max;
   p.lmin = -3.0e38f;
   p.refine = 0;
+  p.stall_window = 0;
   return p;
 }
 

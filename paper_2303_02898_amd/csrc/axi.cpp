@@ -122,6 +122,7 @@ mem_err_t params_axi(const mem_axi_s* h, const mem_solve_opts_t* o, SolveParams&
   p.beta_max = o->beta_max;
   p.lmin = h->lmin;
   p.refine = 0;
+  p.stall_window = 0;
   return MEM_OK;
 }
 
@@ -312,6 +313,11 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
   }
   uint32_t* st = status ? status : h->w_st;
   const int tpb = (int)h->P;
+  // the per-step solves start from the previous step's multipliers: a cell
+  // that does not halve its residual below the stall gate within 6 iterations
+  // sits at its FP32 floor (the set-up solve keeps the longer default window)
+  SolveParams pw = p;
+  pw.stall_window = 6;
   if (n_steps == 0) {  // set-up: the solve of the initial state and its dt
     AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, p, nullptr, nullptr, st, s));
     AXI_HIP(launch_axi_fix(n, M, beta, st, s));
@@ -321,7 +327,7 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
   }
   for (int k = 0; k < n_steps; ++k) {
     AXI_HIP(launch_axi_collide(n, M, g, dt, 0.5f, pb->prandtl, pb->mu_ref, s));
-    AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, p, nullptr, nullptr, st, s));
+    AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, pw, nullptr, nullptr, st, s));
     AXI_HIP(launch_axi_fix(n, M, beta, st, s));
     AXI_HIP(launch_axi_moments(n, tpb, h->d_tab, beta, g, nullptr, h->w_F, s));
     AXI_HIP(launch_axi_speeds(n, tpb, h->d_tab, beta, g, h->ux_min, h->ux_max, h->w_lam, s));
@@ -333,7 +339,7 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
       AXI_HIP(launch_axi_iface(n, M, h->w_F, h->w_lam, g, beta, gM, gF, gL, gG, gB, h->w_scal,
                                pb->dx, pb->scheme == MEM_FLUX_FLIC, h->w_fLF, h->w_Mh, h->w_gI,
                                h->w_bI, h->w_phi, s));
-      AXI_HIP(launch_axi_solve(n + 1, tpb, h->d_tab, h->w_Mh, h->w_gI, h->w_bI, p, nullptr,
+      AXI_HIP(launch_axi_solve(n + 1, tpb, h->d_tab, h->w_Mh, h->w_gI, h->w_bI, pw, nullptr,
                                nullptr, h->w_stI, s));
       AXI_HIP(launch_axi_moments(n + 1, tpb, h->d_tab, h->w_bI, h->w_gI, nullptr, h->w_fLW, s));
       AXI_HIP(launch_axi_fv2(n, M, g, gG, h->w_fLF, h->w_fLW, h->w_phi, h->w_stI, h->w_scal,

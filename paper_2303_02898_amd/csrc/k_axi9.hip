@@ -413,7 +413,9 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
       if (cur.L < p.lmin) { st |= MEM_ST_NONREALIZABLE; break; }  // no minimiser exists
       if (p.beta_max > 0.f && bmax > p.beta_max) { st |= MEM_ST_NONREALIZABLE; break; }
       if (!isfinite(r) || !dfin) { st |= MEM_ST_NONFINITE; break; }
-      if (alpha <= p.alpha_min || (r <= AX_STALL_GATE && it - itbest >= AX_STALL_WINDOW)) {
+      if (alpha <= p.alpha_min ||
+          (r <= AX_STALL_GATE &&
+           it - itbest >= (p.stall_window > 0 ? p.stall_window : AX_STALL_WINDOW))) {
         st |= MEM_ST_STAGNATED;
         break;
       }

@@ -46,6 +46,8 @@ struct SolveParams {
   float lmin;  // min_p log w~_p: a dual value below it certifies non-realizability
   int refine;  // > 0: converged and stalled cells go on to compensated refinement
   float beta_max;  // |beta|_inf beyond this ends a cell as non-realizable (0 = off)
+  int stall_window;  // nine-statistic solve: iterations without halving below the
+                     // stall gate before a cell stops as stagnated (0 = default 20)
 };
 
 }  // namespace memk
