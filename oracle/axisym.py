@@ -382,7 +382,7 @@ class ShockSolver:
         and j + 1 of [left ghost, cells, right ghost], in the gauge of element
         j + 1.  One MaxEnt solve per interface; an interface whose half-step
         state cannot be solved keeps F_LF."""
-        from .kinetics import van_leer
+        from .kinetics import flic_limiter
         MLg, FLg, rL, gL, bL = self.ghost_left
         MRg, FRg, rR, gR, bR = self.ghost_right
         Me = np.vstack([MLg[None], M, MRg[None]])
@@ -413,10 +413,12 @@ class ShockSolver:
             if self.scheme == "lw":
                 phi = np.ones(K9)
             else:
-                LL = max(L - 1, 0)   # the left ghost continues beyond the boundary
+                # the ghosts continue beyond both boundaries
+                LL, RR = max(L - 1, 0), min(R + 1, N + 1)
                 ML = change_matrix(ge[R], ge[L]) @ Me[L]
                 MLL = change_matrix(ge[R], ge[LL]) @ Me[LL]
-                phi = van_leer(ML - MLL, Me[R] - ML)
+                MRR = change_matrix(ge[R], ge[RR]) @ Me[RR] if RR != R else Me[R]
+                phi = flic_limiter(ML - MLL, Me[R] - ML, MRR - Me[R])
             out[j] = out[j] + phi * (f_lw - out[j])
         return out
 

@@ -42,9 +42,11 @@ def char_speeds(beta, g, nodes, Phi, logw):
     C = beta.shape[0]
     lo = np.empty(C)
     hi = np.empty(C)
+    # E_sigma[phi phi^T] and E_sigma[u_bar_x phi phi^T], direct weighted sums
+    Bs = _maxent.second_moments(sig, Phi)
+    Cs = _maxent.second_moments(sig * ux[None, :], Phi)
     for c in range(C):
-        B = (Phi * sig[c][:, None]).T @ Phi
-        Cx = (Phi * (sig[c] * ux)[:, None]).T @ Phi
+        B, Cx = Bs[c], Cs[c]
         try:
             mu = scipy.linalg.eigh(Cx, B, eigvals_only=True)
             m0, m1 = mu[0], mu[-1]

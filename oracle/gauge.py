@@ -17,6 +17,8 @@ u_bar = ((u_x - w_x)/s_x, u_y/s_r, u_z/s_r).
   beta'_i = alpha'_i for i >= 1 (eq. "form transformation"); beta'_0 = n.
 """
 
+import math
+
 import numpy as np
 
 from . import basis as _basis
@@ -73,19 +75,34 @@ def _affine(g_to, g_from, dim):
     return a, b
 
 
+def _axis_projection(a, b, n=6):
+    """t[c, k, l] = E_{z~N(0,1)}[p_k(a_c z + b_c) p_l(z)], p_k = He_k/sqrt(k!), k, l <= 4.
+
+    One axis of the projection below, by an n-point Gauss--Hermite rule (exact:
+    the integrand has degree <= 8)."""
+    z, w = _quad.gauss_hermite(n)
+    norm = np.sqrt([float(math.factorial(k)) for k in range(5)])
+    P0 = _basis.hermite_e(4, z) / norm[:, None]                      # (5, n)
+    Ps = _basis.hermite_e(4, a[:, None] * z[None, :] + b[:, None])   # (5, C, n)
+    Ps = np.moveaxis(Ps, 0, 1) / norm[None, :, None]                 # (C, 5, n)
+    return (Ps * w[None, None, :]) @ P0.T
+
+
 def change_matrix(g_to, g_from, dim):
-    """T(g_to, g_from): (C, K, K), by Gaussian projection."""
+    """T(g_to, g_from): (C, K, K), by Gaussian projection.
+
+    T_ij = E_{z~N(0,I)}[phi_i(a*z + b) phi_j(z)] over the tensor rule.  The
+    basis and the rule are both tensor products, so the sum factorises into
+    one projection per axis: T_(abc),(a'b'c') = t_x[a,a'] t_y[b,b'] t_z[c,c']."""
     g_to = np.atleast_2d(np.asarray(g_to, dtype=np.float64))
     g_from = np.atleast_2d(np.asarray(g_from, dtype=np.float64))
-    z, w = _proj_rule(dim)
-    Phi = _basis.evaluate(z, dim)
     a, b = _affine(g_to, g_from, dim)
-    C = a.shape[0]
-    K = Phi.shape[1]
-    T = np.empty((C, K, K))
-    for c in range(C):
-        Phi_s = _basis.evaluate(z * a[c][None, :] + b[c][None, :], dim)
-        T[c] = (Phi_s * w[:, None]).T @ Phi
+    idx = np.asarray(_basis.multi_indices(dim))                      # (K, dim)
+    T = None
+    for d in range(dim):
+        t = _axis_projection(a[:, d], b[:, d])                       # (C, 5, 5)
+        f = t[:, idx[:, d][:, None], idx[:, d][None, :]]             # (C, K, K)
+        T = f if T is None else T * f
     return T
 
 

@@ -38,8 +38,13 @@ solved from the right cell's beta.  Where it cannot be represented (the solve
 certifies non-realizability or does not stay finite) the interface takes the
 LLF flux.  The limiter is the van Leer function (r + |r|)/(1 + |r|); the
 printed denominator 1 + r agrees with it for r >= 0 and only differs where
-the numerator is zero.  The ghost states continue beyond the boundary, so the
-first interface has r = 0.
+the numerator is zero.  The printed ratio r looks one element upwind for waves
+moving in +x; the scheme is a centred one, and the moment system carries waves
+in both directions (behind a shock, the subsonic side), so the limiter takes
+the smaller of phi(r_L) and phi(r_R), r_R being the same ratio one element to
+the right (``flic_limiter``).  Then it is TVD for either direction of motion
+and the step is symmetric under x -> -x.  The ghost states continue beyond the
+boundaries, so the first and the last interface have phi = 0.
 
 Reading for the step size (paper gives only a CFL relation): the step taken at
 step k is CFL*dx/max rho from the characteristic speeds of the transport of
@@ -84,24 +89,27 @@ def macroscopic(M, g):
     return dict(n=n, v=v, T=T, Pxx=Pxx, Pyy=Pyy, Pzz=Pzz, qx=qx)
 
 
-def gaussian_moments(n, v, Sxx, Srr, g, nq=8):
-    """Moments in gauge g of n * N((v, 0, 0), diag(Sxx, Srr, Srr)) by quadrature."""
+def gaussian_moments(n, v, Sxx, Srr, g, nq=5):
+    """Moments in gauge g of n * N((v, 0, 0), diag(Sxx, Srr, Srr)) by quadrature.
+
+    The integrand is a polynomial of degree <= 4 in the Gaussian's own
+    coordinates, so nq >= 3 points per axis integrate it exactly."""
     n, v, Sxx, Srr = (np.atleast_1d(np.asarray(a, dtype=np.float64))
                       for a in (n, v, Sxx, Srr))
     g = np.atleast_2d(np.asarray(g, dtype=np.float64))
     z, w = _quad.tensor_rule(nq, DIM)
-    out = np.empty((n.shape[0], len(_basis.multi_indices(DIM))))
-    for c in range(n.shape[0]):
-        u = np.empty_like(z)
-        u[:, 0] = v[c] + math.sqrt(Sxx[c]) * z[:, 0]
-        u[:, 1] = math.sqrt(Srr[c]) * z[:, 1]
-        u[:, 2] = math.sqrt(Srr[c]) * z[:, 2]
-        ub = np.empty_like(u)
-        ub[:, 0] = (u[:, 0] - g[c, 0]) / g[c, 1]
-        ub[:, 1] = u[:, 1] / g[c, 2]
-        ub[:, 2] = u[:, 2] / g[c, 2]
-        out[c] = n[c] * (w @ _basis.evaluate(ub, DIM))
-    return out
+    C, P = n.shape[0], z.shape[0]
+    # velocities of the Gaussian's nodes, then their gauge coordinates: (C, P, 3)
+    u = np.empty((C, P, DIM))
+    u[:, :, 0] = v[:, None] + np.sqrt(Sxx)[:, None] * z[None, :, 0]
+    u[:, :, 1] = np.sqrt(Srr)[:, None] * z[None, :, 1]
+    u[:, :, 2] = np.sqrt(Srr)[:, None] * z[None, :, 2]
+    ub = np.empty_like(u)
+    ub[:, :, 0] = (u[:, :, 0] - g[:, None, 0]) / g[:, None, 1]
+    ub[:, :, 1] = u[:, :, 1] / g[:, None, 2]
+    ub[:, :, 2] = u[:, :, 2] / g[:, None, 2]
+    Phi = _basis.evaluate(ub.reshape(-1, DIM), DIM).reshape(C, P, -1)
+    return n[:, None] * np.einsum("p,cpi->ci", w, Phi)
 
 
 def es_bgk_target(M, g, prandtl):
@@ -167,6 +175,15 @@ def van_leer(a, b):
     pos = a * b > 0
     out[pos] = 2.0 * a[pos] / (a[pos] + b[pos])
     return out
+
+
+def flic_limiter(d_left, d_mid, d_right):
+    """FLIC limiter per moment: min(phi(r_L), phi(r_R)) with the van Leer phi,
+    r_L = d_left / d_mid and r_R = d_right / d_mid, where d_mid is the jump
+    across the interface and d_left, d_right the jumps one element upwind of it
+    on either side (eq. "The FLIC" prints r_L, the upwind ratio of waves moving
+    in +x; r_R is the upwind ratio of waves moving in -x)."""
+    return np.minimum(van_leer(d_left, d_mid), van_leer(d_right, d_mid))
 
 
 class FVSolver:
@@ -285,9 +302,15 @@ class FVSolver:
         if self.scheme == "lw":
             phi = np.ones_like(f_lw)
         else:
+            # the ratio on either side of the interface, each moved into its gauge;
+            # the ghost states continue beyond both boundaries
+            RR = np.minimum(R + 1, N + 1)
             TLL = _gauge.change_matrix(gI, ge[LL], DIM)
             MLL = np.einsum("cij,cj->ci", TLL, Me[LL])
-            phi = van_leer(ML - MLL, MR - ML)
+            TRR = _gauge.change_matrix(gI, ge[RR], DIM)
+            MRR = np.einsum("cij,cj->ci", TRR, Me[RR])
+            MRR[RR == R] = MR[RR == R]
+            phi = flic_limiter(ML - MLL, MR - ML, MRR - MR)
         f = f_lf + phi * (f_lw - f_lf)
         f[failed] = f_lf[failed]
         return f, failed

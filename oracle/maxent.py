@@ -24,7 +24,8 @@ decouples the 0-block, so the Newton system is the (K-1)x(K-1) block; the
 oracle stops on max_{i>=1} |G_i| <= tol_grad so that it reaches the FP64 floor.
 
 Moments and the Hessian are direct weighted sums over nodes (Phi^T diag(sigma)
-Phi), never a table of basis products.
+Phi), never a table of basis products.  The large dense sums and exponentials
+run as plain PyTorch CPU operations in FP64 (threaded); the rest is NumPy.
 
 Realizability on the node set (Sec. 2.3 discusses when beta exists): at a
 minimiser sigma* matches the targets, so
@@ -36,23 +37,30 @@ moment set of distributions on the nodes); such cells stop as non-realizable.
 """
 
 import numpy as np
+import torch
 
-_CHUNK = 96  # cells per weighted-Gram chunk (bounds memory)
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+
+
+def _exponent(beta, Phi, logw):
+    """e[c, p] = sum_{i>=1} beta_i phi_i(u_p) + log w~_p (torch, FP64)."""
+    return _t(beta[:, 1:]) @ _t(Phi[:, 1:]).T + _t(logw)[None, :]
 
 
 def log_partition(beta, Phi, logw):
     """log Z(beta) by log-sum-exp.  beta: (C, K) with column 0 = beta_0 (unused)."""
-    e = beta[:, 1:] @ Phi[:, 1:].T + logw[None, :]
-    q = np.max(e, axis=1)
-    return q + np.log(np.sum(np.exp(e - q[:, None]), axis=1))
+    e = _exponent(beta, Phi, logw)
+    q = torch.max(e, dim=1).values
+    return (q + torch.log(torch.sum(torch.exp(e - q[:, None]), dim=1))).numpy()
 
 
 def sigma(beta, Phi, logw, logZ=None):
     """Discrete probabilities sigma[c, p]."""
     if logZ is None:
         logZ = log_partition(beta, Phi, logw)
-    e = beta[:, 1:] @ Phi[:, 1:].T + logw[None, :]
-    return np.exp(e - logZ[:, None])
+    e = _exponent(beta, Phi, logw)
+    return torch.exp(e - _t(logZ)[:, None]).numpy()
 
 
 def expectations(beta, Phi, logw):
@@ -66,13 +74,13 @@ def model_moments(beta, Phi, logw):
 
 
 def second_moments(sig, Phi):
-    """E_sigma[phi_i phi_j]: (C, K, K) by chunked Phi^T diag(sigma) Phi."""
-    C, K = sig.shape[0], Phi.shape[1]
-    out = np.empty((C, K, K))
-    for s in range(0, C, _CHUNK):
-        X = sig[s:s + _CHUNK, None, :] * Phi.T[None, :, :]
-        out[s:s + _CHUNK] = X @ Phi
-    return out
+    """E_sigma[phi_i phi_j]: (C, K, K); row i is (sigma * phi_i) @ Phi over the nodes."""
+    s, P = _t(sig), _t(Phi)
+    C, K = s.shape[0], P.shape[1]
+    out = torch.empty((C, K, K), dtype=torch.float64)
+    for i in range(K):
+        out[:, i, :] = (s * P[:, i]) @ P
+    return out.numpy()
 
 
 def objective(beta, M, Phi, logw):
@@ -204,7 +212,21 @@ def newton_solve(M, beta_init, Phi, logw, tol_grad=1e-12, tol_dec=0.0,
         resid[act] = r
         newd = np.zeros((act.size, K))
         res = np.zeros(act.size)
-        for j in range(act.size):
+        # Cholesky of every unshifted block at once; where any block needs the
+        # lambda shift, every cell takes the per-cell loop below instead
+        try:
+            Lb = np.linalg.cholesky(H) if act.size else None
+        except np.linalg.LinAlgError:
+            Lb = None
+        if Lb is not None:
+            w = np.linalg.solve(Lb, -G[:, :, None])
+            newd[:, 1:] = np.linalg.solve(np.swapaxes(Lb, 1, 2), w)[:, :, 0]
+            res = 0.5 * np.sum(w[:, :, 0] ** 2, axis=1)
+            if want_cond:
+                ev = np.linalg.eigvalsh(H)
+                with np.errstate(divide="ignore"):
+                    cond[act] = np.where(ev[:, 0] > 0, ev[:, -1] / ev[:, 0], np.inf)
+        for j in range(act.size if Lb is None else 0):
             Lh, lam = _shifted_cholesky(H[j], lambda0, lambda_mul)
             if lam > 0:
                 shifted[act[j]] = True
