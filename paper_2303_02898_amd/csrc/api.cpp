@@ -39,7 +39,14 @@ bool dalloc(T*& p, size_t count) {
   return hipMalloc((void**)&p, std::max<size_t>(count, 1) * sizeof(T)) == hipSuccess;
 }
 
+// A captured mem_step graph holds workspace pointers: drop it with the workspace.
+void drop_step_graph(mem_ctx_t c) {
+  ++c->ws_gen;
+  if (c->step_exec) { (void)hipGraphExecDestroy(c->step_exec); c->step_exec = nullptr; }
+}
+
 void free_workspace(mem_ctx_t c) {
+  drop_step_graph(c);
   dfree(c->w_S); dfree(c->w_S5); dfree(c->w_dbeta); dfree(c->w_logZ); dfree(c->w_L);
   dfree(c->w_alpha); dfree(c->w_gdot); dfree(c->w_resid); dfree(c->w_iters);
   dfree(c->w_status);
@@ -53,6 +60,7 @@ void free_workspace(mem_ctx_t c) {
 }
 
 void free_problems(mem_ctx_t c) {
+  drop_step_graph(c);
   dfree(c->w_gM); dfree(c->w_gB); dfree(c->w_gG); dfree(c->w_gF); dfree(c->w_gR);
   dfree(c->w_rmax);
   c->cap_problems = 0;
@@ -547,7 +555,7 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
   key.b = *b;
   key.M = M; key.beta = beta; key.g = g; key.t = t; key.dt = dt; key.status = status;
   key.p = p; key.refine = refine;
-  key.ws = c->w_S;
+  key.gen = c->ws_gen;
   if (!c->step_exec || std::memcmp(&key, &c->step_key, sizeof(key)) != 0) {
     if (c->step_exec) { (void)hipGraphExecDestroy(c->step_exec); c->step_exec = nullptr; }
     if (!c->cap_stream) MEM_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -592,6 +600,7 @@ mem_err_t mem_set_tuning(mem_ctx_t c, const mem_tuning_t* in) {
       in->split_want > 65536)
     return fail(c, MEM_ERR_INVALID_ARG, "mem_set_tuning: dir_waves in {2,4,8}, split_want in [0, 65536]");
   c->tune = *in;
+  ++c->ws_gen;
   return MEM_OK;
 }
 
@@ -653,6 +662,7 @@ mem_err_t mem_autotune(mem_ctx_t c, int64_t n, const float* M, const float* beta
   (void)hipEventDestroy(ev[1]);
   best.tuned_ms = best_ms;
   c->tune = best;
+  ++c->ws_gen;
   if (out) *out = best;
   return e;
 }

@@ -897,28 +897,36 @@ __global__ void k_axi_iface(int64_t n, const float* __restrict__ M, const float*
   const AxElem L = axi_elem(j, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
   const AxElem R = axi_elem(j + 1, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
   const AxElem LL = axi_elem(j > 0 ? j - 1 : 0, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
+  // the ghosts repeat beyond both ends
+  const bool rr_is_r = j + 1 > n;
+  const AxElem RR = axi_elem(rr_is_r ? j + 1 : j + 2, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
   auto rho_of = [](const float* l) { return (double)fmaxf(fabsf(l[0]), fabsf(l[1])); };
   const double a = fmax(rho_of(L.lam), rho_of(R.lam));
-  double t[5][5], r[3][3], t2[5][5], r2[3][3];
+  double t[5][5], r[3][3], t2[5][5], r2[3][3], t3[5][5], r3[3][3];
   axi_T(R.g, L.g, t, r);
   axi_T(R.g, LL.g, t2, r2);
+  axi_T(R.g, RR.g, t3, r3);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    double ml = 0.0, fl = 0.0, mll = 0.0;
+    double ml = 0.0, fl = 0.0, mll = 0.0, mrr = 0.0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       const double tk = tij(t, r, i, k);
       ml += tk * (double)L.M[k];
       fl += tk * (double)L.F[k];
       mll += tij(t2, r2, i, k) * (double)LL.M[k];
+      mrr += tij(t3, r3, i, k) * (double)RR.M[k];
     }
     const double mr = R.M[i], fr = R.F[i];
+    if (rr_is_r) mrr = mr;
     fLF[j * 9 + i] = (float)(0.5 * (fl + fr) + 0.5 * a * (ml - mr));
     Mh[j * 9 + i] = (float)(0.5 * (ml + mr) + 0.5 * (dt / dx) * (fl - fr));
     double ph = 1.0;
-    if (flic) {  // van Leer: 2 a / (a + b) for a b > 0, else 0
-      const double da = ml - mll, db = mr - ml;
-      ph = da * db > 0.0 ? 2.0 * da / (da + db) : 0.0;
+    if (flic) {  // van Leer on both sides: 2 a / (a + b) for a b > 0, else 0; the smaller
+      const double da = ml - mll, db = mr - ml, dc = mrr - mr;
+      const double pl = da * db > 0.0 ? 2.0 * da / (da + db) : 0.0;
+      const double pr = dc * db > 0.0 ? 2.0 * dc / (dc + db) : 0.0;
+      ph = fmin(pl, pr);
     }
     phi[j * 9 + i] = (float)ph;
     bI[j * 9 + i] = R.b[i];

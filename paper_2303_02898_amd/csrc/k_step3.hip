@@ -620,16 +620,33 @@ __global__ __launch_bounds__(64) void k_iface3(int64_t n, int P, const float* __
   }
   change_gauge(ml, gI, gl);
   if (flic) {
-    float u[K3];
-    const float* src = row(M, gM, ll, K3);
+    // the element beyond r on the right (the right ghost repeats past the end)
+    const int64_t rr = (r >= 0 && r + 1 < off[p + 1]) ? r + 1 : -2;
+    float u[K3], v[K3];
+    {
+      const float* src = row(M, gM, ll, K3);
 #pragma unroll
-    for (int i = 0; i < K3; ++i) u[i] = src[i];
-    change_gauge(u, gI, row(g, gG, ll, 3));
-    // van Leer phi(r) = (r + |r|) / (1 + |r|), r = (M_l - M_ll) / (M_r - M_l)
+      for (int i = 0; i < K3; ++i) u[i] = src[i];
+      change_gauge(u, gI, row(g, gG, ll, 3));
+    }
+    if (rr == r) {
+#pragma unroll
+      for (int i = 0; i < K3; ++i) v[i] = MR[i];
+    } else {
+      const float* src = row(M, gM, rr, K3);
+#pragma unroll
+      for (int i = 0; i < K3; ++i) v[i] = src[i];
+      change_gauge(v, gI, row(g, gG, rr, 3));
+    }
+    // van Leer phi(r) = (r + |r|) / (1 + |r|) on both sides of the interface:
+    // r_L = (M_l - M_ll) / (M_r - M_l), r_R = (M_rr - M_r) / (M_r - M_l); the
+    // smaller one is taken (waves in either direction)
 #pragma unroll
     for (int i = 0; i < K3; ++i) {
-      const float a = ml[i] - u[i], b = MR[i] - ml[i];
-      hPhi[iface * K3 + i] = a * b > 0.f ? 2.f * a / (a + b) : 0.f;
+      const float a = ml[i] - u[i], b = MR[i] - ml[i], c = v[i] - MR[i];
+      const float pl = a * b > 0.f ? 2.f * a / (a + b) : 0.f;
+      const float pr = c * b > 0.f ? 2.f * c / (c + b) : 0.f;
+      hPhi[iface * K3 + i] = fminf(pl, pr);
     }
   }
   float fl[K3];

@@ -60,7 +60,7 @@ struct StepKey {
   uint32_t* status;
   memk::SolveParams p;
   int refine;
-  float* ws;  // workspace generation (mem_reserve reallocates)
+  uint64_t gen;  // workspace and tuning generation (see mem_ctx_s::ws_gen)
 };
 
 struct mem_ctx_s {
@@ -131,6 +131,9 @@ struct mem_ctx_s {
   float* w_gF = nullptr;      // ghost fluxes    [2*P][K]
   float* w_gR = nullptr;      // ghost radius    [2*P]
   uint32_t* w_rmax = nullptr; // per-problem max radius (float bits) [P]
+  // bumped by every reallocation of the workspace and every change of the
+  // launch parameters: a captured step holds the old pointers and grid shapes
+  uint64_t ws_gen = 0;
   // captured time step of mem_step (use_graph)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t step_exec = nullptr;

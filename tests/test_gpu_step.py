@@ -355,6 +355,31 @@ def test_graph_step_matches_eager(ctx3):
     print(f"[graph] 4 calls (1..4 steps) identical to plain launches, t = {runs[True][-1][3].item():.4f}")
 
 
+def test_graph_step_after_workspace_growth():
+    # a captured step holds workspace pointers and launch shapes: growing the
+    # workspace (mem_reserve with more cells and problems) and changing the
+    # launch parameters between replays must rebuild it; graph and plain
+    # launches then agree bit for bit
+    problem = mem_inputs.shock_problem(3.0, 200, -8.0, 8.0, 3.0)
+    runs = {}
+    for graph in (False, True):
+        c = mem.Context(3, 12)
+        try:
+            batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, c, 0, use_graph=graph)
+            c.step(batch, Md, bd, gd, t, dt, 2, status=status)
+            c.reserve(8192, 64)          # every workspace buffer is reallocated
+            c.step(batch, Md, bd, gd, t, dt, 2, status=status)
+            c.set_tuning(dir_waves=8, split_want=1024)
+            c.step(batch, Md, bd, gd, t, dt, 2, status=status)
+            torch.cuda.synchronize()
+            runs[graph] = [x.clone() for x in (Md, bd, gd, t, dt, status)]
+        finally:
+            c.close()
+    for k, (x, y) in enumerate(zip(runs[False], runs[True])):
+        assert torch.equal(x, y), k
+    print(f"\n[graph] rebuilt after reserve and set_tuning, t = {runs[True][3].item():.4f}")
+
+
 @pytest.mark.parametrize("scheme", ["lw", "flic"])
 def test_second_order_steps_match_oracle(ctx3, scheme):
     # Mach 3, 240 cells of 0.1 upstream mean free paths: both interface schemes
@@ -514,9 +539,10 @@ def test_flic_shock_reaches_steady_state(ctx3):
     dmass = abs(tot1[0, 0] - tot0[0, 0]) / ((t.item() - t0) * n1 * v1)
     print(f"[flic steady] mass change over {t.item() - t0:.2f} time units: {dmass:.2e} of the inflow")
     assert dmass < 1e-3
-    # At the sub-shock the limiter switches from step to step: the state is a
-    # short limit cycle whose average no longer moves.  One step from it, GPU and
-    # FP64 oracle agree cell by cell.
+    # One step from the steady state, GPU and FP64 oracle agree cell by cell.
+    # The step itself is a few FP32 roundings of n (the limiter, taken on both
+    # sides of each interface, no longer switches at the sub-shock), so the
+    # comparison of the increments is bounded by 1e-6 n as well as by 2% of it.
     ora = kinetics.ShockSolver(3.0, 250, -20.0, 20.0, 5.44, nodes_1d=12, scheme="flic")
     ora.M, ora.g = Md.cpu().numpy().astype(np.float64), gd.cpu().numpy().astype(np.float64)
     ora.beta = ora._solve(ora.M, bd.cpu().numpy().astype(np.float64))
@@ -529,10 +555,10 @@ def test_flic_shock_reaches_steady_state(ctx3):
     n_gpu = Md[:, 0].cpu().numpy().astype(np.float64)
     step_o = ora.M[:, 0] - n_before
     step_g = n_gpu - n_before
-    err = np.max(np.abs(step_g - step_o)) / np.max(np.abs(step_o))
+    derr = np.max(np.abs(step_g - step_o))
     print(f"[flic steady] one step from the steady state: max |dn| {np.max(np.abs(step_o)):.3e}, "
-          f"GPU vs oracle {err:.2e} of it; drift per 100 steps {change:.2e}")
-    assert err < 2e-2
+          f"GPU vs oracle {derr:.2e}; drift per 100 steps {change:.2e}")
+    assert derr < max(2e-2 * np.max(np.abs(step_o)), 1e-6 * np.max(n_before))
     mo = kinetics.macroscopic(ora.M, ora.g)
     mgs = kinetics.macroscopic(Md.cpu().numpy().astype(np.float64), gd.cpu().numpy().astype(np.float64))
     assert np.max(np.abs(mgs["n"] - mo["n"]) / mo["n"]) < 1e-5
