@@ -221,6 +221,24 @@ MEM_API mem_err_t mem_maxent_solve(mem_ctx_t ctx, int64_t n_cells, const float* 
                                    int32_t* iters, float* resid, uint32_t* status,
                                    hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): mem_maxent_solve
+ * with the Newton workspace taken from a static device array of about 25 MiB
+ * that the library holds on every GPU it runs on until the process ends.
+ * Same arguments, kernels and results as mem_maxent_solve; at most 8192 cells
+ * per call (more returns MEM_ERR_INVALID_ARG and launches nothing).  The call
+ * allocates nothing and calls no allocating library routine; with
+ * opts->check_every = 0 it never synchronises the stream (each of the
+ * max_iter Newton passes is launched; passes with no live cell end at once),
+ * so it can be captured.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (two streams, or two contexts on the same
+ * device) race and give wrong results.  dim 1 contexts need no workspace and
+ * run the 1D solve. */
+MEM_API mem_err_t mem_maxent_solve_noalloc(mem_ctx_t ctx, int64_t n_cells, const float* M,
+                                           float* beta, const mem_solve_opts_t* opts,
+                                           int32_t* iters, float* resid, uint32_t* status,
+                                           hipStream_t stream);
+
 /* Dual evaluation at given beta (Sec. 3.1 and App. C), for checking the
  * kernels: logZ[n] (log partition function with Lebesgue weights), E[n][K] =
  * E_sigma[phi], H[n][K-1][K-1] = covariance block of the Hessian (i,j >= 1).

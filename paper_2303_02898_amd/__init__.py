@@ -94,6 +94,7 @@ def load_library():
         "mem_host_table": ([_c_i32, _c_i32, _c_i32, P, _c_i64, ctypes.POINTER(_c_i64)], E),
         "mem_gauge": ([P, _c_i64, P, P, P, P], E),
         "mem_maxent_solve": ([P, _c_i64, P, P, ctypes.POINTER(SolveOpts), P, P, P, P], E),
+        "mem_maxent_solve_noalloc": ([P, _c_i64, P, P, ctypes.POINTER(SolveOpts), P, P, P, P], E),
         "mem_dual": ([P, _c_i64, P, P, P, P, P], E),
         "mem_moment_residual": ([P, _c_i64, P, P, P, P], E),
         "mem_flux": ([P, _c_i64, P, P, P, P, P], E),
@@ -294,6 +295,28 @@ class Context:
             _ptr(beta, torch.float32, (self.K,), "beta"), o, _ptr(iters, torch.int32),
             _ptr(resid, torch.float32), _ptr(status, torch.int32), _stream(stream)),
             "mem_maxent_solve")
+        return iters, resid, status
+
+    def solve_noalloc(self, M, beta, opts=None, iters=None, resid=None, status=None,
+                      stream=None):
+        """mem_maxent_solve_noalloc: the same solve on the library's static device
+        scratch (at most 8192 cells per call); the output tensors must be given
+        by callers that cannot allocate."""
+        import torch
+        n = M.shape[0]
+        dev = M.device
+        if iters is None:
+            iters = torch.zeros(n, dtype=torch.int32, device=dev)
+        if resid is None:
+            resid = torch.zeros(n, dtype=torch.float32, device=dev)
+        if status is None:
+            status = torch.zeros(n, dtype=torch.int32, device=dev)
+        o = ctypes.byref(opts) if opts is not None else None
+        self._check(self._lib.mem_maxent_solve_noalloc(
+            self._h, n, _ptr(M, torch.float32, (self.K,), "M"),
+            _ptr(beta, torch.float32, (self.K,), "beta"), o, _ptr(iters, torch.int32),
+            _ptr(resid, torch.float32), _ptr(status, torch.int32), _stream(stream)),
+            "mem_maxent_solve_noalloc")
         return iters, resid, status
 
     def dual(self, beta, stream=None):

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "mem_internal.h"
@@ -10,6 +11,103 @@
 using namespace memk;
 
 namespace {
+
+// ---- device scratch of mem_maxent_solve_noalloc --------------------------------
+// The Newton workspace of up to NOALLOC_MAX_CELLS cells plus a node-range split
+// buffer, carved in a fixed order from one file-scope device array.  Every GPU
+// the library runs on holds its own copy until the process ends.  Host code
+// never takes the array's address directly: mem_create resolves its device
+// address once per device with hipGetSymbolAddress (the device current) and
+// every host use goes through that pointer.
+constexpr int64_t NOALLOC_MAX_CELLS = 8192;
+constexpr int64_t NOALLOC_SPLIT_ROWS = 1024;
+constexpr size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Byte offsets of the carved regions (n = NOALLOC_MAX_CELLS rows each).
+struct NoallocLayout {
+  size_t S, dbeta, logZ, L, alpha, gdot, resid, iters, status, list[5], ctr, code, Sp, Gacc,
+      racc, rbest, itbest, total;
+};
+constexpr NoallocLayout noalloc_layout() {
+  NoallocLayout l{};
+  const size_t n = (size_t)NOALLOC_MAX_CELLS;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) { const size_t at = o; o += al256(bytes); return at; };
+  l.S = take(n * NCOL * 4);
+  l.dbeta = take(n * 36 * 4);
+  l.logZ = take(n * 4);
+  l.L = take(n * 4);
+  l.alpha = take(n * 4);
+  l.gdot = take(n * 4);
+  l.resid = take(n * 4);
+  l.iters = take(n * 4);
+  l.status = take(n * 4);
+  for (int k = 0; k < 5; ++k) l.list[k] = take(n * 4);
+  l.ctr = take(8 * 4);
+  l.code = take(n);
+  l.Sp = take((size_t)NOALLOC_SPLIT_ROWS * NCOL * 4);
+  l.Gacc = take(n * 36 * 4);
+  l.racc = take(n * 4);
+  l.rbest = take(n * 4);
+  l.itbest = take(n * 4);
+  l.total = o;
+  return l;
+}
+constexpr NoallocLayout NOALLOC = noalloc_layout();
+
+__device__ __align__(256) unsigned char scratch[NOALLOC.total];
+
+// The context fields the Newton loop (newton3) reads as its workspace.
+struct NewtonWorkspace {
+  float *S, *dbeta, *logZ, *L, *alpha, *gdot, *resid;
+  int32_t* iters;
+  uint32_t* status;
+  int32_t* list[5];
+  int32_t* ctr;
+  int8_t* code;
+  float* Sp;
+  int64_t sp_rows;
+  float *Gacc, *racc, *rbest;
+  int32_t* itbest;
+  bool prof;
+  static NewtonWorkspace of(const mem_ctx_s* c) {
+    NewtonWorkspace w;
+    w.S = c->w_S; w.dbeta = c->w_dbeta; w.logZ = c->w_logZ; w.L = c->w_L;
+    w.alpha = c->w_alpha; w.gdot = c->w_gdot; w.resid = c->w_resid; w.iters = c->w_iters;
+    w.status = c->w_status;
+    for (int k = 0; k < 5; ++k) w.list[k] = c->w_list[k];
+    w.ctr = c->w_ctr; w.code = c->w_code; w.Sp = c->w_Sp; w.sp_rows = c->sp_rows;
+    w.Gacc = c->w_Gacc; w.racc = c->w_racc; w.rbest = c->w_rbest; w.itbest = c->w_itbest;
+    w.prof = c->prof;
+    return w;
+  }
+  void install(mem_ctx_s* c) const {
+    c->w_S = S; c->w_dbeta = dbeta; c->w_logZ = logZ; c->w_L = L; c->w_alpha = alpha;
+    c->w_gdot = gdot; c->w_resid = resid; c->w_iters = iters; c->w_status = status;
+    for (int k = 0; k < 5; ++k) c->w_list[k] = list[k];
+    c->w_ctr = ctr; c->w_code = code; c->w_Sp = Sp; c->sp_rows = sp_rows; c->w_Gacc = Gacc;
+    c->w_racc = racc; c->w_rbest = rbest; c->w_itbest = itbest; c->prof = prof;
+  }
+};
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (resolved once per device).
+hipError_t resolve_scratch(int device, unsigned char** out) {
+  *out = nullptr;
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 mem_err_t fail(mem_ctx_t c, mem_err_t e, const std::string& msg) {
   if (c) c->err = msg;
@@ -264,6 +362,10 @@ mem_err_t mem_create(const mem_config_t* cfg, mem_ctx_t* out) {
     mem_destroy(c);
     return MEM_ERR_NOMEM;
   }
+  if (resolve_scratch(c->device, &c->scratch) != hipSuccess) {
+    mem_destroy(c);
+    return MEM_ERR_HIP;
+  }
   *out = c;
   return MEM_OK;
 }
@@ -382,6 +484,62 @@ mem_err_t mem_maxent_solve(mem_ctx_t c, int64_t n, const float* M, float* beta,
   p.refine = refine;
   return newton3(c, n, M, beta, p, p.max_iter, poll, refine, iters, resid, status, s, nullptr,
                  true);
+}
+
+mem_err_t mem_maxent_solve_noalloc(mem_ctx_t c, int64_t n, const float* M, float* beta,
+                                   const mem_solve_opts_t* opts, int32_t* iters, float* resid,
+                                   uint32_t* status, hipStream_t s) {
+  if (!c) return MEM_ERR_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!M || !beta)))
+    return fail(c, MEM_ERR_INVALID_ARG, "mem_maxent_solve_noalloc: arguments");
+  if (n > NOALLOC_MAX_CELLS)
+    return fail(c, MEM_ERR_INVALID_ARG,
+                "mem_maxent_solve_noalloc: at most " + std::to_string(NOALLOC_MAX_CELLS) +
+                    " cells per call (static device scratch)");
+  if (!opts_ok(opts)) return fail(c, MEM_ERR_INVALID_ARG, "mem_maxent_solve_noalloc: options");
+  if (n == 0) return MEM_OK;
+  SolveParams p = params_from(opts);
+  p.lmin = dual_floor(c);
+  if (c->dim == 1) {  // the 1D solve keeps its whole state in registers
+    p.refine = 0;
+    MEM_HIP(c, launch_solve1(c, n, M, beta, p, iters, resid, status, s));
+    return MEM_OK;
+  }
+  if (!c->scratch) return fail(c, MEM_ERR_HIP, "mem_maxent_solve_noalloc: no device scratch");
+  mem_solve_opts_t d;
+  mem_solve_opts_default(&d);
+  const int poll = opts ? opts->check_every : d.check_every;
+  const int refine = opts ? opts->refine : d.refine;
+  p.refine = refine;
+  // point the Newton workspace at the scratch for this call, then put the
+  // context's own workspace back (the kernels are those of mem_maxent_solve)
+  NewtonWorkspace own = NewtonWorkspace::of(c);
+  unsigned char* b = c->scratch;
+  NewtonWorkspace w;
+  w.S = reinterpret_cast<float*>(b + NOALLOC.S);
+  w.dbeta = reinterpret_cast<float*>(b + NOALLOC.dbeta);
+  w.logZ = reinterpret_cast<float*>(b + NOALLOC.logZ);
+  w.L = reinterpret_cast<float*>(b + NOALLOC.L);
+  w.alpha = reinterpret_cast<float*>(b + NOALLOC.alpha);
+  w.gdot = reinterpret_cast<float*>(b + NOALLOC.gdot);
+  w.resid = reinterpret_cast<float*>(b + NOALLOC.resid);
+  w.iters = reinterpret_cast<int32_t*>(b + NOALLOC.iters);
+  w.status = reinterpret_cast<uint32_t*>(b + NOALLOC.status);
+  for (int k = 0; k < 5; ++k) w.list[k] = reinterpret_cast<int32_t*>(b + NOALLOC.list[k]);
+  w.ctr = reinterpret_cast<int32_t*>(b + NOALLOC.ctr);
+  w.code = reinterpret_cast<int8_t*>(b + NOALLOC.code);
+  w.Sp = reinterpret_cast<float*>(b + NOALLOC.Sp);
+  w.sp_rows = NOALLOC_SPLIT_ROWS;
+  w.Gacc = reinterpret_cast<float*>(b + NOALLOC.Gacc);
+  w.racc = reinterpret_cast<float*>(b + NOALLOC.racc);
+  w.rbest = reinterpret_cast<float*>(b + NOALLOC.rbest);
+  w.itbest = reinterpret_cast<int32_t*>(b + NOALLOC.itbest);
+  w.prof = false;  // no host-side event bookkeeping
+  w.install(c);
+  const mem_err_t e = newton3(c, n, M, beta, p, p.max_iter, poll, refine, iters, resid, status,
+                              s, nullptr, true);
+  own.install(c);
+  return e;
 }
 
 mem_err_t mem_dual(mem_ctx_t c, int64_t n, const float* beta, float* logZ, float* E, float* H,

@@ -112,6 +112,7 @@ struct mem_ctx_s {
   float* w_rbest = nullptr;   // [cap] best FP32 residual so far (stall test)
   int32_t* w_itbest = nullptr;// [cap] iteration of the last halving of the residual
   int32_t* h_ctr = nullptr;   // pinned host mirror for polling
+  unsigned char* scratch = nullptr;  // this device's static scratch (mem_maxent_solve_noalloc)
   // time stepping
   float* w_Mnew = nullptr;    // [cap][K]
   float* w_F = nullptr;       // [cap][K]
