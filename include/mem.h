@@ -324,10 +324,20 @@ typedef struct {
                           splitting the quadrature nodes into ranges (the node tile
                           of a workgroup is Q / splits); 0 = never split (512)     */
   double  tuned_ms;    /* time of the best trial in mem_autotune (0 = not tuned)   */
+  int32_t solver;      /* Newton loop of the 3D FP32 solve: 0 = list-compacted
+                          launches per pass with the MFMA assembly (sigma . Psi);
+                          1 = one persistent kernel, a wavefront per live cell
+                          taken from a work queue, the assembly sum-factorised on
+                          the tensor grid (12-point rules only; other rules and the
+                          mixed precisions use 0) (default 1)                       */
+  int32_t wave_max_cells; /* with solver 1: launches of more cells use solver 0;
+                          0 = no limit (default 0)                                   */
 } mem_tuning_t;
 
-/* Time full solves of this batch with every candidate (dir_waves in {2, 4, 8},
- * then split_want in {0, 256, 512, 1024, 2048}, one coordinate at a time, each
+/* Time full solves of this batch with every candidate (the Newton loop,
+ * solver in {0, 1}, where the persistent kernel applies; then for solver 0
+ * dir_waves in {2, 4, 8} and split_want in {0, 256, 512, 1024, 2048}), one
+ * coordinate at a time, each
  * trial warm and timed with HIP events on `stream`), keep the fastest in the
  * context and return it in *out (nullable).  beta_init is not modified; the
  * trials run in beta_work [n_cells][35] (device, caller-owned).  Synchronous. */

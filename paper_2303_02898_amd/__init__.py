@@ -68,7 +68,8 @@ class AxiShockStruct(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("dir_waves", _c_i32), ("split_want", _c_i32), ("tuned_ms", ctypes.c_double)]
+    _fields_ = [("dir_waves", _c_i32), ("split_want", _c_i32), ("tuned_ms", ctypes.c_double),
+                ("solver", _c_i32), ("wave_max_cells", _c_i32)]
 
 
 def load_library():
@@ -229,15 +230,17 @@ class Context:
                                            _ptr(beta_init, torch.float32, (self.K,), "beta_init"),
                                            work.data_ptr(), o, ctypes.byref(t), _stream(stream)),
                     "mem_autotune")
-        return {"dir_waves": t.dir_waves, "split_want": t.split_want, "tuned_ms": t.tuned_ms}
+        return {"dir_waves": t.dir_waves, "split_want": t.split_want, "tuned_ms": t.tuned_ms,
+                "solver": t.solver, "wave_max_cells": t.wave_max_cells}
 
     def tuning(self):
         t = Tuning()
         self._check(self._lib.mem_get_tuning(self._h, ctypes.byref(t)), "mem_get_tuning")
-        return {"dir_waves": t.dir_waves, "split_want": t.split_want, "tuned_ms": t.tuned_ms}
+        return {"dir_waves": t.dir_waves, "split_want": t.split_want, "tuned_ms": t.tuned_ms,
+                "solver": t.solver, "wave_max_cells": t.wave_max_cells}
 
-    def set_tuning(self, dir_waves=4, split_want=512):
-        t = Tuning(int(dir_waves), int(split_want), 0.0)
+    def set_tuning(self, dir_waves=4, split_want=512, solver=1, wave_max_cells=0):
+        t = Tuning(int(dir_waves), int(split_want), 0.0, int(solver), int(wave_max_cells))
         self._check(self._lib.mem_set_tuning(self._h, ctypes.byref(t)), "mem_set_tuning")
 
     def reserve(self, max_cells, max_problems=0):
@@ -264,7 +267,7 @@ class Context:
 
     def profile_read(self, kernel):
         """(total ms, launches) for kernel 'assemble', 'direction' or 'lse'."""
-        kid = {"assemble": 0, "direction": 1, "lse": 2}[kernel]
+        kid = {"assemble": 0, "direction": 1, "lse": 2, "wave": 3}[kernel]
         ms, cnt = ctypes.c_double(), _c_i64()
         self._check(self._lib.mem_profile_read(self._h, kid, ctypes.byref(ms), ctypes.byref(cnt)),
                     "mem_profile_read")

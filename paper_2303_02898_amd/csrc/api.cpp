@@ -220,6 +220,12 @@ struct ProfScope {
   }
 };
 
+// The persistent one-wave-per-cell Newton kernel serves this launch.
+bool wave_solver(mem_ctx_t c, int64_t n) {
+  return c->tune.solver == 1 && c->prec == MEM_PREC_FP32 && c->n1d == 12 &&
+         (c->tune.wave_max_cells <= 0 || n <= c->tune.wave_max_cells);
+}
+
 // Newton iterations of Alg. 1 over the live work-list.  With poll > 0 the
 // stream is synchronised every `poll` iterations to stop once no cell is live.
 // Counters: 0/1 live lists (alternating), 2 FP64 list, 3 converged list,
@@ -231,6 +237,12 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
   int32_t* ctr = c->w_ctr;
   int32_t* done = refine > 0 ? c->w_list[3] : nullptr;
   MEM_HIP(c, launch_set_ctr(ctr, 8, s));
+  if (wave_solver(c, n)) {
+    // one persistent kernel for the whole Newton loop (counter 7: work queue)
+    ProfScope ps(c, 3, s);
+    MEM_HIP(c, launch_newton_wave(c, n, M, beta, p, try_closed_start && c->n1d >= 5, &ctr[7],
+                                  iters, resid, status, done, &ctr[3], cond, s));
+  } else {
   MEM_HIP(c, launch_init3(c, n, M, beta, c->w_list[0], &ctr[0], iters, resid, status, s));
   {
     ProfScope ps(c, 2, s);
@@ -280,6 +292,7 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
       if (*c->h_ctr == 0) break;
       grid = *c->h_ctr;
     }
+  }
   }
   if (refine > 0) {
     // compensated residual of the converged cells; those above tol_grad get a
@@ -351,6 +364,9 @@ mem_err_t mem_create(const mem_config_t* cfg, mem_ctx_t* out) {
   c->n1d = cfg->n_nodes_1d;
   c->prec = cfg->prec;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return MEM_ERR_HIP; }
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) !=
+          hipSuccess || c->n_cu <= 0)
+    c->n_cu = 256;
   try {
     memt::build_tables(c);
   } catch (...) {
@@ -755,8 +771,10 @@ mem_err_t mem_get_tuning(mem_ctx_t c, mem_tuning_t* out) {
 mem_err_t mem_set_tuning(mem_ctx_t c, const mem_tuning_t* in) {
   if (!c || !in) return MEM_ERR_INVALID_ARG;
   if ((in->dir_waves != 2 && in->dir_waves != 4 && in->dir_waves != 8) || in->split_want < 0 ||
-      in->split_want > 65536)
-    return fail(c, MEM_ERR_INVALID_ARG, "mem_set_tuning: dir_waves in {2,4,8}, split_want in [0, 65536]");
+      in->split_want > 65536 || (in->solver != 0 && in->solver != 1) || in->wave_max_cells < 0)
+    return fail(c, MEM_ERR_INVALID_ARG,
+                "mem_set_tuning: dir_waves in {2,4,8}, split_want in [0, 65536], solver 0 or 1, "
+                "wave_max_cells >= 0");
   c->tune = *in;
   ++c->ws_gen;
   return MEM_OK;
@@ -799,9 +817,26 @@ mem_err_t mem_autotune(mem_ctx_t c, int64_t n, const float* M, const float* beta
   };
   mem_tuning_t best = c->tune;
   double best_ms = 1e30;
+  // the Newton loop first: the persistent kernel (when it applies) or the
+  // list-compacted passes, whose launch shapes are tuned next
+  if (c->prec == MEM_PREC_FP32 && c->n1d == 12) {
+    for (int sv : {1, 0}) {
+      if (e != MEM_OK) break;
+      mem_tuning_t t = best;
+      t.solver = sv;
+      t.wave_max_cells = 0;
+      double ms = 0.0;
+      if ((e = trial(t, ms)) != MEM_OK) break;
+      if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+  } else {
+    best.solver = 0;
+  }
+  const bool list_loop = best.solver == 0;
   const int dws[] = {2, 4, 8};
   const int sws[] = {0, 256, 512, 1024, 2048};
   for (int dw : dws) {
+    if (e != MEM_OK || !list_loop) break;
     mem_tuning_t t = best;
     t.dir_waves = dw;
     double ms = 0.0;
@@ -809,7 +844,7 @@ mem_err_t mem_autotune(mem_ctx_t c, int64_t n, const float* M, const float* beta
     if (ms < best_ms) { best_ms = ms; best = t; }
   }
   for (int sw : sws) {
-    if (e != MEM_OK) break;
+    if (e != MEM_OK || !list_loop) break;
     mem_tuning_t t = best;
     t.split_want = sw;
     double ms = 0.0;

@@ -1321,6 +1321,530 @@ __global__ void k_unpack3(int64_t n, const float* __restrict__ S, float* E, floa
       }
 }
 
+
+// --------------------------------------------------------------------------
+// Persistent Newton solve: one wavefront runs the whole of Alg. 1 for a cell
+// --------------------------------------------------------------------------
+// Each wave takes cells from a work queue (one atomic per cell) and iterates
+// a cell until a stopping test of Alg. 1 ends it; a converged cell frees its
+// wave for the next live one (convergence masking and re-compaction without a
+// grid-wide barrier or a launch per Newton pass).  Every step is the one of the
+// list-based kernels above: the stopping tests and book-keeping, the
+// lambda-shifted Cholesky with the FP64 switch on the pivot ratio, the Armijo
+// line search on the sum-factorised exponent, the closed-form first pass from
+// the gauge Maxwellian.
+//
+// The Hessian assembly exploits the tensor grid (x_i, x_j, x_l) and the product
+// basis phi_(abc) = h_a h_b h_c:
+//   E[phi_(abc) phi_(a'b'c')] = sum_{i,j,l} sigma_ijl H_aa'(x_i) H_bb'(x_j) H_cc'(x_l)
+// with H_pq = h_p h_q (15 unordered pairs p <= q <= 4), contracted one axis at a
+// time (sum factorisation):
+//   P1[i][j][cc'] = sum_l sigma_ijl H_cc'(x_l)                (n^3 * 15 FMA)
+//   P2_i[bb'][cc'] = sum_j P1[i][j][cc'] H_bb'(x_j)           (n^2 * 105 FMA)
+//   T[aa'][bb'][cc'] += H_aa'(x_i) P2_i[bb'][cc']             (n * 484 FMA)
+// for the 105 (bb', cc') and 484 (aa', bb', cc') combinations the 630 pair
+// columns need: about 47 k FMA per cell and iteration at n = 12, against 1.09 M
+// for the dense sigma . Psi product.
+
+// Unordered pair (p, q) of one-dimensional Hermite indices (p, q <= 4): 0..14.
+__host__ __device__ constexpr int up_idx(int p, int q) {
+  const int lo = p < q ? p : q, hi = p < q ? q : p;
+  return lo * 5 - lo * (lo - 1) / 2 + (hi - lo);
+}
+
+constexpr int SF_NBC = 105;  // (bb', cc') combinations of the 630 pairs
+constexpr int SF_NT = 484;   // (aa', bb', cc') combinations
+
+struct SfTables {
+  int8_t bcB[128], bcC[128];  // up-indices of each (bb', cc') combination
+  int8_t tA[512];             // aa' of each triple
+  int16_t tBC[512];           // its (bb', cc') combination
+  int16_t colT[NCOL];         // triple of each pair column (-1: padding column)
+  int nbc, nt;
+};
+
+// (a, b, c) of basis index k (inverse of bidx3).
+__host__ __device__ constexpr void abc_of(int k, int& a, int& b, int& c) {
+  int t = 0;
+  while ((t + 1) * (t + 2) * (t + 3) / 6 <= k) ++t;
+  const int rr = k - t * (t + 1) * (t + 2) / 6;
+  int m = 0;
+  while ((m + 1) * (m + 2) / 2 <= rr) ++m;
+  c = rr - m * (m + 1) / 2;
+  b = m - c;
+  a = t - m;
+}
+
+constexpr SfTables make_sf_tables() {
+  SfTables s{};
+  int bc_of[225] = {};
+  int tri_of[15 * 225] = {};
+  for (int q = 0; q < 225; ++q) bc_of[q] = -1;
+  for (int q = 0; q < 15 * 225; ++q) tri_of[q] = -1;
+  s.nbc = 0;
+  s.nt = 0;
+  for (int col = 0; col < NCOL; ++col) s.colT[col] = -1;
+  for (int i = 0; i < K3; ++i)
+    for (int j = i; j < K3; ++j) {
+      int a1 = 0, b1 = 0, c1 = 0, a2 = 0, b2 = 0, c2 = 0;
+      abc_of(i, a1, b1, c1);
+      abc_of(j, a2, b2, c2);
+      const int A = up_idx(a1, a2), B = up_idx(b1, b2), C = up_idx(c1, c2);
+      if (bc_of[B * 15 + C] < 0) {
+        bc_of[B * 15 + C] = s.nbc;
+        s.bcB[s.nbc] = (int8_t)B;
+        s.bcC[s.nbc] = (int8_t)C;
+        ++s.nbc;
+      }
+      const int q = bc_of[B * 15 + C];
+      if (tri_of[A * 225 + B * 15 + C] < 0) {
+        tri_of[A * 225 + B * 15 + C] = s.nt;
+        s.tA[s.nt] = (int8_t)A;
+        s.tBC[s.nt] = (int16_t)q;
+        ++s.nt;
+      }
+      s.colT[pair_col(i, j)] = (int16_t)tri_of[A * 225 + B * 15 + C];
+    }
+  return s;
+}
+static_assert(make_sf_tables().nbc == SF_NBC && make_sf_tables().nt == SF_NT,
+              "sum-factorisation table sizes");
+__constant__ SfTables c_sf = make_sf_tables();
+
+// V[q][c] = sum_{a+b+c<=4} b_abc h_a(x_i) h_b(x_j) for every node pair q = (i, j):
+// the per-pair coefficients of the sum-factorised exponent (as in k_lse3).
+template <int NT>
+__device__ __forceinline__ void build_v(const float* sB, const float* sH, float* sV, int lane) {
+  float bb[K3];
+#pragma unroll
+  for (int k = 0; k < K3; ++k) bb[k] = sB[k];
+#pragma unroll 1
+  for (int q = lane; q < NT * NT; q += 64) {
+    const int i = q / NT, j = q - (q / NT) * NT;
+    float ha[5], hb[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) { ha[a] = sH[a * NT + i]; hb[a] = sH[a * NT + j]; }
+    float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+#pragma unroll
+      for (int b = 0; a + b < 5; ++b) {
+        const float pab = ha[a] * hb[b];
+#pragma unroll
+        for (int c = 0; a + b + c < 5; ++c) v[c] = fmaf(bb[bidx3(a, b, c)], pab, v[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sV[q * 5 + c] = v[c];
+  }
+}
+
+// Log-sum-exp of the exponent with coefficients sVb + alpha sVd over all nodes.
+template <bool LS, int NT>
+__device__ __forceinline__ float wave_lse(int lane, float alpha, const float* sH, const float* sVb,
+                                          const float* sVd) {
+  float mx = -FLT_MAX, sm = 0.f;
+  int z = 0;
+  asm volatile("" : "+v"(z));  // keep the table loads inside the pass (see the assembly)
+  lse_pairs<LS, NT>(NT, lane, alpha, sH + z, sVb, sVd, mx, sm);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float om = __shfl_xor(mx, off), os = __shfl_xor(sm, off);
+    const float nm = fmaxf(mx, om);
+    sm = sm * __expf(mx - nm) + os * __expf(om - nm);
+    mx = nm;
+  }
+  return mx + __logf(sm);
+}
+
+// Stopping tests and book-keeping of Alg. 1, as finish_cell, on the wave's
+// register copy of the cell's state.  Returns 1 (live), 2 (refinement
+// candidate) or 0 (finished).
+__device__ __forceinline__ int wave_finish(float r, float res, bool dir_ok, uint32_t extra,
+                                           const SolveParams& p, CellState& cs) {
+  const int it = cs.it + 1;
+  cs.it = it;
+  uint32_t st = cs.st | extra;
+  if (r < 0.5f * cs.rbest) { cs.rbest = r; cs.itbest = it; }
+  const bool conv = (r <= p.tol_grad) || (res <= p.tol_dec && r <= p.tol_loose);
+  const bool near = r <= STALL_GATE && p.refine > 0;
+  const bool stall = near && (it - cs.itbest >= STALL_WINDOW || cs.alpha <= p.alpha_min ||
+                              it >= p.max_iter);
+  bool done = true, cand = false;
+  if (conv || stall) { st |= MEM_ST_CONVERGED; cand = p.refine > 0; }
+  else if (cs.L < p.lmin || (p.beta_max > 0.f && cs.bmax > p.beta_max))
+    st |= MEM_ST_NONREALIZABLE;
+  else if (!isfinite(r) || !dir_ok) st |= MEM_ST_NONFINITE;
+  else if (cs.alpha <= p.alpha_min || it - cs.itbest >= NOPROGRESS_WINDOW)
+    st |= MEM_ST_STAGNATED;
+  else if (it >= p.max_iter) st |= MEM_ST_MAXITER;
+  else done = false;
+  cs.st = st;
+  return done ? (cand ? 2 : 0) : 1;
+}
+
+// Wave-uniform copies (scalar registers).  Every value that decides control
+// flow in k_newton_wave goes through these: the compiler cannot see that a
+// cross-lane broadcast or reduction is equal on all lanes, and a branch on a
+// vector register is compiled as divergent; lanes could then run different
+// queue iterations, where a broadcast from a masked-off lane is undefined.
+__device__ __forceinline__ float uf(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int ui(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double ud(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float uni(float v) { return uf(v); }
+__device__ __forceinline__ double uni(double v) { return ud(v); }
+
+// wave_chol with the pivot made wave-uniform (see uf): the early exit on a
+// failed pivot is then a uniform branch.
+template <typename T>
+__device__ __forceinline__ bool wave_chol_u(T (&a)[NH], T& dinv, int lane, T& dmin, T& dmax, T* Lm) {
+  dmin = (T)FLT_MAX; dmax = 0;
+  dinv = 1;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    T* row = Lm + k * LST;
+    if (lane < NH) row[lane] = a[k];
+    __builtin_amdgcn_wave_barrier();
+    T u[NH];
+#pragma unroll
+    for (int i = k; i < NH; ++i) u[i] = row[i];
+    const T d = uni(u[k]);
+    if (!((d > (T)0) && isfinite(d))) return false;
+    dmin = d < dmin ? d : dmin;
+    dmax = d > dmax ? d : dmax;
+    const T inv = rsq(d);
+    if (lane == k) dinv = inv;
+    const T cj = lane > k ? a[k] * (inv * inv) : (T)0;
+#pragma unroll
+    for (int i = k + 1; i < NH; ++i) a[i] = fma(-u[i], cj, a[i]);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < NH) row[lane] = lane >= k ? a[k] * inv : (T)0;
+    keep_col(a);
+    __builtin_amdgcn_wave_barrier();
+  }
+  return true;
+}
+
+// LDS of one wave (floats).  W holds P1 during the assembly, then the S row,
+// E and the factor (FP32), or E and the factor in FP64 (the S row then read
+// back from global memory).
+template <int NT>
+struct WaveLds {
+  static constexpr int NP = NT * NT;
+  static constexpr int W32 = NCOL + 36 + NH * LST;          // S, E, L (FP32)
+  static constexpr int W64 = 2 * (36 + NH * LST);           // E, L (FP64)
+  static constexpr int WP = NP * 15;                        // P1
+  static constexpr int WN = (WP > W32 ? (WP > W64 ? WP : W64) : (W32 > W64 ? W32 : W64));
+  float sH[6 * NT];
+  float sHp[15 * NT];
+  float sB[72];
+  float sVb[NP * 5];
+  float sVd[NP * 5];
+  float sP2[128];
+  float sT[512];
+  __align__(16) float W[(WN + 3) / 4 * 4];
+};
+
+template <int NT>
+__global__ __launch_bounds__(64) void k_newton_wave(
+    const float2* __restrict__ t1, int32_t* __restrict__ queue, int64_t ncell,
+    const float* __restrict__ M, float* __restrict__ beta, SolveParams p, int closed_start,
+    float* __restrict__ S_w, float* __restrict__ logZ_w, int32_t* __restrict__ iters_w,
+    uint32_t* __restrict__ status_w, float* __restrict__ resid_w, DirOut o) {
+  constexpr int NP = NT * NT;
+  static_assert(NP * 5 >= NCOL, "the FP64 direction keeps the S row in sVd");
+  __shared__ WaveLds<NT> L;
+  const int lane = threadIdx.x;
+  for (int t = lane; t < 6 * NT; t += 64) L.sH[t] = t1[t].x;
+  __builtin_amdgcn_wave_barrier();
+  for (int t = lane; t < 15 * NT; t += 64) {
+    const int pq = t / NT, k = t - (t / NT) * NT;
+    int pp = 0;
+    while (up_idx(pp, 4) < pq) ++pp;  // pq = up_idx(pp, qq) with qq >= pp
+    const int qq = pp + (pq - up_idx(pp, pp));
+    L.sHp[t] = L.sH[pp * NT + k] * L.sH[qq * NT + k];
+  }
+  __builtin_amdgcn_wave_barrier();
+  const float sq = -0.70710678118654752f;
+
+  for (;;) {
+    int got = 0;
+    if (lane == 0) got = atomicAdd(queue, 1);
+    const int slot = __builtin_amdgcn_readlane(got, 0);
+    if ((int64_t)slot >= ncell) break;
+    const int64_t cell = slot;
+    const float* Mc = M + cell * K3;
+    float* bc = beta + cell * K3;
+    const bool kin = lane >= 1 && lane < K3;
+    const float mraw = lane < K3 ? Mc[lane] : 0.f;
+    float bk = kin ? bc[lane] : 0.f;
+    const bool fin = lane >= K3 || (isfinite(mraw) && (lane == 0 || isfinite(bk)));
+    const float nn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mraw), 0));
+    uint32_t st0 = 0;
+    if (__ballot(!fin) != 0ull) st0 = MEM_ST_NONFINITE;
+    else if (!(nn > 0.f)) st0 = MEM_ST_NONREALIZABLE;
+    st0 = (uint32_t)ui((int)st0);
+    // one latch for the queue loop (no continue): a rejected cell skips the
+    // solve under a uniform branch and takes its status below
+    if (st0 == 0u) {
+    if (lane == 0) bc[0] = nn;
+    const float mn = kin ? mraw / nn : 0.f;          // M_k / n on lane k
+    // cross-lane reads with every lane active: M_{j+1} / n and M_{j+1} on lane j
+    const float mnj = __shfl(mn, (lane + 1) & 63);
+    const float mrj = __shfl(mraw, (lane + 1) & 63);
+    // log Z and the dual value at the starting beta (k_lse3 without search)
+    if (lane < 36) L.sB[lane] = bk;
+    __builtin_amdgcn_wave_barrier();
+    build_v<NT>(L.sB, L.sH, L.sVb, lane);
+    __builtin_amdgcn_wave_barrier();
+    float lz = uf(wave_lse<false, NT>(lane, 0.f, L.sH, L.sVb, L.sVd));
+    CellState cs;
+    cs.it = 0; cs.itbest = 0; cs.st = 0; cs.rbest = INFINITY; cs.alpha = 1.f;
+    cs.L = uf(lz - wave_sum(bk * mn));
+    bool maxw = false;
+    if (closed_start) {
+      const bool square = lane == bidx3(2, 0, 0) || lane == bidx3(0, 2, 0) || lane == bidx3(0, 0, 2);
+      maxw = __ballot(kin && bk != (square ? sq : 0.f)) == 0ull;
+    }
+    float r = 0.f, res = 0.f;
+    int code = 1;
+    bool ident_S = false;  // closed-form pass: S is the identity (refinement reads it)
+    for (;;) {
+      float dk = 0.f;  // direction on lane k (beta_k), k >= 1
+      uint32_t extra = 0;
+      bool dfin = true;
+      float cnd = 1.f;
+      cs.bmax = uf(wave_max(kin ? fabsf(bk) : 0.f));
+      if (cs.it == 0 && maxw) {
+        // closed-form first pass from the gauge Maxwellian: H = I, G = -M/n
+        const float gk = kin ? -mn : 0.f;
+        r = uf(wave_max(fabsf(gk)));
+        res = uf(0.5f * wave_sum(gk * gk));
+        if (!(nn > 0.f) || !isfinite(res)) r = NAN;
+        cs.bmax = 0.70710678118654752f;
+        dk = mn;
+        ident_S = true;
+      } else {
+        ident_S = false;
+        // rebuild the exponent coefficients at the current beta
+        if (lane < 36) L.sB[lane] = bk;
+        __builtin_amdgcn_wave_barrier();
+        build_v<NT>(L.sB, L.sH, L.sVb, lane);
+        __builtin_amdgcn_wave_barrier();
+        // stage 1: sigma and P1[q][pq] = sum_l sigma(q, l) H_pq(x_l)
+        float* P1 = L.W;
+#pragma unroll 1
+        for (int q = lane; q < NP; q += 64) {
+          // the tables never change, so without an opaque offset the compiler
+          // keeps all 252 of them in registers across the whole kernel
+          int z = 0;
+          asm volatile("" : "+v"(z));
+          const float* sh = L.sH + z;
+          const float* shp = L.sHp + z;
+          const int i = q / NT, j = q - (q / NT) * NT;
+          const float base = sh[5 * NT + i] + sh[5 * NT + j];
+          float v[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) v[c] = L.sVb[q * 5 + c];
+          float acc[15];
+#pragma unroll
+          for (int t = 0; t < 15; ++t) acc[t] = 0.f;
+#pragma unroll
+          for (int l = 0; l < NT; ++l) {
+            float x = base + sh[5 * NT + l];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) x = fmaf(v[c], sh[c * NT + l], x);
+            const float sg = __expf(x - lz);
+#pragma unroll
+            for (int t = 0; t < 15; ++t) acc[t] = fmaf(sg, shp[t * NT + l], acc[t]);
+          }
+#pragma unroll
+          for (int t = 0; t < 15; ++t) P1[q * 15 + t] = acc[t];
+        }
+        __builtin_amdgcn_wave_barrier();
+        // stages 2 and 3, one x node at a time
+        float tacc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tacc[k] = 0.f;
+        for (int x = 0; x < NT; ++x) {
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int qb = lane + 64 * k;
+            if (qb < SF_NBC) {
+              const int B = c_sf.bcB[qb], C = c_sf.bcC[qb];
+              float sacc = 0.f;
+#pragma unroll
+              for (int y = 0; y < NT; ++y)
+                sacc = fmaf(P1[(x * NT + y) * 15 + C], L.sHp[B * NT + y], sacc);
+              L.sP2[qb] = sacc;
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int t = lane + 64 * k;
+            if (t < SF_NT) tacc[k] = fmaf(L.sHp[c_sf.tA[t] * NT + x], L.sP2[c_sf.tBC[t]], tacc[k]);
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int t = lane + 64 * k;
+          if (t < SF_NT) L.sT[t] = tacc[k];
+        }
+        __builtin_amdgcn_wave_barrier();
+        float* Sr = L.W;  // the S row over the dead P1
+        for (int col = lane; col < NCOL; col += 64) {
+          const int t = c_sf.colT[col];
+          Sr[col] = t >= 0 ? L.sT[t] : 0.f;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // gradient, residual and Newton direction (k_direction3 / k_fallback3)
+        const float s00 = uf(Sr[0]);
+        const float inv0 = 1.f / s00;
+        float* E = L.W + NCOL;
+        if (lane < K3) E[lane] = lane == 0 ? 1.f : Sr[lane] * inv0;
+        __builtin_amdgcn_wave_barrier();
+        const float g = lane < NH ? E[lane + 1] - mnj : 0.f;
+        r = uf(wave_max(fabsf(g)));
+        if (!isfinite(s00) || !(s00 > 0.f)) r = NAN;
+        float* Lm = E + 36;
+        float a[NH], dinv = 1.f, dmin = 0.f, dmax = 0.f;
+        bool ok = false, to64 = false;
+        float lam = 0.f;
+        for (int tries = 0;; ++tries) {
+          int ln = lane;
+          asm volatile("" : "+v"(ln));
+          load_hcol(Sr, inv0, E, ln, lam, a);
+          ok = wave_chol_u(a, dinv, ln, dmin, dmax, Lm);
+          if (tries == 0) cnd = ok ? dmax / dmin : __builtin_inff();
+          if (tries == 0 && p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
+            to64 = isfinite(r);
+            break;
+          }
+          if (ok || !isfinite(r) || tries >= 40) break;
+          lam = tries == 0 ? p.lambda0 : lam * p.lambda_mul;
+          extra |= MEM_ST_SHIFTED;
+        }
+        if (!to64) {
+          float w = 0.f, d = 0.f;
+          if (ok) wave_solve(a, Lm, dinv, lane, -g, w, d);
+          res = ok ? uf(0.5f * wave_sum(lane < NH ? w * w : 0.f)) : 0.f;
+          dfin = ok && __all(lane >= NH || isfinite(d));
+          dk = __shfl(d, (lane + 63) & 63);
+        } else {
+          // FP64 direction: the S row moves to the line search's sVd area
+          // (rebuilt before its next use), its own space takes E and the factor
+          // in double.  Lanes exchange it through LDS only: global memory
+          // written by one lane and read by another in the same wave is not
+          // ordered without a fence.
+          float* Sg = L.sVd;
+          for (int col = lane; col < NCOL; col += 64) Sg[col] = Sr[col];
+          __builtin_amdgcn_wave_barrier();
+          double* Ed = reinterpret_cast<double*>(L.W);
+          double* Lmd = Ed + 36;
+          const double inv0d = 1.0 / (double)s00;
+          if (lane < K3) Ed[lane] = lane == 0 ? 1.0 : (double)Sr[lane] * inv0d;
+          __builtin_amdgcn_wave_barrier();
+          const double gd = lane < NH ? Ed[lane + 1] - (double)mrj / (double)nn : 0.0;
+          r = uf(wave_max((float)fabs(gd)));
+          double ad[NH], dinvd = 1.0, dmind = 0.0, dmaxd = 0.0;
+          double lamd = 0.0;
+          bool okd = false;
+          extra = MEM_ST_FP64;
+          for (int tries = 0; tries < 41 && !okd; ++tries) {
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            load_hcol(Sg, inv0d, Ed, ln, lamd, ad);
+            okd = wave_chol_u(ad, dinvd, ln, dmind, dmaxd, Lmd);
+            if (!okd) {
+              lamd = tries == 0 ? (double)p.lambda0 : lamd * (double)p.lambda_mul;
+              extra |= MEM_ST_SHIFTED;
+            }
+          }
+          double w = 0.0, d = 0.0;
+          if (okd) wave_solve(ad, Lmd, dinvd, lane, -gd, w, d);
+          res = uf((float)(0.5 * wave_sum(lane < NH ? w * w : 0.0)));
+          dfin = okd && __all(lane >= NH || isfinite(d));
+          dk = (float)__shfl(d, (lane + 63) & 63);
+          __builtin_amdgcn_wave_barrier();
+          // restore the S row in LDS (a refinement candidate writes it back)
+          for (int col = lane; col < NCOL; col += 64) Sr[col] = Sg[col];
+          __builtin_amdgcn_wave_barrier();
+        }
+        dk = kin ? dk : 0.f;
+      }
+      if (o.cond && lane == 0 && isfinite(r)) o.cond[cell] = fmaxf(o.cond[cell], cnd);
+      code = wave_finish(r, res, dfin, extra, p, cs);
+      if (code != 1) break;
+      // backtracking line search (k_lse3 with the Armijo test of Alg. 1)
+      if (lane < 36) L.sB[36 + lane] = lane < K3 ? dk : 0.f;
+      __builtin_amdgcn_wave_barrier();
+      build_v<NT>(L.sB + 36, L.sH, L.sVd, lane);
+      __builtin_amdgcn_wave_barrier();
+      const float L0 = cs.L, gdt = -2.f * res;
+      float alpha = 1.f;
+      for (int s = 0;; ++s) {
+        const float lzt = uf(wave_lse<true, NT>(lane, alpha, L.sH, L.sVb, L.sVd));
+        const float bt = fmaf(alpha, dk, bk);
+        const float Lt = uf(lzt - wave_sum(bt * mn));
+        const float LD = L0 - Lt;
+        const float gradD = -p.c * alpha * gdt;
+        const bool sat = (LD - gradD) >= -(p.atol + p.rtol * fabsf(LD));
+        const bool last = sat || s >= p.max_ls;
+        bk = (last && kin) ? bt : bk;
+        if (last) {
+          lz = lzt;
+          cs.L = Lt;
+          cs.alpha = alpha;
+          break;
+        }
+        alpha *= 0.5f;
+      }
+    }
+    // results of the cell
+    if (kin) bc[lane] = bk;
+    if (code == 2) {
+      float* Sg = S_w + cell * NCOL;
+      if (ident_S) {
+        // E[phi_i phi_j] = delta_ij: every column written once, by one lane
+        for (int col = lane; col < NCOL; col += 64) {
+          bool diag = false;
+          for (int k = 0; k < K3; ++k) diag = diag || (col == pair_col(k, k));
+          Sg[col] = diag ? 1.f : 0.f;
+        }
+      } else {
+        for (int col = lane; col < NCOL; col += 64) Sg[col] = L.W[col];
+      }
+    }
+    if (lane == 0) {
+      iters_w[cell] = cs.it;
+      status_w[cell] = cs.st;
+      resid_w[cell] = r;
+      logZ_w[cell] = lz;
+      if (o.iters_out) o.iters_out[cell] = cs.it;
+      if (o.resid_out) o.resid_out[cell] = r;
+      if (o.status_out) o.status_out[cell] = cs.st;
+      if (code == 2 && o.done_list) o.done_list[atomicAdd(o.done_ctr, 1)] = (int)cell;
+    }
+    }  // st0 == 0
+    if (st0 != 0u && lane == 0) {
+      iters_w[cell] = 0; status_w[cell] = st0; resid_w[cell] = INFINITY;
+      if (o.iters_out) o.iters_out[cell] = 0;
+      if (o.resid_out) o.resid_out[cell] = INFINITY;
+      if (o.status_out) o.status_out[cell] = st0;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
@@ -1513,6 +2037,22 @@ hipError_t launch_refine_final(mem_ctx_t c, int64_t grid_cells, const int32_t* l
   if (grid_cells <= 0) return hipSuccess;
   k_refine_final<<<nblocks(grid_cells, 256), 256, 0, s>>>(list, ctr, c->w_racc, tol_loose,
                                                           c->w_status, resid, status);
+  return hipGetLastError();
+}
+
+// Persistent Newton solve of cells 0..n-1 (one wave per live cell); ctr[7] is
+// the work queue (zeroed by the caller).
+hipError_t launch_newton_wave(mem_ctx_t c, int64_t n, const float* M, float* beta,
+                              const SolveParams& p, bool closed_start, int32_t* queue,
+                              int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
+                              int32_t* done_ctr, float* cond, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (c->n1d != 12) return hipErrorNotSupported;
+  DirOut o{nullptr, nullptr, iters, resid, status, done_list, done_ctr, cond};
+  const int64_t waves = std::min<int64_t>(n, (int64_t)c->n_cu * WAVE_SOLVE_PER_CU);
+  k_newton_wave<12><<<(unsigned)waves, 64, 0, s>>>(c->d_t1, queue, n, M, beta, p,
+                                                   closed_start ? 1 : 0, c->w_S, c->w_logZ,
+                                                   c->w_iters, c->w_status, c->w_resid, o);
   return hipGetLastError();
 }
 

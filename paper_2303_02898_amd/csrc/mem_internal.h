@@ -65,8 +65,9 @@ struct StepKey {
 
 struct mem_ctx_s {
   int dim = 3, n1d = 12, K = 35, Q = 0, Qpad = 0, ngroups = 0, prec = 0;
-  mem_tuning_t tune{4, 512, 0.0};  // launch parameters (mem_autotune / mem_set_tuning)
+  mem_tuning_t tune{4, 512, 0.0, 1, 0};  // launch parameters (mem_autotune / mem_set_tuning)
   int device = 0;
+  int n_cu = 256;  // compute units of the device (grid of the persistent solve)
   // host FP64 tables (checked against the oracle by the tests)
   std::vector<double> h_nodes, h_w, h_phi, h_logw;
   // device tables, 3D
@@ -240,6 +241,14 @@ hipError_t launch_refine_final(mem_ctx_t c, int64_t grid_cells, const int32_t* l
                                const int32_t* ctr, float tol_loose, float* resid,
                                uint32_t* status, hipStream_t s);
 hipError_t launch_set_ctr(int32_t* ctr, int n, hipStream_t s);
+// Persistent Newton solve of cells 0..n-1: one wavefront per live cell from
+// the work queue `queue` (zeroed by the caller); converged cells are appended
+// to done_list for the refinement kernels.
+constexpr int WAVE_SOLVE_PER_CU = 8;
+hipError_t launch_newton_wave(mem_ctx_t c, int64_t n, const float* M, float* beta,
+                              const SolveParams& p, bool closed_start, int32_t* queue,
+                              int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
+                              int32_t* done_ctr, float* cond, hipStream_t s);
 hipError_t launch_unpack3(mem_ctx_t c, int64_t n, float* E, float* H, hipStream_t s);
 hipError_t launch_flux3(mem_ctx_t c, int64_t n, const float* beta, const float* g,
                         float* F, float* rho_or_lam, bool want_lam, bool radius_only,
