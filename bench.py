@@ -31,6 +31,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "35-moment MaxEnt solves/s at rel. residual ≤1e-5, FP32 vs mixed; cell-steps/s"
 MFMA_PEAK = {"fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}
+# FP32 vector peak (MI355X published, 256 CUs at 2.4 GHz); the kernels are built
+# without packed FP32 instructions, whose unpacked rate is half of it
+FP32_VECTOR_PEAK = 157.3
+FP32_VECTOR_UNPACKED = 78.6
+# k_newton_wave, algorithmic flops per assembled cell-iteration at 12^3 nodes
+# (lower bound): the sum-factorised Hessian assembly (46,848 FMA: 25,920 +
+# 15,120 + 5,808 over the three axes), the exponent of sigma (5 FMA per node)
+# and one line-search trial (5 FMA per node); exp, the coefficient builds, the
+# Cholesky and further trials are not counted
+WAVE_FLOP_ITER = 2.0 * (25920 + 15120 + 5808 + 5 * 1728 + 5 * 1728)
 
 # HBM bytes per k_assemble3 launch on this bench's timed solve (65536 cells,
 # launch parameters 2,2048): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per
@@ -87,6 +97,11 @@ def cpu_baseline(M, b0, n_sample):
                        if d.get("user_api") == "blas"] or [1])
     except Exception:
         threads = os.cpu_count() or 1
+    try:
+        import torch   # the oracle's dense sums run on torch's CPU threads
+        threads = max(threads, torch.get_num_threads())
+    except Exception:
+        pass
     nodes, w = quadrature.tensor_rule(12, 3)
     Phi, logw = basis.evaluate(nodes, 3), quadrature.lebesgue_log_weights(nodes, w)
     Ms = M[:n_sample].astype(np.float64)
@@ -98,6 +113,22 @@ def cpu_baseline(M, b0, n_sample):
     res = {"value": ok / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
            "sample": f"first {n_sample} cells of the same 65,536-cell batch, FP64 NumPy "
                      f"Alg. 1 to max|G| <= 1e-10, {el:.1f} s wall"}
+    # the same oracle on one thread (BLAS and torch), a smaller sample
+    try:
+        import torch
+        from threadpoolctl import threadpool_limits
+        n1 = max(1, n_sample // 8)
+        tt = torch.get_num_threads()
+        torch.set_num_threads(1)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            o1 = maxent.newton_solve(Ms[:n1], bs[:n1], Phi, logw, tol_grad=1e-10)
+            el1 = time.perf_counter() - t0
+        torch.set_num_threads(tt)
+        res["single_thread"] = {"value": int(np.sum(o1["converged"])) / el1, "unit": "solves/s",
+                                "cores": 1, "sample": f"first {n1} cells, {el1:.1f} s wall"}
+    except Exception as exc:   # threadpoolctl missing: leave it out
+        res["single_thread"] = {"error": str(exc)}
     # the oracle's time step beside the shock workloads: Mach-3 shock, 240 cells,
     # 4 LLF steps after the set-up (cell-steps/s, warm solves)
     from oracle import kinetics
@@ -273,9 +304,10 @@ def run_solves(mem, ctx, Md, b0d, steps, warmup, tune=True):
     rs = resid.cpu().numpy()
     it = iters.cpu().numpy()
     ok = ((st & mem.ST_CONVERGED) != 0) & (rs <= 1e-5)
-    prof = {k: ctx.profile_read(k) for k in ("assemble", "direction", "lse")}
+    prof = {k: ctx.profile_read(k) for k in ("assemble", "direction", "lse", "wave")}
     ctx.profile(False)
     asm_ms, asm_n = prof["assemble"]
+    wave_ms, wave_n = prof["wave"]
     # assembled cell-iterations: a cell that starts exactly at the Maxwellian of
     # its gauge takes its first direction in closed form (no assembly)
     b0 = b0d.cpu().numpy()
@@ -284,11 +316,14 @@ def run_solves(mem, ctx, Md, b0d, steps, warmup, tune=True):
     closed = np.all(b0[:, 1:] == maxw[:, 1:], axis=1) & (it >= 1)
     assembled = float(np.sum(it - closed.astype(it.dtype)))
     total_flop = 2.0 * 1728 * 630 * assembled * steps
+    wave_flop = WAVE_FLOP_ITER * assembled * steps
     return dict(
         value=int(ok.sum()) * steps / elapsed, ms=1e3 * elapsed / steps, ok=ok, it=it, st=st,
         assembled_cell_iterations=assembled,
         asm_tflops=total_flop / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0, tuning=tuning,
         asm_launches=asm_n, asm_avg_ms=asm_ms / max(asm_n, 1),
+        wave_tflops=wave_flop / (wave_ms * 1e-3) / 1e12 if wave_ms > 0 else 0.0,
+        wave_launches=wave_n, wave_avg_ms=wave_ms / max(wave_n, 1),
         kernel_ms={k: v[0] / steps for k, v in prof.items()}, beta=bg)
 
 
@@ -314,11 +349,14 @@ def passes(mem, torch, ctx, Md, gd, r, reps=20):
     # beta, log Z, L, alpha out (the 1D node tables stay in LDS / L2)
     lse_bytes = 4 * float(r["it"].sum()) * (35 + 36 + 35 + 3 + 35 + 3)
     lse_ms = r["kernel_ms"]["lse"]
+    exp_lse = ({"kernels": "k_lse3 (log-sum-exp pass and Armijo trials)",
+                "ms_per_solve": lse_ms, "bytes_per_cell_iteration": 4 * 147,
+                "achieved_GBps": lse_bytes / (lse_ms * 1e-3) / 1e9, "peak_GBps": 8000.0,
+                "bound": "valu (sum-factorised exponent)"} if lse_ms > 0 else
+               {"kernels": "inside k_newton_wave (the persistent Newton loop): no separate "
+                           "exponent pass"})
     return {
-        "exp_lse": {"kernels": "k_lse3 (log-sum-exp pass and Armijo trials)",
-                    "ms_per_solve": lse_ms, "bytes_per_cell_iteration": 4 * 147,
-                    "achieved_GBps": lse_bytes / (lse_ms * 1e-3) / 1e9, "peak_GBps": 8000.0,
-                    "bound": "valu (sum-factorised exponent)"},
+        "exp_lse": exp_lse,
         "flux": {"kernels": "k_flux3 + k_eig3 (moment fluxes and extreme speeds)",
                  "cells": n, "ms": flux_ms, "bytes_per_cell": 4 * 75,
                  "achieved_GBps": flux_bytes / (flux_ms * 1e-3) / 1e9, "peak_GBps": 8000.0,
@@ -339,10 +377,13 @@ def mixed_comparison(mem, torch, dev, cells, steps, warmup):
            "cells": cells}
     base = None
     beta32 = None
-    for prec in ("fp32", "bf16x3", "fp16x3"):
-        ctx = mem.Context(3, 12, prec)
+    for prec in ("fp32", "fp32_list", "bf16x3", "fp16x3"):
+        ctx = mem.Context(3, 12, "fp32" if prec == "fp32_list" else prec)
         ctx.reserve(cells)
-        r = run_solves(mem, ctx, Md, b0d, steps, warmup)
+        if prec == "fp32_list":
+            # the same FP32 solve on the list-compacted loop with the MFMA assembly
+            ctx.set_tuning(dir_waves=2, split_want=512, solver=0)
+        r = run_solves(mem, ctx, Md, b0d, steps, warmup, tune=prec != "fp32_list")
         # per-moment residual G_k = E[phi_k]/E[phi_0] - M_k/n of the converged cells,
         # evaluated in compensated arithmetic (agrees with FP64 to a few 1e-8)
         G = ctx.moment_residual(Md, r["beta"]).abs().cpu().numpy()
@@ -355,7 +396,10 @@ def mixed_comparison(mem, torch, dev, cells, steps, warmup):
         both = ok & ok32
         scale = np.maximum(1.0, np.abs(beta32[both]).max(axis=1))
         out[prec] = {"solves_per_s": r["value"], "ms_per_solve": r["ms"],
+                     "newton_loop": "persistent" if r["tuning"].get("solver") == 1 else "list/MFMA",
                      "speedup_vs_fp32": r["value"] / base if base else None,
+                     "speedup_vs_fp32_list": (r["value"] / out["fp32_list"]["solves_per_s"]
+                                              if "fp32_list" in out else None),
                      "converged_fraction": float(ok.mean()),
                      "iterations_mean": float(r["it"].mean()), "iterations_max": int(r["it"].max()),
                      "assemble_ms_per_solve": r["kernel_ms"]["assemble"],
@@ -370,7 +414,7 @@ def mixed_comparison(mem, torch, dev, cells, steps, warmup):
 
 
 def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph, iter_hist=None, flux_scheme="llf",
-                cond_max=None):
+                cond_max=None, status_counts=None, budget=8):
     """Device state and batch for a list of shock problems (gauge applied)."""
     import mem_inputs
     M = np.concatenate([p["M"] for p in probs]).astype(np.float32)
@@ -386,7 +430,8 @@ def shock_setup(mem, torch, dev, ctx, probs, dx, use_graph, iter_hist=None, flux
                            np.stack([p["g_left"] for p in probs]),
                            np.stack([p["g_right"] for p in probs]), device=dev,
                            use_graph=use_graph, iter_hist=iter_hist, flux_scheme=flux_scheme,
-                           cond_max=cond_max)
+                           cond_max=cond_max, status_counts=status_counts,
+                           newton_per_step=budget)
     P = len(probs)
     return batch, Md, bd, gd, torch.zeros(P, device=dev), torch.zeros(P, device=dev)
 
@@ -507,19 +552,23 @@ def ragged_rate(mem, torch, dev, steps):
     import mem_inputs
     rb = mem_inputs.ragged_batch(2048)
     ctx = mem.Context(3, 12)
-    budget = 8
+    # the Newton budget per step of the oracle parity test of this workload
+    budget = 40
     hist = torch.zeros(budget + 1, dtype=torch.int64, device=dev)
+    counts = torch.zeros(9, dtype=torch.int64, device=dev)
     b, M, be, g, t, dt = shock_setup(mem, torch, dev, ctx, rb["problems"], [rb["dx"]] * 2048, True,
-                                     iter_hist=hist)
+                                     iter_hist=hist, status_counts=counts, budget=budget)
     status = torch.zeros(b.n_cells, dtype=torch.int32, device=dev)
     ctx.step(b, M, be, g, t, dt, 1, status=status)
     torch.cuda.synchronize()
     hist.zero_()
+    counts.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.step(b, M, be, g, t, dt, steps, status=status)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    ctx_loop = "persistent" if ctx.tuning().get("solver") == 1 else "list/MFMA"
     ctx.close()
     st = status.cpu().numpy()
     off = b.offsets.cpu().numpy()
@@ -528,13 +577,26 @@ def ragged_rate(mem, torch, dev, steps):
     prob_mx = np.array([mx[off[p]:off[p + 1]].any() for p in range(2048)])
     prob_fin = np.array([fin[off[p]:off[p + 1]].all() for p in range(2048)])
     h = hist.cpu().numpy().astype(np.int64)
+    cnt = counts.cpu().numpy().astype(np.int64)
+    cell_steps = b.n_cells * steps
+    # cell-steps that ended MAXITER (an unconverged beta) or stepped with the
+    # Maxwellian of their gauge are reported apart and not counted as solved
+    apart = int(cnt[1]) + int(cnt[8])
     cdf = np.cumsum(h) / max(int(h.sum()), 1)
     pct = {f"p{q}": int(np.searchsorted(cdf, q / 100.0)) for q in (50, 90, 99)}
     return {"workload": f"2048 normal shocks (Mach U(1.2,10), tanh initial profiles), cell counts "
                         f"log-uniform in [64, 4096] ({b.n_cells} cells), dx = 1, {steps} steps, "
-                        "hipGraph replay",
+                        f"Newton budget {budget} per step, hipGraph replay",
+            "newton_loop": ctx_loop,
             "cells": b.n_cells, "steps": steps, "ms_per_step": 1e3 * el / steps,
-            "cell_steps_per_s": b.n_cells * steps / el,
+            "cell_steps_per_s": (cell_steps - apart) / el,
+            "cell_steps_per_s_all": cell_steps / el,
+            "cell_steps_by_status": {
+                "total": cell_steps, "converged": int(cnt[0]), "maxiter": int(cnt[1]),
+                "stagnated": int(cnt[2]), "fp64_direction": int(cnt[4]),
+                "nonfinite": int(cnt[5]), "nonrealizable": int(cnt[6]),
+                "maxwell_flux": int(cnt[8]),
+                "note": "cell_steps_per_s leaves out the maxiter and maxwell_flux cell-steps"},
             "newton_iterations": {
                 "per_cell_step_histogram": h.tolist(),
                 "budget": budget,
@@ -637,8 +699,54 @@ def main():
     r = run_solves(mem, ctx, Md, b0d, args.steps, args.warmup, tune=not args.tuning)
     pass_rates = passes(mem, torch, ctx, Md, torch.tensor(cells["g"].astype(np.float32),
                                                            device=dev), r)
+    wave = r["tuning"].get("solver") == 1 and args.prec == "fp32"
+    # the same workload on the list-compacted Newton loop with the MFMA assembly
+    rl = None
+    if wave:
+        ctx.set_tuning(dir_waves=2, split_want=512, solver=0)
+        rl = run_solves(mem, ctx, Md, b0d, args.steps, args.warmup, tune=False)
     ctx.close()
     peak = MFMA_PEAK[args.prec]
+
+    def mfma_roofline(rr):
+        return {
+            "bound": "mfma",
+            "kernel": "k_assemble3 (sigma . Psi, 630 pair columns)" if args.prec == "fp32"
+                      else "k_assemble3m (sigma . Psi, hi+lo 16-bit products)",
+            "achieved": rr["asm_tflops"],
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": rr["asm_tflops"] / peak,
+            "traffic": assembly_traffic(args.prec, C),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_tuning": ASM_TRAFFIC["tuning"],
+            "flop_per_cell_iteration": 2.0 * 1728 * 630,
+            "assembled_cell_iterations_per_step": rr["assembled_cell_iterations"],
+            "launches": rr["asm_launches"],
+            "avg_launch_ms": rr["asm_avg_ms"],
+        }
+
+    if wave:
+        roof = {
+            "bound": "alu",
+            "kernel": "k_newton_wave (persistent Newton loop, one wavefront per cell, "
+                      "sum-factorised assembly)",
+            "achieved": r["wave_tflops"],
+            "peak": FP32_VECTOR_PEAK,
+            "unit": "TFLOP/s",
+            "frac": r["wave_tflops"] / FP32_VECTOR_PEAK,
+            "frac_of_unpacked_fp32": r["wave_tflops"] / FP32_VECTOR_UNPACKED,
+            "traffic": None,
+            "flop_per_cell_iteration": WAVE_FLOP_ITER,
+            "flop_note": "lower bound: sum-factorised assembly, the exponent of sigma and one "
+                         "line-search trial per assembled cell-iteration; exp, coefficient "
+                         "builds, Cholesky and further trials not counted",
+            "assembled_cell_iterations_per_step": r["assembled_cell_iterations"],
+            "launches": r["wave_launches"],
+            "avg_launch_ms": r["wave_avg_ms"],
+        }
+    else:
+        roof = mfma_roofline(r)
 
     line = {
         "metric": METRIC,
@@ -659,33 +767,28 @@ def main():
                         "cold start from the Maxwellian, Alg. 1 to max|G|<=2e-6",
             "cells": C, "nodes": 1728, "basis": 35, "prec": args.prec,
         },
-        "roofline": {
-            "bound": "mfma",
-            "kernel": "k_assemble3 (sigma . Psi, 630 pair columns)" if args.prec == "fp32"
-                      else "k_assemble3m (sigma . Psi, hi+lo 16-bit products)",
-            "achieved": r["asm_tflops"],
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": r["asm_tflops"] / peak,
-            "traffic": assembly_traffic(args.prec, C),
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "traffic_tuning": ASM_TRAFFIC["tuning"],
-            "flop_per_cell_iteration": 2.0 * 1728 * 630,
-            "assembled_cell_iterations_per_step": r["assembled_cell_iterations"],
-            "launches": r["asm_launches"],
-            "avg_launch_ms": r["asm_avg_ms"],
-        },
+        "roofline": roof,
         "solver": {
             "converged_fraction": float(r["ok"].mean()),
             "iterations_mean": float(r["it"].mean()),
             "iterations_max": int(r["it"].max()),
             "fp64_direction_fraction": float(np.mean((r["st"] & mem.ST_FP64) != 0)),
             "tuning": r["tuning"],
+            "newton_loop": "persistent (k_newton_wave)" if wave else "list/MFMA",
             "kernel_ms_per_step": {"assemble": r["kernel_ms"]["assemble"],
                                    "direction": r["kernel_ms"]["direction"],
-                                   "lse_linesearch": r["kernel_ms"]["lse"]},
+                                   "lse_linesearch": r["kernel_ms"]["lse"],
+                                   "newton_wave": r["kernel_ms"]["wave"]},
         },
     }
+    if rl is not None:
+        line["mfma_path"] = {
+            "workload": "the same solve on the list-compacted Newton loop (launches per pass, "
+                        "MFMA assembly), launch parameters 2,512",
+            "solves_per_s": rl["value"], "ms_per_step": rl["ms"],
+            "converged_fraction": float(rl["ok"].mean()),
+            "iterations_mean": float(rl["it"].mean()),
+            "roofline": mfma_roofline(rl)}
     line["passes"] = pass_rates
     if args.mixed_cells > 0:
         line["mixed"] = mixed_comparison(mem, torch, dev, args.mixed_cells, 3, 1)

@@ -168,6 +168,11 @@ typedef struct {
                                     positive.  The conditioning monitor of the paper's
                                     cell-count study (Sec. 3.5, Sec. 4.6).  Accumulates over
                                     calls; never cleared.                                   */
+  int64_t*       status_counts;  /* device [9] or NULL: after each step's MaxEnt solve of the
+                                    cells (and the Maxwellian substitution), entry k is
+                                    incremented by the number of cells whose status has bit
+                                    1 << k (MEM_ST_*; 8 = MEM_ST_MAXWELL_FLUX): cell-steps by
+                                    outcome.  Accumulates over calls; never cleared.        */
 } mem_batch_t;
 
 /* ---- context -------------------------------------------------------------- */

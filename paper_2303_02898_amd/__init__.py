@@ -50,7 +50,8 @@ class Batch(ctypes.Structure):
                 ("cell_offsets", _vp), ("dx", _vp), ("M_left", _vp), ("M_right", _vp),
                 ("g_left", _vp), ("g_right", _vp), ("cfl", _c_f32), ("prandtl", _c_f32),
                 ("mu_ref", _c_f32), ("newton_per_step", _c_i32), ("use_graph", _c_i32),
-                ("iter_hist", _vp), ("flux_scheme", _c_i32), ("cond_max", _vp)]
+                ("iter_hist", _vp), ("flux_scheme", _c_i32), ("cond_max", _vp),
+                ("status_counts", _vp)]
 
 
 _lib = None
@@ -508,7 +509,7 @@ class ShockBatch:
     def __init__(self, offsets, dx, M_left, M_right, g_left, g_right, device="cuda",
                  cfl=0.5, prandtl=2.0 / 3.0, mu_ref=0.7978845608028654, collision=1,
                  newton_per_step=8, use_graph=False, iter_hist=None, flux_scheme="llf",
-                 cond_max=None):
+                 cond_max=None, status_counts=None):
         import torch
         if flux_scheme not in FLUX_SCHEMES:
             raise ValueError(f"flux_scheme must be one of {sorted(FLUX_SCHEMES)}")
@@ -544,3 +545,12 @@ class ShockBatch:
                                  "n_problems entries")
             self.cond_max = cond_max
             self.struct.cond_max = cond_max.data_ptr()
+        # cell-steps by status bit (device int64 [9]), accumulated by mem_step
+        self.status_counts = None
+        if status_counts is not None:
+            if (status_counts.dtype != torch.int64 or not status_counts.is_contiguous()
+                    or status_counts.numel() != 9 or not status_counts.is_cuda):
+                raise ValueError("status_counts must be a contiguous device int64 tensor of 9 "
+                                 "entries")
+            self.status_counts = status_counts
+            self.struct.status_counts = status_counts.data_ptr()

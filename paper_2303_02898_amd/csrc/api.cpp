@@ -690,6 +690,7 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
     MEM_HIP(c, launch_maxwell_fallback(c, n, M, beta, st));
     if (status) MEM_HIP(c, launch_status_or(n, c->w_status, status, st));
     if (b->iter_hist) MEM_HIP(c, launch_iter_hist(n, c->w_iters, budget + 1, b->iter_hist, st));
+    if (b->status_counts) MEM_HIP(c, launch_status_count(n, c->w_status, b->status_counts, st));
     MEM_HIP(c, launch_flux3(c, n, beta, g, c->w_F, c->w_rho, true, true, status, st));
     MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, st));
     // the transport step never exceeds the CFL limit of its own speeds

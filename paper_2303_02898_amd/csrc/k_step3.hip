@@ -837,6 +837,22 @@ __global__ void k_maxwell_fallback(int64_t n, const float* __restrict__ M, float
   status_w[c] = st | MEM_ST_MAXWELL_FLUX;
 }
 
+// Cell-steps by outcome: counts[k] += number of cells with status bit 1 << k
+// (k < 9), an LDS count per workgroup added to the device array at the end.
+__global__ __launch_bounds__(256) void k_status_count(int64_t n, const uint32_t* __restrict__ st,
+                                                      unsigned long long* counts) {
+  __shared__ unsigned int sh[9];
+  if (threadIdx.x < 9) sh[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
+    const uint32_t v = st[c];
+    for (int k = 0; k < 9; ++k)
+      if (v & (1u << k)) atomicAdd(&sh[k], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 9 && sh[threadIdx.x]) atomicAdd(&counts[threadIdx.x], (unsigned long long)sh[threadIdx.x]);
+}
+
 // Distribution of per-cell Newton iterations of one step's solve: an LDS
 // histogram per workgroup, added to the device histogram at the end.
 __global__ __launch_bounds__(256) void k_iter_hist(int64_t n, const int32_t* __restrict__ iters,
@@ -1036,6 +1052,13 @@ hipError_t launch_maxwell_fallback(mem_ctx_t c, int64_t n, const float* M, float
                                    hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_maxwell_fallback<<<nb(n, 256), 256, 0, s>>>(n, M, beta, c->w_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_count(int64_t n, const uint32_t* st, int64_t* counts, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>(nb(n, 256), 1024);
+  k_status_count<<<grid, 256, 0, s>>>(n, st, reinterpret_cast<unsigned long long*>(counts));
   return hipGetLastError();
 }
 

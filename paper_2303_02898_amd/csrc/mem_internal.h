@@ -286,6 +286,7 @@ hipError_t launch_maxwell_fallback(mem_ctx_t c, int64_t n, const float* M, float
                                    hipStream_t s);
 hipError_t launch_iter_hist(int64_t n, const int32_t* iters, int nbins, int64_t* hist,
                             hipStream_t s);
+hipError_t launch_status_count(int64_t n, const uint32_t* st, int64_t* counts, hipStream_t s);
 hipError_t launch_rmax_init(mem_ctx_t c, int P, hipStream_t s);
 hipError_t launch_copy(int64_t n, const float* src, float* dst, hipStream_t s);
 hipError_t launch_conserved(mem_ctx_t c, const mem_batch_t* b, const float* M,

@@ -16,6 +16,13 @@ when, over the last 100 steps, both
 * the centred profiles of n, T and q_x (normalised as in the test, sampled on
   the offsets of the output grid) moved by at most ``--tol-centred``.
 
+The centred change decays slowly (a few per cent per 100 steps near t = 13)
+while the start-up transient is carried out through the downstream boundary,
+so the centred tolerance is 1e-4: a tenth of the bar the profiles are held to.
+The GPU test steps its own solver the same number of steps and compares at
+that time, so the golden need not be fully stationary for the comparison to be
+exact up to precision.
+
 The shock centre is where n = (n- + n+)/2, by linear interpolation between
 cell centres.
 
@@ -69,8 +76,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--checkpoint", default=None)
     ap.add_argument("--tol-raw", type=float, default=2e-5)
-    ap.add_argument("--tol-centred", type=float, default=1e-6)
-    ap.add_argument("--max-steps", type=int, default=60000)
+    ap.add_argument("--tol-centred", type=float, default=1e-4)
+    ap.add_argument("--max-steps", type=int, default=24000)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "shock_mach3_steady.json"))
     args = ap.parse_args()

@@ -132,6 +132,45 @@ def test_mixed_solve_matches_oracle(ctxm, rule3, config, mach):
     assert np.all(dr <= 2e-7 + 0.01 * r)
 
 
+def test_mixed_full_size_sampled(ctxm, rule3):
+    """The full mixed-precision workload (262,144 Mott-Smith cells, Mach 5-10,
+    12^3 nodes) in one solve: its own compensated residual on every cell, and
+    48 sampled cells against the FP64 oracle at the same bars as the FP32 path."""
+    C = 262144
+    cells = mem_inputs.mott_smith_cells(C, 5.0, 10.0, config=4, replica=0)
+    M = f32(cells["M"])
+    b0 = f32(mem_inputs.maxwellian_beta(C, 35, M[:, 0]))
+    print(f"\n[{ctxm.prec_name} full] {C} cells", flush=True)
+    beta, it, res, st = _solve(ctxm, M, b0)
+    conv = (st & mem.ST_CONVERGED) != 0
+    nonreal = (st & mem.ST_NONREALIZABLE) != 0
+    print(f"[{ctxm.prec_name} full] converged {conv.mean():.5f}, certified non-realizable "
+          f"{nonreal.mean():.5f}, fp64 direction {np.mean((st & mem.ST_FP64) != 0):.4f}, "
+          f"iterations mean {it.mean():.2f} max {it.max()}", flush=True)
+    assert np.all(res[conv] <= 1e-5)
+    assert np.mean(conv | nonreal) >= 0.99
+    rng = np.random.default_rng(48)
+    idx = np.sort(rng.choice(C, 48, replace=False))
+    ref = maxent.newton_solve(M[idx], b0[idx], rule3["Phi"], rule3["logw"])
+    good, bad = ref["converged"], ref["nonrealizable"]
+    assert np.all(good | bad)
+    assert not np.any(conv[idx][bad])
+    sel = good & conv[idx]
+    assert sel.sum() >= 0.95 * good.sum()
+    Ms, bs, rs = M[idx][sel], beta[idx][sel], ref["beta"][sel]
+    r = maxent.moment_residual(bs, Ms, rule3["Phi"], rule3["logw"])
+    floor = maxent.moment_residual(f32(rs), Ms, rule3["Phi"], rule3["logw"])
+    bar = np.maximum(1e-5, 2.0 * floor)
+    scale = np.maximum(1.0, np.max(np.abs(rs), axis=1))
+    berr = np.max(np.abs(bs - rs), axis=1) / scale
+    print(f"[{ctxm.prec_name} full] sample: {sel.sum()} of {good.sum()} realizable converged; "
+          f"r max {r.max():.2e}; beta err max {berr.max():.2e}", flush=True)
+    assert np.all(r <= bar)
+    assert berr.max() <= 1e-4
+    dr = np.abs(res[idx][sel] - r)
+    assert np.all(dr <= 2e-7 + 0.01 * r)
+
+
 def test_mixed_precision_steps_match_oracle(ctxm):
     """mem_step on a mixed-precision context: the cells' Newton Hessians come from
     the hi+lo 16-bit assembly, gradients, fluxes and speeds stay FP32.  Mach-3

@@ -193,16 +193,25 @@ def test_ragged_batch_runs_and_matches_single(ctx3, scheme):
     ctx3.gauge(Md, None, gd)
     bd = dev(f32(mem_inputs.maxwellian_beta(M.shape[0], 35, Md[:, 0].cpu().numpy())))
     hist = torch.zeros(9, dtype=torch.int64, device=DEV)
+    sc = torch.zeros(9, dtype=torch.int64, device=DEV)
     cm = torch.zeros(3, device=DEV)
     batch = mem.ShockBatch(off, [p["dx"] for p in probs], np.stack([p["M_left"] for p in probs]),
                            np.stack([p["M_right"] for p in probs]),
                            np.stack([p["g_left"] for p in probs]),
                            np.stack([p["g_right"] for p in probs]), device=DEV, iter_hist=hist,
-                           flux_scheme=scheme, cond_max=cm)
+                           flux_scheme=scheme, cond_max=cm, status_counts=sc)
     t = torch.zeros(3, device=DEV)
     dt = torch.zeros(3, device=DEV)
-    ctx3.step(batch, Md, bd, gd, t, dt, 5)
+    status = torch.zeros(M.shape[0], dtype=torch.int32, device=DEV)
+    ctx3.step(batch, Md, bd, gd, t, dt, 4)
+    assert sc[0].item() > 0
+    sc.zero_()
+    ctx3.step(batch, Md, bd, gd, t, dt, 1, status=status)
     torch.cuda.synchronize()
+    # the per-step status counts are the population counts of the status bits
+    st = status.cpu().numpy()
+    want = [int(np.count_nonzero(st & (1 << k))) for k in range(9)]
+    assert sc.cpu().tolist() == want, (sc.cpu().tolist(), want)
     # every cell is counted once per step, in a bin within the iteration budget
     h = hist.cpu().numpy()
     assert h.sum() == 5 * M.shape[0], h
@@ -215,7 +224,9 @@ def test_ragged_batch_runs_and_matches_single(ctx3, scheme):
         b1 = mem.ShockBatch([0, counts[k]], [p["dx"]], p["M_left"][None], p["M_right"][None],
                             p["g_left"][None], p["g_right"][None], device=DEV,
                             flux_scheme=scheme, cond_max=c1)
-        ctx3.step(b1, M1, b1d, g1, t1, dt1, 5)
+        # the same calls as the batch: every call starts by re-solving its state
+        ctx3.step(b1, M1, b1d, g1, t1, dt1, 4)
+        ctx3.step(b1, M1, b1d, g1, t1, dt1, 1)
         torch.cuda.synchronize()
         sl = slice(off[k], off[k + 1])
         assert torch.allclose(Md[sl], M1, rtol=1e-5, atol=1e-6), k
