@@ -1339,12 +1339,14 @@ __global__ void k_unpack3(int64_t n, const float* __restrict__ S, float* E, floa
 //   E[phi_(abc) phi_(a'b'c')] = sum_{i,j,l} sigma_ijl H_aa'(x_i) H_bb'(x_j) H_cc'(x_l)
 // with H_pq = h_p h_q (15 unordered pairs p <= q <= 4), contracted one axis at a
 // time (sum factorisation):
-//   P1[i][j][cc'] = sum_l sigma_ijl H_cc'(x_l)                (n^3 * 15 FMA)
-//   P2_i[bb'][cc'] = sum_j P1[i][j][cc'] H_bb'(x_j)           (n^2 * 105 FMA)
-//   T[aa'][bb'][cc'] += H_aa'(x_i) P2_i[bb'][cc']             (n * 484 FMA)
+//   P1[i][cc'][j] = sum_l sigma_ijl H_cc'(x_l)                (n^3 * 15 FMA)
+//   P2[bb'cc'][i] = sum_j P1[i][cc'][j] H_bb'(x_j)            (n^2 * 105 FMA)
+//   T[aa'][bb'][cc'] = sum_i H_aa'(x_i) P2[bb'cc'][i]          (n * 484 FMA)
 // for the 105 (bb', cc') and 484 (aa', bb', cc') combinations the 630 pair
 // columns need: about 47 k FMA per cell and iteration at n = 12, against 1.09 M
-// for the dense sigma . Psi product.
+// for the dense sigma . Psi product.  The kernel evaluates the last stage once
+// per pair column (630 rather than 484 sums, but no gather pass), and lays P1
+// and P2 out so that each sum reads contiguous float4 rows of LDS.
 
 // Unordered pair (p, q) of one-dimensional Hermite indices (p, q <= 4): 0..14.
 __host__ __device__ constexpr int up_idx(int p, int q) {
@@ -1409,7 +1411,39 @@ constexpr SfTables make_sf_tables() {
 }
 static_assert(make_sf_tables().nbc == SF_NBC && make_sf_tables().nt == SF_NT,
               "sum-factorisation table sizes");
-__constant__ SfTables c_sf = make_sf_tables();
+
+// The same tables laid out per lane for the persistent kernel at n = 12, so
+// that each lane reads its whole share with ten coalesced loads:
+//   stage 2, element e = lane + 64 r (e = bc * 12 + x, r < 20): B | C << 4 in
+//     byte r & 3 of s2[r >> 2][lane];
+//   stage 3, pair column col = lane + 64 r (r < 10): aa' | bc << 4 in half
+//     r & 1 of s3[r >> 1][lane], 0xffff for the padding columns.
+constexpr int SF_N = 12;
+constexpr int SF_R2 = (SF_NBC * SF_N + 63) / 64;  // 20 rounds
+constexpr int SF_R3 = NCOL / 64;                   // 10 rounds
+struct SfLane {
+  uint32_t s2[(SF_R2 + 3) / 4][64];
+  uint32_t s3[(SF_R3 + 1) / 2][64];
+};
+constexpr SfLane make_sf_lane() {
+  const SfTables t = make_sf_tables();
+  SfLane s{};
+  for (int r = 0; r < SF_R2; ++r)
+    for (int ln = 0; ln < 64; ++ln) {
+      const int e = ln + 64 * r;
+      const uint32_t v = e < SF_NBC * SF_N
+          ? (uint32_t)t.bcB[e / SF_N] | ((uint32_t)t.bcC[e / SF_N] << 4) : 0u;
+      s.s2[r >> 2][ln] |= v << (8 * (r & 3));
+    }
+  for (int r = 0; r < SF_R3; ++r)
+    for (int ln = 0; ln < 64; ++ln) {
+      const int tt = t.colT[ln + 64 * r];
+      const uint32_t v = tt >= 0 ? (uint32_t)t.tA[tt] | ((uint32_t)t.tBC[tt] << 4) : 0xffffu;
+      s.s3[r >> 1][ln] |= v << (16 * (r & 1));
+    }
+  return s;
+}
+__constant__ SfLane c_sfl = make_sf_lane();
 
 // V[q][c] = sum_{a+b+c<=4} b_abc h_a(x_i) h_b(x_j) for every node pair q = (i, j):
 // the per-pair coefficients of the sum-factorised exponent (as in k_lse3).
@@ -1492,30 +1526,20 @@ __device__ __forceinline__ float uf(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 __device__ __forceinline__ int ui(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ double ud(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
-  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float uni(float v) { return uf(v); }
-__device__ __forceinline__ double uni(double v) { return ud(v); }
 
-// wave_chol with the pivot made wave-uniform (see uf): the early exit on a
-// failed pivot is then a uniform branch.
+// Right-looking Cholesky (as wave_chol) with the rows in registers only: lane
+// i holds row i of A, and step k broadcasts row k from lane k with readlane
+// (scalar registers), so no LDS round trip sits in the chain from one pivot to
+// the next.  Afterwards lane i keeps a[k] = L[i][k] L[k][k] for k < i (frozen
+// at step k) and lane k keeps dinv = 1 / L[k][k]; the pivot is uniform, so a
+// failed factorisation returns on every lane at the same step.
 template <typename T>
-__device__ __forceinline__ bool wave_chol_u(T (&a)[NH], T& dinv, int lane, T& dmin, T& dmax, T* Lm) {
+__device__ __forceinline__ bool wave_chol_rl(T (&a)[NH], T& dinv, int lane, T& dmin, T& dmax) {
   dmin = (T)FLT_MAX; dmax = 0;
   dinv = 1;
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
-    T* row = Lm + k * LST;
-    if (lane < NH) row[lane] = a[k];
-    __builtin_amdgcn_wave_barrier();
-    T u[NH];
-#pragma unroll
-    for (int i = k; i < NH; ++i) u[i] = row[i];
-    const T d = uni(u[k]);
+    const T d = rl(a[k], k);
     if (!((d > (T)0) && isfinite(d))) return false;
     dmin = d < dmin ? d : dmin;
     dmax = d > dmax ? d : dmax;
@@ -1523,32 +1547,51 @@ __device__ __forceinline__ bool wave_chol_u(T (&a)[NH], T& dinv, int lane, T& dm
     if (lane == k) dinv = inv;
     const T cj = lane > k ? a[k] * (inv * inv) : (T)0;
 #pragma unroll
-    for (int i = k + 1; i < NH; ++i) a[i] = fma(-u[i], cj, a[i]);
-    __builtin_amdgcn_wave_barrier();
-    if (lane < NH) row[lane] = lane >= k ? a[k] * inv : (T)0;
-    keep_col(a);
-    __builtin_amdgcn_wave_barrier();
+    for (int i = k + 1; i < NH; ++i) a[i] = fma(-rl(a[i], k), cj, a[i]);
   }
   return true;
 }
 
+// Forward L w = b and backward L^T d = w on the registers wave_chol_rl leaves:
+// lane i holds b_i and gets w_i, d_i.
+template <typename T>
+__device__ __forceinline__ void wave_solve_rl(const T (&a)[NH], T dinv, int lane, T b, T& w,
+                                              T& d) {
+  T acc = b;
+  w = 0;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) {
+    const T ik = rl(dinv, k);
+    const T wk = rl(acc, k) * ik;
+    if (lane == k) w = wk;
+    if (lane > k && lane < NH) acc = fma(-(a[k] * ik), wk, acc);
+  }
+  T acc2 = w;
+  d = 0;
+#pragma unroll
+  for (int i = NH - 1; i >= 0; --i) {
+    const T di = rl(acc2 * dinv, i);
+    if (lane == i) d = di;
+    if (lane < i) acc2 = fma(-a[i] * dinv, di, acc2);
+  }
+}
+
 // LDS of one wave (floats).  W holds P1 during the assembly, then the S row,
-// E and the factor (FP32), or E and the factor in FP64 (the S row then read
-// back from global memory).
+// E in FP32 and, for the FP64 direction, E in FP64.  sVd holds the line search's direction coefficients, and P2 during the
+// assembly.
 template <int NT>
 struct WaveLds {
   static constexpr int NP = NT * NT;
-  static constexpr int W32 = NCOL + 36 + NH * LST;          // S, E, L (FP32)
-  static constexpr int W64 = 2 * (36 + NH * LST);           // E, L (FP64)
+  static constexpr int W32 = NCOL + 36;                     // S, E (FP32)
+  static constexpr int W64 = NCOL + 36 + 2 * 36;            // S, E (FP32), E (FP64)
   static constexpr int WP = NP * 15;                        // P1
   static constexpr int WN = (WP > W32 ? (WP > W64 ? WP : W64) : (W32 > W64 ? W32 : W64));
-  float sH[6 * NT];
-  float sHp[15 * NT];
-  float sB[72];
-  float sVb[NP * 5];
-  float sVd[NP * 5];
-  float sP2[128];
-  float sT[512];
+  static constexpr int VD = NP * 5 > SF_NBC * NT ? NP * 5 : SF_NBC * NT;
+  __align__(16) float sH[6 * NT];
+  __align__(16) float sHp[15 * NT];
+  __align__(16) float sB[72];
+  __align__(16) float sVb[NP * 5];
+  __align__(16) float sVd[VD];
   __align__(16) float W[(WN + 3) / 4 * 4];
 };
 
@@ -1559,7 +1602,8 @@ __global__ __launch_bounds__(64) void k_newton_wave(
     float* __restrict__ S_w, float* __restrict__ logZ_w, int32_t* __restrict__ iters_w,
     uint32_t* __restrict__ status_w, float* __restrict__ resid_w, DirOut o) {
   constexpr int NP = NT * NT;
-  static_assert(NP * 5 >= NCOL, "the FP64 direction keeps the S row in sVd");
+  static_assert(NT == SF_N, "the per-lane assembly tables are laid out for 12 nodes per axis");
+  static_assert(NT % 4 == 0, "P1, P2 and H rows are read as float4");
   __shared__ WaveLds<NT> L;
   const int lane = threadIdx.x;
   for (int t = lane; t < 6 * NT; t += 64) L.sH[t] = t1[t].x;
@@ -1638,7 +1682,19 @@ __global__ __launch_bounds__(64) void k_newton_wave(
         __builtin_amdgcn_wave_barrier();
         build_v<NT>(L.sB, L.sH, L.sVb, lane);
         __builtin_amdgcn_wave_barrier();
-        // stage 1: sigma and P1[q][pq] = sum_l sigma(q, l) H_pq(x_l)
+        // this lane's share of the stage-2 and stage-3 index tables (loaded
+        // here, behind an opaque offset, so that they are not held in
+        // registers across the direction solve)
+        uint32_t s2p[(SF_R2 + 3) / 4], s3p[(SF_R3 + 1) / 2];
+        {
+          int z = lane;
+          asm volatile("" : "+v"(z));
+#pragma unroll
+          for (int k = 0; k < (SF_R2 + 3) / 4; ++k) s2p[k] = c_sfl.s2[k][z];
+#pragma unroll
+          for (int k = 0; k < (SF_R3 + 1) / 2; ++k) s3p[k] = c_sfl.s3[k][z];
+        }
+        // stage 1: sigma and P1[i][pq][j] = sum_l sigma(i, j, l) H_pq(x_l)
         float* P1 = L.W;
 #pragma unroll 1
         for (int q = lane; q < NP; q += 64) {
@@ -1666,44 +1722,55 @@ __global__ __launch_bounds__(64) void k_newton_wave(
             for (int t = 0; t < 15; ++t) acc[t] = fmaf(sg, shp[t * NT + l], acc[t]);
           }
 #pragma unroll
-          for (int t = 0; t < 15; ++t) P1[q * 15 + t] = acc[t];
+          for (int t = 0; t < 15; ++t) P1[(i * 15 + t) * NT + j] = acc[t];
         }
         __builtin_amdgcn_wave_barrier();
-        // stages 2 and 3, one x node at a time
-        float tacc[8];
+        // stage 2, one element (bc, x) per lane and round, no barrier between
+        // rounds: P2[bc][x] = sum_y P1[x][C][y] H_B(x_y)
+        float* P2 = L.sVd;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) tacc[k] = 0.f;
-        for (int x = 0; x < NT; ++x) {
+        for (int r = 0; r < SF_R2; ++r) {
+          const int e = lane + 64 * r;
+          if (r + 1 < SF_R2 || e < SF_NBC * NT) {
+            const uint32_t v = (s2p[r >> 2] >> (8 * (r & 3))) & 0xffu;
+            const int B = (int)(v & 15u), C = (int)(v >> 4);
+            const int x = e - (e / NT) * NT;
+            const float4* a4 = reinterpret_cast<const float4*>(P1 + (x * 15 + C) * NT);
+            const float4* h4 = reinterpret_cast<const float4*>(L.sHp + B * NT);
+            float acc = 0.f;
 #pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const int qb = lane + 64 * k;
-            if (qb < SF_NBC) {
-              const int B = c_sf.bcB[qb], C = c_sf.bcC[qb];
-              float sacc = 0.f;
+            for (int k = 0; k < NT / 4; ++k) {
+              const float4 a = a4[k], h = h4[k];
+              acc = fmaf(a.x, h.x, acc);
+              acc = fmaf(a.y, h.y, acc);
+              acc = fmaf(a.z, h.z, acc);
+              acc = fmaf(a.w, h.w, acc);
+            }
+            P2[e] = acc;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        // stage 3 straight into the S row (over the dead P1): pair column col
+        // of triple (aa', bc) is sum_x H_aa'(x_x) P2[bc][x]
+        float* Sr = L.W;
 #pragma unroll
-              for (int y = 0; y < NT; ++y)
-                sacc = fmaf(P1[(x * NT + y) * 15 + C], L.sHp[B * NT + y], sacc);
-              L.sP2[qb] = sacc;
+        for (int r = 0; r < SF_R3; ++r) {
+          const uint32_t v = (s3p[r >> 1] >> (16 * (r & 1))) & 0xffffu;
+          float acc = 0.f;
+          if (v != 0xffffu) {
+            const int A = (int)(v & 15u), bc = (int)(v >> 4);
+            const float4* h4 = reinterpret_cast<const float4*>(L.sHp + A * NT);
+            const float4* p4 = reinterpret_cast<const float4*>(P2 + bc * NT);
+#pragma unroll
+            for (int k = 0; k < NT / 4; ++k) {
+              const float4 h = h4[k], b = p4[k];
+              acc = fmaf(h.x, b.x, acc);
+              acc = fmaf(h.y, b.y, acc);
+              acc = fmaf(h.z, b.z, acc);
+              acc = fmaf(h.w, b.w, acc);
             }
           }
-          __builtin_amdgcn_wave_barrier();
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const int t = lane + 64 * k;
-            if (t < SF_NT) tacc[k] = fmaf(L.sHp[c_sf.tA[t] * NT + x], L.sP2[c_sf.tBC[t]], tacc[k]);
-          }
-          __builtin_amdgcn_wave_barrier();
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int t = lane + 64 * k;
-          if (t < SF_NT) L.sT[t] = tacc[k];
-        }
-        __builtin_amdgcn_wave_barrier();
-        float* Sr = L.W;  // the S row over the dead P1
-        for (int col = lane; col < NCOL; col += 64) {
-          const int t = c_sf.colT[col];
-          Sr[col] = t >= 0 ? L.sT[t] : 0.f;
+          Sr[lane + 64 * r] = acc;
         }
         __builtin_amdgcn_wave_barrier();
         // gradient, residual and Newton direction (k_direction3 / k_fallback3)
@@ -1715,7 +1782,6 @@ __global__ __launch_bounds__(64) void k_newton_wave(
         const float g = lane < NH ? E[lane + 1] - mnj : 0.f;
         r = uf(wave_max(fabsf(g)));
         if (!isfinite(s00) || !(s00 > 0.f)) r = NAN;
-        float* Lm = E + 36;
         float a[NH], dinv = 1.f, dmin = 0.f, dmax = 0.f;
         bool ok = false, to64 = false;
         float lam = 0.f;
@@ -1723,7 +1789,7 @@ __global__ __launch_bounds__(64) void k_newton_wave(
           int ln = lane;
           asm volatile("" : "+v"(ln));
           load_hcol(Sr, inv0, E, ln, lam, a);
-          ok = wave_chol_u(a, dinv, ln, dmin, dmax, Lm);
+          ok = wave_chol_rl(a, dinv, ln, dmin, dmax);
           if (tries == 0) cnd = ok ? dmax / dmin : __builtin_inff();
           if (tries == 0 && p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
             to64 = isfinite(r);
@@ -1735,21 +1801,14 @@ __global__ __launch_bounds__(64) void k_newton_wave(
         }
         if (!to64) {
           float w = 0.f, d = 0.f;
-          if (ok) wave_solve(a, Lm, dinv, lane, -g, w, d);
+          if (ok) wave_solve_rl(a, dinv, lane, -g, w, d);
           res = ok ? uf(0.5f * wave_sum(lane < NH ? w * w : 0.f)) : 0.f;
           dfin = ok && __all(lane >= NH || isfinite(d));
           dk = __shfl(d, (lane + 63) & 63);
         } else {
-          // FP64 direction: the S row moves to the line search's sVd area
-          // (rebuilt before its next use), its own space takes E and the factor
-          // in double.  Lanes exchange it through LDS only: global memory
-          // written by one lane and read by another in the same wave is not
-          // ordered without a fence.
-          float* Sg = L.sVd;
-          for (int col = lane; col < NCOL; col += 64) Sg[col] = Sr[col];
-          __builtin_amdgcn_wave_barrier();
-          double* Ed = reinterpret_cast<double*>(L.W);
-          double* Lmd = Ed + 36;
+          // FP64 direction: E in double after the FP32 E; the factor stays in
+          // registers
+          double* Ed = reinterpret_cast<double*>(L.W + NCOL + 36);
           const double inv0d = 1.0 / (double)s00;
           if (lane < K3) Ed[lane] = lane == 0 ? 1.0 : (double)Sr[lane] * inv0d;
           __builtin_amdgcn_wave_barrier();
@@ -1762,22 +1821,18 @@ __global__ __launch_bounds__(64) void k_newton_wave(
           for (int tries = 0; tries < 41 && !okd; ++tries) {
             int ln = lane;
             asm volatile("" : "+v"(ln));
-            load_hcol(Sg, inv0d, Ed, ln, lamd, ad);
-            okd = wave_chol_u(ad, dinvd, ln, dmind, dmaxd, Lmd);
+            load_hcol(Sr, inv0d, Ed, ln, lamd, ad);
+            okd = wave_chol_rl(ad, dinvd, ln, dmind, dmaxd);
             if (!okd) {
               lamd = tries == 0 ? (double)p.lambda0 : lamd * (double)p.lambda_mul;
               extra |= MEM_ST_SHIFTED;
             }
           }
           double w = 0.0, d = 0.0;
-          if (okd) wave_solve(ad, Lmd, dinvd, lane, -gd, w, d);
+          if (okd) wave_solve_rl(ad, dinvd, lane, -gd, w, d);
           res = uf((float)(0.5 * wave_sum(lane < NH ? w * w : 0.0)));
           dfin = okd && __all(lane >= NH || isfinite(d));
           dk = (float)__shfl(d, (lane + 63) & 63);
-          __builtin_amdgcn_wave_barrier();
-          // restore the S row in LDS (a refinement candidate writes it back)
-          for (int col = lane; col < NCOL; col += 64) Sr[col] = Sg[col];
-          __builtin_amdgcn_wave_barrier();
         }
         dk = kin ? dk : 0.f;
       }

@@ -99,10 +99,13 @@ def _split_by_oracle(st, ref, what):
     good = ref["converged"]
     bad = ref["nonrealizable"]
     assert np.all(good | bad), "oracle left cells unresolved"
-    # realizable cells converge (a few stop at the FP32 precision floor);
-    # cells without a minimiser are never reported converged
-    # (about 0.5% of the hardest Mott-Smith cells stop at the FP32 floor)
-    assert np.mean((st[good] & mem.ST_CONVERGED) != 0) >= 0.97
+    # realizable cells converge, except the few hardest (bimodal, high-Mach)
+    # cells whose FP32 gradient noise sits at the tolerance: they end
+    # stagnated (0.3% of the Mott-Smith cells here; at most 1%); cells without
+    # a minimiser are never reported converged
+    conv = (st[good] & mem.ST_CONVERGED) != 0
+    assert conv.mean() >= 0.99
+    assert np.all(st[good][~conv] & mem.ST_STAGNATED), np.unique(st[good][~conv])
     assert not np.any(st[bad] & mem.ST_CONVERGED), np.unique(st[bad])
     print(f"[{what}] oracle-realizable {good.sum()} / {good.size}; converged "
           f"{np.sum((st[good] & mem.ST_CONVERGED) != 0)}")
@@ -426,7 +429,8 @@ def test_closed_form_first_pass(ctx3, rule3):
         out[name] = (bg.cpu().numpy().astype(np.float64), iters.cpu().numpy(), status.cpu().numpy())
     (ba, ia, sa), (bb, ib, sb) = out["closed"], out["assembled"]
     both = ((sa & mem.ST_CONVERGED) != 0) & ((sb & mem.ST_CONVERGED) != 0)
-    assert both.mean() >= 0.97
+    print(f"\n[closed start] converged in both runs: {both.mean():.3f}")
+    assert both.mean() >= 0.98
     ref = maxent.newton_solve(M, b0, rule3["Phi"], rule3["logw"])
     for beta in (ba, bb):
         err = np.max(np.abs(beta[both] - ref["beta"][both]), axis=1) / np.maximum(
