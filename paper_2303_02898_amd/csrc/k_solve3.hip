@@ -1412,14 +1412,16 @@ constexpr SfTables make_sf_tables() {
 static_assert(make_sf_tables().nbc == SF_NBC && make_sf_tables().nt == SF_NT,
               "sum-factorisation table sizes");
 
-// The same tables laid out per lane for the persistent kernel at n = 12, so
-// that each lane reads its whole share with ten coalesced loads:
-//   stage 2, element e = lane + 64 r (e = bc * 12 + x, r < 20): B | C << 4 in
-//     byte r & 3 of s2[r >> 2][lane];
+// The same tables laid out per lane for the persistent kernel at n = 12, which
+// runs the three stages on chunks of SF_XC nodes of the first axis; each lane
+// reads its whole share with seven coalesced loads:
+//   stage 2, element e = lane + 64 r of a chunk (e = bc * SF_XC + x, r < 7):
+//     B | C << 4 in byte r & 3 of s2[r >> 2][lane];
 //   stage 3, pair column col = lane + 64 r (r < 10): aa' | bc << 4 in half
 //     r & 1 of s3[r >> 1][lane], 0xffff for the padding columns.
 constexpr int SF_N = 12;
-constexpr int SF_R2 = (SF_NBC * SF_N + 63) / 64;  // 20 rounds
+constexpr int SF_XC = 4;                            // first-axis nodes per chunk
+constexpr int SF_R2 = (SF_NBC * SF_XC + 63) / 64;  // 7 rounds per chunk
 constexpr int SF_R3 = NCOL / 64;                   // 10 rounds
 struct SfLane {
   uint32_t s2[(SF_R2 + 3) / 4][64];
@@ -1431,8 +1433,8 @@ constexpr SfLane make_sf_lane() {
   for (int r = 0; r < SF_R2; ++r)
     for (int ln = 0; ln < 64; ++ln) {
       const int e = ln + 64 * r;
-      const uint32_t v = e < SF_NBC * SF_N
-          ? (uint32_t)t.bcB[e / SF_N] | ((uint32_t)t.bcC[e / SF_N] << 4) : 0u;
+      const uint32_t v = e < SF_NBC * SF_XC
+          ? (uint32_t)t.bcB[e / SF_XC] | ((uint32_t)t.bcC[e / SF_XC] << 4) : 0u;
       s.s2[r >> 2][ln] |= v << (8 * (r & 3));
     }
   for (int r = 0; r < SF_R3; ++r)
@@ -1576,34 +1578,34 @@ __device__ __forceinline__ void wave_solve_rl(const T (&a)[NH], T dinv, int lane
   }
 }
 
-// LDS of one wave (floats).  W holds P1 during the assembly, then the S row,
-// E in FP32 and, for the FP64 direction, E in FP64.  sVd holds the line search's direction coefficients, and P2 during the
-// assembly.
+// LDS of one wave (floats).  W holds one chunk of P1 and of P2 during the
+// assembly, then the S row, E in FP32 and, for the FP64 direction, E in FP64.
+// sVd holds the line search's direction coefficients.  About 11.6 KB at
+// n = 12: three waves per SIMD fit in the 160 KB of a CU.
 template <int NT>
 struct WaveLds {
   static constexpr int NP = NT * NT;
-  static constexpr int W32 = NCOL + 36;                     // S, E (FP32)
-  static constexpr int W64 = NCOL + 36 + 2 * 36;            // S, E (FP32), E (FP64)
-  static constexpr int WP = NP * 15;                        // P1
-  static constexpr int WN = (WP > W32 ? (WP > W64 ? WP : W64) : (W32 > W64 ? W32 : W64));
-  static constexpr int VD = NP * 5 > SF_NBC * NT ? NP * 5 : SF_NBC * NT;
+  static constexpr int W32 = NCOL + 36 + 2 * 36;           // S, E (FP32 and FP64)
+  static constexpr int P1C = SF_XC * 15 * NT;               // P1 of a chunk
+  static constexpr int WP = P1C + SF_NBC * SF_XC;           // P1 and P2 of a chunk
+  static constexpr int WN = WP > W32 ? WP : W32;
   __align__(16) float sH[6 * NT];
   __align__(16) float sHp[15 * NT];
   __align__(16) float sB[72];
   __align__(16) float sVb[NP * 5];
-  __align__(16) float sVd[VD];
+  __align__(16) float sVd[NP * 5];
   __align__(16) float W[(WN + 3) / 4 * 4];
 };
 
 template <int NT>
-__global__ __launch_bounds__(64) void k_newton_wave(
+__global__ __launch_bounds__(64, 3) void k_newton_wave(
     const float2* __restrict__ t1, int32_t* __restrict__ queue, int64_t ncell,
     const float* __restrict__ M, float* __restrict__ beta, SolveParams p, int closed_start,
     float* __restrict__ S_w, float* __restrict__ logZ_w, int32_t* __restrict__ iters_w,
     uint32_t* __restrict__ status_w, float* __restrict__ resid_w, DirOut o) {
   constexpr int NP = NT * NT;
   static_assert(NT == SF_N, "the per-lane assembly tables are laid out for 12 nodes per axis");
-  static_assert(NT % 4 == 0, "P1, P2 and H rows are read as float4");
+  static_assert(SF_XC == 4 && NT % SF_XC == 0, "chunks of four nodes, read as float4");
   __shared__ WaveLds<NT> L;
   const int lane = threadIdx.x;
   for (int t = lane; t < 6 * NT; t += 64) L.sH[t] = t1[t].x;
@@ -1694,84 +1696,91 @@ __global__ __launch_bounds__(64) void k_newton_wave(
 #pragma unroll
           for (int k = 0; k < (SF_R3 + 1) / 2; ++k) s3p[k] = c_sfl.s3[k][z];
         }
-        // stage 1: sigma and P1[i][pq][j] = sum_l sigma(i, j, l) H_pq(x_l)
-        float* P1 = L.W;
+        // the three stages on chunks of SF_XC first-axis nodes; the pair
+        // columns accumulate in registers across the chunks
+        float* P1 = L.W;                          // P1[i][pq][j], i in the chunk
+        float* P2 = L.W + WaveLds<NT>::P1C;       // P2[bc][i], i in the chunk
+        float tcol[SF_R3];
+#pragma unroll
+        for (int r = 0; r < SF_R3; ++r) tcol[r] = 0.f;
 #pragma unroll 1
-        for (int q = lane; q < NP; q += 64) {
-          // the tables never change, so without an opaque offset the compiler
-          // keeps all 252 of them in registers across the whole kernel
-          int z = 0;
-          asm volatile("" : "+v"(z));
-          const float* sh = L.sH + z;
-          const float* shp = L.sHp + z;
-          const int i = q / NT, j = q - (q / NT) * NT;
-          const float base = sh[5 * NT + i] + sh[5 * NT + j];
-          float v[5];
+        for (int x0 = 0; x0 < NT; x0 += SF_XC) {
+          // stage 1: sigma and P1[i][pq][j] = sum_l sigma(i, j, l) H_pq(x_l)
+          if (lane < SF_XC * NT) {
+            // the tables never change, so without an opaque offset the
+            // compiler keeps all 252 of them in registers across the kernel
+            int z = 0;
+            asm volatile("" : "+v"(z));
+            const float* sh = L.sH + z;
+            const float* shp = L.sHp + z;
+            const int il = lane / NT, j = lane - (lane / NT) * NT;
+            const int q = (x0 + il) * NT + j;
+            const float base = sh[5 * NT + x0 + il] + sh[5 * NT + j];
+            float v[5];
 #pragma unroll
-          for (int c = 0; c < 5; ++c) v[c] = L.sVb[q * 5 + c];
-          float acc[15];
+            for (int c = 0; c < 5; ++c) v[c] = L.sVb[q * 5 + c];
+            float acc[15];
 #pragma unroll
-          for (int t = 0; t < 15; ++t) acc[t] = 0.f;
+            for (int t = 0; t < 15; ++t) acc[t] = 0.f;
 #pragma unroll
-          for (int l = 0; l < NT; ++l) {
-            float x = base + sh[5 * NT + l];
+            for (int l = 0; l < NT; ++l) {
+              float x = base + sh[5 * NT + l];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) x = fmaf(v[c], sh[c * NT + l], x);
-            const float sg = __expf(x - lz);
+              for (int c = 0; c < 5; ++c) x = fmaf(v[c], sh[c * NT + l], x);
+              const float sg = __expf(x - lz);
 #pragma unroll
-            for (int t = 0; t < 15; ++t) acc[t] = fmaf(sg, shp[t * NT + l], acc[t]);
-          }
-#pragma unroll
-          for (int t = 0; t < 15; ++t) P1[(i * 15 + t) * NT + j] = acc[t];
-        }
-        __builtin_amdgcn_wave_barrier();
-        // stage 2, one element (bc, x) per lane and round, no barrier between
-        // rounds: P2[bc][x] = sum_y P1[x][C][y] H_B(x_y)
-        float* P2 = L.sVd;
-#pragma unroll
-        for (int r = 0; r < SF_R2; ++r) {
-          const int e = lane + 64 * r;
-          if (r + 1 < SF_R2 || e < SF_NBC * NT) {
-            const uint32_t v = (s2p[r >> 2] >> (8 * (r & 3))) & 0xffu;
-            const int B = (int)(v & 15u), C = (int)(v >> 4);
-            const int x = e - (e / NT) * NT;
-            const float4* a4 = reinterpret_cast<const float4*>(P1 + (x * 15 + C) * NT);
-            const float4* h4 = reinterpret_cast<const float4*>(L.sHp + B * NT);
-            float acc = 0.f;
-#pragma unroll
-            for (int k = 0; k < NT / 4; ++k) {
-              const float4 a = a4[k], h = h4[k];
-              acc = fmaf(a.x, h.x, acc);
-              acc = fmaf(a.y, h.y, acc);
-              acc = fmaf(a.z, h.z, acc);
-              acc = fmaf(a.w, h.w, acc);
+              for (int t = 0; t < 15; ++t) acc[t] = fmaf(sg, shp[t * NT + l], acc[t]);
             }
-            P2[e] = acc;
+#pragma unroll
+            for (int t = 0; t < 15; ++t) P1[(il * 15 + t) * NT + j] = acc[t];
           }
-        }
-        __builtin_amdgcn_wave_barrier();
-        // stage 3 straight into the S row (over the dead P1): pair column col
-        // of triple (aa', bc) is sum_x H_aa'(x_x) P2[bc][x]
-        float* Sr = L.W;
+          __builtin_amdgcn_wave_barrier();
+          // stage 2: P2[bc][i] = sum_j P1[i][C][j] H_B(x_j)
 #pragma unroll
-        for (int r = 0; r < SF_R3; ++r) {
-          const uint32_t v = (s3p[r >> 1] >> (16 * (r & 1))) & 0xffffu;
-          float acc = 0.f;
-          if (v != 0xffffu) {
-            const int A = (int)(v & 15u), bc = (int)(v >> 4);
-            const float4* h4 = reinterpret_cast<const float4*>(L.sHp + A * NT);
-            const float4* p4 = reinterpret_cast<const float4*>(P2 + bc * NT);
+          for (int r = 0; r < SF_R2; ++r) {
+            const int e = lane + 64 * r;
+            if (r + 1 < SF_R2 || e < SF_NBC * SF_XC) {
+              const uint32_t v = (s2p[r >> 2] >> (8 * (r & 3))) & 0xffu;
+              const int B = (int)(v & 15u), C = (int)(v >> 4);
+              const int il = e & (SF_XC - 1);
+              const float4* a4 = reinterpret_cast<const float4*>(P1 + (il * 15 + C) * NT);
+              const float4* h4 = reinterpret_cast<const float4*>(L.sHp + B * NT);
+              float acc = 0.f;
 #pragma unroll
-            for (int k = 0; k < NT / 4; ++k) {
-              const float4 h = h4[k], b = p4[k];
+              for (int k = 0; k < NT / 4; ++k) {
+                const float4 a = a4[k], h = h4[k];
+                acc = fmaf(a.x, h.x, acc);
+                acc = fmaf(a.y, h.y, acc);
+                acc = fmaf(a.z, h.z, acc);
+                acc = fmaf(a.w, h.w, acc);
+              }
+              P2[e] = acc;
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+          // stage 3: pair column col of triple (aa', bc) gains
+          // sum_{i in chunk} H_aa'(x_i) P2[bc][i]
+#pragma unroll
+          for (int r = 0; r < SF_R3; ++r) {
+            const uint32_t v = (s3p[r >> 1] >> (16 * (r & 1))) & 0xffffu;
+            if (v != 0xffffu) {
+              const int A = (int)(v & 15u), bc = (int)(v >> 4);
+              const float4 h = *reinterpret_cast<const float4*>(L.sHp + A * NT + x0);
+              const float4 b = *reinterpret_cast<const float4*>(P2 + bc * SF_XC);
+              float acc = tcol[r];
               acc = fmaf(h.x, b.x, acc);
               acc = fmaf(h.y, b.y, acc);
               acc = fmaf(h.z, b.z, acc);
               acc = fmaf(h.w, b.w, acc);
+              tcol[r] = acc;
             }
           }
-          Sr[lane + 64 * r] = acc;
+          __builtin_amdgcn_wave_barrier();
         }
+        // the S row over the dead chunk buffers
+        float* Sr = L.W;
+#pragma unroll
+        for (int r = 0; r < SF_R3; ++r) Sr[lane + 64 * r] = tcol[r];
         __builtin_amdgcn_wave_barrier();
         // gradient, residual and Newton direction (k_direction3 / k_fallback3)
         const float s00 = uf(Sr[0]);

@@ -244,7 +244,7 @@ hipError_t launch_set_ctr(int32_t* ctr, int n, hipStream_t s);
 // Persistent Newton solve of cells 0..n-1: one wavefront per live cell from
 // the work queue `queue` (zeroed by the caller); converged cells are appended
 // to done_list for the refinement kernels.
-constexpr int WAVE_SOLVE_PER_CU = 8;
+constexpr int WAVE_SOLVE_PER_CU = 12;
 hipError_t launch_newton_wave(mem_ctx_t c, int64_t n, const float* M, float* beta,
                               const SolveParams& p, bool closed_start, int32_t* queue,
                               int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
