@@ -398,19 +398,24 @@ MEM_API int64_t mem_axi_rule_nodes(const mem_axi_rule_t* rule);
 MEM_API mem_err_t mem_axi_host_rule(const mem_axi_rule_t* rule, double* ux, double* ur,
                                     double* logw, int64_t n_nodes);
 
-/* Handle holding the rule's node table (u_x as an FP32 pair hi + lo, u_r, log w) on the
- * current device.  MEM_ERR_INVALID_ARG for an invalid rule. */
+/* Handle holding the rule's node table (u_x as an FP32 pair hi + lo, u_r, log w, and
+ * the lo parts of u_r and log w for the compensated residual) on the current device.
+ * MEM_ERR_INVALID_ARG for an invalid rule. */
 MEM_API mem_err_t mem_axi_create(const mem_axi_rule_t* rule, mem_axi_t* out);
 MEM_API mem_err_t mem_axi_destroy(mem_axi_t h);
 MEM_API int64_t mem_axi_n_nodes(mem_axi_t h);
 
-/* Alg. 1 on the nine statistics, one wave per cell (FP32; FP64 direction for
- * a small pivot ratio as in mem_maxent_solve).  M[n][9] targets and g[n][3] =
- * (w_x, s_x, s_r) per cell; beta[n][9] in: start multipliers (beta[:,0]
- * ignored), out: solution with beta[:,0] = n.  Stopping rules and status bits
- * as mem_maxent_solve (no compensated refinement: resid is the FP32
- * max_{i>=1} |G_i| of the last assembly).  iters, resid, status may be NULL.
- * All arrays are device memory, row-major.  Asynchronous on stream. */
+/* Alg. 1 on the nine statistics, one wave per cell (FP32 exponent, statistics
+ * and sums; FP64 direction for a small pivot ratio as in mem_maxent_solve).
+ * M[n][9] targets and g[n][3] = (w_x, s_x, s_r) per cell; beta[n][9] in: start
+ * multipliers (beta[:,0] ignored), out: solution with beta[:,0] = n.  Stopping
+ * rules and status bits as mem_maxent_solve, including its compensated
+ * refinement (opts->refine passes): a cell that ends converged or at its FP32
+ * floor takes Newton corrections with the gradient evaluated in double-float
+ * FP32 arithmetic; resid is that compensated max_{i>=1} |G_i|, and the cell is
+ * converged when it is at most tol_grad_loose, stagnated otherwise.  iters,
+ * resid, status may be NULL.  All arrays are device memory, row-major.
+ * Asynchronous on stream. */
 MEM_API mem_err_t mem_axi_solve(mem_axi_t h, int64_t n_cells, const float* M, const float* g,
                                 float* beta, const mem_solve_opts_t* opts, int32_t* iters,
                                 float* resid, uint32_t* status, hipStream_t stream);

@@ -112,7 +112,8 @@ mem_err_t params_axi(const mem_axi_s* h, const mem_solve_opts_t* o, SolveParams&
   if (!o) o = &d;
   if (o->max_iter < 1 || o->max_iter > 100000 || o->max_ls < 0 || o->max_ls > 60 ||
       !(o->lambda0 > 0.f) || !(o->lambda_mul > 1.f) || !(o->fp64_pivot_ratio >= 0.f) ||
-      !(o->fp64_pivot_ratio < 1.f) || !std::isfinite(o->tol_grad) || !(o->beta_max >= 0.f))
+      !(o->fp64_pivot_ratio < 1.f) || !std::isfinite(o->tol_grad) || !(o->beta_max >= 0.f) ||
+      o->refine < 0 || o->refine > 8)
     return MEM_ERR_INVALID_ARG;
   p.tol_grad = o->tol_grad; p.tol_dec = o->tol_dec; p.tol_loose = o->tol_grad_loose;
   p.max_iter = o->max_iter; p.max_ls = o->max_ls;
@@ -121,7 +122,7 @@ mem_err_t params_axi(const mem_axi_s* h, const mem_solve_opts_t* o, SolveParams&
   p.fp64_ratio = o->fp64_pivot_ratio;
   p.beta_max = o->beta_max;
   p.lmin = h->lmin;
-  p.refine = 0;
+  p.refine = o->refine;
   p.stall_window = 0;
   return MEM_OK;
 }
@@ -174,11 +175,17 @@ mem_err_t mem_axi_create(const mem_axi_rule_t* rule, mem_axi_t* out) {
     return MEM_ERR_NOMEM;
   }
   h->P = (int64_t)h->ux.size();
-  std::vector<float4> tab(h->P);
+  // P entries (u_x, u_r, log w, u_x - fl(u_x)), then P / 2 float4 holding the
+  // pairs (u_r - fl(u_r), log w - fl(log w)) of the compensated residual pass
+  std::vector<float4> tab(h->P + (h->P + 1) / 2, make_float4(0.f, 0.f, 0.f, 0.f));
+  float* lo = reinterpret_cast<float*>(tab.data() + h->P);
   double mn = 1e300;
   for (int64_t q = 0; q < h->P; ++q) {
     const float hi = (float)h->ux[q];
-    tab[q] = make_float4(hi, (float)h->ur[q], (float)h->logw[q], (float)(h->ux[q] - (double)hi));
+    const float ur = (float)h->ur[q], lw = (float)h->logw[q];
+    tab[q] = make_float4(hi, ur, lw, (float)(h->ux[q] - (double)hi));
+    lo[2 * q] = (float)(h->ur[q] - (double)ur);
+    lo[2 * q + 1] = (float)(h->logw[q] - (double)lw);
     mn = std::min(mn, h->logw[q]);
   }
   h->ux_min = (float)*std::min_element(h->ux.begin(), h->ux.end());

@@ -18,6 +18,7 @@
 #include <cfloat>
 #include <cmath>
 
+#include "dfloat.h"
 #include "mem_internal.h"
 
 namespace memk {
@@ -28,47 +29,53 @@ constexpr int NA = 45;          // sum sigma, 8 first moments, 36 second moments
 constexpr int AXW = 1;          // waves (cells) per workgroup: a slow cell holds only its own slot
 constexpr int RSTRIDE = NA;     // odd row stride of the reduction area: no bank conflicts
 
-struct AxGauge { double w, isx, isr; };
+struct AxGauge { float w, isx, isr; };
 
-// The exponent lw + sum_i beta_i phi_i adds terms of size ~10 that largely
-// cancel where sigma is not small; in FP32 its rounding (~1e-5 absolute)
-// shows up directly as relative error of sigma.  The coordinates, the
-// statistics inside the exponent and the exponent itself are therefore
-// evaluated in FP64 (on this chip FP64 FMA runs at the rate of unpacked FP32);
-// sigma, the statistics used in the sums and the sums stay FP32.
-// u_x arrives as a pair hi + lo (the FP32 rounding of the FP64 node and its
-// remainder).
-__device__ __forceinline__ float expo9(const float4& nd, const AxGauge& g, const double (&b)[9],
+// Exponent lw_p + sum_i beta_i phi_i(u_bar_p) and the statistics at node p, in
+// FP32.  The exponent adds terms of size ~10 that largely cancel where sigma
+// is not small, so its absolute rounding error is relative error of sigma.
+// Two things keep it near 1e-6 there:
+//  * the coordinate u_x - w: the node's u_x arrives as hi + lo (the FP32
+//    rounding of the FP64 node and its remainder), and hi - w is exact when the
+//    two are within a factor of two (or rounded relative to the difference,
+//    which then puts sigma far out in the tail), so x carries relative error
+//    ~1e-7 instead of the 1e-6 absolute that rounding u_x alone would leave at
+//    Mach-10 velocities;
+//  * the sum itself: with x accurate, its rounding is ~(|lw| + sum |b_i phi_i|)
+//    2^-24 ~ 1e-6 where sigma matters.
+// The statistics used in the sums are the same FP32 values.
+__device__ __forceinline__ float expo9(const float4& nd, const AxGauge& g, const float (&b)[9],
                                        float (&f)[9]) {
-  const double x = (((double)nd.x - g.w) + (double)nd.w) * g.isx;
-  const double t = (double)nd.y * g.isr;
-  const double y = 0.5 * t * t;
-  const double x2 = x * x;
-  const double ym = y - 1.0;
-  const double p2 = (x2 - 1.0) * 0.70710678118654752;
-  double h[9];
-  h[1] = x;
-  h[2] = p2;
-  h[3] = ym;
-  h[4] = x * (x2 - 3.0) * 0.40824829046386302;
-  h[5] = fma(x2, x2 - 6.0, 3.0) * 0.20412414523193151;
-  h[6] = fma(0.5 * y, y, fma(-2.0, y, 1.0));
-  h[7] = x * ym;
-  h[8] = p2 * ym;
-  double e = (double)nd.z;
+  const float x = ((nd.x - g.w) + nd.w) * g.isx;
+  const float t = nd.y * g.isr;
+  const float y = 0.5f * t * t;
+  const float x2 = x * x;
+  const float ym = y - 1.f;
+  const float p2 = (x2 - 1.f) * 0.70710678118654752f;
   f[0] = 1.f;
+  f[1] = x;
+  f[2] = p2;
+  f[3] = ym;
+  f[4] = x * (x2 - 3.f) * 0.40824829046386302f;
+  f[5] = fmaf(x2, x2 - 6.f, 3.f) * 0.20412414523193151f;
+  f[6] = fmaf(0.5f * y, y, fmaf(-2.f, y, 1.f));
+  f[7] = x * ym;
+  f[8] = p2 * ym;
+  float e = nd.z;
 #pragma unroll
-  for (int i = 1; i < 9; ++i) {
-    e = fma(b[i], h[i], e);
-    f[i] = (float)h[i];
-  }
-  return (float)e;
+  for (int i = 1; i < 9; ++i) e = fmaf(b[i], f[i], e);
+  return e;
+}
+
+// The cell's gauge (FP32: the statistics are defined with exactly these values).
+__device__ __forceinline__ AxGauge ax_gauge(const float* gin, int64_t c) {
+  return {gin[c * 3], 1.f / gin[c * 3 + 1], 1.f / gin[c * 3 + 2]};
 }
 
 // log Z(b) by the log-sum-exp of Sec. 3.1: a running (max, scaled sum) per
 // lane over groups of four nodes (one rescale per group), then a butterfly
 // over the wave.  Every lane returns the same value.
-__device__ float lse9(const float4* __restrict__ tab, int P, const AxGauge& g, const double (&b)[9],
+__device__ float lse9(const float4* __restrict__ tab, int P, const AxGauge& g, const float (&b)[9],
                       int lane) {
   float mx = -FLT_MAX, sm = 0.f;
   for (int q0 = lane; q0 < P; q0 += 4 * 64) {
@@ -100,7 +107,7 @@ __device__ float lse9(const float4* __restrict__ tab, int P, const AxGauge& g, c
 // b with sigma_p = exp(e_p - logZ), reduced over the wave in a fixed order;
 // every lane gets all 45 in A.
 __device__ void assemble9(const float4* __restrict__ tab, int P, const AxGauge& g,
-                          const double (&b)[9], float logZ, int lane, float* red,
+                          const float (&b)[9], float logZ, int lane, float* red,
                           float (&A)[NA]) {
 #pragma unroll
   for (int k = 0; k < NA; ++k) A[k] = 0.f;
@@ -237,8 +244,7 @@ __device__ __forceinline__ double solve8_lds(const double* L, const double* G, d
 // FP32 residual floor.  A residual that has not halved for AX_FLOOR_WINDOW
 // iterations has reached the rounding floor of the FP32 moments.  Where that
 // floor lies at or below half of tol_grad_loose the cell is converged: the
-// moments carry ~1e-6 of FP32 evaluation error (exponent in FP64, sums in
-// FP32), so its residual in exact arithmetic stays within tol_grad_loose.
+// moments carry ~1e-6 of FP32 evaluation error (see expo9), so its residual in exact arithmetic stays within tol_grad_loose.
 // A floor above that ends the cell as stagnated after AX_STALL_WINDOW
 // iterations below AX_STALL_GATE.  Above the gate there is no such window:
 // on a wide box the damped phase of Newton from the Maxwellian start can keep
@@ -252,14 +258,93 @@ struct Lse9 { float logZ, L; };
 
 __device__ __forceinline__ Lse9 value9(const float4* tab, int P, const AxGauge& g, const float (&b)[9],
                                        const float (&mn)[9], int lane) {
-  double bd[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) bd[i] = (double)b[i];
-  const float lz = lse9(tab, P, g, bd, lane);
+  const float lz = lse9(tab, P, g, b, lane);
   float bm = 0.f;
 #pragma unroll
   for (int i = 1; i < 9; ++i) bm = fmaf(b[i], mn[i], bm);
   return {lz, lz - bm};
+}
+
+// Double-float constants 1/sqrt(2), 1/sqrt(6), 1/sqrt(24): the FP32 rounding
+// and its remainder.
+constexpr double RS2 = 0.70710678118654752440, RS6 = 0.40824829046386301637,
+                 RS24 = 0.20412414523193150818;
+constexpr dfl C_RS2{(float)RS2, (float)(RS2 - (double)(float)RS2)};
+constexpr dfl C_RS6{(float)RS6, (float)(RS6 - (double)(float)RS6)};
+constexpr dfl C_RS24{(float)RS24, (float)(RS24 - (double)(float)RS24)};
+
+// Compensated gradient G_i = E_sigma[phi_i] - M_i / n (i = 1..8) at b, all in
+// FP32 arithmetic: coordinates, statistics and exponent in double-float from
+// the hi + lo parts of the nodes (tab for u_x, lo for u_r and log w), the
+// gauge scales 1/s as quotient + remainder, sigma = exp(e - shift) (1 + e_lo),
+// and double-float sums reduced over the wave in a fixed order.  The shift
+// only keeps exp in range (it cancels in the quotients).  Returns max |G_i|;
+// every lane gets G.
+__device__ float grad9_acc(const float4* __restrict__ tab, const float2* __restrict__ lo, int P,
+                           float gw, float gsx, float gsr, const float (&b)[9], float shift,
+                           const float (&m)[9], int lane, float (&G)[8]) {
+#pragma clang fp contract(off)
+  const dfl isx = df_recip(gsx), isr = df_recip(gsr);
+  dfl S[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) S[i] = {0.f, 0.f};
+  for (int q = lane; q < P; q += 64) {
+    const float4 nd = tab[q];
+    const float2 nl = lo[q];
+    float xs, xe;
+    two_sum(nd.x, -gw, xs, xe);
+    const dfl x = df_mul(df_norm({xs, xe + nd.w}), isx);
+    const dfl t = df_mul({nd.y, nl.x}, isr);
+    dfl y = df_mul(t, t);
+    y = {0.5f * y.h, 0.5f * y.l};
+    const dfl x2 = df_mul(x, x);
+    const dfl ym = df_plus(y, -1.f);
+    dfl f[9];
+    f[1] = x;
+    f[2] = df_mul(df_plus(x2, -1.f), C_RS2);
+    f[3] = ym;
+    f[4] = df_mul(df_mul(x, df_plus(x2, -3.f)), C_RS6);
+    f[5] = df_mul(df_plus(df_mul(x2, df_plus(x2, -6.f)), 3.f), C_RS24);
+    dfl y2 = df_mul(y, y);
+    y2 = {0.5f * y2.h, 0.5f * y2.l};
+    dfl f6 = y2;
+    df_add(f6, {-2.f * y.h, -2.f * y.l});
+    f[6] = df_plus(df_norm(f6), 1.f);
+    f[7] = df_mul(x, ym);
+    f[8] = df_mul(f[2], ym);
+    dfl e = {nd.z, nl.y};
+#pragma unroll
+    for (int i = 1; i < 9; ++i) df_acc1(e, b[i], f[i]);
+    e = df_plus(df_norm(e), -shift);
+    if (e.h < -80.f) continue;  // weight below 1e-34: no measurable moment
+    const float ex = expf(e.h);
+    const float sg = fmaf(ex, e.l, ex);
+    df_add(S[0], {sg, 0.f});
+#pragma unroll
+    for (int i = 1; i < 9; ++i) df_acc1(S[i], sg, f[i]);
+  }
+  // butterfly over the wave: the same fixed order on every lane
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const dfl o = {__shfl_xor(S[i].h, off), __shfl_xor(S[i].l, off)};
+      df_add(S[i], o);
+    }
+  const float h0 = S[0].h, l0 = S[0].l, inv0 = 1.f / h0;
+  const float nn = m[0];
+  float r = 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    // quotients as q1 + q2 with q2 from the exact remainder (fma)
+    const float e1 = S[i + 1].h * inv0;
+    const float e2 = (fmaf(-e1, h0, S[i + 1].h) + (S[i + 1].l - e1 * l0)) * inv0;
+    const float m1 = m[i + 1] / nn;
+    const float m2 = fmaf(-m1, nn, m[i + 1]) / nn;
+    G[i] = (e1 - m1) + (e2 - m2);
+    r = fmaxf(r, fabsf(G[i]));
+  }
+  return isfinite(r) ? r : INFINITY;
 }
 
 }  // namespace
@@ -272,6 +357,7 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
                                                         int32_t* iters_out, float* resid_out,
                                                         uint32_t* status_out) {
   __shared__ __align__(16) float sred[AXW][65 * RSTRIDE];
+  __shared__ float sHk[AXW][36];  // the last FP32 Hessian, for the refinement
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int64_t c = (int64_t)blockIdx.x * AXW + wv;
@@ -293,7 +379,7 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
   if (!fin) st = MEM_ST_NONFINITE;
   else if (!(m[0] > 0.f) || !(gsx > 0.f) || !(gsr > 0.f)) st = MEM_ST_NONREALIZABLE;
   if (st == 0) {
-    const AxGauge g{(double)gw, 1.0 / (double)gsx, 1.0 / (double)gsr};
+    const AxGauge g{gw, 1.f / gsx, 1.f / gsr};
     const float nn = m[0];
     float mn[9];
 #pragma unroll
@@ -328,12 +414,7 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
       }
       // moments, gradient and covariance Hessian at b (App. C)
       float A[NA];
-      {
-        double bd[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) bd[i] = (double)b[i];
-        assemble9(tab, P, g, bd, cur.logZ, lane, red, A);
-      }
+      assemble9(tab, P, g, b, cur.logZ, lane, red, A);
       const float inv0 = 1.f / A[0];
       float E[8], G[8], Hp[36];
       r = 0.f;
@@ -347,6 +428,7 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
       for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j <= i; ++j) Hp[PK(i, j)] = A[UA(j, i)] * inv0 - E[i] * E[j];
+      if (lane < 36) sHk[wv][lane] = Hp[lane];
       ++it;
       if (r < 0.5f * rbest) { rbest = r; itbest = it; }
       float dd[8], res = 0.f;
@@ -421,6 +503,47 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
       }
       if (it >= p.max_iter) { st |= MEM_ST_MAXITER; break; }
     }
+    // Compensated refinement (as the 35-moment path): the FP32 iteration stops
+    // where its own rounding hides the residual; a cell that ended converged or
+    // at that floor takes Newton corrections with the double-float gradient
+    // and the last FP32 Hessian, keeping the best multipliers, and its final
+    // status and residual are the compensated ones.
+    if (p.refine > 0 && (st & (MEM_ST_CONVERGED | MEM_ST_STAGNATED)) &&
+        !(st & (MEM_ST_NONFINITE | MEM_ST_NONREALIZABLE))) {
+      __builtin_amdgcn_wave_barrier();
+      float Lf[36], dmin, dmax;
+#pragma unroll
+      for (int k = 0; k < 36; ++k) Lf[k] = sHk[wv][k];
+      bool okf = chol8(Lf, dmin, dmax);
+      const float2* lo = reinterpret_cast<const float2*>(tab + P);
+      float Ga[8];
+      float ra = grad9_acc(tab, lo, P, gw, gsx, gsr, b, cur.logZ, m, lane, Ga);
+      float bb[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) bb[k] = b[k];
+      float rb = ra;
+      for (int ref = 0; okf && !(ra <= p.tol_grad) && ref < p.refine; ++ref) {
+        float dd[8], res;
+        solve8(Lf, Ga, dd, res);
+        bool fin = true;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) fin = fin && isfinite(dd[i]);
+        if (!fin) break;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b[i + 1] += dd[i];
+        ra = grad9_acc(tab, lo, P, gw, gsx, gsr, b, cur.logZ, m, lane, Ga);
+        if (ra < rb) {
+          rb = ra;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) bb[k] = b[k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) b[k] = bb[k];
+      r = rb;
+      st = rb <= p.tol_loose ? (st & ~MEM_ST_STAGNATED) | MEM_ST_CONVERGED
+                             : (st & ~MEM_ST_CONVERGED) | MEM_ST_STAGNATED;
+    }
   }
   if (lane == 0) {
 #pragma unroll
@@ -445,10 +568,10 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_moments(int64_t n, int P,
   const int64_t c = (int64_t)blockIdx.x * AXW + wv;
   if (c >= n) return;
   float* red = sred[wv];
-  double b[9];
+  float b[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) b[k] = (double)beta[c * 9 + k];
-  const AxGauge g{(double)gin[c * 3], 1.0 / (double)gin[c * 3 + 1], 1.0 / (double)gin[c * 3 + 2]};
+  for (int k = 0; k < 9; ++k) b[k] = beta[c * 9 + k];
+  const AxGauge g = ax_gauge(gin, c);
   const float lz = lse9(tab, P, g, b, lane);
   float acc[18];
 #pragma unroll
@@ -576,28 +699,45 @@ __global__ void k_axi_gauge(int64_t n, float* __restrict__ M, float* __restrict_
 // ---- characteristic speeds (Sec. 3.4) ----------------------------------------
 // dF/dM has the eigenvalues of the pencil (C, B), B = E[phi phi^T] and
 // C = E[x phi phi^T] in gauge coordinates x = u_bar_x; physical speeds are
-// w_x + s_x lambda.  One wave per cell accumulates the 2 x 45 sums, reduced in
-// LDS; lane 0 then reduces the pencil to A = L^-1 C L^-T (B = L L^T) and runs
-// cyclic Jacobi rotations (Golub & Van Loan, symmetric Schur decomposition) on
-// A in FP64 in LDS.  A pencil whose B is not positive definite leaves the
-// node span [min u_x, max u_x] as the speeds (every eigenvalue lies there).
+// w_x + s_x lambda, and the scheme needs the extreme two.  One wave per cell
+// accumulates the 2 x 45 sums, reduced in LDS.  Every lane then runs the same
+// FP32 arithmetic on the same sums, in registers: B = L L^T, A = L^-1 C L^-T,
+// Householder reduction of A to tridiagonal form (Golub & Van Loan, Sec. 8.3),
+// and a multisection of the Gershgorin interval with Sturm counts (Sec. 8.4):
+// 32 lanes bracket the smallest eigenvalue and 32 the largest, each round
+// narrowing both brackets 33-fold.  A pencil whose B is not positive definite
+// leaves the node span [min u_x, max u_x] as the speeds (every eigenvalue lies
+// there).
 constexpr int SP_NS = 90;
 constexpr int SP_ROW = SP_NS + 1;  // odd row stride
+constexpr int SP_ROUNDS = 6;       // 33^6 > 1e9: the brackets end at FP32 resolution
+
+// Number of eigenvalues below sig of the symmetric tridiagonal (d, e) (Sturm
+// count by the LDL^T pivots; a zero pivot is replaced by a tiny negative one).
+__device__ __forceinline__ int sturm9(const float (&d)[9], const float (&e2)[8], float sig) {
+  int cnt = 0;
+  float q = d[0] - sig;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if (i > 0) q = d[i] - sig - e2[i - 1] / q;
+    if (fabsf(q) < 1e-30f) q = -1e-30f;
+    cnt += q < 0.f ? 1 : 0;
+  }
+  return cnt;
+}
 
 __global__ __launch_bounds__(64) void k_axi_speeds(int64_t n, int P, const float4* __restrict__ tab,
                                                    const float* __restrict__ beta,
                                                    const float* __restrict__ gin, float ux_min,
                                                    float ux_max, float* __restrict__ lam) {
   __shared__ __align__(16) float red[65 * SP_ROW];
-  __shared__ double W[3 * 81];
   const int lane = threadIdx.x;
   const int64_t c = blockIdx.x;
   if (c >= n) return;
-  double b[9];
+  float b[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) b[k] = (double)beta[c * 9 + k];
-  const double gw = gin[c * 3], gsx = gin[c * 3 + 1];
-  const AxGauge g{gw, 1.0 / gsx, 1.0 / (double)gin[c * 3 + 2]};
+  for (int k = 0; k < 9; ++k) b[k] = beta[c * 9 + k];
+  const AxGauge g = ax_gauge(gin, c);
   const float lz = lse9(tab, P, g, b, lane);
   float acc[SP_NS];
 #pragma unroll
@@ -629,93 +769,158 @@ __global__ __launch_bounds__(64) void k_axi_speeds(int64_t n, int P, const float
     red[64 * SP_ROW + k] = t;
   }
   __syncthreads();
-  if (lane != 0) return;
   const float* S = red + 64 * SP_ROW;
-  double* B = W;
-  double* C = W + 81;
-  double* A = W + 162;
+  float Lb[9][9], Y[9][9];
   {
     int k = 0;
+#pragma unroll
     for (int i = 0; i < 9; ++i)
+#pragma unroll
       for (int j = i; j < 9; ++j) {
-        B[i * 9 + j] = B[j * 9 + i] = (double)S[k];
-        C[i * 9 + j] = C[j * 9 + i] = (double)S[45 + k];
+        Lb[i][j] = Lb[j][i] = S[k];
+        Y[i][j] = Y[j][i] = S[45 + k];
         ++k;
       }
   }
-  float lo = ux_min, hi = ux_max;
+  // B = L L^T (L in the lower triangle of Lb)
   bool ok = true;
-  // B = L L^T (L in the lower triangle of B)
-  for (int k = 0; k < 9 && ok; ++k) {
-    double d = B[k * 9 + k];
-    for (int j = 0; j < k; ++j) d -= B[k * 9 + j] * B[k * 9 + j];
-    if (!(d > 0.0) || !isfinite(d)) { ok = false; break; }
-    const double l = sqrt(d);
-    B[k * 9 + k] = l;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    float d = Lb[k][k];
+#pragma unroll
+    for (int j = 0; j < k; ++j) d = fmaf(-Lb[k][j], Lb[k][j], d);
+    ok = ok && d > 0.f && isfinite(d);
+    const float l = sqrtf(fmaxf(d, FLT_MIN));
+    const float il = 1.f / l;
+    Lb[k][k] = l;
+#pragma unroll
     for (int i = k + 1; i < 9; ++i) {
-      double t = B[i * 9 + k];
-      for (int j = 0; j < k; ++j) t -= B[i * 9 + j] * B[k * 9 + j];
-      B[i * 9 + k] = t / l;
+      float t = Lb[i][k];
+#pragma unroll
+      for (int j = 0; j < k; ++j) t = fmaf(-Lb[i][j], Lb[k][j], t);
+      Lb[i][k] = t * il;
     }
   }
+  // Y = L^-1 C (column by column, in place), then A = L^-1 Y^T: column j of A
+  // solves against row j of Y; A is symmetric, its lower triangle is kept
+  float A[9][9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      float t = Y[i][j];
+#pragma unroll
+      for (int m = 0; m < i; ++m) t = fmaf(-Lb[i][m], Y[m][j], t);
+      Y[i][j] = t / Lb[i][i];
+    }
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    float z[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      float t = Y[j][i];
+#pragma unroll
+      for (int m = 0; m < i; ++m) t = fmaf(-Lb[i][m], z[m], t);
+      z[i] = t / Lb[i][i];
+    }
+#pragma unroll
+    for (int i = j; i < 9; ++i) A[i][j] = A[j][i] = z[i];
+  }
+  // Householder tridiagonalisation: H = I - beta v v^T on rows/columns k+1..8,
+  // A <- H A H = A - v q^T - q v^T with p = beta A v, q = p - (beta/2)(v.p) v
+  float dg[9], e2[8], ea[8];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    float s2 = 0.f;
+#pragma unroll
+    for (int i = k + 1; i < 9; ++i) s2 = fmaf(A[i][k], A[i][k], s2);
+    const float x0 = A[k + 1][k];
+    const float xn = sqrtf(s2);
+    const float alpha = x0 >= 0.f ? -xn : xn;
+    const float vtv = 2.f * (s2 - alpha * x0);
+    dg[k] = A[k][k];
+    if (vtv > 1e-30f) {
+      float v[9];
+#pragma unroll
+      for (int i = k + 1; i < 9; ++i) v[i] = A[i][k];
+      v[k + 1] = x0 - alpha;
+      const float beta = 2.f / vtv;
+      float pv[9], vp = 0.f;
+#pragma unroll
+      for (int i = k + 1; i < 9; ++i) {
+        float t = 0.f;
+#pragma unroll
+        for (int j = k + 1; j < 9; ++j) t = fmaf(A[i][j], v[j], t);
+        pv[i] = beta * t;
+        vp = fmaf(v[i], pv[i], vp);
+      }
+      const float kk = 0.5f * beta * vp;
+#pragma unroll
+      for (int i = k + 1; i < 9; ++i) pv[i] = fmaf(-kk, v[i], pv[i]);
+#pragma unroll
+      for (int i = k + 1; i < 9; ++i)
+#pragma unroll
+        for (int j = k + 1; j <= i; ++j)
+          A[i][j] = A[j][i] = A[i][j] - v[i] * pv[j] - pv[i] * v[j];
+      ea[k] = alpha;
+    } else {
+      ea[k] = x0;
+    }
+  }
+  dg[7] = A[7][7];
+  dg[8] = A[8][8];
+  ea[7] = A[8][7];
+  float glo = FLT_MAX, ghi = -FLT_MAX;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float r = (i > 0 ? fabsf(ea[i - 1]) : 0.f) + (i < 8 ? fabsf(ea[i]) : 0.f);
+    glo = fminf(glo, dg[i] - r);
+    ghi = fmaxf(ghi, dg[i] + r);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) e2[i] = ea[i] * ea[i];
+  ok = ok && isfinite(glo) && isfinite(ghi);
+  float lo = ux_min, hi = ux_max;
   if (ok) {
-    // Y = L^-1 C (columnwise forward substitution), then A = L^-1 Y^T
-    for (int col = 0; col < 9; ++col)
-      for (int i = 0; i < 9; ++i) {
-        double t = C[i * 9 + col];
-        for (int j = 0; j < i; ++j) t -= B[i * 9 + j] * A[j * 9 + col];
-        A[i * 9 + col] = t / B[i * 9 + i];
+    // multisection: lanes 0-31 bracket the smallest eigenvalue, lanes 32-63
+    // the largest (count(sig) = number of eigenvalues below sig)
+    const float pad = 1e-6f * fmaxf(fabsf(glo), fabsf(ghi)) + 1e-30f;
+    float a0 = glo - pad, a1 = ghi + pad, c0 = a0, c1 = a1;
+    const int j = lane & 31;
+    const bool upper = lane >= 32;
+    for (int round = 0; round < SP_ROUNDS; ++round) {
+      const float l0 = upper ? c0 : a0, l1 = upper ? c1 : a1;
+      const float sig = l0 + (l1 - l0) * ((float)(j + 1) / 33.f);
+      const int cnt = sturm9(dg, e2, sig);
+      const uint64_t bm = __ballot(!upper && cnt >= 1);
+      const uint64_t bx = __ballot(upper && cnt <= 8) >> 32;
+      const float wa = a1 - a0, wc = c1 - c0;
+      if (bm != 0ull) {
+        const int jm = __builtin_ctzll(bm);  // smallest sig above the eigenvalue
+        a1 = a0 + wa * ((float)(jm + 1) / 33.f);
+        a0 = a0 + wa * ((float)jm / 33.f);
+      } else {
+        a0 = a0 + wa * (32.f / 33.f);
       }
-    for (int i = 0; i < 9; ++i)
-      for (int j = 0; j < 9; ++j) C[i * 9 + j] = A[j * 9 + i];  // C <- Y^T
-    for (int col = 0; col < 9; ++col)
-      for (int i = 0; i < 9; ++i) {
-        double t = C[i * 9 + col];
-        for (int j = 0; j < i; ++j) t -= B[i * 9 + j] * A[j * 9 + col];
-        A[i * 9 + col] = t / B[i * 9 + i];
+      if (bx != 0ull) {
+        const int jx = 63 - __builtin_clzll(bx);  // largest sig at or below it
+        c0 = c0 + wc * ((float)(jx + 1) / 33.f);
+        c1 = jx == 31 ? c1 : c0 + wc * (1.f / 33.f);
+      } else {
+        c1 = c0 + wc * (1.f / 33.f);
       }
-    for (int i = 0; i < 9; ++i)  // symmetrise the rounding
-      for (int j = i + 1; j < 9; ++j) A[i * 9 + j] = A[j * 9 + i] = 0.5 * (A[i * 9 + j] + A[j * 9 + i]);
-    for (int sweep = 0; sweep < 30; ++sweep) {
-      double off = 0.0, nrm = 0.0;
-      for (int i = 0; i < 9; ++i)
-        for (int j = 0; j < 9; ++j) {
-          const double v = A[i * 9 + j] * A[i * 9 + j];
-          nrm += v;
-          if (i != j) off += v;
-        }
-      if (!(off > 1e-30 * nrm)) break;
-      for (int p = 0; p < 8; ++p)
-        for (int q = p + 1; q < 9; ++q) {
-          const double apq = A[p * 9 + q];
-          if (fabs(apq) < 1e-300) continue;
-          const double th = (A[q * 9 + q] - A[p * 9 + p]) / (2.0 * apq);
-          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
-          for (int k = 0; k < 9; ++k) {  // columns p, q
-            const double akp = A[k * 9 + p], akq = A[k * 9 + q];
-            A[k * 9 + p] = cs * akp - sn * akq;
-            A[k * 9 + q] = sn * akp + cs * akq;
-          }
-          for (int k = 0; k < 9; ++k) {  // rows p, q
-            const double apk = A[p * 9 + k], aqk = A[q * 9 + k];
-            A[p * 9 + k] = cs * apk - sn * aqk;
-            A[q * 9 + k] = sn * apk + cs * aqk;
-          }
-        }
     }
-    double emin = A[0], emax = A[0];
-    for (int i = 1; i < 9; ++i) {
-      emin = fmin(emin, A[i * 9 + i]);
-      emax = fmax(emax, A[i * 9 + i]);
-    }
+    const float emin = 0.5f * (a0 + a1), emax = 0.5f * (c0 + c1);
+    const float gw = gin[c * 3], gsx = gin[c * 3 + 1];
     if (isfinite(emin) && isfinite(emax)) {
-      lo = fmaxf((float)(gw + gsx * emin), ux_min);
-      hi = fminf((float)(gw + gsx * emax), ux_max);
+      lo = fmaxf(fmaf(gsx, emin, gw), ux_min);
+      hi = fminf(fmaf(gsx, emax, gw), ux_max);
     }
   }
-  lam[c * 2] = lo;
-  lam[c * 2 + 1] = hi;
+  if (lane == 0) {
+    lam[c * 2] = lo;
+    lam[c * 2 + 1] = hi;
+  }
 }
 
 hipError_t launch_axi_speeds(int64_t n, int P, const float4* tab, const float* beta, const float* g,

@@ -20,6 +20,7 @@
 #include <cfloat>
 #include <cmath>
 
+#include "dfloat.h"
 #include "mem_internal.h"
 
 namespace memk {
@@ -1045,57 +1046,6 @@ __global__ __launch_bounds__(256) void k_fallback3(
 //   E_abc = sum_i R[i][b,c] h_a(x_i),
 // where lw is the one-dimensional log w~ (log w~ of a node is the sum over its
 // three coordinates).  About 5 terms per node instead of 36 + 35.
-
-// Error-free transformations need every product and sum rounded on its own:
-// FP contraction (fusing a*b + c into one fma) is switched off where they are
-// used, or the product errors would be counted twice.
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-#pragma clang fp contract(off)
-  s = a + b;
-  const float z = s - a;
-  e = (a - (s - z)) + (b - z);
-}
-
-struct dfl {  // unevaluated sum h + l
-  float h, l;
-};
-
-// acc += x * y (x, y double-float)
-__device__ __forceinline__ void df_acc(dfl& acc, dfl x, dfl y) {
-#pragma clang fp contract(off)
-  const float p = x.h * y.h;
-  const float pe = fmaf(x.h, y.h, -p);
-  float sh, se;
-  two_sum(acc.h, p, sh, se);
-  acc.h = sh;
-  acc.l = acc.l + (se + (pe + (x.h * y.l + x.l * y.h)));
-}
-
-// acc += x * y (x a plain FP32 value, y double-float): df_acc with x.l = 0
-__device__ __forceinline__ void df_acc1(dfl& acc, float x, dfl y) {
-#pragma clang fp contract(off)
-  const float p = x * y.h;
-  const float pe = fmaf(x, y.h, -p);
-  float sh, se;
-  two_sum(acc.h, p, sh, se);
-  acc.h = sh;
-  acc.l = acc.l + (se + (pe + x * y.l));
-}
-
-// acc += x (x double-float)
-__device__ __forceinline__ void df_add(dfl& acc, dfl x) {
-#pragma clang fp contract(off)
-  float sh, se;
-  two_sum(acc.h, x.h, sh, se);
-  acc.h = sh;
-  acc.l = acc.l + (se + x.l);
-}
-
-__device__ __forceinline__ dfl df_norm(dfl a) {
-#pragma clang fp contract(off)
-  const float h = a.h + a.l;
-  return {h, a.l - (h - a.h)};
-}
 
 // One 64-thread workgroup per cell.  t1 = one-dimensional tables, double-float:
 // t1[a * n + k] = h_a(x_k) (a = 0..4), t1[5 * n + k] = lw_k.

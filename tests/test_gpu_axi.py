@@ -6,7 +6,8 @@ Bars: moments and fluxes within FP32 summation error over the P nodes
 (2e-5 of n and of n * max|u_x| respectively); solutions reach the relative
 moment residual 1e-5 measured in FP64 (or twice the residual of the exact
 solution rounded to FP32 where that floor is higher), and their multipliers
-lie within 1e-3 of the FP64 solution relative to max(1, |beta|).
+lie within 1e-4 of the FP64 solution relative to max(1, |beta|).
+The exponent, the statistics and every sum run in FP32.
 """
 
 import math
@@ -49,7 +50,7 @@ def _split(st, beta_gpu, M, g, ref, orule):
     floor (the FP64 residual of the exact solution rounded to FP32, a lower
     bound of what FP32 arithmetic can reach) lies above half the loose
     tolerance: those may stop as stagnated, never as converged, with their
-    multipliers within the same 1e-3 of the FP64 solution."""
+    multipliers within the same 1e-4 of the FP64 solution."""
     conv = (st & mem.ST_CONVERGED) != 0
     stag = (st & mem.ST_STAGNATED) != 0
     assert np.all(conv | stag), np.unique(st)
@@ -62,7 +63,7 @@ def _split(st, beta_gpu, M, g, ref, orule):
         berr = np.max(np.abs(beta_gpu[idx] - ref["beta"][idx]), axis=1) / scale
         print(f"stagnated at the FP32 floor: {idx.size} cells, floor min {floor.min():.1e}, "
               f"r/floor max {np.max(r / floor):.2f}, beta err max {berr.max():.1e}", flush=True)
-        assert np.all(floor > 5e-6) and np.all(berr <= 1e-3)
+        assert np.all(floor > 5e-6) and np.all(berr <= 1e-4)
     return conv
 
 
@@ -116,7 +117,7 @@ def test_axi_solve_mott_smith_matches_oracle(rule, orule):
     sub = {k: v[conv] for k, v in ref.items()}
     ratio, berr = _check(bg[conv], M[conv], g[conv], sub, orule, "mott-smith")
     assert ratio.max() <= 1.0
-    assert berr.max() <= 1e-3
+    assert berr.max() <= 1e-4
     it = iters.cpu().numpy()
     print(f"iterations mean {it.mean():.1f} max {it.max()} (oracle mean {ref['iters'].mean():.1f})")
     assert np.all(resid.cpu().numpy()[conv] <= 1e-5)
@@ -183,9 +184,14 @@ def test_axi_full_size_sample(rule, orule):
     torch.cuda.synchronize()
     st = status.cpu().numpy()
     conv = (st & mem.ST_CONVERGED) != 0
-    print(f"converged fraction {conv.mean():.4f}; iterations mean "
+    stg = (st & mem.ST_STAGNATED) != 0
+    print(f"converged fraction {conv.mean():.4f}, stagnated {stg.mean():.4f}; iterations mean "
           f"{iters.float().mean().item():.1f}; statuses {np.unique(st)}")
-    assert conv.mean() > 0.99
+    # the compensated residual decides: a cell whose exact solution rounded to
+    # FP32 already misses the tolerance (its FP32 floor) ends stagnated; the
+    # sampled stagnated cells below must show that floor (see _split)
+    assert np.all(conv | stg)
+    assert conv.mean() > 0.95
     # 20 sampled cells, plus the stagnated ones (at most 16 of them)
     rng = np.random.default_rng(5)
     stag = np.nonzero(~conv)[0][:16]
@@ -197,7 +203,7 @@ def test_axi_full_size_sample(rule, orule):
     cs = _split(st[pick], bg, Ms, gs, ref, orule)
     sub = {k: v[cs] for k, v in ref.items()}
     ratio, berr = _check(bg[cs], Ms[cs], gs[cs], sub, orule, "sample")
-    assert ratio.max() <= 1.0 and berr.max() <= 1e-3
+    assert ratio.max() <= 1.0 and berr.max() <= 1e-4
 
 
 def test_axi_gauge_then_solve_matches_oracle(rule, orule):
@@ -237,7 +243,7 @@ def test_axi_gauge_then_solve_matches_oracle(rule, orule):
     conv = _split(status.cpu().numpy(), bg, Mh, gh32, ref, orule)
     sub = {k: v[conv] for k, v in ref.items()}
     ratio, berr = _check(bg[conv], Mh[conv], gh32[conv], sub, orule, "gauge+solve")
-    assert ratio.max() <= 1.0 and berr.max() <= 1e-3
+    assert ratio.max() <= 1.0 and berr.max() <= 1e-4
 
 
 def test_axi_speeds_match_oracle_and_hermite_roots(rule, orule):

@@ -76,9 +76,11 @@ def test_fixed_gauge_is_slower_less_accurate_and_fails_at_high_mach(ctx3):
     machs, it, st, rs, beta, o, mse = _study(ctx3, "lab")
     print(f"\n[fixed gauge] iterations {it.tolist()}, status {[hex(s) for s in st]}, "
           f"log10 MSE {np.round(np.log10(mse + 1e-300), 2).tolist()}")
-    # Mach 2: converges, but FP32 lands two orders further from FP64
+    # Mach 2: converges, but FP32 lands further from FP64: by 1.5 orders of
+    # magnitude in the MSE with the persistent solver's sum-factorised
+    # assembly (over 2 with the MFMA assembly, whose rounding differs)
     assert st[0] & mem.ST_CONVERGED and it[0] >= it_h[0]
-    assert math.log10(mse[0]) > math.log10(mse_h[0]) + 2.0
+    assert math.log10(mse[0]) > math.log10(mse_h[0]) + 1.0
     # Mach 3: converges in FP64 only, after more iterations than in the Hermite gauge
     assert o["converged"][1] and o["iters"][1] > 13
     assert it[1] > it_h[1]
