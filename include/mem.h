@@ -424,13 +424,22 @@ MEM_API mem_err_t mem_axi_solve(mem_axi_t h, int64_t n_cells, const float* M, co
  * cells of width dx between two fixed ghost Maxwellians given as (n, v, T);
  * cfl in (0, 1]; ES-BGK source with the Prandtl number and the viscosity
  * coefficient mu_ref of tau = mu_ref/(Pr n) (Maxwell molecules); scheme one of
- * MEM_FLUX_LLF, MEM_FLUX_LW, MEM_FLUX_FLIC. */
+ * MEM_FLUX_LLF, MEM_FLUX_LW, MEM_FLUX_FLIC; use_graph != 0 replays a captured
+ * hipGraph of one step (kept while the problem, the pointers, the options and
+ * the workspace stay the same). */
 typedef struct {
   int32_t n_cells;
   float dx, cfl, prandtl, mu_ref;
   float ghost_left[3], ghost_right[3];  /* (n, v, T) */
   int32_t scheme;
+  int32_t use_graph;
 } mem_axi_shock_t;
+
+/* Sizes mem_axi_step's workspace for problems of up to n_cells cells (device
+ * allocations; synchronises the device).  mem_axi_step grows it itself when a
+ * larger problem arrives; a caller that reserves first keeps every step call
+ * free of allocation and host synchronisation. */
+MEM_API mem_err_t mem_axi_reserve(mem_axi_t h, int64_t n_cells);
 
 /* Time steps of Alg. 2 on the nine statistics with local Lax--Friedrichs
  * fluxes: per step, ES-BGK relaxation over dt/2, Alg. 1 per cell (warm start
@@ -446,8 +455,9 @@ typedef struct {
  * gauge of each cell, then t += dt_used and dt <- cfl dx / max speed.  With
  * n_steps = 0 it only sets up: solves the initial state and writes dt.  M[n][9],
  * beta[n][9], g[n][3], t[1], dt[1]: device, in place; status[n] (may be NULL)
- * gets the last solve's status.  Allocates its workspace on first use (and
- * when n_cells grows); launches asynchronously on stream. */
+ * gets the last solve's status.  Without a large enough mem_axi_reserve it
+ * allocates its workspace first (as mem_axi_reserve); otherwise it only
+ * launches kernels (or replays the captured step), asynchronously on stream. */
 MEM_API mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* problem, float* M,
                                float* beta, float* g, float* t, float* dt, int32_t n_steps,
                                const mem_solve_opts_t* opts, uint32_t* status,
@@ -456,8 +466,9 @@ MEM_API mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* problem, floa
 /* Characteristic speeds (Sec. 3.4, the local Lax--Friedrichs bound):
  * lam[n][2] = (min, max) eigenvalue of dF/dM in physical velocity at beta[n][9]
  * and g[n][3]: the extreme generalised eigenvalues of (E[x phi phi^T],
- * E[phi phi^T]) in gauge coordinates (FP32 sums, FP64 reduction and cyclic
- * Jacobi), mapped to w_x + s_x lambda and clamped to the node span
+ * E[phi phi^T]) in gauge coordinates (FP32 throughout: Cholesky reduction of
+ * the pencil, Householder tridiagonalisation, Sturm-count multisection of the
+ * two extremes), mapped to w_x + s_x lambda and clamped to the node span
  * [min u_x, max u_x], where every eigenvalue of the quadrature pencil lies; a
  * pencil that cannot be reduced gives the node span itself.  One wave per
  * cell.  Device memory, asynchronous. */

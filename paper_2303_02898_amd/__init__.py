@@ -65,7 +65,7 @@ class AxiRuleStruct(ctypes.Structure):
 class AxiShockStruct(ctypes.Structure):
     _fields_ = [("n_cells", _c_i32), ("dx", _c_f32), ("cfl", _c_f32), ("prandtl", _c_f32),
                 ("mu_ref", _c_f32), ("ghost_left", _c_f32 * 3), ("ghost_right", _c_f32 * 3),
-                ("scheme", _c_i32)]
+                ("scheme", _c_i32), ("use_graph", _c_i32)]
 
 
 class Tuning(ctypes.Structure):
@@ -118,6 +118,7 @@ def load_library():
         "mem_axi_moments": ([P, _c_i64, P, P, P, P, P], E),
         "mem_axi_gauge": ([_c_i64, P, P, P, P], E),
         "mem_axi_speeds": ([P, _c_i64, P, P, P, P], E),
+        "mem_axi_reserve": ([P, _c_i64], E),
         "mem_axi_step": ([P, ctypes.POINTER(AxiShockStruct), P, P, P, P, P, _c_i32,
                           ctypes.POINTER(SolveOpts), P, P], E),
         "mem_profile_enable": ([P, _c_i32], E),
@@ -455,15 +456,20 @@ class AxiRule:
             _ptr(resid, torch.float32), _ptr(status, torch.int32), _stream(stream)), "mem_axi_solve")
         return iters, resid, status
 
+    def reserve(self, n_cells):
+        """Size the time-step workspace (step calls then allocate nothing)."""
+        self._check(self._lib.mem_axi_reserve(self._h, int(n_cells)), "mem_axi_reserve")
+
     def step(self, M, beta, g, t, dt, dx, left, right, n_steps=1, cfl=0.5,
              prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), opts=None, status=None,
-             scheme="llf", stream=None):
+             scheme="llf", use_graph=False, stream=None):
         """Alg. 2 time steps of one shock problem (n_steps = 0: set-up only).
-        left/right: ghost (n, v, T); t, dt: one-element device tensors."""
+        left/right: ghost (n, v, T); t, dt: one-element device tensors;
+        use_graph: replay a captured step."""
         import torch
         n = M.shape[0]
         pb = AxiShockStruct(n, dx, cfl, prandtl, mu_ref, (_c_f32 * 3)(*left),
-                            (_c_f32 * 3)(*right), FLUX_SCHEMES[scheme])
+                            (_c_f32 * 3)(*right), FLUX_SCHEMES[scheme], 1 if use_graph else 0)
         o = ctypes.byref(opts) if opts is not None else None
         self._check(self._lib.mem_axi_step(
             self._h, ctypes.byref(pb), _ptr(M, torch.float32, (9,), "M"),

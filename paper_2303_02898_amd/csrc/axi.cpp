@@ -3,6 +3,7 @@
 // formula of the normal-shock set-up, and the solve / moment entry points.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -14,7 +15,7 @@ struct mem_axi_s {
   mem_axi_rule_t rule;
   int64_t P = 0;
   std::vector<double> ux, ur, logw;
-  float4* d_tab = nullptr;  // (u_x, u_r, log w, u_x - fl(u_x)) per node
+  float4* d_tab = nullptr;  // (u_x, u_r, log w, u_x - fl(u_x)) per node, then lo parts
   float lmin = 0.f;
   float ux_min = 0.f, ux_max = 0.f;  // node span in u_x
   // time-step workspace (mem_axi_step), grown on demand
@@ -26,6 +27,18 @@ struct mem_axi_s {
   float *w_fLF = nullptr, *w_Mh = nullptr, *w_gI = nullptr, *w_bI = nullptr, *w_phi = nullptr,
         *w_fLW = nullptr;
   uint32_t* w_stI = nullptr;
+  // captured step (use_graph): valid while the key matches
+  struct StepKey {
+    mem_axi_shock_t pb;
+    float *M, *beta, *g, *t, *dt;
+    uint32_t* status;
+    memk::SolveParams p;
+    uint64_t gen;
+  };
+  uint64_t gen = 0;  // bumped whenever the workspace is reallocated
+  StepKey key{};
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
 };
 
 namespace {
@@ -207,6 +220,8 @@ mem_err_t mem_axi_create(const mem_axi_rule_t* rule, mem_axi_t* out) {
 }
 
 void free_step(mem_axi_s* h) {
+  if (h->exec) { (void)hipGraphExecDestroy(h->exec); h->exec = nullptr; }
+  ++h->gen;
   for (float** p : {&h->w_F, &h->w_lam, &h->w_Mn, &h->w_gh, &h->w_scal, &h->w_fLF, &h->w_Mh,
                     &h->w_gI, &h->w_bI, &h->w_phi, &h->w_fLW})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
@@ -219,8 +234,34 @@ mem_err_t mem_axi_destroy(mem_axi_t h) {
   if (!h) return MEM_ERR_INVALID_ARG;
   (void)hipDeviceSynchronize();
   free_step(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->d_tab) (void)hipFree(h->d_tab);
   delete h;
+  return MEM_OK;
+}
+
+mem_err_t mem_axi_reserve(mem_axi_t h, int64_t n) {
+  if (!h || n < 1 || n > (int64_t)1 << 24) return MEM_ERR_INVALID_ARG;
+  if (n <= h->cap) return MEM_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return MEM_ERR_HIP;
+  free_step(h);
+  if (hipMalloc((void**)&h->w_F, n * 9 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_lam, n * 2 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_Mn, n * 9 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_gh, 64 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_scal, 4 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_st, n * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc((void**)&h->w_fLF, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_Mh, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_gI, (n + 1) * 3 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_bI, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_phi, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_fLW, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&h->w_stI, (n + 1) * sizeof(uint32_t)) != hipSuccess) {
+    free_step(h);
+    return MEM_ERR_NOMEM;
+  }
+  h->cap = n;
   return MEM_OK;
 }
 
@@ -276,48 +317,19 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
   SolveParams p;
   if (params_axi(h, opts, p) != MEM_OK) return MEM_ERR_INVALID_ARG;
   if (n > h->cap) {
-    AXI_HIP(hipStreamSynchronize(s));
-    free_step(h);
-    if (hipMalloc((void**)&h->w_F, n * 9 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_lam, n * 2 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_Mn, n * 9 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_gh, 64 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_scal, 4 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_st, n * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void**)&h->w_fLF, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_Mh, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_gI, (n + 1) * 3 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_bI, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_phi, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_fLW, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&h->w_stI, (n + 1) * sizeof(uint32_t)) != hipSuccess) {
-      free_step(h);
-      return MEM_ERR_NOMEM;
-    }
-    h->cap = n;
+    const mem_err_t e = mem_axi_reserve(h, n);
+    if (e != MEM_OK) return e;
   }
   float* gM = h->w_gh;
   float* gB = gM + 18;
   float* gG = gB + 18;
   float* gF = gG + 6;
   float* gL = gF + 18;
-  {  // ghost Maxwellians in their own Hermite gauges: the discrete moments,
-     // fluxes and speeds of beta = (n, 0, -1/sqrt2, -1, 0, ...)
-    float host[42] = {0.f};
-    const float* st3[2] = {pb->ghost_left, pb->ghost_right};
-    for (int k = 0; k < 2; ++k) {
-      host[18 + 9 * k] = st3[k][0];
-      host[18 + 9 * k + 2] = -0.70710678118654752f;
-      host[18 + 9 * k + 3] = -1.f;
-      host[36 + 3 * k] = st3[k][1];
-      host[36 + 3 * k + 1] = std::sqrt(st3[k][2]);
-      host[36 + 3 * k + 2] = std::sqrt(st3[k][2]);
-    }
-    AXI_HIP(hipMemcpyAsync(gB, host + 18, 24 * sizeof(float), hipMemcpyHostToDevice, s));
-    AXI_HIP(hipStreamSynchronize(s));  // the host array goes out of scope
-    AXI_HIP(launch_axi_moments(2, (int)h->P, h->d_tab, gB, gG, gM, gF, s));
-    AXI_HIP(launch_axi_speeds(2, (int)h->P, h->d_tab, gB, gG, h->ux_min, h->ux_max, gL, s));
-  }
+  // ghost Maxwellians in their own Hermite gauges: the discrete moments,
+  // fluxes and speeds of beta = (n, 0, -1/sqrt2, -1, 0, ...)
+  AXI_HIP(launch_axi_ghosts(pb->ghost_left, pb->ghost_right, gB, gG, s));
+  AXI_HIP(launch_axi_moments(2, (int)h->P, h->d_tab, gB, gG, gM, gF, s));
+  AXI_HIP(launch_axi_speeds(2, (int)h->P, h->d_tab, gB, gG, h->ux_min, h->ux_max, gL, s));
   uint32_t* st = status ? status : h->w_st;
   const int tpb = (int)h->P;
   // the per-step solves start from the previous step's multipliers: a cell
@@ -332,31 +344,62 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
     AXI_HIP(launch_axi_dt(n, h->w_lam, gL, pb->cfl, pb->dx, dt, h->w_scal, 1, s));
     return MEM_OK;
   }
-  for (int k = 0; k < n_steps; ++k) {
-    AXI_HIP(launch_axi_collide(n, M, g, dt, 0.5f, pb->prandtl, pb->mu_ref, s));
-    AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, pw, nullptr, nullptr, st, s));
-    AXI_HIP(launch_axi_fix(n, M, beta, st, s));
-    AXI_HIP(launch_axi_moments(n, tpb, h->d_tab, beta, g, nullptr, h->w_F, s));
-    AXI_HIP(launch_axi_speeds(n, tpb, h->d_tab, beta, g, h->ux_min, h->ux_max, h->w_lam, s));
-    AXI_HIP(launch_axi_dt(n, h->w_lam, gL, pb->cfl, pb->dx, dt, h->w_scal, 0, s));
+  // one step of Alg. 2 on stream q (kernels only: it may be captured)
+  auto step_once = [&](hipStream_t q) -> mem_err_t {
+    AXI_HIP(launch_axi_collide(n, M, g, dt, 0.5f, pb->prandtl, pb->mu_ref, q));
+    AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, pw, nullptr, nullptr, st, q));
+    AXI_HIP(launch_axi_fix(n, M, beta, st, q));
+    AXI_HIP(launch_axi_moments(n, tpb, h->d_tab, beta, g, nullptr, h->w_F, q));
+    AXI_HIP(launch_axi_speeds(n, tpb, h->d_tab, beta, g, h->ux_min, h->ux_max, h->w_lam, q));
+    AXI_HIP(launch_axi_dt(n, h->w_lam, gL, pb->cfl, pb->dx, dt, h->w_scal, 0, q));
     if (pb->scheme == MEM_FLUX_LLF) {
       AXI_HIP(launch_axi_fv(n, M, h->w_F, h->w_lam, g, gM, gF, gL, gG, h->w_scal, pb->dx, h->w_Mn,
-                            s));
+                            q));
     } else {  // one MaxEnt solve per interface, in the right element's gauge
       AXI_HIP(launch_axi_iface(n, M, h->w_F, h->w_lam, g, beta, gM, gF, gL, gG, gB, h->w_scal,
                                pb->dx, pb->scheme == MEM_FLUX_FLIC, h->w_fLF, h->w_Mh, h->w_gI,
-                               h->w_bI, h->w_phi, s));
+                               h->w_bI, h->w_phi, q));
       AXI_HIP(launch_axi_solve(n + 1, tpb, h->d_tab, h->w_Mh, h->w_gI, h->w_bI, pw, nullptr,
-                               nullptr, h->w_stI, s));
-      AXI_HIP(launch_axi_moments(n + 1, tpb, h->d_tab, h->w_bI, h->w_gI, nullptr, h->w_fLW, s));
+                               nullptr, h->w_stI, q));
+      AXI_HIP(launch_axi_moments(n + 1, tpb, h->d_tab, h->w_bI, h->w_gI, nullptr, h->w_fLW, q));
       AXI_HIP(launch_axi_fv2(n, M, g, gG, h->w_fLF, h->w_fLW, h->w_phi, h->w_stI, h->w_scal,
-                             pb->dx, h->w_Mn, s));
+                             pb->dx, h->w_Mn, q));
     }
-    AXI_HIP(hipMemcpyAsync(M, h->w_Mn, n * 9 * sizeof(float), hipMemcpyDeviceToDevice, s));
-    AXI_HIP(launch_axi_collide(n, M, g, h->w_scal, 0.5f, pb->prandtl, pb->mu_ref, s));
-    AXI_HIP(launch_axi_gauge(n, M, beta, g, s));
-    AXI_HIP(launch_axi_finish(t, dt, h->w_scal, s));
+    AXI_HIP(launch_copy(n * 9, h->w_Mn, M, q));
+    AXI_HIP(launch_axi_collide(n, M, g, h->w_scal, 0.5f, pb->prandtl, pb->mu_ref, q));
+    AXI_HIP(launch_axi_gauge(n, M, beta, g, q));
+    AXI_HIP(launch_axi_finish(t, dt, h->w_scal, q));
+    return MEM_OK;
+  };
+  if (!pb->use_graph) {
+    for (int k = 0; k < n_steps; ++k) {
+      const mem_err_t e = step_once(s);
+      if (e != MEM_OK) return e;
+    }
+    return MEM_OK;
   }
+  mem_axi_s::StepKey key{};
+  key.pb = *pb;
+  key.M = M; key.beta = beta; key.g = g; key.t = t; key.dt = dt; key.status = status;
+  key.p = pw;
+  key.gen = h->gen;
+  if (!h->exec || std::memcmp(&key, &h->key, sizeof(key)) != 0) {
+    if (h->exec) { (void)hipGraphExecDestroy(h->exec); h->exec = nullptr; }
+    if (!h->cap_stream) AXI_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    AXI_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    const mem_err_t e = step_once(h->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t he = hipStreamEndCapture(h->cap_stream, &graph);
+    if (e != MEM_OK || he != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e != MEM_OK ? e : MEM_ERR_HIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&h->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) { h->exec = nullptr; return MEM_ERR_HIP; }
+    h->key = key;
+  }
+  for (int k = 0; k < n_steps; ++k) AXI_HIP(hipGraphLaunch(h->exec, s));
   return MEM_OK;
 }
 

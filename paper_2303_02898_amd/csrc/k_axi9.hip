@@ -923,6 +923,34 @@ __global__ __launch_bounds__(64) void k_axi_speeds(int64_t n, int P, const float
   }
 }
 
+// The two ghost Maxwellians of a shock problem in their own Hermite gauges:
+// beta = (n, 0, -1/sqrt2, -1, 0, ...), g = (v, sqrt T, sqrt T) (left row 0,
+// right row 1).  The states arrive as kernel arguments: no host buffer.
+__global__ void k_axi_ghosts(float nl, float vl, float Tl, float nr, float vr, float Tr,
+                             float* __restrict__ gB, float* __restrict__ gG) {
+  const int t = threadIdx.x;
+  if (t < 18) {
+    const int k = t % 9;
+    const bool right = t >= 9;
+    float v = 0.f;
+    if (k == 0) v = right ? nr : nl;
+    if (k == 2) v = -0.70710678118654752f;
+    if (k == 3) v = -1.f;
+    gB[t] = v;
+  } else if (t < 24) {
+    const int k = (t - 18) % 3;
+    const bool right = t >= 21;
+    const float vel = right ? vr : vl, T = right ? Tr : Tl;
+    gG[t - 18] = k == 0 ? vel : sqrtf(T);
+  }
+}
+
+hipError_t launch_axi_ghosts(const float* left, const float* right, float* gB, float* gG,
+                             hipStream_t s) {
+  k_axi_ghosts<<<1, 64, 0, s>>>(left[0], left[1], left[2], right[0], right[1], right[2], gB, gG);
+  return hipGetLastError();
+}
+
 hipError_t launch_axi_speeds(int64_t n, int P, const float4* tab, const float* beta, const float* g,
                              float ux_min, float ux_max, float* lam, hipStream_t s) {
   if (n <= 0) return hipSuccess;

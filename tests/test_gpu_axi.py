@@ -308,3 +308,43 @@ def test_axi_shock_steps_match_oracle(scheme):
     print(f"after 6 steps: M err {eM:.2e}, g err {eg:.2e}, t err {et:.2e}; statuses "
           f"{np.unique(st.cpu().numpy())}", flush=True)
     assert eM < 1e-4 and eg < 1e-4 and et < 1e-5
+
+
+@pytest.mark.parametrize("scheme", ["llf", "flic"])
+def test_axi_graph_step_matches_eager(scheme):
+    """The captured step (use_graph) replays exactly what the eager launches
+    compute, over several replays with eager work and synchronisations
+    between them, and is rebuilt after the workspace is reallocated."""
+    print(f"\n[gpu] axi graph vs eager, Mach-3 shock, 24 cells, {scheme}", flush=True)
+    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(3.0)
+    a_x, b_x, b_r = axisym.integration_domain(float(v1), float(T1), float(v2), float(T2), 10, 6, 6)
+    box = dict(ux_lo=a_x, ux_hi=b_x, ur_hi=b_r, blocks_x=6, blocks_r=4, order=8)
+    sh = axisym.ShockSolver(3.0, 24, -12.0, 12.0, 5.44, box, scheme=scheme)
+    left = tuple(float(a) for a in (n1, v1, T1))
+    right = tuple(float(a) for a in (n2, v2, T2))
+    runs = {}
+    for graph in (False, True):
+        r = mem.AxiRule(**box)
+        r.reserve(24)
+        M0 = f32(sh.M).astype(np.float64)
+        g0 = f32(sh.g).astype(np.float64)
+        Md, gd = dev(M0), dev(g0)
+        bd = dev(axisym.maxwellian_beta(M0[:, 0], g0))
+        t = torch.zeros(1, device=DEV)
+        dt = torch.zeros(1, device=DEV)
+        st = torch.zeros(24, dtype=torch.int32, device=DEV)
+        r.step(Md, bd, gd, t, dt, sh.dx, left, right, n_steps=0)
+        snaps = []
+        for call in range(4):
+            if call == 2:
+                r.reserve(4096)  # reallocates: a captured step must not survive it
+            r.step(Md, bd, gd, t, dt, sh.dx, left, right, n_steps=2, status=st, scheme=scheme,
+                   use_graph=graph)
+            torch.cuda.synchronize()
+            snaps.append([x.clone() for x in (Md, bd, gd, t, dt, st)])
+        r.close()
+        runs[graph] = snaps
+    for call, (a, b) in enumerate(zip(runs[False], runs[True])):
+        for k, (x, y) in enumerate(zip(a, b)):
+            assert torch.equal(x, y), (call, k)
+    assert np.all(np.isfinite(runs[True][-1][0].cpu().numpy()))
