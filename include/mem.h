@@ -487,6 +487,17 @@ MEM_API mem_err_t mem_axi_speeds(mem_axi_t h, int64_t n_cells, const float* beta
 MEM_API mem_err_t mem_axi_gauge(int64_t n_cells, float* M, float* beta, float* g,
                                 hipStream_t stream);
 
+/* Moments of the non-canonical form of the family, the form the canonical one
+ * replaces (relation alpha_0 = log beta_0 - log Z(beta), alpha_i = beta_i; the
+ * comparison of Sec. 4.1, Fig. 1): M[n][9] with M_j = sum_p w_p
+ * exp(alpha_0 + alpha_i phi_i(u_bar_p)) phi_j(u_bar_p) for alpha[n][9] and
+ * g[n][3], summed in plain FP32 with no shift of the exponent.  Rows whose
+ * exponent exceeds log(FLT_MAX) at some node come out non-finite (that is the
+ * measured outcome, not an error).  One wave per row; device memory,
+ * asynchronous. */
+MEM_API mem_err_t mem_axi_moments_noncanonical(mem_axi_t h, int64_t n_rows, const float* alpha,
+                                               const float* g, float* M, hipStream_t stream);
+
 /* Parameter-to-moment map (Sec. 3.1) and fluxes: M[n][9] = beta_0
  * E_sigma[phi_i], F[n][9] = beta_0 E_sigma[u_x phi_i] with u_x the physical
  * velocity of the node, at beta[n][9] and g[n][3] (E_sigma normalised by

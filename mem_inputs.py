@@ -32,6 +32,10 @@ Workloads (seed = 1000*config + replica):
 6. ``mott_smith_cells9``: the Mott-Smith mixtures of workload 2 on the paper's
    nine statistics of (u_x, u_r), by default at Mach 10 (the paper's Mach-10
    shock; its box ``AXI_MACH10_BOX``).
+7. ``overflow_samples``: parameters drawn around the equilibrium n = 1, v = 0,
+   T = 1 (standard deviation 0.1 in every component) in the canonical and in
+   the non-canonical form of the nine-statistic family, on the box
+   ``E1_BOX`` (the overflow experiment of Sec. 4.1, Fig. 1).
 """
 
 import math
@@ -259,3 +263,32 @@ def mott_smith_cells9(n_cells, mach_lo=10.0, mach_hi=10.0, config=6, replica=0):
     M = ((1.0 - nu)[:, None] * gaussian_moments9(n1, v1, T1, T1, g)
          + nu[:, None] * gaussian_moments9(n2, v2, T2, T2, g))
     return dict(M=M, g=g, mach=mach, nu=nu)
+
+
+# --------------------------------------------------------------------------
+# overflow experiment (Sec. 4.1, Fig. 1): random parameters about equilibrium
+# --------------------------------------------------------------------------
+# Box [-30.7, 37.3] x [0, 34.0], 16 x 16 blocks of 8 x 8 Gauss--Legendre
+# points (16,384 nodes), trivial gauge (0, 1, 1).
+E1_BOX = dict(ux_lo=-30.7, ux_hi=37.3, ur_hi=34.0, blocks_x=16, blocks_r=16, order=8)
+
+
+def overflow_samples(n_samples, sigma=0.1, config=7, replica=0):
+    """Parameters of the nine-statistic family about the equilibrium n = 1,
+    v = 0, T = 1 in the gauge (0, 1, 1).
+
+    The equilibrium density n (2 pi)^(-3/2) exp(-|u|^2 / 2) written with the
+    statistics (He_2(x)/sqrt2 and y - 1 carry -|u|^2/2 up to a constant):
+      canonical      beta  = (n, 0, -1/sqrt2, -1, 0, 0, 0, 0, 0),
+      non-canonical  alpha = (log n - 3/2 (log(2 pi) + 1), 0, -1/sqrt2, -1, 0, ...),
+    alpha_0 being the log of the Maxwellian's normalisation.  Every component
+    of each form gets an independent N(0, sigma^2) draw (separate draws for
+    the two forms)."""
+    rng = np.random.default_rng(seed_for(config, replica))
+    centre_b = np.array([1.0, 0.0, -1.0 / math.sqrt(2.0), -1.0, 0, 0, 0, 0, 0])
+    centre_a = centre_b.copy()
+    centre_a[0] = -1.5 * (math.log(2.0 * math.pi) + 1.0)
+    beta = centre_b + sigma * rng.normal(size=(n_samples, 9))
+    alpha = centre_a + sigma * rng.normal(size=(n_samples, 9))
+    return dict(beta=beta, alpha=alpha, g=np.tile([0.0, 1.0, 1.0], (n_samples, 1)),
+                centre_beta=centre_b, centre_alpha=centre_a)

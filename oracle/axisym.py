@@ -448,3 +448,66 @@ class ShockSolver:
         self.t += dt
         self.dt = self._dt(rho)
         return dt
+
+
+# ---- the two forms of the family and overflow (Sec. 2, the canonical form;
+# Sec. 4.1, Fig. 1) ---------------------------------------------------------------
+# canonical:     f = beta_0 exp(beta_i phi_i - log Z(beta)),
+# non-canonical: f = exp(alpha_0 + alpha_i phi_i), with alpha_0 = log beta_0 -
+# log Z(beta) and alpha_i = beta_i for the same density.
+
+LOG_FLT_MAX = math.log(float(np.finfo(np.float32).max))   # 88.72...
+
+
+def noncanonical_alpha(beta, g, rule):
+    """Non-canonical parameters of the densities given canonically."""
+    beta = np.asarray(beta, dtype=np.float64)
+    alpha = beta.copy()
+    for c in range(beta.shape[0]):
+        lz = maxent.log_partition(beta[c:c + 1], cell_phi(rule, g[c]), rule["logw"])[0]
+        alpha[c, 0] = math.log(beta[c, 0]) - lz
+    return alpha
+
+
+def _noncanonical_exponents(alpha, Phi):
+    """alpha_0 + alpha_i phi_i(u_p), i >= 1: (C, P)."""
+    return alpha[:, :1] + alpha[:, 1:] @ Phi[:, 1:].T
+
+
+def noncanonical_moments(alpha, g, rule):
+    """M_j = sum_p w_p exp(alpha_0 + alpha_i phi_i(u_p)) phi_j(u_p), the plain
+    sum with no shift of the exponent (FP64)."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    out = np.empty((alpha.shape[0], K9))
+    for c in range(alpha.shape[0]):
+        Phi = cell_phi(rule, g[c])
+        e = _noncanonical_exponents(alpha[c:c + 1], Phi)[0] + rule["logw"]
+        out[c] = np.exp(e) @ Phi
+    return out
+
+
+def noncanonical_overflow(alpha, g, rule, margin=1.0):
+    """Whether the FP32 evaluation of the non-canonical moments (exp of each
+    exponent, times w_p, times phi_j, summed) overflows, decided in FP64.
+
+    Returns (certain, safe): certain where some exponent exceeds
+    log(FLT_MAX) + margin (exp itself is infinite there); safe where every
+    exponent and, for every j, log sum_p w_p exp(.) |phi_j| stay below
+    log(FLT_MAX) - margin (no product and no partial sum can reach FLT_MAX).
+    Samples in neither class sit within the margin, where FP32 rounding of the
+    exponent decides."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    C = alpha.shape[0]
+    certain = np.zeros(C, dtype=bool)
+    safe = np.zeros(C, dtype=bool)
+    for c in range(C):
+        Phi = cell_phi(rule, g[c])
+        e = _noncanonical_exponents(alpha[c:c + 1], Phi)[0]
+        emax = e.max()
+        lt = e + rule["logw"]
+        q = lt.max()
+        with np.errstate(divide="ignore"):
+            lsum = q + np.log(np.exp(lt - q) @ np.abs(Phi))   # log sum_p w e |phi_j|
+        certain[c] = emax > LOG_FLT_MAX + margin
+        safe[c] = emax < LOG_FLT_MAX - margin and np.all(lsum < LOG_FLT_MAX - margin)
+    return certain, safe

@@ -116,6 +116,7 @@ def load_library():
         "mem_axi_n_nodes": ([P], _c_i64),
         "mem_axi_solve": ([P, _c_i64, P, P, P, ctypes.POINTER(SolveOpts), P, P, P, P], E),
         "mem_axi_moments": ([P, _c_i64, P, P, P, P, P], E),
+        "mem_axi_moments_noncanonical": ([P, _c_i64, P, P, P, P], E),
         "mem_axi_gauge": ([_c_i64, P, P, P, P], E),
         "mem_axi_speeds": ([P, _c_i64, P, P, P, P], E),
         "mem_axi_reserve": ([P, _c_i64], E),
@@ -496,6 +497,17 @@ class AxiRule:
             n, _ptr(M, torch.float32, (9,), "M"),
             _ptr(beta, torch.float32, (9,), "beta") if beta is not None else None,
             _ptr(g, torch.float32, (3,), "g"), _stream(stream)), "mem_axi_gauge")
+
+    def moments_noncanonical(self, alpha, g, stream=None):
+        """Moments of f = exp(alpha_0 + alpha_i phi_i), plain FP32 sums (no shift)."""
+        import torch
+        n = alpha.shape[0]
+        M = torch.empty(n, 9, dtype=torch.float32, device=alpha.device)
+        self._check(self._lib.mem_axi_moments_noncanonical(
+            self._h, n, _ptr(alpha, torch.float32, (9,), "alpha"),
+            _ptr(g, torch.float32, (3,), "g"), M.data_ptr(), _stream(stream)),
+            "mem_axi_moments_noncanonical")
+        return M
 
     def moments(self, beta, g, want_flux=True, stream=None):
         import torch

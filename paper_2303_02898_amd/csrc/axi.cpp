@@ -410,6 +410,15 @@ mem_err_t mem_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t 
   return launch_axi_gauge(n, M, beta, g, s) == hipSuccess ? MEM_OK : MEM_ERR_HIP;
 }
 
+mem_err_t mem_axi_moments_noncanonical(mem_axi_t h, int64_t n, const float* alpha, const float* g,
+                                       float* M, hipStream_t s) {
+  if (!h || n < 0 || n > (int64_t)INT32_MAX - 4) return MEM_ERR_INVALID_ARG;
+  if (n == 0) return MEM_OK;
+  if (!alpha || !g || !M) return MEM_ERR_INVALID_ARG;
+  return launch_axi_moments_nc(n, (int)h->P, h->d_tab, alpha, g, M, s) == hipSuccess ? MEM_OK
+                                                                                     : MEM_ERR_HIP;
+}
+
 mem_err_t mem_axi_moments(mem_axi_t h, int64_t n, const float* beta, const float* g, float* M,
                           float* F, hipStream_t s) {
   if (!h || n < 0 || n > (int64_t)INT32_MAX - 4) return MEM_ERR_INVALID_ARG;

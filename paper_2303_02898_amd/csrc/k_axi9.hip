@@ -923,6 +923,55 @@ __global__ __launch_bounds__(64) void k_axi_speeds(int64_t n, int P, const float
   }
 }
 
+// Moments of the non-canonical form f = exp(alpha_0 + alpha_i phi_i), the
+// comparison of Sec. 4.1: M_j = sum_p w_p exp(alpha_0 + alpha_i phi_i(u_bar_p))
+// phi_j(u_bar_p) summed in plain FP32 with no shift of the exponent, so that
+// exp overflows wherever the exponent exceeds log(FLT_MAX) -- the failure the
+// canonical form's log-sum-exp removes.  One wave per parameter row.
+__global__ __launch_bounds__(64) void k_axi_moments_nc(int64_t n, int P,
+                                                       const float4* __restrict__ tab,
+                                                       const float* __restrict__ alpha,
+                                                       const float* __restrict__ gin,
+                                                       float* __restrict__ M) {
+  __shared__ float red[65 * 9];
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  if (c >= n) return;
+  float a[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) a[k] = alpha[c * 9 + k];
+  const AxGauge g = ax_gauge(gin, c);
+  float acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.f;
+  for (int q = lane; q < P; q += 64) {
+    const float4 nd = tab[q];
+    float f[9];
+    (void)expo9(nd, g, a, f);
+    float e = a[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) e = fmaf(a[i], f[i], e);
+    const float v = expf(e) * expf(nd.z);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = fmaf(v, f[k], acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) red[lane * 9 + k] = acc[k];
+  __syncthreads();
+  if (lane < 9) {
+    float t = 0.f;
+    for (int l = 0; l < 64; ++l) t += red[l * 9 + lane];
+    M[c * 9 + lane] = t;
+  }
+}
+
+hipError_t launch_axi_moments_nc(int64_t n, int P, const float4* tab, const float* alpha,
+                                 const float* g, float* M, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axi_moments_nc<<<(unsigned)n, 64, 0, s>>>(n, P, tab, alpha, g, M);
+  return hipGetLastError();
+}
+
 // The two ghost Maxwellians of a shock problem in their own Hermite gauges:
 // beta = (n, 0, -1/sqrt2, -1, 0, ...), g = (v, sqrt T, sqrt T) (left row 0,
 // right row 1).  The states arrive as kernel arguments: no host buffer.

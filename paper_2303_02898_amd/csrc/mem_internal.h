@@ -179,6 +179,8 @@ hipError_t launch_axi_fv2(int64_t n, const float* M, const float* g, const float
                           const uint32_t* stI, const float* scal, float dx, float* Mout,
                           hipStream_t s);
 hipError_t launch_axi_finish(float* t, float* dt, const float* scal, hipStream_t s);
+hipError_t launch_axi_moments_nc(int64_t n, int P, const float4* tab, const float* alpha,
+                                 const float* g, float* M, hipStream_t s);
 hipError_t launch_axi_ghosts(const float* left, const float* right, float* gB, float* gG,
                              hipStream_t s);
 hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s);

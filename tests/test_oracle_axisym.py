@@ -313,3 +313,67 @@ def test_second_order_interface_fluxes_reduce_to_lf():
     for _ in range(2):
         sh.step()
     assert np.all(np.isfinite(sh.M))
+
+
+# ---- the two forms of the family and overflow (Sec. 2; Sec. 4.1, Fig. 1) ----
+
+@pytest.fixture(scope="module")
+def e1_rule():
+    return axisym.blockwise_rule(**mem_inputs.E1_BOX)
+
+
+def test_noncanonical_form_is_the_same_density(e1_rule):
+    # alpha_0 = log beta_0 - log Z(beta), alpha_i = beta_i gives the same
+    # moments as the canonical form, summed without any shift
+    d = mem_inputs.overflow_samples(6, sigma=0.02, replica=3)
+    beta = d["beta"].copy()
+    beta[:, 5] = -np.abs(beta[:, 5]) - 0.01     # decaying quartic terms: finite sums
+    beta[:, 6] = -np.abs(beta[:, 6]) - 0.01
+    alpha = axisym.noncanonical_alpha(beta, d["g"], e1_rule)
+    assert np.array_equal(alpha[:, 1:], beta[:, 1:])
+    Mn = axisym.noncanonical_moments(alpha, d["g"], e1_rule)
+    Mc = axisym.moments(beta, d["g"], e1_rule)
+    assert np.max(np.abs(Mn - Mc) / beta[:, :1]) < 1e-12
+
+
+def test_equilibrium_alpha_is_the_maxwellian_normalisation(e1_rule):
+    # the non-canonical equilibrium is n (2 pi)^(-3/2) exp(-|u|^2/2): its
+    # alpha_0 is the Maxwellian's normalisation up to the box quadrature error
+    d = mem_inputs.overflow_samples(1)
+    a = axisym.noncanonical_alpha(d["centre_beta"][None], d["g"], e1_rule)
+    assert a[0, 0] == pytest.approx(-1.5 * (math.log(2.0 * math.pi) + 1.0), abs=1e-7)
+    M = axisym.noncanonical_moments(d["centre_alpha"][None], d["g"], e1_rule)
+    assert M[0, 0] == pytest.approx(1.0, abs=1e-7)
+
+
+def test_overflow_classification_by_hand(e1_rule):
+    d = mem_inputs.overflow_samples(1)
+    a = np.tile(d["centre_alpha"], (3, 1))
+    a[1, 5] += 0.1          # u_x^4 coefficient positive
+    a[2, 6] += 0.1          # u_r^4 coefficient positive
+    certain, safe = axisym.noncanonical_overflow(a, d["g"][[0, 0, 0]], e1_rule)
+    assert safe[0] and not certain[0]
+    # row 1: at the node nearest u_x = -30.7, u_r = 0 the exponent is about
+    # alpha_0 - x^2/2 + 0.1 He_4(x)/sqrt24 with x ~ -30.7: far above log(FLT_MAX)
+    x = e1_rule["ux"].min()
+    by_hand = a[1, 0] - 0.5 * x * x + 0.1 * (x ** 4 - 6 * x * x + 3) / math.sqrt(24.0)
+    assert by_hand > 1e4
+    assert certain[1] and not safe[1]
+    # row 2: y = u_r^2/2 ~ 578 at the outer radius, 0.1 (y^2/2 - 2y + 1) ~ 1.7e4
+    assert certain[2] and not safe[2]
+
+
+def test_overflow_free_samples_lie_in_the_third_quadrant(e1_rule):
+    # Fig. 1(b): without the partition function the samples that stay finite
+    # nearly all have both the u_x^4 and u_r^4 coefficients negative (a few
+    # with a slightly positive one outweighed by the other terms); with it none
+    # overflow
+    d = mem_inputs.overflow_samples(256, replica=1)
+    certain, safe = axisym.noncanonical_overflow(d["alpha"], d["g"], e1_rule)
+    third = (d["alpha"][:, 5] < 0.0) & (d["alpha"][:, 6] < 0.0)
+    assert np.mean(third[safe]) >= 0.9
+    assert not np.any(safe & (d["alpha"][:, 5] > 0.01))
+    assert certain.mean() > 0.5
+    # canonical: log-sum-exp moments of every beta sample are finite
+    M = axisym.moments(d["beta"], d["g"], e1_rule)
+    assert np.all(np.isfinite(M))
