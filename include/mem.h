@@ -107,8 +107,11 @@ typedef struct {
   float   alpha_min;        /* alpha <= alpha_min ends the solve as stagnated (1e-6)         */
   float   fp64_pivot_ratio; /* min/max Cholesky pivot below this -> FP64 direction (1e-6);
                                0 disables the FP64 path (pure FP32 Alg. 1)                   */
-  int32_t check_every;      /* mem_maxent_solve polls the live-cell count every this many
-                               iterations (2); 0 = never poll (runs max_iter iterations)     */
+  int32_t check_every;      /* list-compacted Newton loop only (tuning solver 0): poll the
+                               live-cell count every this many passes (2), a stream
+                               synchronisation each; 0 = never poll (max_iter passes).
+                               The persistent solver (solver 1, the default for FP32 on
+                               12-point rules) never synchronises and ignores it.         */
   int32_t refine;           /* residual refinement passes (3): cells that converge, or
                                whose FP32 residual (<= 1e-3) stops halving for 6
                                iterations, get their residual re-evaluated with a
@@ -219,8 +222,11 @@ MEM_API mem_err_t mem_gauge(mem_ctx_t ctx, int64_t n_cells, float* M, float* bet
  * moments M (in each cell's gauge, M[:,0] = n > 0).  beta: in = initial guess
  * (beta[:,0] ignored), out = solution with beta[:,0] = n.  iters, resid
  * (max_{i>=1}|G_i| at the returned beta, FP32) and status are per-cell
- * outputs, each may be NULL.  Synchronises `stream` every check_every
- * iterations to poll the number of live cells. */
+ * outputs, each may be NULL.  With the persistent solver (mem_tuning_t solver
+ * 1) the whole Newton loop is one kernel and the call is fully asynchronous;
+ * with the list-compacted loop (solver 0, or the 16-bit precisions) it
+ * synchronises `stream` every opts->check_every passes to poll the number of
+ * live cells (0 = never). */
 MEM_API mem_err_t mem_maxent_solve(mem_ctx_t ctx, int64_t n_cells, const float* M,
                                    float* beta, const mem_solve_opts_t* opts,
                                    int32_t* iters, float* resid, uint32_t* status,

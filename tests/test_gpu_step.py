@@ -10,9 +10,14 @@
   a few steps from the tanh initial profile, density / velocity / temperature
   compared cell by cell with the oracle's FP64 run; FP64 totals of the GPU
   state conserve mass up to the boundary fluxes.
+* The same shock run as far as the oracle's committed steady state
+  (tests/golden/shock_mach3_steady.json): centred profiles of n, T and q_x
+  within 1e-3.
 """
 
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -657,3 +662,58 @@ def test_strong_shock_stays_finite_and_conservative(ctx3):
     assert np.all(np.isfinite(M)) and np.all(M[:, 0] > 0)
     assert np.all(np.isfinite(gd.cpu().numpy())) and np.all(gd.cpu().numpy()[:, 1:] > 0)
     assert np.all(rel <= 1e-5), rel
+
+
+GOLDEN_SHOCK = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                            "shock_mach3_steady.json")
+PROFILE_OFFSETS = np.linspace(-12.0, 12.0, 481)
+
+
+def _centred_profiles(x, n, T, qx, up, down):
+    """Normalised n, T, q_x sampled around the shock centre (where n crosses
+    (n- + n+)/2, by linear interpolation between cell centres)."""
+    (n1, _, T1), (n2, _, T2) = up, down
+    half = 0.5 * (n1 + n2)
+    k = int(np.nonzero((n[:-1] - half) * (n[1:] - half) <= 0.0)[0][0])
+    xc = x[k] + (half - n[k]) / (n[k + 1] - n[k]) * (x[k + 1] - x[k])
+    prof = ((n - n1) / (n2 - n1), (T - T1) / (T2 - T1), qx / (n1 * T1 ** 1.5))
+    return xc, np.stack([np.interp(PROFILE_OFFSETS, x - xc, p) for p in prof])
+
+
+def test_shock_profile_matches_fp64_steady_golden(ctx3):
+    """Mach-3 normal shock (1000 cells on [-20, 20], LLF, CFL 0.5) stepped on
+    the GPU in FP32 as many steps as the FP64 oracle's committed steady run
+    (tests/golden/make_shock_mach3_steady.py), from the same tanh profile:
+    after centring both shocks, density, temperature and heat flux on a unit
+    scale agree within 1e-3 everywhere within 12 upstream mean free paths."""
+    with open(GOLDEN_SHOCK) as f:
+        gold = json.load(f)
+    problem = mem_inputs.shock_problem(3.0, 1000, -20.0, 20.0, 5.44)
+    batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0, use_graph=True)
+    steps = int(gold["steps"])
+    print(f"\n[golden] {steps} GPU steps (oracle: t = {gold['t']:.4f}, reached "
+          f"{gold['reached']})", flush=True)
+    done = 0
+    while done < steps:
+        k = min(2000, steps - done)
+        ctx3.step(batch, Md, bd, gd, t, dt, k, status=status)
+        torch.cuda.synchronize()
+        done += k
+        print(f"[golden] {done} steps, t = {t.item():.4f}", flush=True)
+    assert t.item() == pytest.approx(gold["t"], rel=1e-3)
+    st = status.cpu().numpy()
+    assert not np.any(st & (mem.ST_NONFINITE | mem.ST_NONREALIZABLE | mem.ST_LAMBDA_FAIL))
+    mg = kinetics.macroscopic(Md.cpu().numpy().astype(np.float64),
+                              gd.cpu().numpy().astype(np.float64))
+    x = np.asarray(gold["x"])
+    up, down = gold["upstream"], gold["downstream"]
+    xg, pg = _centred_profiles(x, mg["n"], mg["T"], mg["qx"], up, down)
+    xo, po = _centred_profiles(x, np.asarray(gold["n"]), np.asarray(gold["T"]),
+                               np.asarray(gold["qx"]), up, down)
+    # n and T are normalised to [0, 1] by their jumps; q_x vanishes at both ends
+    # and peaks at ~5.4 n- T-^(3/2), so it is put on the same unit scale by the
+    # oracle profile's extreme
+    err = np.max(np.abs(pg - po), axis=1) / np.array([1.0, 1.0, np.max(np.abs(po[2]))])
+    print(f"[golden] centres GPU {xg:.5f}, oracle {xo:.5f}; max |difference| of the centred "
+          f"profiles (unit scale): n {err[0]:.2e}, T {err[1]:.2e}, q_x {err[2]:.2e}", flush=True)
+    assert np.all(err <= 1e-3)
