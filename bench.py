@@ -42,34 +42,48 @@ FP32_VECTOR_UNPACKED = 78.6
 # Cholesky and further trials are not counted
 WAVE_FLOP_ITER = 2.0 * (25920 + 15120 + 5808 + 5 * 1728 + 5 * 1728)
 
-# HBM bytes per k_assemble3 launch on this bench's timed solve (65536 cells,
-# launch parameters 2,2048): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB per
-# dispatch averaged over the solve's 24 launches (the first one empty: the
-# cells start at their gauge's Maxwellian and take the first pass in closed
-# form), each scaled by what the counter reads for a 1 GiB device-to-device
-# copy (FETCH x 2.0, WRITE x 1.0).  It describes one version of the kernel and
-# of the Newton loop that sizes its launches: both source texts are pinned by
-# hash, and any other version reports null.
+# HBM bytes per launch from two rocprofv3 runs of this bench's solve (65,536
+# cells): --pmc FETCH_SIZE, then --pmc WRITE_SIZE, KiB per dispatch, each scaled
+# by what the counter reads for a 1 GiB device-to-device copy (--copy-mib 1024:
+# FETCH x 2.0, WRITE x 1.0).  Each figure describes one version of its kernel and
+# of the Newton loop that launches it: the source texts are pinned by hash, and
+# any other version reports null.
+#  * k_assemble3 on the list loop (launch parameters 2,512): averaged over the
+#    timed solve's 24 launches, the first one empty (the cells start at their
+#    gauge's Maxwellian and take the first pass in closed form);
+#  * k_newton_wave: one launch per solve, averaged over the run's four launches.
 ASM_TRAFFIC = {
-    "kernel_sha256": "5150fe1c56da121b2719d6e7c862de82d29c13ff6720d49379832089cd3d56fa",
-    "fetch_kib": 30746.9, "fetch_scale": 1.99995,
+    "kernel_sha256": "5bd660d93d75a15d1c131793260315a4c315e5ebb76e9c1e720195cbdb8cb737",
+    "fetch_kib": 30801.7, "fetch_scale": 1.99995,
     "write_kib": 63904.4, "write_scale": 1.0,
-    "cells": 65536, "tuning": [2, 2048],
+    "cells": 65536, "tuning": [2, 512],
 }
-# the figure depends on the kernel and on the Newton loop that sizes its launches
+WAVE_TRAFFIC = {
+    "kernel_sha256": "c5932b0c16fd3328bce60fd9c7a73e0cbb8bae2f8a4afecbdd8d485858278bae",
+    "fetch_kib": 28542.9, "fetch_scale": 1.99995,
+    "write_kib": 224895.4, "write_scale": 1.0,
+    "cells": 65536,
+}
+# the figures depend on the kernels and on the Newton loop that launches them
 _ASM_SRC = (("paper_2303_02898_amd/csrc/k_solve3.hip",
              "__global__ __launch_bounds__(256, 2) void k_assemble3(",
              "// S[cell] = sum over splits"),
             ("paper_2303_02898_amd/csrc/api.cpp",
              "mem_err_t newton3(",
              "}  // namespace"))
+_WAVE_SRC = (("paper_2303_02898_amd/csrc/k_solve3.hip",
+              "// Unordered pair (p, q) of one-dimensional Hermite indices",
+              "hipError_t launch_newton_wave("),
+             ("paper_2303_02898_amd/csrc/api.cpp",
+              "mem_err_t newton3(",
+              "}  // namespace"))
 
 
-def assembly_source_sha():
-    """sha256 of the k_assemble3 kernel and newton3 texts (None if not found)."""
+def source_sha(spans):
+    """sha256 of the given source spans (None if one is not found)."""
     h = hashlib.sha256()
     try:
-        for path, begin, end in _ASM_SRC:
+        for path, begin, end in spans:
             with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), path)) as f:
                 txt = f.read()
             a = txt.index(begin)
@@ -79,11 +93,10 @@ def assembly_source_sha():
     return h.hexdigest()
 
 
-def assembly_traffic(prec, cells):
+def measured_traffic(t, spans, prec, cells):
     """Calibrated HBM bytes per launch, or None when they were not measured for
     this kernel version and workload."""
-    t = ASM_TRAFFIC
-    if prec != "fp32" or cells != t["cells"] or assembly_source_sha() != t["kernel_sha256"]:
+    if prec != "fp32" or cells != t["cells"] or source_sha(spans) != t["kernel_sha256"]:
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
@@ -718,7 +731,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": rr["asm_tflops"] / peak,
-            "traffic": assembly_traffic(args.prec, C),
+            "traffic": measured_traffic(ASM_TRAFFIC, _ASM_SRC, args.prec, C),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "traffic_tuning": ASM_TRAFFIC["tuning"],
             "flop_per_cell_iteration": 2.0 * 1728 * 630,
@@ -737,7 +750,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": r["wave_tflops"] / FP32_VECTOR_PEAK,
             "frac_of_unpacked_fp32": r["wave_tflops"] / FP32_VECTOR_UNPACKED,
-            "traffic": None,
+            "traffic": measured_traffic(WAVE_TRAFFIC, _WAVE_SRC, args.prec, C),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flop_per_cell_iteration": WAVE_FLOP_ITER,
             "flop_note": "lower bound: sum-factorised assembly, the exponent of sigma and one "
                          "line-search trial per assembled cell-iteration; exp, coefficient "
