@@ -189,3 +189,20 @@ def test_target_outside_node_hull_is_certified_nonrealizable(rule1):
     M = np.array([[1.0, 7.0, 0.0, 0.0, 0.0]])
     out = maxent.newton_solve(M, maxent.maxwellian_beta(M, 1), rule1["Phi"], rule1["logw"])
     assert out["nonrealizable"][0] and not out["converged"][0]
+
+
+def test_committed_config1_targets_are_the_oracles():
+    """tests/golden/config1_targets.json (read by the bench's 1D leg) holds
+    exactly what its oracle-only script computes."""
+    import hashlib
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(here, "config1_targets.json")) as f:
+        d = json.load(f)
+    with open(os.path.join(here, "make_config1_targets.py"), "rb") as f:
+        assert hashlib.sha256(f.read()).hexdigest() == d["script_sha256"]
+    M, g, b = workloads.config1_targets(mem_inputs.config1_candidates(4096), d["cells"])
+    assert np.array_equal(np.asarray(d["M"]), M)
+    assert np.array_equal(np.asarray(d["g"]), g)
+    assert np.array_equal(np.asarray(d["beta_generating"]), b)
