@@ -9,7 +9,8 @@ The paper's plain Newton breaks down along this sweep on its wide
 Gauss-Legendre box.  On Gauss-Hermite nodes in the gauge the Hessian stays
 well conditioned (cond(H) <= 71 at M_(400) = 0.5, from the oracle), the
 modification never engages and both variants land on the FP64 solution: this
-test pins that outcome.
+test pins that outcome.  The second test runs the sweep on the paper's own box,
+where the Hessian does become ill-conditioned and FP32 still copes.
 """
 
 import numpy as np
@@ -62,4 +63,57 @@ def test_m4_sweep_needs_no_hessian_modification(ctx3):
         assert not np.any(s & (mem.ST_SHIFTED | mem.ST_FP64))
         assert np.all(err < 1e-4)
         results[name] = beta
+    assert np.array_equal(results["modified"], results["plain"])
+
+
+def test_m4_sweep_on_the_paper_box():
+    """The same sweep on the paper's own set-up of Sec. 4.2: the nine statistics
+    in the gauge (0, 1, 1) on the box [-30.7, 37.3] x [0, 34.0] (16 x 16 blocks
+    of 8 x 8 Gauss-Legendre points), M_4 read as the u_x^4 statistic
+    He_4(x)/sqrt24.  There the Hessian does become ill-conditioned as M_4 grows
+    (the oracle's cond(H) rises from 1 to ~1.6e5: the solution puts mass at the
+    box's ends), as the paper says.  Both FP32 variants still converge at every
+    point to the FP64 solution: the FP32 pivot ratio never falls below the
+    switch to the FP64 direction (1e-6) and no Cholesky fails, so the
+    modification never engages and the paper's breakdown of plain Newton is not
+    reproduced by this implementation."""
+    from oracle import axisym
+    box = mem_inputs.E1_BOX
+    r = mem.AxiRule(**box)
+    orule = axisym.blockwise_rule(**box)
+    m4 = np.linspace(0.0, 0.5, 11)
+    N = m4.size
+    M = np.zeros((N, 9))
+    M[:, 0] = 1.0
+    M[:, 5] = m4
+    g = np.tile([0.0, 1.0, 1.0], (N, 1))
+    b0 = axisym.maxwellian_beta(np.ones(N), g)
+    o = axisym.solve(M, g, b0, orule, tol_grad=1e-12, max_iter=500)
+    assert np.all(o["converged"])
+    Phi = axisym.cell_phi(orule, g[0])
+    H = maxent.hessian(o["beta"], np.repeat(o["beta"][:, :1], 9, 1), Phi, orule["logw"])[:, 1:, 1:]
+    ev = np.linalg.eigvalsh(H)
+    cond = ev[:, -1] / ev[:, 0]
+    print(f"\n[box sweep] oracle cond(H) {np.round(cond, 0).tolist()}")
+    assert cond[0] < 2.0 and cond[-1] > 1e5 and np.all(np.diff(cond) > 0)
+    results = {}
+    for name, opts in (("modified", mem.default_opts()),
+                       ("plain", mem.default_opts(lambda0=1e-30, lambda_mul=1.0001,
+                                                   fp64_pivot_ratio=0.0))):
+        Md = torch.tensor(M.astype(np.float32), device=DEV)
+        gd = torch.tensor(g.astype(np.float32), device=DEV)
+        bd = torch.tensor(b0.astype(np.float32), device=DEV)
+        it, rs, st = r.solve(Md, gd, bd, opts=opts)
+        torch.cuda.synchronize()
+        s = st.cpu().numpy()
+        beta = bd.cpu().numpy().astype(np.float64)
+        err = np.max(np.abs(beta - o["beta"]), axis=1) / np.maximum(
+            1.0, np.max(np.abs(o["beta"]), axis=1))
+        print(f"[box sweep, {name}] iterations {it.cpu().tolist()}, max beta err {err.max():.1e}")
+        assert np.all(s & mem.ST_CONVERGED)
+        assert not np.any(s & (mem.ST_SHIFTED | mem.ST_FP64))
+        assert np.all(err < 1e-4)
+        assert np.all(rs.cpu().numpy() <= 1e-5)
+        results[name] = beta
+    r.close()
     assert np.array_equal(results["modified"], results["plain"])
