@@ -89,3 +89,54 @@ def test_fixed_gauge_is_slower_less_accurate_and_fails_at_high_mach(ctx3):
     assert not np.any(st[2:] & mem.ST_CONVERGED)
     assert np.all(o["nonrealizable"][3:])
     assert np.all(st[3:] & mem.ST_NONREALIZABLE)
+
+
+def test_gauge_study_on_the_paper_box():
+    """Sec. 4.3 on the paper's own box ([-30.7, 37.3] x [0, 34.0], 16 x 16 blocks
+    of 8 x 8 Gauss-Legendre points): upstream Maxwellians of Mach 2..12 solved in
+    FP32 by the nine-statistic solver from the uniform distribution (beta_i = 0,
+    i >= 1), once in the Hermite gauge of each state and once in the fixed gauge
+    (0, 1, 1), tolerance 1e-6, against the FP64 oracle of the same problems.
+    The paper states its experiment with the Maxwell family {1, u_x, u_x^2,
+    u_r^2}; the nine statistics contain it, so the solution is the same with the
+    other five multipliers at zero.  As in Fig. 3: in the Hermite gauge the
+    iterations stay within a narrow band and FP32 lands on FP64; in the fixed
+    gauge they climb and scatter with the Mach number and FP32 drifts far from
+    FP64 (from about Mach 7 on it does not converge)."""
+    from oracle import axisym
+    box = mem_inputs.E1_BOX
+    r = mem.AxiRule(**box)
+    orule = axisym.blockwise_rule(**box)
+    machs = np.arange(2, 13, dtype=np.float64)
+    N = machs.size
+    v = math.sqrt(5.0 / 3.0) * machs
+    out = {}
+    for gauge in ("hermite", "fixed"):
+        w = v if gauge == "hermite" else np.zeros(N)
+        g = np.stack([w, np.ones(N), np.ones(N)], axis=1)
+        M = mem_inputs.gaussian_moments9(np.ones(N), v, np.ones(N), np.ones(N), g)
+        b0 = np.zeros((N, 9))
+        b0[:, 0] = 1.0
+        o = axisym.solve(M, g, b0, orule, tol_grad=1e-12, max_iter=500)
+        assert np.all(o["converged"])
+        opts = mem.default_opts(tol_grad=1e-6, max_iter=500)
+        Md = torch.tensor(M.astype(np.float32), device=DEV)
+        gd = torch.tensor(g.astype(np.float32), device=DEV)
+        bd = torch.tensor(b0.astype(np.float32), device=DEV)
+        it, rs, st = r.solve(Md, gd, bd, opts=opts)
+        torch.cuda.synchronize()
+        beta = bd.cpu().numpy().astype(np.float64)
+        lmse = np.log10(np.mean((beta[:, 1:] - o["beta"][:, 1:]) ** 2, axis=1) + 1e-300)
+        out[gauge] = (it.cpu().numpy(), st.cpu().numpy(), lmse)
+        print(f"\n[box gauge study, {gauge}] iterations {it.cpu().tolist()}, log10 MSE "
+              f"{np.round(lmse, 2).tolist()}")
+    r.close()
+    it_h, st_h, l_h = out["hermite"]
+    it_f, st_f, l_f = out["fixed"]
+    assert np.all(st_h & mem.ST_CONVERGED)
+    assert l_h.max() < -13.0
+    assert it_h.max() <= 35 and it_h.max() - it_h.min() <= 10
+    assert l_f[0] < -10.0                       # Mach 2 still converges without the gauge
+    assert np.all(l_f[machs >= 7] > -4.0)       # far from FP64 beyond Mach 7
+    assert not np.all(st_f & mem.ST_CONVERGED)
+    assert np.sum(it_f > it_h) >= 8
