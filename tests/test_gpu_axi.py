@@ -420,3 +420,78 @@ def test_axi_mach10_flic_shock_paper_run():
     assert rate_o <= 0.2 * rate0
     assert rate_o <= 1.5 * rate_gpu + 1e-6
     r.close()
+
+
+def _exact_cond(beta, g, rule):
+    """cond(H) of each cell's 8 x 8 Hessian at beta (FP64, from the oracle)."""
+    from oracle import maxent
+    out = np.empty(beta.shape[0])
+    for c in range(beta.shape[0]):
+        Phi = axisym.cell_phi(rule, g[c])
+        H = maxent.hessian(beta[c:c + 1], np.repeat(beta[c:c + 1, :1], 9, 1), Phi,
+                           rule["logw"])[0, 1:, 1:]
+        ev = np.linalg.eigvalsh(H)
+        out[c] = ev[-1] / ev[0] if ev[0] > 0 else np.inf
+    return out
+
+
+def _flic_cond_run(mach, n, x_lo, x_hi, thickness, box, t_end):
+    """FLIC from the tanh profile to t_end on the GPU; the largest exact cond(H)
+    over the cells, sampled every 500 steps; whether any solve was certified
+    non-realizable."""
+    sh = axisym.ShockSolver(mach, n, x_lo, x_hi, thickness, box, scheme="flic",
+                            newton=dict(max_iter=60))
+    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(mach)
+    left = tuple(float(a) for a in (n1, v1, T1))
+    right = tuple(float(a) for a in (n2, v2, T2))
+    r = mem.AxiRule(**box)
+    r.reserve(n)
+    M0, g0 = f32(sh.M), f32(sh.g)
+    Md, gd = dev(M0), dev(g0)
+    bd = dev(axisym.maxwellian_beta(M0[:, 0].astype(np.float64), g0.astype(np.float64)))
+    t = torch.zeros(1, device=DEV)
+    dt = torch.zeros(1, device=DEV)
+    st = torch.zeros(n, dtype=torch.int32, device=DEV)
+    args = (Md, bd, gd, t, dt, sh.dx, left, right)
+    r.step(*args, n_steps=0, scheme="flic")
+    cmax, steps, nonreal = 0.0, 0, False
+    while t.item() < t_end:
+        r.step(*args, n_steps=100, status=st, scheme="flic", use_graph=True)
+        steps += 100
+        nonreal = nonreal or bool(np.any(st.cpu().numpy() & mem.ST_NONREALIZABLE))
+        if steps % 500 == 0:
+            c = _exact_cond(bd.cpu().numpy().astype(np.float64),
+                            gd.cpu().numpy().astype(np.float64), sh.rule)
+            cmax = max(cmax, float(np.max(c)))
+    finite = bool(torch.isfinite(Md).all().item())
+    r.close()
+    return cmax, nonreal, finite
+
+
+def test_cell_count_study_on_the_paper_box():
+    """Sec. 4.6, Fig. 7: the largest condition number of the Hessian met while
+    the FLIC scheme runs a shock, against the number of cells.  Mach 4 on
+    [-16.3, 16.3] (thickness 5.44, box [-22.7, 16.1] x [0, 14.5]) to t = 10;
+    Mach 10 on [-47.1, 47.1] (thickness 15.7, the Mach-10 box) to t = 30.  The
+    exact 8 x 8 cond comes from the oracle at the GPU's multipliers.  As the
+    paper reports: of order 1e5 at Mach 4, rising with the cell count; over ten
+    times larger at Mach 10, where beyond ~160 cells the solves start to fail
+    (here: certified non-realizable at 300 cells, none at 150)."""
+    box4 = dict(ux_lo=-22.7, ux_hi=16.1, ur_hi=14.5, blocks_x=6, blocks_r=4, order=8)
+    res = {}
+    for n in (125, 250, 500):
+        res[(4, n)] = _flic_cond_run(4.0, n, -16.3, 16.3, 5.44, box4, 10.0)
+    for n in (150, 300):
+        res[(10, n)] = _flic_cond_run(10.0, n, -47.1, 47.1, 15.7, mem_inputs.AXI_MACH10_BOX, 30.0)
+    for k, (c, nr, fin) in res.items():
+        print(f"\n[cell count] Mach {k[0]}, {k[1]} cells: max cond {c:.3e}, non-realizable {nr}, "
+              f"finite {fin}", flush=True)
+    for n in (125, 250, 500):
+        c, nr, fin = res[(4, n)]
+        assert fin and not nr and 3e4 < c < 1e6
+    assert res[(4, 500)][0] >= 0.99 * res[(4, 125)][0]
+    c150, nr150, fin150 = res[(10, 150)]
+    assert fin150 and not nr150
+    assert c150 > 10.0 * res[(4, 500)][0]
+    assert res[(10, 300)][1]     # beyond ~160 cells the Mach-10 solves break down
+    assert res[(10, 300)][2]     # the step itself stays finite (Maxwellian fallback)
