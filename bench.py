@@ -73,17 +73,19 @@ WAVE_TRAFFIC = {
 }
 # the figures depend on the kernels and on the Newton loop that launches them
 _ASM_SRC = (("paper_2303_02898_amd/csrc/k_solve3.hip",
-             "__global__ __launch_bounds__(256, 2) void k_assemble3(",
+             "// assembly: S[cell][col] = sum_p sigma_p Psi[p][col] on FP32 MFMA",
              "// S[cell] = sum over splits"),
+            ("paper_2303_02898_amd/csrc/k_solve3.hip",
+             "int assembly_splits(", "hipError_t launch_assemble5("),
             ("paper_2303_02898_amd/csrc/api.cpp",
-             "mem_err_t newton3(",
-             "}  // namespace"))
+             "mem_err_t newton3(", "// Process-wide tuning results"))
 _WAVE_SRC = (("paper_2303_02898_amd/csrc/k_solve3.hip",
               "// Unordered pair (p, q) of one-dimensional Hermite indices",
-              "hipError_t launch_newton_wave("),
+              "hipError_t launch_set_ctr("),
+             ("paper_2303_02898_amd/csrc/k_solve3.hip",
+              "hipError_t launch_newton_wave(", "hipError_t launch_unpack3("),
              ("paper_2303_02898_amd/csrc/api.cpp",
-              "mem_err_t newton3(",
-              "}  // namespace"))
+              "mem_err_t newton3(", "// Process-wide tuning results"))
 
 
 def source_sha(spans):
@@ -188,11 +190,12 @@ AXI_FLOP_ASM = 16 + 89
 VALU_PEAK_TFLOPS = 78.6
 
 
-def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400, scheme="llf"):
-    """Alg. 2 steps of the Mach-10 shock on the nine statistics (wall time)."""
+def _axi_shock_init(mach, n_cells):
+    """Tanh profile of a normal shock on [-47.1, 47.1] (thickness 15.7): moments
+    in the gauge (mean speed, 1, 1), that gauge, the ghost states and dx."""
     import math
     import mem_inputs
-    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(10.0)
+    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(mach)
     n1, v1, T1, n2, v2, T2 = (float(a) for a in (n1, v1, T1, n2, v2, T2))
     x_lo, x_hi, th = -47.1, 47.1, 15.7 / 2.0
     dx = (x_hi - x_lo) / n_cells
@@ -205,14 +208,26 @@ def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400, scheme="llf")
     Mp = mem_inputs.gaussian_moments9(np.array([n2]), np.array([v2]), np.array([T2]),
                                       np.array([T2]), gm)[0]
     M0 = (Mp - Mm)[None, :] * frac[:, None] + 0.5 * (Mp + Mm)[None, :]
-    Md = torch.tensor(M0.astype(np.float32), device=dev)
-    gd = torch.tensor(np.repeat(gm, n_cells, axis=0).astype(np.float32), device=dev)
-    rule.gauge(Md, None, gd)
-    b0 = np.zeros((n_cells, 9), np.float32)
+    return M0, np.repeat(gm, n_cells, axis=0), ((n1, v1, T1), (n2, v2, T2)), dx
+
+
+def _axi_start_beta(torch, Md):
+    """Maxwellian multipliers of each cell's gauge (the solves' cold start)."""
+    b0 = np.zeros((Md.shape[0], 9), np.float32)
     b0[:, 2] = -1.0 / np.sqrt(2.0)
     b0[:, 3] = -1.0
-    bd = torch.tensor(b0, device=dev)
+    bd = torch.tensor(b0, device=Md.device)
     bd[:, 0] = Md[:, 0]
+    return bd
+
+
+def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400, scheme="llf"):
+    """Alg. 2 steps of the Mach-10 shock on the nine statistics (wall time)."""
+    M0, g0, ((n1, v1, T1), (n2, v2, T2)), dx = _axi_shock_init(10.0, n_cells)
+    Md = torch.tensor(M0.astype(np.float32), device=dev)
+    gd = torch.tensor(g0.astype(np.float32), device=dev)
+    rule.gauge(Md, None, gd)
+    bd = _axi_start_beta(torch, Md)
     t = torch.zeros(1, device=dev)
     dt = torch.zeros(1, device=dev)
     st = torch.zeros(n_cells, dtype=torch.int32, device=dev)
@@ -233,6 +248,44 @@ def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400, scheme="llf")
             "cell_steps_per_s": n_cells * steps / el, "t": float(t.item()),
             "finite": bool(np.all(np.isfinite(Mh))),
             "density_ends": [float(Mh[0, 0]), float(Mh[-1, 0])]}
+
+
+def _axi_shock_batch_rate(mem, torch, dev, rule, n_problems=256, steps=100, scheme="llf"):
+    """Alg. 2 steps of a ragged batch of normal shocks on the nine statistics in
+    one mem_axi_step_batch: Mach numbers spread over [6, 10], 100 to 200 cells
+    each, every problem with its own dx, ghosts, t and dt (wall time)."""
+    rng = np.random.default_rng(2303)
+    machs = np.linspace(6.0, 10.0, n_problems)
+    cells = rng.integers(100, 201, n_problems)
+    inits = [_axi_shock_init(float(m), int(c)) for m, c in zip(machs, cells)]
+    Md = torch.tensor(np.concatenate([i[0] for i in inits]).astype(np.float32), device=dev)
+    gd = torch.tensor(np.concatenate([i[1] for i in inits]).astype(np.float32), device=dev)
+    rule.gauge(Md, None, gd)
+    bd = _axi_start_beta(torch, Md)
+    off = torch.tensor(np.concatenate([[0], np.cumsum(cells)]).astype(np.int64), device=dev)
+    dxd = torch.tensor([i[3] for i in inits], dtype=torch.float32, device=dev)
+    ghd = torch.tensor([[a for st in i[2] for a in st] for i in inits], dtype=torch.float32,
+                       device=dev)
+    n = int(cells.sum())
+    t = torch.zeros(n_problems, device=dev)
+    dt = torch.zeros(n_problems, device=dev)
+    st = torch.zeros(n, dtype=torch.int32, device=dev)
+    rule.reserve(n, n_problems)
+    args = (Md, bd, gd, t, dt, off, dxd, ghd)
+    rule.step_batch(*args, n_steps=0, status=st, scheme=scheme)
+    rule.step_batch(*args, n_steps=10, status=st, scheme=scheme, use_graph=True)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rule.step_batch(*args, n_steps=steps, status=st, scheme=scheme, use_graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"workload": f"{n_problems} normal shocks, Mach 6-10, 100-200 cells each "
+                        f"({n} cells) on [-47.1, 47.1], {scheme.upper()} in local gauges with "
+                        "ES-BGK halves, same box, one batched hipGraph replay per step",
+            "problems": n_problems, "cells": n, "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "cell_steps_per_s": n * steps / el,
+            "finite": bool(torch.isfinite(Md).all().item()),
+            "t_range": [float(t.min().item()), float(t.max().item())]}
 
 
 def paper_discretisation(mem, torch, dev, reps=5):
@@ -270,6 +323,8 @@ def paper_discretisation(mem, torch, dev, reps=5):
     # [-47.1, 47.1], tanh thickness 15.7, the same box; LLF steps
     shock = _axi_shock_rate(mem, torch, dev, rule)
     shock_flic = _axi_shock_rate(mem, torch, dev, rule, scheme="flic")
+    batch = _axi_shock_batch_rate(mem, torch, dev, rule)
+    batch_flic = _axi_shock_batch_rate(mem, torch, dev, rule, scheme="flic")
     rule.close()
     ms = float(np.mean(times))
     s = st.cpu().numpy()
@@ -289,6 +344,7 @@ def paper_discretisation(mem, torch, dev, reps=5):
             "stagnated_fraction": float(np.mean((s & mem.ST_STAGNATED) != 0)),
             "iterations_mean": float(iters.mean()), "iterations_max": int(iters.max()),
             "shock_llf": shock, "shock_flic": shock_flic,
+            "shock_batch_llf": batch, "shock_batch_flic": batch_flic,
             "roofline": {"bound": "alu", "kernel": "k_axi_solve", "achieved": achieved,
                          "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / VALU_PEAK_TFLOPS,
@@ -739,10 +795,13 @@ def main():
                                                            device=dev), r)
     wave = r["tuning"].get("solver") == 1 and args.prec == "fp32"
     # the same workload on the list-compacted Newton loop with the MFMA assembly
-    rl = None
+    rl = rl128 = None
     if wave:
         ctx.set_tuning(dir_waves=2, split_want=512, solver=0)
         rl = run_solves(mem, ctx, Md, b0d, args.steps, args.warmup, tune=False)
+        # the assembly's other workgroup size: 128 cells (eight waves) per node tile
+        ctx.set_tuning(dir_waves=2, split_want=512, solver=0, asm_waves=8)
+        rl128 = run_solves(mem, ctx, Md, b0d, args.steps, args.warmup, tune=False)
     ctx.close()
     peak = MFMA_PEAK[args.prec]
 
@@ -839,7 +898,11 @@ def main():
             "solves_per_s": rl["value"], "ms_per_step": rl["ms"],
             "converged_fraction": float(rl["ok"].mean()),
             "iterations_mean": float(rl["it"].mean()),
-            "roofline": mfma_roofline(rl)}
+            "roofline": mfma_roofline(rl),
+            "assembly_cells_per_workgroup": {
+                str(cells): {"avg_launch_ms": rr["asm_avg_ms"], "tflops": rr["asm_tflops"],
+                             "solves_per_s": rr["value"]}
+                for cells, rr in ((64, rl), (128, rl128))}}
     line["passes"] = pass_rates
     if args.mixed_cells > 0:
         line["mixed"] = mixed_comparison(mem, torch, dev, args.mixed_cells, 3, 1)

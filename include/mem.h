@@ -343,20 +343,35 @@ typedef struct {
                           mixed precisions use 0) (default 1)                       */
   int32_t wave_max_cells; /* with solver 1: launches of more cells use solver 0;
                           0 = no limit (default 0)                                   */
+  int32_t wave_per_cu; /* with solver 1: wavefronts (cells in flight) per compute
+                          unit in the persistent kernel's grid: 4, 8 or 12;
+                          0 = 12 (default 12)                                       */
+  int32_t asm_waves;   /* with solver 0 in FP32: wavefronts of 16 cells per workgroup
+                          of the MFMA assembly, 4 or 8 (64 or 128 cells sharing each
+                          node tile staged in LDS); 0 = 4 (default 4)               */
+  int32_t cached;      /* set by mem_autotune: 1 when the result came from the
+                          process-wide cache instead of timed trials                */
 } mem_tuning_t;
 
-/* Time full solves of this batch with every candidate (the Newton loop,
- * solver in {0, 1}, where the persistent kernel applies; then for solver 0
- * dir_waves in {2, 4, 8} and split_want in {0, 256, 512, 1024, 2048}), one
- * coordinate at a time, each
- * trial warm and timed with HIP events on `stream`), keep the fastest in the
- * context and return it in *out (nullable).  beta_init is not modified; the
- * trials run in beta_work [n_cells][35] (device, caller-owned).  Synchronous. */
+/* Time full solves of this batch with every candidate, one coordinate at a
+ * time, each trial warm and timed with HIP events on `stream`: the Newton
+ * loop (solver in {1, 0}, where the persistent kernel applies); then for
+ * solver 1 wave_per_cu in {12, 8, 4}; for solver 0 dir_waves in {2, 4, 8},
+ * asm_waves in {4, 8} (FP32) and split_want in {0, 256, 512, 1024, 2048}.
+ * Keep the fastest in the context and return it in *out (nullable).  The
+ * result is also kept in a process-wide cache keyed by (device architecture,
+ * dim, n_nodes_1d, moments, precision, bit length of n_cells): a later call
+ * with the same key, from any context, takes the cached result without
+ * timing (out->cached = 1).  The same parameters serve mem_step's solves.
+ * beta_init is not modified; the trials run in beta_work [n_cells][35]
+ * (device, caller-owned).  Synchronous. */
 MEM_API mem_err_t mem_autotune(mem_ctx_t ctx, int64_t n_cells, const float* M,
                                const float* beta_init, float* beta_work,
                                const mem_solve_opts_t* opts, mem_tuning_t* out,
                                hipStream_t stream);
 MEM_API mem_err_t mem_get_tuning(mem_ctx_t ctx, mem_tuning_t* out);
+/* Forget every cached mem_autotune result (the next call times again). */
+MEM_API void mem_tuning_cache_clear(void);
 MEM_API mem_err_t mem_set_tuning(mem_ctx_t ctx, const mem_tuning_t* in);
 
 /* ---- the paper's own discretisation: nine statistics on a box ---------------- */
@@ -441,10 +456,31 @@ typedef struct {
   int32_t use_graph;
 } mem_axi_shock_t;
 
-/* Sizes mem_axi_step's workspace for problems of up to n_cells cells (device
- * allocations; synchronises the device).  mem_axi_step grows it itself when a
- * larger problem arrives; a caller that reserves first keeps every step call
- * free of allocation and host synchronisation. */
+/* A ragged batch of normal-shock problems on the nine statistics, each as in
+ * mem_axi_shock_t, stepped together: problem p owns cells
+ * [cell_offsets[p], cell_offsets[p+1]) of the concatenated state arrays and
+ * keeps its own dx, ghost states, time and dt.  The scheme, cfl, Prandtl
+ * number and mu_ref are common.  dx and ghosts are device memory and are not
+ * checked on the host: dx > 0 and ghost n, T > 0 (finite) are the caller's to
+ * keep, and values outside that give non-finite states, never an access
+ * outside the arrays. */
+typedef struct {
+  int64_t        n_cells;        /* host copy of cell_offsets[n_problems]              */
+  int32_t        n_problems;
+  int32_t        scheme;         /* MEM_FLUX_LLF, MEM_FLUX_LW or MEM_FLUX_FLIC         */
+  const int64_t* cell_offsets;   /* device [n_problems + 1]: 0, increasing, n_cells    */
+  const float*   dx;             /* device [n_problems]                                */
+  const float*   ghosts;         /* device [n_problems][6]: left (n, v, T), right (n, v, T) */
+  float          cfl, prandtl, mu_ref;
+  int32_t        use_graph;      /* as in mem_axi_shock_t                              */
+} mem_axi_batch_t;
+
+/* Sizes the step workspace for up to n_cells cells in up to n_problems problems
+ * (device allocations; synchronises the device; never shrinks).  The step
+ * entry points grow it themselves when a larger call arrives; a caller that
+ * reserves first keeps every step call free of allocation and host
+ * synchronisation.  mem_axi_reserve(h, n) is mem_axi_reserve_batch(h, n, 1). */
+MEM_API mem_err_t mem_axi_reserve_batch(mem_axi_t h, int64_t n_cells, int32_t n_problems);
 MEM_API mem_err_t mem_axi_reserve(mem_axi_t h, int64_t n_cells);
 
 /* Time steps of Alg. 2 on the nine statistics with local Lax--Friedrichs
@@ -468,6 +504,21 @@ MEM_API mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* problem, floa
                                float* beta, float* g, float* t, float* dt, int32_t n_steps,
                                const mem_solve_opts_t* opts, uint32_t* status,
                                hipStream_t stream);
+
+/* mem_axi_step for a batch (Alg. 2 per problem, all problems in the same
+ * launches): M[n][9], beta[n][9], g[n][3], status[n] (nullable) over the
+ * concatenated cells; t[n_problems] and dt[n_problems] per problem (dt from
+ * each problem's own cells and ghosts).  The per-cell arithmetic is that of
+ * mem_axi_step, so each problem's result equals a separate mem_axi_step of it.
+ * cell_offsets are read back and checked (start 0, end n_cells, every problem
+ * at least one cell; else MEM_ERR_INVALID_ARG) on the first call with a given
+ * (cell_offsets, n_cells, n_problems), which synchronises once; later calls
+ * with the same three trust the contents.  Device memory, asynchronous
+ * otherwise. */
+MEM_API mem_err_t mem_axi_step_batch(mem_axi_t h, const mem_axi_batch_t* batch, float* M,
+                                     float* beta, float* g, float* t, float* dt,
+                                     int32_t n_steps, const mem_solve_opts_t* opts,
+                                     uint32_t* status, hipStream_t stream);
 
 /* Characteristic speeds (Sec. 3.4, the local Lax--Friedrichs bound):
  * lam[n][2] = (min, max) eigenvalue of dF/dM in physical velocity at beta[n][9]

@@ -68,9 +68,19 @@ class AxiShockStruct(ctypes.Structure):
                 ("scheme", _c_i32), ("use_graph", _c_i32)]
 
 
+class AxiBatchStruct(ctypes.Structure):
+    _fields_ = [("n_cells", _c_i64), ("n_problems", _c_i32), ("scheme", _c_i32),
+                ("cell_offsets", _vp), ("dx", _vp), ("ghosts", _vp), ("cfl", _c_f32),
+                ("prandtl", _c_f32), ("mu_ref", _c_f32), ("use_graph", _c_i32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("dir_waves", _c_i32), ("split_want", _c_i32), ("tuned_ms", ctypes.c_double),
-                ("solver", _c_i32), ("wave_max_cells", _c_i32)]
+                ("solver", _c_i32), ("wave_max_cells", _c_i32), ("wave_per_cu", _c_i32),
+                ("asm_waves", _c_i32), ("cached", _c_i32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 def load_library():
@@ -107,6 +117,7 @@ def load_library():
         "mem_autotune": ([P, _c_i64, P, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(Tuning),
                           P], E),
         "mem_get_tuning": ([P, ctypes.POINTER(Tuning)], E),
+        "mem_tuning_cache_clear": ([], None),
         "mem_set_tuning": ([P, ctypes.POINTER(Tuning)], E),
         "mem_axi_domain": ([ctypes.c_double] * 4 + [_c_i32] * 3 + [P], E),
         "mem_axi_rule_nodes": ([ctypes.POINTER(AxiRuleStruct)], _c_i64),
@@ -120,6 +131,9 @@ def load_library():
         "mem_axi_gauge": ([_c_i64, P, P, P, P], E),
         "mem_axi_speeds": ([P, _c_i64, P, P, P, P], E),
         "mem_axi_reserve": ([P, _c_i64], E),
+        "mem_axi_reserve_batch": ([P, _c_i64, _c_i32], E),
+        "mem_axi_step_batch": ([P, ctypes.POINTER(AxiBatchStruct), P, P, P, P, P, _c_i32,
+                                ctypes.POINTER(SolveOpts), P, _vp], E),
         "mem_axi_step": ([P, ctypes.POINTER(AxiShockStruct), P, P, P, P, P, _c_i32,
                           ctypes.POINTER(SolveOpts), P, P], E),
         "mem_profile_enable": ([P, _c_i32], E),
@@ -132,6 +146,11 @@ def load_library():
         fn.restype = res
     _lib = lib
     return lib
+
+
+def tuning_cache_clear():
+    """Forget every cached autotune result (the next autotune times again)."""
+    load_library().mem_tuning_cache_clear()
 
 
 def host_table(dim, n_nodes_1d, which):
@@ -233,17 +252,17 @@ class Context:
                                            _ptr(beta_init, torch.float32, (self.K,), "beta_init"),
                                            work.data_ptr(), o, ctypes.byref(t), _stream(stream)),
                     "mem_autotune")
-        return {"dir_waves": t.dir_waves, "split_want": t.split_want, "tuned_ms": t.tuned_ms,
-                "solver": t.solver, "wave_max_cells": t.wave_max_cells}
+        return t.as_dict()
 
     def tuning(self):
         t = Tuning()
         self._check(self._lib.mem_get_tuning(self._h, ctypes.byref(t)), "mem_get_tuning")
-        return {"dir_waves": t.dir_waves, "split_want": t.split_want, "tuned_ms": t.tuned_ms,
-                "solver": t.solver, "wave_max_cells": t.wave_max_cells}
+        return t.as_dict()
 
-    def set_tuning(self, dir_waves=4, split_want=512, solver=1, wave_max_cells=0):
-        t = Tuning(int(dir_waves), int(split_want), 0.0, int(solver), int(wave_max_cells))
+    def set_tuning(self, dir_waves=4, split_want=512, solver=1, wave_max_cells=0, wave_per_cu=12,
+                   asm_waves=4):
+        t = Tuning(int(dir_waves), int(split_want), 0.0, int(solver), int(wave_max_cells),
+                   int(wave_per_cu), int(asm_waves), 0)
         self._check(self._lib.mem_set_tuning(self._h, ctypes.byref(t)), "mem_set_tuning")
 
     def reserve(self, max_cells, max_problems=0):
@@ -457,9 +476,33 @@ class AxiRule:
             _ptr(resid, torch.float32), _ptr(status, torch.int32), _stream(stream)), "mem_axi_solve")
         return iters, resid, status
 
-    def reserve(self, n_cells):
+    def reserve(self, n_cells, n_problems=1):
         """Size the time-step workspace (step calls then allocate nothing)."""
-        self._check(self._lib.mem_axi_reserve(self._h, int(n_cells)), "mem_axi_reserve")
+        self._check(self._lib.mem_axi_reserve_batch(self._h, int(n_cells), int(n_problems)),
+                    "mem_axi_reserve_batch")
+
+    def step_batch(self, M, beta, g, t, dt, cell_offsets, dx, ghosts, n_steps=1, cfl=0.5,
+                   prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), opts=None, status=None,
+                   scheme="llf", use_graph=False, stream=None):
+        """Alg. 2 time steps of a ragged batch of shock problems (n_steps = 0:
+        set-up only).  cell_offsets: device int64 [P + 1]; dx: device [P];
+        ghosts: device [P, 6] = left (n, v, T), right (n, v, T); t, dt: device [P]."""
+        import torch
+        P = cell_offsets.shape[0] - 1
+        n = M.shape[0]
+        if dx.shape != (P,) or ghosts.shape != (P, 6) or t.shape != (P,) or dt.shape != (P,):
+            raise ValueError("dx, t, dt must be [P] and ghosts [P, 6]")
+        b = AxiBatchStruct(n, P, FLUX_SCHEMES[scheme], _ptr(cell_offsets, torch.int64, name="cell_offsets"),
+                           _ptr(dx, torch.float32, name="dx"),
+                           _ptr(ghosts, torch.float32, (6,), "ghosts"), cfl, prandtl, mu_ref,
+                           1 if use_graph else 0)
+        o = ctypes.byref(opts) if opts is not None else None
+        self._check(self._lib.mem_axi_step_batch(
+            self._h, ctypes.byref(b), _ptr(M, torch.float32, (9,), "M"),
+            _ptr(beta, torch.float32, (9,), "beta"), _ptr(g, torch.float32, (3,), "g"),
+            _ptr(t, torch.float32), _ptr(dt, torch.float32), n_steps, o,
+            _ptr(status, torch.int32) if status is not None else None, _stream(stream)),
+            "mem_axi_step_batch")
 
     def step(self, M, beta, g, t, dt, dx, left, right, n_steps=1, cfl=0.5,
              prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), opts=None, status=None,

@@ -3,8 +3,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
+#include <tuple>
 
 #include "mem_internal.h"
 
@@ -314,6 +317,28 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
   return MEM_OK;
 }
 
+
+// Process-wide tuning results: key = (device architecture, dimension, nodes per
+// axis, moments, precision, bit length of the cell count).  Contexts of the
+// same kind on the same kind of device reuse a result instead of timing again.
+struct TuneKey {
+  std::string arch;
+  int dim, n1d, K, prec, bits;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(arch, dim, n1d, K, prec, bits) <
+           std::tie(o.arch, o.dim, o.n1d, o.K, o.prec, o.bits);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, mem_tuning_t>& tune_cache() {
+  static std::map<TuneKey, mem_tuning_t> m;
+  return m;
+}
+TuneKey tune_key(mem_ctx_t c, int64_t n) {
+  int bits = 0;
+  while (bits < 63 && (int64_t(1) << bits) <= n) ++bits;
+  return TuneKey{c->arch, c->dim, c->n1d, c->K, c->prec, bits};
+}
 }  // namespace
 
 extern "C" {
@@ -367,6 +392,10 @@ mem_err_t mem_create(const mem_config_t* cfg, mem_ctx_t* out) {
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) !=
           hipSuccess || c->n_cu <= 0)
     c->n_cu = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->arch = prop.gcnArchName;
+  }
   try {
     memt::build_tables(c);
   } catch (...) {
@@ -771,14 +800,24 @@ mem_err_t mem_get_tuning(mem_ctx_t c, mem_tuning_t* out) {
 
 mem_err_t mem_set_tuning(mem_ctx_t c, const mem_tuning_t* in) {
   if (!c || !in) return MEM_ERR_INVALID_ARG;
+  const int wpc = in->wave_per_cu, aw = in->asm_waves;
   if ((in->dir_waves != 2 && in->dir_waves != 4 && in->dir_waves != 8) || in->split_want < 0 ||
-      in->split_want > 65536 || (in->solver != 0 && in->solver != 1) || in->wave_max_cells < 0)
+      in->split_want > 65536 || (in->solver != 0 && in->solver != 1) || in->wave_max_cells < 0 ||
+      (wpc != 0 && wpc != 4 && wpc != 8 && wpc != 12) || (aw != 0 && aw != 4 && aw != 8))
     return fail(c, MEM_ERR_INVALID_ARG,
                 "mem_set_tuning: dir_waves in {2,4,8}, split_want in [0, 65536], solver 0 or 1, "
-                "wave_max_cells >= 0");
+                "wave_max_cells >= 0, wave_per_cu in {0,4,8,12}, asm_waves in {0,4,8}");
   c->tune = *in;
+  if (c->tune.wave_per_cu == 0) c->tune.wave_per_cu = WAVE_SOLVE_PER_CU;
+  if (c->tune.asm_waves == 0) c->tune.asm_waves = 4;
+  c->tune.cached = 0;
   ++c->ws_gen;
   return MEM_OK;
+}
+
+void mem_tuning_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_cache().clear();
 }
 
 mem_err_t mem_autotune(mem_ctx_t c, int64_t n, const float* M, const float* beta_init,
@@ -789,6 +828,18 @@ mem_err_t mem_autotune(mem_ctx_t c, int64_t n, const float* M, const float* beta
   if (c->dim != 3) {  // the 1D solver has no launch parameters
     if (out) *out = c->tune;
     return MEM_OK;
+  }
+  const TuneKey key = tune_key(c, n);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      c->tune = it->second;
+      c->tune.cached = 1;
+      ++c->ws_gen;
+      if (out) *out = c->tune;
+      return MEM_OK;
+    }
   }
   mem_err_t e = ensure_cells(c, n);
   if (e != MEM_OK) return e;
@@ -816,47 +867,45 @@ mem_err_t mem_autotune(mem_ctx_t c, int64_t n, const float* M, const float* beta
     }
     return MEM_OK;
   };
-  mem_tuning_t best = c->tune;
+  // the search starts from the defaults, so a result does not depend on what
+  // the context held before
+  mem_tuning_t best = TUNE_DEFAULT;
   double best_ms = 1e30;
-  // the Newton loop first: the persistent kernel (when it applies) or the
-  // list-compacted passes, whose launch shapes are tuned next
-  if (c->prec == MEM_PREC_FP32 && c->n1d == 12) {
-    for (int sv : {1, 0}) {
-      if (e != MEM_OK) break;
+  // one coordinate at a time: each candidate value of the field, the others
+  // at the best so far
+  auto sweep = [&](std::initializer_list<int> vals, int32_t mem_tuning_t::*field) {
+    for (int v : vals) {
+      if (e != MEM_OK) return;
       mem_tuning_t t = best;
-      t.solver = sv;
-      t.wave_max_cells = 0;
+      t.*field = v;
       double ms = 0.0;
-      if ((e = trial(t, ms)) != MEM_OK) break;
+      if ((e = trial(t, ms)) != MEM_OK) return;
       if (ms < best_ms) { best_ms = ms; best = t; }
     }
-  } else {
+  };
+  // the Newton loop first: the persistent kernel (when it applies) or the
+  // list-compacted passes, whose launch shapes are tuned next
+  best.wave_max_cells = 0;
+  if (c->prec == MEM_PREC_FP32 && c->n1d == 12)
+    sweep({1, 0}, &mem_tuning_t::solver);
+  else
     best.solver = 0;
-  }
-  const bool list_loop = best.solver == 0;
-  const int dws[] = {2, 4, 8};
-  const int sws[] = {0, 256, 512, 1024, 2048};
-  for (int dw : dws) {
-    if (e != MEM_OK || !list_loop) break;
-    mem_tuning_t t = best;
-    t.dir_waves = dw;
-    double ms = 0.0;
-    if ((e = trial(t, ms)) != MEM_OK) break;
-    if (ms < best_ms) { best_ms = ms; best = t; }
-  }
-  for (int sw : sws) {
-    if (e != MEM_OK || !list_loop) break;
-    mem_tuning_t t = best;
-    t.split_want = sw;
-    double ms = 0.0;
-    if ((e = trial(t, ms)) != MEM_OK) break;
-    if (ms < best_ms) { best_ms = ms; best = t; }
+  if (best.solver == 1) {
+    sweep({12, 8, 4}, &mem_tuning_t::wave_per_cu);
+  } else {
+    sweep({2, 4, 8}, &mem_tuning_t::dir_waves);
+    if (c->prec == MEM_PREC_FP32) sweep({4, 8}, &mem_tuning_t::asm_waves);
+    sweep({0, 256, 512, 1024, 2048}, &mem_tuning_t::split_want);
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   best.tuned_ms = best_ms;
   c->tune = best;
   ++c->ws_gen;
+  if (e == MEM_OK) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache()[key] = best;
+  }
   if (out) *out = best;
   return e;
 }

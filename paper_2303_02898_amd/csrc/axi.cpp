@@ -18,18 +18,28 @@ struct mem_axi_s {
   float4* d_tab = nullptr;  // (u_x, u_r, log w, u_x - fl(u_x)) per node, then lo parts
   float lmin = 0.f;
   float ux_min = 0.f, ux_max = 0.f;  // node span in u_x
-  // time-step workspace (mem_axi_step), grown on demand
+  // time-step workspace (mem_axi_step, mem_axi_step_batch) for up to cap cells
+  // in up to cap_p problems, grown on demand
   int64_t cap = 0;
+  int32_t cap_p = 0;
   float *w_F = nullptr, *w_lam = nullptr, *w_Mn = nullptr, *w_gh = nullptr, *w_scal = nullptr;
   uint32_t* w_st = nullptr;
-  // interface rows (n + 1): F_LF, half-step state, gauge, multipliers, limiter,
+  // interface rows (n + P): F_LF, half-step state, gauge, multipliers, limiter,
   // F_LW, status
   float *w_fLF = nullptr, *w_Mh = nullptr, *w_gI = nullptr, *w_bI = nullptr, *w_phi = nullptr,
         *w_fLW = nullptr;
   uint32_t* w_stI = nullptr;
+  int32_t *w_pid = nullptr, *w_pidI = nullptr;  // problem of each cell / interface row
+  // descriptors of a single problem (mem_axi_step): offsets {0, n}, dx, ghosts
+  int64_t* w_off1 = nullptr;
+  float *w_dx1 = nullptr, *w_gs1 = nullptr;
+  // the last batch whose offsets were read back and checked
+  const int64_t* v_off = nullptr;
+  int64_t v_n = -1;
+  int32_t v_P = -1;
   // captured step (use_graph): valid while the key matches
   struct StepKey {
-    mem_axi_shock_t pb;
+    mem_axi_batch_t b;
     float *M, *beta, *g, *t, *dt;
     uint32_t* status;
     memk::SolveParams p;
@@ -223,11 +233,15 @@ void free_step(mem_axi_s* h) {
   if (h->exec) { (void)hipGraphExecDestroy(h->exec); h->exec = nullptr; }
   ++h->gen;
   for (float** p : {&h->w_F, &h->w_lam, &h->w_Mn, &h->w_gh, &h->w_scal, &h->w_fLF, &h->w_Mh,
-                    &h->w_gI, &h->w_bI, &h->w_phi, &h->w_fLW})
+                    &h->w_gI, &h->w_bI, &h->w_phi, &h->w_fLW, &h->w_dx1, &h->w_gs1})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
-  if (h->w_st) { (void)hipFree(h->w_st); h->w_st = nullptr; }
-  if (h->w_stI) { (void)hipFree(h->w_stI); h->w_stI = nullptr; }
+  for (uint32_t** p : {&h->w_st, &h->w_stI})
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+  for (int32_t** p : {&h->w_pid, &h->w_pidI})
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+  if (h->w_off1) { (void)hipFree(h->w_off1); h->w_off1 = nullptr; }
   h->cap = 0;
+  h->cap_p = 0;
 }
 
 mem_err_t mem_axi_destroy(mem_axi_t h) {
@@ -240,30 +254,39 @@ mem_err_t mem_axi_destroy(mem_axi_t h) {
   return MEM_OK;
 }
 
-mem_err_t mem_axi_reserve(mem_axi_t h, int64_t n) {
-  if (!h || n < 1 || n > (int64_t)1 << 24) return MEM_ERR_INVALID_ARG;
-  if (n <= h->cap) return MEM_OK;
+mem_err_t mem_axi_reserve_batch(mem_axi_t h, int64_t n, int32_t np) {
+  if (!h || n < 1 || n > (int64_t)1 << 24 || np < 1 || np > n) return MEM_ERR_INVALID_ARG;
+  if (n <= h->cap && np <= h->cap_p) return MEM_OK;
+  n = std::max(n, h->cap);
+  np = std::max(np, h->cap_p);
   if (hipDeviceSynchronize() != hipSuccess) return MEM_ERR_HIP;
   free_step(h);
-  if (hipMalloc((void**)&h->w_F, n * 9 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_lam, n * 2 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_Mn, n * 9 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_gh, 64 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_scal, 4 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_st, n * sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc((void**)&h->w_fLF, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_Mh, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_gI, (n + 1) * 3 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_bI, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_phi, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_fLW, (n + 1) * 9 * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&h->w_stI, (n + 1) * sizeof(uint32_t)) != hipSuccess) {
+  const int64_t ni = n + np;  // interface rows
+  auto fl = [](float*& p, int64_t count) {
+    return hipMalloc((void**)&p, (size_t)count * sizeof(float)) == hipSuccess;
+  };
+  auto u32 = [](uint32_t*& p, int64_t count) {
+    return hipMalloc((void**)&p, (size_t)count * sizeof(uint32_t)) == hipSuccess;
+  };
+  auto i32 = [](int32_t*& p, int64_t count) {
+    return hipMalloc((void**)&p, (size_t)count * sizeof(int32_t)) == hipSuccess;
+  };
+  if (!fl(h->w_F, n * 9) || !fl(h->w_lam, n * 2) || !fl(h->w_Mn, n * 9) ||
+      !fl(h->w_gh, 64 * (int64_t)np) || !fl(h->w_scal, 2 * (int64_t)np) || !u32(h->w_st, n) ||
+      !fl(h->w_fLF, ni * 9) || !fl(h->w_Mh, ni * 9) || !fl(h->w_gI, ni * 3) ||
+      !fl(h->w_bI, ni * 9) || !fl(h->w_phi, ni * 9) || !fl(h->w_fLW, ni * 9) ||
+      !u32(h->w_stI, ni) || !i32(h->w_pid, n) || !i32(h->w_pidI, ni) || !fl(h->w_dx1, 1) ||
+      !fl(h->w_gs1, 6) ||
+      hipMalloc((void**)&h->w_off1, 2 * sizeof(int64_t)) != hipSuccess) {
     free_step(h);
     return MEM_ERR_NOMEM;
   }
   h->cap = n;
+  h->cap_p = np;
   return MEM_OK;
 }
+
+mem_err_t mem_axi_reserve(mem_axi_t h, int64_t n) { return mem_axi_reserve_batch(h, n, 1); }
 
 int64_t mem_axi_n_nodes(mem_axi_t h) { return h ? h->P : -1; }
 
@@ -297,39 +320,30 @@ mem_err_t mem_axi_speeds(mem_axi_t h, int64_t n, const float* beta, const float*
     if ((x) != hipSuccess) return MEM_ERR_HIP;         \
   } while (0)
 
-// Alg. 2 on the nine statistics for one normal-shock problem (see mem.h).
-// Ghost rows: gh = [M 2x9 | beta 2x9 | g 2x3 | F 2x9 | lam 2x2].
-mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* beta, float* g,
-                       float* t, float* dt, int32_t n_steps, const mem_solve_opts_t* opts,
-                       uint32_t* status, hipStream_t s) {
-  if (!h || !pb || !M || !beta || !g || !t || !dt || n_steps < 0) return MEM_ERR_INVALID_ARG;
-  const int64_t n = pb->n_cells;
-  if (n < 1 || n > (int64_t)1 << 24 || !(pb->dx > 0.f) || !(pb->cfl > 0.f) || !(pb->cfl <= 1.f) ||
-      !(pb->prandtl > 0.f) || !(pb->mu_ref > 0.f) || pb->scheme < MEM_FLUX_LLF ||
-      pb->scheme > MEM_FLUX_FLIC)
-    return MEM_ERR_INVALID_ARG;
-  for (int k = 0; k < 3; ++k)
-    if (!std::isfinite(pb->ghost_left[k]) || !std::isfinite(pb->ghost_right[k]))
-      return MEM_ERR_INVALID_ARG;
-  if (!(pb->ghost_left[0] > 0.f) || !(pb->ghost_left[2] > 0.f) || !(pb->ghost_right[0] > 0.f) ||
-      !(pb->ghost_right[2] > 0.f))
-    return MEM_ERR_INVALID_ARG;
-  SolveParams p;
-  if (params_axi(h, opts, p) != MEM_OK) return MEM_ERR_INVALID_ARG;
-  if (n > h->cap) {
-    const mem_err_t e = mem_axi_reserve(h, n);
-    if (e != MEM_OK) return e;
-  }
+}  // extern "C"
+
+namespace {
+
+// Alg. 2 on the nine statistics for a batch of normal-shock problems whose
+// descriptors are on the device (see mem.h).  bd: the batch as the caller
+// gave it (or the single problem's descriptors); gs: its ghost states.
+// Ghost rows: gh = [M 2Px9 | beta 2Px9 | g 2Px3 | F 2Px9 | lam 2Px2].
+mem_err_t axi_steps(mem_axi_t h, const mem_axi_batch_t& bd, float* M, float* beta, float* g,
+                    float* t, float* dt, int32_t n_steps, const SolveParams& p, uint32_t* status,
+                    hipStream_t s) {
+  const int64_t n = bd.n_cells;
+  const int np = bd.n_problems;
   float* gM = h->w_gh;
-  float* gB = gM + 18;
-  float* gG = gB + 18;
-  float* gF = gG + 6;
-  float* gL = gF + 18;
-  // ghost Maxwellians in their own Hermite gauges: the discrete moments,
-  // fluxes and speeds of beta = (n, 0, -1/sqrt2, -1, 0, ...)
-  AXI_HIP(launch_axi_ghosts(pb->ghost_left, pb->ghost_right, gB, gG, s));
-  AXI_HIP(launch_axi_moments(2, (int)h->P, h->d_tab, gB, gG, gM, gF, s));
-  AXI_HIP(launch_axi_speeds(2, (int)h->P, h->d_tab, gB, gG, h->ux_min, h->ux_max, gL, s));
+  float* gB = gM + 18 * np;
+  float* gG = gB + 18 * np;
+  float* gF = gG + 6 * np;
+  float* gL = gF + 18 * np;
+  const AxBatch b{n, np, bd.cell_offsets, h->w_pid, h->w_pidI, bd.dx};
+  // problem maps, and the ghost Maxwellians in their own Hermite gauges: the
+  // discrete moments, fluxes and speeds of beta = (n, 0, -1/sqrt2, -1, 0, ...)
+  AXI_HIP(launch_axi_prologue(b, bd.ghosts, h->w_pid, h->w_pidI, gB, gG, s));
+  AXI_HIP(launch_axi_moments(2 * np, (int)h->P, h->d_tab, gB, gG, gM, gF, s));
+  AXI_HIP(launch_axi_speeds(2 * np, (int)h->P, h->d_tab, gB, gG, h->ux_min, h->ux_max, gL, s));
   uint32_t* st = status ? status : h->w_st;
   const int tpb = (int)h->P;
   // the per-step solves start from the previous step's multipliers: a cell
@@ -341,45 +355,45 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
     AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, p, nullptr, nullptr, st, s));
     AXI_HIP(launch_axi_fix(n, M, beta, st, s));
     AXI_HIP(launch_axi_speeds(n, tpb, h->d_tab, beta, g, h->ux_min, h->ux_max, h->w_lam, s));
-    AXI_HIP(launch_axi_dt(n, h->w_lam, gL, pb->cfl, pb->dx, dt, h->w_scal, 1, s));
+    AXI_HIP(launch_axi_dt(b, h->w_lam, gL, bd.cfl, dt, h->w_scal, 1, s));
     return MEM_OK;
   }
   // one step of Alg. 2 on stream q (kernels only: it may be captured)
   auto step_once = [&](hipStream_t q) -> mem_err_t {
-    AXI_HIP(launch_axi_collide(n, M, g, dt, 0.5f, pb->prandtl, pb->mu_ref, q));
+    AXI_HIP(launch_axi_collide(b, M, g, dt, 1, 0.5f, bd.prandtl, bd.mu_ref, q));
     AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, pw, nullptr, nullptr, st, q));
     AXI_HIP(launch_axi_fix(n, M, beta, st, q));
     AXI_HIP(launch_axi_moments(n, tpb, h->d_tab, beta, g, nullptr, h->w_F, q));
     AXI_HIP(launch_axi_speeds(n, tpb, h->d_tab, beta, g, h->ux_min, h->ux_max, h->w_lam, q));
-    AXI_HIP(launch_axi_dt(n, h->w_lam, gL, pb->cfl, pb->dx, dt, h->w_scal, 0, q));
-    if (pb->scheme == MEM_FLUX_LLF) {
-      AXI_HIP(launch_axi_fv(n, M, h->w_F, h->w_lam, g, gM, gF, gL, gG, h->w_scal, pb->dx, h->w_Mn,
-                            q));
+    AXI_HIP(launch_axi_dt(b, h->w_lam, gL, bd.cfl, dt, h->w_scal, 0, q));
+    if (bd.scheme == MEM_FLUX_LLF) {
+      AXI_HIP(launch_axi_fv(b, M, h->w_F, h->w_lam, g, gM, gF, gL, gG, h->w_scal, h->w_Mn, q));
     } else {  // one MaxEnt solve per interface, in the right element's gauge
-      AXI_HIP(launch_axi_iface(n, M, h->w_F, h->w_lam, g, beta, gM, gF, gL, gG, gB, h->w_scal,
-                               pb->dx, pb->scheme == MEM_FLUX_FLIC, h->w_fLF, h->w_Mh, h->w_gI,
-                               h->w_bI, h->w_phi, q));
-      AXI_HIP(launch_axi_solve(n + 1, tpb, h->d_tab, h->w_Mh, h->w_gI, h->w_bI, pw, nullptr,
+      AXI_HIP(launch_axi_iface(b, M, h->w_F, h->w_lam, g, beta, gM, gF, gL, gG, gB, h->w_scal,
+                               bd.scheme == MEM_FLUX_FLIC, h->w_fLF, h->w_Mh, h->w_gI, h->w_bI,
+                               h->w_phi, q));
+      AXI_HIP(launch_axi_solve(n + np, tpb, h->d_tab, h->w_Mh, h->w_gI, h->w_bI, pw, nullptr,
                                nullptr, h->w_stI, q));
-      AXI_HIP(launch_axi_moments(n + 1, tpb, h->d_tab, h->w_bI, h->w_gI, nullptr, h->w_fLW, q));
-      AXI_HIP(launch_axi_fv2(n, M, g, gG, h->w_fLF, h->w_fLW, h->w_phi, h->w_stI, h->w_scal,
-                             pb->dx, h->w_Mn, q));
+      AXI_HIP(launch_axi_moments(n + np, tpb, h->d_tab, h->w_bI, h->w_gI, nullptr, h->w_fLW, q));
+      AXI_HIP(launch_axi_fv2(b, M, g, gG, h->w_fLF, h->w_fLW, h->w_phi, h->w_stI, h->w_scal,
+                             h->w_Mn, q));
     }
     AXI_HIP(launch_copy(n * 9, h->w_Mn, M, q));
-    AXI_HIP(launch_axi_collide(n, M, g, h->w_scal, 0.5f, pb->prandtl, pb->mu_ref, q));
+    AXI_HIP(launch_axi_collide(b, M, g, h->w_scal, 2, 0.5f, bd.prandtl, bd.mu_ref, q));
     AXI_HIP(launch_axi_gauge(n, M, beta, g, q));
-    AXI_HIP(launch_axi_finish(t, dt, h->w_scal, q));
+    AXI_HIP(launch_axi_finish(np, t, dt, h->w_scal, q));
     return MEM_OK;
   };
-  if (!pb->use_graph) {
+  if (!bd.use_graph) {
     for (int k = 0; k < n_steps; ++k) {
       const mem_err_t e = step_once(s);
       if (e != MEM_OK) return e;
     }
     return MEM_OK;
   }
-  mem_axi_s::StepKey key{};
-  key.pb = *pb;
+  mem_axi_s::StepKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.b = bd;
   key.M = M; key.beta = beta; key.g = g; key.t = t; key.dt = dt; key.status = status;
   key.p = pw;
   key.gen = h->gen;
@@ -401,6 +415,82 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
   }
   for (int k = 0; k < n_steps; ++k) AXI_HIP(hipGraphLaunch(h->exec, s));
   return MEM_OK;
+}
+
+bool scheme_ok(int32_t sc) { return sc >= MEM_FLUX_LLF && sc <= MEM_FLUX_FLIC; }
+
+}  // namespace
+
+extern "C" {
+
+// One normal-shock problem (see mem.h): its descriptors go to the device and
+// the batch driver runs it as a batch of one.
+mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* beta, float* g,
+                       float* t, float* dt, int32_t n_steps, const mem_solve_opts_t* opts,
+                       uint32_t* status, hipStream_t s) {
+  if (!h || !pb || !M || !beta || !g || !t || !dt || n_steps < 0) return MEM_ERR_INVALID_ARG;
+  const int64_t n = pb->n_cells;
+  if (n < 1 || n > (int64_t)1 << 24 || !(pb->dx > 0.f) || !(pb->cfl > 0.f) || !(pb->cfl <= 1.f) ||
+      !(pb->prandtl > 0.f) || !(pb->mu_ref > 0.f) || !scheme_ok(pb->scheme))
+    return MEM_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(pb->ghost_left[k]) || !std::isfinite(pb->ghost_right[k]))
+      return MEM_ERR_INVALID_ARG;
+  if (!(pb->ghost_left[0] > 0.f) || !(pb->ghost_left[2] > 0.f) || !(pb->ghost_right[0] > 0.f) ||
+      !(pb->ghost_right[2] > 0.f))
+    return MEM_ERR_INVALID_ARG;
+  SolveParams p;
+  if (params_axi(h, opts, p) != MEM_OK) return MEM_ERR_INVALID_ARG;
+  if (n > h->cap || h->cap_p < 1) {
+    const mem_err_t e = mem_axi_reserve_batch(h, n, 1);
+    if (e != MEM_OK) return e;
+  }
+  AXI_HIP(launch_axi_single(n, pb->dx, pb->ghost_left, pb->ghost_right, h->w_off1, h->w_dx1,
+                            h->w_gs1, s));
+  mem_axi_batch_t bd;
+  std::memset(&bd, 0, sizeof(bd));
+  bd.n_cells = n;
+  bd.n_problems = 1;
+  bd.scheme = pb->scheme;
+  bd.cell_offsets = h->w_off1;
+  bd.dx = h->w_dx1;
+  bd.ghosts = h->w_gs1;
+  bd.cfl = pb->cfl;
+  bd.prandtl = pb->prandtl;
+  bd.mu_ref = pb->mu_ref;
+  bd.use_graph = pb->use_graph;
+  return axi_steps(h, bd, M, beta, g, t, dt, n_steps, p, status, s);
+}
+
+mem_err_t mem_axi_step_batch(mem_axi_t h, const mem_axi_batch_t* b, float* M, float* beta,
+                             float* g, float* t, float* dt, int32_t n_steps,
+                             const mem_solve_opts_t* opts, uint32_t* status, hipStream_t s) {
+  if (!h || !b || !M || !beta || !g || !t || !dt || n_steps < 0) return MEM_ERR_INVALID_ARG;
+  const int64_t n = b->n_cells;
+  const int32_t np = b->n_problems;
+  if (np < 1 || n < np || n > (int64_t)1 << 24 || !b->cell_offsets || !b->dx || !b->ghosts ||
+      !(b->cfl > 0.f) || !(b->cfl <= 1.f) || !(b->prandtl > 0.f) || !(b->mu_ref > 0.f) ||
+      !scheme_ok(b->scheme))
+    return MEM_ERR_INVALID_ARG;
+  SolveParams p;
+  if (params_axi(h, opts, p) != MEM_OK) return MEM_ERR_INVALID_ARG;
+  if (n > h->cap || np > h->cap_p) {
+    const mem_err_t e = mem_axi_reserve_batch(h, n, np);
+    if (e != MEM_OK) return e;
+  }
+  // offsets are read back and checked once per (pointer, n_cells, n_problems)
+  if (b->cell_offsets != h->v_off || n != h->v_n || np != h->v_P) {
+    std::vector<int64_t> off((size_t)np + 1);
+    AXI_HIP(hipMemcpy(off.data(), b->cell_offsets, off.size() * sizeof(int64_t),
+                      hipMemcpyDeviceToHost));
+    if (off[0] != 0 || off[np] != n) return MEM_ERR_INVALID_ARG;
+    for (int32_t q = 0; q < np; ++q)
+      if (off[q + 1] <= off[q]) return MEM_ERR_INVALID_ARG;
+    h->v_off = b->cell_offsets;
+    h->v_n = n;
+    h->v_P = np;
+  }
+  return axi_steps(h, *b, M, beta, g, t, dt, n_steps, p, status, s);
 }
 
 mem_err_t mem_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s) {

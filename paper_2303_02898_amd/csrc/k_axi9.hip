@@ -972,31 +972,79 @@ hipError_t launch_axi_moments_nc(int64_t n, int P, const float4* tab, const floa
   return hipGetLastError();
 }
 
-// The two ghost Maxwellians of a shock problem in their own Hermite gauges:
-// beta = (n, 0, -1/sqrt2, -1, 0, ...), g = (v, sqrt T, sqrt T) (left row 0,
-// right row 1).  The states arrive as kernel arguments: no host buffer.
-__global__ void k_axi_ghosts(float nl, float vl, float Tl, float nr, float vr, float Tr,
-                             float* __restrict__ gB, float* __restrict__ gG) {
-  const int t = threadIdx.x;
-  if (t < 18) {
-    const int k = t % 9;
-    const bool right = t >= 9;
-    float v = 0.f;
-    if (k == 0) v = right ? nr : nl;
-    if (k == 2) v = -0.70710678118654752f;
-    if (k == 3) v = -1.f;
-    gB[t] = v;
-  } else if (t < 24) {
-    const int k = (t - 18) % 3;
-    const bool right = t >= 21;
-    const float vel = right ? vr : vl, T = right ? Tr : Tl;
-    gG[t - 18] = k == 0 ? vel : sqrtf(T);
+// ---- batches of shock problems -------------------------------------------------
+// Problem p owns cells [off[p], off[p+1]) and interface rows
+// [off[p] + p, off[p+1] + p] (one more than its cells); its ghosts are rows 2p
+// (left) and 2p + 1 (right) of the ghost arrays, and scal[2p], scal[2p + 1]
+// hold its dt used and next dt.  Every index below is clamped into its array,
+// so offsets that break the layout give wrong numbers, never a stray access.
+
+// Cell range of problem p, clamped to [0, n) and non-empty.
+__device__ __forceinline__ void ax_range(const AxBatch& b, int p, int64_t& lo, int64_t& hi) {
+  lo = b.off[p];
+  hi = b.off[p + 1];
+  lo = lo < 0 ? 0 : (lo > b.n - 1 ? b.n - 1 : lo);
+  hi = hi < lo + 1 ? lo + 1 : (hi > b.n ? b.n : hi);
+}
+
+// The problem of each cell (the last p with off[p] <= c) and of each
+// interface row (the last p with off[p] + p <= i), by bisection.
+__global__ void k_axi_maps(AxBatch b, int32_t* __restrict__ pid, int32_t* __restrict__ pidI) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= b.n + b.P) return;
+  auto last_le = [&](int64_t x, bool iface) {
+    int lo = 0, hi = b.P - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (b.off[mid] + (iface ? mid : 0) <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  if (t < b.n) pid[t] = last_le(t, false);
+  pidI[t] = last_le(t, true);
+}
+
+// One problem's descriptors from scalars: off = {0, n}, dx, ghost states.
+__global__ void k_axi_single(int64_t n, float dx, float nl, float vl, float Tl, float nr, float vr,
+                             float Tr, int64_t* __restrict__ off, float* __restrict__ dxo,
+                             float* __restrict__ gs) {
+  if (threadIdx.x == 0) {
+    off[0] = 0;
+    off[1] = n;
+    dxo[0] = dx;
+    gs[0] = nl; gs[1] = vl; gs[2] = Tl;
+    gs[3] = nr; gs[4] = vr; gs[5] = Tr;
   }
 }
 
-hipError_t launch_axi_ghosts(const float* left, const float* right, float* gB, float* gG,
-                             hipStream_t s) {
-  k_axi_ghosts<<<1, 64, 0, s>>>(left[0], left[1], left[2], right[0], right[1], right[2], gB, gG);
+// The two ghost Maxwellians of every problem in their own Hermite gauges:
+// beta = (n, 0, -1/sqrt2, -1, 0, ...), g = (v, sqrt T, sqrt T); ghost row r is
+// side r % 2 of problem r / 2, from gs[p][6] = left (n, v, T), right (n, v, T).
+__global__ void k_axi_ghosts(int P, const float* __restrict__ gs, float* __restrict__ gB,
+                             float* __restrict__ gG) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 2 * P) return;
+  const float* st = gs + (r / 2) * 6 + (r % 2) * 3;
+  const float mb[9] = {st[0], 0.f, -0.70710678118654752f, -1.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gB[r * 9 + k] = mb[k];
+  gG[r * 3] = st[1];
+  gG[r * 3 + 1] = sqrtf(st[2]);
+  gG[r * 3 + 2] = sqrtf(st[2]);
+}
+
+hipError_t launch_axi_prologue(const AxBatch& b, const float* gs, int32_t* pid, int32_t* pidI,
+                               float* gB, float* gG, hipStream_t s) {
+  const int64_t rows = b.n + b.P;
+  k_axi_maps<<<(unsigned)((rows + 255) / 256), 256, 0, s>>>(b, pid, pidI);
+  k_axi_ghosts<<<(unsigned)((2 * b.P + 63) / 64), 64, 0, s>>>(b.P, gs, gB, gG);
+  return hipGetLastError();
+}
+
+hipError_t launch_axi_single(int64_t n, float dx, const float* left, const float* right,
+                             int64_t* off, float* dxo, float* gs, hipStream_t s) {
+  k_axi_single<<<1, 64, 0, s>>>(n, dx, left[0], left[1], left[2], right[0], right[1], right[2],
+                                off, dxo, gs);
   return hipGetLastError();
 }
 
@@ -1008,15 +1056,17 @@ hipError_t launch_axi_speeds(int64_t n, int P, const float4* tab, const float* b
 }
 
 // ---- the time step of Alg. 2 (Sec. 3.4; ES-BGK source of the appendix) -------
-// ES-BGK relaxation over f * dt[0]: M <- (1 - r) M + r M~, r = h/tau,
+// ES-BGK relaxation over f * dt of the cell's problem (dtp[pid * stride]):
+// M <- (1 - r) M + r M~, r = h/tau,
 // tau = mu_ref/(Pr n); M~ the Gaussian n N((v,0,0), diag(Sxx, Srr, Srr)),
 // Sigma = T/Pr + (1 - 1/Pr) P/n, in the cell's gauge: x ~ N(mu, var) gives
 // E[He_k(x)] = h_k(mu; var - 1), y ~ Exp(theta) gives E[l_1] = theta - 1 and
 // E[l_2] = (theta - 1)^2.  One thread per cell.
-__global__ void k_axi_collide(int64_t n, float* __restrict__ M, const float* __restrict__ g,
-                              const float* __restrict__ dtp, float f, float prandtl, float mu_ref) {
+__global__ void k_axi_collide(AxBatch b, float* __restrict__ M, const float* __restrict__ g,
+                              const float* __restrict__ dtp, int stride, float f, float prandtl,
+                              float mu_ref) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+  if (c >= b.n) return;
   double m[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) m[k] = (double)M[c * 9 + k];
@@ -1038,7 +1088,7 @@ __global__ void k_axi_collide(int64_t n, float* __restrict__ M, const float* __r
                         hx[4] * 0.20412414523193151};
   const double th = srr / (sr * sr);
   const double ly[3] = {1.0, th - 1.0, (th - 1.0) * (th - 1.0)};
-  const double r = (double)f * (double)dtp[0] * Pr * nn / (double)mu_ref;
+  const double r = (double)f * (double)dtp[b.pid[c] * stride] * Pr * nn / (double)mu_ref;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double mt = nn * px[AX_A[i]] * ly[AX_K[i]];
@@ -1061,19 +1111,25 @@ __global__ void k_axi_fix(int64_t n, const float* __restrict__ M, float* __restr
   for (int k = 0; k < 9; ++k) beta[c * 9 + k] = mb[k];
 }
 
-// dt of this step: min(previous dt, cfl dx / max speed) (cells and ghosts);
-// scal[0] = dt used, scal[1] = cfl dx / max speed (the next step's dt).  With
-// init, dt[0] <- scal[1] and nothing else.
-__global__ __launch_bounds__(256) void k_axi_dt(int64_t n, const float* __restrict__ lam,
-                                                const float* __restrict__ glam, float cfl, float dx,
+// dt of this step, per problem (one workgroup each): min(previous dt,
+// cfl dx / max speed) over its cells and ghosts; scal[2p] = dt used,
+// scal[2p + 1] = cfl dx / max speed (the next step's dt).  With init,
+// dt[p] <- cfl dx / max speed and nothing else.
+__global__ __launch_bounds__(256) void k_axi_dt(AxBatch b, const float* __restrict__ lam,
+                                                const float* __restrict__ glam, float cfl,
                                                 float* __restrict__ dt, float* __restrict__ scal,
                                                 int init) {
   __shared__ float sm[256];
+  const int p = blockIdx.x;
+  int64_t lo, hi;
+  ax_range(b, p, lo, hi);
   float r = 0.f;
-  for (int64_t c = threadIdx.x; c < n; c += 256)
+  for (int64_t c = lo + threadIdx.x; c < hi; c += 256)
     r = fmaxf(r, fmaxf(fabsf(lam[c * 2]), fabsf(lam[c * 2 + 1])));
-  if (threadIdx.x < 2)
-    r = fmaxf(r, fmaxf(fabsf(glam[threadIdx.x * 2]), fabsf(glam[threadIdx.x * 2 + 1])));
+  if (threadIdx.x < 2) {
+    const float* gl = glam + (2 * p + threadIdx.x) * 2;
+    r = fmaxf(r, fmaxf(fabsf(gl[0]), fabsf(gl[1])));
+  }
   sm[threadIdx.x] = r;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -1081,12 +1137,12 @@ __global__ __launch_bounds__(256) void k_axi_dt(int64_t n, const float* __restri
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const float dn = cfl * dx / sm[0];
+    const float dn = cfl * b.dx[p] / sm[0];
     if (init) {
-      dt[0] = dn;
+      dt[p] = dn;
     } else {
-      scal[0] = fminf(dt[0], dn);
-      scal[1] = dn;
+      scal[2 * p] = fminf(dt[p], dn);
+      scal[2 * p + 1] = dn;
     }
   }
 }
@@ -1100,15 +1156,19 @@ __device__ __forceinline__ void axi_T(const float* gto, const float* gfrom, doub
 
 // LLF in local gauges: neighbour moments and fluxes moved into the cell's gauge
 // by T(g_i, g_j); both cells of a face use max(rho_i, rho_j), rho = max |lam|.
-// Row -1 and row n are the ghosts (gM, gF, glam, gG rows 0 and 1).
-__global__ void k_axi_fv(int64_t n, const float* __restrict__ M, const float* __restrict__ F,
+// The first and last cell of a problem face its ghosts (ghost rows 2p, 2p + 1).
+__global__ void k_axi_fv(AxBatch b, const float* __restrict__ M, const float* __restrict__ F,
                          const float* __restrict__ lam, const float* __restrict__ g,
                          const float* __restrict__ gM, const float* __restrict__ gF,
                          const float* __restrict__ glam, const float* __restrict__ gG,
-                         const float* __restrict__ scal, float dx, float* __restrict__ Mout) {
+                         const float* __restrict__ scal, float* __restrict__ Mout) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const double dt = scal[0];
+  if (c >= b.n) return;
+  const int p = b.pid[c];
+  int64_t lo, hi;
+  ax_range(b, p, lo, hi);
+  const double dt = scal[2 * p];
+  const double dx = b.dx[p];
   auto rho_of = [](const float* l) { return (double)fmaxf(fabsf(l[0]), fabsf(l[1])); };
   const double ri = rho_of(lam + c * 2);
   double acc[9];
@@ -1116,12 +1176,13 @@ __global__ void k_axi_fv(int64_t n, const float* __restrict__ M, const float* __
   for (int k = 0; k < 9; ++k) acc[k] = (double)M[c * 9 + k];
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
-    const bool ghost = side == 0 ? (c == 0) : (c == n - 1);
+    const bool ghost = side == 0 ? (c <= lo) : (c >= hi - 1);
     const int64_t j = side == 0 ? c - 1 : c + 1;
-    const float* Mj = ghost ? gM + side * 9 : M + j * 9;
-    const float* Fj = ghost ? gF + side * 9 : F + j * 9;
-    const float* gj = ghost ? gG + side * 3 : g + j * 3;
-    const double rj = rho_of(ghost ? glam + side * 2 : lam + j * 2);
+    const int gr = 2 * p + side;
+    const float* Mj = ghost ? gM + gr * 9 : M + j * 9;
+    const float* Fj = ghost ? gF + gr * 9 : F + j * 9;
+    const float* gj = ghost ? gG + gr * 3 : g + j * 3;
+    const double rj = rho_of(ghost ? glam + gr * 2 : lam + j * 2);
     const double a = fmax(ri, rj);
     double t[5][5], r[3][3];
     axi_T(g + c * 3, gj, t, r);
@@ -1147,8 +1208,9 @@ __global__ void k_axi_fv(int64_t n, const float* __restrict__ M, const float* __
 }
 
 // ---- second-order fluxes (Sec. 3.4: two-step LW, FLIC) ------------------------
-// Elements e = 0..n+1 are [left ghost, cells, right ghost]; interface j lies
-// between elements j and j + 1 and works in the gauge of element j + 1.
+// Elements e = 0..n+1 of a problem of n cells are [left ghost, cells, right
+// ghost]; its interface j lies between elements j and j + 1 and works in the
+// gauge of element j + 1.
 struct AxElem { const float *M, *F, *g, *b, *lam; };
 __device__ __forceinline__ AxElem axi_elem(int64_t e, int64_t n, const float* M, const float* F,
                                            const float* g, const float* beta, const float* lam,
@@ -1164,18 +1226,30 @@ __device__ __forceinline__ AxElem axi_elem(int64_t e, int64_t n, const float* M,
 // Mh = (M_L + M_R)/2 + dt/(2 dx) (F_L - F_R) in the right element's gauge, the
 // per-moment van Leer limiter of FLIC (1 for LW), and the right element's
 // gauge and multipliers as the interface solve's gauge and start.
-__global__ void k_axi_iface(int64_t n, const float* __restrict__ M, const float* __restrict__ F,
-                            const float* __restrict__ lam, const float* __restrict__ g,
-                            const float* __restrict__ beta, const float* __restrict__ gM,
-                            const float* __restrict__ gF, const float* __restrict__ glam,
-                            const float* __restrict__ gG, const float* __restrict__ gB,
-                            const float* __restrict__ scal, float dx, int flic,
+__global__ void k_axi_iface(AxBatch b, const float* __restrict__ M0, const float* __restrict__ F0,
+                            const float* __restrict__ lam0, const float* __restrict__ g0,
+                            const float* __restrict__ beta0, const float* __restrict__ gM0,
+                            const float* __restrict__ gF0, const float* __restrict__ glam0,
+                            const float* __restrict__ gG0, const float* __restrict__ gB0,
+                            const float* __restrict__ scal, int flic,
                             float* __restrict__ fLF, float* __restrict__ Mh,
                             float* __restrict__ gI, float* __restrict__ bI,
                             float* __restrict__ phi) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > n) return;
-  const double dt = scal[0];
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= b.n + b.P) return;
+  const int p = b.pidI[row];
+  int64_t lo, hi;
+  ax_range(b, p, lo, hi);
+  const int64_t n = hi - lo;  // the problem's cells
+  int64_t j = row - lo - p;   // its interface
+  j = j < 0 ? 0 : (j > n ? n : j);
+  const double dt = scal[2 * p];
+  const double dx = b.dx[p];
+  // the problem's cells and ghost rows
+  const float *M = M0 + lo * 9, *F = F0 + lo * 9, *g = g0 + lo * 3, *beta = beta0 + lo * 9,
+              *lam = lam0 + lo * 2;
+  const float *gM = gM0 + 2 * p * 9, *gF = gF0 + 2 * p * 9, *gG = gG0 + 2 * p * 3,
+              *gB = gB0 + 2 * p * 9, *glam = glam0 + 2 * p * 2;
   const AxElem L = axi_elem(j, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
   const AxElem R = axi_elem(j + 1, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
   const AxElem LL = axi_elem(j > 0 ? j - 1 : 0, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
@@ -1201,8 +1275,8 @@ __global__ void k_axi_iface(int64_t n, const float* __restrict__ M, const float*
     }
     const double mr = R.M[i], fr = R.F[i];
     if (rr_is_r) mrr = mr;
-    fLF[j * 9 + i] = (float)(0.5 * (fl + fr) + 0.5 * a * (ml - mr));
-    Mh[j * 9 + i] = (float)(0.5 * (ml + mr) + 0.5 * (dt / dx) * (fl - fr));
+    fLF[row * 9 + i] = (float)(0.5 * (fl + fr) + 0.5 * a * (ml - mr));
+    Mh[row * 9 + i] = (float)(0.5 * (ml + mr) + 0.5 * (dt / dx) * (fl - fr));
     double ph = 1.0;
     if (flic) {  // van Leer on both sides: 2 a / (a + b) for a b > 0, else 0; the smaller
       const double da = ml - mll, db = mr - ml, dc = mrr - mr;
@@ -1210,77 +1284,82 @@ __global__ void k_axi_iface(int64_t n, const float* __restrict__ M, const float*
       const double pr = dc * db > 0.0 ? 2.0 * dc / (dc + db) : 0.0;
       ph = fmin(pl, pr);
     }
-    phi[j * 9 + i] = (float)ph;
-    bI[j * 9 + i] = R.b[i];
+    phi[row * 9 + i] = (float)ph;
+    bI[row * 9 + i] = R.b[i];
   }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) gI[j * 3 + k] = R.g[k];
+  for (int k = 0; k < 3; ++k) gI[row * 3 + k] = R.g[k];
 }
 
 // Blend F = F_LF + phi (F_LW - F_LF) (F_LF where the interface solve failed)
-// and apply: cell i takes its left face as given and its right face moved into
-// its gauge by T(g_i, g_{i+1}).
-__global__ void k_axi_fv2(int64_t n, const float* __restrict__ M, const float* __restrict__ g,
+// and apply: cell c takes its left face (interface row c + p) as given and its
+// right face (row c + p + 1) moved into its gauge by T(g_c, g_{c+1}).
+__global__ void k_axi_fv2(AxBatch b, const float* __restrict__ M, const float* __restrict__ g,
                           const float* __restrict__ gG, const float* __restrict__ fLF,
                           const float* __restrict__ fLW, const float* __restrict__ phi,
                           const uint32_t* __restrict__ stI, const float* __restrict__ scal,
-                          float dx, float* __restrict__ Mout) {
+                          float* __restrict__ Mout) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const double dt = scal[0];
+  if (c >= b.n) return;
+  const int p = b.pid[c];
+  int64_t lo, hi;
+  ax_range(b, p, lo, hi);
+  const double dt = scal[2 * p];
+  const double dx = b.dx[p];
   auto face = [&](int64_t j, int i) {
     const bool bad = (stI[j] & (MEM_ST_NONREALIZABLE | MEM_ST_NONFINITE)) != 0;
     const double lf = fLF[j * 9 + i];
     return bad ? lf : lf + (double)phi[j * 9 + i] * ((double)fLW[j * 9 + i] - lf);
   };
-  const float* gn = c + 1 < n ? g + (c + 1) * 3 : gG + 3;
+  const float* gn = c + 1 < hi ? g + (c + 1) * 3 : gG + (2 * p + 1) * 3;
   double t[5][5], r[3][3];
   axi_T(g + c * 3, gn, t, r);
+  const int64_t fl = c + p;  // the left face's interface row
   double fr[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) fr[k] = face(c + 1, k);
+  for (int k = 0; k < 9; ++k) fr[k] = face(fl + 1, k);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc += tij(t, r, i, k) * fr[k];
-    Mout[c * 9 + i] = (float)((double)M[c * 9 + i] + dt / dx * (face(c, i) - acc));
+    Mout[c * 9 + i] = (float)((double)M[c * 9 + i] + dt / dx * (face(fl, i) - acc));
   }
 }
 
-hipError_t launch_axi_iface(int64_t n, const float* M, const float* F, const float* lam,
+hipError_t launch_axi_iface(const AxBatch& b, const float* M, const float* F, const float* lam,
                             const float* g, const float* beta, const float* gM, const float* gF,
                             const float* glam, const float* gG, const float* gB,
-                            const float* scal, float dx, int flic, float* fLF, float* Mh,
-                            float* gI, float* bI, float* phi, hipStream_t s) {
-  k_axi_iface<<<(unsigned)((n + 1 + 127) / 128), 128, 0, s>>>(n, M, F, lam, g, beta, gM, gF, glam,
-                                                             gG, gB, scal, dx, flic, fLF, Mh, gI,
-                                                             bI, phi);
+                            const float* scal, int flic, float* fLF, float* Mh, float* gI,
+                            float* bI, float* phi, hipStream_t s) {
+  k_axi_iface<<<(unsigned)((b.n + b.P + 127) / 128), 128, 0, s>>>(
+      b, M, F, lam, g, beta, gM, gF, glam, gG, gB, scal, flic, fLF, Mh, gI, bI, phi);
   return hipGetLastError();
 }
 
-hipError_t launch_axi_fv2(int64_t n, const float* M, const float* g, const float* gG,
+hipError_t launch_axi_fv2(const AxBatch& b, const float* M, const float* g, const float* gG,
                           const float* fLF, const float* fLW, const float* phi,
-                          const uint32_t* stI, const float* scal, float dx, float* Mout,
-                          hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  k_axi_fv2<<<(unsigned)((n + 127) / 128), 128, 0, s>>>(n, M, g, gG, fLF, fLW, phi, stI, scal, dx,
-                                                       Mout);
+                          const uint32_t* stI, const float* scal, float* Mout, hipStream_t s) {
+  if (b.n <= 0) return hipSuccess;
+  k_axi_fv2<<<(unsigned)((b.n + 127) / 128), 128, 0, s>>>(b, M, g, gG, fLF, fLW, phi, stI, scal,
+                                                         Mout);
   return hipGetLastError();
 }
 
-__global__ void k_axi_finish(float* __restrict__ t, float* __restrict__ dt,
+__global__ void k_axi_finish(int P, float* __restrict__ t, float* __restrict__ dt,
                              const float* __restrict__ scal) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    t[0] += scal[0];
-    dt[0] = scal[1];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < P) {
+    t[p] += scal[2 * p];
+    dt[p] = scal[2 * p + 1];
   }
 }
 
-hipError_t launch_axi_collide(int64_t n, float* M, const float* g, const float* dtp, float f,
-                              float prandtl, float mu_ref, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  k_axi_collide<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, M, g, dtp, f, prandtl, mu_ref);
+hipError_t launch_axi_collide(const AxBatch& b, float* M, const float* g, const float* dtp,
+                              int stride, float f, float prandtl, float mu_ref, hipStream_t s) {
+  if (b.n <= 0) return hipSuccess;
+  k_axi_collide<<<(unsigned)((b.n + 255) / 256), 256, 0, s>>>(b, M, g, dtp, stride, f, prandtl,
+                                                             mu_ref);
   return hipGetLastError();
 }
 
@@ -1290,23 +1369,23 @@ hipError_t launch_axi_fix(int64_t n, const float* M, float* beta, const uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_axi_dt(int64_t n, const float* lam, const float* glam, float cfl, float dx,
+hipError_t launch_axi_dt(const AxBatch& b, const float* lam, const float* glam, float cfl,
                          float* dt, float* scal, int init, hipStream_t s) {
-  k_axi_dt<<<1, 256, 0, s>>>(n, lam, glam, cfl, dx, dt, scal, init);
+  k_axi_dt<<<(unsigned)b.P, 256, 0, s>>>(b, lam, glam, cfl, dt, scal, init);
   return hipGetLastError();
 }
 
-hipError_t launch_axi_fv(int64_t n, const float* M, const float* F, const float* lam, const float* g,
-                         const float* gM, const float* gF, const float* glam, const float* gG,
-                         const float* scal, float dx, float* Mout, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  k_axi_fv<<<(unsigned)((n + 127) / 128), 128, 0, s>>>(n, M, F, lam, g, gM, gF, glam, gG, scal, dx,
-                                                      Mout);
+hipError_t launch_axi_fv(const AxBatch& b, const float* M, const float* F, const float* lam,
+                         const float* g, const float* gM, const float* gF, const float* glam,
+                         const float* gG, const float* scal, float* Mout, hipStream_t s) {
+  if (b.n <= 0) return hipSuccess;
+  k_axi_fv<<<(unsigned)((b.n + 127) / 128), 128, 0, s>>>(b, M, F, lam, g, gM, gF, glam, gG, scal,
+                                                        Mout);
   return hipGetLastError();
 }
 
-hipError_t launch_axi_finish(float* t, float* dt, const float* scal, hipStream_t s) {
-  k_axi_finish<<<1, 64, 0, s>>>(t, dt, scal);
+hipError_t launch_axi_finish(int P, float* t, float* dt, const float* scal, hipStream_t s) {
+  k_axi_finish<<<(unsigned)((P + 63) / 64), 64, 0, s>>>(P, t, dt, scal);
   return hipGetLastError();
 }
 

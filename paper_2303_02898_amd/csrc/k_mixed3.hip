@@ -236,7 +236,7 @@ hipError_t launch_assemble3m(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
                              hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
   const int ntile = (int)nblocks(grid_cells, TILE);
-  const int nsplit = assembly_splits(c, ntile, 2 * c->nsg_m);
+  const int nsplit = assembly_splits(c, ntile, 2 * c->nsg_m, TILE);
   const unsigned grid = (unsigned)(ntile * nsplit);
   if (c->prec == MEM_PREC_FP16X3)
     k_assemble3m<true><<<grid, 64 * MW, 0, s>>>(c->d_phiA_m, c->d_psiF_m,
@@ -250,7 +250,7 @@ hipError_t launch_assemble3m(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
                                              static_cast<const uint4*>(c->d_psi_lo), c->nsg_m,
                                              list, ctr, n, beta, c->w_logZ, S, ntile, nsplit,
                                              c->w_Sp);
-  if (nsplit > 1) return launch_sum_splits(c, list, ctr, n, ntile, nsplit, S, s);
+  if (nsplit > 1) return launch_sum_splits(c, list, ctr, n, (int64_t)ntile * TILE, nsplit, S, s);
   return hipGetLastError();
 }
 

@@ -272,15 +272,18 @@ __global__ __launch_bounds__(64) void k_lse3(
 // Sp[split][slot][NCOL]; k_sum_splits adds them in a fixed order.
 // NB4 quadruples of 16-column blocks: 10 (S, 640 columns) or 2 (the 128
 // columns of the degree-5 products used by the characteristic speeds).
-template <int NB4>
-__global__ __launch_bounds__(256, 2) void k_assemble3(
+// AW wavefronts of 16 cells per workgroup (4 or 8): a workgroup holds 16 AW
+// cells, and its AW waves share each node half staged in LDS.
+template <int NB4, int AW>
+__global__ __launch_bounds__(64 * AW, 8 / AW) void k_assemble3(
     const float* __restrict__ phiA, const float* __restrict__ psi, int ngroups,
     const int32_t* __restrict__ list, const int32_t* __restrict__ ctr, int64_t n,
     const float* __restrict__ beta, const float* __restrict__ logZ, float* __restrict__ S,
     int ntile, int nsplit, float* __restrict__ Sp) {
   const int64_t count = ctr ? (int64_t)(*ctr) : n;
+  constexpr int TW = 16 * AW;  // cells per workgroup
   const int split = (int)(blockIdx.x / ntile);
-  const int64_t tile = (int64_t)(blockIdx.x % ntile) * TILE;
+  const int64_t tile = (int64_t)(blockIdx.x % ntile) * TW;
   if (tile >= count) return;
   const int gbeg = (int)((int64_t)split * ngroups / nsplit);
   const int gend = (int)((int64_t)(split + 1) * ngroups / nsplit);
@@ -292,11 +295,12 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
 
   // exponent B operand (beta, lane l holding k = 4j + l/16), kept in LDS to
   // leave the registers to the 160 accumulators
-  __shared__ float sBt[NJ * 256];
+  __shared__ float sBt[NJ * 64 * AW];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int k = 4 * j + kq;
-    sBt[j * 256 + threadIdx.x] = k == 0 ? 1.f : ((valid && k < K3) ? beta[cell * K3 + k] : 0.f);
+    sBt[j * 64 * AW + threadIdx.x] =
+        k == 0 ? 1.f : ((valid && k < K3) ? beta[cell * K3 + k] : 0.f);
   }
   const float lz = valid ? logZ[cell] : 0.f;
 
@@ -317,18 +321,23 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
   __shared__ f4 sA4[NJ * 16];      // exponent operand of one node group
   const float* sA = reinterpret_cast<const float*>(sA4);
   // buffer resources (bounds = the tables); lane l of wave w moves the 16 bytes
-  // at offset 16 (64 w + l) + 4096 i of a half into LDS element 64 w + 256 i + l
+  // at offset 16 (64 w + l) + 1024 AW i of a half into LDS element
+  // 64 w + 64 AW i + l (a half is 128 NB4 elements; with AW = 8 the last
+  // round covers only its first waves, a wave-uniform test)
   const __amdgpu_buffer_rsrc_t rB =
       __builtin_amdgcn_make_buffer_rsrc((void*)psi, (short)0, ngroups * (4 * NB4 * 64 * 16), BUF_DW3);
   const __amdgpu_buffer_rsrc_t rA =
       __builtin_amdgcn_make_buffer_rsrc((void*)phiA, (short)0, ngroups * (NJ * 64 * 4), BUF_DW3);
   const int voff = (int)threadIdx.x * 16;
   const int hend = 2 * gend;
+  constexpr int HALF = 2 * NB4 * 64;              // elements of a half
+  constexpr int ROUNDS = (HALF + 64 * AW - 1) / (64 * AW);
   auto fetch = [&](f4* dst, int h, bool first) {
 #pragma unroll
-    for (int i = 0; i < NB4 / 2; ++i)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, lds_ptr(dst + 64 * wave + 256 * i), 16, voff,
-                                               h * (2 * NB4 * 64 * 16) + 4096 * i, 0, 0);
+    for (int i = 0; i < ROUNDS; ++i)
+      if (HALF % (64 * AW) == 0 || 64 * wave + 64 * AW * i < HALF)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, lds_ptr(dst + 64 * wave + 64 * AW * i), 16,
+                                                 voff, h * (HALF * 16) + 1024 * AW * i, 0, 0);
     if (first && threadIdx.x < NJ * 16)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rA, lds_ptr(sA4 + 64 * wave), 16, voff,
                                                (h >> 1) * (NJ * 64 * 4), 0, 0);
@@ -358,7 +367,7 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
     fetch(sB1, h + 1, false);
     f4 e = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) e = mfma4(sA[j * 64 + lane], sBt[j * 256 + threadIdx.x], e);
+    for (int j = 0; j < NJ; ++j) e = mfma4(sA[j * 64 + lane], sBt[j * 64 * AW + threadIdx.x], e);
     float sg[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) sg[r] = valid ? __expf(e[r] - lz) : 0.f;
@@ -378,7 +387,7 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
     if (sl < count) {
       float* dst;
       if (nsplit > 1) {
-        dst = Sp + ((size_t)split * ntile * TILE + sl) * WIDTH + (lane & 15);
+        dst = Sp + ((size_t)split * ntile * TW + sl) * WIDTH + (lane & 15);
       } else {
         const int64_t cw = list ? (int64_t)list[sl] : sl;
         dst = S + cw * WIDTH + (lane & 15);
@@ -393,7 +402,7 @@ __global__ __launch_bounds__(256, 2) void k_assemble3(
 // rows of W floats.
 template <int W>
 __global__ void k_sum_splits(const int32_t* __restrict__ list, const int32_t* __restrict__ ctr,
-                             int64_t n, int ntile, int nsplit, const float* __restrict__ Sp,
+                             int64_t n, int64_t rows, int nsplit, const float* __restrict__ Sp,
                              float* __restrict__ S) {
   const int64_t count = ctr ? (int64_t)(*ctr) : n;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -401,7 +410,7 @@ __global__ void k_sum_splits(const int32_t* __restrict__ list, const int32_t* __
   const int q = (int)(t % (W / 4));
   if (slot >= count) return;
   const int64_t cell = list ? (int64_t)list[slot] : slot;
-  const size_t stride = (size_t)ntile * TILE * W;
+  const size_t stride = (size_t)rows * W;  // rows = tiles x cells per tile
   const f4* src = reinterpret_cast<const f4*>(Sp + (size_t)slot * W) + q;
   f4 acc = src[0];
   for (int k = 1; k < nsplit; ++k) {
@@ -1897,22 +1906,22 @@ hipError_t launch_lse3(mem_ctx_t c, int64_t grid_cells, const int32_t* list, con
   return hipGetLastError();
 }
 
-// Node-range splits for a launch of ntile 64-cell tiles: enough workgroups to
-// fill the chip when few cells are live, at least 4 node groups per split,
-// partial sums within the split buffer.
-int assembly_splits(mem_ctx_t c, int ntile, int ngroups) {
+// Node-range splits for a launch of ntile tiles of tw cells: enough
+// workgroups to fill the chip when few cells are live, at least 4 node groups
+// per split, partial sums within the split buffer.
+int assembly_splits(mem_ctx_t c, int ntile, int ngroups, int tw) {
   const int want = c->tune.split_want;  // workgroups
   if (want <= 0 || ntile >= want / 2 || !c->w_Sp) return 1;
   int ns = (want + ntile - 1) / ntile;
   ns = std::min(ns, std::max(1, ngroups / 4));
-  while (ns > 1 && (int64_t)ns * ntile * TILE > c->sp_rows) --ns;
+  while (ns > 1 && (int64_t)ns * ntile * tw > c->sp_rows) --ns;
   return ns;
 }
 
 hipError_t launch_sum_splits(mem_ctx_t c, const int32_t* list, const int32_t* ctr, int64_t n,
-                             int ntile, int nsplit, float* S, hipStream_t s) {
-  k_sum_splits<NCOL><<<(unsigned)nblocks((int64_t)ntile * TILE * (NCOL / 4), 256), 256, 0, s>>>(
-      list, ctr, n, ntile, nsplit, c->w_Sp, S);
+                             int64_t rows, int nsplit, float* S, hipStream_t s) {
+  k_sum_splits<NCOL><<<(unsigned)nblocks(rows * (NCOL / 4), 256), 256, 0, s>>>(
+      list, ctr, n, rows, nsplit, c->w_Sp, S);
   return hipGetLastError();
 }
 
@@ -1920,13 +1929,19 @@ hipError_t launch_assemble3(mem_ctx_t c, int64_t grid_cells, const int32_t* list
                             const int32_t* ctr, int64_t n, const float* beta, const float* table,
                             float* S, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  const int ntile = (int)nblocks(grid_cells, TILE);
-  const int nsplit = assembly_splits(c, ntile, c->ngroups);
-  k_assemble3<NBLK / 4><<<(unsigned)(ntile * nsplit), 256, 0, s>>>(
-      c->d_phiA, table, c->ngroups, list, ctr, n, beta, c->w_logZ, S, ntile, nsplit, c->w_Sp);
-  if (nsplit > 1)
-    k_sum_splits<NCOL><<<(unsigned)nblocks((int64_t)ntile * TILE * (NCOL / 4), 256), 256, 0, s>>>(
-        list, ctr, n, ntile, nsplit, c->w_Sp, S);
+  // cells per workgroup: 64 (four waves) or 128 (eight), a tuning parameter
+  const int aw = c->tune.asm_waves == 8 ? 8 : 4;
+  const int tw = 16 * aw;
+  const int ntile = (int)nblocks(grid_cells, tw);
+  const int nsplit = assembly_splits(c, ntile, c->ngroups, tw);
+  const unsigned grid = (unsigned)(ntile * nsplit);
+  if (aw == 8)
+    k_assemble3<NBLK / 4, 8><<<grid, 512, 0, s>>>(c->d_phiA, table, c->ngroups, list, ctr, n,
+                                                  beta, c->w_logZ, S, ntile, nsplit, c->w_Sp);
+  else
+    k_assemble3<NBLK / 4, 4><<<grid, 256, 0, s>>>(c->d_phiA, table, c->ngroups, list, ctr, n,
+                                                  beta, c->w_logZ, S, ntile, nsplit, c->w_Sp);
+  if (nsplit > 1) return launch_sum_splits(c, list, ctr, n, (int64_t)ntile * tw, nsplit, S, s);
   return hipGetLastError();
 }
 
@@ -1934,13 +1949,13 @@ hipError_t launch_assemble5(mem_ctx_t c, int64_t n, const float* beta, const flo
                             float* S5, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int ntile = (int)nblocks(n, TILE);
-  const int nsplit = assembly_splits(c, ntile, c->ngroups);
-  k_assemble3<NC5 / 64><<<(unsigned)(ntile * nsplit), 256, 0, s>>>(
+  const int nsplit = assembly_splits(c, ntile, c->ngroups, TILE);
+  k_assemble3<NC5 / 64, 4><<<(unsigned)(ntile * nsplit), 256, 0, s>>>(
       c->d_phiA, table, c->ngroups, nullptr, nullptr, n, beta, c->w_logZ, S5, ntile, nsplit,
       c->w_Sp);
   if (nsplit > 1)
     k_sum_splits<NC5><<<(unsigned)nblocks((int64_t)ntile * TILE * (NC5 / 4), 256), 256, 0, s>>>(
-        nullptr, nullptr, n, ntile, nsplit, c->w_Sp, S5);
+        nullptr, nullptr, n, (int64_t)ntile * TILE, nsplit, c->w_Sp, S5);
   return hipGetLastError();
 }
 
@@ -2063,7 +2078,8 @@ hipError_t launch_newton_wave(mem_ctx_t c, int64_t n, const float* M, float* bet
   if (n <= 0) return hipSuccess;
   if (c->n1d != 12) return hipErrorNotSupported;
   DirOut o{nullptr, nullptr, iters, resid, status, done_list, done_ctr, cond};
-  const int64_t waves = std::min<int64_t>(n, (int64_t)c->n_cu * WAVE_SOLVE_PER_CU);
+  const int wpc = c->tune.wave_per_cu > 0 ? c->tune.wave_per_cu : WAVE_SOLVE_PER_CU;
+  const int64_t waves = std::min<int64_t>(n, (int64_t)c->n_cu * wpc);
   k_newton_wave<12><<<(unsigned)waves, 64, 0, s>>>(c->d_t1, queue, n, M, beta, p,
                                                    closed_start ? 1 : 0, c->w_S, c->w_logZ,
                                                    c->w_iters, c->w_status, c->w_resid, o);

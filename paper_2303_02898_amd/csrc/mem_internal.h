@@ -63,11 +63,15 @@ struct StepKey {
   uint64_t gen;  // workspace and tuning generation (see mem_ctx_s::ws_gen)
 };
 
+// default launch parameters (field order of mem_tuning_t)
+constexpr mem_tuning_t TUNE_DEFAULT{4, 512, 0.0, 1, 0, 12, 4, 0};
+
 struct mem_ctx_s {
   int dim = 3, n1d = 12, K = 35, Q = 0, Qpad = 0, ngroups = 0, prec = 0;
-  mem_tuning_t tune{4, 512, 0.0, 1, 0};  // launch parameters (mem_autotune / mem_set_tuning)
+  mem_tuning_t tune = TUNE_DEFAULT;  // launch parameters (mem_autotune / mem_set_tuning)
   int device = 0;
   int n_cu = 256;  // compute units of the device (grid of the persistent solve)
+  std::string arch;  // gcnArchName of the device (key of the tuning cache)
   // host FP64 tables (checked against the oracle by the tests)
   std::vector<double> h_nodes, h_w, h_phi, h_logw;
   // device tables, 3D
@@ -161,28 +165,43 @@ hipError_t launch_axi_solve(int64_t n, int P, const float4* tab, const float* M,
                             uint32_t* status, hipStream_t s);
 hipError_t launch_axi_speeds(int64_t n, int P, const float4* tab, const float* beta, const float* g,
                              float ux_min, float ux_max, float* lam, hipStream_t s);
-hipError_t launch_axi_collide(int64_t n, float* M, const float* g, const float* dtp, float f,
-                              float prandtl, float mu_ref, hipStream_t s);
+// A batch of nine-statistic shock problems as the step kernels see it: n
+// cells in P problems, problem p owning cells [off[p], off[p+1]); pid[n] and
+// pidI[n + P] give the problem of each cell and each interface row; dx[P].
+struct AxBatch {
+  int64_t n;
+  int P;
+  const int64_t* off;
+  const int32_t* pid;
+  const int32_t* pidI;
+  const float* dx;
+};
+// pid, pidI and the ghost multipliers and gauges (rows 2p, 2p + 1) from the
+// batch and its ghost states gs[P][6]
+hipError_t launch_axi_prologue(const AxBatch& b, const float* gs, int32_t* pid, int32_t* pidI,
+                               float* gB, float* gG, hipStream_t s);
+// one problem's descriptors: off = {0, n}, dx, gs = left (n, v, T), right (n, v, T)
+hipError_t launch_axi_single(int64_t n, float dx, const float* left, const float* right,
+                             int64_t* off, float* dxo, float* gs, hipStream_t s);
+hipError_t launch_axi_collide(const AxBatch& b, float* M, const float* g, const float* dtp,
+                              int stride, float f, float prandtl, float mu_ref, hipStream_t s);
 hipError_t launch_axi_fix(int64_t n, const float* M, float* beta, const uint32_t* st, hipStream_t s);
-hipError_t launch_axi_dt(int64_t n, const float* lam, const float* glam, float cfl, float dx,
+hipError_t launch_axi_dt(const AxBatch& b, const float* lam, const float* glam, float cfl,
                          float* dt, float* scal, int init, hipStream_t s);
-hipError_t launch_axi_fv(int64_t n, const float* M, const float* F, const float* lam, const float* g,
-                         const float* gM, const float* gF, const float* glam, const float* gG,
-                         const float* scal, float dx, float* Mout, hipStream_t s);
-hipError_t launch_axi_iface(int64_t n, const float* M, const float* F, const float* lam,
+hipError_t launch_axi_fv(const AxBatch& b, const float* M, const float* F, const float* lam,
+                         const float* g, const float* gM, const float* gF, const float* glam,
+                         const float* gG, const float* scal, float* Mout, hipStream_t s);
+hipError_t launch_axi_iface(const AxBatch& b, const float* M, const float* F, const float* lam,
                             const float* g, const float* beta, const float* gM, const float* gF,
                             const float* glam, const float* gG, const float* gB,
-                            const float* scal, float dx, int flic, float* fLF, float* Mh,
-                            float* gI, float* bI, float* phi, hipStream_t s);
-hipError_t launch_axi_fv2(int64_t n, const float* M, const float* g, const float* gG,
+                            const float* scal, int flic, float* fLF, float* Mh, float* gI,
+                            float* bI, float* phi, hipStream_t s);
+hipError_t launch_axi_fv2(const AxBatch& b, const float* M, const float* g, const float* gG,
                           const float* fLF, const float* fLW, const float* phi,
-                          const uint32_t* stI, const float* scal, float dx, float* Mout,
-                          hipStream_t s);
-hipError_t launch_axi_finish(float* t, float* dt, const float* scal, hipStream_t s);
+                          const uint32_t* stI, const float* scal, float* Mout, hipStream_t s);
+hipError_t launch_axi_finish(int P, float* t, float* dt, const float* scal, hipStream_t s);
 hipError_t launch_axi_moments_nc(int64_t n, int P, const float4* tab, const float* alpha,
                                  const float* g, float* M, hipStream_t s);
-hipError_t launch_axi_ghosts(const float* left, const float* right, float* gB, float* gG,
-                             hipStream_t s);
 hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s);
 hipError_t launch_axi_moments(int64_t n, int P, const float4* tab, const float* beta,
                               const float* g, float* M, float* F, hipStream_t s);
@@ -210,9 +229,9 @@ hipError_t launch_assemble3m(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
                              const int32_t* ctr, int64_t n, const float* beta, float* S,
                              hipStream_t s);
 // Splits of the node range for small launches (1 = none) and their sum.
-int assembly_splits(mem_ctx_t c, int ntile, int ngroups);
+int assembly_splits(mem_ctx_t c, int ntile, int ngroups, int tw);
 hipError_t launch_sum_splits(mem_ctx_t c, const int32_t* list, const int32_t* ctr, int64_t n,
-                             int ntile, int nsplit, float* S, hipStream_t s);
+                             int64_t rows, int nsplit, float* S, hipStream_t s);
 // First Newton pass of the cells whose beta is exactly the Maxwellian of their
 // gauge (closed form: H = I, E = e_0); the others go to asm_list/asm_ctr for
 // the ordinary first assembly.
@@ -248,7 +267,7 @@ hipError_t launch_set_ctr(int32_t* ctr, int n, hipStream_t s);
 // Persistent Newton solve of cells 0..n-1: one wavefront per live cell from
 // the work queue `queue` (zeroed by the caller); converged cells are appended
 // to done_list for the refinement kernels.
-constexpr int WAVE_SOLVE_PER_CU = 12;
+constexpr int WAVE_SOLVE_PER_CU = 12;  // default and most: 3 waves per SIMD
 hipError_t launch_newton_wave(mem_ctx_t c, int64_t n, const float* M, float* beta,
                               const SolveParams& p, bool closed_start, int32_t* queue,
                               int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,

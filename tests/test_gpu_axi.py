@@ -350,6 +350,68 @@ def test_axi_graph_step_matches_eager(scheme):
     assert np.all(np.isfinite(runs[True][-1][0].cpu().numpy()))
 
 
+@pytest.mark.parametrize("scheme", ["llf", "flic"])
+def test_axi_batch_matches_separate_problems(scheme):
+    """Three shock problems of different Mach number, cell count and dx stepped
+    as one batch (mem_axi_step_batch) give bit for bit what three separate
+    mem_axi_step runs give: states, multipliers, gauges, statuses, and each
+    problem's own t and dt, eager and with the captured step."""
+    print(f"\n[gpu] axi batch of 3 shocks vs separate runs, {scheme}", flush=True)
+    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(3.0)
+    a_x, b_x, b_r = axisym.integration_domain(float(v1), float(T1), float(v2), float(T2), 10, 6, 6)
+    box = dict(ux_lo=a_x, ux_hi=b_x, ur_hi=b_r, blocks_x=6, blocks_r=4, order=8)
+    specs = [(3.0, 24, 12.0), (2.0, 17, 10.0), (2.5, 31, 14.0)]  # Mach, cells, half-width
+    shocks = [axisym.ShockSolver(m, nc, -w, w, 5.44, box, scheme=scheme) for m, nc, w in specs]
+    ghosts = [tuple(float(a) for st in mem_inputs.rankine_hugoniot(m) for a in st)
+              for m, _, _ in specs]
+
+    def start(sh):
+        M0 = f32(sh.M).astype(np.float64)
+        g0 = f32(sh.g).astype(np.float64)
+        return dev(M0), dev(axisym.maxwellian_beta(M0[:, 0], g0)), dev(g0)
+
+    sep = []
+    for sh, gh in zip(shocks, ghosts):
+        r = mem.AxiRule(**box)
+        Md, bd, gd = start(sh)
+        t = torch.zeros(1, device=DEV)
+        dt = torch.zeros(1, device=DEV)
+        st = torch.zeros(sh.M.shape[0], dtype=torch.int32, device=DEV)
+        r.step(Md, bd, gd, t, dt, sh.dx, gh[:3], gh[3:], n_steps=0)
+        for k in (3, 2):
+            r.step(Md, bd, gd, t, dt, sh.dx, gh[:3], gh[3:], n_steps=k, status=st, scheme=scheme)
+        torch.cuda.synchronize()
+        sep.append((Md.clone(), bd.clone(), gd.clone(), st.clone(), t.clone(), dt.clone()))
+        r.close()
+    sizes = [sh.M.shape[0] for sh in shocks]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    for graph in (False, True):
+        r = mem.AxiRule(**box)
+        r.reserve(int(off[-1]), len(specs))
+        parts = [start(sh) for sh in shocks]
+        Md, bd, gd = (torch.cat([p[k] for p in parts]) for k in range(3))
+        offd = torch.tensor(off, device=DEV)
+        dxd = torch.tensor([sh.dx for sh in shocks], dtype=torch.float32, device=DEV)
+        ghd = torch.tensor(ghosts, dtype=torch.float32, device=DEV)
+        t = torch.zeros(len(specs), device=DEV)
+        dt = torch.zeros(len(specs), device=DEV)
+        st = torch.zeros(int(off[-1]), dtype=torch.int32, device=DEV)
+        r.step_batch(Md, bd, gd, t, dt, offd, dxd, ghd, n_steps=0)
+        for k in (3, 2):
+            r.step_batch(Md, bd, gd, t, dt, offd, dxd, ghd, n_steps=k, status=st, scheme=scheme,
+                         use_graph=graph)
+        torch.cuda.synchronize()
+        r.close()
+        for p in range(len(specs)):
+            a, b = off[p], off[p + 1]
+            got = (Md[a:b], bd[a:b], gd[a:b], st[a:b], t[p:p + 1], dt[p:p + 1])
+            for k, (x, y) in enumerate(zip(got, sep[p])):
+                assert torch.equal(x, y), (graph, p, k)
+        print(f"  graph={graph}: t = {t.cpu().numpy()}, identical to the separate runs",
+              flush=True)
+    assert len(set(float(x[4].item()) for x in sep)) == 3   # three different clocks
+
+
 def test_axi_mach10_flic_shock_paper_run():
     """The paper's single-precision headline run (Sec. 4.5): the Mach-10 normal
     shock on 150 cells of [-47.1, 47.1] (tanh thickness 15.7) on the printed

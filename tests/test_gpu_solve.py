@@ -278,39 +278,63 @@ def test_solve_is_deterministic(ctx3):
 
 def test_autotune_keeps_results(ctx3, rule3):
     """Launch tuning changes how work maps to workgroups, never what is computed:
-    the direction-kernel variants (2, 4, 8 cells per workgroup) give identical
-    results, and the tuned solve meets the oracle bars."""
+    on the list loop the direction kernel's 2, 4, 8 cells per workgroup and the
+    assembly's 64 or 128 cells per workgroup give identical results; on the
+    persistent kernel 4, 8 or 12 waves per CU do too.  A node-split assembly
+    with 128-cell workgroups, and the tuned solve, meet the oracle bars; a
+    second autotune of the same kind of batch comes from the cache."""
     C = 4096
     cells = mem_inputs.mott_smith_cells(C, config=2, replica=9)
     M = f32(cells["M"])
     b0 = f32(mem_inputs.maxwellian_beta(C, 35, M[:, 0]))
     Md, b0d = dev(M), dev(b0)
-    outs = []
-    for dw in (2, 4, 8):
-        ctx3.set_tuning(dir_waves=dw, split_want=0)
+    idx = np.arange(0, C, 64)
+    ref = maxent.newton_solve(M[idx], b0[idx], rule3["Phi"], rule3["logw"])
+
+    def run(**tuning):
+        ctx3.set_tuning(**tuning)
         bg = b0d.clone()
         _, _, st = ctx3.solve(Md, bg)
         torch.cuda.synchronize()
-        outs.append((bg.clone(), st.clone()))
-    for bg, st in outs[1:]:
-        assert torch.equal(bg, outs[0][0]) and torch.equal(st, outs[0][1])
+        return bg, st
+
+    def meets_bars(bg, st, what):
+        st = st.cpu().numpy()
+        good = _split_by_oracle(st[idx], ref, what)
+        r, berr = _check_solution(bg.cpu().numpy().astype(np.float64)[idx][good], M[idx][good],
+                                  rule3, ref["beta"][good], what)
+        conv = (st[idx][good] & mem.ST_CONVERGED) != 0
+        assert r[conv].max() <= 1.0 and berr.max() <= 1e-4
+
+    for variants in ([dict(solver=0, dir_waves=dw, asm_waves=aw, split_want=0)
+                      for dw, aw in ((4, 4), (2, 4), (8, 4), (4, 8))],
+                     [dict(solver=1, wave_per_cu=w) for w in (12, 8, 4)]):
+        outs = [run(**v) for v in variants]
+        for v, (bg, st) in zip(variants[1:], outs[1:]):
+            assert torch.equal(bg, outs[0][0]) and torch.equal(st, outs[0][1]), v
+    print("\n[autotune] list-loop and persistent launch variants identical", flush=True)
+    meets_bars(*run(solver=0, asm_waves=8, split_want=512), "split, 128-cell workgroups")
+
+    mem.tuning_cache_clear()
     tuned = ctx3.autotune(Md, b0d)
-    print(f"\n[autotune] {tuned}", flush=True)
+    print(f"[autotune] {tuned}", flush=True)
+    assert tuned["solver"] in (0, 1) and tuned["cached"] == 0
     assert tuned["dir_waves"] in (2, 4, 8) and tuned["split_want"] in (0, 256, 512, 1024, 2048)
+    assert tuned["wave_per_cu"] in (4, 8, 12) and tuned["asm_waves"] in (4, 8)
     assert tuned["tuned_ms"] > 0.0
     assert torch.equal(b0d, dev(b0))   # the initial guess is left alone
     bg = b0d.clone()
     _, _, st = ctx3.solve(Md, bg)
     torch.cuda.synchronize()
-    st = st.cpu().numpy()
-    idx = np.arange(0, C, 64)
-    ref = maxent.newton_solve(M[idx], b0[idx], rule3["Phi"], rule3["logw"])
-    good = _split_by_oracle(st[idx], ref, "autotuned")
-    r, berr = _check_solution(bg.cpu().numpy().astype(np.float64)[idx][good], M[idx][good], rule3,
-                              ref["beta"][good], "autotuned")
-    conv = (st[idx][good] & mem.ST_CONVERGED) != 0
-    assert r[conv].max() <= 1.0 and berr.max() <= 1e-4
-    ctx3.set_tuning(4, 512)
+    meets_bars(bg, st, "autotuned")
+    ctx3.set_tuning(solver=0, asm_waves=8)   # the cached result replaces it
+    again = ctx3.autotune(Md, b0d)
+    assert again["cached"] == 1
+    assert {k: v for k, v in again.items() if k != "cached"} == \
+        {k: v for k, v in tuned.items() if k != "cached"}
+    # 2048 cells fall in another size bucket (bit length 12, not 13): timed again
+    assert ctx3.autotune(Md[:2048], b0d[:2048])["cached"] == 0
+    ctx3.set_tuning()
 
 
 def test_moment_residual_matches_fp64(ctx3, rule3):
