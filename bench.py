@@ -231,13 +231,14 @@ def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400, scheme="llf")
     t = torch.zeros(1, device=dev)
     dt = torch.zeros(1, device=dev)
     st = torch.zeros(n_cells, dtype=torch.int32, device=dev)
+    cm = torch.zeros(1, device=dev)   # conditioning monitor, on in the timed steps
     args = (Md, bd, gd, t, dt, dx, (n1, v1, T1), (n2, v2, T2))
     rule.reserve(n_cells)
     rule.step(*args, n_steps=0, status=st, scheme=scheme)
-    rule.step(*args, n_steps=20, status=st, scheme=scheme, use_graph=True)   # warm-up
+    rule.step(*args, n_steps=20, status=st, scheme=scheme, use_graph=True, cond_max=cm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rule.step(*args, n_steps=steps, status=st, scheme=scheme, use_graph=True)
+    rule.step(*args, n_steps=steps, status=st, scheme=scheme, use_graph=True, cond_max=cm)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     Mh = Md.cpu().numpy()
@@ -247,7 +248,8 @@ def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400, scheme="llf")
             "steps": steps, "ms_per_step": 1e3 * el / steps,
             "cell_steps_per_s": n_cells * steps / el, "t": float(t.item()),
             "finite": bool(np.all(np.isfinite(Mh))),
-            "density_ends": [float(Mh[0, 0]), float(Mh[-1, 0])]}
+            "density_ends": [float(Mh[0, 0]), float(Mh[-1, 0])],
+            "cond_bound": float(cm.item())}
 
 
 def _axi_shock_batch_rate(mem, torch, dev, rule, n_problems=256, steps=100, scheme="llf"):

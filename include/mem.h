@@ -454,6 +454,14 @@ typedef struct {
   float ghost_left[3], ghost_right[3];  /* (n, v, T) */
   int32_t scheme;
   int32_t use_graph;
+  float* cond_max;  /* device [1] or NULL: conditioning monitor (Sec. 3.5,
+                       Sec. 4.6): running maximum, over the steps and the cells,
+                       of a lower bound of cond(H) for the FP32 8 x 8 Hessian at
+                       the last iterate of each cell's solve: |H v| |H^-1 u| for
+                       the unit vectors of six power and inverse iterations from
+                       (1, ..., 1)/sqrt 8, or max_i H_ii / min pivot if larger;
+                       +inf where that Hessian's Cholesky fails.  Accumulates
+                       over calls; never cleared. */
 } mem_axi_shock_t;
 
 /* A ragged batch of normal-shock problems on the nine statistics, each as in
@@ -473,6 +481,8 @@ typedef struct {
   const float*   ghosts;         /* device [n_problems][6]: left (n, v, T), right (n, v, T) */
   float          cfl, prandtl, mu_ref;
   int32_t        use_graph;      /* as in mem_axi_shock_t                              */
+  float*         cond_max;       /* device [n_problems] or NULL: per problem, as in
+                                    mem_axi_shock_t                                   */
 } mem_axi_batch_t;
 
 /* Sizes the step workspace for up to n_cells cells in up to n_problems problems

@@ -65,13 +65,14 @@ class AxiRuleStruct(ctypes.Structure):
 class AxiShockStruct(ctypes.Structure):
     _fields_ = [("n_cells", _c_i32), ("dx", _c_f32), ("cfl", _c_f32), ("prandtl", _c_f32),
                 ("mu_ref", _c_f32), ("ghost_left", _c_f32 * 3), ("ghost_right", _c_f32 * 3),
-                ("scheme", _c_i32), ("use_graph", _c_i32)]
+                ("scheme", _c_i32), ("use_graph", _c_i32), ("cond_max", _vp)]
 
 
 class AxiBatchStruct(ctypes.Structure):
     _fields_ = [("n_cells", _c_i64), ("n_problems", _c_i32), ("scheme", _c_i32),
                 ("cell_offsets", _vp), ("dx", _vp), ("ghosts", _vp), ("cfl", _c_f32),
-                ("prandtl", _c_f32), ("mu_ref", _c_f32), ("use_graph", _c_i32)]
+                ("prandtl", _c_f32), ("mu_ref", _c_f32), ("use_graph", _c_i32),
+                ("cond_max", _vp)]
 
 
 class Tuning(ctypes.Structure):
@@ -483,7 +484,7 @@ class AxiRule:
 
     def step_batch(self, M, beta, g, t, dt, cell_offsets, dx, ghosts, n_steps=1, cfl=0.5,
                    prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), opts=None, status=None,
-                   scheme="llf", use_graph=False, stream=None):
+                   scheme="llf", use_graph=False, cond_max=None, stream=None):
         """Alg. 2 time steps of a ragged batch of shock problems (n_steps = 0:
         set-up only).  cell_offsets: device int64 [P + 1]; dx: device [P];
         ghosts: device [P, 6] = left (n, v, T), right (n, v, T); t, dt: device [P]."""
@@ -495,7 +496,8 @@ class AxiRule:
         b = AxiBatchStruct(n, P, FLUX_SCHEMES[scheme], _ptr(cell_offsets, torch.int64, name="cell_offsets"),
                            _ptr(dx, torch.float32, name="dx"),
                            _ptr(ghosts, torch.float32, (6,), "ghosts"), cfl, prandtl, mu_ref,
-                           1 if use_graph else 0)
+                           1 if use_graph else 0,
+                           _ptr(cond_max, torch.float32, name="cond_max"))
         o = ctypes.byref(opts) if opts is not None else None
         self._check(self._lib.mem_axi_step_batch(
             self._h, ctypes.byref(b), _ptr(M, torch.float32, (9,), "M"),
@@ -506,14 +508,16 @@ class AxiRule:
 
     def step(self, M, beta, g, t, dt, dx, left, right, n_steps=1, cfl=0.5,
              prandtl=2.0 / 3.0, mu_ref=math.sqrt(2.0 / math.pi), opts=None, status=None,
-             scheme="llf", use_graph=False, stream=None):
+             scheme="llf", use_graph=False, cond_max=None, stream=None):
         """Alg. 2 time steps of one shock problem (n_steps = 0: set-up only).
         left/right: ghost (n, v, T); t, dt: one-element device tensors;
-        use_graph: replay a captured step."""
+        use_graph: replay a captured step; cond_max: one-element device tensor,
+        the running max of the pivot-ratio bound of cond(H)."""
         import torch
         n = M.shape[0]
         pb = AxiShockStruct(n, dx, cfl, prandtl, mu_ref, (_c_f32 * 3)(*left),
-                            (_c_f32 * 3)(*right), FLUX_SCHEMES[scheme], 1 if use_graph else 0)
+                            (_c_f32 * 3)(*right), FLUX_SCHEMES[scheme], 1 if use_graph else 0,
+                            _ptr(cond_max, torch.float32, name="cond_max"))
         o = ctypes.byref(opts) if opts is not None else None
         self._check(self._lib.mem_axi_step(
             self._h, ctypes.byref(pb), _ptr(M, torch.float32, (9,), "M"),

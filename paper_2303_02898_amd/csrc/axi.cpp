@@ -30,6 +30,7 @@ struct mem_axi_s {
         *w_fLW = nullptr;
   uint32_t* w_stI = nullptr;
   int32_t *w_pid = nullptr, *w_pidI = nullptr;  // problem of each cell / interface row
+  float* w_cond = nullptr;  // per-cell pivot ratios of the last solve (monitor)
   // descriptors of a single problem (mem_axi_step): offsets {0, n}, dx, ghosts
   int64_t* w_off1 = nullptr;
   float *w_dx1 = nullptr, *w_gs1 = nullptr;
@@ -233,7 +234,7 @@ void free_step(mem_axi_s* h) {
   if (h->exec) { (void)hipGraphExecDestroy(h->exec); h->exec = nullptr; }
   ++h->gen;
   for (float** p : {&h->w_F, &h->w_lam, &h->w_Mn, &h->w_gh, &h->w_scal, &h->w_fLF, &h->w_Mh,
-                    &h->w_gI, &h->w_bI, &h->w_phi, &h->w_fLW, &h->w_dx1, &h->w_gs1})
+                    &h->w_gI, &h->w_bI, &h->w_phi, &h->w_fLW, &h->w_dx1, &h->w_gs1, &h->w_cond})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
   for (uint32_t** p : {&h->w_st, &h->w_stI})
     if (*p) { (void)hipFree(*p); *p = nullptr; }
@@ -276,6 +277,7 @@ mem_err_t mem_axi_reserve_batch(mem_axi_t h, int64_t n, int32_t np) {
       !fl(h->w_fLF, ni * 9) || !fl(h->w_Mh, ni * 9) || !fl(h->w_gI, ni * 3) ||
       !fl(h->w_bI, ni * 9) || !fl(h->w_phi, ni * 9) || !fl(h->w_fLW, ni * 9) ||
       !u32(h->w_stI, ni) || !i32(h->w_pid, n) || !i32(h->w_pidI, ni) || !fl(h->w_dx1, 1) ||
+      !fl(h->w_cond, n) ||
       !fl(h->w_gs1, 6) ||
       hipMalloc((void**)&h->w_off1, 2 * sizeof(int64_t)) != hipSuccess) {
     free_step(h);
@@ -361,7 +363,9 @@ mem_err_t axi_steps(mem_axi_t h, const mem_axi_batch_t& bd, float* M, float* bet
   // one step of Alg. 2 on stream q (kernels only: it may be captured)
   auto step_once = [&](hipStream_t q) -> mem_err_t {
     AXI_HIP(launch_axi_collide(b, M, g, dt, 1, 0.5f, bd.prandtl, bd.mu_ref, q));
-    AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, pw, nullptr, nullptr, st, q));
+    AXI_HIP(launch_axi_solve(n, tpb, h->d_tab, M, g, beta, pw, nullptr, nullptr, st, q,
+                             bd.cond_max ? h->w_cond : nullptr));
+    if (bd.cond_max) AXI_HIP(launch_axi_cond_max(b, h->w_cond, bd.cond_max, q));
     AXI_HIP(launch_axi_fix(n, M, beta, st, q));
     AXI_HIP(launch_axi_moments(n, tpb, h->d_tab, beta, g, nullptr, h->w_F, q));
     AXI_HIP(launch_axi_speeds(n, tpb, h->d_tab, beta, g, h->ux_min, h->ux_max, h->w_lam, q));
@@ -459,6 +463,7 @@ mem_err_t mem_axi_step(mem_axi_t h, const mem_axi_shock_t* pb, float* M, float* 
   bd.prandtl = pb->prandtl;
   bd.mu_ref = pb->mu_ref;
   bd.use_graph = pb->use_graph;
+  bd.cond_max = pb->cond_max;
   return axi_steps(h, bd, M, beta, g, t, dt, n_steps, p, status, s);
 }
 

@@ -180,6 +180,63 @@ __device__ __forceinline__ bool chol8(T (&A)[36], T& dmin, T& dmax) {
   return true;
 }
 
+// Lower bound of cond(H) for the conditioning monitor (Sec. 3.5), H SPD in
+// packed storage with its Cholesky factor L (packed) and smallest pivot dmin:
+// for unit vectors v, u, |H v| <= lambda_max and |H^-1 u| <= 1 / lambda_min,
+// so |H v| |H^-1 u| <= cond(H).  v and u come from CE_ITERS steps of power and
+// inverse iteration from (1, ..., 1)/sqrt 8; the bound max_i H_ii / dmin (every
+// pivot lies between the extreme eigenvalues) is folded in.
+constexpr int CE_ITERS = 6;
+__device__ __forceinline__ float cond_est8(const float (&H)[36], const float (&L)[36],
+                                           float dmin) {
+  float v[8], u[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = u[i] = 0.35355339059327376f;
+  float nv = 0.f, nu = 0.f;
+  for (int k = 0; k < CE_ITERS; ++k) {
+    float w[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float s = 0.f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s += H[i >= j ? PK(i, j) : PK(j, i)] * v[j];
+      w[i] = s;
+    }
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q += w[i] * w[i];
+    nv = sqrtf(q);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = w[i] / nv;
+    // w = (L L^T)^-1 u
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      float s = u[i];
+#pragma unroll
+      for (int j = 0; j < i; ++j) s -= L[PK(i, j)] * w[j];
+      w[i] = s / L[PK(i, i)];
+    }
+#pragma unroll
+    for (int i = 7; i >= 0; --i) {
+      float s = w[i];
+#pragma unroll
+      for (int j = i + 1; j < 8; ++j) s -= L[PK(j, i)] * w[j];
+      w[i] = s / L[PK(i, i)];
+    }
+    q = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q += w[i] * w[i];
+    nu = sqrtf(q);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[i] = w[i] / nu;
+  }
+  float hmax = 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) hmax = fmaxf(hmax, H[PK(i, i)]);
+  const float est = nv * nu;
+  return isfinite(est) ? fmaxf(est, hmax / dmin) : INFINITY;
+}
+
 // direction d = -(L L^T)^-1 G and decrement 1/2 |L^-1 G|^2 (L packed)
 template <typename T>
 __device__ __forceinline__ void solve8(const T (&L)[36], const T (&G)[8], T (&d)[8], T& res) {
@@ -355,7 +412,7 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
                                                         const float* __restrict__ gin,
                                                         float* __restrict__ beta, SolveParams p,
                                                         int32_t* iters_out, float* resid_out,
-                                                        uint32_t* status_out) {
+                                                        uint32_t* status_out, float* cond_out) {
   __shared__ __align__(16) float sred[AXW][65 * RSTRIDE];
   __shared__ float sHk[AXW][36];  // the last FP32 Hessian, for the refinement
   const int lane = threadIdx.x & 63;
@@ -376,6 +433,10 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
   uint32_t st = 0;
   int it = 0;
   float r = INFINITY;
+  // conditioning monitor (Sec. 3.5): cond_est8 of the FP32 Hessian at the
+  // solve's last iterate (a lower bound of cond(H)); +inf where its Cholesky
+  // fails; 0 for a cell that never assembled one
+  float cmon = 0.f;
   if (!fin) st = MEM_ST_NONFINITE;
   else if (!(m[0] > 0.f) || !(gsx > 0.f) || !(gsr > 0.f)) st = MEM_ST_NONREALIZABLE;
   if (st == 0) {
@@ -503,6 +564,13 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
       }
       if (it >= p.max_iter) { st |= MEM_ST_MAXITER; break; }
     }
+    if (cond_out && it > 0) {  // the Hessian of the last direction, kept in sHk
+      __builtin_amdgcn_wave_barrier();
+      float Hk[36], Lk[36], dmin, dmax;
+#pragma unroll
+      for (int k = 0; k < 36; ++k) Lk[k] = Hk[k] = sHk[wv][k];
+      cmon = chol8(Lk, dmin, dmax) ? cond_est8(Hk, Lk, dmin) : INFINITY;
+    }
     // Compensated refinement (as the 35-moment path): the FP32 iteration stops
     // where its own rounding hides the residual; a cell that ended converged or
     // at that floor takes Newton corrections with the double-float gradient
@@ -551,6 +619,7 @@ __global__ __launch_bounds__(64 * AXW) void k_axi_solve(int64_t n, int P,
     if (iters_out) iters_out[c] = it;
     if (resid_out) resid_out[c] = r;
     if (status_out) status_out[c] = st;
+    if (cond_out) cond_out[c] = cmon;
   }
 }
 
@@ -1397,10 +1466,38 @@ hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStrea
 
 hipError_t launch_axi_solve(int64_t n, int P, const float4* tab, const float* M, const float* g,
                             float* beta, const SolveParams& p, int32_t* iters, float* resid,
-                            uint32_t* status, hipStream_t s) {
+                            uint32_t* status, hipStream_t s, float* cond) {
   if (n <= 0) return hipSuccess;
   k_axi_solve<<<(unsigned)((n + AXW - 1) / AXW), 64 * AXW, 0, s>>>(n, P, tab, M, g, beta, p, iters,
-                                                                 resid, status);
+                                                                 resid, status, cond);
+  return hipGetLastError();
+}
+
+// cond_max[p] = max(cond_max[p], max over the problem's cells of cond[c]), as
+// an unsigned max of the float bits (all values >= 0); a wave whose cells all
+// belong to one problem makes one atomic.
+__global__ void k_axi_cond_max(AxBatch b, const float* __restrict__ cond, uint32_t* out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = c < b.n;
+  const float r = in ? cond[c] : 0.f;
+  const uint32_t v = (in && r >= 0.f) ? __float_as_uint(r) : 0u;
+  const int p = in ? b.pid[c] : -1;
+  const int p0 = __shfl(p, 0);
+  if (__all(!in || p == p0)) {
+    uint32_t m = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0 && p0 >= 0 && m > 0u) atomicMax(&out[p0], m);
+  } else if (in && v > 0u) {
+    atomicMax(&out[p], v);
+  }
+}
+
+hipError_t launch_axi_cond_max(const AxBatch& b, const float* cond, float* cond_max,
+                               hipStream_t s) {
+  if (b.n <= 0) return hipSuccess;
+  k_axi_cond_max<<<(unsigned)((b.n + 255) / 256), 256, 0, s>>>(
+      b, cond, reinterpret_cast<uint32_t*>(cond_max));
   return hipGetLastError();
 }
 

@@ -160,9 +160,11 @@ hipError_t launch_solve1(mem_ctx_t c, int64_t n, const float* M, float* beta,
                          uint32_t* status, hipStream_t s);
 hipError_t launch_gauge1(mem_ctx_t c, int64_t n, float* M, float* beta, float* g,
                          hipStream_t s);
+// cond (nullable): per cell, a lower bound of cond(H) of the FP32 Hessian at the
+// solve's last iterate (+inf where its Cholesky fails; 0 if none assembled)
 hipError_t launch_axi_solve(int64_t n, int P, const float4* tab, const float* M, const float* g,
                             float* beta, const SolveParams& p, int32_t* iters, float* resid,
-                            uint32_t* status, hipStream_t s);
+                            uint32_t* status, hipStream_t s, float* cond = nullptr);
 hipError_t launch_axi_speeds(int64_t n, int P, const float4* tab, const float* beta, const float* g,
                              float ux_min, float ux_max, float* lam, hipStream_t s);
 // A batch of nine-statistic shock problems as the step kernels see it: n
@@ -200,6 +202,9 @@ hipError_t launch_axi_fv2(const AxBatch& b, const float* M, const float* g, cons
                           const float* fLF, const float* fLW, const float* phi,
                           const uint32_t* stI, const float* scal, float* Mout, hipStream_t s);
 hipError_t launch_axi_finish(int P, float* t, float* dt, const float* scal, hipStream_t s);
+// cond_max[p] = max(cond_max[p], max of cond over problem p's cells)
+hipError_t launch_axi_cond_max(const AxBatch& b, const float* cond, float* cond_max,
+                               hipStream_t s);
 hipError_t launch_axi_moments_nc(int64_t n, int P, const float4* tab, const float* alpha,
                                  const float* g, float* M, hipStream_t s);
 hipError_t launch_axi_gauge(int64_t n, float* M, float* beta, float* g, hipStream_t s);

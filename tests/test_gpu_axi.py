@@ -18,7 +18,7 @@ import torch
 
 import mem_inputs
 import paper_2303_02898_amd as mem
-from oracle import axisym
+from oracle import axisym, maxent
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -412,6 +412,84 @@ def test_axi_batch_matches_separate_problems(scheme):
     assert len(set(float(x[4].item()) for x in sep)) == 3   # three different clocks
 
 
+def test_axi_cond_monitor_at_equilibrium_matches_the_oracle():
+    """A uniform Maxwellian in its Hermite gauge (the Mach-3 upstream state on
+    the Mach-3 box).  With exact integrals the Hessian of the orthonormal
+    statistics would be the identity; the box's 8-point Gauss--Legendre blocks
+    leave it about 0.4% away.  The monitor's bound must lie between the
+    oracle's max_i H_ii / min pivot (a bound it takes the larger of) and the
+    exact cond(H) of the oracle's FP64 Hessian at this state, to FP32 rounding
+    and the 1e-6 drift of the state under the closed-form collision target."""
+    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(3.0)
+    a_x, b_x, b_r = axisym.integration_domain(float(v1), float(T1), float(v2), float(T2), 10, 6, 6)
+    box = dict(ux_lo=a_x, ux_hi=b_x, ur_hi=b_r, blocks_x=6, blocks_r=4, order=8)
+    orule = axisym.blockwise_rule(**box)
+    C = 16
+    up = tuple(float(a) for a in (n1, v1, T1))
+    g0 = np.tile([[up[1], np.sqrt(up[2]), np.sqrt(up[2])]], (C, 1))
+    b0 = axisym.maxwellian_beta(np.full(C, up[0]), g0)
+    M0 = axisym.moments(b0, g0, orule)
+    # the oracle: Hessian at the Maxwellian, its pivots and its eigenvalues
+    H = maxent.hessian(b0[:1], np.repeat(b0[:1, :1], 9, 1), axisym.cell_phi(orule, g0[0]),
+                       orule["logw"])[0, 1:, 1:]
+    piv = np.diag(np.linalg.cholesky(H)) ** 2
+    ratio = float(np.max(np.diag(H)) / piv.min())
+    ev = np.linalg.eigvalsh(H)
+    cond = float(ev[-1] / ev[0])
+    r = mem.AxiRule(**box)
+    Md, gd, bd = dev(M0), dev(g0), dev(b0)
+    t = torch.zeros(1, device=DEV)
+    dt = torch.zeros(1, device=DEV)
+    cm = torch.zeros(1, device=DEV)
+    r.step(Md, bd, gd, t, dt, 1.0, up, up, n_steps=0)
+    r.step(Md, bd, gd, t, dt, 1.0, up, up, n_steps=2, cond_max=cm)
+    torch.cuda.synchronize()
+    r.close()
+    print(f"\n[axi cond] equilibrium monitor {cm.item():.8f}, oracle max H_ii / min pivot "
+          f"{ratio:.8f}, exact cond {cond:.8f}", flush=True)
+    assert 1.0 < ratio < cond
+    assert ratio * (1.0 - 1e-4) <= cm.item() <= cond * (1.0 + 1e-5)
+
+
+def test_axi_cond_monitor_bounds_the_oracle_condition_number():
+    """The monitor bounds cond(H) at each solve's solution from below, and six
+    power and inverse iterations bring it close.  The oracle's exact cond(H)
+    (eigenvalues of the 8 x 8 Hessian at each cell's solution, in the gauge of
+    that solve) over 8 LLF steps of the Mach-3 shock on the box brackets it:
+    exact / 2 <= monitor <= 1.05 exact (FP32 Hessians of nearby iterates)."""
+    (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(3.0)
+    a_x, b_x, b_r = axisym.integration_domain(float(v1), float(T1), float(v2), float(T2), 10, 6, 6)
+    box = dict(ux_lo=a_x, ux_hi=b_x, ur_hi=b_r, blocks_x=6, blocks_r=4, order=8)
+    sh = axisym.ShockSolver(3.0, 24, -12.0, 12.0, 5.44, box)
+    left = tuple(float(a) for a in (n1, v1, T1))
+    right = tuple(float(a) for a in (n2, v2, T2))
+    r = mem.AxiRule(**box)
+    M0 = f32(sh.M).astype(np.float64)
+    g0 = f32(sh.g).astype(np.float64)
+    Md, gd = dev(M0), dev(g0)
+    bd = dev(axisym.maxwellian_beta(M0[:, 0], g0))
+    t = torch.zeros(1, device=DEV)
+    dt = torch.zeros(1, device=DEV)
+    cm = torch.zeros(1, device=DEV)
+    r.step(Md, bd, gd, t, dt, sh.dx, left, right, n_steps=0)
+    r.step(Md, bd, gd, t, dt, sh.dx, left, right, n_steps=8, cond_max=cm)
+    torch.cuda.synchronize()
+    r.close()
+    solved = []   # each step's solution and the gauge it was solved in
+    solve = sh._solve
+
+    def recording_solve(M, beta):
+        b = solve(M, beta)
+        solved.append((b.copy(), sh.g.copy()))
+        return b
+    sh._solve = recording_solve
+    for _ in range(8):
+        sh.step()
+    exact = max(float(np.max(_exact_cond(b, g, sh.rule))) for b, g in solved)
+    print(f"\n[axi cond] GPU bound {cm.item():.1f}, oracle max cond(H) {exact:.1f}", flush=True)
+    assert exact / 2.0 <= cm.item() <= 1.05 * exact
+
+
 def test_axi_mach10_flic_shock_paper_run():
     """The paper's single-precision headline run (Sec. 4.5): the Mach-10 normal
     shock on 150 cells of [-47.1, 47.1] (tanh thickness 15.7) on the printed
@@ -500,7 +578,8 @@ def _exact_cond(beta, g, rule):
 def _flic_cond_run(mach, n, x_lo, x_hi, thickness, box, t_end):
     """FLIC from the tanh profile to t_end on the GPU; the largest exact cond(H)
     over the cells, sampled every 500 steps; whether any solve was certified
-    non-realizable."""
+    non-realizable; whether the state stayed finite; the in-kernel monitor's
+    pivot-ratio bound over every step."""
     sh = axisym.ShockSolver(mach, n, x_lo, x_hi, thickness, box, scheme="flic",
                             newton=dict(max_iter=60))
     (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(mach)
@@ -514,11 +593,12 @@ def _flic_cond_run(mach, n, x_lo, x_hi, thickness, box, t_end):
     t = torch.zeros(1, device=DEV)
     dt = torch.zeros(1, device=DEV)
     st = torch.zeros(n, dtype=torch.int32, device=DEV)
+    cm = torch.zeros(1, device=DEV)
     args = (Md, bd, gd, t, dt, sh.dx, left, right)
     r.step(*args, n_steps=0, scheme="flic")
     cmax, steps, nonreal = 0.0, 0, False
     while t.item() < t_end:
-        r.step(*args, n_steps=100, status=st, scheme="flic", use_graph=True)
+        r.step(*args, n_steps=100, status=st, scheme="flic", use_graph=True, cond_max=cm)
         steps += 100
         nonreal = nonreal or bool(np.any(st.cpu().numpy() & mem.ST_NONREALIZABLE))
         if steps % 500 == 0:
@@ -527,7 +607,7 @@ def _flic_cond_run(mach, n, x_lo, x_hi, thickness, box, t_end):
             cmax = max(cmax, float(np.max(c)))
     finite = bool(torch.isfinite(Md).all().item())
     r.close()
-    return cmax, nonreal, finite
+    return cmax, nonreal, finite, cm.item()
 
 
 def test_cell_count_study_on_the_paper_box():
@@ -545,14 +625,15 @@ def test_cell_count_study_on_the_paper_box():
         res[(4, n)] = _flic_cond_run(4.0, n, -16.3, 16.3, 5.44, box4, 10.0)
     for n in (150, 300):
         res[(10, n)] = _flic_cond_run(10.0, n, -47.1, 47.1, 15.7, mem_inputs.AXI_MACH10_BOX, 30.0)
-    for k, (c, nr, fin) in res.items():
+    for k, (c, nr, fin, mon) in res.items():
         print(f"\n[cell count] Mach {k[0]}, {k[1]} cells: max cond {c:.3e}, non-realizable {nr}, "
-              f"finite {fin}", flush=True)
+              f"finite {fin}, monitor bound {mon:.3e}", flush=True)
     for n in (125, 250, 500):
-        c, nr, fin = res[(4, n)]
+        c, nr, fin, mon = res[(4, n)]
         assert fin and not nr and 3e4 < c < 1e6
+        assert c / 2.0 <= mon < np.inf   # the monitor saw every step's solutions
     assert res[(4, 500)][0] >= 0.99 * res[(4, 125)][0]
-    c150, nr150, fin150 = res[(10, 150)]
+    c150, nr150, fin150, _ = res[(10, 150)]
     assert fin150 and not nr150
     assert c150 > 10.0 * res[(4, 500)][0]
     assert res[(10, 300)][1]     # beyond ~160 cells the Mach-10 solves break down
