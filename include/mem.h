@@ -548,7 +548,7 @@ MEM_API mem_err_t mem_axi_speeds(mem_axi_t h, int64_t n_cells, const float* beta
  * then M <- T(g_H, g) M, beta_i <- sum_j T(g, g_H)_ji beta_j for i >= 1
  * (beta_0 kept; beta may be NULL) and g <- g_H.  T is the closed form: 1D
  * Hermite connection coefficients in x times the Laguerre dilation in
- * y = u_bar_r^2/2, evaluated in FP64.  Cells with M_0 <= 0, a non-positive
+ * y = u_bar_r^2/2, evaluated in FP32.  Cells with M_0 <= 0, a non-positive
  * variance or non-finite values are left unchanged.  M[n][9], beta[n][9],
  * g[n][3]: device, in place.  No handle needed. */
 MEM_API mem_err_t mem_axi_gauge(int64_t n_cells, float* M, float* beta, float* g,

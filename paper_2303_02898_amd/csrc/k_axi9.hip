@@ -681,35 +681,35 @@ __constant__ int AX_K[9] = {0, 0, 0, 1, 0, 0, 2, 1, 1};
 
 // p_n(a x + b) = sum_k t[n][k] p_k(x): t = C(n,k) a^k h_{n-k}(b; a^2 - 1) sqrt(k!/n!),
 // h_m(b; c) = E[He_m(X)], X ~ N(b, 1 + c)
-__device__ __forceinline__ void conn_x(double a, double b, double (&t)[5][5]) {
-  const double c = a * a - 1.0;
-  const double h[5] = {1.0, b, b * b + c, b * b * b + 3.0 * b * c,
-                       b * b * b * b + 6.0 * b * b * c + 3.0 * c * c};
-  const double binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0},
+__device__ __forceinline__ void conn_x(float a, float b, float (&t)[5][5]) {
+  const float c = a * a - 1.0f;
+  const float h[5] = {1.0f, b, b * b + c, b * b * b + 3.0f * b * c,
+                       b * b * b * b + 6.0f * b * b * c + 3.0f * c * c};
+  const float binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0},
                               {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
-  const double sf[5] = {1.0, 1.0, 1.41421356237309505, 2.44948974278317810,
-                        4.89897948556635620};
-  double ak = 1.0;
-  double apow[5];
+  const float sf[5] = {1.0f, 1.0f, 1.41421356237309505f, 2.44948974278317810f,
+                        4.89897948556635620f};
+  float ak = 1.0f;
+  float apow[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) { apow[k] = ak; ak *= a; }
 #pragma unroll
   for (int n = 0; n < 5; ++n)
 #pragma unroll
     for (int k = 0; k < 5; ++k)
-      t[n][k] = k <= n ? binom[n][k] * apow[k] * h[n - k] * sf[k] / sf[n] : 0.0;
+      t[n][k] = k <= n ? binom[n][k] * apow[k] * h[n - k] * sf[k] / sf[n] : 0.0f;
 }
 
 // l_k(c y) = sum_k' r[k][k'] l_k'(y) (dilation of the radial variable)
-__device__ __forceinline__ void conn_y(double c, double (&r)[3][3]) {
-  r[0][0] = 1.0; r[0][1] = 0.0; r[0][2] = 0.0;
-  r[1][0] = c - 1.0; r[1][1] = c; r[1][2] = 0.0;
-  r[2][0] = (c - 1.0) * (c - 1.0); r[2][1] = 2.0 * c * (c - 1.0); r[2][2] = c * c;
+__device__ __forceinline__ void conn_y(float c, float (&r)[3][3]) {
+  r[0][0] = 1.0f; r[0][1] = 0.0f; r[0][2] = 0.0f;
+  r[1][0] = c - 1.0f; r[1][1] = c; r[1][2] = 0.0f;
+  r[2][0] = (c - 1.0f) * (c - 1.0f); r[2][1] = 2.0f * c * (c - 1.0f); r[2][2] = c * c;
 }
 
 // T(g', g)_ij = t[a_i][a_j] r[k_i][k_j] with a = s_x/s_x', b = (w - w')/s_x',
 // c = (s_r/s_r')^2
-__device__ __forceinline__ double tij(const double (&t)[5][5], const double (&r)[3][3], int i,
+__device__ __forceinline__ float tij(const float (&t)[5][5], const float (&r)[3][3], int i,
                                       int j) {
   return t[AX_A[i]][AX_A[j]] * r[AX_K[i]][AX_K[j]];
 }
@@ -721,40 +721,40 @@ __global__ void k_axi_gauge(int64_t n, float* __restrict__ M, float* __restrict_
                             float* __restrict__ g) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  double m[9];
+  float m[9];
   bool fin = true;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    m[k] = (double)M[c * 9 + k];
+    m[k] = M[c * 9 + k];
     fin = fin && isfinite(m[k]);
   }
-  const double w = g[c * 3], sx = g[c * 3 + 1], sr = g[c * 3 + 2];
-  if (!fin || !(m[0] > 0.0) || !(sx > 0.0) || !(sr > 0.0)) return;
-  const double m1 = m[1] / m[0];
-  const double exx = 1.41421356237309505 * m[2] / m[0] + 1.0;
-  const double err = 2.0 * (m[3] / m[0] + 1.0);
-  const double vx = exx - m1 * m1;
-  if (!(vx > 0.0) || !(err > 0.0) || !isfinite(vx) || !isfinite(err)) return;
-  const double wH = w + sx * m1, sxH = sx * sqrt(vx), srH = sr * sqrt(0.5 * err);
-  double t[5][5], r[3][3];
+  const float w = g[c * 3], sx = g[c * 3 + 1], sr = g[c * 3 + 2];
+  if (!fin || !(m[0] > 0.0f) || !(sx > 0.0f) || !(sr > 0.0f)) return;
+  const float m1 = m[1] / m[0];
+  const float exx = 1.41421356237309505f * m[2] / m[0] + 1.0f;
+  const float err = 2.0f * (m[3] / m[0] + 1.0f);
+  const float vx = exx - m1 * m1;
+  if (!(vx > 0.0f) || !(err > 0.0f) || !isfinite(vx) || !isfinite(err)) return;
+  const float wH = w + sx * m1, sxH = sx * sqrtf(vx), srH = sr * sqrtf(0.5f * err);
+  float t[5][5], r[3][3];
   conn_x(sx / sxH, (w - wH) / sxH, t);
   conn_y((sr / srH) * (sr / srH), r);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    double acc = 0.0;
+    float acc = 0.0f;
 #pragma unroll
     for (int j = 0; j < 9; ++j) acc += tij(t, r, i, j) * m[j];
     M[c * 9 + i] = (float)acc;
   }
   if (beta) {
-    double b[9];
+    float b[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) b[k] = (double)beta[c * 9 + k];
+    for (int k = 0; k < 9; ++k) b[k] = beta[c * 9 + k];
     conn_x(sxH / sx, (wH - w) / sx, t);
     conn_y((srH / sr) * (srH / sr), r);
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-      double acc = 0.0;
+      float acc = 0.0f;
 #pragma unroll
       for (int j = 1; j < 9; ++j) acc += tij(t, r, j, i) * b[j];
       beta[c * 9 + i] = (float)acc;
@@ -1136,32 +1136,32 @@ __global__ void k_axi_collide(AxBatch b, float* __restrict__ M, const float* __r
                               float mu_ref) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= b.n) return;
-  double m[9];
+  float m[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) m[k] = (double)M[c * 9 + k];
-  const double w = g[c * 3], sx = g[c * 3 + 1], sr = g[c * 3 + 2];
-  const double nn = m[0];
-  if (!(nn > 0.0) || !isfinite(nn)) return;
-  const double ex = m[1] / nn;
-  const double exx = 1.41421356237309505 * m[2] / nn + 1.0;
-  const double err = 2.0 * (m[3] / nn + 1.0);
-  const double pxx = sx * sx * (exx - ex * ex), prr = 0.5 * sr * sr * err;
-  const double T = (pxx + 2.0 * prr) / 3.0;
-  const double Pr = prandtl;
-  const double sxx = T / Pr + (1.0 - 1.0 / Pr) * pxx, srr = T / Pr + (1.0 - 1.0 / Pr) * prr;
-  const double mu = ex;  // (v - w)/s_x with v = w + s_x E[x]
-  const double cv = sxx / (sx * sx) - 1.0;
-  const double hx[5] = {1.0, mu, mu * mu + cv, mu * mu * mu + 3.0 * mu * cv,
-                        mu * mu * mu * mu + 6.0 * mu * mu * cv + 3.0 * cv * cv};
-  const double px[5] = {hx[0], hx[1], hx[2] * 0.70710678118654752, hx[3] * 0.40824829046386302,
-                        hx[4] * 0.20412414523193151};
-  const double th = srr / (sr * sr);
-  const double ly[3] = {1.0, th - 1.0, (th - 1.0) * (th - 1.0)};
-  const double r = (double)f * (double)dtp[b.pid[c] * stride] * Pr * nn / (double)mu_ref;
+  for (int k = 0; k < 9; ++k) m[k] = M[c * 9 + k];
+  const float w = g[c * 3], sx = g[c * 3 + 1], sr = g[c * 3 + 2];
+  const float nn = m[0];
+  if (!(nn > 0.0f) || !isfinite(nn)) return;
+  const float ex = m[1] / nn;
+  const float exx = 1.41421356237309505f * m[2] / nn + 1.0f;
+  const float err = 2.0f * (m[3] / nn + 1.0f);
+  const float pxx = sx * sx * (exx - ex * ex), prr = 0.5f * sr * sr * err;
+  const float T = (pxx + 2.0f * prr) / 3.0f;
+  const float Pr = prandtl;
+  const float sxx = T / Pr + (1.0f - 1.0f / Pr) * pxx, srr = T / Pr + (1.0f - 1.0f / Pr) * prr;
+  const float mu = ex;  // (v - w)/s_x with v = w + s_x E[x]
+  const float cv = sxx / (sx * sx) - 1.0f;
+  const float hx[5] = {1.0f, mu, mu * mu + cv, mu * mu * mu + 3.0f * mu * cv,
+                        mu * mu * mu * mu + 6.0f * mu * mu * cv + 3.0f * cv * cv};
+  const float px[5] = {hx[0], hx[1], hx[2] * 0.70710678118654752f, hx[3] * 0.40824829046386302f,
+                        hx[4] * 0.20412414523193151f};
+  const float th = srr / (sr * sr);
+  const float ly[3] = {1.0f, th - 1.0f, (th - 1.0f) * (th - 1.0f)};
+  const float r = f * dtp[b.pid[c] * stride] * Pr * nn / mu_ref;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const double mt = nn * px[AX_A[i]] * ly[AX_K[i]];
-    M[c * 9 + i] = (float)((1.0 - r) * m[i] + r * mt);
+    const float mt = nn * px[AX_A[i]] * ly[AX_K[i]];
+    M[c * 9 + i] = (1.0f - r) * m[i] + r * mt;
   }
 }
 
@@ -1216,10 +1216,10 @@ __global__ __launch_bounds__(256) void k_axi_dt(AxBatch b, const float* __restri
   }
 }
 
-__device__ __forceinline__ void axi_T(const float* gto, const float* gfrom, double (&t)[5][5],
-                                      double (&r)[3][3]) {
-  const double sxt = gto[1], sx = gfrom[1], srt = gto[2], sr = gfrom[2];
-  conn_x(sx / sxt, ((double)gfrom[0] - (double)gto[0]) / sxt, t);
+__device__ __forceinline__ void axi_T(const float* gto, const float* gfrom, float (&t)[5][5],
+                                      float (&r)[3][3]) {
+  const float sxt = gto[1], sx = gfrom[1], srt = gto[2], sr = gfrom[2];
+  conn_x(sx / sxt, (gfrom[0] - gto[0]) / sxt, t);
   conn_y((sr / srt) * (sr / srt), r);
 }
 
@@ -1236,13 +1236,13 @@ __global__ void k_axi_fv(AxBatch b, const float* __restrict__ M, const float* __
   const int p = b.pid[c];
   int64_t lo, hi;
   ax_range(b, p, lo, hi);
-  const double dt = scal[2 * p];
-  const double dx = b.dx[p];
-  auto rho_of = [](const float* l) { return (double)fmaxf(fabsf(l[0]), fabsf(l[1])); };
-  const double ri = rho_of(lam + c * 2);
-  double acc[9];
+  const float dt = scal[2 * p];
+  const float dx = b.dx[p];
+  auto rho_of = [](const float* l) { return fmaxf(fabsf(l[0]), fabsf(l[1])); };
+  const float ri = rho_of(lam + c * 2);
+  float acc[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = (double)M[c * 9 + k];
+  for (int k = 0; k < 9; ++k) acc[k] = M[c * 9 + k];
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     const bool ghost = side == 0 ? (c <= lo) : (c >= hi - 1);
@@ -1251,24 +1251,24 @@ __global__ void k_axi_fv(AxBatch b, const float* __restrict__ M, const float* __
     const float* Mj = ghost ? gM + gr * 9 : M + j * 9;
     const float* Fj = ghost ? gF + gr * 9 : F + j * 9;
     const float* gj = ghost ? gG + gr * 3 : g + j * 3;
-    const double rj = rho_of(ghost ? glam + gr * 2 : lam + j * 2);
-    const double a = fmax(ri, rj);
-    double t[5][5], r[3][3];
+    const float rj = rho_of(ghost ? glam + gr * 2 : lam + j * 2);
+    const float a = fmaxf(ri, rj);
+    float t[5][5], r[3][3];
     axi_T(g + c * 3, gj, t, r);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      double mj = 0.0, fj = 0.0;
+      float mj = 0.0f, fj = 0.0f;
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        const double tk = tij(t, r, i, k);
-        mj += tk * (double)Mj[k];
-        fj += tk * (double)Fj[k];
+        const float tk = tij(t, r, i, k);
+        mj += tk * Mj[k];
+        fj += tk * Fj[k];
       }
-      const double mi = M[c * 9 + i], fi = F[c * 9 + i];
+      const float mi = M[c * 9 + i], fi = F[c * 9 + i];
       // left face: + dt/dx (1/2 (F_l + F_i) + 1/2 a (M_l - M_i));
       // right face: - dt/dx (1/2 (F_i + F_r) + 1/2 a (M_i - M_r))
-      const double face = side == 0 ? 0.5 * (fj + fi) + 0.5 * a * (mj - mi)
-                                    : -(0.5 * (fi + fj) + 0.5 * a * (mi - mj));
+      const float face = side == 0 ? 0.5f * (fj + fi) + 0.5f * a * (mj - mi)
+                                    : -(0.5f * (fi + fj) + 0.5f * a * (mi - mj));
       acc[i] += dt / dx * face;
     }
   }
@@ -1312,8 +1312,8 @@ __global__ void k_axi_iface(AxBatch b, const float* __restrict__ M0, const float
   const int64_t n = hi - lo;  // the problem's cells
   int64_t j = row - lo - p;   // its interface
   j = j < 0 ? 0 : (j > n ? n : j);
-  const double dt = scal[2 * p];
-  const double dx = b.dx[p];
+  const float dt = scal[2 * p];
+  const float dx = b.dx[p];
   // the problem's cells and ghost rows
   const float *M = M0 + lo * 9, *F = F0 + lo * 9, *g = g0 + lo * 3, *beta = beta0 + lo * 9,
               *lam = lam0 + lo * 2;
@@ -1325,33 +1325,33 @@ __global__ void k_axi_iface(AxBatch b, const float* __restrict__ M0, const float
   // the ghosts repeat beyond both ends
   const bool rr_is_r = j + 1 > n;
   const AxElem RR = axi_elem(rr_is_r ? j + 1 : j + 2, n, M, F, g, beta, lam, gM, gF, gG, gB, glam);
-  auto rho_of = [](const float* l) { return (double)fmaxf(fabsf(l[0]), fabsf(l[1])); };
-  const double a = fmax(rho_of(L.lam), rho_of(R.lam));
-  double t[5][5], r[3][3], t2[5][5], r2[3][3], t3[5][5], r3[3][3];
+  auto rho_of = [](const float* l) { return fmaxf(fabsf(l[0]), fabsf(l[1])); };
+  const float a = fmaxf(rho_of(L.lam), rho_of(R.lam));
+  float t[5][5], r[3][3], t2[5][5], r2[3][3], t3[5][5], r3[3][3];
   axi_T(R.g, L.g, t, r);
   axi_T(R.g, LL.g, t2, r2);
   axi_T(R.g, RR.g, t3, r3);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    double ml = 0.0, fl = 0.0, mll = 0.0, mrr = 0.0;
+    float ml = 0.0f, fl = 0.0f, mll = 0.0f, mrr = 0.0f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const double tk = tij(t, r, i, k);
-      ml += tk * (double)L.M[k];
-      fl += tk * (double)L.F[k];
-      mll += tij(t2, r2, i, k) * (double)LL.M[k];
-      mrr += tij(t3, r3, i, k) * (double)RR.M[k];
+      const float tk = tij(t, r, i, k);
+      ml += tk * L.M[k];
+      fl += tk * L.F[k];
+      mll += tij(t2, r2, i, k) * LL.M[k];
+      mrr += tij(t3, r3, i, k) * RR.M[k];
     }
-    const double mr = R.M[i], fr = R.F[i];
+    const float mr = R.M[i], fr = R.F[i];
     if (rr_is_r) mrr = mr;
-    fLF[row * 9 + i] = (float)(0.5 * (fl + fr) + 0.5 * a * (ml - mr));
-    Mh[row * 9 + i] = (float)(0.5 * (ml + mr) + 0.5 * (dt / dx) * (fl - fr));
-    double ph = 1.0;
+    fLF[row * 9 + i] = 0.5f * (fl + fr) + 0.5f * a * (ml - mr);
+    Mh[row * 9 + i] = 0.5f * (ml + mr) + 0.5f * (dt / dx) * (fl - fr);
+    float ph = 1.0f;
     if (flic) {  // van Leer on both sides: 2 a / (a + b) for a b > 0, else 0; the smaller
-      const double da = ml - mll, db = mr - ml, dc = mrr - mr;
-      const double pl = da * db > 0.0 ? 2.0 * da / (da + db) : 0.0;
-      const double pr = dc * db > 0.0 ? 2.0 * dc / (dc + db) : 0.0;
-      ph = fmin(pl, pr);
+      const float da = ml - mll, db = mr - ml, dc = mrr - mr;
+      const float pl = da * db > 0.0f ? 2.0f * da / (da + db) : 0.0f;
+      const float pr = dc * db > 0.0f ? 2.0f * dc / (dc + db) : 0.0f;
+      ph = fminf(pl, pr);
     }
     phi[row * 9 + i] = (float)ph;
     bI[row * 9 + i] = R.b[i];
@@ -1373,26 +1373,26 @@ __global__ void k_axi_fv2(AxBatch b, const float* __restrict__ M, const float* _
   const int p = b.pid[c];
   int64_t lo, hi;
   ax_range(b, p, lo, hi);
-  const double dt = scal[2 * p];
-  const double dx = b.dx[p];
+  const float dt = scal[2 * p];
+  const float dx = b.dx[p];
   auto face = [&](int64_t j, int i) {
     const bool bad = (stI[j] & (MEM_ST_NONREALIZABLE | MEM_ST_NONFINITE)) != 0;
-    const double lf = fLF[j * 9 + i];
-    return bad ? lf : lf + (double)phi[j * 9 + i] * ((double)fLW[j * 9 + i] - lf);
+    const float lf = fLF[j * 9 + i];
+    return bad ? lf : lf + phi[j * 9 + i] * (fLW[j * 9 + i] - lf);
   };
   const float* gn = c + 1 < hi ? g + (c + 1) * 3 : gG + (2 * p + 1) * 3;
-  double t[5][5], r[3][3];
+  float t[5][5], r[3][3];
   axi_T(g + c * 3, gn, t, r);
   const int64_t fl = c + p;  // the left face's interface row
-  double fr[9];
+  float fr[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) fr[k] = face(fl + 1, k);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    double acc = 0.0;
+    float acc = 0.0f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc += tij(t, r, i, k) * fr[k];
-    Mout[c * 9 + i] = (float)((double)M[c * 9 + i] + dt / dx * (face(fl, i) - acc));
+    Mout[c * 9 + i] = M[c * 9 + i] + dt / dx * (face(fl, i) - acc);
   }
 }
 
