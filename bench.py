@@ -58,17 +58,17 @@ WAVE_FLOP_ITER = 2.0 * (25920 + 15120 + 5808 + 5 * 1728 + 5 * 1728)
 #  * k_assemble3 on the list loop (launch parameters 2,512): averaged over the
 #    timed solve's 24 launches, the first one empty (the cells start at their
 #    gauge's Maxwellian and take the first pass in closed form);
-#  * k_newton_wave: one launch per solve, averaged over the run's four launches.
+#  * k_newton_wave: one launch per solve (12 waves per CU), the run's one launch.
 ASM_TRAFFIC = {
-    "kernel_sha256": "5bd660d93d75a15d1c131793260315a4c315e5ebb76e9c1e720195cbdb8cb737",
-    "fetch_kib": 30801.7, "fetch_scale": 1.99995,
+    "kernel_sha256": "0364a77ce7899adb59bfb4fd47ac06e0b0d562092973764bbaf3a10eebc50cca",
+    "fetch_kib": 30753.2, "fetch_scale": 1.99995,
     "write_kib": 63904.4, "write_scale": 1.0,
     "cells": 65536, "tuning": [2, 512],
 }
 WAVE_TRAFFIC = {
-    "kernel_sha256": "c5932b0c16fd3328bce60fd9c7a73e0cbb8bae2f8a4afecbdd8d485858278bae",
-    "fetch_kib": 28542.9, "fetch_scale": 1.99995,
-    "write_kib": 224895.4, "write_scale": 1.0,
+    "kernel_sha256": "1abd84cadd2bf6ca80fd91c65a93c0c19d859102d80255f57df0ea62434de64b",
+    "fetch_kib": 28939.5, "fetch_scale": 1.99995,
+    "write_kib": 229099.6, "write_scale": 1.0,
     "cells": 65536,
 }
 # the figures depend on the kernels and on the Newton loop that launches them
@@ -242,6 +242,7 @@ def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400, scheme="llf")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     Mh = Md.cpu().numpy()
+    sh = st.cpu().numpy()
     return {"workload": f"Mach-10 normal shock, {n_cells} cells on [-47.1, 47.1], tanh "
                         f"thickness 15.7, {scheme.upper()} in local gauges with ES-BGK halves, "
                         "same box, hipGraph replay",
@@ -249,7 +250,11 @@ def _axi_shock_rate(mem, torch, dev, rule, n_cells=150, steps=400, scheme="llf")
             "cell_steps_per_s": n_cells * steps / el, "t": float(t.item()),
             "finite": bool(np.all(np.isfinite(Mh))),
             "density_ends": [float(Mh[0, 0]), float(Mh[-1, 0])],
-            "cond_bound": float(cm.item())}
+            "cond_bound": float(cm.item()),
+            "last_step_cells": {k: float(np.mean((sh & bit) != 0)) for k, bit in
+                                (("converged", mem.ST_CONVERGED), ("stagnated", mem.ST_STAGNATED),
+                                 ("fp64_direction", mem.ST_FP64),
+                                 ("nonrealizable", mem.ST_NONREALIZABLE))}}
 
 
 def _axi_shock_batch_rate(mem, torch, dev, rule, n_problems=256, steps=100, scheme="llf"):
