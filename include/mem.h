@@ -163,14 +163,17 @@ typedef struct {
                                     directions).  Accumulates over calls; never cleared. */
   int32_t        flux_scheme;    /* MEM_FLUX_LLF, MEM_FLUX_LW or MEM_FLUX_FLIC (Sec. 3.4)  */
   float*         cond_max;       /* device [n_problems] or NULL: running maximum, over the
-                                    steps and the problem's cells, of max d_k / min d_k over
-                                    the LDL^T pivots of the unshifted Hessian of every Newton
-                                    direction of the cells' solves -- a lower bound of
-                                    cond(H) (each pivot of an SPD matrix lies between its
-                                    extreme eigenvalues); +inf where an FP32 pivot was not
-                                    positive.  The conditioning monitor of the paper's
-                                    cell-count study (Sec. 3.5, Sec. 4.6).  Accumulates over
-                                    calls; never cleared.                                   */
+                                    steps and the problem's cells, of a lower bound of
+                                    cond(H) for the FP32 Hessian at each cell's solution
+                                    (from the S row the step's flux pass assembles there):
+                                    |H v| |H^-1 u| for the unit vectors of six power and
+                                    inverse iterations from (1, ..., 1)/sqrt 34, or
+                                    max(max_j |H e_j|, max_k d_k) / min_k d_k over the LDL^T
+                                    pivots d_k if larger; +inf where the FP32 Cholesky of
+                                    that Hessian fails.  The conditioning monitor of the
+                                    paper's cell-count study (Sec. 3.5, Sec. 4.6).  Costs one
+                                    extra kernel per step when set.  Accumulates over calls;
+                                    never cleared.                                          */
   int64_t*       status_counts;  /* device [9] or NULL: after each step's MaxEnt solve of the
                                     cells (and the Maxwellian substitution), entry k is
                                     incremented by the number of cells whose status has bit

@@ -512,7 +512,7 @@ class AxiRule:
         """Alg. 2 time steps of one shock problem (n_steps = 0: set-up only).
         left/right: ghost (n, v, T); t, dt: one-element device tensors;
         use_graph: replay a captured step; cond_max: one-element device tensor,
-        the running max of the pivot-ratio bound of cond(H)."""
+        the running max of the in-kernel lower bound of cond(H)."""
         import torch
         n = M.shape[0]
         pb = AxiShockStruct(n, dx, cfl, prandtl, mu_ref, (_c_f32 * 3)(*left),

@@ -235,8 +235,7 @@ bool wave_solver(mem_ctx_t c, int64_t n) {
 // 4/5 refinement lists.
 mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const SolveParams& p,
                   int max_iter, int poll, int refine, int32_t* iters, float* resid,
-                  uint32_t* status, hipStream_t s, float* cond = nullptr,
-                  bool try_closed_start = false) {
+                  uint32_t* status, hipStream_t s, bool try_closed_start = false) {
   int32_t* ctr = c->w_ctr;
   int32_t* done = refine > 0 ? c->w_list[3] : nullptr;
   MEM_HIP(c, launch_set_ctr(ctr, 8, s));
@@ -244,7 +243,7 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
     // one persistent kernel for the whole Newton loop (counter 7: work queue)
     ProfScope ps(c, 3, s);
     MEM_HIP(c, launch_newton_wave(c, n, M, beta, p, try_closed_start && c->n1d >= 5, &ctr[7],
-                                  iters, resid, status, done, &ctr[3], cond, s));
+                                  iters, resid, status, done, &ctr[3], s));
   } else {
   MEM_HIP(c, launch_init3(c, n, M, beta, c->w_list[0], &ctr[0], iters, resid, status, s));
   {
@@ -260,7 +259,7 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
   const bool closed_start = try_closed_start && c->n1d >= 5;
   if (closed_start)
     MEM_HIP(c, launch_start3(c, n, c->w_list[0], &ctr[0], M, beta, p, c->w_list[1], &ctr[1],
-                             c->w_list[4], &ctr[6], iters, resid, status, done, &ctr[3], cond, s));
+                             c->w_list[4], &ctr[6], iters, resid, status, done, &ctr[3], s));
   // every live cell takes one direction per pass and ends, at the latest, as
   // MAXITER at its max_iter-th: max_iter passes leave no live cell
   for (int it = 0; it < max_iter; ++it) {
@@ -278,8 +277,7 @@ mem_err_t newton3(mem_ctx_t c, int64_t n, const float* M, float* beta, const Sol
     {
       ProfScope ps(c, 1, s);
       MEM_HIP(c, launch_direction3(c, grid, la, ca, M, beta, p, c->w_list[nxt], &ctr[nxt],
-                                   c->w_list[2], &ctr[2], iters, resid, status, done, &ctr[3], s,
-                                   cond));
+                                   c->w_list[2], &ctr[2], iters, resid, status, done, &ctr[3], s));
     }
     MEM_HIP(c, launch_fallback3(c, grid, c->w_list[2], &ctr[2], M, beta, p, c->w_list[nxt], &ctr[nxt],
                                 iters, resid, status, done, &ctr[3], s));
@@ -527,8 +525,7 @@ mem_err_t mem_maxent_solve(mem_ctx_t c, int64_t n, const float* M, float* beta,
   const int poll = opts ? opts->check_every : d.check_every;
   const int refine = opts ? opts->refine : d.refine;
   p.refine = refine;
-  return newton3(c, n, M, beta, p, p.max_iter, poll, refine, iters, resid, status, s, nullptr,
-                 true);
+  return newton3(c, n, M, beta, p, p.max_iter, poll, refine, iters, resid, status, s, true);
 }
 
 mem_err_t mem_maxent_solve_noalloc(mem_ctx_t c, int64_t n, const float* M, float* beta,
@@ -582,7 +579,7 @@ mem_err_t mem_maxent_solve_noalloc(mem_ctx_t c, int64_t n, const float* M, float
   w.prof = false;  // no host-side event bookkeeping
   w.install(c);
   const mem_err_t e = newton3(c, n, M, beta, p, p.max_iter, poll, refine, iters, resid, status,
-                              s, nullptr, true);
+                              s, true);
   own.install(c);
   return e;
 }
@@ -697,12 +694,12 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
   const int refine = opts ? opts->refine : dflt.refine;
   p.refine = refine;
   e = newton3(c, 2 * (int64_t)P, c->w_gM, c->w_gB, p, budget, 0, refine, nullptr, nullptr, nullptr, s,
-              nullptr, true);
+              true);
   if (e != MEM_OK) return e;
   MEM_HIP(c, launch_flux3(c, 2 * (int64_t)P, c->w_gB, c->w_gG, c->w_gF, c->w_gR, true, true, nullptr, s));
   MEM_HIP(c, launch_rmax_init(c, P, s));
   // solve the current state; set dt where the caller asked for one
-  e = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, s, nullptr, true);
+  e = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, s, true);
   if (e != MEM_OK) return e;
   MEM_HIP(c, launch_maxwell_fallback(c, n, M, beta, s));
   MEM_HIP(c, launch_flux3(c, n, beta, g, nullptr, c->w_rho, true, true, status, s));
@@ -711,16 +708,17 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
   // one step of Alg. 2 on stream st (no host synchronisation inside)
   auto step_once = [&](hipStream_t st) -> mem_err_t {
     MEM_HIP(c, launch_collide3(c, n, M, g, 0.f, dt, c->w_prob, Pr, b->mu_ref, st));
-    float* cond = b->cond_max ? c->w_cond : nullptr;
-    if (cond) MEM_HIP(c, launch_zero(n, cond, st));
-    mem_err_t er = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, st, cond);
+    mem_err_t er = newton3(c, n, M, beta, p, budget, 0, refine, nullptr, nullptr, nullptr, st);
     if (er != MEM_OK) return er;
-    if (cond) MEM_HIP(c, launch_cond_max(n, cond, c->w_prob, b->cond_max, st));
     MEM_HIP(c, launch_maxwell_fallback(c, n, M, beta, st));
     if (status) MEM_HIP(c, launch_status_or(n, c->w_status, status, st));
     if (b->iter_hist) MEM_HIP(c, launch_iter_hist(n, c->w_iters, budget + 1, b->iter_hist, st));
     if (b->status_counts) MEM_HIP(c, launch_status_count(n, c->w_status, b->status_counts, st));
     MEM_HIP(c, launch_flux3(c, n, beta, g, c->w_F, c->w_rho, true, true, status, st));
+    if (b->cond_max) {  // the monitor, on the S rows the flux pass left at the solutions
+      MEM_HIP(c, launch_cond3(c, n, c->w_cond, st));
+      MEM_HIP(c, launch_cond_max(n, c->w_cond, c->w_prob, b->cond_max, st));
+    }
     MEM_HIP(c, launch_rho_max(c, n, c->w_rho, c->w_prob, P, st));
     // the transport step never exceeds the CFL limit of its own speeds
     MEM_HIP(c, launch_dt_cap(c, P, b->dx, b->cfl, dt, st));

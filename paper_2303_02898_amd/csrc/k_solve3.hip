@@ -428,11 +428,6 @@ struct DirOut {
   int32_t* next_list; int32_t* next_ctr;
   int32_t* iters_out; float* resid_out; uint32_t* status_out;
   int32_t* done_list; int32_t* done_ctr;  // converged cells (for refinement), may be null
-  // running max per cell of max d_k / min d_k over the LDL^T pivots of the
-  // unshifted Hessian of each direction (every pivot of an SPD matrix lies
-  // between its extreme eigenvalues, so this bounds cond(H) from below); +inf
-  // where a pivot was not positive.  May be null.
-  float* cond;
 };
 
 // Stopping tests of Alg. 1 (residual sign read as 1/2 G^T (H + lambda I)^-1 G)
@@ -802,11 +797,9 @@ __global__ __launch_bounds__(64 * DW) void k_direction3(
   bool to_fp64 = false;
   uint32_t extra = 0;
   float lam = 0.f;
-  float cnd = 0.f;
   for (int tries = 0;; ++tries) {
     load_h(lam);
     factor();
-    if (tries == 0) cnd = ok ? dmax / dmin : __builtin_inff();
     if (tries == 0 && p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
       to_fp64 = isfinite(r);
       break;
@@ -849,7 +842,6 @@ __global__ __launch_bounds__(64 * DW) void k_direction3(
                    : finish_cell(cell, r, res, dfin, extra, p, cs, gdot, iters_w, status_w,
                                  resid_w, rbest_w, itbest_w, o);
     codes[slot] = (int8_t)code;
-    if (o.cond && isfinite(r)) o.cond[cell] = fmaxf(o.cond[cell], cnd);
   }
   code = __shfl(code, lane & 32);
   if (code == 1 && live) {
@@ -908,7 +900,6 @@ __global__ __launch_bounds__(256) void k_start3(
   cs.bmax = 0.70710678118654752f;
   const int code = finish_cell(cell, r, res, true, 0u, p, cs, gdot, iters_w, status_w, resid_w,
                                rbest_w, itbest_w, o);
-  if (o.cond && isfinite(r)) o.cond[cell] = fmaxf(o.cond[cell], 1.f);
   if (code == 1) {
     float* db = dbeta + cell * 36;
     db[0] = 0.f;
@@ -1625,7 +1616,6 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
       float dk = 0.f;  // direction on lane k (beta_k), k >= 1
       uint32_t extra = 0;
       bool dfin = true;
-      float cnd = 1.f;
       cs.bmax = uf(wave_max(kin ? fabsf(bk) : 0.f));
       if (cs.it == 0 && maxw) {
         // closed-form first pass from the gauge Maxwellian: H = I, G = -M/n
@@ -1758,7 +1748,6 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
           asm volatile("" : "+v"(ln));
           load_hcol(Sr, inv0, E, ln, lam, a);
           ok = wave_chol_rl(a, dinv, ln, dmin, dmax);
-          if (tries == 0) cnd = ok ? dmax / dmin : __builtin_inff();
           if (tries == 0 && p.fp64_ratio > 0.f && (!ok || dmin < p.fp64_ratio * dmax)) {
             to64 = isfinite(r);
             break;
@@ -1804,7 +1793,6 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
         }
         dk = kin ? dk : 0.f;
       }
-      if (o.cond && lane == 0 && isfinite(r)) o.cond[cell] = fmaxf(o.cond[cell], cnd);
       code = wave_finish(r, res, dfin, extra, p, cs);
       if (code != 1) break;
       // backtracking line search (k_lse3 with the Armijo test of Alg. 1)
@@ -1963,9 +1951,9 @@ hipError_t launch_start3(mem_ctx_t c, int64_t n, const int32_t* list, const int3
                          const float* M, const float* beta, const SolveParams& p,
                          int32_t* next_list, int32_t* next_ctr, int32_t* asm_list, int32_t* asm_ctr,
                          int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
-                         int32_t* done_ctr, float* cond, hipStream_t s) {
+                         int32_t* done_ctr, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr, cond};
+  DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
   k_start3<<<nblocks(n, 256), 256, 0, s>>>(list, ctr, M, beta, c->w_dbeta, c->w_gdot, c->w_alpha,
                                            c->w_iters, c->w_status, c->w_resid, c->w_L,
                                            c->w_rbest, c->w_itbest, p, c->w_code, c->w_S, o);
@@ -1980,9 +1968,9 @@ hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* lis
                              const SolveParams& p,
                              int32_t* next_list, int32_t* next_ctr, int32_t* fb_list,
                              int32_t* fb_ctr, int32_t* iters, float* resid, uint32_t* status,
-                             int32_t* done_list, int32_t* done_ctr, hipStream_t s, float* cond) {
+                             int32_t* done_list, int32_t* done_ctr, hipStream_t s) {
   if (grid_cells <= 0) return hipSuccess;
-  DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr, cond};
+  DirOut o{next_list, next_ctr, iters, resid, status, done_list, done_ctr};
 #define MEM_DIR(DW)                                                                        \
   k_direction3<DW><<<nblocks(grid_cells, 2 * DW), 64 * DW, 0, s>>>(                       \
       list, ctr, c->w_S, M, c->w_dbeta, c->w_gdot, c->w_alpha, c->w_iters, c->w_status,   \
@@ -2074,10 +2062,10 @@ hipError_t launch_refine_final(mem_ctx_t c, int64_t grid_cells, const int32_t* l
 hipError_t launch_newton_wave(mem_ctx_t c, int64_t n, const float* M, float* beta,
                               const SolveParams& p, bool closed_start, int32_t* queue,
                               int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
-                              int32_t* done_ctr, float* cond, hipStream_t s) {
+                              int32_t* done_ctr, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (c->n1d != 12) return hipErrorNotSupported;
-  DirOut o{nullptr, nullptr, iters, resid, status, done_list, done_ctr, cond};
+  DirOut o{nullptr, nullptr, iters, resid, status, done_list, done_ctr};
   const int wpc = c->tune.wave_per_cu > 0 ? c->tune.wave_per_cu : WAVE_SOLVE_PER_CU;
   const int64_t waves = std::min<int64_t>(n, (int64_t)c->n_cu * wpc);
   k_newton_wave<12><<<(unsigned)waves, 64, 0, s>>>(c->d_t1, queue, n, M, beta, p,
@@ -2089,6 +2077,74 @@ hipError_t launch_newton_wave(mem_ctx_t c, int64_t n, const float* M, float* bet
 hipError_t launch_unpack3(mem_ctx_t c, int64_t n, float* E, float* H, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_unpack3<<<nblocks(n, 128), 128, 0, s>>>(n, c->w_S, E, H);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// conditioning monitor of the time step (Sec. 3.5, Sec. 4.6)
+// --------------------------------------------------------------------------
+// Per cell, a lower bound of cond(H) for the FP32 Hessian at the cell's
+// solution, built from the S row the step's flux pass assembled there.  One
+// wave per cell; lane j < 34 holds column j of H (= row j).  For unit vectors
+// v and u, |H v| <= lambda_max and |H^-1 u| <= 1 / lambda_min, so
+// |H v| |H^-1 u| <= cond(H): v and u come from CE3_ITERS steps of power and
+// inverse iteration from (1, ..., 1)/sqrt 34, the inverse through the register
+// Cholesky.  max(max_j |H e_j|, max_k d_k) / min_k d_k (every LDL^T pivot lies
+// between the extreme eigenvalues) is folded in.  +inf where a pivot fails; 0
+// for a cell whose S row is not usable.
+constexpr int CE3_ITERS = 6;
+__global__ __launch_bounds__(64) void k_cond3(int64_t n, const float* __restrict__ S,
+                                              float* __restrict__ cond) {
+  __shared__ float sS[NCOL + 36];
+  const int64_t c = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (c >= n) return;
+  for (int t = lane; t < NCOL; t += 64) sS[t] = S[c * NCOL + t];
+  __builtin_amdgcn_wave_barrier();
+  const float s00 = uf(sS[0]);
+  float* E = sS + NCOL;
+  if (lane < K3) E[lane] = lane == 0 ? 1.f : sS[lane] / s00;
+  __builtin_amdgcn_wave_barrier();
+  if (!(s00 > 0.f) || !isfinite(s00)) {
+    if (lane == 0) cond[c] = 0.f;
+    return;
+  }
+  float a[NH];
+  load_hcol(sS, 1.f / s00, E, lane, 0.f, a);
+  float cs = 0.f;
+#pragma unroll
+  for (int i = 0; i < NH; ++i) cs = fmaf(a[i], a[i], cs);
+  const float hn = uf(sqrtf(wave_max(lane < NH ? cs : 0.f)));
+  // power iteration on H (before the factorisation overwrites it)
+  const float v0 = lane < NH ? 0.17149858514250882f : 0.f;  // 1 / sqrt 34
+  float v = v0, nv = 0.f;
+  for (int k = 0; k < CE3_ITERS; ++k) {
+    float w = 0.f;
+#pragma unroll
+    for (int i = 0; i < NH; ++i) w = fmaf(a[i], rl(v, i), w);
+    w = lane < NH ? w : 0.f;
+    nv = uf(sqrtf(wave_sum(w * w)));
+    v = w / nv;
+  }
+  float dinv = 1.f, dmin = 0.f, dmax = 0.f;
+  const bool ok = wave_chol_rl(a, dinv, lane, dmin, dmax);
+  float u = v0, nu = 0.f;
+  for (int k = 0; ok && k < CE3_ITERS; ++k) {
+    float w = 0.f, d = 0.f;
+    wave_solve_rl(a, dinv, lane, u, w, d);
+    d = lane < NH ? d : 0.f;
+    nu = uf(sqrtf(wave_sum(d * d)));
+    u = d / nu;
+  }
+  const float est = nv * nu;
+  const float cnd = ok ? fmaxf(isfinite(est) ? est : 0.f, fmaxf(dmax, hn) / dmin)
+                       : __builtin_inff();
+  if (lane == 0) cond[c] = cnd;
+}
+
+hipError_t launch_cond3(mem_ctx_t c, int64_t n, float* cond, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_cond3<<<(unsigned)n, 64, 0, s>>>(n, c->w_S, cond);
   return hipGetLastError();
 }
 

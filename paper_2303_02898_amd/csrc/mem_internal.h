@@ -122,7 +122,7 @@ struct mem_ctx_s {
   float* w_Mnew = nullptr;    // [cap][K]
   float* w_F = nullptr;       // [cap][K]
   float* w_rho = nullptr;     // [cap]
-  float* w_cond = nullptr;    // [cap] pivot-ratio bound of cond(H) of the cells' solves
+  float* w_cond = nullptr;    // [cap] lower bound of cond(H) per cell (the step's monitor)
   // second-order interface fluxes: one row per interface (cells + problems <= cap)
   float* w_hM = nullptr;      // Lax--Wendroff half-step moments [cap][K]
   float* w_hB = nullptr;      // their beta [cap][K]
@@ -244,14 +244,14 @@ hipError_t launch_start3(mem_ctx_t c, int64_t n, const int32_t* list, const int3
                          const float* M, const float* beta, const SolveParams& p,
                          int32_t* next_list, int32_t* next_ctr, int32_t* asm_list, int32_t* asm_ctr,
                          int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
-                         int32_t* done_ctr, float* cond, hipStream_t s);
+                         int32_t* done_ctr, hipStream_t s);
 hipError_t launch_direction3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                              const int32_t* ctr, const float* M, const float* beta,
                              const SolveParams& p,
                              int32_t* next_list, int32_t* next_ctr, int32_t* fb_list,
                              int32_t* fb_ctr, int32_t* iters, float* resid,
                              uint32_t* status, int32_t* done_list, int32_t* done_ctr,
-                             hipStream_t s, float* cond = nullptr);
+                             hipStream_t s);
 hipError_t launch_fallback3(mem_ctx_t c, int64_t grid_cells, const int32_t* list,
                             const int32_t* ctr, const float* M, const float* beta,
                             const SolveParams& p,
@@ -276,7 +276,7 @@ constexpr int WAVE_SOLVE_PER_CU = 12;  // default and most: 3 waves per SIMD
 hipError_t launch_newton_wave(mem_ctx_t c, int64_t n, const float* M, float* beta,
                               const SolveParams& p, bool closed_start, int32_t* queue,
                               int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
-                              int32_t* done_ctr, float* cond, hipStream_t s);
+                              int32_t* done_ctr, hipStream_t s);
 hipError_t launch_unpack3(mem_ctx_t c, int64_t n, float* E, float* H, hipStream_t s);
 hipError_t launch_flux3(mem_ctx_t c, int64_t n, const float* beta, const float* g,
                         float* F, float* rho_or_lam, bool want_lam, bool radius_only,
@@ -303,6 +303,9 @@ hipError_t launch_fv3i(mem_ctx_t c, int64_t n, const float* M, const float* g, c
                        const int64_t* offsets, const float* dx, const float* dt, bool flic,
                        float* Mnew, hipStream_t s);
 hipError_t launch_zero(int64_t n, float* x, hipStream_t s);
+// per cell, a lower bound of cond(H) at the Hessian of the S rows in w_S (the
+// step's flux pass): power and inverse iterations, see k_cond3
+hipError_t launch_cond3(mem_ctx_t c, int64_t n, float* cond, hipStream_t s);
 hipError_t launch_cond_max(int64_t n, const float* cond, const int32_t* prob, float* out,
                            hipStream_t s);
 hipError_t launch_dt_cap(mem_ctx_t c, int P, const float* dx, float cfl, float* dt,

@@ -579,7 +579,7 @@ def _flic_cond_run(mach, n, x_lo, x_hi, thickness, box, t_end):
     """FLIC from the tanh profile to t_end on the GPU; the largest exact cond(H)
     over the cells, sampled every 500 steps; whether any solve was certified
     non-realizable; whether the state stayed finite; the in-kernel monitor's
-    pivot-ratio bound over every step."""
+    lower bound of cond(H) over every step."""
     sh = axisym.ShockSolver(mach, n, x_lo, x_hi, thickness, box, scheme="flic",
                             newton=dict(max_iter=60))
     (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(mach)

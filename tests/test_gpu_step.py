@@ -606,7 +606,8 @@ def test_flic_shock_reaches_steady_state(ctx3):
 
 def test_cond_monitor_is_one_at_equilibrium(ctx3):
     # a uniform Maxwellian in its Hermite gauge: H = E[phi phi^T] - E E^T is the
-    # identity on orthonormal statistics, so every LDL^T pivot is 1
+    # identity on orthonormal statistics, so every pivot, column norm and
+    # power or inverse iterate gives 1
     problem = mem_inputs.shock_problem(1.0, 200, -10.0, 10.0, 2.0)
     cm = torch.zeros(1, device=DEV)
     batch, Md, bd, gd, t, dt, status = _gpu_shock(problem, ctx3, 0)
@@ -620,8 +621,10 @@ def test_cond_monitor_is_one_at_equilibrium(ctx3):
 
 
 def test_cond_monitor_bounds_the_oracle_condition_number(ctx3):
-    # the pivot ratio bounds cond(H) from below; the oracle computes cond(H)
-    # exactly (eigenvalues of the covariance block at each cell's solution)
+    # the monitor bounds cond(H) from below at each cell's solution, and six
+    # power and inverse iterations bring it within a few percent; the oracle
+    # computes cond(H) exactly (eigenvalues of the covariance block of each
+    # cell's last Newton direction)
     args = (3.0, 240, -12.0, 12.0, 3.0)
     problem = mem_inputs.shock_problem(*args)
     cm = torch.zeros(1, device=DEV)
@@ -638,7 +641,7 @@ def test_cond_monitor_bounds_the_oracle_condition_number(ctx3):
         conds.append(float(np.max(ora.last_solve["cond"])))
     exact = max(conds)
     print(f"\n[cond] GPU bound {cm.item():.1f}, oracle max cond(H) {exact:.1f}")
-    assert exact / 20.0 <= cm.item() <= 1.05 * exact
+    assert exact / 2.0 <= cm.item() <= 1.05 * exact
 
 
 def test_strong_shock_stays_finite_and_conservative(ctx3):
