@@ -412,6 +412,35 @@ def test_axi_batch_matches_separate_problems(scheme):
     assert len(set(float(x[4].item()) for x in sep)) == 3   # three different clocks
 
 
+def test_axi_batch_rejects_malformed_offsets():
+    """mem_axi_step_batch reads the offsets back on first use and refuses a
+    layout that does not start at 0, does not end at n_cells or holds an empty
+    problem (MEM_ERR_INVALID_ARG, nothing launched); a good layout then runs."""
+    box = dict(ux_lo=-10.0, ux_hi=14.0, ur_hi=10.0, blocks_x=4, blocks_r=3, order=6)
+    r = mem.AxiRule(**box)
+    n, P = 12, 3
+    up = (1.0, 2.0, 1.0)
+    g0 = np.tile([[up[1], 1.0, 1.0]], (n, 1))
+    b0 = axisym.maxwellian_beta(np.full(n, up[0]), g0)
+    M0 = axisym.moments(b0, g0, axisym.blockwise_rule(**box))
+    Md, gd, bd = dev(M0), dev(g0), dev(b0)
+    t = torch.zeros(P, device=DEV)
+    dt = torch.zeros(P, device=DEV)
+    dxd = torch.full((P,), 0.5, device=DEV)
+    ghd = torch.tensor([list(up) * 2] * P, dtype=torch.float32, device=DEV)
+    for bad in ([1, 4, 8, 12], [0, 4, 8, 11], [0, 4, 4, 12], [0, 8, 4, 12]):
+        with pytest.raises(mem.MemError):
+            r.step_batch(Md, bd, gd, t, dt, torch.tensor(bad, dtype=torch.int64, device=DEV),
+                         dxd, ghd, n_steps=0)
+    assert torch.equal(dt, torch.zeros(P, device=DEV))   # nothing ran
+    good = torch.tensor([0, 4, 8, 12], dtype=torch.int64, device=DEV)
+    r.step_batch(Md, bd, gd, t, dt, good, dxd, ghd, n_steps=0)
+    r.step_batch(Md, bd, gd, t, dt, good, dxd, ghd, n_steps=2)
+    torch.cuda.synchronize()
+    r.close()
+    assert np.all(t.cpu().numpy() > 0) and torch.isfinite(Md).all()
+
+
 def test_axi_cond_monitor_at_equilibrium_matches_the_oracle():
     """A uniform Maxwellian in its Hermite gauge (the Mach-3 upstream state on
     the Mach-3 box).  With exact integrals the Hessian of the orthonormal
