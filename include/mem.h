@@ -313,8 +313,12 @@ MEM_API mem_err_t mem_collide(mem_ctx_t ctx, int64_t n_cells, float* M, const fl
  * of r = (M_l - M_ll)/(M_r - M_l) per moment (ghosts extend beyond the
  * boundary).  An interface whose half-step state the nodes cannot represent
  * keeps the LLF flux.  The cell to an interface's left takes the same flux
- * moved into its own gauge, so the update stays conservative.  No host
- * synchronisation. */
+ * moved into its own gauge, so the update stays conservative.  The batch's
+ * cell_offsets are read back on `stream` and checked on every call (start 0,
+ * end n_cells, every problem at least one cell; else MEM_ERR_INVALID_ARG and
+ * nothing launched): one synchronisation of `stream` per call, before any
+ * launch; the n_steps steps then run without host synchronisation
+ * (mem_conserved makes the same check). */
 MEM_API mem_err_t mem_step(mem_ctx_t ctx, const mem_batch_t* batch, float* M, float* beta,
                            float* g, float* t, float* dt, int32_t n_steps,
                            const mem_solve_opts_t* opts, uint32_t* status,

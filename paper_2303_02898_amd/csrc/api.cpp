@@ -647,7 +647,10 @@ mem_err_t mem_collide(mem_ctx_t c, int64_t n, float* M, const float* g, float h,
 
 // Validates the host fields and the device cell offsets (copied to the host:
 // every kernel indexes neighbours and problems through them).
-static mem_err_t check_batch(mem_ctx_t c, const mem_batch_t* b) {
+// Field and offset checks on every call: the step kernels index neighbours
+// through the offsets, so they are read back (ordered on the caller's stream)
+// each time rather than trusted from an earlier call with the same pointer.
+static mem_err_t check_batch(mem_ctx_t c, const mem_batch_t* b, hipStream_t s) {
   if (!b || b->n_problems <= 0 || b->n_cells < b->n_problems || !b->cell_offsets || !b->dx ||
       !b->M_left || !b->M_right || !b->g_left || !b->g_right || !(b->cfl > 0.f) ||
       !(b->prandtl > 0.5f) || !(b->mu_ref > 0.f) || b->newton_per_step < 1 ||
@@ -656,8 +659,9 @@ static mem_err_t check_batch(mem_ctx_t c, const mem_batch_t* b) {
       b->flux_scheme > MEM_FLUX_FLIC)
     return fail(c, MEM_ERR_INVALID_ARG, "mem_batch_t");
   std::vector<int64_t> off((size_t)b->n_problems + 1);
-  MEM_HIP(c, hipMemcpy(off.data(), b->cell_offsets, off.size() * sizeof(int64_t),
-                       hipMemcpyDeviceToHost));
+  MEM_HIP(c, hipMemcpyAsync(off.data(), b->cell_offsets, off.size() * sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+  MEM_HIP(c, hipStreamSynchronize(s));
   if (off[0] != 0 || off.back() != b->n_cells)
     return fail(c, MEM_ERR_INVALID_ARG, "cell_offsets must start at 0 and end at n_cells");
   for (size_t p = 0; p + 1 < off.size(); ++p)
@@ -670,7 +674,7 @@ mem_err_t mem_step(mem_ctx_t c, const mem_batch_t* b, float* M, float* beta, flo
                    hipStream_t s) {
   if (!c) return MEM_ERR_INVALID_ARG;
   if (c->dim != 3) return fail(c, MEM_ERR_UNSUPPORTED, "mem_step: dim 3 only");
-  mem_err_t e = check_batch(c, b);
+  mem_err_t e = check_batch(c, b, s);
   if (e != MEM_OK) return e;
   if (!M || !beta || !g || !t || !dt || n_steps < 0 || !opts_ok(opts))
     return fail(c, MEM_ERR_INVALID_ARG, "mem_step: arguments");
@@ -783,7 +787,7 @@ mem_err_t mem_conserved(mem_ctx_t c, const mem_batch_t* b, const float* M, const
                         double* out, hipStream_t s) {
   if (!c) return MEM_ERR_INVALID_ARG;
   if (c->dim != 3) return fail(c, MEM_ERR_UNSUPPORTED, "mem_conserved: dim 3 only");
-  mem_err_t e = check_batch(c, b);
+  mem_err_t e = check_batch(c, b, s);
   if (e != MEM_OK) return e;
   if (!M || !g || !out) return fail(c, MEM_ERR_INVALID_ARG, "mem_conserved: arguments");
   MEM_HIP(c, launch_conserved(c, b, M, g, out, s));

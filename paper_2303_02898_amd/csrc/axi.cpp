@@ -486,8 +486,9 @@ mem_err_t mem_axi_step_batch(mem_axi_t h, const mem_axi_batch_t* b, float* M, fl
   // offsets are read back and checked once per (pointer, n_cells, n_problems)
   if (b->cell_offsets != h->v_off || n != h->v_n || np != h->v_P) {
     std::vector<int64_t> off((size_t)np + 1);
-    AXI_HIP(hipMemcpy(off.data(), b->cell_offsets, off.size() * sizeof(int64_t),
-                      hipMemcpyDeviceToHost));
+    AXI_HIP(hipMemcpyAsync(off.data(), b->cell_offsets, off.size() * sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s));
+    AXI_HIP(hipStreamSynchronize(s));
     if (off[0] != 0 || off[np] != n) return MEM_ERR_INVALID_ARG;
     for (int32_t q = 0; q < np; ++q)
       if (off[q + 1] <= off[q]) return MEM_ERR_INVALID_ARG;

@@ -278,6 +278,35 @@ def test_tiny_problems_match_oracle(ctx3, scheme):
         assert err < 1e-4, (k, err)
 
 
+def test_step_rejects_malformed_offsets(ctx3):
+    """mem_step reads the offsets back on every call and refuses a layout that
+    does not start at 0, does not end at n_cells or holds an empty problem
+    (nothing launched), also in place of a layout it has stepped before; the
+    good layout then steps again."""
+    problem = mem_inputs.shock_problem(3.0, 64, -5.0, 5.0, 2.0)
+    batch, Md, bd, gd, t, dt, _ = _gpu_shock(problem, ctx3, 0)
+    two = mem.ShockBatch([0, 32, 64], [problem["dx"]] * 2,
+                         np.repeat(problem["M_left"][None], 2, 0),
+                         np.repeat(problem["M_right"][None], 2, 0),
+                         np.repeat(problem["g_left"][None], 2, 0),
+                         np.repeat(problem["g_right"][None], 2, 0), device=DEV)
+    t2 = torch.zeros(2, device=DEV)
+    dt2 = torch.zeros(2, device=DEV)
+    good = two.offsets.clone()
+    ctx3.step(two, Md, bd, gd, t2, dt2, 1)   # the layout steps once
+    torch.cuda.synchronize()
+    M0 = Md.clone()
+    for bad in ([1, 32, 64], [0, 32, 63], [0, 0, 64], [0, 40, 32]):
+        two.offsets.copy_(torch.tensor(bad, dtype=torch.int64, device=DEV))  # same pointer
+        with pytest.raises(mem.MemError, match="cell_offsets|problem needs"):
+            ctx3.step(two, Md, bd, gd, t2, dt2, 1)
+    assert torch.equal(Md, M0)   # nothing ran
+    two.offsets.copy_(good)
+    ctx3.step(two, Md, bd, gd, t2, dt2, 1)
+    torch.cuda.synchronize()
+    assert torch.isfinite(Md).all() and np.all(t2.cpu().numpy() > 0)
+
+
 def test_step_rejects_bad_batch_fields(ctx3):
     # the C ABI validates the new batch fields itself (the binding's checks aside)
     problem = mem_inputs.shock_problem(3.0, 64, -5.0, 5.0, 2.0)
