@@ -765,8 +765,8 @@ def main():
                          "kernel for calibrating hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the cell batch would be sharded across GPUs without communication.",
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the cell "
+              "batch would be sharded across GPUs without communication.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -840,7 +840,7 @@ def main():
                       "sum-factorised assembly)",
             "achieved": r["wave_tflops"],
             "peak": FP32_VECTOR_UNPACKED,
-            "peak_note": "FP32 vector without packed instructions (disabled in this build): "
+            "peak_note": "FP32 vector without packed instructions (the kernels are compiled without them): "
                          "256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz",
             "unit": "TFLOP/s",
             "frac": r["wave_tflops"] / FP32_VECTOR_UNPACKED,

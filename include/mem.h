@@ -57,7 +57,7 @@ typedef enum {
   MEM_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad option      */
   MEM_ERR_HIP = 2,           /* a HIP runtime call or kernel launch failed   */
   MEM_ERR_NOMEM = 3,         /* device allocation failed                     */
-  MEM_ERR_UNSUPPORTED = 4    /* configuration this build does not implement  */
+  MEM_ERR_UNSUPPORTED = 4    /* configuration the library does not implement */
 } mem_err_t;
 
 /* Arithmetic of the moment/Hessian assembly GEMM. */

@@ -1,0 +1,36 @@
+"""Host-side checks of bench.py's contract (no GPU): the one-GPU rule, the
+peaks its roofline divides by, and the HBM-traffic figures being those
+measured for the kernels as they stand."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert out.returncode == 2
+    assert "one GPU" in (out.stdout + out.stderr)
+
+
+def test_fp32_peaks_follow_from_the_unit_counts():
+    # 256 CUs x 4 SIMDs x 16 lanes x 2 flop (one FMA) x 2.4 GHz without packed
+    # FP32; the published vector figure counts two FMAs per lane per clock
+    unpacked = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+    assert abs(bench.FP32_VECTOR_UNPACKED - unpacked) < 0.05
+    assert abs(bench.FP32_VECTOR_PEAK - 2 * unpacked) < 0.05
+
+
+def test_traffic_figures_belong_to_the_current_kernels():
+    """The counter-derived HBM bytes are pinned to a hash of the kernels' and
+    the Newton loop's source; a change there must come with new FETCH_SIZE /
+    WRITE_SIZE runs (profiles/hbm_traffic_*), or the bench reports null."""
+    assert bench.source_sha(bench._ASM_SRC) == bench.ASM_TRAFFIC["kernel_sha256"]
+    assert bench.source_sha(bench._WAVE_SRC) == bench.WAVE_TRAFFIC["kernel_sha256"]
+    assert bench.measured_traffic(bench.ASM_TRAFFIC, bench._ASM_SRC, "fp32", 65536) > 0
+    assert bench.measured_traffic(bench.WAVE_TRAFFIC, bench._WAVE_SRC, "fp32", 65536) > 0
+    assert bench.measured_traffic(bench.WAVE_TRAFFIC, bench._WAVE_SRC, "bf16x3", 65536) is None

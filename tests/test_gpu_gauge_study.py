@@ -1,5 +1,5 @@
-"""The gauge experiment of Sec. 4.3 ("Gauge transformation accelerates the
-convergence of optimization"), on this build's discretisation: upstream
+"""The gauge experiment of Sec. 4.3 (the Hermite gauge against a fixed one),
+on the 35-moment Gauss-Hermite discretisation: upstream
 Maxwellians of normal shocks for Mach 2..12 (n = 1, T = 1, v = sqrt(5/3) Ma),
 solved in FP32 from the uniform start (beta_i = 0 for i >= 1) once in the
 Hermite gauge of each state and once in the fixed gauge (0, 1, 1), against the

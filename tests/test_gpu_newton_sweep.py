@@ -1,4 +1,4 @@
-"""The Newton comparison of Sec. 4.2 on this build's discretisation: the
+"""The Newton comparison of Sec. 4.2 on the 35-moment Gauss-Hermite discretisation: the
 degree-4 moment M_(400) swept from 0 (equilibrium, n = 1, v = 0, T = 1 in the
 gauge (0, 1, 1)) to 0.5 with all other moments fixed, solved in FP32 from the
 Maxwellian by Alg. 1 (modified Newton: lambda I shift on a failed Cholesky,
