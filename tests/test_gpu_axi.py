@@ -354,8 +354,9 @@ def test_axi_graph_step_matches_eager(scheme):
 def test_axi_batch_matches_separate_problems(scheme):
     """Three shock problems of different Mach number, cell count and dx stepped
     as one batch (mem_axi_step_batch) give bit for bit what three separate
-    mem_axi_step runs give: states, multipliers, gauges, statuses, and each
-    problem's own t and dt, eager and with the captured step."""
+    mem_axi_step runs give: states, multipliers, gauges, statuses, each
+    problem's own t and dt and its conditioning monitor, eager and with the
+    captured step."""
     print(f"\n[gpu] axi batch of 3 shocks vs separate runs, {scheme}", flush=True)
     (n1, v1, T1), (n2, v2, T2) = mem_inputs.rankine_hugoniot(3.0)
     a_x, b_x, b_r = axisym.integration_domain(float(v1), float(T1), float(v2), float(T2), 10, 6, 6)
@@ -377,11 +378,14 @@ def test_axi_batch_matches_separate_problems(scheme):
         t = torch.zeros(1, device=DEV)
         dt = torch.zeros(1, device=DEV)
         st = torch.zeros(sh.M.shape[0], dtype=torch.int32, device=DEV)
+        cm = torch.zeros(1, device=DEV)
         r.step(Md, bd, gd, t, dt, sh.dx, gh[:3], gh[3:], n_steps=0)
         for k in (3, 2):
-            r.step(Md, bd, gd, t, dt, sh.dx, gh[:3], gh[3:], n_steps=k, status=st, scheme=scheme)
+            r.step(Md, bd, gd, t, dt, sh.dx, gh[:3], gh[3:], n_steps=k, status=st, scheme=scheme,
+                   cond_max=cm)
         torch.cuda.synchronize()
-        sep.append((Md.clone(), bd.clone(), gd.clone(), st.clone(), t.clone(), dt.clone()))
+        sep.append((Md.clone(), bd.clone(), gd.clone(), st.clone(), t.clone(), dt.clone(),
+                    cm.clone()))
         r.close()
     sizes = [sh.M.shape[0] for sh in shocks]
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -396,19 +400,20 @@ def test_axi_batch_matches_separate_problems(scheme):
         t = torch.zeros(len(specs), device=DEV)
         dt = torch.zeros(len(specs), device=DEV)
         st = torch.zeros(int(off[-1]), dtype=torch.int32, device=DEV)
+        cm = torch.zeros(len(specs), device=DEV)
         r.step_batch(Md, bd, gd, t, dt, offd, dxd, ghd, n_steps=0)
         for k in (3, 2):
             r.step_batch(Md, bd, gd, t, dt, offd, dxd, ghd, n_steps=k, status=st, scheme=scheme,
-                         use_graph=graph)
+                         use_graph=graph, cond_max=cm)
         torch.cuda.synchronize()
         r.close()
         for p in range(len(specs)):
             a, b = off[p], off[p + 1]
-            got = (Md[a:b], bd[a:b], gd[a:b], st[a:b], t[p:p + 1], dt[p:p + 1])
+            got = (Md[a:b], bd[a:b], gd[a:b], st[a:b], t[p:p + 1], dt[p:p + 1], cm[p:p + 1])
             for k, (x, y) in enumerate(zip(got, sep[p])):
                 assert torch.equal(x, y), (graph, p, k)
-        print(f"  graph={graph}: t = {t.cpu().numpy()}, identical to the separate runs",
-              flush=True)
+        print(f"  graph={graph}: t = {t.cpu().numpy()}, monitor {cm.cpu().numpy()}, identical "
+              "to the separate runs", flush=True)
     assert len(set(float(x[4].item()) for x in sep)) == 3   # three different clocks
 
 
