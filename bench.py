@@ -44,10 +44,12 @@ FP32_VECTOR_UNPACKED = 78.6
 DENSE_FLOP_ITER = 2.43e6
 # k_newton_wave, algorithmic flops per assembled cell-iteration at 12^3 nodes
 # (lower bound): the sum-factorised Hessian assembly (46,848 FMA: 25,920 +
-# 15,120 + 5,808 over the three axes), the exponent of sigma (5 FMA per node)
-# and one line-search trial (5 FMA per node); exp, the coefficient builds, the
-# Cholesky and further trials are not counted
-WAVE_FLOP_ITER = 2.0 * (25920 + 15120 + 5808 + 5 * 1728 + 5 * 1728)
+# 15,120 + 5,808 over the three axes), the exponent of sigma (5 FMA per node),
+# one line-search trial (5 FMA per node), the Cholesky of the 34 x 34 Newton
+# matrix ((34^3 - 34) / 6 = 6,545 FMA) and its two triangular solves
+# (2 x 34 x 33 / 2 = 1,122 FMA); exp, the coefficient builds and further
+# trials are not counted
+WAVE_FLOP_ITER = 2.0 * (25920 + 15120 + 5808 + 5 * 1728 + 5 * 1728 + 6545 + 1122)
 
 # HBM bytes per launch from two rocprofv3 runs of this bench's solve (65,536
 # cells): --pmc FETCH_SIZE, then --pmc WRITE_SIZE, KiB per dispatch, each scaled
@@ -856,9 +858,10 @@ def main():
             "traffic": measured_traffic(WAVE_TRAFFIC, _WAVE_SRC, args.prec, C),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flop_per_cell_iteration": WAVE_FLOP_ITER,
-            "flop_note": "lower bound: sum-factorised assembly, the exponent of sigma and one "
-                         "line-search trial per assembled cell-iteration; exp, coefficient "
-                         "builds, Cholesky and further trials not counted",
+            "flop_note": "lower bound: sum-factorised assembly, the exponent of sigma, one "
+                         "line-search trial, the 34 x 34 Cholesky and its two triangular "
+                         "solves per assembled cell-iteration; exp, coefficient builds and "
+                         "further trials not counted",
             "assembled_cell_iterations_per_step": r["assembled_cell_iterations"],
             "launches": r["wave_launches"],
             "avg_launch_ms": r["wave_avg_ms"],

@@ -34,3 +34,18 @@ def test_traffic_figures_belong_to_the_current_kernels():
     assert bench.measured_traffic(bench.ASM_TRAFFIC, bench._ASM_SRC, "fp32", 65536) > 0
     assert bench.measured_traffic(bench.WAVE_TRAFFIC, bench._WAVE_SRC, "fp32", 65536) > 0
     assert bench.measured_traffic(bench.WAVE_TRAFFIC, bench._WAVE_SRC, "bf16x3", 65536) is None
+
+
+def test_wave_flop_count_includes_the_newton_solve():
+    """The persistent kernel's per-iteration count carries the Cholesky of the
+    34 x 34 Newton matrix and its forward and backward solves, counted here by
+    walking the loops of a textbook column Cholesky."""
+    n = 34
+    chol = 0
+    for j in range(n):
+        chol += j                      # diagonal: j products subtracted
+        chol += (n - 1 - j) * j        # each entry below it: j products
+    tri = 2 * sum(range(n))            # row i of a triangular solve: i products
+    assert (chol, tri) == (6545, 1122)
+    assembly = 25920 + 15120 + 5808 + 5 * 1728 + 5 * 1728
+    assert bench.WAVE_FLOP_ITER == 2 * (assembly + chol + tri)
