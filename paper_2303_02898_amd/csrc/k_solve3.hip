@@ -1479,53 +1479,79 @@ __device__ __forceinline__ float uf(float v) {
 }
 __device__ __forceinline__ int ui(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Uniform minimum and maximum over the wave (butterfly, then lane 0's value in
+// scalar registers).
+template <typename T>
+__device__ __forceinline__ T wave_min_u(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const T o = __shfl_xor(v, off);
+    v = o < v ? o : v;
+  }
+  return rl(v, 0);
+}
+template <typename T>
+__device__ __forceinline__ T wave_max_u(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const T o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  return rl(v, 0);
+}
+
 // Right-looking Cholesky (as wave_chol) with the rows in registers only: lane
 // i holds row i of A, and step k broadcasts row k from lane k with readlane
 // (scalar registers), so no LDS round trip sits in the chain from one pivot to
 // the next.  Afterwards lane i keeps a[k] = L[i][k] L[k][k] for k < i (frozen
-// at step k) and lane k keeps dinv = 1 / L[k][k]; the pivot is uniform, so a
-// failed factorisation returns on every lane at the same step.
+// at step k) and lane k keeps dinv = 1 / L[k][k].  Each step only parks its
+// pivot on lane k: the test of the pivots, their range and the reciprocal
+// roots are taken once after the last step, so no branch or bookkeeping sits
+// in the chain from one pivot to the next.  A pivot that is not positive and
+// finite leaves NaN or infinite values behind it in the registers; the test
+// after the last step still finds that pivot on its lane and reports the
+// factorisation as failed.
 template <typename T>
 __device__ __forceinline__ bool wave_chol_rl(T (&a)[NH], T& dinv, int lane, T& dmin, T& dmax) {
-  dmin = (T)FLT_MAX; dmax = 0;
-  dinv = 1;
+  T dk = 1;
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
     const T d = rl(a[k], k);
-    if (!((d > (T)0) && isfinite(d))) return false;
-    dmin = d < dmin ? d : dmin;
-    dmax = d > dmax ? d : dmax;
+    if (lane == k) dk = d;
     const T inv = rsq(d);
-    if (lane == k) dinv = inv;
     const T cj = lane > k ? a[k] * (inv * inv) : (T)0;
 #pragma unroll
     for (int i = k + 1; i < NH; ++i) a[i] = fma(-rl(a[i], k), cj, a[i]);
   }
-  return true;
+  const bool ok = __all(lane >= NH || ((dk > (T)0) && isfinite(dk)));
+  dinv = lane < NH ? rsq(dk) : (T)1;
+  dmin = ok ? wave_min_u(lane < NH ? dk : (T)FLT_MAX) : (T)0;
+  dmax = ok ? wave_max_u(lane < NH ? dk : (T)0) : (T)0;
+  return ok;
 }
 
 // Forward L w = b and backward L^T d = w on the registers wave_chol_rl leaves:
-// lane i holds b_i and gets w_i, d_i.
+// lane i holds b_i and gets w_i, d_i.  Lane k's running sum is final once
+// step k has read it (later steps update only the lanes below or above it), so
+// w and d are scaled on every lane at once after each sweep.
 template <typename T>
 __device__ __forceinline__ void wave_solve_rl(const T (&a)[NH], T dinv, int lane, T b, T& w,
                                               T& d) {
   T acc = b;
-  w = 0;
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
     const T ik = rl(dinv, k);
     const T wk = rl(acc, k) * ik;
-    if (lane == k) w = wk;
     if (lane > k && lane < NH) acc = fma(-(a[k] * ik), wk, acc);
   }
+  w = lane < NH ? acc * dinv : (T)0;
   T acc2 = w;
-  d = 0;
 #pragma unroll
   for (int i = NH - 1; i >= 0; --i) {
     const T di = rl(acc2 * dinv, i);
-    if (lane == i) d = di;
     if (lane < i) acc2 = fma(-a[i] * dinv, di, acc2);
   }
+  d = lane < NH ? acc2 * dinv : (T)0;
 }
 
 // LDS of one wave (floats).  W holds one chunk of P1 and of P2 during the
@@ -1708,28 +1734,33 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
           }
           __builtin_amdgcn_wave_barrier();
           // stage 3: pair column col of triple (aa', bc) gains
-          // sum_{i in chunk} H_aa'(x_i) P2[bc][i]
+          // sum_{i in chunk} H_aa'(x_i) P2[bc][i].  A column that is no pair
+          // (entry 0xffff) reads entry 0 and is zeroed after the last chunk, so
+          // the loop has no divergent branch and its loads can all be issued
+          // ahead of the FMAs.
 #pragma unroll
           for (int r = 0; r < SF_R3; ++r) {
-            const uint32_t v = (s3p[r >> 1] >> (16 * (r & 1))) & 0xffffu;
-            if (v != 0xffffu) {
-              const int A = (int)(v & 15u), bc = (int)(v >> 4);
-              const float4 h = *reinterpret_cast<const float4*>(L.sHp + A * NT + x0);
-              const float4 b = *reinterpret_cast<const float4*>(P2 + bc * SF_XC);
-              float acc = tcol[r];
-              acc = fmaf(h.x, b.x, acc);
-              acc = fmaf(h.y, b.y, acc);
-              acc = fmaf(h.z, b.z, acc);
-              acc = fmaf(h.w, b.w, acc);
-              tcol[r] = acc;
-            }
+            const uint32_t v0 = (s3p[r >> 1] >> (16 * (r & 1))) & 0xffffu;
+            const uint32_t v = v0 == 0xffffu ? 0u : v0;
+            const int A = (int)(v & 15u), bc = (int)(v >> 4);
+            const float4 h = *reinterpret_cast<const float4*>(L.sHp + A * NT + x0);
+            const float4 b = *reinterpret_cast<const float4*>(P2 + bc * SF_XC);
+            float acc = tcol[r];
+            acc = fmaf(h.x, b.x, acc);
+            acc = fmaf(h.y, b.y, acc);
+            acc = fmaf(h.z, b.z, acc);
+            acc = fmaf(h.w, b.w, acc);
+            tcol[r] = acc;
           }
           __builtin_amdgcn_wave_barrier();
         }
         // the S row over the dead chunk buffers
         float* Sr = L.W;
 #pragma unroll
-        for (int r = 0; r < SF_R3; ++r) Sr[lane + 64 * r] = tcol[r];
+        for (int r = 0; r < SF_R3; ++r) {
+          const uint32_t v0 = (s3p[r >> 1] >> (16 * (r & 1))) & 0xffffu;
+          Sr[lane + 64 * r] = v0 == 0xffffu ? 0.f : tcol[r];
+        }
         __builtin_amdgcn_wave_barrier();
         // gradient, residual and Newton direction (k_direction3 / k_fallback3)
         const float s00 = uf(Sr[0]);
