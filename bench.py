@@ -68,9 +68,9 @@ ASM_TRAFFIC = {
     "cells": 65536, "tuning": [2, 512],
 }
 WAVE_TRAFFIC = {
-    "kernel_sha256": "11ab32dfbf010e45d0e8fb75fd6917dcb78c3954cadefab2459153abe7ecf1a7",
-    "fetch_kib": 25704.9, "fetch_scale": 1.99995,
-    "write_kib": 222619.5, "write_scale": 1.0,
+    "kernel_sha256": "c2e02af5c21423f7cfe13871365a2ed4d392b92015bba5663a1023040a74a212",
+    "fetch_kib": 27497.7, "fetch_scale": 1.99995,
+    "write_kib": 227653.9, "write_scale": 1.0,
     "cells": 65536,
 }
 # the figures depend on the kernels and on the Newton loop that launches them

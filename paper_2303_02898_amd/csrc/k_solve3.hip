@@ -530,6 +530,8 @@ __device__ __forceinline__ double rl(double v, int src) {
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 
 // Lm: this wave's LDS copy of L, row k = column k of L ([NH][LST]).  At step k
 // every lane publishes its L[lane][k] with one LDS write and reads column k
@@ -1518,8 +1520,10 @@ __device__ __forceinline__ bool wave_chol_rl(T (&a)[NH], T& dinv, int lane, T& d
   for (int k = 0; k < NH; ++k) {
     const T d = rl(a[k], k);
     if (lane == k) dk = d;
-    const T inv = rsq(d);
-    const T cj = lane > k ? a[k] * (inv * inv) : (T)0;
+    // the mask is applied to a[k] (ready with the pivot), so only the
+    // reciprocal's products sit between one pivot and the next
+    const T ak = lane > k ? a[k] : (T)0;
+    const T cj = ak * rcp(d);
 #pragma unroll
     for (int i = k + 1; i < NH; ++i) a[i] = fma(-rl(a[i], k), cj, a[i]);
   }
@@ -1537,19 +1541,22 @@ __device__ __forceinline__ bool wave_chol_rl(T (&a)[NH], T& dinv, int lane, T& d
 template <typename T>
 __device__ __forceinline__ void wave_solve_rl(const T (&a)[NH], T dinv, int lane, T b, T& w,
                                               T& d) {
+  // Each step's coefficient carries both reciprocal roots, so the chain from
+  // one lane's running sum to the next is a broadcast and one FMA.
   T acc = b;
 #pragma unroll
   for (int k = 0; k < NH; ++k) {
     const T ik = rl(dinv, k);
-    const T wk = rl(acc, k) * ik;
-    if (lane > k && lane < NH) acc = fma(-(a[k] * ik), wk, acc);
+    const T ck = (lane > k && lane < NH) ? a[k] * (ik * ik) : (T)0;
+    acc = fma(-ck, rl(acc, k), acc);
   }
   w = lane < NH ? acc * dinv : (T)0;
   T acc2 = w;
 #pragma unroll
   for (int i = NH - 1; i >= 0; --i) {
-    const T di = rl(acc2 * dinv, i);
-    if (lane < i) acc2 = fma(-a[i] * dinv, di, acc2);
+    const T ii = rl(dinv, i);
+    const T ci = lane < i ? a[i] * (dinv * ii) : (T)0;
+    acc2 = fma(-ci, rl(acc2, i), acc2);
   }
   d = lane < NH ? acc2 * dinv : (T)0;
 }
