@@ -1283,8 +1283,9 @@ __global__ void k_unpack3(int64_t n, const float* __restrict__ S, float* E, floa
 // grid-wide barrier or a launch per Newton pass).  Every step is the one of the
 // list-based kernels above: the stopping tests and book-keeping, the
 // lambda-shifted Cholesky with the FP64 switch on the pivot ratio, the Armijo
-// line search on the sum-factorised exponent, the closed-form first pass from
-// the gauge Maxwellian.
+// line search (a full step once full steps are being taken is tested from the
+// next pass's own assembly, backtracking on the sum-factorised exponent), the
+// closed-form first pass from the gauge Maxwellian.
 //
 // The Hessian assembly exploits the tensor grid (x_i, x_j, x_l) and the product
 // basis phi_(abc) = h_a h_b h_c:
@@ -1645,6 +1646,39 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
     float r = 0.f, res = 0.f;
     int code = 1;
     bool ident_S = false;  // closed-form pass: S is the identity (refinement reads it)
+    // The full Newton step is tried by the next pass's own assembly: that
+    // pass's sum of sigma gives log Z at the trial point, so accepting the
+    // full step under the Armijo test needs no log-sum-exp pass of its own.
+    // pending: sB holds the trial point bk + dkp; L0p and gdtp are the dual
+    // value and the directional term of the step it was taken from.
+    bool pending = false;
+    float dkp = 0.f, L0p = 0.f, gdtp = 0.f;
+    // backtracking line search of Alg. 1 from alpha = 1 along dv (k_lse3 with
+    // the Armijo test); sVb must hold the exponent coefficients at bk
+    auto backtrack = [&](float dv, float L0v, float gdtv) {
+      if (lane < 36) L.sB[36 + lane] = lane < K3 ? dv : 0.f;
+      __builtin_amdgcn_wave_barrier();
+      build_v<NT>(L.sB + 36, L.sH, L.sVd, lane);
+      __builtin_amdgcn_wave_barrier();
+      float alpha = 1.f;
+      for (int s = 0;; ++s) {
+        const float lzs = uf(wave_lse<true, NT>(lane, alpha, L.sH, L.sVb, L.sVd));
+        const float bs = fmaf(alpha, dv, bk);
+        const float Ls = uf(lzs - wave_sum(bs * mn));
+        const float LD = L0v - Ls;
+        const float gradD = -p.c * alpha * gdtv;
+        const bool sat = (LD - gradD) >= -(p.atol + p.rtol * fabsf(LD));
+        const bool last = sat || s >= p.max_ls;
+        bk = (last && kin) ? bs : bk;
+        if (last) {
+          lz = lzs;
+          cs.L = Ls;
+          cs.alpha = alpha;
+          break;
+        }
+        alpha *= 0.5f;
+      }
+    };
     for (;;) {
       float dk = 0.f;  // direction on lane k (beta_k), k >= 1
       uint32_t extra = 0;
@@ -1661,8 +1695,8 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
         ident_S = true;
       } else {
         ident_S = false;
-        // rebuild the exponent coefficients at the current beta
-        if (lane < 36) L.sB[lane] = bk;
+        // the exponent coefficients at the current beta, or at the trial point
+        if (!pending && lane < 36) L.sB[lane] = bk;
         __builtin_amdgcn_wave_barrier();
         build_v<NT>(L.sB, L.sH, L.sVb, lane);
         __builtin_amdgcn_wave_barrier();
@@ -1771,6 +1805,36 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
         __builtin_amdgcn_wave_barrier();
         // gradient, residual and Newton direction (k_direction3 / k_fallback3)
         const float s00 = uf(Sr[0]);
+        if (pending) {
+          // Armijo test of the full step from this assembly: the sum of sigma,
+          // shifted by the old log Z, is exp of the change of log Z.  Outside a
+          // range of e^(+-20) (or if the test fails) the step goes through the
+          // backtracking search of Alg. 1 from alpha = 1, and the accepted
+          // point is assembled afresh.
+          pending = false;
+          const float bt = fmaf(1.f, dkp, bk);
+          bool accept = false;
+          float lzt = 0.f, Lt = 0.f;
+          if (isfinite(s00) && s00 > 2e-9f && s00 < 5e8f) {
+            lzt = lz + __logf(s00);
+            Lt = uf(lzt - wave_sum(bt * mn));
+            const float LD = L0p - Lt;
+            const float gradD = -p.c * gdtp;
+            accept = (LD - gradD) >= -(p.atol + p.rtol * fabsf(LD)) || p.max_ls <= 0;
+          }
+          if (!accept) {
+            if (lane < 36) L.sB[lane] = bk;
+            __builtin_amdgcn_wave_barrier();
+            build_v<NT>(L.sB, L.sH, L.sVb, lane);
+            backtrack(dkp, L0p, gdtp);
+            continue;  // assemble at the accepted point
+          }
+          bk = kin ? bt : bk;
+          lz = lzt;
+          cs.L = Lt;
+          cs.alpha = 1.f;
+          cs.bmax = uf(wave_max(kin ? fabsf(bk) : 0.f));
+        }
         const float inv0 = 1.f / s00;
         float* E = L.W + NCOL;
         if (lane < K3) E[lane] = lane == 0 ? 1.f : Sr[lane] * inv0;
@@ -1833,29 +1897,15 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
       }
       code = wave_finish(r, res, dfin, extra, p, cs);
       if (code != 1) break;
-      // backtracking line search (k_lse3 with the Armijo test of Alg. 1)
-      if (lane < 36) L.sB[36 + lane] = lane < K3 ? dk : 0.f;
-      __builtin_amdgcn_wave_barrier();
-      build_v<NT>(L.sB + 36, L.sH, L.sVd, lane);
-      __builtin_amdgcn_wave_barrier();
-      const float L0 = cs.L, gdt = -2.f * res;
-      float alpha = 1.f;
-      for (int s = 0;; ++s) {
-        const float lzt = uf(wave_lse<true, NT>(lane, alpha, L.sH, L.sVb, L.sVd));
-        const float bt = fmaf(alpha, dk, bk);
-        const float Lt = uf(lzt - wave_sum(bt * mn));
-        const float LD = L0 - Lt;
-        const float gradD = -p.c * alpha * gdt;
-        const bool sat = (LD - gradD) >= -(p.atol + p.rtol * fabsf(LD));
-        const bool last = sat || s >= p.max_ls;
-        bk = (last && kin) ? bt : bk;
-        if (last) {
-          lz = lzt;
-          cs.L = Lt;
-          cs.alpha = alpha;
-          break;
-        }
-        alpha *= 0.5f;
+      if (cs.it >= 2 && cs.alpha == 1.f) {
+        // full steps are being taken: try this one by the next pass
+        dkp = dk;
+        L0p = cs.L;
+        gdtp = -2.f * res;
+        if (lane < 36) L.sB[lane] = fmaf(1.f, dk, bk);
+        pending = true;
+      } else {
+        backtrack(dk, cs.L, -2.f * res);
       }
     }
     // results of the cell
