@@ -20,6 +20,7 @@ Prints ONE JSON line.  Single-GPU build: --gpus above 1 exits with a message.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -88,6 +89,19 @@ _WAVE_SRC = (("paper_2303_02898_amd/csrc/k_solve3.hip",
               "hipError_t launch_newton_wave(", "hipError_t launch_unpack3("),
              ("paper_2303_02898_amd/csrc/api.cpp",
               "mem_err_t newton3(", "// Process-wide tuning results"))
+
+
+def strict_json(v):
+    """The bench line as strict JSON: a non-finite float (a conditioning bound
+    whose Cholesky failed, say) is written as the string "inf", "-inf" or
+    "nan"."""
+    if isinstance(v, float) and not math.isfinite(v):
+        return "nan" if v != v else ("inf" if v > 0 else "-inf")
+    if isinstance(v, dict):
+        return {k: strict_json(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [strict_json(x) for x in v]
+    return v
 
 
 def source_sha(spans):
@@ -779,7 +793,8 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     if args.only_paper_discretisation:
-        print(json.dumps({"paper_discretisation": paper_discretisation(mem, torch, dev)}),
+        print(json.dumps(strict_json({"paper_discretisation": paper_discretisation(mem, torch, dev)}),
+                         allow_nan=False),
               flush=True)
         return
     if args.copy_mib > 0:
@@ -933,7 +948,7 @@ def main():
             line["ragged"] = ragged_rate(mem, torch, dev, args.ragged_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(M32, b032, args.cpu_sample)
-    print(json.dumps(line), flush=True)
+    print(json.dumps(strict_json(line), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

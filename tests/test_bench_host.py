@@ -50,3 +50,12 @@ def test_wave_flop_count_includes_the_newton_solve():
     assert (chol, tri) == (6545, 1122)
     assembly = 25920 + 15120 + 5808 + 5 * 1728
     assert bench.WAVE_FLOP_ITER == 2 * (assembly + chol + tri)
+
+
+def test_bench_line_is_strict_json():
+    """A non-finite figure (a conditioning bound whose Cholesky failed) must not
+    turn the bench line into non-standard JSON."""
+    import json
+    line = {"a": float("inf"), "b": [1.0, float("nan")], "c": {"d": -float("inf"), "e": 2}}
+    out = json.dumps(bench.strict_json(line), allow_nan=False)
+    assert json.loads(out) == {"a": "inf", "b": [1.0, "nan"], "c": {"d": "-inf", "e": 2}}
