@@ -69,9 +69,9 @@ ASM_TRAFFIC = {
     "cells": 65536, "tuning": [2, 512],
 }
 WAVE_TRAFFIC = {
-    "kernel_sha256": "73ff79dfa495fda3b241de0790623e701e898728356669ea83209153dca329be",
-    "fetch_kib": 22970.6, "fetch_scale": 1.99995,
-    "write_kib": 211305.6, "write_scale": 1.0,
+    "kernel_sha256": "b103023626336613d16bf51652ebabcf672a2cae42a072d69899ef8e3c068e12",
+    "fetch_kib": 22796.6, "fetch_scale": 1.99995,
+    "write_kib": 211239.4, "write_scale": 1.0,
     "cells": 65536,
 }
 # the figures depend on the kernels and on the Newton loop that launches them
@@ -83,6 +83,11 @@ _ASM_SRC = (("paper_2303_02898_amd/csrc/k_solve3.hip",
             ("paper_2303_02898_amd/csrc/api.cpp",
              "mem_err_t newton3(", "// Process-wide tuning results"))
 _WAVE_SRC = (("paper_2303_02898_amd/csrc/k_solve3.hip",
+              "__device__ __forceinline__ float rl(float v, int src)",
+              "// Lm: this wave's LDS copy of L"),
+             ("paper_2303_02898_amd/csrc/k_solve3.hip",
+              "// Column `lane` of H = S/s00 - E E^T", "constexpr int DIR_WAVES"),
+             ("paper_2303_02898_amd/csrc/k_solve3.hip",
               "// Unordered pair (p, q) of one-dimensional Hermite indices",
               "hipError_t launch_set_ctr("),
              ("paper_2303_02898_amd/csrc/k_solve3.hip",

@@ -620,10 +620,18 @@ __device__ __forceinline__ void load_hcol(const float* Sc, T inv0, const T* E, i
                                           T (&a)[NH]) {
   const int j = lane < NH ? lane : 0;
   const T ej = E[j + 1];
+  // column pair_col(min + 1, max + 1) of S: row i + 1 of the pair triangle at
+  // column j + 1 for i < j, row j + 1 at column i + 1 for i >= j; both are a
+  // row's diagonal entry plus an offset, so the index is one add and a select
+  const int dj = pair_col(j + 1, j + 1) - j;
 #pragma unroll
   for (int i = 0; i < NH; ++i) {
-    const int lo = i < j ? i : j, hi = i < j ? j : i;
-    a[i] = (T)Sc[pair_col(lo + 1, hi + 1)] * inv0 - E[i + 1] * ej + (i == j ? lam : (T)0);
+    const int col = i < j ? pair_col(i + 1, i + 1) - i + j : dj + i;
+    a[i] = (T)Sc[col] * inv0 - E[i + 1] * ej;
+  }
+  if (lam != (T)0) {  // uniform: only the shifted retries of Alg. 1
+#pragma unroll
+    for (int i = 0; i < NH; ++i) a[i] += i == j ? lam : (T)0;
   }
 }
 
