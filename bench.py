@@ -69,9 +69,9 @@ ASM_TRAFFIC = {
     "cells": 65536, "tuning": [2, 512],
 }
 WAVE_TRAFFIC = {
-    "kernel_sha256": "b103023626336613d16bf51652ebabcf672a2cae42a072d69899ef8e3c068e12",
-    "fetch_kib": 22796.6, "fetch_scale": 1.99995,
-    "write_kib": 211239.4, "write_scale": 1.0,
+    "kernel_sha256": "bc72dee0fe29965052a6e8ca28194e4903143fc812b59aa6c0cccb38e15653ed",
+    "fetch_kib": 21379.1, "fetch_scale": 1.99995,
+    "write_kib": 218310.4, "write_scale": 1.0,
     "cells": 65536,
 }
 # the figures depend on the kernels and on the Newton loop that launches them

@@ -1617,7 +1617,8 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
     if (lane == 0) got = atomicAdd(queue, 1);
     const int slot = __builtin_amdgcn_readlane(got, 0);
     if ((int64_t)slot >= ncell) break;
-    const int64_t cell = slot;
+    // o.next_list, when given, is the order of the cells (a permutation)
+    const int64_t cell = o.next_list ? (int64_t)ui(o.next_list[slot]) : (int64_t)slot;
     const float* Mc = M + cell * K3;
     float* bc = beta + cell * K3;
     const bool kin = lane >= 1 && lane < K3;
@@ -2155,15 +2156,101 @@ hipError_t launch_refine_final(mem_ctx_t c, int64_t grid_cells, const int32_t* l
 
 // Persistent Newton solve of cells 0..n-1 (one wave per live cell); ctr[7] is
 // the work queue (zeroed by the caller).
+// Order in which the persistent kernel takes its cells.  A cell's Newton
+// iterations grow with how far its normalised moments lie from the Maxwellian
+// it starts from; taking the far ones first leaves short solves for the end
+// of the queue, where the grid drains.  Counting sort on max_k |M_k| / M_0
+// (k >= 1), two buckets per octave over [2^-8, 2^8), largest first; within a
+// bucket the order is arbitrary (each cell's solve does not depend on it).
+constexpr int ORD_NB = 32;
+constexpr int ORD_TPB = 256;
+
+__device__ __forceinline__ int order_bucket(const float* __restrict__ m) {
+  float g = 0.f;
+  for (int k = 1; k < K3; ++k) g = fmaxf(g, fabsf(m[k]));
+  g = g / m[0];
+  const float f = (g > 0.f && isfinite(g))
+                      ? fminf(fmaxf(floorf(2.f * log2f(g)) + 16.f, 0.f), (float)(ORD_NB - 1))
+                      : 0.f;
+  return ORD_NB - 1 - (int)f;
+}
+
+__global__ void k_order_zero(int32_t* __restrict__ hist) {
+  if (threadIdx.x < ORD_NB) hist[threadIdx.x] = 0;
+}
+
+// bucket of every cell, and the buckets' sizes (block histograms in LDS)
+__global__ __launch_bounds__(ORD_TPB) void k_order_key(int64_t n, const float* __restrict__ M,
+                                                       int32_t* __restrict__ key,
+                                                       int32_t* __restrict__ hist) {
+  __shared__ int32_t lh[ORD_NB];
+  if (threadIdx.x < ORD_NB) lh[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * ORD_TPB + threadIdx.x;
+  if (c < n) {
+    const int b = order_bucket(M + c * K3);
+    key[c] = b;
+    atomicAdd(&lh[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < ORD_NB && lh[threadIdx.x] > 0) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
+}
+
+// bucket sizes -> first position of each bucket (exclusive prefix sum)
+__global__ void k_order_scan(int32_t* __restrict__ hist) {
+  if (threadIdx.x == 0) {
+    int32_t sum = 0;
+    for (int b = 0; b < ORD_NB; ++b) {
+      const int32_t h = hist[b];
+      hist[b] = sum;
+      sum += h;
+    }
+  }
+}
+
+// each block reserves its range in every bucket, then writes its cells there
+__global__ __launch_bounds__(ORD_TPB) void k_order_scatter(int64_t n,
+                                                           const int32_t* __restrict__ key,
+                                                           int32_t* __restrict__ cursor,
+                                                           int32_t* __restrict__ order) {
+  __shared__ int32_t lh[ORD_NB], lb[ORD_NB];
+  if (threadIdx.x < ORD_NB) lh[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * ORD_TPB + threadIdx.x;
+  int b = 0, r = 0;
+  if (c < n) {
+    b = key[c];
+    r = atomicAdd(&lh[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < ORD_NB && lh[threadIdx.x] > 0)
+    lb[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], lh[threadIdx.x]);
+  __syncthreads();
+  if (c < n) order[lb[b] + r] = (int32_t)c;
+}
+
 hipError_t launch_newton_wave(mem_ctx_t c, int64_t n, const float* M, float* beta,
                               const SolveParams& p, bool closed_start, int32_t* queue,
                               int32_t* iters, float* resid, uint32_t* status, int32_t* done_list,
                               int32_t* done_ctr, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (c->n1d != 12) return hipErrorNotSupported;
-  DirOut o{nullptr, nullptr, iters, resid, status, done_list, done_ctr};
   const int wpc = c->tune.wave_per_cu > 0 ? c->tune.wave_per_cu : WAVE_SOLVE_PER_CU;
   const int64_t waves = std::min<int64_t>(n, (int64_t)c->n_cu * wpc);
+  // with several cells per wave, the cells far from their start go first; the
+  // order goes to the kernel as o.next_list (lists 0 to 2 are free while the
+  // persistent kernel runs: it keeps no work lists)
+  int32_t* order = nullptr;
+  if (n >= 4 * waves && n <= INT32_MAX && c->w_list[0] && c->w_list[1] && c->w_list[2]) {
+    order = c->w_list[0];
+    int32_t* key = c->w_list[1];
+    int32_t* hist = c->w_list[2];
+    k_order_zero<<<1, 64, 0, s>>>(hist);
+    k_order_key<<<nblocks(n, ORD_TPB), ORD_TPB, 0, s>>>(n, M, key, hist);
+    k_order_scan<<<1, 64, 0, s>>>(hist);
+    k_order_scatter<<<nblocks(n, ORD_TPB), ORD_TPB, 0, s>>>(n, key, hist, order);
+  }
+  DirOut o{order, nullptr, iters, resid, status, done_list, done_ctr};
   k_newton_wave<12><<<(unsigned)waves, 64, 0, s>>>(c->d_t1, queue, n, M, beta, p,
                                                    closed_start ? 1 : 0, c->w_S, c->w_logZ,
                                                    c->w_iters, c->w_status, c->w_resid, o);
