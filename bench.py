@@ -69,9 +69,9 @@ ASM_TRAFFIC = {
     "cells": 65536, "tuning": [2, 512],
 }
 WAVE_TRAFFIC = {
-    "kernel_sha256": "bc72dee0fe29965052a6e8ca28194e4903143fc812b59aa6c0cccb38e15653ed",
-    "fetch_kib": 21379.1, "fetch_scale": 1.99995,
-    "write_kib": 218310.4, "write_scale": 1.0,
+    "kernel_sha256": "311f5b120e56592825f8e11cdb7fc618d9bf7ebd3b437bcb0aed9d9150813717",
+    "fetch_kib": 18926.2, "fetch_scale": 1.99995,
+    "write_kib": 197486.7, "write_scale": 1.0,
     "cells": 65536,
 }
 # the figures depend on the kernels and on the Newton loop that launches them

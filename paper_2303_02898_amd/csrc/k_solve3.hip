@@ -1572,7 +1572,7 @@ __device__ __forceinline__ void wave_solve_rl(const T (&a)[NH], T dinv, int lane
 
 // LDS of one wave (floats).  W holds one chunk of P1 and of P2 during the
 // assembly, then the S row, E in FP32 and, for the FP64 direction, E in FP64.
-// sVd holds the line search's direction coefficients.  About 11.6 KB at
+// sVd holds the line search's direction coefficients.  About 12.5 KB at
 // n = 12: three waves per SIMD fit in the 160 KB of a CU.
 template <int NT>
 struct WaveLds {
@@ -1583,6 +1583,8 @@ struct WaveLds {
   static constexpr int WN = WP > W32 ? WP : W32;
   __align__(16) float sH[6 * NT];
   __align__(16) float sHp[15 * NT];
+  __align__(16) float sHpT[NT * 16];  // sHp by node: 15 products and a pad per row
+  __align__(16) float sHT[NT * 8];     // h_0..h_4 and log w~ by node, two pads per row
   __align__(16) float sB[72];
   __align__(16) float sVb[NP * 5];
   __align__(16) float sVd[NP * 5];
@@ -1608,6 +1610,12 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
     while (up_idx(pp, 4) < pq) ++pp;  // pq = up_idx(pp, qq) with qq >= pp
     const int qq = pp + (pq - up_idx(pp, pp));
     L.sHp[t] = L.sH[pp * NT + k] * L.sH[qq * NT + k];
+    L.sHpT[k * 16 + pq] = L.sHp[t];
+  }
+  for (int t = lane; t < NT; t += 64) L.sHpT[t * 16 + 15] = 0.f;
+  for (int t = lane; t < NT * 8; t += 64) {
+    const int k = t >> 3, c = t & 7;
+    L.sHT[t] = c < 6 ? L.sH[c * NT + k] : 0.f;
   }
   __builtin_amdgcn_wave_barrier();
   const float sq = -0.70710678118654752f;
@@ -1737,7 +1745,8 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
             int z = 0;
             asm volatile("" : "+v"(z));
             const float* sh = L.sH + z;
-            const float* shp = L.sHp + z;
+            const float* sht = L.sHT + z;
+            const float* shpt = L.sHpT + z;
             const int il = lane / NT, j = lane - (lane / NT) * NT;
             const int q = (x0 + il) * NT + j;
             const float base = sh[5 * NT + x0 + il] + sh[5 * NT + j];
@@ -1749,12 +1758,24 @@ __global__ __launch_bounds__(64, 3) void k_newton_wave(
             for (int t = 0; t < 15; ++t) acc[t] = 0.f;
 #pragma unroll
             for (int l = 0; l < NT; ++l) {
-              float x = base + sh[5 * NT + l];
+              // node l's basis values and log weight as two 16-byte reads
+              const float4* hn = reinterpret_cast<const float4*>(sht + l * 8);
+              const float4 h03 = hn[0], h47 = hn[1];
+              const float hb[6] = {h03.x, h03.y, h03.z, h03.w, h47.x, h47.y};
+              float x = base + hb[5];
 #pragma unroll
-              for (int c = 0; c < 5; ++c) x = fmaf(v[c], sh[c * NT + l], x);
+              for (int c = 0; c < 5; ++c) x = fmaf(v[c], hb[c], x);
               const float sg = __expf(x - lz);
+              // node l's 15 products as four 16-byte reads
+              const float4* hq = reinterpret_cast<const float4*>(shpt + l * 16);
+              float hp[16];
 #pragma unroll
-              for (int t = 0; t < 15; ++t) acc[t] = fmaf(sg, shp[t * NT + l], acc[t]);
+              for (int u = 0; u < 4; ++u) {
+                const float4 h4 = hq[u];
+                hp[4 * u] = h4.x; hp[4 * u + 1] = h4.y; hp[4 * u + 2] = h4.z; hp[4 * u + 3] = h4.w;
+              }
+#pragma unroll
+              for (int t = 0; t < 15; ++t) acc[t] = fmaf(sg, hp[t], acc[t]);
             }
 #pragma unroll
             for (int t = 0; t < 15; ++t) P1[(il * 15 + t) * NT + j] = acc[t];
